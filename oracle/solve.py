@@ -1,0 +1,167 @@
+"""Direct FP64 solvers for the KKT system of Sec. 2 (test oracle).
+
+O1  ``range_space_two_factor``: the paper's range-space method (Sec. 3.1, Schur
+    system and primal recovery) with S applied through its complex
+    factorization (Sec. 4): both complex factors are solved with one sparse LU
+    of Z = K + i alpha M, alpha = beta^(-1/2); the second factor Zbar is solved
+    by conjugation of the same LU.
+O1' ``range_space_one_solve``: the same LU used once, reading (y, lam) off the
+    complex solution (see ``range_space_one_solve``).
+O2  ``reduced_saddle``: the 2n real saddle system left after eliminating u
+    exactly (KKT rows 1 and 3), sparse LU; independent of the factorization.
+O3  ``dense_kkt``: numpy.linalg.solve of the full 3n system (tiny meshes).
+O4  ``closed_form_sines``: exact discrete solution for targets made of
+    discrete sine modes, which are common eigenvectors of K and M.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import kkt as _kkt
+
+
+def schur_rhs(K, Kc, ybar, yc):
+    """b = K_c y_c + K ybar, right-hand side of the Schur system (Sec. 3.1)."""
+    b = K @ ybar
+    if yc is not None:
+        b = b + Kc @ yc
+    return b
+
+
+def complex_factor(K, M, beta: float):
+    """Z = K + i beta^(-1/2) M, the factor of S (Sec. 4, complex factorization).
+
+    The paper writes S_c = (K + V/(i sqrt(phi))) V^-1 (K - V/(i sqrt(phi))).
+    Since 1/i = -i the left factor is K - i alpha M = conj(Z) and the right one
+    is Z; S = conj(Z) M^-1 Z = Z M^-1 conj(Z) because the cross terms
+    +-i alpha K cancel in either order.
+    """
+    alpha = beta ** -0.5
+    return (K.astype(np.complex128) + 1j * alpha * M).tocsc()
+
+
+def range_space_two_factor(K, M, Kc, beta, ybar, yc=None, lu=None):
+    """O1: range-space solve with the two complex factors (Sec. 3.1 + Sec. 4).
+
+    lam = S^-1 b = conj(Z)^-1 M Z^-1 b: factor one w1 = Z^-1 b, the middle
+    factor v = M w1, factor two lam_hat = conj(Z)^-1 v computed as
+    conj(Z^-1 conj(v)) with the same LU.  u = lam / beta (Sec. 3.1, primal
+    recovery).  y is read off factor one as y = ybar - Re(w1): with
+    z = M^-1 K lam one has w1 = z - i alpha lam exactly, so Re(w1) is the
+    paper's M^-1 K lam without a mass solve.  The paper's own formula
+    y = ybar - M^-1 K lam is returned as ``y_paper`` for comparison.
+    """
+    if lu is None:
+        lu = spla.splu(complex_factor(K, M, beta))
+    b = schur_rhs(K, Kc, ybar, yc).astype(np.complex128)
+    w1 = lu.solve(b)
+    v = M @ w1
+    lam_hat = np.conj(lu.solve(np.conj(v)))
+    lam = lam_hat.real.copy()
+    u = lam / beta
+    y = ybar - w1.real
+    Mlu = spla.splu(M.tocsc())
+    y_paper = ybar - Mlu.solve(K @ lam)
+    imag_ratio = float(np.linalg.norm(lam_hat.imag) / max(np.linalg.norm(lam), 1e-300))
+    return {"y": y, "u": u, "lam": lam, "w1": w1, "lam_hat": lam_hat,
+            "y_paper": y_paper, "imag_ratio": imag_ratio}
+
+
+def range_space_one_solve(K, M, Kc, beta, ybar, yc=None, lu=None):
+    """O1': one solve with Z gives the KKT solution.
+
+    With w = Z^-1 b and lam the solution of the Schur system, w = M^-1 K lam -
+    i alpha lam (multiply out Z w = K M^-1 K lam + alpha^2 M lam = S lam = b).
+    Hence lam = -Im(w) / alpha, u = lam / beta, y = ybar - Re(w).
+    """
+    if lu is None:
+        lu = spla.splu(complex_factor(K, M, beta))
+    alpha = beta ** -0.5
+    w = lu.solve(schur_rhs(K, Kc, ybar, yc).astype(np.complex128))
+    lam = -w.imag / alpha
+    return {"y": ybar - w.real, "u": lam / beta, "lam": lam, "w": w}
+
+
+def reduced_saddle(K, M, Kc, beta, ybar, yc=None):
+    """O2: eliminate u = lam / beta from KKT row 2 and solve rows 1 and 3.
+
+        [ M   K       ] [y  ]   [ M ybar   ]
+        [ K  -M/beta  ] [lam] = [ -K_c y_c ]
+    """
+    n = K.shape[0]
+    A2 = sp.bmat([[M, K], [K, -M / beta]], format="csc")
+    rhs = np.concatenate([M @ ybar, -(Kc @ yc) if yc is not None else np.zeros(n)])
+    x = spla.splu(A2).solve(rhs)
+    y, lam = x[:n], x[n:]
+    return {"y": y, "u": lam / beta, "lam": lam}
+
+
+def dense_kkt(K, M, Kc, beta, ybar, yc=None):
+    """O3: dense brute-force solve of the 3n KKT system (tiny meshes only)."""
+    n = K.shape[0]
+    if n > 1500:
+        raise ValueError("dense_kkt is for tiny meshes")
+    A = _kkt.kkt_matrix(K, M, beta).toarray()
+    x = np.linalg.solve(A, _kkt.kkt_rhs(M, Kc, ybar, yc))
+    return {"y": x[:n], "u": x[n:2 * n], "lam": x[2 * n:]}
+
+
+def dense_schur(K, M, beta):
+    """S = K M^-1 K + M / beta as a dense matrix (Sec. 3.1), tiny meshes."""
+    Kd, Md = K.toarray(), M.toarray()
+    return Kd @ np.linalg.solve(Md, Kd) + Md / beta
+
+
+def sine_mode_eigs(N: int, kvec):
+    """Eigenvalues of K and M for the discrete sine mode with wave numbers kvec.
+
+    1D interior rows of the P1 stiffness (1/h)(-1, 2, -1) and mass
+    (h/6)(1, 4, 1) act on s(i) = sin(k pi i h) as multiplication by
+    kappa_k = (4/h) sin^2(k pi h / 2) and m_k = (h/3)(2 + cos(k pi h)).  The Q1
+    matrices are Kronecker sums/products of these (Sec. 2 discretisation on a
+    uniform grid), so in d dimensions
+        mu_M = prod_d m_kd,  mu_K = sum_d kappa_kd prod_{e != d} m_ke.
+    """
+    h = 1.0 / N
+    kap = [(4.0 / h) * np.sin(k * np.pi * h / 2) ** 2 for k in kvec]
+    ms = [(h / 3.0) * (2.0 + np.cos(k * np.pi * h)) for k in kvec]
+    muM = float(np.prod(ms))
+    muK = 0.0
+    for d in range(len(kvec)):
+        t = kap[d]
+        for e in range(len(kvec)):
+            if e != d:
+                t *= ms[e]
+        muK += t
+    return muK, muM
+
+
+def closed_form_sines(mesh, beta: float, modes, coefs):
+    """O4: exact discrete KKT solution for ybar = sum_j a_j s_{k_j} (y_c = 0).
+
+    Each discrete sine s_k (nodal sin(k1 pi x) sin(k2 pi y) [sin(k3 pi z)]) is
+    an eigenvector of K and M (``sine_mode_eigs``).  Per mode the KKT system
+    of Sec. 2 reduces to 2x2 scalar equations
+        mu_M y + mu_K lam = mu_M a,   mu_K y - mu_M lam / beta = 0,
+    whose solution is lam = a mu_K mu_M / (mu_K^2 + mu_M^2 / beta),
+    y = a (mu_M^2 / beta) / (mu_K^2 + mu_M^2 / beta), u = lam / beta.
+    Also returns w = Z^-1 b = sum a mu_K / (mu_K + i alpha mu_M) s_k.
+    """
+    xyz = mesh.node_xyz("free")
+    n = xyz.shape[1]
+    y = np.zeros(n)
+    lam = np.zeros(n)
+    w = np.zeros(n, dtype=np.complex128)
+    alpha = beta ** -0.5
+    for kvec, a in zip(modes, coefs):
+        s = np.ones(n)
+        for d, k in enumerate(kvec):
+            s = s * np.sin(k * np.pi * xyz[d])
+        muK, muM = sine_mode_eigs(mesh.N, kvec)
+        den = muK ** 2 + muM ** 2 / beta
+        lam += a * muK * muM / den * s
+        y += a * (muM ** 2 / beta) / den * s
+        w += a * muK / (muK + 1j * alpha * muM) * s
+    return {"y": y, "u": lam / beta, "lam": lam, "w": w}
