@@ -1,0 +1,199 @@
+/*
+ * sfdp.h -- C ABI of the MI355X range-space Schur solver for
+ * Poisson-constrained distributed optimal control.
+ *
+ * Method (Choi, Farhat, Murray, Saunders, arXiv 1312.5653):
+ *   The discrete control problem of Sec. 2 (discrete QP) has the KKT system
+ *       [ M   0     K ] [y  ]   [ M ybar   ]
+ *       [ 0  beta M -M ] [u  ] = [ 0        ]
+ *       [ K  -M     0 ] [lam]   [ -Kc yc   ]
+ *   (the paper's phi is beta here and its volume matrix V is the consistent
+ *   mass matrix M).  The range-space method (Sec. 3.1) solves
+ *       S lam = Kc yc + K ybar,   S = K M^-1 K + M / beta,
+ *   then y = ybar - M^-1 K lam and u = lam / beta.  S is applied through its
+ *   exact complex factorization (Sec. 4)
+ *       S = conj(Z) M^-1 Z,   Z = K + i alpha M,   alpha = beta^(-1/2),
+ *   so one Schur solve is a solve with Z, a product with M, and a solve with
+ *   conj(Z) done by conjugating the right-hand side and the result of a solve
+ *   with Z.  Each Z solve is a FETI-DP domain decomposition solve (Sec. 5):
+ *   subdomain factorizations, the corner coarse problem, and GMRES on the
+ *   interface multipliers with the Dirichlet preconditioner.  On one GPU the
+ *   subdomains are a batch.
+ *
+ * Problem class: the unit square (dim 2) or cube (dim 3), a uniform grid of
+ * n_elem^dim Q1 cells, unit conductivity, Dirichlet data on the whole
+ * boundary, split into (n_elem / sub_elem)^dim subdomains of sub_elem^dim
+ * cells each.  Supported: dim 2 with 2 <= sub_elem <= 32; dim 3 with
+ * 2 <= sub_elem <= 8; n_elem % sub_elem == 0 and n_elem / sub_elem >= 2.
+ *
+ * Dof numbering (all vectors):
+ *   free node (i, j[, k]), 1 <= i, j, k <= n_elem - 1, has index
+ *   (i-1) + (n_elem-1)(j-1) [+ (n_elem-1)^2 (k-1)]  (x fastest);
+ *   boundary node has the index of its position among boundary nodes when
+ *   all full-grid nodes (0..n_elem per axis) are visited with x fastest.
+ *
+ * Memory: every array argument is a DEVICE pointer on the context's GPU
+ * (e.g. torch.Tensor.data_ptr() of a CUDA tensor), FP64, contiguous, owned by
+ * the caller and accessed in stream order on the stream given at context
+ * creation.  Complex vectors are interleaved (re, im) pairs.  Multiple
+ * right-hand sides are stored one after another (column-major n x nrhs).
+ * The library owns factors and workspaces; their device memory is charged
+ * against the context's memory budget.
+ *
+ * Errors: every call returns an sfdp_status; nothing aborts or throws across
+ * the ABI.  sfdp_last_error() returns a thread-local message for the last
+ * failing call on the calling thread.  SFDP_E_INVALID: bad sizes, NULL
+ * required pointers, beta <= 0 or not finite.  SFDP_E_STATE: solve before
+ * sfdp_set_beta.  SFDP_E_NOMEM: the memory budget or the device ran out.
+ * SFDP_E_NOCONV: the iteration limit was reached; outputs hold the last
+ * iterate and info->rel_kkt its residual.  SFDP_E_DEVICE: a HIP error.
+ *
+ * Threading: a problem is used by one host thread at a time.
+ */
+#ifndef SFDP_H
+#define SFDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfdp_ctx sfdp_ctx;
+typedef struct sfdp_problem sfdp_problem;
+
+typedef enum {
+  SFDP_OK = 0,
+  SFDP_E_INVALID = -1,
+  SFDP_E_NOMEM = -2,
+  SFDP_E_NOCONV = -3,
+  SFDP_E_DEVICE = -4,
+  SFDP_E_STATE = -5
+} sfdp_status;
+
+/* Arithmetic of the subdomain factors and of the interface operator.
+ * SFDP_FP64:  complex128 everywhere.
+ * SFDP_MIXED: subdomain factors, subdomain solves and the interface
+ *             operators in complex64 with FP32 accumulation; the coarse
+ *             problem, the Krylov orthogonalisation, the KKT residual and
+ *             the outer iterative refinement in FP64. */
+typedef enum { SFDP_FP64 = 0, SFDP_MIXED = 1 } sfdp_precision;
+
+/* Solver controls; zero-initialised fields take the defaults in brackets. */
+typedef struct {
+  double tol_kkt;   /* stop when ||b - A x|| / ||b|| of the KKT system <= tol_kkt [1e-10] */
+  double tol_inner; /* relative interface residual of each FETI-DP solve
+                       [1e-13 FP64, 1e-6 MIXED] */
+  int max_outer;    /* outer refinement steps [8] */
+  int max_krylov;   /* GMRES iterations per FETI-DP solve, <= 400 [300] */
+} sfdp_opts;
+
+/* Per-solve report. */
+typedef struct {
+  double rel_kkt;        /* final ||b - A x|| / ||b|| (FP64, on the GPU) */
+  double rel_kkt_first;  /* the same after the first two-factor step */
+  double imag_ratio;     /* ||Im lam_hat|| / ||Re lam_hat|| of the last factor-two solve */
+  int outer_steps;       /* two-factor steps taken */
+  int krylov_total;      /* GMRES iterations over all FETI-DP solves */
+  int krylov_its[16];    /* per FETI-DP solve, in order (factor 1, factor 2, ...) */
+  int n_feti;            /* FETI-DP solves done */
+} sfdp_info;
+
+/* Sizes of a problem. */
+typedef struct {
+  int64_t n_free;        /* unconstrained dofs (n_elem-1)^dim */
+  int64_t n_bdry;        /* Dirichlet dofs */
+  int64_t n_sub;         /* subdomains */
+  int64_t n_mult;        /* interface multipliers */
+  int64_t n_corner;      /* coarse (corner) dofs */
+  int64_t max_delta;     /* largest number of interface (Delta) dofs of a subdomain */
+  int64_t resident_bytes;/* device bytes held by the problem after sfdp_set_beta */
+} sfdp_sizes;
+
+/* Create a context on HIP device `device`; all work is ordered on `stream`
+ * (a hipStream_t, NULL for the default stream).  mem_budget_bytes = 0 means
+ * no limit beyond the device's memory. */
+sfdp_status sfdp_ctx_create(int device, size_t mem_budget_bytes, void* stream, sfdp_ctx** out);
+void sfdp_ctx_destroy(sfdp_ctx* ctx);
+const char* sfdp_last_error(void);
+
+/* Set up the mesh, the subdomain partition and the interface maps (Sec. 5:
+ * signed Boolean matrices, corners) for the problem class described above. */
+sfdp_status sfdp_problem_create(sfdp_ctx* ctx, int dim, int n_elem, int sub_elem,
+                                sfdp_precision prec, sfdp_problem** out);
+sfdp_status sfdp_problem_sizes(const sfdp_problem* p, sfdp_sizes* out);
+void sfdp_problem_destroy(sfdp_problem* p);
+
+/* Fix beta (Sec. 2 regularisation) and build the FETI-DP operators of
+ * Z = K + i beta^(-1/2) M (Sec. 4 factor, Sec. 5 solver): per subdomain the
+ * factorization of the remainder block, its interface Schur complement and
+ * its inverse, the corner condensation; then the coarse matrix and its
+ * inverse.  The factors stay resident until the next call or destroy. */
+sfdp_status sfdp_set_beta(sfdp_problem* p, double beta);
+
+/* Range-space solve (Sec. 3.1 with the Sec. 4 factorization) for nrhs targets.
+ *   ybar: n_free x nrhs    target state at the free nodes
+ *   yc:   n_bdry x nrhs    Dirichlet data, or NULL for zero
+ *   y, u, lam: n_free x nrhs outputs (state, control, adjoint).
+ * Starts from (y, u, lam) = (ybar, 0, 0), whose KKT residual is
+ * (0, 0, -(K ybar + Kc yc)); every step applies the two complex factors to
+ * the current FP64 KKT residual (r1, r2, r3):
+ *   dw = Z^-1 (-r3 - i alpha r1);  v = r1 + M dw;
+ *   dlam = Re conj(Z^-1 conj(v));  dy = -Re dw;  u = lam / beta.
+ * The first step is the paper's range-space solve with the real right-hand
+ * side b = K ybar + Kc yc; later steps are iterative refinement.
+ * opts and info may be NULL; info, if given, has nrhs entries. */
+sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar, const double* yc,
+                                   double* y, double* u, double* lam, const sfdp_opts* opts,
+                                   sfdp_info* info);
+
+/* z = S^-1 r for real r (n_free x nrhs), through the two complex factors
+ * (Sec. 4): z = Re conj(Z^-1 conj(M Z^-1 r)).  This is the S block of the
+ * block-diagonal preconditioner of Sec. 3.2. */
+sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, double* z,
+                                 const sfdp_opts* opts, sfdp_info* info);
+
+/* One FETI-DP solve (Sec. 5) of Z x = f (conj_z = 0) or conj(Z) x = f
+ * (conj_z = 1); f and x are complex n_free x nrhs, interleaved. */
+sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double* f, double* x,
+                            const sfdp_opts* opts, int* krylov_its);
+
+/* FP64 products with the assembled matrices (Sec. 2): which = 'K' gives
+ * y = K x + Kc xc (xc may be NULL), 'M' gives y = M x.  x, y: n_free x nrhs
+ * real; xc: n_bdry x nrhs. */
+sfdp_status sfdp_apply_operator(sfdp_problem* p, char which, int nrhs, const double* x,
+                                const double* xc, double* y);
+
+/* Relative KKT residual ||b - A x|| / ||b|| of (y, u, lam) in FP64 (Sec. 2
+ * KKT system), one value per right-hand side written to rel (host array). */
+sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, const double* yc,
+                              const double* y, const double* u, const double* lam, double* rel);
+
+/* Inspection of the resident FETI-DP operators, for testing.  Writes FP64
+ * complex (interleaved) values to the device array out, row-major:
+ *   SFDP_Q_SINV  sub s: n_d x n_d  (Z_rr^-1 restricted to the subdomain's
+ *                Delta dofs, in increasing local node index a + (m+1) b
+ *                [+ (m+1)^2 c]; n_d is returned in *rows and *cols);
+ *   SFDP_Q_SBB   sub s: n_d x n_d  interface Schur complement (Sec. 5, S_bb);
+ *   SFDP_Q_PHI   sub s: n_d x n_c  (Z_rr^-1 Z_rc restricted to Delta rows,
+ *                corners in increasing local index);
+ *   SFDP_Q_COARSE     : n_corner x n_corner coarse matrix K_cc*;
+ * out may be NULL to query the shape only. */
+typedef enum { SFDP_Q_SINV = 0, SFDP_Q_SBB = 1, SFDP_Q_PHI = 2, SFDP_Q_COARSE = 3 } sfdp_query;
+sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out, int* rows, int* cols);
+
+/* Interface-level products for testing, on multiplier vectors (complex,
+ * interleaved, length n_mult; multipliers ordered by the full id of their
+ * node, then by the pair of subdomains (s_a < s_b), signed +1 on s_a):
+ *   which = 'F': y = F_DP x (Sec. 5 interface operator with the coarse
+ *                correction);  which = 'P': y = P^-1 x (Dirichlet
+ *                preconditioner);  which = 'D': y = d(f) for the complex
+ *                free-node load x (length n_free) -- the FETI-DP
+ *                right-hand side. */
+sfdp_status sfdp_interface_apply(sfdp_problem* p, char which, const double* x, double* y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFDP_H */

@@ -1,0 +1,244 @@
+// Internal declarations shared by the host code and the HIP kernels of sfdp.
+//
+// Layout of a problem on the device (2D; dim = 2, ml = m + 1 nodes per
+// subdomain side, L = ml^2 local nodes, ND = padded Delta count):
+//   local node l = a + ml * b of subdomain s = sx + P * sy sits at full-grid
+//   node (sx m + a, sy m + b).  A local node is a remainder (r) node unless it
+//   is a Dirichlet node or a subdomain vertex; vertices that are not Dirichlet
+//   nodes are the corner (primal) unknowns of FETI-DP (Sec. 5).
+//   The extended local matrix E^s is Z^s on r x r and the identity elsewhere,
+//   so every subdomain has the same (ml lines) x (ml nodes) block-tridiagonal
+//   shape; E^s^-1 restricted to r is Z_rr^s^-1.
+//
+//   G    [nsub][ml][ml][ml]  inverse Schur recursions G_j = T_j^-1 of the line
+//                            block-tridiagonal LDL^T of E^s, stored transposed
+//                            (element (i, k) of G_j at [j][k][i]).
+//   Sinv [nsub][ND][ND]      Z_rr^-1 restricted to Delta (row-major, symmetric)
+//   Sbb  [nsub][ND][ND]      interface Schur complement (its inverse)
+//   Phi  [nsub][ND][4]       Z_rr^-1 Z_rc on Delta rows
+//   Kinv [nC][nC]            inverse of the coarse matrix K_cc* (FP64)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/sfdp.h"
+
+namespace sfdp {
+
+template <class R>
+struct C {
+  R x, y;
+};
+using cd = C<double>;
+using cf = C<float>;
+
+template <class R>
+__host__ __device__ inline C<R> mk(R a, R b) { return C<R>{a, b}; }
+template <class R>
+__host__ __device__ inline C<R> operator+(C<R> a, C<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <class R>
+__host__ __device__ inline C<R> operator-(C<R> a, C<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <class R>
+__host__ __device__ inline C<R> operator-(C<R> a) { return {-a.x, -a.y}; }
+template <class R>
+__host__ __device__ inline C<R> operator*(C<R> a, C<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class R>
+__host__ __device__ inline C<R> operator*(R s, C<R> a) { return {s * a.x, s * a.y}; }
+template <class R>
+__host__ __device__ inline C<R> conj(C<R> a) { return {a.x, -a.y}; }
+template <class R>
+__host__ __device__ inline R abs2(C<R> a) { return a.x * a.x + a.y * a.y; }
+// fused a += b * c
+template <class R>
+__host__ __device__ inline void fma_acc(C<R>& a, C<R> b, C<R> c) {
+  a.x = fma(b.x, c.x, a.x);
+  a.x = fma(-b.y, c.y, a.x);
+  a.y = fma(b.x, c.y, a.y);
+  a.y = fma(b.y, c.x, a.y);
+}
+// a += conj(b) * c
+template <class R>
+__host__ __device__ inline void fma_conj_acc(C<R>& a, C<R> b, C<R> c) {
+  a.x = fma(b.x, c.x, a.x);
+  a.x = fma(b.y, c.y, a.x);
+  a.y = fma(b.x, c.y, a.y);
+  a.y = fma(-b.y, c.x, a.y);
+}
+template <class R>
+__host__ __device__ inline C<R> cdiv(C<R> a, C<R> b) {
+  R d = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+template <class R, class S>
+__host__ __device__ inline C<R> cvt(C<S> a) { return C<R>{(R)a.x, (R)a.y}; }
+
+// Real type of a complex storage type.
+template <class T> struct real_of;
+template <> struct real_of<cd> { using type = double; };
+template <> struct real_of<cf> { using type = float; };
+
+// 1D local (Neumann) P1 matrices on a subdomain side of m cells of size h:
+//   k1 = (1/h) tridiag(-1, [1 2 ... 2 1], -1),  m1 = (h/6) tridiag(1, [2 4 ... 4 2], 1).
+// The Q1 local matrix is the Kronecker sum  K = k1 (x) m1 + m1 (x) k1,  M = m1 (x) m1.
+struct Line1D {
+  double h;
+  int m;
+  __host__ __device__ inline double k(int a, int b) const {
+    int d = a - b;
+    if (d == 0) return ((a == 0 || a == m) ? 1.0 : 2.0) / h;
+    if (d == 1 || d == -1) return -1.0 / h;
+    return 0.0;
+  }
+  __host__ __device__ inline double mm(int a, int b) const {
+    int d = a - b;
+    if (d == 0) return ((a == 0 || a == m) ? 2.0 : 4.0) * h / 6.0;
+    if (d == 1 || d == -1) return h / 6.0;
+    return 0.0;
+  }
+};
+
+// Geometry of one 2D instance, passed by value to kernels.
+struct Geo2 {
+  int N, m, P, ml, nsub, ND, nmu, nC;
+  double h, alpha;
+  // subdomain coordinates
+  __device__ __host__ inline int sx(int s) const { return s % P; }
+  __device__ __host__ inline int sy(int s) const { return s / P; }
+  // node classes of local node (a, b) of subdomain s
+  __device__ __host__ inline bool dirich(int s, int a, int b) const {
+    int gi = sx(s) * m + a, gj = sy(s) * m + b;
+    return gi == 0 || gi == N || gj == 0 || gj == N;
+  }
+  __device__ __host__ inline bool vert(int a, int b) const {
+    return (a == 0 || a == m) && (b == 0 || b == m);
+  }
+  __device__ __host__ inline bool rnode(int s, int a, int b) const {
+    return !dirich(s, a, b) && !vert(a, b);
+  }
+  // free-node index of local node (a, b); valid only when not Dirichlet
+  __device__ __host__ inline int freeidx(int s, int a, int b) const {
+    int gi = sx(s) * m + a, gj = sy(s) * m + b;
+    return (gi - 1) + (N - 1) * (gj - 1);
+  }
+  // number of subdomains sharing local node (a, b) (non-Dirichlet)
+  __device__ __host__ inline int mult(int a, int b) const {
+    return ((a == 0 || a == m) ? 2 : 1) * ((b == 0 || b == m) ? 2 : 1);
+  }
+  // local Neumann matrix entry Z((a,b),(a2,b2)) = K + i alpha M
+  __device__ __host__ inline cd zloc(int a, int b, int a2, int b2) const {
+    Line1D L{h, m};
+    double kx = L.k(a, a2), mx = L.mm(a, a2), ky = L.k(b, b2), my = L.mm(b, b2);
+    return cd{kx * my + mx * ky, alpha * mx * my};
+  }
+  // extended matrix E: Z on r x r, identity elsewhere
+  __device__ __host__ inline cd eloc(int s, int a, int b, int a2, int b2) const {
+    bool r1 = rnode(s, a, b), r2 = rnode(s, a2, b2);
+    if (r1 && r2) return zloc(a, b, a2, b2);
+    if (a == a2 && b == b2) return cd{1.0, 0.0};
+    return cd{0.0, 0.0};
+  }
+};
+
+// Device-side index maps of one 2D instance (all arrays device-resident).
+struct Maps2 {
+  const int* dloc;   // [nsub][ND] local node index of Delta slot, -1 pad
+  const int* dmid;   // [nsub][ND] multiplier id
+  const float* dsgn; // [nsub][ND] +1 / -1, 0 pad
+  const int* dpart;  // [nsub][ND] partner slot (t * ND + slot_t)
+  const int* nd;     // [nsub] Delta count
+  const int* cloc;   // [nsub][4] local node of corner slot, -1 pad
+  const int* cgid;   // [nsub][4] global corner id, -1 pad
+  const int* muown;  // [nmu][2] (s+ * ND + slot+), (s- * ND + slot-)
+  const int* mufree; // [nmu] free index of the multiplier's node
+  const int* cown;   // [nC][4] (s * 4 + slot) of the sharing subdomains, -1 pad
+  const int* cfree;  // [nC] free index of each global corner
+};
+
+// Host-side problem.
+struct Ctx;
+struct Problem {
+  Ctx* ctx = nullptr;
+  int dim = 2, N = 0, m = 0, P = 0, nsub = 0, ml = 0, L = 0, ND = 0, nC = 0, nmu = 0;
+  int64_t n_free = 0, n_bdry = 0;
+  sfdp_precision prec = SFDP_FP64;
+  double beta = 0, alpha = 0;
+  bool factored = false;
+  // index maps (device)
+  int *dloc = nullptr, *dmid = nullptr, *dpart = nullptr, *nd = nullptr, *cloc = nullptr,
+      *cgid = nullptr, *muown = nullptr, *mufree = nullptr, *cown = nullptr, *cfree = nullptr;
+  float* dsgn = nullptr;
+  int* full2bdry = nullptr;  // [(N+1)^2] boundary index of a full-grid node, -1 if free
+  // factors (storage precision: cd for FP64, cf for MIXED)
+  void *G = nullptr, *Sinv = nullptr, *Sbb = nullptr, *Phi = nullptr;
+  cd* Kcc = nullptr;
+  cd* Kinv = nullptr;
+  cd* Kwork = nullptr;
+  // solve workspaces (FP64 complex)
+  cd *Xd = nullptr, *Ubuf = nullptr, *Abuf = nullptr, *Ybuf = nullptr, *Cbuf = nullptr,
+     *Qc = nullptr, *fcs = nullptr, *u0 = nullptr, *dvec = nullptr, *mu = nullptr, *wv = nullptr,
+     *Qk = nullptr, *Hk = nullptr, *part = nullptr, *ymin = nullptr;
+  double* dscal = nullptr;    // device scalars
+  unsigned* bar = nullptr;    // grid barrier counter
+  int* flags = nullptr;       // device flags / outputs of the GMRES kernel
+  int kmax_alloc = 0, gmres_blocks = 0;
+  // range-space workspaces (FP64)
+  double *r1 = nullptr, *r2 = nullptr, *r3 = nullptr, *red = nullptr;
+  cd *cvec = nullptr, *cvec2 = nullptr, *cvec3 = nullptr;
+  int nrhs_alloc = 0;
+  size_t bytes = 0;
+  Maps2 maps() const {
+    return Maps2{dloc, dmid, dsgn, dpart, nd, cloc, cgid, muown, mufree, cown, cfree};
+  }
+  Geo2 geo() const {
+    return Geo2{N, m, P, ml, nsub, ND, nmu, nC, 1.0 / N, alpha};
+  }
+};
+
+struct Ctx {
+  int device = 0;
+  size_t budget = 0, used = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+};
+
+// ---- launchers implemented in the .hip files ----
+// setup
+hipError_t launch_factor_lines(const Problem& p, cd* G64, hipStream_t st);
+hipError_t launch_multi_solve(const Problem& p, const cd* G64, cd* Sinv64, cd* Phi64, cd* PhiFull,
+                              cd* scratch, hipStream_t st);
+hipError_t launch_invert_batched(const Problem& p, cd* A64, hipStream_t st);
+hipError_t launch_zcc_and_coarse(const Problem& p, const cd* PhiFull, cd* Kcc, hipStream_t st);
+hipError_t launch_invert_dense(int n, cd* A, cd* work, hipStream_t st);
+hipError_t launch_store_factors(const Problem& p, const cd* G64, const cd* Sinv64, const cd* S64,
+                                const cd* Phi64, hipStream_t st);
+// solve
+hipError_t launch_local_solve(const Problem& p, int mode, const cd* f, int conj_in, cd* x_out,
+                              hipStream_t st);
+hipError_t launch_coarse_rhs(const Problem& p, const cd* f, int conj_in, hipStream_t st);
+hipError_t launch_fetidp_rhs(const Problem& p, hipStream_t st);
+hipError_t launch_gmres(Problem& p, double tol, int kmax, hipStream_t st);
+hipError_t launch_recover_coarse(const Problem& p, hipStream_t st);
+hipError_t launch_assemble_solution(const Problem& p, cd* x, int conj_out, hipStream_t st);
+hipError_t launch_interface_apply(Problem& p, char which, const cd* x, cd* y, hipStream_t st);
+// ops
+hipError_t launch_apply_K(const Problem& p, int nrhs, const double* x, const double* xc, double* y,
+                          hipStream_t st);
+hipError_t launch_apply_M(const Problem& p, int nrhs, const double* x, double* y, hipStream_t st);
+hipError_t launch_kkt_residual(const Problem& p, const double* ybar, const double* yc,
+                               const double* y, const double* u, const double* lam, double* r1,
+                               double* r2, double* r3, double* red, hipStream_t st);
+hipError_t launch_make_rhs1(const Problem& p, const double* r1, const double* r3, cd* g,
+                            hipStream_t st);
+hipError_t launch_make_rhs2(const Problem& p, const double* r1, const cd* dw, cd* v,
+                            hipStream_t st);
+hipError_t launch_update(const Problem& p, const cd* dw, const cd* z, double* y, double* u,
+                         double* lam, double* red, hipStream_t st);
+hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t st);
+hipError_t launch_copy_real_to_complex(int64_t n, const double* x, cd* y, hipStream_t st);
+hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t st);
+
+}  // namespace sfdp

@@ -1,0 +1,230 @@
+"""Python binding of the sfdp C ABI (include/sfdp.h): argument marshalling only.
+
+Every computation runs in the native library ``libsfdp.so`` (HIP kernels for
+gfx950).  Arrays are torch tensors on the GPU; complex vectors are
+``torch.complex128`` (interleaved re/im in memory, as the ABI expects).  There
+is no fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfdp.so")
+
+SFDP_FP64, SFDP_MIXED = 0, 1
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_NOCONV", -4: "E_DEVICE", -5: "E_STATE"}
+Q_SINV, Q_SBB, Q_PHI, Q_COARSE = 0, 1, 2, 3
+
+EXPORTS = [
+    "sfdp_ctx_create", "sfdp_ctx_destroy", "sfdp_last_error", "sfdp_problem_create",
+    "sfdp_problem_sizes", "sfdp_problem_destroy", "sfdp_set_beta", "sfdp_solve_range_space",
+    "sfdp_apply_schur_inv", "sfdp_feti_solve", "sfdp_apply_operator", "sfdp_kkt_residual",
+    "sfdp_inspect", "sfdp_interface_apply",
+]
+
+
+class SfdpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"sfdp {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol_kkt", ctypes.c_double), ("tol_inner", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("max_krylov", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("rel_kkt", ctypes.c_double), ("rel_kkt_first", ctypes.c_double),
+                ("imag_ratio", ctypes.c_double), ("outer_steps", ctypes.c_int),
+                ("krylov_total", ctypes.c_int), ("krylov_its", ctypes.c_int * 16),
+                ("n_feti", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"rel_kkt": self.rel_kkt, "rel_kkt_first": self.rel_kkt_first,
+                "imag_ratio": self.imag_ratio, "outer_steps": self.outer_steps,
+                "krylov_total": self.krylov_total, "n_feti": self.n_feti,
+                "krylov_its": list(self.krylov_its)[: self.n_feti]}
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("n_free", ctypes.c_int64), ("n_bdry", ctypes.c_int64), ("n_sub", ctypes.c_int64),
+                ("n_mult", ctypes.c_int64), ("n_corner", ctypes.c_int64),
+                ("max_delta", ctypes.c_int64), ("resident_bytes", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsfdp.so and declare the ABI; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} is not built; run python -m paper_1312_5653_amd.build")
+    lib = ctypes.CDLL(path)
+    P, I, D, VP = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    lib.sfdp_ctx_create.argtypes = [I, ctypes.c_size_t, VP, ctypes.POINTER(P)]
+    lib.sfdp_ctx_destroy.argtypes = [P]
+    lib.sfdp_ctx_destroy.restype = None
+    lib.sfdp_last_error.restype = ctypes.c_char_p
+    lib.sfdp_problem_create.argtypes = [P, I, I, I, I, ctypes.POINTER(P)]
+    lib.sfdp_problem_sizes.argtypes = [P, ctypes.POINTER(Sizes)]
+    lib.sfdp_problem_destroy.argtypes = [P]
+    lib.sfdp_problem_destroy.restype = None
+    lib.sfdp_set_beta.argtypes = [P, D]
+    lib.sfdp_solve_range_space.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    lib.sfdp_apply_schur_inv.argtypes = [P, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    lib.sfdp_feti_solve.argtypes = [P, I, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(I)]
+    lib.sfdp_apply_operator.argtypes = [P, ctypes.c_char, I, VP, VP, VP]
+    lib.sfdp_kkt_residual.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(D)]
+    lib.sfdp_inspect.argtypes = [P, I, I, VP, ctypes.POINTER(I), ctypes.POINTER(I)]
+    lib.sfdp_interface_apply.argtypes = [P, ctypes.c_char, VP, VP]
+    for name in ("sfdp_ctx_create", "sfdp_problem_create", "sfdp_problem_sizes", "sfdp_set_beta",
+                 "sfdp_solve_range_space", "sfdp_apply_schur_inv", "sfdp_feti_solve",
+                 "sfdp_apply_operator", "sfdp_kkt_residual", "sfdp_inspect", "sfdp_interface_apply"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st: int, allow_noconv: bool = False):
+    if st == 0 or (allow_noconv and st == -3):
+        return st
+    raise SfdpError(st, _lib.sfdp_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("arrays must be contiguous CUDA tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opts(tol_kkt=0.0, tol_inner=0.0, max_outer=0, max_krylov=0):
+    return Opts(tol_kkt, tol_inner, max_outer, max_krylov)
+
+
+class Context:
+    """One GPU; work is ordered on torch's current stream at creation time."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0):
+        import torch
+        lib = load_library()
+        torch.cuda.set_device(device)
+        stream = torch.cuda.current_stream(device).cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib.sfdp_ctx_create(device, mem_budget, ctypes.c_void_p(stream), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if self._h:
+            _lib.sfdp_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """A 2D unit-square Q1 instance split into (n_elem/sub_elem)^2 subdomains."""
+
+    def __init__(self, ctx: Context, dim: int, n_elem: int, sub_elem: int, precision: int = SFDP_FP64):
+        h = ctypes.c_void_p()
+        _check(_lib.sfdp_problem_create(ctx._h, dim, n_elem, sub_elem, precision, ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.dim, self.n_elem, self.sub_elem, self.precision = dim, n_elem, sub_elem, precision
+        s = Sizes()
+        _check(_lib.sfdp_problem_sizes(h, ctypes.byref(s)))
+        self.sizes = {f: getattr(s, f) for f, _ in Sizes._fields_}
+        self.n_free = s.n_free
+        self.n_bdry = s.n_bdry
+
+    def close(self):
+        if self._h:
+            _lib.sfdp_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def refresh_sizes(self):
+        s = Sizes()
+        _check(_lib.sfdp_problem_sizes(self._h, ctypes.byref(s)))
+        self.sizes = {f: getattr(s, f) for f, _ in Sizes._fields_}
+        return self.sizes
+
+    def set_beta(self, beta: float):
+        _check(_lib.sfdp_set_beta(self._h, float(beta)))
+        self.beta = beta
+
+    def solve_range_space(self, ybar, yc=None, y=None, u=None, lam=None, **opts):
+        import torch
+        nrhs = 1 if ybar.dim() == 1 else ybar.shape[0]
+        y = torch.empty_like(ybar) if y is None else y
+        u = torch.empty_like(ybar) if u is None else u
+        lam = torch.empty_like(ybar) if lam is None else lam
+        infos = (Info * nrhs)()
+        o = _opts(**opts)
+        st = _lib.sfdp_solve_range_space(self._h, nrhs, _ptr(ybar), _ptr(yc), _ptr(y), _ptr(u), _ptr(lam),
+                                         ctypes.byref(o), infos)
+        _check(st, allow_noconv=True)
+        return y, u, lam, [i.as_dict() for i in infos], st
+
+    def apply_schur_inv(self, r, z=None, **opts):
+        import torch
+        nrhs = 1 if r.dim() == 1 else r.shape[0]
+        z = torch.empty_like(r) if z is None else z
+        info = Info()
+        o = _opts(**opts)
+        _check(_lib.sfdp_apply_schur_inv(self._h, nrhs, _ptr(r), _ptr(z), ctypes.byref(o), ctypes.byref(info)))
+        return z, info.as_dict()
+
+    def feti_solve(self, f, conj_z: bool = False, x=None, **opts):
+        import torch
+        nrhs = 1 if f.dim() == 1 else f.shape[0]
+        x = torch.empty_like(f) if x is None else x
+        its = (ctypes.c_int * max(nrhs, 32))()
+        o = _opts(**opts)
+        _check(_lib.sfdp_feti_solve(self._h, int(conj_z), nrhs, _ptr(f), _ptr(x), ctypes.byref(o), its))
+        return x, list(its)[:nrhs]
+
+    def apply_operator(self, which: str, x, xc=None, y=None):
+        import torch
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x) if y is None else y
+        _check(_lib.sfdp_apply_operator(self._h, which.encode(), nrhs, _ptr(x), _ptr(xc), _ptr(y)))
+        return y
+
+    def kkt_residual(self, ybar, yc, y, u, lam):
+        nrhs = 1 if ybar.dim() == 1 else ybar.shape[0]
+        rel = (ctypes.c_double * nrhs)()
+        _check(_lib.sfdp_kkt_residual(self._h, nrhs, _ptr(ybar), _ptr(yc), _ptr(y), _ptr(u), _ptr(lam), rel))
+        return list(rel)
+
+    def inspect(self, what: int, sub: int = 0):
+        import torch
+        r, c = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.sfdp_inspect(self._h, what, sub, None, ctypes.byref(r), ctypes.byref(c)))
+        out = torch.zeros((r.value, c.value), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
+        _check(_lib.sfdp_inspect(self._h, what, sub, _ptr(out), ctypes.byref(r), ctypes.byref(c)))
+        return out
+
+    def interface_apply(self, which: str, x):
+        import torch
+        n = self.sizes["n_mult"]
+        y = torch.zeros(n, dtype=torch.complex128, device=x.device)
+        _check(_lib.sfdp_interface_apply(self._h, which.encode(), _ptr(x), _ptr(y)))
+        return y

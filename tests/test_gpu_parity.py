@@ -1,0 +1,256 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances follow the arithmetic:
+* FP64 operator products and assembled local operators: 1e-12 relative
+  (a few hundred roundings of entries of size O(1) and O(h^2));
+* FETI-DP solves and range-space solves on the FP64 path: the relative KKT
+  residual gate 1e-10 at the 32^2 size, and at 512^2 max(1e-10, 2 floor) where
+  floor is the larger of the residuals of the sparse-direct solution and of the
+  exact discrete solution rounded to FP64 (the rounding floor grows like h^-2);
+  forward error vs the oracle 1e-9;
+* mixed path: relative KKT residual 1e-8.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+torch = pytest.importorskip("torch")
+
+from oracle import fem, feti, kkt, solve  # noqa: E402
+from paper_1312_5653_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1312_5653_amd import sfdp
+    ctx = sfdp.Context(0)
+    yield sfdp, ctx
+    ctx.close()
+
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("N,m", [(12, 4), (32, 8)])
+def test_apply_operator_matches_oracle(sf, N, m):
+    sfdp, ctx = sf
+    mesh = fem.Mesh(2, N)
+    A = fem.assemble(mesh)
+    prob = sfdp.Problem(ctx, 2, N, m)
+    x = np.stack([W.random_vector(mesh.n, 1), W.random_vector(mesh.n, 2)])
+    xc = np.stack([W.random_vector(mesh.m, 3), W.random_vector(mesh.m, 4)])
+    yK = prob.apply_operator("K", _t(x), _t(xc)).cpu().numpy()
+    yM = prob.apply_operator("M", _t(x)).cpu().numpy()
+    for r in range(2):
+        assert _rel(yK[r], A["K"] @ x[r] + A["Kc"] @ xc[r]) < 1e-13
+        assert _rel(yM[r], A["M"] @ x[r]) < 1e-13
+    prob.close()
+
+
+@pytest.mark.parametrize("N,m,beta", [(12, 4, 1e-3), (32, 8, 1e-4), (24, 6, 1e-6)])
+def test_local_operators_and_coarse_match_definitions(sf, N, m, beta):
+    """Z_rr^-1|Delta, S_bb, Phi per subdomain and the coarse matrix (Sec. 5) vs dense definitions."""
+    sfdp, ctx = sf
+    mesh = fem.Mesh(2, N)
+    dec = feti.Decomposition(mesh, m)
+    ops = feti.fetidp_operators(dec, beta ** -0.5)
+    prob = sfdp.Problem(ctx, 2, N, m)
+    prob.set_beta(beta)
+    for s, pc in enumerate(ops["pieces"]):
+        isd = pc["is_delta"]
+        sinv = prob.inspect(sfdp.Q_SINV, s).cpu().numpy()
+        sbb = prob.inspect(sfdp.Q_SBB, s).cpu().numpy()
+        phi = prob.inspect(sfdp.Q_PHI, s).cpu().numpy()
+        ref_sinv = pc["Zrr_inv"][np.ix_(isd, isd)]
+        assert sinv.shape == ref_sinv.shape
+        assert np.abs(sinv - ref_sinv).max() / np.abs(ref_sinv).max() < 1e-12
+        assert np.abs(sbb - pc["Sbb"]).max() / np.abs(pc["Sbb"]).max() < 1e-11
+        ref_phi = pc["Phi"][isd]
+        assert np.abs(phi - ref_phi).max() / np.abs(ref_phi).max() < 1e-12
+    kc = prob.inspect(sfdp.Q_COARSE).cpu().numpy()
+    assert np.abs(kc - ops["Kcc"]).max() / np.abs(ops["Kcc"]).max() < 1e-12
+    prob.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_interface_operators_match_definitions(sf, precision):
+    """F_DP, Dirichlet P^-1 and the right-hand side d (Sec. 5) on multiplier vectors."""
+    sfdp, ctx = sf
+    N, m, beta = 16, 4, 1e-3
+    mesh = fem.Mesh(2, N)
+    dec = feti.Decomposition(mesh, m)
+    ops = feti.fetidp_operators(dec, beta ** -0.5)
+    prob = sfdp.Problem(ctx, 2, N, m, precision)
+    prob.set_beta(beta)
+    tol = 1e-12 if precision == 0 else 1e-5
+    mu = W.random_vector(dec.nmu, 5, complex_=True)
+    F = prob.interface_apply("F", _t(mu)).cpu().numpy()
+    assert _rel(F, feti.fetidp_apply(ops, mu)) < tol
+    P = prob.interface_apply("P", _t(mu)).cpu().numpy()
+    assert _rel(P, feti.dirichlet_preconditioner(dec, ops) @ mu) < tol
+    f = W.random_vector(mesh.n, 6, complex_=True)
+    d = prob.interface_apply("D", _t(f)).cpu().numpy()
+    dref, _, _ = feti.fetidp_rhs(dec, ops, f)
+    assert _rel(d, dref) < tol
+    prob.close()
+
+
+@pytest.mark.parametrize("N,m,beta,conj_z", [(32, 8, 1e-4, 0), (32, 8, 1e-4, 1), (48, 16, 1e-2, 0),
+                                             (64, 4, 1e-6, 0)])
+def test_feti_solve_matches_direct(sf, N, m, beta, conj_z):
+    sfdp, ctx = sf
+    mesh = fem.Mesh(2, N)
+    A = fem.assemble(mesh)
+    Z = solve.complex_factor(A["K"], A["M"], beta)
+    if conj_z:
+        Z = Z.conj()
+    f = np.stack([W.random_vector(mesh.n, 7, complex_=True), W.random_vector(mesh.n, 8, complex_=True)])
+    prob = sfdp.Problem(ctx, 2, N, m)
+    prob.set_beta(beta)
+    x, its = prob.feti_solve(_t(f), conj_z=bool(conj_z), tol_inner=1e-12)
+    x = x.cpu().numpy()
+    lu = spla.splu(Z.tocsc())
+    for r in range(2):
+        xr = lu.solve(f[r])
+        assert _rel(x[r], xr) < 1e-9, (its, _rel(x[r], xr))
+        assert 0 < its[r] < 300
+    prob.close()
+
+
+def _c1_inputs():
+    N = 32
+    modes, coefs = W.modes_for("four2d", 0)
+    ybar, yc = W.sine_target(2, N, modes, coefs)
+    return N, modes, coefs, ybar, yc
+
+
+@pytest.mark.parametrize("beta", [1e-2, 1e-4, 1e-6])
+def test_range_space_c1_fp64(sf, beta):
+    sfdp, ctx = sf
+    N, modes, coefs, ybar, yc = _c1_inputs()
+    mesh = fem.Mesh(2, N)
+    A = fem.assemble(mesh)
+    prob = sfdp.Problem(ctx, 2, N, 8, sfdp.SFDP_FP64)
+    prob.set_beta(beta)
+    y, u, lam, info, st = prob.solve_range_space(_t(ybar), None, tol_kkt=1e-10)
+    assert st == 0, info
+    y, u, lam = (t.cpu().numpy() for t in (y, u, lam))
+    rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc, y, u, lam)
+    assert rho <= 1e-10, (rho, info)
+    # the GPU's own FP64 residual agrees with the oracle's up to the rounding of
+    # the residual evaluation itself (about 1e-14 here)
+    assert abs(rho - info[0]["rel_kkt"]) <= 0.25 * rho + 2e-12
+    ref = solve.range_space_two_factor(A["K"], A["M"], A["Kc"], beta, ybar, yc)
+    cf = solve.closed_form_sines(mesh, beta, modes, coefs)
+    for key, v in (("y", y), ("u", u), ("lam", lam)):
+        assert _rel(v, ref[key]) < 1e-9
+        assert _rel(v, cf[key]) < 1e-9
+    assert info[0]["imag_ratio"] < 1e-6
+    prob.close()
+
+
+def test_range_space_thermal_nonzero_boundary(sf):
+    """Sec. 6.1 target with y_c = ybar on the boundary (non-zero Dirichlet data)."""
+    sfdp, ctx = sf
+    N, m, beta = 64, 8, 2e-5
+    ybar, yc = W.thermal_target(N)
+    mesh = fem.Mesh(2, N)
+    A = fem.assemble(mesh)
+    prob = sfdp.Problem(ctx, 2, N, m, sfdp.SFDP_FP64)
+    prob.set_beta(beta)
+    y, u, lam, info, st = prob.solve_range_space(_t(ybar), _t(yc), tol_kkt=1e-10)
+    y, u, lam = (t.cpu().numpy() for t in (y, u, lam))
+    rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc, y, u, lam)
+    ref = solve.range_space_two_factor(A["K"], A["M"], A["Kc"], beta, ybar, yc)
+    rho_ref = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc, ref["y"], ref["u"], ref["lam"])
+    assert rho <= max(1e-10, 2 * rho_ref), (rho, rho_ref, info)
+    for key, v in (("y", y), ("u", u), ("lam", lam)):
+        assert _rel(v, ref[key]) < 1e-9
+
+
+@pytest.mark.parametrize("beta", [1e-2, 1e-4, 1e-6])
+def test_range_space_512_fp64_and_mixed(sf, beta):
+    """The 512^2 workload (16 x 16 subdomains of 32^2): FP64 and mixed paths vs the oracle."""
+    sfdp, ctx = sf
+    N, m = 512, 32
+    modes, coefs = W.modes_for("sixteen2d", 0)
+    ybar, yc = W.sine_target(2, N, modes, coefs)
+    mesh = fem.Mesh(2, N)
+    A = fem.assemble(mesh)
+    ref = solve.range_space_two_factor(A["K"], A["M"], A["Kc"], beta, ybar, yc)
+    rho_ref = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc, ref["y"], ref["u"], ref["lam"])
+    # rounding floor: the residual of the exact discrete solution rounded to FP64
+    cf = solve.closed_form_sines(mesh, beta, modes, coefs)
+    rho_exact = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc, cf["y"], cf["u"], cf["lam"])
+    floor = max(rho_ref, rho_exact)
+    for prec, gate in ((sfdp.SFDP_FP64, max(1e-10, 2 * floor)), (sfdp.SFDP_MIXED, 1e-8)):
+        prob = sfdp.Problem(ctx, 2, N, m, prec)
+        prob.set_beta(beta)
+        y, u, lam, info, st = prob.solve_range_space(_t(ybar), None, tol_kkt=gate)
+        y, u, lam = (t.cpu().numpy() for t in (y, u, lam))
+        rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc, y, u, lam)
+        print(f"beta={beta:g} prec={prec} rho={rho:.3e} rho_ref={rho_ref:.3e} rho_exact={rho_exact:.3e} info={info[0]}")
+        assert st == 0 and rho <= gate, (rho, info)
+        if prec == sfdp.SFDP_FP64:
+            for key, v in (("y", y), ("lam", lam)):
+                assert _rel(v, ref[key]) < 1e-9
+        prob.close()
+
+
+def test_apply_schur_inv_matches_dense(sf):
+    sfdp, ctx = sf
+    N, m, beta = 16, 4, 3e-3
+    mesh = fem.Mesh(2, N)
+    A = fem.assemble(mesh)
+    S = solve.dense_schur(A["K"], A["M"], beta)
+    r = W.random_vector(mesh.n, 12)
+    prob = sfdp.Problem(ctx, 2, N, m)
+    prob.set_beta(beta)
+    z, info = prob.apply_schur_inv(_t(r), tol_inner=1e-13)
+    assert _rel(z.cpu().numpy(), np.linalg.solve(S, r)) < 1e-8
+    prob.close()
+
+
+def test_error_codes(sf):
+    sfdp, ctx = sf
+    with pytest.raises(sfdp.SfdpError) as e:
+        sfdp.Problem(ctx, 2, 30, 8)
+    assert e.value.status == -1
+    prob = sfdp.Problem(ctx, 2, 32, 8)
+    ybar = _t(np.ones(prob.n_free))
+    with pytest.raises(sfdp.SfdpError) as e:
+        prob.solve_range_space(ybar)
+    assert e.value.status == -5
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(sfdp.SfdpError) as e:
+            prob.set_beta(bad)
+        assert e.value.status == -1
+    prob.set_beta(1e-4)
+    _, _, _, info, st = prob.solve_range_space(ybar, max_krylov=1, max_outer=1, tol_kkt=1e-12)
+    assert st == -3 and info[0]["rel_kkt"] > 1e-12
+    prob.close()
+
+
+def test_solves_are_deterministic(sf):
+    sfdp, ctx = sf
+    N, modes, coefs, ybar, yc = _c1_inputs()
+    prob = sfdp.Problem(ctx, 2, 64, 8)
+    prob.set_beta(1e-4)
+    yb = _t(W.sine_target(2, 64, modes, coefs)[0])
+    a = prob.solve_range_space(yb)
+    b = prob.solve_range_space(yb)
+    for i in range(3):
+        assert torch.equal(a[i], b[i])
+    prob.close()
