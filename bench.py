@@ -1,0 +1,198 @@
+#!/usr/bin/env python
+"""Benchmark: range-space Schur solves per second on one MI355X.
+
+Workload (the paper's thermal problem family, Sec. 6.1, at the 512^2 size):
+2D unit square, Q1 Poisson, 512 x 512 cells (261,121 free dofs), 16 x 16
+subdomains of 32 x 32 cells, beta = 1e-4, target ybar = 16 sine modes
+sin(k pi x) sin(l pi y), k, l in 1..4, N(0,1) coefficients (seed 0), y_c = 0.
+One step = one range-space Schur solve (two-factor complex factorization,
+FETI-DP per factor, FP64 refinement) to relative KKT residual <= 1e-8, with
+the subdomain factors resident (sfdp_set_beta is done once, outside the timed
+region, and reported as setup_ms).
+
+Prints one JSON line.  --gpus > 1 is not supported (one process, one GPU).
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def gmres_bytes_per_iteration(N, m, nmu, ncorner, elem_bytes, mean_its):
+    """Algorithmic bytes one GMRES iteration of the interface solve must move.
+
+    Per subdomain: the packed symmetric interface Schur complement and its
+    inverse (n_d (n_d + 1) entries together) and Phi (n_d x n_c), in the storage
+    precision; the coarse inverse once (n_C^2 FP64 complex); the Krylov basis
+    for classical Gram-Schmidt twice (4 (j + 1) vectors read at step j, mean
+    over the launch) plus 6 vector reads/writes, FP64 complex.
+    """
+    P = N // m
+    tot = 0
+    for sy in range(P):
+        for sx in range(P):
+            nd = sum(m - 1 for side in (sx > 0, sx < P - 1, sy > 0, sy < P - 1) if side)
+            nc = sum(1 for cx in (sx, sx + 1) for cy in (sy, sy + 1) if 0 < cx < P and 0 < cy < P)
+            tot += (nd * (nd + 1) + nd * nc) * elem_bytes
+    tot += ncorner * ncorner * 16
+    jmean = (mean_its - 1) / 2.0
+    tot += (4 * (jmean + 1) + 6) * nmu * 16
+    return tot
+
+
+def cpu_baseline(N, m, beta, ybar, budget_s=15.0):
+    """The CPU oracle (SciPy SuperLU of Z, two-factor solve) on the same workload."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import numpy as np
+    import scipy.sparse.linalg as spla
+    from oracle import fem, solve
+    A = fem.assemble(fem.Mesh(2, N))
+    t0 = time.perf_counter()
+    lu = spla.splu(solve.complex_factor(A["K"], A["M"], beta))
+    t_factor = time.perf_counter() - t0
+    times = []
+    t_start = time.perf_counter()
+    while time.perf_counter() - t_start < budget_s or len(times) < 2:
+        t0 = time.perf_counter()
+        solve.range_space_two_factor(A["K"], A["M"], A["Kc"], beta, ybar, None, lu=lu, paper_y=False)
+        times.append(time.perf_counter() - t0)
+        if len(times) >= 50:
+            break
+    t_solve = statistics.median(times)
+    return {"value": 1.0 / t_solve, "unit": "Schur solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(times)} two-factor solves with one resident SuperLU factor of Z at 512^2 "
+                      f"(median {t_solve:.3f} s each); the factorization itself took {t_factor:.2f} s",
+            "factor_s": t_factor, "solve_s": t_solve, "host_threads": os.cpu_count()}
+
+
+def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup, tol_kkt, tol_inner):
+    p = sfdp.Problem(ctx, 2, N, m, precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.set_beta(beta)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    y = torch.empty_like(ybar_t)
+    u = torch.empty_like(ybar_t)
+    lam = torch.empty_like(ybar_t)
+    for _ in range(warmup):
+        p.solve_range_space(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner)
+    p.timing_enable(True)
+    lat, rhos, its = [], [], []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        _, _, _, info, st = p.solve_range_space(ybar_t, None, y, u, lam, tol_kkt=tol_kkt,
+                                                tol_inner=tol_inner)
+        lat.append(time.perf_counter() - t0)
+        rhos.append(info[0]["rel_kkt"])
+        its.append(info[0]["krylov_total"])
+        if st != 0:
+            raise RuntimeError(f"solve did not converge: {info[0]}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_all
+    kt = p.kernel_times()
+    sizes = p.refresh_sizes()
+    p.timing_enable(False)
+    p.close()
+    lat_ms = sorted(x * 1e3 for x in lat)
+    q = lambda f: lat_ms[min(len(lat_ms) - 1, int(round(f * (len(lat_ms) - 1))))]
+    return {"solves_per_s": steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+            "p50_ms": q(0.5), "p99_ms": q(0.99), "setup_ms": setup_ms,
+            "max_rel_kkt": max(rhos), "krylov_per_solve": statistics.mean(its),
+            "kernel_times": kt, "sizes": sizes}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--beta", type=float, default=1e-4)
+    ap.add_argument("--N", type=int, default=512)
+    ap.add_argument("--m", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--fp64-only", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world > 1:
+        print("bench.py runs on one GPU only: the FETI-DP subdomains of an instance are a batch "
+              "on a single MI355X; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1312_5653_amd import sfdp, workloads
+
+    N, m, beta = args.N, args.m, args.beta
+    modes, coefs = workloads.modes_for("sixteen2d", 0)
+    ybar, _ = workloads.sine_target(2, N, modes, coefs)
+    ybar_t = torch.tensor(ybar, device="cuda:0")
+    ctx = sfdp.Context(0)
+    tol_kkt = 1e-8
+    res = {}
+    if not args.fp64_only:
+        res["mixed"] = run_precision(sfdp, torch, ctx, sfdp.SFDP_MIXED, N, m, beta, ybar_t,
+                                     args.steps, args.warmup, tol_kkt, 1e-6)
+    res["fp64"] = run_precision(sfdp, torch, ctx, sfdp.SFDP_FP64, N, m, beta, ybar_t,
+                                args.steps, args.warmup, tol_kkt, 1e-13)
+    head = "mixed" if "mixed" in res else "fp64"
+    r = res[head]
+    kt = r["kernel_times"]
+    sz = r["sizes"]
+    mean_its = kt["gmres_iters"] / max(kt["gmres_launches"], 1)
+    ebytes = 8 if head == "mixed" else 16
+    bpi = gmres_bytes_per_iteration(N, m, sz["n_mult"], sz["n_corner"], ebytes, mean_its)
+    launch_ms = kt["gmres_ms"] / max(kt["gmres_launches"], 1)
+    achieved = bpi * mean_its / (launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": "Schur solves/sec at rel. KKT residual 1e-8 (512² Q1); p50/p99 solve latency",
+        "value": r["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64" if head == "mixed" else "c128",
+        "data": "synthetic",
+        "config": {"workload": f"2D Q1 Poisson control {N}x{N} cells, {N // m}x{N // m} subdomains of "
+                               f"{m}x{m}, beta={beta:g}, 16-mode sine target (seed 0), one RHS per solve",
+                   "precision": head, "tol_kkt": tol_kkt, "parallelism": "1 GPU, subdomains as a batch"},
+        "p50_ms": r["p50_ms"],
+        "p99_ms": r["p99_ms"],
+        "setup_ms": r["setup_ms"],
+        "max_rel_kkt": r["max_rel_kkt"],
+        "krylov_its_per_solve": r["krylov_per_solve"],
+        "roofline": {"bound": "hbm", "kernel": "k_gmres (interface Krylov solve, persistent)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_iteration": bpi, "iterations_per_launch": mean_its,
+                     "launch_ms": launch_ms,
+                     "time_share": kt["gmres_ms"] / (r["ms_per_step"] * args.steps)},
+        "subdomain_solve_kernel": {"launch_ms": kt["local_ms"] / max(kt["local_launches"], 1),
+                                   "launches": kt["local_launches"]},
+    }
+    other = [k for k in res if k != head]
+    for k in other:
+        o = res[k]
+        out[k] = {"solves_per_s": o["solves_per_s"], "ms_per_step": o["ms_per_step"],
+                  "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"], "max_rel_kkt": o["max_rel_kkt"],
+                  "krylov_its_per_solve": o["krylov_per_solve"], "setup_ms": o["setup_ms"]}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(N, m, beta, ybar)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,9 +82,10 @@ typedef enum { SFDP_FP64 = 0, SFDP_MIXED = 1 } sfdp_precision;
 
 /* Solver controls; zero-initialised fields take the defaults in brackets. */
 typedef struct {
-  double tol_kkt;   /* stop when ||b - A x|| / ||b|| of the KKT system <= tol_kkt [1e-10] */
+  double tol_kkt;   /* stop when ||b - A x|| / ||b|| of the KKT system <= tol_kkt
+                       [1e-10 FP64, 1e-8 MIXED] */
   double tol_inner; /* relative interface residual of each FETI-DP solve
-                       [1e-13 FP64, 1e-6 MIXED] */
+                       [1e-8 FP64, 1e-6 MIXED] */
   int max_outer;    /* outer refinement steps [8] */
   int max_krylov;   /* GMRES iterations per FETI-DP solve, <= 400 [300] */
 } sfdp_opts;
@@ -192,6 +193,23 @@ sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out,
  *                free-node load x (length n_free) -- the FETI-DP
  *                right-hand side. */
 sfdp_status sfdp_interface_apply(sfdp_problem* p, char which, const double* x, double* y);
+
+/* Kernel timing with HIP events recorded on the context's stream around the
+ * launches of the two hot kernels of every FETI-DP solve: the persistent
+ * interface GMRES kernel and the batched subdomain solve kernel (two launches
+ * per FETI-DP solve).  enable != 0 starts recording (and clears the totals);
+ * sfdp_kernel_times reports totals in milliseconds, launch counts and the
+ * GMRES iterations done by the timed launches.  Timing adds one event pair per
+ * launch and is meant for measurement runs. */
+typedef struct {
+  double gmres_ms;        /* summed duration of the GMRES kernel launches */
+  double local_ms;        /* summed duration of the subdomain solve launches */
+  int64_t gmres_launches;
+  int64_t gmres_iters;    /* iterations summed over the timed GMRES launches */
+  int64_t local_launches;
+} sfdp_timing;
+sfdp_status sfdp_timing_enable(sfdp_problem* p, int enable);
+sfdp_status sfdp_kernel_times(sfdp_problem* p, sfdp_timing* out);
 
 #ifdef __cplusplus
 }

@@ -42,7 +42,7 @@ def complex_factor(K, M, beta: float):
     return (K.astype(np.complex128) + 1j * alpha * M).tocsc()
 
 
-def range_space_two_factor(K, M, Kc, beta, ybar, yc=None, lu=None):
+def range_space_two_factor(K, M, Kc, beta, ybar, yc=None, lu=None, paper_y=True):
     """O1: range-space solve with the two complex factors (Sec. 3.1 + Sec. 4).
 
     lam = S^-1 b = conj(Z)^-1 M Z^-1 b: factor one w1 = Z^-1 b, the middle
@@ -51,7 +51,8 @@ def range_space_two_factor(K, M, Kc, beta, ybar, yc=None, lu=None):
     recovery).  y is read off factor one as y = ybar - Re(w1): with
     z = M^-1 K lam one has w1 = z - i alpha lam exactly, so Re(w1) is the
     paper's M^-1 K lam without a mass solve.  The paper's own formula
-    y = ybar - M^-1 K lam is returned as ``y_paper`` for comparison.
+    y = ybar - M^-1 K lam is returned as ``y_paper`` for comparison (it needs
+    an extra mass-matrix LU; ``paper_y=False`` skips this diagnostic).
     """
     if lu is None:
         lu = spla.splu(complex_factor(K, M, beta))
@@ -62,8 +63,7 @@ def range_space_two_factor(K, M, Kc, beta, ybar, yc=None, lu=None):
     lam = lam_hat.real.copy()
     u = lam / beta
     y = ybar - w1.real
-    Mlu = spla.splu(M.tocsc())
-    y_paper = ybar - Mlu.solve(K @ lam)
+    y_paper = ybar - spla.splu(M.tocsc()).solve(K @ lam) if paper_y else None
     imag_ratio = float(np.linalg.norm(lam_hat.imag) / max(np.linalg.norm(lam), 1e-300))
     return {"y": y, "u": u, "lam": lam, "w1": w1, "lam_hat": lam_hat,
             "y_paper": y_paper, "imag_ratio": imag_ratio}

@@ -185,18 +185,60 @@ sfdp_status check_launch(Problem& p, int kmax) {
   return SFDP_OK;
 }
 
+// Event pairs around hot launches (kind 0: GMRES, 1: subdomain solve).
+hipError_t ev_begin(Problem& p, int kind, int* slot) {
+  *slot = -1;
+  if (!p.timing) return hipSuccess;
+  if (p.ev_used + 2 > (int)p.ev_pool.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      p.ev_pool.push_back(e);
+    }
+  }
+  *slot = p.ev_used;
+  p.ev_used += 2;
+  p.ev_pending.push_back({*slot, kind});
+  return hipEventRecord(p.ev_pool[*slot], p.ctx->stream);
+}
+hipError_t ev_end(Problem& p, int slot) {
+  if (slot < 0) return hipSuccess;
+  return hipEventRecord(p.ev_pool[slot + 1], p.ctx->stream);
+}
+// After a stream synchronisation: fold the recorded pairs into the totals.
+hipError_t ev_harvest(Problem& p) {
+  for (auto& pr : p.ev_pending) {
+    float ms = 0.f;
+    hipError_t r = hipEventElapsedTime(&ms, p.ev_pool[pr.first], p.ev_pool[pr.first + 1]);
+    if (r != hipSuccess) return r;
+    if (pr.second == 0) { p.t_gmres_ms += ms; ++p.n_gmres; }
+    else { p.t_local_ms += ms; ++p.n_local; }
+  }
+  p.ev_pending.clear();
+  p.ev_used = 0;
+  return hipSuccess;
+}
+
 // One FETI-DP solve of Z x = f (conj_in: conj(Z) x = f).  Iteration count to *its.
 sfdp_status feti_one(Problem& p, const cd* f, int conj_in, cd* x, double tol, int kmax, int* its_dev_slot) {
   hipStream_t st = p.ctx->stream;
+  int ev;
+  HIPCHK(ev_begin(p, 1, &ev));
   HIPCHK(launch_local_solve(p, 0, f, conj_in, nullptr, st));
+  HIPCHK(ev_end(p, ev));
   HIPCHK(launch_coarse_rhs(p, f, conj_in, st));
   HIPCHK(launch_fetidp_rhs(p, st));
   sfdp_status s = check_launch(p, kmax);
   if (s != SFDP_OK) return s;
+  HIPCHK(ev_begin(p, 0, &ev));
   HIPCHK(launch_gmres(p, tol, kmax, st));
+  HIPCHK(ev_end(p, ev));
   if (its_dev_slot) HIPCHK(hipMemcpyAsync(its_dev_slot, p.flags, sizeof(int), hipMemcpyDeviceToDevice, st));
   HIPCHK(launch_recover_coarse(p, st));
+  HIPCHK(ev_begin(p, 1, &ev));
   HIPCHK(launch_local_solve(p, 1, f, conj_in, x, st));
+  HIPCHK(ev_end(p, ev));
   HIPCHK(launch_assemble_solution(p, x, conj_in, st));
   return SFDP_OK;
 }
@@ -291,14 +333,14 @@ sfdp_status sfdp_problem_create(sfdp_ctx* ctx, int dim, int n_elem, int sub_elem
       (s = dalloc(*p, (void**)&p->fcs, sizeof(cd) * nC)) || (s = dalloc(*p, (void**)&p->u0, sizeof(cd) * nC)) ||
       (s = dalloc(*p, (void**)&p->ymin, sizeof(cd) * nC)) || (s = dalloc(*p, (void**)&p->dvec, sizeof(cd) * p->nmu)) ||
       (s = dalloc(*p, (void**)&p->mu, sizeof(cd) * p->nmu)) || (s = dalloc(*p, (void**)&p->wv, sizeof(cd) * p->nmu)) ||
-      (s = dalloc(*p, (void**)&p->dscal, sizeof(double) * 8)) || (s = dalloc(*p, (void**)&p->bar, 64)) ||
+      (s = dalloc(*p, (void**)&p->dscal, sizeof(double) * 8)) || (s = dalloc(*p, (void**)&p->bar, 4096)) ||
       (s = dalloc(*p, (void**)&p->flags, sizeof(int) * 64))) {
     sfdp_problem_destroy(p);
     return s;
   }
   p->gmres_blocks = std::min(p->nsub, ctx->num_cu);
   hipError_t ez = launch_fill(p->flags, sizeof(int) * 64, ctx->stream);
-  if (ez == hipSuccess) ez = launch_fill(p->bar, 64, ctx->stream);
+  if (ez == hipSuccess) ez = launch_fill(p->bar, 4096, ctx->stream);
   if (ez == hipSuccess) ez = launch_fill(p->dscal, sizeof(double) * 8, ctx->stream);
   if (ez == hipSuccess) ez = hipStreamSynchronize(ctx->stream);
   if (ez != hipSuccess) {
@@ -332,6 +374,7 @@ void sfdp_problem_destroy(sfdp_problem* p) {
                  p->bar, p->flags, p->r1, p->r2, p->r3, p->red, p->cvec, p->cvec2, p->cvec3, p->Kwork};
   for (void* a : arr)
     if (a) hipFree(a);
+  for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
   p->ctx->used -= std::min(p->ctx->used, p->bytes);
   delete p;
 }
@@ -409,8 +452,11 @@ sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double*
   HIPCHK(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, p->ctx->stream));
   HIPCHK(hipStreamSynchronize(p->ctx->stream));
   if (flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
-  if (krylov_its)
-    for (int r = 0; r < nrhs && r < 32; ++r) krylov_its[r] = flags[8 + r];
+  HIPCHK(ev_harvest(*p));
+  for (int r = 0; r < nrhs && r < 32; ++r) {
+    if (krylov_its) krylov_its[r] = flags[8 + r];
+    if (p->timing) p->it_gmres += flags[8 + r];
+  }
   return SFDP_OK;
 }
 
@@ -460,6 +506,7 @@ static sfdp_status range_space_one(sfdp_problem* p, const double* ybar, const do
     HIPCHK(launch_kkt_residual(*p, ybar, yc, y, u, lam, p->r1, p->r2, p->r3, p->red, st));
     HIPCHK(hipMemcpyAsync(red2, p->red, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(ev_harvest(*p));
     rho = red2[0];
     if (step == 1) loc.rel_kkt_first = rho;
     if (step > 0) loc.imag_ratio = red2[1];
@@ -488,6 +535,7 @@ static sfdp_status range_space_one(sfdp_problem* p, const double* ybar, const do
     loc.krylov_its[i] = flags[8 + i];
     loc.krylov_total += flags[8 + i];
   }
+  if (p->timing) p->it_gmres += loc.krylov_total;
   if (info) *info = loc;
   return status;
 }
@@ -546,6 +594,8 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
   HIPCHK(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
+  HIPCHK(ev_harvest(*p));
+  if (p->timing) p->it_gmres += flags[8] + flags[9];
   if (info) {
     memset(info, 0, sizeof(*info));
     info->n_feti = 2;
@@ -604,6 +654,31 @@ sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out,
       }
   }
   HIPCHK(hipMemcpy(out, host.data(), sizeof(cd) * host.size(), hipMemcpyHostToDevice));
+  return SFDP_OK;
+}
+
+sfdp_status sfdp_timing_enable(sfdp_problem* p, int enable) {
+  if (!p) return fail(SFDP_E_INVALID, "null problem");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  p->ev_pending.clear();
+  p->ev_used = 0;
+  p->timing = enable != 0;
+  p->t_gmres_ms = p->t_local_ms = 0;
+  p->n_gmres = p->n_local = p->it_gmres = 0;
+  return SFDP_OK;
+}
+
+sfdp_status sfdp_kernel_times(sfdp_problem* p, sfdp_timing* out) {
+  if (!p || !out) return fail(SFDP_E_INVALID, "NULL argument");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  HIPCHK(ev_harvest(*p));
+  out->gmres_ms = p->t_gmres_ms;
+  out->local_ms = p->t_local_ms;
+  out->gmres_launches = p->n_gmres;
+  out->gmres_iters = p->it_gmres;
+  out->local_launches = p->n_local;
   return SFDP_OK;
 }
 

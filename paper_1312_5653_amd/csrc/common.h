@@ -190,6 +190,13 @@ struct Problem {
   cd *cvec = nullptr, *cvec2 = nullptr, *cvec3 = nullptr;
   int nrhs_alloc = 0;
   size_t bytes = 0;
+  // kernel timing (events recorded around hot kernel launches)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_pending;  // (event index, kind: 0 gmres, 1 local)
+  int ev_used = 0;
+  double t_gmres_ms = 0, t_local_ms = 0;
+  int64_t n_gmres = 0, n_local = 0, it_gmres = 0;
   Maps2 maps() const {
     return Maps2{dloc, dmid, dsgn, dpart, nd, cloc, cgid, muown, mufree, cown, cfree};
   }

@@ -23,27 +23,95 @@ namespace sfdp {
 constexpr int ML = 33;
 
 // ------------------------------------------------------------------------------------------
-// Grid barrier for a cooperative launch (all blocks co-resident).  A monotone
-// counter: barrier number e completes when the counter reaches e * nblocks.  A
-// spin limit turns a broken barrier into an error flag instead of a hang.
+// Grid barrier for a cooperative launch (all blocks co-resident), two levels to
+// spread the atomics: blocks arrive on one of G group counters (separate
+// 128-byte lines), the last arrival of each group arrives on the top counter,
+// and the last group publishes the epoch in a generation word that every block
+// polls.  Counters only grow (barrier e completes at e * size), so nothing is
+// reset inside a launch.  A spin limit turns a broken barrier into an error
+// flag instead of a hang.  bar holds BAR_WORDS words.
+constexpr int BAR_GROUPS = 16, BAR_STRIDE = 32, BAR_TOP = BAR_GROUPS * BAR_STRIDE,
+              BAR_GEN = BAR_TOP + BAR_STRIDE, BAR_WORDS = BAR_GEN + BAR_STRIDE;
 __device__ inline void grid_barrier(unsigned* bar, unsigned nblocks, unsigned& epoch, int* err) {
-  __threadfence();
-  __syncthreads();
+  __syncthreads();  // every wave of the block has finished its stores
   epoch += 1;
   if (threadIdx.x == 0) {
-    unsigned target = epoch * nblocks;
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // release the block's stores at agent scope, then arrive (relaxed RMW)
+    __atomic_thread_fence(__ATOMIC_RELEASE);
+    const unsigned G = nblocks >= 8 * BAR_GROUPS ? BAR_GROUPS : (nblocks + 7) / 8;
+    const unsigned grp = blockIdx.x % G;
+    const unsigned gsize = nblocks / G + (grp < nblocks % G ? 1u : 0u);
+    unsigned old = __hip_atomic_fetch_add(bar + grp * BAR_STRIDE, 1u, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == epoch * gsize) {
+      // last of its group: acquire the group's stores, release them onward
+      __atomic_thread_fence(__ATOMIC_ACQ_REL);
+      unsigned o2 = __hip_atomic_fetch_add(bar + BAR_TOP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (o2 + 1 == epoch * G) {
+        __atomic_thread_fence(__ATOMIC_ACQ_REL);
+        __hip_atomic_store(bar + BAR_GEN, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    // poll without cache maintenance; one acquire fence once the epoch is published
     unsigned spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(bar + BAR_GEN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1u << 26)) {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
   }
   __syncthreads();
-  __threadfence();
+}
+
+// out[i] = sum_q part[i * nb + q] for i < n, in a fixed order (identical in every
+// block).  Wave w takes i = w, w + 4, ...; four values of i per batch keep 16
+// loads in flight per lane.  nb <= 256.
+__device__ inline void reduce_partials(const cd* __restrict__ part, int nb, int n, cd* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i0 = wv * 4; i0 < n; i0 += 16) {
+    cd v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i = i0 + u, q = lane + 64 * r;
+        v[u][r] = (i < n && q < nb) ? part[(size_t)i * nb + q] : cd{0.0, 0.0};
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      cd a = (v[u][0] + v[u][1]) + (v[u][2] + v[u][3]);
+      for (int off = 32; off > 0; off >>= 1) {
+        a.x += __shfl_xor(a.x, off, 64);
+        a.y += __shfl_xor(a.y, off, 64);
+      }
+      if (lane == 0 && i0 + u < n) out[i0 + u] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// part[i * nb + b] = sum_{k < kn} conj(Q[i][k0 + k]) w[k] for i < nvec.  Eight
+// lanes per vector (32 vectors per pass), partial sums combined by shuffles.
+__device__ inline void block_dots(const cd* __restrict__ Q, int nmu, int k0, int kn, int nvec,
+                                  const cd* wch, cd* part, int nb, int b) {
+  const int t = threadIdx.x, g = t & 7;
+  for (int i0 = 0; i0 < nvec; i0 += 32) {
+    int i = i0 + (t >> 3);
+    cd acc{0.0, 0.0};
+    if (i < nvec) {
+      const cd* q = Q + (size_t)i * nmu + k0;
+#pragma unroll 4
+      for (int k = g; k < kn; k += 8) fma_conj_acc(acc, q[k], wch[k]);
+    }
+    for (int off = 4; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off, 64);
+      acc.y += __shfl_xor(acc.y, off, 64);
+    }
+    if (g == 0 && i < nvec) part[(size_t)i * nb + b] = acc;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -55,6 +123,7 @@ template <class TS>
 __device__ inline void symv_block(const TS* __restrict__ A, int ND, int nd, const TS* xs,
                                   cd* red, cd* y) {
   using R = typename real_of<TS>::type;
+  constexpr int KB = 16;  // loads in flight per thread
   const int rows = ND < 256 ? ND : 256;
   const int nsplit = 256 / rows;
   const int i = threadIdx.x % rows, part = threadIdx.x / rows;
@@ -62,7 +131,14 @@ __device__ inline void symv_block(const TS* __restrict__ A, int ND, int nd, cons
   C<R> acc{0, 0};
   if (part < nsplit && i < nd) {
     int k0 = part * klen, k1 = min(nd, k0 + klen);
-    for (int k = k0; k < k1; ++k) fma_acc(acc, A[(size_t)k * ND + i], xs[k]);
+    for (int kb = k0; kb < k1; kb += KB) {
+      TS v[KB];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) v[u] = (kb + u < k1) ? A[(size_t)(kb + u) * ND + i] : TS{0, 0};
+#pragma unroll
+      for (int u = 0; u < KB; ++u)
+        if (kb + u < k1) fma_acc(acc, v[u], xs[kb + u]);
+    }
   }
   red[threadIdx.x] = cd{(double)acc.x, (double)acc.y};
   __syncthreads();
@@ -74,17 +150,36 @@ __device__ inline void symv_block(const TS* __restrict__ A, int ND, int nd, cons
   __syncthreads();
 }
 
-// t[p] = sum_k G(p,k) z[k] for a line (G stored transposed at Gt[k*ml + p]);
-// four wave groups split k, partial sums reduced through LDS.
+// Bulk copy of one line factor (ml * ml entries, <= 33 * 33) global -> registers:
+// every thread issues its (at most 5) loads back to back.
+constexpr int GPT = (ML * ML + 255) / 256;
+template <class TS>
+__device__ inline void line_load(const TS* __restrict__ src, int n2, TS (&reg)[GPT]) {
+#pragma unroll
+  for (int r = 0; r < GPT; ++r) {
+    int idx = threadIdx.x + 256 * r;
+    if (idx < n2) reg[r] = src[idx];
+  }
+}
+template <class TS>
+__device__ inline void line_store(TS* dst, int n2, const TS (&reg)[GPT]) {
+#pragma unroll
+  for (int r = 0; r < GPT; ++r) {
+    int idx = threadIdx.x + 256 * r;
+    if (idx < n2) dst[idx] = reg[r];
+  }
+}
+
+// t[p] = sum_k G(p,k) z[k] for one line; G in LDS stored transposed (G(p,k) at
+// Gl[k*ml + p]); four wave groups split k, partial sums reduced through LDS.
 template <class TS, class T>
-__device__ inline void line_mv(const TS* __restrict__ Gt, int ml, const T* z, T* red, T* out,
-                               bool subtract) {
+__device__ inline void line_mv(const TS* Gl, int ml, const T* z, T* red, T* out, bool subtract) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int kq = (ml + 3) / 4;
   T acc{0, 0};
   if (lane < ml) {
     int k0 = wv * kq, k1 = min(ml, k0 + kq);
-    for (int k = k0; k < k1; ++k) fma_acc(acc, cvt<typename real_of<T>::type>(Gt[k * ml + lane]), z[k]);
+    for (int k = k0; k < k1; ++k) fma_acc(acc, cvt<typename real_of<T>::type>(Gl[k * ml + lane]), z[k]);
   }
   if (lane < ml) red[wv * ML + lane] = acc;
   __syncthreads();
@@ -113,7 +208,11 @@ __global__ void __launch_bounds__(256) k_local_solve(Geo2 g, Maps2 mp, const TS*
   __shared__ T xall[ML * ML];
   __shared__ T zl[ML];
   __shared__ T red[4 * ML];
+  __shared__ TS gbuf[2][ML * ML];
   const int s = blockIdx.x, ml = g.ml, n2 = ml * ml, ND = g.ND;
+  const TS* Gs = G + (size_t)s * ml * n2;
+  TS greg[GPT];
+  line_load<TS>(Gs, n2, greg);  // line 0 in flight while the load vector is built
   // load right-hand side
   for (int l = threadIdx.x; l < n2; l += blockDim.x) {
     int a = l % ml, b = l / ml;
@@ -144,9 +243,12 @@ __global__ void __launch_bounds__(256) k_local_solve(Geo2 g, Maps2 mp, const TS*
     }
     __syncthreads();
   }
-  const TS* Gs = G + (size_t)s * ml * n2;
+  line_store<TS>(gbuf[0], n2, greg);
+  __syncthreads();
   // forward: z_j = f_j - A_j,j-1 t_j-1 ; t_j = G_j z_j   (t_j overwrites f_j in xall)
   for (int j = 0; j < ml; ++j) {
+    const int nxt = (j + 1 < ml) ? j + 1 : ml - 2;  // the backward sweep starts at line ml-2
+    line_load<TS>(Gs + (size_t)nxt * n2, n2, greg);
     if (threadIdx.x < ml) {
       int p = threadIdx.x;
       T v = xall[p + ml * j];
@@ -159,10 +261,15 @@ __global__ void __launch_bounds__(256) k_local_solve(Geo2 g, Maps2 mp, const TS*
       zl[p] = v;
     }
     __syncthreads();
-    line_mv<TS, T>(Gs + (size_t)j * n2, ml, zl, red, xall + ml * j, false);
+    line_mv<TS, T>(gbuf[j & 1], ml, zl, red, xall + ml * j, false);
+    line_store<TS>(gbuf[(j + 1) & 1], n2, greg);
+    __syncthreads();
   }
-  // backward: x_j = t_j - G_j A_j,j+1 x_j+1
+  // backward: x_j = t_j - G_j A_j,j+1 x_j+1   (line j's factor sits in gbuf[(ml - 1 - j + ml) & 1]
+  // after the forward loop: buffer parity continues from the forward sweep)
+  int par = ml & 1;
   for (int j = ml - 2; j >= 0; --j) {
+    if (j > 0) line_load<TS>(Gs + (size_t)(j - 1) * n2, n2, greg);
     if (threadIdx.x < ml) {
       int p = threadIdx.x;
       T v{0, 0};
@@ -173,7 +280,10 @@ __global__ void __launch_bounds__(256) k_local_solve(Geo2 g, Maps2 mp, const TS*
       zl[p] = v;
     }
     __syncthreads();
-    line_mv<TS, T>(Gs + (size_t)j * n2, ml, zl, red, xall + ml * j, true);
+    line_mv<TS, T>(gbuf[par], ml, zl, red, xall + ml * j, true);
+    par ^= 1;
+    if (j > 0) line_store<TS>(gbuf[par], n2, greg);
+    __syncthreads();
   }
   // outputs
   const int nd = mp.nd[s];
@@ -258,21 +368,27 @@ __global__ void k_fetidp_rhs(Geo2 g, Maps2 mp, const cd* Xd, const TS* Phi, cons
   d[k] = out;
 }
 
-// c^s_q = sum_i Phi[s][i][q] sign_i mu[mid_i]  (F_rc^T mu contributions)
+// c^s_q = sum_i Phi[s][i][q] sign_i mu[mid_i]  (F_rc^T mu contributions); one
+// wavefront per (subdomain, corner slot).
 template <class TS>
 __global__ void k_frct(Geo2 g, Maps2 mp, const TS* Phi, const cd* mu, cd* Cbuf) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int t = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
   if (t >= g.nsub * 4) return;
   int s = t / 4, q = t % 4;
   cd acc{0.0, 0.0};
   if (mp.cloc[s * 4 + q] >= 0) {
     int nd = mp.nd[s];
-    for (int i = 0; i < nd; ++i) {
+    for (int i = lane; i < nd; i += 64) {
       cd x = (double)mp.dsgn[s * g.ND + i] * mu[mp.dmid[s * g.ND + i]];
       fma_acc(acc, cvt<double>(Phi[((size_t)s * g.ND + i) * 4 + q]), x);
     }
   }
-  Cbuf[t] = acc;
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.x += __shfl_down(acc.x, off, 64);
+    acc.y += __shfl_down(acc.y, off, 64);
+  }
+  if (lane == 0) Cbuf[t] = acc;
 }
 
 // rhs_c = fcs_c + sum_owners Cbuf
@@ -475,12 +591,9 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
     if (threadIdx.x == 0) part2[b] = cd{t, 0.0};
   }
   grid_barrier(a.bar, nb, epoch, a.flags + 1);
-  double beta0;
-  {
-    double t = 0.0;
-    for (unsigned q = 0; q < nb; ++q) t += part2[q].x;
-    beta0 = sqrt(t);
-  }
+  reduce_partials(part2, nb, 1, ucs);
+  const double beta0 = sqrt(ucs[0].x);
+  __syncthreads();
   if (threadIdx.x == 0) gv[0] = cd{beta0, 0.0};
   if (beta0 == 0.0) {
     for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) a.mu[k] = cd{0.0, 0.0};
@@ -511,49 +624,25 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
       wch[k] = a.Ybuf[mp.muown[2 * kk]] - a.Ybuf[mp.muown[2 * kk + 1]];
     }
     __syncthreads();
-    for (int i = wv; i <= j; i += 4) {
-      cd acc{0.0, 0.0};
-      for (int k = lane; k < kn; k += 64) fma_conj_acc(acc, a.Q[(size_t)i * nmu + k0 + k], wch[k]);
-      for (int off = 32; off > 0; off >>= 1) {
-        acc.x += __shfl_down(acc.x, off, 64);
-        acc.y += __shfl_down(acc.y, off, 64);
-      }
-      if (lane == 0) part0[(size_t)i * nb + b] = acc;
-    }
+    block_dots(a.Q, nmu, k0, kn, j + 1, wch, part0, nb, b);
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
     // ---- O2: h = sum partials; w -= Q h; second projections
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-      cd t{0.0, 0.0};
-      for (unsigned q = 0; q < nb; ++q) t = t + part0[(size_t)i * nb + q];
-      hv[i] = t;
-    }
-    __syncthreads();
+    reduce_partials(part0, nb, j + 1, hv);
     for (int k = threadIdx.x; k < kn; k += blockDim.x) {
       cd v = wch[k];
+#pragma unroll 8
       for (int i = 0; i <= j; ++i) v = v - hv[i] * a.Q[(size_t)i * nmu + k0 + k];
       wch[k] = v;
     }
     __syncthreads();
-    for (int i = wv; i <= j; i += 4) {
-      cd acc{0.0, 0.0};
-      for (int k = lane; k < kn; k += 64) fma_conj_acc(acc, a.Q[(size_t)i * nmu + k0 + k], wch[k]);
-      for (int off = 32; off > 0; off >>= 1) {
-        acc.x += __shfl_down(acc.x, off, 64);
-        acc.y += __shfl_down(acc.y, off, 64);
-      }
-      if (lane == 0) part1[(size_t)i * nb + b] = acc;
-    }
+    block_dots(a.Q, nmu, k0, kn, j + 1, wch, part1, nb, b);
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
     // ---- O3: second correction, norm
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-      cd t{0.0, 0.0};
-      for (unsigned q = 0; q < nb; ++q) t = t + part1[(size_t)i * nb + q];
-      h2[i] = t;
-    }
-    __syncthreads();
+    reduce_partials(part1, nb, j + 1, h2);
     double loc = 0.0;
     for (int k = threadIdx.x; k < kn; k += blockDim.x) {
       cd v = wch[k];
+#pragma unroll 8
       for (int i = 0; i <= j; ++i) v = v - h2[i] * a.Q[(size_t)i * nmu + k0 + k];
       a.w[k0 + k] = v;
       loc += abs2(v);
@@ -563,9 +652,8 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
     if (threadIdx.x == 0) part2[b] = cd{t, 0.0};
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
     // ---- Arnoldi column j complete: hn, Givens rotations (identical in every block)
-    double hn2 = 0.0;
-    for (unsigned q = 0; q < nb; ++q) hn2 += part2[q].x;
-    double hn = sqrt(hn2);
+    reduce_partials(part2, nb, 1, ucs);
+    double hn = sqrt(ucs[0].x);
     if (threadIdx.x == 0) {
       for (int i = 0; i < j; ++i) {
         cd c = csv[i], sn = snv[i];
@@ -613,6 +701,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
   // t = Q y on the chunk
   for (int k = threadIdx.x; k < kn; k += blockDim.x) {
     cd v{0.0, 0.0};
+#pragma unroll 8
     for (int i = 0; i < kk; ++i) fma_acc(v, a.Q[(size_t)i * nmu + k0 + k], h2[i]);
     a.w[k0 + k] = v;
   }
@@ -720,7 +809,7 @@ static hipError_t gmres_t(Problem& p, double tol, int kmax) {
   a.tol = tol;
   a.kmax = kmax;
   a.chunk = chunk;
-  hipError_t e = launch_fill(p.bar, sizeof(unsigned), st);
+  hipError_t e = launch_fill(p.bar, BAR_WORDS * sizeof(unsigned), st);
   if (e != hipSuccess) return e;
   Geo2 g = p.geo();
   Maps2 mp = p.maps();
@@ -757,10 +846,10 @@ size_t gmres_lds_bytes(const Problem& p, int kmax, int nb) {
 
 hipError_t launch_recover_coarse(const Problem& p, hipStream_t st) {
   if (p.prec == SFDP_MIXED)
-    hipLaunchKernelGGL(k_frct<cf>, dim3((p.nsub * 4 + 127) / 128), dim3(128), 0, st, p.geo(),
+    hipLaunchKernelGGL(k_frct<cf>, dim3((p.nsub * 4 + 3) / 4), dim3(256), 0, st, p.geo(),
                        p.maps(), (const cf*)p.Phi, p.mu, p.Cbuf);
   else
-    hipLaunchKernelGGL(k_frct<cd>, dim3((p.nsub * 4 + 127) / 128), dim3(128), 0, st, p.geo(),
+    hipLaunchKernelGGL(k_frct<cd>, dim3((p.nsub * 4 + 3) / 4), dim3(256), 0, st, p.geo(),
                        p.maps(), (const cd*)p.Phi, p.mu, p.Cbuf);
   hipLaunchKernelGGL(k_corner_sum, dim3((p.nC + 127) / 128), dim3(128), 0, st, p.geo(), p.maps(),
                      p.fcs, p.Cbuf, p.ymin);

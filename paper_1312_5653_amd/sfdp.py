@@ -21,7 +21,7 @@ EXPORTS = [
     "sfdp_ctx_create", "sfdp_ctx_destroy", "sfdp_last_error", "sfdp_problem_create",
     "sfdp_problem_sizes", "sfdp_problem_destroy", "sfdp_set_beta", "sfdp_solve_range_space",
     "sfdp_apply_schur_inv", "sfdp_feti_solve", "sfdp_apply_operator", "sfdp_kkt_residual",
-    "sfdp_inspect", "sfdp_interface_apply",
+    "sfdp_inspect", "sfdp_interface_apply", "sfdp_timing_enable", "sfdp_kernel_times",
 ]
 
 
@@ -47,6 +47,12 @@ class Info(ctypes.Structure):
                 "imag_ratio": self.imag_ratio, "outer_steps": self.outer_steps,
                 "krylov_total": self.krylov_total, "n_feti": self.n_feti,
                 "krylov_its": list(self.krylov_its)[: self.n_feti]}
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("gmres_ms", ctypes.c_double), ("local_ms", ctypes.c_double),
+                ("gmres_launches", ctypes.c_int64), ("gmres_iters", ctypes.c_int64),
+                ("local_launches", ctypes.c_int64)]
 
 
 class Sizes(ctypes.Structure):
@@ -83,9 +89,12 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_kkt_residual.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(D)]
     lib.sfdp_inspect.argtypes = [P, I, I, VP, ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.sfdp_interface_apply.argtypes = [P, ctypes.c_char, VP, VP]
+    lib.sfdp_timing_enable.argtypes = [P, I]
+    lib.sfdp_kernel_times.argtypes = [P, ctypes.POINTER(Timing)]
     for name in ("sfdp_ctx_create", "sfdp_problem_create", "sfdp_problem_sizes", "sfdp_set_beta",
                  "sfdp_solve_range_space", "sfdp_apply_schur_inv", "sfdp_feti_solve",
-                 "sfdp_apply_operator", "sfdp_kkt_residual", "sfdp_inspect", "sfdp_interface_apply"):
+                 "sfdp_apply_operator", "sfdp_kkt_residual", "sfdp_inspect", "sfdp_interface_apply",
+                 "sfdp_timing_enable", "sfdp_kernel_times"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -228,3 +237,11 @@ class Problem:
         y = torch.zeros(n, dtype=torch.complex128, device=x.device)
         _check(_lib.sfdp_interface_apply(self._h, which.encode(), _ptr(x), _ptr(y)))
         return y
+
+    def timing_enable(self, enable: bool = True):
+        _check(_lib.sfdp_timing_enable(self._h, int(enable)))
+
+    def kernel_times(self):
+        t = Timing()
+        _check(_lib.sfdp_kernel_times(self._h, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in Timing._fields_}
