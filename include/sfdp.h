@@ -87,7 +87,7 @@ typedef struct {
   double tol_inner; /* relative interface residual of each FETI-DP solve
                        [1e-8 FP64, 1e-6 MIXED] */
   int max_outer;    /* outer refinement steps [8] */
-  int max_krylov;   /* GMRES iterations per FETI-DP solve, <= 400 [300] */
+  int max_krylov;   /* GMRES iterations per FETI-DP solve, <= 400 [150] */
 } sfdp_opts;
 
 /* Per-solve report. */

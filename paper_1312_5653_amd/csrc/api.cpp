@@ -97,6 +97,7 @@ sfdp_status build_maps(Problem& p) {
       }
     }
     ndv[s] = nd;
+    p.ndmax = std::max(p.ndmax, nd);
   }
   int nmu = 0;
   std::vector<int> muown, mufree;
@@ -153,8 +154,9 @@ size_t elem_size(const Problem& p) { return p.prec == SFDP_MIXED ? sizeof(cf) : 
 void free_factors(Problem& p) {
   size_t es = elem_size(p);
   dfree(p, p.G, es * p.nsub * p.ml * p.ml * p.ml);
-  dfree(p, p.Sinv, es * p.nsub * p.ND * p.ND);
-  dfree(p, p.Sbb, es * p.nsub * p.ND * p.ND);
+  const size_t PK = (size_t)p.ND * (p.ND + 1) / 2;
+  dfree(p, p.Sinv, es * p.nsub * PK);
+  dfree(p, p.Sbb, sizeof(cf) * p.nsub * PK);
   dfree(p, p.Phi, es * p.nsub * p.ND * 4);
   dfree(p, (void*&)p.Kinv, sizeof(cd) * p.nC * p.nC);
   dfree(p, (void*&)p.Kcc, sizeof(cd) * p.nC * p.nC);
@@ -249,7 +251,7 @@ void defaults(const Problem& p, const sfdp_opts* o, double& tol_kkt, double& tol
   tol_kkt = (o && o->tol_kkt > 0) ? o->tol_kkt : (mixed ? 1e-8 : 1e-10);
   tol_inner = (o && o->tol_inner > 0) ? o->tol_inner : (mixed ? 1e-6 : 1e-8);
   max_outer = (o && o->max_outer > 0) ? o->max_outer : 8;
-  kmax = (o && o->max_krylov > 0) ? std::min(o->max_krylov, KMAX_LIMIT) : 300;
+  kmax = (o && o->max_krylov > 0) ? std::min(o->max_krylov, KMAX_LIMIT) : 150;
 }
 
 sfdp_status check_ready(const Problem* p) {
@@ -293,6 +295,9 @@ sfdp_status sfdp_ctx_create(int device, size_t mem_budget_bytes, void* stream, s
   c->budget = mem_budget_bytes;
   c->stream = (hipStream_t)stream;
   c->num_cu = prop.multiProcessorCount;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    c->max_lds = lds;
   *out = c;
   return SFDP_OK;
 }
@@ -390,9 +395,10 @@ sfdp_status sfdp_set_beta(sfdp_problem* p, double beta) {
   const int ml = p->ml, ND = p->ND, nsub = p->nsub;
   size_t es = elem_size(*p);
   size_t nG = (size_t)nsub * ml * ml * ml, nS = (size_t)nsub * ND * ND, nP = (size_t)nsub * ND * 4;
+  const size_t nPK = (size_t)nsub * ND * (ND + 1) / 2;
   sfdp_status s;
-  if ((s = dalloc(*p, &p->G, es * nG)) || (s = dalloc(*p, &p->Sinv, es * nS)) ||
-      (s = dalloc(*p, &p->Sbb, es * nS)) || (s = dalloc(*p, &p->Phi, es * nP)) ||
+  if ((s = dalloc(*p, &p->G, es * nG)) || (s = dalloc(*p, &p->Sinv, es * nPK)) ||
+      (s = dalloc(*p, &p->Sbb, sizeof(cf) * nPK)) || (s = dalloc(*p, &p->Phi, es * nP)) ||
       (s = dalloc(*p, (void**)&p->Kinv, sizeof(cd) * std::max(p->nC * p->nC, 1))) ||
       (s = dalloc(*p, (void**)&p->Kcc, sizeof(cd) * std::max(p->nC * p->nC, 1))))
     return s;
@@ -636,16 +642,33 @@ sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out,
   std::vector<cd> host((size_t)r * c);
   if (what == SFDP_Q_COARSE) {
     HIPCHK(hipMemcpy(host.data(), p->Kcc, sizeof(cd) * host.size(), hipMemcpyDeviceToHost));
-  } else {
+  } else if (what == SFDP_Q_PHI) {
     size_t es = elem_size(*p);
-    int ld = (what == SFDP_Q_PHI) ? 4 : p->ND;
-    const char* base = (const char*)(what == SFDP_Q_SINV ? p->Sinv : what == SFDP_Q_SBB ? p->Sbb : p->Phi);
-    std::vector<char> raw((size_t)p->ND * ld * es);
-    HIPCHK(hipMemcpy(raw.data(), base + (size_t)sub * p->ND * ld * es, raw.size(), hipMemcpyDeviceToHost));
+    std::vector<char> raw((size_t)p->ND * 4 * es);
+    HIPCHK(hipMemcpy(raw.data(), (const char*)p->Phi + (size_t)sub * p->ND * 4 * es, raw.size(),
+                     hipMemcpyDeviceToHost));
     for (int i = 0; i < r; ++i)
       for (int j = 0; j < c; ++j) {
-        size_t idx = (size_t)i * ld + j;
-        if (p->prec == SFDP_MIXED) {
+        size_t idx = (size_t)i * 4 + j;
+        if (es == sizeof(cf)) {
+          cf v = ((const cf*)raw.data())[idx];
+          host[(size_t)i * c + j] = cd{v.x, v.y};
+        } else {
+          host[(size_t)i * c + j] = ((const cd*)raw.data())[idx];
+        }
+      }
+  } else {
+    // packed lower triangles: Sinv in the storage precision, Sbb in complex64
+    size_t es = (what == SFDP_Q_SBB) ? sizeof(cf) : elem_size(*p);
+    size_t PK = (size_t)p->ND * (p->ND + 1) / 2;
+    const char* base = (const char*)(what == SFDP_Q_SINV ? p->Sinv : p->Sbb);
+    std::vector<char> raw(PK * es);
+    HIPCHK(hipMemcpy(raw.data(), base + (size_t)sub * PK * es, raw.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < c; ++j) {
+        int a = std::max(i, j), b = std::min(i, j);
+        size_t idx = (size_t)a * (a + 1) / 2 + b;
+        if (es == sizeof(cf)) {
           cf v = ((const cf*)raw.data())[idx];
           host[(size_t)i * c + j] = cd{v.x, v.y};
         } else {

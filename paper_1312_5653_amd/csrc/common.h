@@ -13,8 +13,10 @@
 //   G    [nsub][ml][ml][ml]  inverse Schur recursions G_j = T_j^-1 of the line
 //                            block-tridiagonal LDL^T of E^s, stored transposed
 //                            (element (i, k) of G_j at [j][k][i]).
-//   Sinv [nsub][ND][ND]      Z_rr^-1 restricted to Delta (row-major, symmetric)
-//   Sbb  [nsub][ND][ND]      interface Schur complement (its inverse)
+//   Sinv [nsub][PK]          Z_rr^-1 restricted to Delta, packed lower triangle
+//                            (PK = ND (ND + 1) / 2; storage precision)
+//   Sbb  [nsub][PK]          interface Schur complement (its inverse), packed,
+//                            complex64 on both paths (preconditioner only)
 //   Phi  [nsub][ND][4]       Z_rr^-1 Z_rc on Delta rows
 //   Kinv [nC][nC]            inverse of the coarse matrix K_cc* (FP64)
 #pragma once
@@ -162,7 +164,8 @@ struct Maps2 {
 struct Ctx;
 struct Problem {
   Ctx* ctx = nullptr;
-  int dim = 2, N = 0, m = 0, P = 0, nsub = 0, ml = 0, L = 0, ND = 0, nC = 0, nmu = 0;
+  int dim = 2, N = 0, m = 0, P = 0, nsub = 0, ml = 0, L = 0, ND = 0, nC = 0, nmu = 0, ndmax = 0;
+  bool last_resident = false;
   int64_t n_free = 0, n_bdry = 0;
   sfdp_precision prec = SFDP_FP64;
   double beta = 0, alpha = 0;
@@ -210,6 +213,7 @@ struct Ctx {
   size_t budget = 0, used = 0;
   hipStream_t stream = nullptr;
   int num_cu = 0;
+  int max_lds = 65536;  // bytes of LDS one workgroup may allocate
 };
 
 // ---- launchers implemented in the .hip files ----

@@ -272,6 +272,22 @@ __global__ void k_gj_step(int n, int k, const cd* A, cd* B) {
   B[idx] = v;
 }
 
+// Pack the leading nd x nd block of each subdomain's full ND x ND FP64 matrix
+// into lower-triangle row-major storage of the target precision.
+template <class TD>
+__global__ void k_pack(int nsub, int ND, const int* ndv, const cd* src, TD* dst) {
+  const int s = blockIdx.y;
+  const int PK = ND * (ND + 1) / 2;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= PK) return;
+  int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > idx) --i;
+  while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+  int k = idx - i * (i + 1) / 2;
+  cd v = (i < ndv[s]) ? src[((size_t)s * ND + i) * ND + k] : cd{0.0, 0.0};
+  dst[(size_t)s * PK + idx] = TD{(typename real_of<TD>::type)v.x, (typename real_of<TD>::type)v.y};
+}
+
 template <class TS>
 __global__ void k_convert(size_t n, const cd* src, TS* dst) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -335,9 +351,15 @@ hipError_t launch_store_factors(const Problem& p, const cd* G64, const cd* Sinv6
       hipMemcpyAsync(dst, src, n * sizeof(cd), hipMemcpyDeviceToDevice, st);
   };
   conv(nG, G64, p.G);
-  conv(nS, Sinv64, p.Sinv);
-  conv(nS, S64, p.Sbb);
   conv(nP, Phi64, p.Phi);
+  (void)nS;
+  const int PK = p.ND * (p.ND + 1) / 2;
+  dim3 grid((PK + 255) / 256, p.nsub);
+  if (p.prec == SFDP_MIXED)
+    hipLaunchKernelGGL(k_pack<cf>, grid, dim3(256), 0, st, p.nsub, p.ND, p.nd, Sinv64, (cf*)p.Sinv);
+  else
+    hipLaunchKernelGGL(k_pack<cd>, grid, dim3(256), 0, st, p.nsub, p.ND, p.nd, Sinv64, (cd*)p.Sinv);
+  hipLaunchKernelGGL(k_pack<cf>, grid, dim3(256), 0, st, p.nsub, p.ND, p.nd, S64, (cf*)p.Sbb);
   return hipGetLastError();
 }
 

@@ -33,26 +33,25 @@ constexpr int ML = 33;
 constexpr int BAR_GROUPS = 16, BAR_STRIDE = 32, BAR_TOP = BAR_GROUPS * BAR_STRIDE,
               BAR_GEN = BAR_TOP + BAR_STRIDE, BAR_WORDS = BAR_GEN + BAR_STRIDE;
 __device__ inline void grid_barrier(unsigned* bar, unsigned nblocks, unsigned& epoch, int* err) {
-  __syncthreads();  // every wave of the block has finished its stores
+  // Data exchanged between blocks uses agent-scope atomic loads and stores
+  // (ld_coh / st_coh below), which are coherent across the XCDs' L2 caches
+  // without whole-cache write-back or invalidation.  The barrier only has to
+  // order them: every wave waits for its own memory operations to complete,
+  // then one thread arrives and polls.
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
   epoch += 1;
   if (threadIdx.x == 0) {
-    // release the block's stores at agent scope, then arrive (relaxed RMW)
-    __atomic_thread_fence(__ATOMIC_RELEASE);
     const unsigned G = nblocks >= 8 * BAR_GROUPS ? BAR_GROUPS : (nblocks + 7) / 8;
     const unsigned grp = blockIdx.x % G;
     const unsigned gsize = nblocks / G + (grp < nblocks % G ? 1u : 0u);
     unsigned old = __hip_atomic_fetch_add(bar + grp * BAR_STRIDE, 1u, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
     if (old + 1 == epoch * gsize) {
-      // last of its group: acquire the group's stores, release them onward
-      __atomic_thread_fence(__ATOMIC_ACQ_REL);
       unsigned o2 = __hip_atomic_fetch_add(bar + BAR_TOP, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (o2 + 1 == epoch * G) {
-        __atomic_thread_fence(__ATOMIC_ACQ_REL);
+      if (o2 + 1 == epoch * G)
         __hip_atomic_store(bar + BAR_GEN, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
     }
-    // poll without cache maintenance; one acquire fence once the epoch is published
     unsigned spins = 0;
     while (__hip_atomic_load(bar + BAR_GEN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       __builtin_amdgcn_s_sleep(1);
@@ -61,9 +60,20 @@ __device__ inline void grid_barrier(unsigned* bar, unsigned nblocks, unsigned& e
         break;
       }
     }
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
   }
   __syncthreads();
+}
+
+// Coherent (agent-scope) access to data written by one block and read by
+// another inside a persistent launch.
+__device__ inline cd ld_coh(const cd* p) {
+  double x = __hip_atomic_load((const double*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double y = __hip_atomic_load((const double*)p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return cd{x, y};
+}
+__device__ inline void st_coh(cd* p, cd v) {
+  __hip_atomic_store((double*)p, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((double*)p + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // out[i] = sum_q part[i * nb + q] for i < n, in a fixed order (identical in every
@@ -78,7 +88,7 @@ __device__ inline void reduce_partials(const cd* __restrict__ part, int nb, int 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int i = i0 + u, q = lane + 64 * r;
-        v[u][r] = (i < n && q < nb) ? part[(size_t)i * nb + q] : cd{0.0, 0.0};
+        v[u][r] = (i < n && q < nb) ? ld_coh(part + (size_t)i * nb + q) : cd{0.0, 0.0};
       }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -110,42 +120,62 @@ __device__ inline void block_dots(const cd* __restrict__ Q, int nmu, int k0, int
       acc.x += __shfl_xor(acc.x, off, 64);
       acc.y += __shfl_xor(acc.y, off, 64);
     }
-    if (g == 0 && i < nvec) part[(size_t)i * nb + b] = acc;
+    if (g == 0 && i < nvec) st_coh(part + (size_t)i * nb + b, acc);
   }
 }
 
 // ------------------------------------------------------------------------------------------
 // Dense products on LDS vectors.
 
-// y[i] = sum_k A[k*ND + i] x[k] for i < nd (A symmetric, row-major, stride ND).
-// 256 threads; rows across lanes (coalesced), the k range split across thread groups.
-template <class TS>
-__device__ inline void symv_block(const TS* __restrict__ A, int ND, int nd, const TS* xs,
-                                  cd* red, cd* y) {
-  using R = typename real_of<TS>::type;
-  constexpr int KB = 16;  // loads in flight per thread
-  const int rows = ND < 256 ? ND : 256;
-  const int nsplit = 256 / rows;
-  const int i = threadIdx.x % rows, part = threadIdx.x / rows;
-  const int klen = (nd + nsplit - 1) / nsplit;
+// Packed symmetric storage: the lower triangle of an n_d x n_d symmetric matrix,
+// row-major, entry (i, k), k <= i, at i (i + 1) / 2 + k.  Per subdomain the
+// blocks are PK = ND (ND + 1) / 2 entries apart.
+__host__ __device__ inline int packed_len(int n) { return n * (n + 1) / 2; }
+
+// y[i] = sum_k S(i, k) x[k] for i < nd <= 128 with S packed in LDS.  Thread
+// (i, half) sums half of the k range (row part k <= i read along the row,
+// column part k > i read down the column), partial sums combined through red.
+template <class TM, class R>
+__device__ inline void symv_packed(const TM* A, int nd, const C<R>* xs, cd* red, cd* y) {
+  const int i = threadIdx.x & 127, half = threadIdx.x >> 7;
+  const int h = (nd + 1) / 2;
+  const int k0 = half ? h : 0, k1 = half ? nd : h;
   C<R> acc{0, 0};
-  if (part < nsplit && i < nd) {
-    int k0 = part * klen, k1 = min(nd, k0 + klen);
-    for (int kb = k0; kb < k1; kb += KB) {
-      TS v[KB];
-#pragma unroll
-      for (int u = 0; u < KB; ++u) v[u] = (kb + u < k1) ? A[(size_t)(kb + u) * ND + i] : TS{0, 0};
-#pragma unroll
-      for (int u = 0; u < KB; ++u)
-        if (kb + u < k1) fma_acc(acc, v[u], xs[kb + u]);
+  if (i < nd) {
+    const int rb = i * (i + 1) / 2;
+    const int kr = min(k1, i + 1);
+    for (int k = k0; k < kr; ++k) fma_acc(acc, cvt<R>(A[rb + k]), xs[k]);
+    int k = max(k0, i + 1);
+    int cb = k * (k + 1) / 2;
+    for (; k < k1; ++k) {
+      fma_acc(acc, cvt<R>(A[cb + i]), xs[k]);
+      cb += k + 1;
     }
   }
   red[threadIdx.x] = cd{(double)acc.x, (double)acc.y};
   __syncthreads();
-  if (threadIdx.x < nd) {
-    cd s{0.0, 0.0};
-    for (int q = 0; q < nsplit; ++q) s = s + red[q * rows + threadIdx.x];
-    y[threadIdx.x] = s;
+  if (threadIdx.x < nd) y[threadIdx.x] = red[threadIdx.x] + red[128 + threadIdx.x];
+  __syncthreads();
+}
+
+// Coalesced bulk copy global -> LDS in 16-byte words, eight loads in flight per
+// thread.  `bytes` is rounded up to 16 (the global blocks are padded).
+__device__ inline void stage_lds(void* dst, const void* __restrict__ src, int bytes) {
+  const uint4* s4 = (const uint4*)src;
+  uint4* d4 = (uint4*)dst;
+  const int n16 = (bytes + 15) / 16;
+  for (int i0 = threadIdx.x; i0 < n16; i0 += 256 * 8) {
+    uint4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int i = i0 + u * 256;
+      if (i < n16) v[u] = s4[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int i = i0 + u * 256;
+      if (i < n16) d4[i] = v[u];
+    }
   }
   __syncthreads();
 }
@@ -420,54 +450,58 @@ __global__ void k_assemble(Geo2 g, Maps2 mp, const cd* Ubuf, const cd* uc, cd* x
 // Interface phases (device functions shared by the persistent GMRES kernel and
 // the stand-alone test kernels).
 
-// Abuf[s] = S_bb^s x,  x_i = 0.5 * sc * sign_i * vin[mid_i]   (W = 1/2)
+// Abuf[s] = S_bb^s x,  x_i = 0.5 * sc * sign_i * vin[mid_i]   (W = 1/2).
+// S_bb is complex64 (packed); it is staged into `buf` unless `resident`.
 template <class TS>
-__device__ void phase_precond(const Geo2& g, const Maps2& mp, const TS* __restrict__ Sbb, int s,
-                              const cd* vin, double sc, cd* Abuf, typename real_of<TS>::type* xs_raw,
-                              cd* red, cd* ys) {
+__device__ void phase_precond(const Geo2& g, const Maps2& mp, const cf* __restrict__ Sbb, int s,
+                              const cd* vin, double sc, cd* Abuf, cf* buf, bool resident,
+                              typename real_of<TS>::type* xs_raw, cd* red, cd* ys) {
   using R = typename real_of<TS>::type;
   using T = C<R>;
   T* xs = (T*)xs_raw;
   const int ND = g.ND, nd = mp.nd[s];
   __syncthreads();
+  if (!resident) stage_lds(buf, Sbb + (size_t)s * packed_len(ND), packed_len(nd) * (int)sizeof(cf));
   for (int i = threadIdx.x; i < ND; i += blockDim.x) {
     T v{0, 0};
     if (i < nd) {
-      cd m = (0.5 * sc * mp.dsgn[s * ND + i]) * vin[mp.dmid[s * ND + i]];
+      cd m = (0.5 * sc * mp.dsgn[s * ND + i]) * ld_coh(vin + mp.dmid[s * ND + i]);
       v = T{(R)m.x, (R)m.y};
     }
     xs[i] = v;
   }
   __syncthreads();
-  symv_block<TS>(Sbb + (size_t)s * ND * ND, ND, nd, xs, red, ys);
-  for (int i = threadIdx.x; i < nd; i += blockDim.x) Abuf[(size_t)s * ND + i] = ys[i];
+  symv_packed<cf, R>(buf, nd, xs, red, ys);
+  for (int i = threadIdx.x; i < nd; i += blockDim.x) st_coh(Abuf + (size_t)s * ND + i, ys[i]);
 }
 
 // Ybuf[s] = Z_rr^-1|Delta x, Cbuf[s] = Phi^T x.   x from Abuf (preconditioned
-// vector, from_abuf) or directly x_i = sign_i * vin[mid_i].
+// vector, from_abuf) or directly x_i = sign_i * vin[mid_i].  Sinv (packed, in the
+// storage precision) is staged into `buf` unless `resident`.
 template <class TS>
 __device__ void phase_f1(const Geo2& g, const Maps2& mp, const TS* __restrict__ Sinv,
                          const TS* __restrict__ Phi, int s, bool from_abuf, const cd* Abuf,
-                         const cd* vin, cd* Ybuf, cd* Cbuf, typename real_of<TS>::type* xs_raw,
-                         cd* red, cd* ys) {
+                         const cd* vin, cd* Ybuf, cd* Cbuf, TS* buf, bool resident,
+                         typename real_of<TS>::type* xs_raw, cd* red, cd* ys) {
   using R = typename real_of<TS>::type;
   using T = C<R>;
   T* xs = (T*)xs_raw;
   const int ND = g.ND, nd = mp.nd[s];
   __syncthreads();
+  if (!resident) stage_lds(buf, Sinv + (size_t)s * packed_len(ND), packed_len(nd) * (int)sizeof(TS));
   for (int i = threadIdx.x; i < ND; i += blockDim.x) {
     T v{0, 0};
     if (i < nd) {
       cd m;
-      if (from_abuf) m = 0.5 * (Abuf[(size_t)s * ND + i] - Abuf[mp.dpart[s * ND + i]]);
-      else m = (double)mp.dsgn[s * ND + i] * vin[mp.dmid[s * ND + i]];
+      if (from_abuf) m = 0.5 * (ld_coh(Abuf + (size_t)s * ND + i) - ld_coh(Abuf + mp.dpart[s * ND + i]));
+      else m = (double)mp.dsgn[s * ND + i] * ld_coh(vin + mp.dmid[s * ND + i]);
       v = T{(R)m.x, (R)m.y};
     }
     xs[i] = v;
   }
   __syncthreads();
-  symv_block<TS>(Sinv + (size_t)s * ND * ND, ND, nd, xs, red, ys);
-  for (int i = threadIdx.x; i < nd; i += blockDim.x) Ybuf[(size_t)s * ND + i] = ys[i];
+  symv_packed<TS, R>(buf, nd, xs, red, ys);
+  for (int i = threadIdx.x; i < nd; i += blockDim.x) st_coh(Ybuf + (size_t)s * ND + i, ys[i]);
   // corner products: one wavefront per corner slot
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   cd acc{0.0, 0.0};
@@ -481,7 +515,7 @@ __device__ void phase_f1(const Geo2& g, const Maps2& mp, const TS* __restrict__ 
     acc.x += __shfl_down(acc.x, off, 64);
     acc.y += __shfl_down(acc.y, off, 64);
   }
-  if (lane == 0) Cbuf[s * 4 + q] = acc;
+  if (lane == 0) st_coh(Cbuf + s * 4 + q, acc);
 }
 
 // Ybuf[s] += Phi uc_own with uc = K_cc*^-1 g, g_c = sum of Cbuf over the corner's owners.
@@ -495,7 +529,7 @@ __device__ void phase_f2(const Geo2& g, const Maps2& mp, const TS* __restrict__ 
     cd v{0.0, 0.0};
     for (int o = 0; o < 4; ++o) {
       int own = mp.cown[c * 4 + o];
-      if (own >= 0) v = v + Cbuf[own];
+      if (own >= 0) v = v + ld_coh(Cbuf + own);
     }
     gsh[c] = v;
   }
@@ -512,12 +546,12 @@ __device__ void phase_f2(const Geo2& g, const Maps2& mp, const TS* __restrict__ 
   if (lane == 0) ucs[q] = acc;
   __syncthreads();
   for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-    cd y = Ybuf[(size_t)s * ND + i];
+    cd y = ld_coh(Ybuf + (size_t)s * ND + i);
     for (int qq = 0; qq < 4; ++qq) {
       if (mp.cgid[s * 4 + qq] < 0) continue;
       fma_acc(y, cvt<double>(Phi[((size_t)s * ND + i) * 4 + qq]), ucs[qq]);
     }
-    Ybuf[(size_t)s * ND + i] = y;
+    st_coh(Ybuf + (size_t)s * ND + i, y);
   }
 }
 
@@ -539,15 +573,21 @@ struct GmresArgs {
   double tol;
   int kmax;
   int chunk;
+  int resident;     // Schur blocks kept in LDS (requires one subdomain per block)
+  int lds_bufA;     // byte offset of the second resident buffer
 };
 
+// Dynamic LDS of k_gmres: work arrays, then the Schur-block buffers (two
+// resident blocks, or one staging buffer).
+__host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
 template <class TS>
-__global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __restrict__ Sbb,
+__global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __restrict__ Sbb,
                                                const TS* __restrict__ Sinv,
                                                const TS* __restrict__ Phi,
                                                const cd* __restrict__ Kinv, GmresArgs a) {
   using R = typename real_of<TS>::type;
-  extern __shared__ char smem[];
+  extern __shared__ __align__(16) char smem[];
   // dynamic LDS layout
   cd* red = (cd*)smem;                          // 256
   cd* ys = red + 256;                           // ND (<= 256)
@@ -560,6 +600,15 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
   cd* snv = csv + a.kmax;                       // kmax
   cd* gv = snv + a.kmax;                        // kmax + 1
   cd* ucs = gv + a.kmax + 1;                    // 4
+  char* mats = (char*)(ucs + 4);
+  cf* bufS = (cf*)mats;                         // S_bb (resident) or the staging buffer
+  TS* bufI = a.resident ? (TS*)(mats + a.lds_bufA) : (TS*)mats;  // Z_rr^-1|Delta
+  if (a.resident) {
+    // one subdomain per block: both Schur blocks stay in LDS for the whole solve
+    const int s = blockIdx.x, nd = mp.nd[s];
+    stage_lds(bufS, Sbb + (size_t)s * packed_len(g.ND), packed_len(nd) * (int)sizeof(cf));
+    stage_lds(bufI, Sinv + (size_t)s * packed_len(g.ND), packed_len(nd) * (int)sizeof(TS));
+  }
   __shared__ double sc_sh[4];
   __shared__ int stop_sh;
 
@@ -588,7 +637,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
     double loc = 0.0;
     for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) loc += abs2(a.d[k]);
     double t = block_sum_real(loc);
-    if (threadIdx.x == 0) part2[b] = cd{t, 0.0};
+    if (threadIdx.x == 0) st_coh(part2 + b, cd{t, 0.0});
   }
   grid_barrier(a.bar, nb, epoch, a.flags + 1);
   reduce_partials(part2, nb, 1, ucs);
@@ -607,13 +656,14 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
   for (j = 0; j < kmax; ++j) {
     // ---- P: Abuf = S_bb (W B^T q_j); also store q_j = vin * vscale
     for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
-      a.Q[(size_t)j * nmu + k] = vscale * vin[k];
+      a.Q[(size_t)j * nmu + k] = vscale * ld_coh(vin + k);
     for (int s = b; s < g.nsub; s += nb)
-      phase_precond<TS>(g, mp, Sbb, s, vin, vscale, a.Abuf, xs, red, ys);
+      phase_precond<TS>(g, mp, Sbb, s, vin, vscale, a.Abuf, bufS, a.resident, xs, red, ys);
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
     // ---- F1
     for (int s = b; s < g.nsub; s += nb)
-      phase_f1<TS>(g, mp, Sinv, Phi, s, true, a.Abuf, nullptr, a.Ybuf, a.Cbuf, xs, red, ys);
+      phase_f1<TS>(g, mp, Sinv, Phi, s, true, a.Abuf, nullptr, a.Ybuf, a.Cbuf, bufI, a.resident, xs,
+                   red, ys);
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
     // ---- F2 (coarse correction)
     for (int s = b; s < g.nsub; s += nb) phase_f2<TS>(g, mp, Phi, Kinv, s, a.Cbuf, a.Ybuf, gsh, ucs);
@@ -621,7 +671,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
     // ---- O1: w = B_r Y (combine), first Gram-Schmidt projections
     for (int k = threadIdx.x; k < kn; k += blockDim.x) {
       int kk = k0 + k;
-      wch[k] = a.Ybuf[mp.muown[2 * kk]] - a.Ybuf[mp.muown[2 * kk + 1]];
+      wch[k] = ld_coh(a.Ybuf + mp.muown[2 * kk]) - ld_coh(a.Ybuf + mp.muown[2 * kk + 1]);
     }
     __syncthreads();
     block_dots(a.Q, nmu, k0, kn, j + 1, wch, part0, nb, b);
@@ -644,12 +694,12 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
       cd v = wch[k];
 #pragma unroll 8
       for (int i = 0; i <= j; ++i) v = v - h2[i] * a.Q[(size_t)i * nmu + k0 + k];
-      a.w[k0 + k] = v;
+      st_coh(a.w + k0 + k, v);
       loc += abs2(v);
     }
     for (int i = threadIdx.x; i <= j; i += blockDim.x) hv[i] = hv[i] + h2[i];
     double t = block_sum_real(loc);
-    if (threadIdx.x == 0) part2[b] = cd{t, 0.0};
+    if (threadIdx.x == 0) st_coh(part2 + b, cd{t, 0.0});
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
     // ---- Arnoldi column j complete: hn, Givens rotations (identical in every block)
     reduce_partials(part2, nb, 1, ucs);
@@ -679,7 +729,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
     }
     __syncthreads();
     if (b == 0)
-      for (int i = threadIdx.x; i <= j; i += blockDim.x) a.H[(size_t)i * kmax + j] = hv[i];
+      for (int i = threadIdx.x; i <= j; i += blockDim.x) st_coh(a.H + (size_t)i * kmax + j, hv[i]);
     resid = sc_sh[0];
     iters = j + 1;
     if (stop_sh) break;
@@ -692,10 +742,10 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
   for (int i = threadIdx.x; i < kk; i += blockDim.x) h2[i] = gv[i];
   __syncthreads();
   for (int i = kk - 1; i >= 0; --i) {
-    if (threadIdx.x == 0) h2[i] = cdiv(h2[i], a.H[(size_t)i * kmax + i]);
+    if (threadIdx.x == 0) h2[i] = cdiv(h2[i], ld_coh(a.H + (size_t)i * kmax + i));
     __syncthreads();
     cd yi = h2[i];
-    for (int t = threadIdx.x; t < i; t += blockDim.x) h2[t] = h2[t] - a.H[(size_t)t * kmax + i] * yi;
+    for (int t = threadIdx.x; t < i; t += blockDim.x) h2[t] = h2[t] - ld_coh(a.H + (size_t)t * kmax + i) * yi;
     __syncthreads();
   }
   // t = Q y on the chunk
@@ -703,14 +753,15 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
     cd v{0.0, 0.0};
 #pragma unroll 8
     for (int i = 0; i < kk; ++i) fma_acc(v, a.Q[(size_t)i * nmu + k0 + k], h2[i]);
-    a.w[k0 + k] = v;
+    st_coh(a.w + k0 + k, v);
   }
   grid_barrier(a.bar, nb, epoch, a.flags + 1);
   // mu = P^-1 t
-  for (int s = b; s < g.nsub; s += nb) phase_precond<TS>(g, mp, Sbb, s, a.w, 1.0, a.Abuf, xs, red, ys);
+  for (int s = b; s < g.nsub; s += nb)
+    phase_precond<TS>(g, mp, Sbb, s, a.w, 1.0, a.Abuf, bufS, a.resident, xs, red, ys);
   grid_barrier(a.bar, nb, epoch, a.flags + 1);
   for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
-    a.mu[k] = 0.5 * (a.Abuf[mp.muown[2 * k]] - a.Abuf[mp.muown[2 * k + 1]]);
+    a.mu[k] = 0.5 * (ld_coh(a.Abuf + mp.muown[2 * k]) - ld_coh(a.Abuf + mp.muown[2 * k + 1]));
   if (b == 0 && threadIdx.x == 0) {
     a.flags[0] = iters;
     a.scal[0] = resid;
@@ -719,20 +770,23 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const TS* __res
 
 // Stand-alone interface kernels for testing (one block per subdomain).
 template <class TS>
-__global__ void __launch_bounds__(256) k_iface_precond(Geo2 g, Maps2 mp, const TS* Sbb, const cd* x,
+__global__ void __launch_bounds__(256) k_iface_precond(Geo2 g, Maps2 mp, const cf* Sbb, const cd* x,
                                                        cd* Abuf) {
   using R = typename real_of<TS>::type;
+  extern __shared__ __align__(16) char smem[];
   __shared__ cd red[256], ys[256];
   __shared__ R xs[512];
-  phase_precond<TS>(g, mp, Sbb, blockIdx.x, x, 1.0, Abuf, xs, red, ys);
+  phase_precond<TS>(g, mp, Sbb, blockIdx.x, x, 1.0, Abuf, (cf*)smem, false, xs, red, ys);
 }
 template <class TS>
 __global__ void __launch_bounds__(256) k_iface_f1(Geo2 g, Maps2 mp, const TS* Sinv, const TS* Phi,
                                                   const cd* x, cd* Ybuf, cd* Cbuf) {
   using R = typename real_of<TS>::type;
+  extern __shared__ __align__(16) char smem[];
   __shared__ cd red[256], ys[256];
   __shared__ R xs[512];
-  phase_f1<TS>(g, mp, Sinv, Phi, blockIdx.x, false, nullptr, x, Ybuf, Cbuf, xs, red, ys);
+  phase_f1<TS>(g, mp, Sinv, Phi, blockIdx.x, false, nullptr, x, Ybuf, Cbuf, (TS*)smem, false, xs,
+               red, ys);
 }
 template <class TS>
 __global__ void __launch_bounds__(256) k_iface_f2(Geo2 g, Maps2 mp, const TS* Phi, const cd* Kinv,
@@ -783,9 +837,17 @@ hipError_t launch_fetidp_rhs(const Problem& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-static size_t gmres_lds(const Problem& p, int kmax, int chunk) {
+static size_t gmres_work_lds(const Problem& p, int kmax, int chunk) {
   return sizeof(cd) * (256 + 256) + sizeof(double) * 512 +
          sizeof(cd) * (p.nC + chunk + 5 * (size_t)(kmax + 1) + 4);
+}
+// Total LDS, and the offset of the second resident buffer.
+static size_t gmres_lds(const Problem& p, int kmax, int chunk, bool resident, size_t* offB) {
+  size_t es = p.prec == SFDP_MIXED ? sizeof(cf) : sizeof(cd);
+  size_t pk = (size_t)packed_len(p.ndmax);
+  size_t a = align16(pk * sizeof(cf)), b = align16(pk * es);
+  if (offB) *offB = a;
+  return align16(gmres_work_lds(p, kmax, chunk)) + (resident ? a + b : std::max(a, b));
 }
 
 template <class TS>
@@ -793,6 +855,11 @@ static hipError_t gmres_t(Problem& p, double tol, int kmax) {
   hipStream_t st = p.ctx->stream;
   int nb = p.gmres_blocks;
   int chunk = (p.nmu + nb - 1) / nb;
+  size_t offB = 0;
+  bool resident = p.prec == SFDP_MIXED && nb == p.nsub &&
+                  gmres_lds(p, kmax, chunk, true, &offB) <= (size_t)p.ctx->max_lds;
+  size_t lds = gmres_lds(p, kmax, chunk, resident, &offB);
+  if (lds > (size_t)p.ctx->max_lds) return hipErrorOutOfMemory;
   GmresArgs a;
   a.d = p.dvec;
   a.mu = p.mu;
@@ -809,16 +876,20 @@ static hipError_t gmres_t(Problem& p, double tol, int kmax) {
   a.tol = tol;
   a.kmax = kmax;
   a.chunk = chunk;
+  a.resident = resident ? 1 : 0;
+  a.lds_bufA = (int)offB;
   hipError_t e = launch_fill(p.bar, BAR_WORDS * sizeof(unsigned), st);
   if (e != hipSuccess) return e;
   Geo2 g = p.geo();
   Maps2 mp = p.maps();
-  const TS* Sbb = (const TS*)p.Sbb;
+  const cf* Sbb = (const cf*)p.Sbb;
   const TS* Sinv = (const TS*)p.Sinv;
   const TS* Phi = (const TS*)p.Phi;
   const cd* Kinv = p.Kinv;
   void* args[] = {&g, &mp, &Sbb, &Sinv, &Phi, &Kinv, &a};
-  size_t lds = gmres_lds(p, kmax, chunk);
+  e = hipFuncSetAttribute((const void*)k_gmres<TS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  p.last_resident = resident;
   return hipLaunchCooperativeKernel((const void*)k_gmres<TS>, dim3(nb), dim3(256), args, lds, st);
 }
 
@@ -829,19 +900,22 @@ hipError_t launch_gmres(Problem& p, double tol, int kmax, hipStream_t) {
 
 int gmres_max_blocks(const Problem& p, int kmax) {
   int per_cu = 0;
-  int chunk = (p.nmu + p.nsub - 1) / p.nsub;
-  size_t lds = gmres_lds(p, kmax, chunk);
+  int chunk = (p.nmu + p.gmres_blocks - 1) / p.gmres_blocks;
+  size_t lds = gmres_lds(p, kmax, chunk, false, nullptr);
   hipError_t e;
-  if (p.prec == SFDP_MIXED)
+  if (p.prec == SFDP_MIXED) {
+    hipFuncSetAttribute((const void*)k_gmres<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_gmres<cf>, 256, lds);
-  else
+  } else {
+    hipFuncSetAttribute((const void*)k_gmres<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_gmres<cd>, 256, lds);
+  }
   if (e != hipSuccess || per_cu < 1) return 0;
   return per_cu * p.ctx->num_cu;
 }
 
 size_t gmres_lds_bytes(const Problem& p, int kmax, int nb) {
-  return gmres_lds(p, kmax, (p.nmu + nb - 1) / nb);
+  return gmres_lds(p, kmax, (p.nmu + nb - 1) / nb, false, nullptr);
 }
 
 hipError_t launch_recover_coarse(const Problem& p, hipStream_t st) {
@@ -869,12 +943,18 @@ static hipError_t iface_t(Problem& p, char which, const cd* x, cd* y, hipStream_
   Geo2 g = p.geo();
   Maps2 mp = p.maps();
   if (which == 'P') {
-    hipLaunchKernelGGL(k_iface_precond<TS>, dim3(p.nsub), dim3(256), 0, st, g, mp, (const TS*)p.Sbb,
+    size_t bytes = align16((size_t)packed_len(p.ND) * sizeof(cf));
+    hipFuncSetAttribute((const void*)k_iface_precond<TS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)bytes);
+    hipLaunchKernelGGL(k_iface_precond<TS>, dim3(p.nsub), dim3(256), bytes, st, g, mp, (const cf*)p.Sbb,
                        x, p.Abuf);
     // the stand-alone precond kernel scales by 1/2 on the way in; 1/2 on the way out
     hipLaunchKernelGGL(k_combine, dim3((p.nmu + 255) / 256), dim3(256), 0, st, g, mp, p.Abuf, 0.5, y);
   } else if (which == 'F') {
-    hipLaunchKernelGGL(k_iface_f1<TS>, dim3(p.nsub), dim3(256), 0, st, g, mp, (const TS*)p.Sinv,
+    size_t bytes = align16((size_t)packed_len(p.ND) * sizeof(TS));
+    hipFuncSetAttribute((const void*)k_iface_f1<TS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)bytes);
+    hipLaunchKernelGGL(k_iface_f1<TS>, dim3(p.nsub), dim3(256), bytes, st, g, mp, (const TS*)p.Sinv,
                        (const TS*)p.Phi, x, p.Ybuf, p.Cbuf);
     hipLaunchKernelGGL(k_iface_f2<TS>, dim3(p.nsub), dim3(256), sizeof(cd) * (p.nC + 1), st, g, mp,
                        (const TS*)p.Phi, p.Kinv, p.Cbuf, p.Ybuf);

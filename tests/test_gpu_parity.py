@@ -76,7 +76,8 @@ def test_local_operators_and_coarse_match_definitions(sf, N, m, beta):
         ref_sinv = pc["Zrr_inv"][np.ix_(isd, isd)]
         assert sinv.shape == ref_sinv.shape
         assert np.abs(sinv - ref_sinv).max() / np.abs(ref_sinv).max() < 1e-12
-        assert np.abs(sbb - pc["Sbb"]).max() / np.abs(pc["Sbb"]).max() < 1e-11
+        # S_bb is stored in complex64 on both paths (it only preconditions)
+        assert np.abs(sbb - pc["Sbb"]).max() / np.abs(pc["Sbb"]).max() < 1e-6
         ref_phi = pc["Phi"][isd]
         assert np.abs(phi - ref_phi).max() / np.abs(ref_phi).max() < 1e-12
     kc = prob.inspect(sfdp.Q_COARSE).cpu().numpy()
@@ -99,7 +100,8 @@ def test_interface_operators_match_definitions(sf, precision):
     F = prob.interface_apply("F", _t(mu)).cpu().numpy()
     assert _rel(F, feti.fetidp_apply(ops, mu)) < tol
     P = prob.interface_apply("P", _t(mu)).cpu().numpy()
-    assert _rel(P, feti.dirichlet_preconditioner(dec, ops) @ mu) < tol
+    # the preconditioner's S_bb is complex64 on both paths
+    assert _rel(P, feti.dirichlet_preconditioner(dec, ops) @ mu) < 1e-5
     f = W.random_vector(mesh.n, 6, complex_=True)
     d = prob.interface_apply("D", _t(f)).cpu().numpy()
     dref, _, _ = feti.fetidp_rhs(dec, ops, f)
