@@ -5,10 +5,13 @@ Workload (the paper's thermal problem family, Sec. 6.1, at the 512^2 size):
 2D unit square, Q1 Poisson, 512 x 512 cells (261,121 free dofs), 16 x 16
 subdomains of 32 x 32 cells, beta = 1e-4, target ybar = 16 sine modes
 sin(k pi x) sin(l pi y), k, l in 1..4, N(0,1) coefficients (seed 0), y_c = 0.
-One step = one range-space Schur solve (two-factor complex factorization,
-FETI-DP per factor, FP64 refinement) to relative KKT residual <= 1e-8, with
-the subdomain factors resident (sfdp_set_beta is done once, outside the timed
-region, and reported as setup_ms).
+One step = one call that solves a batch of B targets (16-mode sine targets,
+seeds 0..B-1), each a range-space Schur solve (two-factor complex
+factorization, FETI-DP per factor, FP64 refinement) to relative KKT residual
+<= 1e-8, with the subdomain factors resident (sfdp_set_beta is done once,
+outside the timed region, and reported as setup_ms).  The B targets of a step
+share every launch (opts.batch = B).  The headline is mixed precision at
+B = 4; single-target latency (B = 1) and the FP64 path are measured beside it.
 
 Prints one JSON line.  --gpus > 1 is not supported (one process, one GPU).
 """
@@ -25,26 +28,39 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def gmres_bytes_per_iteration(N, m, nmu, ncorner, elem_bytes, mean_its):
-    """Algorithmic bytes one GMRES iteration of the interface solve must move.
-
-    Per subdomain: the packed symmetric interface Schur complement and its
-    inverse (n_d (n_d + 1) entries together) and Phi (n_d x n_c), in the storage
-    precision; the coarse inverse once (n_C^2 FP64 complex); the Krylov basis
-    for classical Gram-Schmidt twice (4 (j + 1) vectors read at step j, mean
-    over the launch) plus 6 vector reads/writes, FP64 complex.
-    """
+def gmres_operator_bytes(N, m, ncorner, elem_bytes):
+    """Operator bytes one GMRES loop trip must pass over, shared by all the
+    right-hand sides of the launch: per subdomain the packed symmetric
+    interface Schur complement (complex64) and the packed Z_rr^-1|Delta
+    (storage precision), n_d (n_d + 1) / 2 entries each, and Phi (n_d x n_c,
+    storage precision); the coarse inverse once (n_C^2 FP64 complex)."""
     P = N // m
     tot = 0
     for sy in range(P):
         for sx in range(P):
             nd = sum(m - 1 for side in (sx > 0, sx < P - 1, sy > 0, sy < P - 1) if side)
             nc = sum(1 for cx in (sx, sx + 1) for cy in (sy, sy + 1) if 0 < cx < P and 0 < cy < P)
-            tot += (nd * (nd + 1) + nd * nc) * elem_bytes
-    tot += ncorner * ncorner * 16
+            tot += nd * (nd + 1) // 2 * (8 + elem_bytes) + nd * nc * elem_bytes
+    return tot + ncorner * ncorner * 16
+
+
+def gmres_vector_bytes(nmu, mean_its):
+    """Vector bytes of one GMRES iteration of one right-hand side (FP64
+    complex): the Krylov basis read twice for classical Gram-Schmidt run twice
+    (4 (j + 1) vectors at step j, j averaged over the solve) and six further
+    vector reads or writes."""
     jmean = (mean_its - 1) / 2.0
-    tot += (4 * (jmean + 1) + 6) * nmu * 16
-    return tot
+    return (4 * (jmean + 1) + 6) * nmu * 16
+
+
+def local_solve_bytes(N, m, elem_bytes):
+    """Bytes one subdomain-solve launch must read per right-hand side: the
+    line factors of every subdomain (m + 1 lines of (m + 1)^2 entries), once
+    in the forward and once in the backward sweep, plus the load vector and
+    the result (FP64 complex)."""
+    P = N // m
+    ml = m + 1
+    return P * P * ml * ml * ml * elem_bytes * 2 + 2 * (N - 1) ** 2 * 16
 
 
 def cpu_baseline(N, m, beta, ybar, budget_s=15.0):
@@ -72,7 +88,8 @@ def cpu_baseline(N, m, beta, ybar, budget_s=15.0):
             "factor_s": t_factor, "solve_s": t_solve, "host_threads": os.cpu_count()}
 
 
-def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup, tol_kkt, tol_inner):
+def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup, tol_kkt, tol_inner,
+                  batch, max_krylov=0):
     p = sfdp.Problem(ctx, 2, N, m, precision)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -82,8 +99,10 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
     y = torch.empty_like(ybar_t)
     u = torch.empty_like(ybar_t)
     lam = torch.empty_like(ybar_t)
+    nb = ybar_t.shape[0]
     for _ in range(warmup):
-        p.solve_range_space(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner)
+        p.solve_range_space(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch,
+                            max_krylov=max_krylov)
     p.timing_enable(True)
     lat, rhos, its = [], [], []
     torch.cuda.synchronize()
@@ -91,12 +110,12 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
     for _ in range(steps):
         t0 = time.perf_counter()
         _, _, _, info, st = p.solve_range_space(ybar_t, None, y, u, lam, tol_kkt=tol_kkt,
-                                                tol_inner=tol_inner)
+                                                tol_inner=tol_inner, batch=batch, max_krylov=max_krylov)
         lat.append(time.perf_counter() - t0)
-        rhos.append(info[0]["rel_kkt"])
-        its.append(info[0]["krylov_total"])
+        rhos.extend(i["rel_kkt"] for i in info)
+        its.extend(i["krylov_total"] for i in info)
         if st != 0:
-            raise RuntimeError(f"solve did not converge: {info[0]}")
+            raise RuntimeError(f"solve did not converge: {info}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_all
     kt = p.kernel_times()
@@ -105,7 +124,7 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
     p.close()
     lat_ms = sorted(x * 1e3 for x in lat)
     q = lambda f: lat_ms[min(len(lat_ms) - 1, int(round(f * (len(lat_ms) - 1))))]
-    return {"solves_per_s": steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+    return {"solves_per_s": nb * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps, "batch": nb,
             "p50_ms": q(0.5), "p99_ms": q(0.99), "setup_ms": setup_ms,
             "max_rel_kkt": max(rhos), "krylov_per_solve": statistics.mean(its),
             "kernel_times": kt, "sizes": sizes}
@@ -121,6 +140,9 @@ def main():
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--batch", type=int, default=4, help="targets per step (1..4)")
+    ap.add_argument("--max-krylov", type=int, default=0,
+                    help="GMRES iteration cap per FETI-DP solve (0: library default)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world > 1:
@@ -131,27 +153,40 @@ def main():
     import torch
     from paper_1312_5653_amd import sfdp, workloads
 
-    N, m, beta = args.N, args.m, args.beta
-    modes, coefs = workloads.modes_for("sixteen2d", 0)
-    ybar, _ = workloads.sine_target(2, N, modes, coefs)
+    N, m, beta, B = args.N, args.m, args.beta, args.batch
+    if not 1 <= B <= 4:
+        print("--batch must be in 1..4", file=sys.stderr)
+        sys.exit(2)
+    ybar = np.stack([workloads.sine_target(2, N, *workloads.modes_for("sixteen2d", s))[0]
+                     for s in range(B)])
     ybar_t = torch.tensor(ybar, device="cuda:0")
+    ybar1_t = ybar_t[:1].contiguous()
     ctx = sfdp.Context(0)
     tol_kkt = 1e-8
     res = {}
+    precs = [("fp64", sfdp.SFDP_FP64, 1e-13)]
     if not args.fp64_only:
-        res["mixed"] = run_precision(sfdp, torch, ctx, sfdp.SFDP_MIXED, N, m, beta, ybar_t,
-                                     args.steps, args.warmup, tol_kkt, 1e-6)
-    res["fp64"] = run_precision(sfdp, torch, ctx, sfdp.SFDP_FP64, N, m, beta, ybar_t,
-                                args.steps, args.warmup, tol_kkt, 1e-13)
-    head = "mixed" if "mixed" in res else "fp64"
+        precs.insert(0, ("mixed", sfdp.SFDP_MIXED, 1e-6))
+    for name, prec, tin in precs:
+        res[name] = run_precision(sfdp, torch, ctx, prec, N, m, beta, ybar_t, args.steps, args.warmup,
+                                  tol_kkt, tin, B, args.max_krylov)
+        if B > 1:
+            res[name + "_b1"] = run_precision(sfdp, torch, ctx, prec, N, m, beta, ybar1_t, args.steps,
+                                              args.warmup, tol_kkt, tin, 1, args.max_krylov)
+    head = precs[0][0]
     r = res[head]
     kt = r["kernel_times"]
     sz = r["sizes"]
-    mean_its = kt["gmres_iters"] / max(kt["gmres_launches"], 1)
+    trips = kt["gmres_iters"] / max(kt["gmres_launches"], 1)          # loop trips per launch
+    rhs_its = kt["gmres_rhs_iters"] / max(kt["gmres_launches"], 1)    # RHS iterations per launch
     ebytes = 8 if head == "mixed" else 16
-    bpi = gmres_bytes_per_iteration(N, m, sz["n_mult"], sz["n_corner"], ebytes, mean_its)
+    op_bytes = gmres_operator_bytes(N, m, sz["n_corner"], ebytes)
+    vec_bytes = gmres_vector_bytes(sz["n_mult"], rhs_its / B)
+    launch_bytes = trips * op_bytes + rhs_its * vec_bytes
     launch_ms = kt["gmres_ms"] / max(kt["gmres_launches"], 1)
-    achieved = bpi * mean_its / (launch_ms * 1e-3) / 1e9
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    local_ms = kt["local_ms"] / max(kt["local_launches"], 1)
+    local_gbs = B * local_solve_bytes(N, m, ebytes) / (local_ms * 1e-3) / 1e9
     out = {
         "metric": "Schur solves/sec at rel. KKT residual 1e-8 (512² Q1); p50/p99 solve latency",
         "value": r["solves_per_s"],
@@ -166,30 +201,40 @@ def main():
         "dtype": "c64+f64" if head == "mixed" else "c128",
         "data": "synthetic",
         "config": {"workload": f"2D Q1 Poisson control {N}x{N} cells, {N // m}x{N // m} subdomains of "
-                               f"{m}x{m}, beta={beta:g}, 16-mode sine target (seed 0), one RHS per solve",
-                   "precision": head, "tol_kkt": tol_kkt, "parallelism": "1 GPU, subdomains as a batch"},
-        "p50_ms": r["p50_ms"],
-        "p99_ms": r["p99_ms"],
+                               f"{m}x{m}, beta={beta:g}, 16-mode sine targets (seeds 0..{B - 1}), "
+                               f"{B} targets per step sharing every launch",
+                   "precision": head, "tol_kkt": tol_kkt, "batch": B,
+                   "max_krylov": args.max_krylov or 150,
+                   "parallelism": "1 GPU, subdomains as a batch"},
+        # latency of one Schur solve: a step with a single target
+        "p50_ms": res.get(head + "_b1", r)["p50_ms"],
+        "p99_ms": res.get(head + "_b1", r)["p99_ms"],
+        "step_p50_ms": r["p50_ms"],
+        "step_p99_ms": r["p99_ms"],
         "setup_ms": r["setup_ms"],
         "max_rel_kkt": r["max_rel_kkt"],
         "krylov_its_per_solve": r["krylov_per_solve"],
         "roofline": {"bound": "hbm", "kernel": "k_gmres (interface Krylov solve, persistent)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_iteration": bpi, "iterations_per_launch": mean_its,
-                     "launch_ms": launch_ms,
+                     "bytes_per_launch": launch_bytes, "operator_bytes_per_trip": op_bytes,
+                     "vector_bytes_per_rhs_iteration": vec_bytes, "trips_per_launch": trips,
+                     "rhs_iterations_per_launch": rhs_its, "launch_ms": launch_ms,
+                     "kernel_width": kt["gmres_width"], "lds_resident": bool(kt["gmres_resident"]),
                      "time_share": kt["gmres_ms"] / (r["ms_per_step"] * args.steps)},
-        "subdomain_solve_kernel": {"launch_ms": kt["local_ms"] / max(kt["local_launches"], 1),
-                                   "launches": kt["local_launches"]},
+        "subdomain_solve_kernel": {"kernel": "k_local_solve", "launch_ms": local_ms,
+                                   "launches": kt["local_launches"], "rhs_per_launch": B,
+                                   "achieved_gbs": local_gbs, "frac": local_gbs / HBM_PEAK_GBS,
+                                   "time_share": kt["local_ms"] / (r["ms_per_step"] * args.steps)},
     }
     other = [k for k in res if k != head]
     for k in other:
         o = res[k]
-        out[k] = {"solves_per_s": o["solves_per_s"], "ms_per_step": o["ms_per_step"],
+        out[k] = {"batch": o["batch"], "solves_per_s": o["solves_per_s"], "ms_per_step": o["ms_per_step"],
                   "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"], "max_rel_kkt": o["max_rel_kkt"],
                   "krylov_its_per_solve": o["krylov_per_solve"], "setup_ms": o["setup_ms"]}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(N, m, beta, ybar)
+        out["cpu_baseline"] = cpu_baseline(N, m, beta, ybar[0])
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -77,8 +77,12 @@ typedef enum {
  * SFDP_MIXED: subdomain factors, subdomain solves and the interface
  *             operators in complex64 with FP32 accumulation; the coarse
  *             problem, the Krylov orthogonalisation, the KKT residual and
- *             the outer iterative refinement in FP64. */
-typedef enum { SFDP_FP64 = 0, SFDP_MIXED = 1 } sfdp_precision;
+ *             the outer iterative refinement in FP64.
+ * SFDP_MIXED_IFACE: the interface operators of the Krylov iteration
+ *             (S_bb, Z_rr^-1 on Delta, Phi) in complex64 as in SFDP_MIXED;
+ *             the subdomain line factors and the two full subdomain solves
+ *             of every FETI-DP solve in complex128. */
+typedef enum { SFDP_FP64 = 0, SFDP_MIXED = 1, SFDP_MIXED_IFACE = 2 } sfdp_precision;
 
 /* Solver controls; zero-initialised fields take the defaults in brackets. */
 typedef struct {
@@ -88,6 +92,11 @@ typedef struct {
                        [1e-8 FP64, 1e-6 MIXED] */
   int max_outer;    /* outer refinement steps [8] */
   int max_krylov;   /* GMRES iterations per FETI-DP solve, <= 400 [150] */
+  int batch;        /* right-hand sides solved together, 1..4 [4]: each FETI-DP
+                       launch sequence (subdomain solves, persistent GMRES)
+                       serves up to this many right-hand sides in lockstep,
+                       sharing every grid barrier and every pass over the
+                       subdomain operators; results do not depend on it */
 } sfdp_opts;
 
 /* Per-solve report. */
@@ -144,14 +153,19 @@ sfdp_status sfdp_set_beta(sfdp_problem* p, double beta);
  *   dlam = Re conj(Z^-1 conj(v));  dy = -Re dw;  u = lam / beta.
  * The first step is the paper's range-space solve with the real right-hand
  * side b = K ybar + Kc yc; later steps are iterative refinement.
- * opts and info may be NULL; info, if given, has nrhs entries. */
+ * Targets are taken in groups of opts->batch; the unfinished members of a
+ * group take each step together and each stops on its own test.
+ * opts and info may be NULL; info, if given, has nrhs entries.
+ * Returns SFDP_E_NOCONV (after finishing all targets) if any target missed
+ * tol_kkt within max_outer steps. */
 sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar, const double* yc,
                                    double* y, double* u, double* lam, const sfdp_opts* opts,
                                    sfdp_info* info);
 
 /* z = S^-1 r for real r (n_free x nrhs), through the two complex factors
  * (Sec. 4): z = Re conj(Z^-1 conj(M Z^-1 r)).  This is the S block of the
- * block-diagonal preconditioner of Sec. 3.2. */
+ * block-diagonal preconditioner of Sec. 3.2.  info, if given, has nrhs
+ * entries (two FETI-DP solves each). */
 sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, double* z,
                                  const sfdp_opts* opts, sfdp_info* info);
 
@@ -205,8 +219,14 @@ typedef struct {
   double gmres_ms;        /* summed duration of the GMRES kernel launches */
   double local_ms;        /* summed duration of the subdomain solve launches */
   int64_t gmres_launches;
-  int64_t gmres_iters;    /* iterations summed over the timed GMRES launches */
+  int64_t gmres_iters;    /* loop trips summed over the timed GMRES launches (a launch
+                             serving several right-hand sides runs as many trips as
+                             its slowest one needs) */
   int64_t local_launches;
+  int64_t gmres_rhs_iters;/* iterations summed over right-hand sides */
+  int gmres_width;        /* right-hand sides per GMRES launch of the last solve
+                             (the widest kernel of 4, 2, 1 whose LDS fits) */
+  int gmres_resident;     /* 1 if that launch kept the Schur blocks in LDS */
 } sfdp_timing;
 sfdp_status sfdp_timing_enable(sfdp_problem* p, int enable);
 sfdp_status sfdp_kernel_times(sfdp_problem* p, sfdp_timing* out);

@@ -13,8 +13,6 @@
 #include "common.h"
 
 namespace sfdp {
-int gmres_max_blocks(const Problem& p, int kmax);
-size_t gmres_lds_bytes(const Problem& p, int kmax, int nb);
 }  // namespace sfdp
 
 using namespace sfdp;
@@ -39,6 +37,11 @@ struct sfdp_problem : public Problem {};
 namespace {
 
 constexpr int KMAX_LIMIT = 400;
+// Device flag words: [1] grid-barrier error, [3] GMRES loop trips, [4] GMRES
+// iterations summed over right-hand sides, [8 + r] last counts per RHS, and
+// from ITLOG a log of 16 counts per group slot (range-space driver).
+constexpr int ITLOG = 64;
+constexpr int FLAG_WORDS = ITLOG + NRMAX * 16;
 
 sfdp_status dalloc(Problem& p, void** ptr, size_t bytes) {
   Ctx* c = p.ctx;
@@ -149,11 +152,12 @@ sfdp_status build_maps(Problem& p) {
   return SFDP_OK;
 }
 
-size_t elem_size(const Problem& p) { return p.prec == SFDP_MIXED ? sizeof(cf) : sizeof(cd); }
+size_t g_size(const Problem& p) { return p.g32() ? sizeof(cf) : sizeof(cd); }  // line factors
+size_t elem_size(const Problem& p) { return p.s32() ? sizeof(cf) : sizeof(cd); }  // Sinv, Phi
 
 void free_factors(Problem& p) {
   size_t es = elem_size(p);
-  dfree(p, p.G, es * p.nsub * p.ml * p.ml * p.ml);
+  dfree(p, p.G, g_size(p) * p.nsub * p.ml * p.ml * p.ml);
   const size_t PK = (size_t)p.ND * (p.ND + 1) / 2;
   dfree(p, p.Sinv, es * p.nsub * PK);
   dfree(p, p.Sbb, sizeof(cf) * p.nsub * PK);
@@ -165,25 +169,27 @@ void free_factors(Problem& p) {
 
 sfdp_status alloc_workspace(Problem& p, int kmax) {
   if (p.kmax_alloc >= kmax) return SFDP_OK;
+  // per right-hand side: Krylov basis, Hessenberg matrix, block partial sums
   if (p.kmax_alloc) {
-    dfree(p, (void*&)p.Qk, sizeof(cd) * (size_t)(p.kmax_alloc + 1) * p.nmu);
-    dfree(p, (void*&)p.Hk, sizeof(cd) * (size_t)(p.kmax_alloc + 1) * p.kmax_alloc);
-    dfree(p, (void*&)p.part, sizeof(cd) * 3 * (size_t)(p.kmax_alloc + 2) * p.gmres_blocks);
+    dfree(p, (void*&)p.Qk, sizeof(cd) * NRMAX * (size_t)(p.kmax_alloc + 1) * p.nmu);
+    dfree(p, (void*&)p.Hk, sizeof(cd) * NRMAX * (size_t)(p.kmax_alloc + 1) * p.kmax_alloc);
+    dfree(p, (void*&)p.part, sizeof(cd) * 3 * NRMAX * (size_t)(p.kmax_alloc + 2) * p.gmres_blocks);
   }
   sfdp_status s;
-  if ((s = dalloc(p, (void**)&p.Qk, sizeof(cd) * (size_t)(kmax + 1) * p.nmu)) ||
-      (s = dalloc(p, (void**)&p.Hk, sizeof(cd) * (size_t)(kmax + 1) * kmax)) ||
-      (s = dalloc(p, (void**)&p.part, sizeof(cd) * 3 * (size_t)(kmax + 2) * p.gmres_blocks)))
+  if ((s = dalloc(p, (void**)&p.Qk, sizeof(cd) * NRMAX * (size_t)(kmax + 1) * p.nmu)) ||
+      (s = dalloc(p, (void**)&p.Hk, sizeof(cd) * NRMAX * (size_t)(kmax + 1) * kmax)) ||
+      (s = dalloc(p, (void**)&p.part, sizeof(cd) * 3 * NRMAX * (size_t)(kmax + 2) * p.gmres_blocks)))
     return s;
   p.kmax_alloc = kmax;
   return SFDP_OK;
 }
 
 sfdp_status check_launch(Problem& p, int kmax) {
-  int maxb = gmres_max_blocks(p, kmax);
-  if (maxb < 1) return fail(SFDP_E_DEVICE, "GMRES kernel does not fit on the device");
-  if (p.gmres_blocks > maxb)
+  hipError_t e = gmres_check(p, kmax);
+  if (e == hipErrorOutOfMemory) return fail(SFDP_E_DEVICE, "GMRES kernel does not fit in LDS (lower max_krylov)");
+  if (e == hipErrorCooperativeLaunchTooLarge)
     return fail(SFDP_E_DEVICE, "cooperative GMRES grid exceeds co-resident blocks");
+  if (e != hipSuccess) return fail(SFDP_E_DEVICE, std::string("GMRES launch check: ") + hipGetErrorString(e));
   return SFDP_OK;
 }
 
@@ -222,37 +228,41 @@ hipError_t ev_harvest(Problem& p) {
   return hipSuccess;
 }
 
-// One FETI-DP solve of Z x = f (conj_in: conj(Z) x = f).  Iteration count to *its.
-sfdp_status feti_one(Problem& p, const cd* f, int conj_in, cd* x, double tol, int kmax, int* its_dev_slot) {
+// One FETI-DP solve of Z x_r = f_r (conj_in: conj(Z) x_r = f_r) for nr <= NRMAX
+// right-hand sides together; f and x are r-major with stride n_free.  The
+// iteration count of RHS r also goes to the device int its_dst[r] (if given).
+sfdp_status feti_one(Problem& p, const cd* f, int conj_in, cd* x, double tol, int kmax, int nr,
+                     int* const* its_dst) {
   hipStream_t st = p.ctx->stream;
+  for (int r = 0; r < NRMAX; ++r) p.its_dst[r] = (its_dst && r < nr) ? its_dst[r] : nullptr;
   int ev;
   HIPCHK(ev_begin(p, 1, &ev));
-  HIPCHK(launch_local_solve(p, 0, f, conj_in, nullptr, st));
+  HIPCHK(launch_local_solve(p, 0, f, conj_in, nullptr, nr, st));
   HIPCHK(ev_end(p, ev));
-  HIPCHK(launch_coarse_rhs(p, f, conj_in, st));
-  HIPCHK(launch_fetidp_rhs(p, st));
+  HIPCHK(launch_coarse_rhs(p, f, conj_in, nr, st));
+  HIPCHK(launch_fetidp_rhs(p, nr, st));
   sfdp_status s = check_launch(p, kmax);
   if (s != SFDP_OK) return s;
   HIPCHK(ev_begin(p, 0, &ev));
-  HIPCHK(launch_gmres(p, tol, kmax, st));
+  HIPCHK(launch_gmres(p, tol, kmax, nr, st));
   HIPCHK(ev_end(p, ev));
-  if (its_dev_slot) HIPCHK(hipMemcpyAsync(its_dev_slot, p.flags, sizeof(int), hipMemcpyDeviceToDevice, st));
-  HIPCHK(launch_recover_coarse(p, st));
+  HIPCHK(launch_recover_coarse(p, nr, st));
   HIPCHK(ev_begin(p, 1, &ev));
-  HIPCHK(launch_local_solve(p, 1, f, conj_in, x, st));
+  HIPCHK(launch_local_solve(p, 1, f, conj_in, x, nr, st));
   HIPCHK(ev_end(p, ev));
-  HIPCHK(launch_assemble_solution(p, x, conj_in, st));
+  HIPCHK(launch_assemble_solution(p, x, conj_in, nr, st));
   return SFDP_OK;
 }
 
 void defaults(const Problem& p, const sfdp_opts* o, double& tol_kkt, double& tol_inner, int& max_outer,
               int& kmax) {
-  bool mixed = p.prec == SFDP_MIXED;
+  bool mixed = p.prec != SFDP_FP64;
   tol_kkt = (o && o->tol_kkt > 0) ? o->tol_kkt : (mixed ? 1e-8 : 1e-10);
   tol_inner = (o && o->tol_inner > 0) ? o->tol_inner : (mixed ? 1e-6 : 1e-8);
   max_outer = (o && o->max_outer > 0) ? o->max_outer : 8;
   kmax = (o && o->max_krylov > 0) ? std::min(o->max_krylov, KMAX_LIMIT) : 150;
 }
+int batch_of(const sfdp_opts* o) { return (o && o->batch > 0) ? std::min(o->batch, NRMAX) : NRMAX; }
 
 sfdp_status check_ready(const Problem* p) {
   if (!p) return fail(SFDP_E_INVALID, "null problem");
@@ -262,8 +272,8 @@ sfdp_status check_ready(const Problem* p) {
 
 sfdp_status alloc_rs(Problem& p) {
   if (p.r1) return SFDP_OK;
-  size_t n = p.n_free;
-  size_t nred = 16 + 2 * ((n + 255) / 256);
+  size_t n = (size_t)NRMAX * p.n_free;
+  size_t nred = RED_HEAD + NRMAX * (size_t)red_pstride(p);
   sfdp_status s;
   if ((s = dalloc(p, (void**)&p.r1, sizeof(double) * n)) || (s = dalloc(p, (void**)&p.r2, sizeof(double) * n)) ||
       (s = dalloc(p, (void**)&p.r3, sizeof(double) * n)) || (s = dalloc(p, (void**)&p.red, sizeof(double) * nred)) ||
@@ -312,7 +322,8 @@ sfdp_status sfdp_problem_create(sfdp_ctx* ctx, int dim, int n_elem, int sub_elem
   if (sub_elem < 2 || sub_elem > 32) return fail(SFDP_E_INVALID, "sub_elem must be in [2, 32] for dim 2");
   if (n_elem % sub_elem != 0 || n_elem / sub_elem < 2)
     return fail(SFDP_E_INVALID, "n_elem must be a multiple of sub_elem with at least 2 subdomains per side");
-  if (prec != SFDP_FP64 && prec != SFDP_MIXED) return fail(SFDP_E_INVALID, "bad precision");
+  if (prec != SFDP_FP64 && prec != SFDP_MIXED && prec != SFDP_MIXED_IFACE)
+    return fail(SFDP_E_INVALID, "bad precision");
   HIPCHK(hipSetDevice(ctx->device));
   sfdp_problem* p = new (std::nothrow) sfdp_problem();
   if (!p) return fail(SFDP_E_NOMEM, "host allocation");
@@ -330,21 +341,24 @@ sfdp_status sfdp_problem_create(sfdp_ctx* ctx, int dim, int n_elem, int sub_elem
   sfdp_status s = build_maps(*p);
   if (s != SFDP_OK) { sfdp_problem_destroy(p); return s; }
   // solve workspaces
-  size_t nsd = (size_t)p->nsub * p->ND;
-  size_t nC = std::max(p->nC, 1);
+  // per right-hand side (NRMAX r-major copies, strides of Problem::rs())
+  size_t nsd = (size_t)NRMAX * p->nsub * p->ND;
+  size_t n4 = (size_t)NRMAX * p->nsub * 4;
+  size_t nC = (size_t)NRMAX * std::max(p->nC, 1);
+  size_t nm = (size_t)NRMAX * p->nmu;
   if ((s = dalloc(*p, (void**)&p->Xd, sizeof(cd) * nsd)) || (s = dalloc(*p, (void**)&p->Ubuf, sizeof(cd) * nsd)) ||
       (s = dalloc(*p, (void**)&p->Abuf, sizeof(cd) * nsd)) || (s = dalloc(*p, (void**)&p->Ybuf, sizeof(cd) * nsd)) ||
-      (s = dalloc(*p, (void**)&p->Cbuf, sizeof(cd) * p->nsub * 4)) || (s = dalloc(*p, (void**)&p->Qc, sizeof(cd) * p->nsub * 4)) ||
+      (s = dalloc(*p, (void**)&p->Cbuf, sizeof(cd) * n4)) || (s = dalloc(*p, (void**)&p->Qc, sizeof(cd) * n4)) ||
       (s = dalloc(*p, (void**)&p->fcs, sizeof(cd) * nC)) || (s = dalloc(*p, (void**)&p->u0, sizeof(cd) * nC)) ||
-      (s = dalloc(*p, (void**)&p->ymin, sizeof(cd) * nC)) || (s = dalloc(*p, (void**)&p->dvec, sizeof(cd) * p->nmu)) ||
-      (s = dalloc(*p, (void**)&p->mu, sizeof(cd) * p->nmu)) || (s = dalloc(*p, (void**)&p->wv, sizeof(cd) * p->nmu)) ||
+      (s = dalloc(*p, (void**)&p->ymin, sizeof(cd) * nC)) || (s = dalloc(*p, (void**)&p->dvec, sizeof(cd) * nm)) ||
+      (s = dalloc(*p, (void**)&p->mu, sizeof(cd) * nm)) || (s = dalloc(*p, (void**)&p->wv, sizeof(cd) * nm)) ||
       (s = dalloc(*p, (void**)&p->dscal, sizeof(double) * 8)) || (s = dalloc(*p, (void**)&p->bar, 4096)) ||
-      (s = dalloc(*p, (void**)&p->flags, sizeof(int) * 64))) {
+      (s = dalloc(*p, (void**)&p->flags, sizeof(int) * FLAG_WORDS))) {
     sfdp_problem_destroy(p);
     return s;
   }
   p->gmres_blocks = std::min(p->nsub, ctx->num_cu);
-  hipError_t ez = launch_fill(p->flags, sizeof(int) * 64, ctx->stream);
+  hipError_t ez = launch_fill(p->flags, sizeof(int) * FLAG_WORDS, ctx->stream);
   if (ez == hipSuccess) ez = launch_fill(p->bar, 4096, ctx->stream);
   if (ez == hipSuccess) ez = launch_fill(p->dscal, sizeof(double) * 8, ctx->stream);
   if (ez == hipSuccess) ez = hipStreamSynchronize(ctx->stream);
@@ -397,7 +411,7 @@ sfdp_status sfdp_set_beta(sfdp_problem* p, double beta) {
   size_t nG = (size_t)nsub * ml * ml * ml, nS = (size_t)nsub * ND * ND, nP = (size_t)nsub * ND * 4;
   const size_t nPK = (size_t)nsub * ND * (ND + 1) / 2;
   sfdp_status s;
-  if ((s = dalloc(*p, &p->G, es * nG)) || (s = dalloc(*p, &p->Sinv, es * nPK)) ||
+  if ((s = dalloc(*p, &p->G, g_size(*p) * nG)) || (s = dalloc(*p, &p->Sinv, es * nPK)) ||
       (s = dalloc(*p, &p->Sbb, sizeof(cf) * nPK)) || (s = dalloc(*p, &p->Phi, es * nP)) ||
       (s = dalloc(*p, (void**)&p->Kinv, sizeof(cd) * std::max(p->nC * p->nC, 1))) ||
       (s = dalloc(*p, (void**)&p->Kcc, sizeof(cd) * std::max(p->nC * p->nC, 1))))
@@ -445,24 +459,27 @@ sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double*
   double tk, ti;
   int mo, kmax;
   defaults(*p, opts, tk, ti, mo, kmax);
+  const int bsz = batch_of(opts);
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax))) return s;
-  HIPCHK(launch_fill(p->flags, sizeof(int) * 64, p->ctx->stream));
-  int* its_dev = p->flags + 8;
-  for (int r = 0; r < nrhs; ++r) {
-    const cd* fr = (const cd*)f + (size_t)r * p->n_free;
-    cd* xr = (cd*)x + (size_t)r * p->n_free;
-    if ((s = feti_one(*p, fr, conj_z ? 1 : 0, xr, ti, kmax, its_dev + (r % 32)))) return s;
+  hipStream_t st = p->ctx->stream;
+  HIPCHK(launch_fill(p->flags, sizeof(int) * FLAG_WORDS, st));
+  std::vector<int> its(nrhs, 0);
+  for (int r0 = 0; r0 < nrhs; r0 += bsz) {
+    const int nr = std::min(bsz, nrhs - r0);
+    const cd* fr = (const cd*)f + (size_t)r0 * p->n_free;
+    cd* xr = (cd*)x + (size_t)r0 * p->n_free;
+    if ((s = feti_one(*p, fr, conj_z ? 1 : 0, xr, ti, kmax, nr, nullptr))) return s;
+    HIPCHK(hipMemcpyAsync(its.data() + r0, p->flags + 8, sizeof(int) * nr, hipMemcpyDeviceToHost, st));
   }
-  int flags[64];
-  HIPCHK(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, p->ctx->stream));
-  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  int flags[8];
+  HIPCHK(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
   if (flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
   HIPCHK(ev_harvest(*p));
-  for (int r = 0; r < nrhs && r < 32; ++r) {
-    if (krylov_its) krylov_its[r] = flags[8 + r];
-    if (p->timing) p->it_gmres += flags[8 + r];
-  }
+  if (p->timing) { p->it_gmres += flags[3]; p->it_rhs += flags[4]; }
+  if (krylov_its)
+    for (int r = 0; r < nrhs; ++r) krylov_its[r] = its[r];
   return SFDP_OK;
 }
 
@@ -485,64 +502,97 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
   if (s) return s;
   hipStream_t st = p->ctx->stream;
   const size_t n = p->n_free;
-  for (int r = 0; r < nrhs; ++r) {
-    HIPCHK(launch_kkt_residual(*p, ybar + r * n, yc ? yc + r * p->n_bdry : nullptr, y + r * n, u + r * n,
-                               lam + r * n, p->r1, p->r2, p->r3, p->red, st));
-    HIPCHK(hipMemcpyAsync(rel + r, p->red, sizeof(double), hipMemcpyDeviceToHost, st));
+  for (int r0 = 0; r0 < nrhs; r0 += NRMAX) {
+    const int nr = std::min(NRMAX, nrhs - r0);
+    const unsigned map = 0x03020100u;  // slot c for the c-th right-hand side
+    double red[2 * NRMAX];
+    HIPCHK(launch_kkt_residual(*p, nr, map, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, y + r0 * n,
+                               u + r0 * n, lam + r0 * n, p->r1, p->r2, p->r3, p->red, st));
+    HIPCHK(hipMemcpyAsync(red, p->red, sizeof(red), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int c = 0; c < nr; ++c) rel[r0 + c] = red[2 * c];
   }
   HIPCHK(hipStreamSynchronize(st));
   return SFDP_OK;
 }
 
-static sfdp_status range_space_one(sfdp_problem* p, const double* ybar, const double* yc, double* y,
-                                   double* u, double* lam, double tol_kkt, double tol_inner, int max_outer,
-                                   int kmax, sfdp_info* info) {
+// Range-space solves of a group of ng <= NRMAX targets (arrays at the group's
+// first RHS, stride n_free / n_bdry).  All unfinished members take each
+// two-factor step together: both FETI-DP solves of a step run the group's
+// active right-hand sides in one launch sequence.
+static sfdp_status range_space_group(sfdp_problem* p, int ng, const double* ybar, const double* yc,
+                                     double* y, double* u, double* lam, double tol_kkt, double tol_inner,
+                                     int max_outer, int kmax, sfdp_info* info) {
   hipStream_t st = p->ctx->stream;
   const int64_t n = p->n_free;
-  HIPCHK(launch_copy(n, ybar, y, st));
-  HIPCHK(launch_fill(u, sizeof(double) * n, st));
-  HIPCHK(launch_fill(lam, sizeof(double) * n, st));
-  sfdp_info loc;
-  memset(&loc, 0, sizeof(loc));
-  int* its_dev = p->flags + 8;
-  double rho = 0.0, red2[2] = {0, 0};
-  int nfeti = 0;
-  sfdp_status status = SFDP_OK;
+  HIPCHK(launch_copy(ng * n, ybar, y, st));
+  HIPCHK(launch_fill(u, sizeof(double) * ng * n, st));
+  HIPCHK(launch_fill(lam, sizeof(double) * ng * n, st));
+  HIPCHK(launch_fill(p->flags + ITLOG, sizeof(int) * NRMAX * 16, st));
+  sfdp_info loc[NRMAX];
+  memset(loc, 0, sizeof(loc));
+  bool act[NRMAX] = {false, false, false, false};
+  int nfeti[NRMAX] = {0, 0, 0, 0};
+  std::string why[NRMAX];
+  for (int q = 0; q < ng; ++q) act[q] = true;
+  double red[2 * NRMAX];
   for (int step = 0;; ++step) {
-    HIPCHK(launch_kkt_residual(*p, ybar, yc, y, u, lam, p->r1, p->r2, p->r3, p->red, st));
-    HIPCHK(hipMemcpyAsync(red2, p->red, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    unsigned map = 0;
+    int na = 0;
+    for (int q = 0; q < ng; ++q)
+      if (act[q]) map |= (unsigned)q << (8 * na++);
+    if (na == 0) break;
+    HIPCHK(launch_kkt_residual(*p, na, map, ybar, yc, y, u, lam, p->r1, p->r2, p->r3, p->red, st));
+    HIPCHK(hipMemcpyAsync(red, p->red, sizeof(red), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(ev_harvest(*p));
-    rho = red2[0];
-    if (step == 1) loc.rel_kkt_first = rho;
-    if (step > 0) loc.imag_ratio = red2[1];
-    if (!std::isfinite(rho)) { status = fail(SFDP_E_NOCONV, "non-finite residual"); break; }
-    if (rho <= tol_kkt) break;
-    if (step >= max_outer) { status = fail(SFDP_E_NOCONV, "outer refinement limit reached"); break; }
-    HIPCHK(launch_make_rhs1(*p, p->r1, p->r3, p->cvec, st));
-    sfdp_status s = feti_one(*p, p->cvec, 0, p->cvec2, tol_inner, kmax, its_dev + (nfeti % 16));
+    unsigned map2 = 0;
+    int nb2 = 0;
+    for (int c = 0; c < na; ++c) {
+      const int q = (map >> (8 * c)) & 255;
+      const double rho = red[2 * q];
+      loc[q].rel_kkt = rho;
+      if (step == 1) loc[q].rel_kkt_first = rho;
+      if (step > 0) loc[q].imag_ratio = red[2 * q + 1];
+      if (!std::isfinite(rho)) { act[q] = false; why[q] = "non-finite residual"; continue; }
+      if (rho <= tol_kkt) { act[q] = false; continue; }
+      if (step >= max_outer) { act[q] = false; why[q] = "outer refinement limit reached"; continue; }
+      map2 |= (unsigned)q << (8 * nb2++);
+    }
+    if (nb2 == 0) break;
+    int* dst[NRMAX];
+    auto set_dst = [&]() {
+      for (int c = 0; c < nb2; ++c) {
+        const int q = (map2 >> (8 * c)) & 255;
+        dst[c] = nfeti[q] < 16 ? p->flags + ITLOG + 16 * q + nfeti[q] : nullptr;
+        ++nfeti[q];
+      }
+    };
+    HIPCHK(launch_make_rhs1(*p, nb2, map2, p->r1, p->r3, p->cvec, st));
+    set_dst();
+    sfdp_status s = feti_one(*p, p->cvec, 0, p->cvec2, tol_inner, kmax, nb2, dst);
     if (s) return s;
-    ++nfeti;
-    HIPCHK(launch_make_rhs2(*p, p->r1, p->cvec2, p->cvec3, st));
-    s = feti_one(*p, p->cvec3, 0, p->cvec, tol_inner, kmax, its_dev + (nfeti % 16));
+    HIPCHK(launch_make_rhs2(*p, nb2, map2, p->r1, p->cvec2, p->cvec3, st));
+    set_dst();
+    s = feti_one(*p, p->cvec3, 0, p->cvec, tol_inner, kmax, nb2, dst);
     if (s) return s;
-    ++nfeti;
-    HIPCHK(launch_update(*p, p->cvec2, p->cvec, y, u, lam, p->red, st));
-    loc.outer_steps = step + 1;
+    HIPCHK(launch_update(*p, nb2, map2, p->cvec2, p->cvec, y, u, lam, p->red, st));
+    for (int c = 0; c < nb2; ++c) loc[(map2 >> (8 * c)) & 255].outer_steps = step + 1;
   }
-  // imaginary ratio of the last factor-two solve: red[1] holds sqrt(sum im^2)/sqrt(sum re^2)
-  int flags[64];
+  int flags[FLAG_WORDS];
   HIPCHK(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
-  loc.rel_kkt = rho;
-  loc.n_feti = nfeti;
-  for (int i = 0; i < nfeti && i < 16; ++i) {
-    loc.krylov_its[i] = flags[8 + i];
-    loc.krylov_total += flags[8 + i];
+  sfdp_status status = SFDP_OK;
+  for (int q = 0; q < ng; ++q) {
+    loc[q].n_feti = nfeti[q];
+    for (int i = 0; i < nfeti[q] && i < 16; ++i) {
+      loc[q].krylov_its[i] = flags[ITLOG + 16 * q + i];
+      loc[q].krylov_total += flags[ITLOG + 16 * q + i];
+    }
+    if (!why[q].empty()) status = fail(SFDP_E_NOCONV, why[q]);
+    if (info) info[q] = loc[q];
   }
-  if (p->timing) p->it_gmres += loc.krylov_total;
-  if (info) *info = loc;
   return status;
 }
 
@@ -555,16 +605,24 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
   double tk, ti;
   int mo, kmax;
   defaults(*p, opts, tk, ti, mo, kmax);
+  const int bsz = batch_of(opts);
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p))) return s;
-  HIPCHK(launch_fill(p->flags, sizeof(int) * 64, p->ctx->stream));
+  HIPCHK(launch_fill(p->flags, sizeof(int) * FLAG_WORDS, p->ctx->stream));
   sfdp_status worst = SFDP_OK;
   const size_t n = p->n_free;
-  for (int r = 0; r < nrhs; ++r) {
-    s = range_space_one(p, ybar + r * n, yc ? yc + r * p->n_bdry : nullptr, y + r * n, u + r * n,
-                        lam + r * n, tk, ti, mo, kmax, info ? info + r : nullptr);
+  for (int r0 = 0; r0 < nrhs; r0 += bsz) {
+    const int ng = std::min(bsz, nrhs - r0);
+    s = range_space_group(p, ng, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, y + r0 * n,
+                          u + r0 * n, lam + r0 * n, tk, ti, mo, kmax, info ? info + r0 : nullptr);
     if (s == SFDP_E_NOCONV) worst = s;
     else if (s) return s;
+  }
+  if (p->timing) {
+    int f[8];
+    HIPCHK(hipMemcpy(f, p->flags, sizeof(f), hipMemcpyDeviceToHost));
+    p->it_gmres += f[3];
+    p->it_rhs += f[4];
   }
   return worst;
 }
@@ -577,37 +635,47 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
   double tk, ti;
   int mo, kmax;
   defaults(*p, opts, tk, ti, mo, kmax);
+  const int bsz = batch_of(opts);
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p))) return s;
   hipStream_t st = p->ctx->stream;
-  HIPCHK(launch_fill(p->flags, sizeof(int) * 64, st));
+  HIPCHK(launch_fill(p->flags, sizeof(int) * FLAG_WORDS, st));
   const int64_t n = p->n_free;
-  int* its_dev = p->flags + 8;
-  for (int q = 0; q < nrhs; ++q) {
-    // factor 1: w = Z^-1 r ; middle: conj(v) = M conj(w) ; factor 2: z = Re conj(Z^-1 conj v)
-    HIPCHK(launch_copy_real_to_complex(n, r + q * n, p->cvec, st));
-    if ((s = feti_one(*p, p->cvec, 0, p->cvec2, ti, kmax, its_dev))) return s;
-    HIPCHK(launch_fill(p->r1, sizeof(double) * n, st));
-    HIPCHK(launch_make_rhs2(*p, p->r1, p->cvec2, p->cvec3, st));
-    if ((s = feti_one(*p, p->cvec3, 0, p->cvec, ti, kmax, its_dev + 1))) return s;
-    // z = Re(conj(Z^-1 conj v)) = Re of the solve
-    HIPCHK(launch_fill(z + q * n, sizeof(double) * n, st));
-    HIPCHK(launch_fill(p->cvec2, sizeof(cd) * n, st));
-    HIPCHK(launch_fill(p->r2, sizeof(double) * n, st));
-    HIPCHK(launch_update(*p, p->cvec2, p->cvec, p->r2, p->r3, z + q * n, p->red, st));
+  // the middle factor needs r1 = 0: v = conj(0 + M w)
+  HIPCHK(launch_fill(p->r1, sizeof(double) * NRMAX * n, st));
+  std::vector<int> its((size_t)2 * nrhs, 0);
+  for (int r0 = 0; r0 < nrhs; r0 += bsz) {
+    const int nr = std::min(bsz, nrhs - r0);
+    const unsigned map = 0x03020100u;
+    // factor 1: w = Z^-1 r ; middle: v = conj(M w) ; factor 2: z = Re conj(Z^-1 v) = Re Z^-1 v
+    HIPCHK(launch_copy_real_to_complex(nr * n, r + r0 * n, p->cvec, st));
+    if ((s = feti_one(*p, p->cvec, 0, p->cvec2, ti, kmax, nr, nullptr))) return s;
+    HIPCHK(hipMemcpyAsync(its.data() + 2 * r0, p->flags + 8, sizeof(int) * nr, hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_make_rhs2(*p, nr, map, p->r1, p->cvec2, p->cvec3, st));
+    if ((s = feti_one(*p, p->cvec3, 0, p->cvec, ti, kmax, nr, nullptr))) return s;
+    HIPCHK(hipMemcpyAsync(its.data() + 2 * r0 + nr, p->flags + 8, sizeof(int) * nr, hipMemcpyDeviceToHost,
+                          st));
+    HIPCHK(launch_real_part(nr * n, p->cvec, z + r0 * n, st));
   }
-  int flags[64];
+  int flags[8];
   HIPCHK(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
   HIPCHK(ev_harvest(*p));
-  if (p->timing) p->it_gmres += flags[8] + flags[9];
+  if (p->timing) { p->it_gmres += flags[3]; p->it_rhs += flags[4]; }
   if (info) {
-    memset(info, 0, sizeof(*info));
-    info->n_feti = 2;
-    info->krylov_its[0] = flags[8];
-    info->krylov_its[1] = flags[9];
-    info->krylov_total = flags[8] + flags[9];
+    // its holds, per group of nr, the nr factor-1 counts then the nr factor-2 counts
+    for (int r0 = 0; r0 < nrhs; r0 += bsz) {
+      const int nr = std::min(bsz, nrhs - r0);
+      for (int c = 0; c < nr; ++c) {
+        sfdp_info& o = info[r0 + c];
+        memset(&o, 0, sizeof(o));
+        o.n_feti = 2;
+        o.krylov_its[0] = its[2 * r0 + c];
+        o.krylov_its[1] = its[2 * r0 + nr + c];
+        o.krylov_total = o.krylov_its[0] + o.krylov_its[1];
+      }
+    }
   }
   return SFDP_OK;
 }
@@ -688,7 +756,7 @@ sfdp_status sfdp_timing_enable(sfdp_problem* p, int enable) {
   p->ev_used = 0;
   p->timing = enable != 0;
   p->t_gmres_ms = p->t_local_ms = 0;
-  p->n_gmres = p->n_local = p->it_gmres = 0;
+  p->n_gmres = p->n_local = p->it_gmres = p->it_rhs = 0;
   return SFDP_OK;
 }
 
@@ -701,6 +769,9 @@ sfdp_status sfdp_kernel_times(sfdp_problem* p, sfdp_timing* out) {
   out->local_ms = p->t_local_ms;
   out->gmres_launches = p->n_gmres;
   out->gmres_iters = p->it_gmres;
+  out->gmres_rhs_iters = p->it_rhs;
+  out->gmres_width = p->last_nrt;
+  out->gmres_resident = p->last_resident ? 1 : 0;
   out->local_launches = p->n_local;
   return SFDP_OK;
 }
@@ -713,9 +784,9 @@ sfdp_status sfdp_interface_apply(sfdp_problem* p, char which, const double* x, d
   hipStream_t st = p->ctx->stream;
   if (which == 'D') {
     const cd* f = (const cd*)x;
-    HIPCHK(launch_local_solve(*p, 0, f, 0, nullptr, st));
-    HIPCHK(launch_coarse_rhs(*p, f, 0, st));
-    HIPCHK(launch_fetidp_rhs(*p, st));
+    HIPCHK(launch_local_solve(*p, 0, f, 0, nullptr, 1, st));
+    HIPCHK(launch_coarse_rhs(*p, f, 0, 1, st));
+    HIPCHK(launch_fetidp_rhs(*p, 1, st));
     HIPCHK(hipMemcpyAsync(y, p->dvec, sizeof(cd) * p->nmu, hipMemcpyDeviceToDevice, st));
     return SFDP_OK;
   }

@@ -22,6 +22,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -160,12 +162,24 @@ struct Maps2 {
   const int* cfree;  // [nC] free index of each global corner
 };
 
+// Right-hand sides processed together by one FETI-DP solve (r-major copies of
+// every per-RHS buffer).
+constexpr int NRMAX = 4;
+struct RhsStride {
+  int64_t nf;   // free-node vectors
+  int64_t nc;   // coarse (corner) vectors
+  int64_t nmu;  // multiplier vectors
+  int64_t sb;   // per-subdomain Delta-slot buffers (nsub * ND)
+  int64_t c4;   // per-subdomain corner buffers (nsub * 4)
+};
+
 // Host-side problem.
 struct Ctx;
 struct Problem {
   Ctx* ctx = nullptr;
   int dim = 2, N = 0, m = 0, P = 0, nsub = 0, ml = 0, L = 0, ND = 0, nC = 0, nmu = 0, ndmax = 0;
-  bool last_resident = false;
+  bool last_resident = false;  // last GMRES launch kept the Schur blocks in LDS
+  int last_nrt = 0;            // right-hand-side width of the last GMRES kernel
   int64_t n_free = 0, n_bdry = 0;
   sfdp_precision prec = SFDP_FP64;
   double beta = 0, alpha = 0;
@@ -188,6 +202,7 @@ struct Problem {
   unsigned* bar = nullptr;    // grid barrier counter
   int* flags = nullptr;       // device flags / outputs of the GMRES kernel
   int kmax_alloc = 0, gmres_blocks = 0;
+  int* its_dst[NRMAX] = {};  // per-RHS device destinations of the next GMRES launch's counts
   // range-space workspaces (FP64)
   double *r1 = nullptr, *r2 = nullptr, *r3 = nullptr, *red = nullptr;
   cd *cvec = nullptr, *cvec2 = nullptr, *cvec3 = nullptr;
@@ -199,9 +214,16 @@ struct Problem {
   std::vector<std::pair<int, int>> ev_pending;  // (event index, kind: 0 gmres, 1 local)
   int ev_used = 0;
   double t_gmres_ms = 0, t_local_ms = 0;
-  int64_t n_gmres = 0, n_local = 0, it_gmres = 0;
+  int64_t n_gmres = 0, n_local = 0, it_gmres = 0, it_rhs = 0;
   Maps2 maps() const {
     return Maps2{dloc, dmid, dsgn, dpart, nd, cloc, cgid, muown, mufree, cown, cfree};
+  }
+  // storage precision: line factors G (g32) and interface operators Sinv, Phi (s32)
+  bool g32() const { return prec == SFDP_MIXED; }
+  bool s32() const { return prec == SFDP_MIXED || prec == SFDP_MIXED_IFACE; }
+  RhsStride rs() const {
+    return RhsStride{n_free, (int64_t)(nC > 0 ? nC : 1), (int64_t)nmu, (int64_t)nsub * ND,
+                     (int64_t)nsub * 4};
   }
   Geo2 geo() const {
     return Geo2{N, m, P, ml, nsub, ND, nmu, nC, 1.0 / N, alpha};
@@ -227,27 +249,36 @@ hipError_t launch_invert_dense(int n, cd* A, cd* work, hipStream_t st);
 hipError_t launch_store_factors(const Problem& p, const cd* G64, const cd* Sinv64, const cd* S64,
                                 const cd* Phi64, hipStream_t st);
 // solve
+// nr <= NRMAX right-hand sides, stored r-major with the strides of Problem::rs()
 hipError_t launch_local_solve(const Problem& p, int mode, const cd* f, int conj_in, cd* x_out,
-                              hipStream_t st);
-hipError_t launch_coarse_rhs(const Problem& p, const cd* f, int conj_in, hipStream_t st);
-hipError_t launch_fetidp_rhs(const Problem& p, hipStream_t st);
-hipError_t launch_gmres(Problem& p, double tol, int kmax, hipStream_t st);
-hipError_t launch_recover_coarse(const Problem& p, hipStream_t st);
-hipError_t launch_assemble_solution(const Problem& p, cd* x, int conj_out, hipStream_t st);
+                              int nr, hipStream_t st);
+hipError_t launch_coarse_rhs(const Problem& p, const cd* f, int conj_in, int nr, hipStream_t st);
+hipError_t launch_fetidp_rhs(const Problem& p, int nr, hipStream_t st);
+hipError_t launch_gmres(Problem& p, double tol, int kmax, int nr, hipStream_t st);
+hipError_t launch_recover_coarse(const Problem& p, int nr, hipStream_t st);
+hipError_t launch_assemble_solution(const Problem& p, cd* x, int conj_out, int nr, hipStream_t st);
+hipError_t gmres_check(const Problem& p, int kmax);  // the one-RHS kernel fits (hipSuccess)
 hipError_t launch_interface_apply(Problem& p, char which, const cd* x, cd* y, hipStream_t st);
 // ops
 hipError_t launch_apply_K(const Problem& p, int nrhs, const double* x, const double* xc, double* y,
                           hipStream_t st);
 hipError_t launch_apply_M(const Problem& p, int nrhs, const double* x, double* y, hipStream_t st);
-hipError_t launch_kkt_residual(const Problem& p, const double* ybar, const double* yc,
-                               const double* y, const double* u, const double* lam, double* r1,
-                               double* r2, double* r3, double* red, hipStream_t st);
-hipError_t launch_make_rhs1(const Problem& p, const double* r1, const double* r3, cd* g,
-                            hipStream_t st);
-hipError_t launch_make_rhs2(const Problem& p, const double* r1, const cd* dw, cd* v,
-                            hipStream_t st);
-hipError_t launch_update(const Problem& p, const cd* dw, const cd* z, double* y, double* u,
-                         double* lam, double* red, hipStream_t st);
+// Batched range-space kernels: nr right-hand sides of a group, `map` packs the
+// group slot of the c-th one in byte c.  red holds (rho, imag ratio) of slot s
+// at red[2 s], red[2 s + 1]; per-block partial sums follow from RED_HEAD.
+constexpr int RED_HEAD = 16;
+int64_t red_pstride(const Problem& p);
+hipError_t launch_kkt_residual(const Problem& p, int nr, unsigned map, const double* ybar,
+                               const double* yc, const double* y, const double* u,
+                               const double* lam, double* r1, double* r2, double* r3, double* red,
+                               hipStream_t st);
+hipError_t launch_make_rhs1(const Problem& p, int nr, unsigned map, const double* r1, const double* r3,
+                            cd* g, hipStream_t st);
+hipError_t launch_make_rhs2(const Problem& p, int nr, unsigned map, const double* r1, const cd* dw,
+                            cd* v, hipStream_t st);
+hipError_t launch_update(const Problem& p, int nr, unsigned map, const cd* dw, const cd* z, double* y,
+                         double* u, double* lam, double* red, hipStream_t st);
+hipError_t launch_real_part(int64_t n, const cd* x, double* y, hipStream_t st);
 hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t st);
 hipError_t launch_copy_real_to_complex(int64_t n, const double* x, cd* y, hipStream_t st);
 hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t st);

@@ -61,10 +61,20 @@ __global__ void k_apply_KM(int N, const int* f2b, const double* x, const double*
   if (yM) yM[r * nfree + t] = Mx;
 }
 
+// Batched elementwise kernels: blockIdx.y = c runs over the nr right-hand sides
+// of a group; `map` packs the group slot of c in byte c (slot = map >> 8c & 255).
+// Slot-indexed arrays (KKT iterates, residuals, partial sums) are offset by
+// slot * stride; the FETI-DP vectors (dw, z, g, v) are compact, offset by c * n.
+__device__ inline int slot_of(unsigned map) { return (int)((map >> (8 * blockIdx.y)) & 255u); }
+
 // complex M product: v = conj(r1 + M dw) = r1 + M conj(dw)
-__global__ void k_make_rhs2(int N, const double* r1, const cd* dw, cd* v, int64_t nfree) {
+__global__ void k_make_rhs2(int N, unsigned map, const double* r1, const cd* dw, cd* v, int64_t nfree) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nfree) return;
+  const int c = blockIdx.y, s = slot_of(map);
+  r1 += s * nfree;
+  dw += c * nfree;
+  v += c * nfree;
   int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
   Sten st = make_sten(1.0 / N);
   cd acc{r1[t], 0.0};
@@ -81,18 +91,30 @@ __global__ void k_make_rhs2(int N, const double* r1, const cd* dw, cd* v, int64_
 }
 
 // per-node KKT residual and its squared norms, block partial sums
-__global__ void __launch_bounds__(256) k_kkt_residual(int N, const int* f2b, double beta,
+// (part + slot * pstride, pairs (||r||^2, ||b||^2) per block)
+__global__ void __launch_bounds__(256) k_kkt_residual(int N, const int* f2b, double beta, unsigned map,
                                                       const double* ybar, const double* yc,
                                                       const double* y, const double* u,
                                                       const double* lam, double* r1, double* r2,
-                                                      double* r3, double* part, int64_t nfree) {
+                                                      double* r3, double* part, int64_t pstride,
+                                                      int64_t nfree, int64_t nbdry) {
   __shared__ double sh[2][4];
+  const int s = slot_of(map);
+  ybar += s * nfree;
+  if (yc) yc += s * nbdry;
+  y += s * nfree;
+  u += s * nfree;
+  lam += s * nfree;
+  r1 += s * nfree;
+  r2 += s * nfree;
+  r3 += s * nfree;
+  part += s * pstride;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double rn = 0.0, bn = 0.0;
   if (t < nfree) {
     int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
     Sten st = make_sten(1.0 / N);
-    double Kyb_unused, Mybar, Ky, My, Kl, Ml, Ku_unused, Mu, Kc, Mc_unused;
+    double Kyb_unused, Mybar, Ky, My, Kl, Ml, Ku_unused, Mu, Kc;
     stencil_KM(st, N, f2b, Field{ybar, nullptr}, i, j, Kyb_unused, Mybar);
     stencil_KM(st, N, f2b, Field{y, nullptr}, i, j, Ky, My);
     stencil_KM(st, N, f2b, Field{lam, nullptr}, i, j, Kl, Ml);
@@ -108,7 +130,6 @@ __global__ void __launch_bounds__(256) k_kkt_residual(int N, const int* f2b, dou
           Kc = fma(wk, yc[f2b[ii + (N + 1) * jj]], Kc);
         }
     }
-    (void)Mc_unused;
     double a1 = Mybar - My - Kl;
     double a2 = -(beta * Mu - Ml);
     double a3 = -Kc - Ky + Mu;
@@ -131,9 +152,13 @@ __global__ void __launch_bounds__(256) k_kkt_residual(int N, const int* f2b, dou
   }
 }
 
-// out[0] = sqrt(sum part[2b]) / sqrt(sum part[2b+1])  (fixed order)
-__global__ void k_reduce_ratio(int nblocks, const double* part, double* out) {
+// out[2 slot] = sqrt(sum part[2b]) / sqrt(sum part[2b+1])  (fixed order), one
+// block per right-hand side (blockIdx.x = c)
+__global__ void k_reduce_ratio(int nblocks, unsigned map, const double* part, int64_t pstride,
+                               double* out) {
   __shared__ double sh[2][256];
+  const int s = (int)((map >> (8 * blockIdx.x)) & 255u);
+  part += s * pstride;
   double a = 0.0, b = 0.0;
   for (int q = threadIdx.x; q < nblocks; q += 256) {
     a += part[2 * q];
@@ -145,20 +170,30 @@ __global__ void k_reduce_ratio(int nblocks, const double* part, double* out) {
   if (threadIdx.x == 0) {
     double sa = 0.0, sb = 0.0;
     for (int q = 0; q < 256; ++q) { sa += sh[0][q]; sb += sh[1][q]; }
-    out[0] = sb > 0.0 ? sqrt(sa) / sqrt(sb) : sqrt(sa);
+    out[2 * s] = sb > 0.0 ? sqrt(sa) / sqrt(sb) : sqrt(sa);
   }
 }
 
 // g = -r3 - i alpha r1
-__global__ void k_make_rhs1(double alpha, const double* r1, const double* r3, cd* g, int64_t n) {
+__global__ void k_make_rhs1(double alpha, unsigned map, const double* r1, const double* r3, cd* g,
+                            int64_t n) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) g[t] = cd{-r3[t], -alpha * r1[t]};
+  const int c = blockIdx.y, s = slot_of(map);
+  if (t < n) g[c * n + t] = cd{-r3[s * n + t], -alpha * r1[s * n + t]};
 }
 
 // y -= Re dw; lam += Re z; u = lam / beta; partial sums of |Im z|^2, |Re z|^2
-__global__ void __launch_bounds__(256) k_update(double beta, const cd* dw, const cd* z, double* y,
-                                                double* u, double* lam, double* part, int64_t n) {
+__global__ void __launch_bounds__(256) k_update(double beta, unsigned map, const cd* dw, const cd* z,
+                                                double* y, double* u, double* lam, double* part,
+                                                int64_t pstride, int64_t n) {
   __shared__ double sh[2][4];
+  const int c = blockIdx.y, s = slot_of(map);
+  dw += c * n;
+  z += c * n;
+  y += s * n;
+  u += s * n;
+  lam += s * n;
+  part += s * pstride;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double im = 0.0, re = 0.0;
   if (t < n) {
@@ -180,6 +215,11 @@ __global__ void __launch_bounds__(256) k_update(double beta, const cd* dw, const
     part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
     part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
   }
+}
+
+__global__ void k_real_part(int64_t n, const cd* x, double* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i].x;
 }
 
 __global__ void k_fill(uint32_t* p, size_t n) {
@@ -208,32 +248,44 @@ hipError_t launch_apply_M(const Problem& p, int nrhs, const double* x, double* y
                      (const double*)nullptr, (double*)nullptr, y, p.n_free, p.n_bdry);
   return hipGetLastError();
 }
-hipError_t launch_kkt_residual(const Problem& p, const double* ybar, const double* yc,
-                               const double* y, const double* u, const double* lam, double* r1,
-                               double* r2, double* r3, double* red, hipStream_t st) {
+// Partial sums of slot s start at red + RED_HEAD + s * red_pstride(p).
+int64_t red_pstride(const Problem& p) { return 2 * (int64_t)nblk(p.n_free); }
+
+hipError_t launch_kkt_residual(const Problem& p, int nr, unsigned map, const double* ybar,
+                               const double* yc, const double* y, const double* u,
+                               const double* lam, double* r1, double* r2, double* r3, double* red,
+                               hipStream_t st) {
   unsigned nb = nblk(p.n_free);
-  hipLaunchKernelGGL(k_kkt_residual, dim3(nb), dim3(256), 0, st, p.N, p.full2bdry, p.beta, ybar, yc,
-                     y, u, lam, r1, r2, r3, red + 8, p.n_free);
-  hipLaunchKernelGGL(k_reduce_ratio, dim3(1), dim3(256), 0, st, (int)nb, red + 8, red);
+  int64_t ps = red_pstride(p);
+  hipLaunchKernelGGL(k_kkt_residual, dim3(nb, nr), dim3(256), 0, st, p.N, p.full2bdry, p.beta, map,
+                     ybar, yc, y, u, lam, r1, r2, r3, red + RED_HEAD, ps, p.n_free, p.n_bdry);
+  hipLaunchKernelGGL(k_reduce_ratio, dim3(nr), dim3(256), 0, st, (int)nb, map, red + RED_HEAD, ps, red);
   return hipGetLastError();
 }
-hipError_t launch_make_rhs1(const Problem& p, const double* r1, const double* r3, cd* g,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_make_rhs1, dim3(nblk(p.n_free)), dim3(256), 0, st, p.alpha, r1, r3, g,
+hipError_t launch_make_rhs1(const Problem& p, int nr, unsigned map, const double* r1, const double* r3,
+                            cd* g, hipStream_t st) {
+  hipLaunchKernelGGL(k_make_rhs1, dim3(nblk(p.n_free), nr), dim3(256), 0, st, p.alpha, map, r1, r3, g,
                      p.n_free);
   return hipGetLastError();
 }
-hipError_t launch_make_rhs2(const Problem& p, const double* r1, const cd* dw, cd* v,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_make_rhs2, dim3(nblk(p.n_free)), dim3(256), 0, st, p.N, r1, dw, v, p.n_free);
+hipError_t launch_make_rhs2(const Problem& p, int nr, unsigned map, const double* r1, const cd* dw,
+                            cd* v, hipStream_t st) {
+  hipLaunchKernelGGL(k_make_rhs2, dim3(nblk(p.n_free), nr), dim3(256), 0, st, p.N, map, r1, dw, v,
+                     p.n_free);
   return hipGetLastError();
 }
-hipError_t launch_update(const Problem& p, const cd* dw, const cd* z, double* y, double* u,
-                         double* lam, double* red, hipStream_t st) {
+hipError_t launch_update(const Problem& p, int nr, unsigned map, const cd* dw, const cd* z, double* y,
+                         double* u, double* lam, double* red, hipStream_t st) {
   unsigned nb = nblk(p.n_free);
-  hipLaunchKernelGGL(k_update, dim3(nb), dim3(256), 0, st, p.beta, dw, z, y, u, lam, red + 8,
-                     p.n_free);
-  hipLaunchKernelGGL(k_reduce_ratio, dim3(1), dim3(256), 0, st, (int)nb, red + 8, red + 1);
+  int64_t ps = red_pstride(p);
+  hipLaunchKernelGGL(k_update, dim3(nb, nr), dim3(256), 0, st, p.beta, map, dw, z, y, u, lam,
+                     red + RED_HEAD, ps, p.n_free);
+  hipLaunchKernelGGL(k_reduce_ratio, dim3(nr), dim3(256), 0, st, (int)nb, map, red + RED_HEAD, ps,
+                     red + 1);
+  return hipGetLastError();
+}
+hipError_t launch_real_part(int64_t n, const cd* x, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_real_part, dim3(nblk(n)), dim3(256), 0, st, n, x, y);
   return hipGetLastError();
 }
 hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t st) {

@@ -344,18 +344,18 @@ hipError_t launch_store_factors(const Problem& p, const cd* G64, const cd* Sinv6
   size_t nG = (size_t)p.nsub * p.ml * p.ml * p.ml;
   size_t nS = (size_t)p.nsub * p.ND * p.ND;
   size_t nP = (size_t)p.nsub * p.ND * 4;
-  auto conv = [&](size_t n, const cd* src, void* dst) {
-    if (p.prec == SFDP_MIXED)
+  auto conv = [&](size_t n, const cd* src, void* dst, bool to32) {
+    if (to32)
       hipLaunchKernelGGL(k_convert<cf>, dim3((n + 255) / 256), dim3(256), 0, st, n, src, (cf*)dst);
     else
       hipMemcpyAsync(dst, src, n * sizeof(cd), hipMemcpyDeviceToDevice, st);
   };
-  conv(nG, G64, p.G);
-  conv(nP, Phi64, p.Phi);
+  conv(nG, G64, p.G, p.g32());
+  conv(nP, Phi64, p.Phi, p.s32());
   (void)nS;
   const int PK = p.ND * (p.ND + 1) / 2;
   dim3 grid((PK + 255) / 256, p.nsub);
-  if (p.prec == SFDP_MIXED)
+  if (p.s32())
     hipLaunchKernelGGL(k_pack<cf>, grid, dim3(256), 0, st, p.nsub, p.ND, p.nd, Sinv64, (cf*)p.Sinv);
   else
     hipLaunchKernelGGL(k_pack<cd>, grid, dim3(256), 0, st, p.nsub, p.ND, p.nd, Sinv64, (cd*)p.Sinv);

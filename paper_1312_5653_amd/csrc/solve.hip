@@ -22,6 +22,16 @@ namespace sfdp {
 
 constexpr int ML = 33;
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
+// (lgkmcnt = 0) but not for outstanding global loads, so prefetches stay in
+// flight across it (a full __syncthreads waits for every global load too).
+__device__ inline void lds_sync() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt = max, expcnt = max, lgkmcnt = 0
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // ------------------------------------------------------------------------------------------
 // Grid barrier for a cooperative launch (all blocks co-resident), two levels to
 // spread the atomics: blocks arrive on one of G group counters (separate
@@ -76,19 +86,36 @@ __device__ inline void st_coh(cd* p, cd v) {
   __hip_atomic_store((double*)p + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// out[i] = sum_q part[i * nb + q] for i < n, in a fixed order (identical in every
-// block).  Wave w takes i = w, w + 4, ...; four values of i per batch keep 16
-// loads in flight per lane.  nb <= 256.
-__device__ inline void reduce_partials(const cd* __restrict__ part, int nb, int n, cd* out) {
+// Sums of per-block partial values for several right-hand sides at once.  The
+// rows are the pairs (a, i), a < na, i < n, of the na right-hand sides
+// r = ract[a]; row (a, i) reads part[r * pstride + i * nb + q], q < nb, and
+// writes out[r * ostride + i].  Every value is summed in the same fixed order
+// in every block.  Wave w takes rows w * 4 .. w * 4 + 3, then 16 further; four
+// rows per batch keep 16 loads in flight per lane.  nb <= 256.
+__device__ inline void reduce_partials(const cd* __restrict__ part, int64_t pstride, int nb, int n,
+                                       int na, const int* ract, cd* out, int ostride) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i0 = wv * 4; i0 < n; i0 += 16) {
+  const int rows = na * n;
+  for (int p0 = wv * 4; p0 < rows; p0 += 16) {
+    const cd* src[4];
+    int dst[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int p = min(p0 + u, rows - 1);
+      const int a = p / n, i = p - a * n, r = ract[a];
+      src[u] = part + r * pstride + (int64_t)i * nb;
+      dst[u] = r * ostride + i;
+    }
     cd v[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int i = i0 + u, q = lane + 64 * r;
-        v[u][r] = (i < n && q < nb) ? ld_coh(part + (size_t)i * nb + q) : cd{0.0, 0.0};
+      for (int q4 = 0; q4 < 4; ++q4) {
+        // load from a clamped, always valid address, then select: keeps v in
+        // registers and all sixteen loads in flight
+        const int q = lane + 64 * q4;
+        cd t = ld_coh(src[u] + min(q, nb - 1));
+        v[u][q4] = q < nb ? t : cd{0.0, 0.0};
       }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -97,31 +124,58 @@ __device__ inline void reduce_partials(const cd* __restrict__ part, int nb, int 
         a.x += __shfl_xor(a.x, off, 64);
         a.y += __shfl_xor(a.y, off, 64);
       }
-      if (lane == 0 && i0 + u < n) out[i0 + u] = a;
+      if (lane == 0 && p0 + u < rows) out[dst[u]] = a;
     }
   }
   __syncthreads();
 }
 
-// part[i * nb + b] = sum_{k < kn} conj(Q[i][k0 + k]) w[k] for i < nvec.  Eight
-// lanes per vector (32 vectors per pass), partial sums combined by shuffles.
-__device__ inline void block_dots(const cd* __restrict__ Q, int nmu, int k0, int kn, int nvec,
-                                  const cd* wch, cd* part, int nb, int b) {
+// part[r * pstride + i * nb + b] = sum_{k < kn} conj(Q_r[i][k0 + k]) w_r[k] for the
+// pairs (r = ract[a], i < nvec); Q_r = Q + r * qs, w_r = wch + r * wstride.
+// Eight lanes per pair (32 pairs per pass), partial sums combined by shuffles.
+__device__ inline void block_dots(const cd* __restrict__ Q, int64_t qs, int nmu, int k0, int kn,
+                                  int nvec, int na, const int* ract, const cd* wch, int wstride,
+                                  cd* part, int64_t pstride, int nb, int b) {
   const int t = threadIdx.x, g = t & 7;
-  for (int i0 = 0; i0 < nvec; i0 += 32) {
-    int i = i0 + (t >> 3);
+  const int pairs = na * nvec;
+  for (int p0 = 0; p0 < pairs; p0 += 32) {
+    const int p = p0 + (t >> 3);
     cd acc{0.0, 0.0};
-    if (i < nvec) {
-      const cd* q = Q + (size_t)i * nmu + k0;
+    int r = 0, i = 0;
+    if (p < pairs) {
+      const int a = p / nvec;
+      i = p - a * nvec;
+      r = ract[a];
+      const cd* q = Q + r * qs + (size_t)i * nmu + k0;
+      const cd* w = wch + r * wstride;
 #pragma unroll 4
-      for (int k = g; k < kn; k += 8) fma_conj_acc(acc, q[k], wch[k]);
+      for (int k = g; k < kn; k += 8) fma_conj_acc(acc, q[k], w[k]);
     }
     for (int off = 4; off > 0; off >>= 1) {
       acc.x += __shfl_xor(acc.x, off, 64);
       acc.y += __shfl_xor(acc.y, off, 64);
     }
-    if (g == 0 && i < nvec) st_coh(part + (size_t)i * nb + b, acc);
+    if (g == 0 && p < pairs) st_coh(part + r * pstride + (size_t)i * nb + b, acc);
   }
+}
+
+// Per right-hand-side block sums: thread t holds a partial value of RHS
+// t / (256 / NRT) (256 threads); out[r] = sum over that RHS's threads, in a
+// fixed order.  wsum holds 4 doubles.
+template <int NRT>
+__device__ inline void rhs_block_sums(double v, double* wsum, double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if (lane == 0) wsum[wv] = v;
+  __syncthreads();
+  if (threadIdx.x < NRT) {
+    constexpr int WPR = 4 / NRT;
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < WPR; ++w) t += wsum[threadIdx.x * WPR + w];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------------------------------
@@ -167,10 +221,7 @@ __device__ inline void stage_lds(void* dst, const void* __restrict__ src, int by
   for (int i0 = threadIdx.x; i0 < n16; i0 += 256 * 8) {
     uint4 v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      int i = i0 + u * 256;
-      if (i < n16) v[u] = s4[i];
-    }
+    for (int u = 0; u < 8; ++u) v[u] = s4[min(i0 + u * 256, n16 - 1)];  // clamped: no branches
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       int i = i0 + u * 256;
@@ -186,10 +237,7 @@ constexpr int GPT = (ML * ML + 255) / 256;
 template <class TS>
 __device__ inline void line_load(const TS* __restrict__ src, int n2, TS (&reg)[GPT]) {
 #pragma unroll
-  for (int r = 0; r < GPT; ++r) {
-    int idx = threadIdx.x + 256 * r;
-    if (idx < n2) reg[r] = src[idx];
-  }
+  for (int r = 0; r < GPT; ++r) reg[r] = src[min((int)threadIdx.x + 256 * r, n2 - 1)];  // clamped
 }
 template <class TS>
 __device__ inline void line_store(TS* dst, int n2, const TS (&reg)[GPT]) {
@@ -200,130 +248,183 @@ __device__ inline void line_store(TS* dst, int n2, const TS (&reg)[GPT]) {
   }
 }
 
-// t[p] = sum_k G(p,k) z[k] for one line; G in LDS stored transposed (G(p,k) at
-// Gl[k*ml + p]); four wave groups split k, partial sums reduced through LDS.
-template <class TS, class T>
-__device__ inline void line_mv(const TS* Gl, int ml, const T* z, T* red, T* out, bool subtract) {
+// t_r[p] = sum_k G(p,k) z_r[k] for one line and nr <= NRT right-hand sides; G in
+// LDS stored transposed (G(p,k) at Gl[k*ml + p]); four wave groups split k,
+// partial sums reduced through LDS (red: [NRT][4][ML]).  z_r = z + r * ML,
+// out_r = out + r * xstride.
+template <class TS, class T, int NRT>
+__device__ inline void line_mv(const TS* Gl, int ml, const T* z, T* red, T* out, int xstride,
+                               bool subtract, int nr) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int kq = (ml + 3) / 4;
-  T acc{0, 0};
+  T acc[NRT];
+#pragma unroll
+  for (int r = 0; r < NRT; ++r) acc[r] = T{0, 0};
   if (lane < ml) {
     int k0 = wv * kq, k1 = min(ml, k0 + kq);
-    for (int k = k0; k < k1; ++k) fma_acc(acc, cvt<typename real_of<T>::type>(Gl[k * ml + lane]), z[k]);
+    for (int k = k0; k < k1; ++k) {
+      const auto gk = cvt<typename real_of<T>::type>(Gl[k * ml + lane]);
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) fma_acc(acc[r], gk, z[r * ML + k]);
+    }
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) red[(r * 4 + wv) * ML + lane] = acc[r];
   }
-  if (lane < ml) red[wv * ML + lane] = acc;
-  __syncthreads();
-  if (threadIdx.x < ml) {
-    T s = red[threadIdx.x] + red[ML + threadIdx.x];
-    s = s + red[2 * ML + threadIdx.x];
-    s = s + red[3 * ML + threadIdx.x];
-    out[threadIdx.x] = subtract ? out[threadIdx.x] - s : s;
+  lds_sync();
+  if (threadIdx.x < ml * nr) {
+    const int r = threadIdx.x / ml, p = threadIdx.x - r * ml;
+    const T* rr = red + r * 4 * ML;
+    T s = rr[p] + rr[ML + p];
+    s = s + rr[2 * ML + p];
+    s = s + rr[3 * ML + p];
+    T* o = out + r * xstride + p;
+    *o = subtract ? *o - s : s;
   }
-  __syncthreads();
+  lds_sync();
 }
 
 // ------------------------------------------------------------------------------------------
-// Full local solve with E^s (extended Z_rr^s).
+// Full local solve with E^s (extended Z_rr^s) for nr <= NRT right-hand sides; one
+// workgroup per subdomain streams the line factors once for all of them.
 //   mode 0: load f_r = f / multiplicity; output x on Delta (Xd) and Z_cr x (Qc).
 //   mode 1: load f_r - Z_rc B_c uc - B_r^T mu; output Delta values (Ubuf) and
 //           interior values straight into xout (conjugated if conj_out).
-template <class TS>
-__global__ void __launch_bounds__(256) k_local_solve(Geo2 g, Maps2 mp, const TS* __restrict__ G,
-                                                     int mode, const cd* __restrict__ f, int conj_in,
-                                                     const cd* __restrict__ uc,
-                                                     const cd* __restrict__ mu, cd* Xd, cd* Qc,
-                                                     cd* Ubuf, cd* xout, int conj_out) {
+template <class TS, int NRT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_local_solve(Geo2 g, Maps2 mp, RhsStride rs, int nr, const TS* __restrict__ G, int mode,
+              const cd* __restrict__ f, int conj_in, const cd* __restrict__ uc,
+              const cd* __restrict__ mu, cd* Xd, cd* Qc, cd* Ubuf, cd* xout, int conj_out) {
   using R = typename real_of<TS>::type;
   using T = C<R>;
-  __shared__ T xall[ML * ML];
-  __shared__ T zl[ML];
-  __shared__ T red[4 * ML];
-  __shared__ TS gbuf[2][ML * ML];
+  constexpr int XS = ML * ML;
+  __shared__ T xall[NRT * XS];
+  __shared__ T zl[NRT * ML];
+  __shared__ T red[NRT * 4 * ML];
+  __shared__ TS gbuf[ML * ML];
+  __shared__ T cpl[ML][3];   // coupling of node p of a line to node p + d - 1 of the next line
   const int s = blockIdx.x, ml = g.ml, n2 = ml * ml, ND = g.ND;
   const TS* Gs = G + (size_t)s * ml * n2;
-  TS greg[GPT];
-  line_load<TS>(Gs, n2, greg);  // line 0 in flight while the load vector is built
-  // load right-hand side
+  // The forward sweep visits lines 0..ml-1, the backward sweep ml-2..0: step t
+  // uses line (t < ml ? t : 2 ml - 2 - t).  Line factors stream through a ring
+  // of LRING register sets, LRING steps ahead of the step being computed
+  // (two sets of complex128, whose ring would not stay in registers).
+  constexpr int LRING = sizeof(TS) == sizeof(cf) ? 4 : 2;
+  const int nsteps = 2 * ml - 1;
+  auto line_of = [&](int t) { return t < ml ? t : 2 * ml - 2 - t; };
+  TS greg[LRING][GPT];
+#pragma unroll
+  for (int u = 0; u < LRING; ++u)
+    if (u < nsteps) line_load<TS>(Gs + (size_t)line_of(u) * n2, n2, greg[u]);
+  // load right-hand sides (loads from a clamped RHS index, results selected)
   for (int l = threadIdx.x; l < n2; l += blockDim.x) {
-    int a = l % ml, b = l / ml;
-    cd v{0.0, 0.0};
-    if (g.rnode(s, a, b)) {
-      cd fv = f[g.freeidx(s, a, b)];
-      if (conj_in) fv = conj(fv);
-      v = (1.0 / g.mult(a, b)) * fv;
-      if (mode == 1) {
-        for (int q = 0; q < 4; ++q) {
-          int cl = mp.cloc[s * 4 + q];
-          if (cl < 0) continue;
-          int ca = cl % ml, cb = cl / ml;
-          if (abs(ca - a) > 1 || abs(cb - b) > 1) continue;
-          v = v - g.zloc(a, b, ca, cb) * uc[mp.cgid[s * 4 + q]];
+    const int a = l % ml, b = l / ml;
+    const bool rn = g.rnode(s, a, b);
+    const int64_t fi = rn ? g.freeidx(s, a, b) : 0;
+    cd fv[NRT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) fv[r] = f[min(r, nr - 1) * rs.nf + fi];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      cd v{0.0, 0.0};
+      if (rn) {
+        cd x = conj_in ? conj(fv[r]) : fv[r];
+        v = (1.0 / g.mult(a, b)) * x;
+        if (mode == 1) {
+          for (int q = 0; q < 4; ++q) {
+            int cl = mp.cloc[s * 4 + q];
+            if (cl < 0) continue;
+            int ca = cl % ml, cb = cl / ml;
+            if (abs(ca - a) > 1 || abs(cb - b) > 1) continue;
+            v = v - g.zloc(a, b, ca, cb) * uc[min(r, nr - 1) * rs.nc + mp.cgid[s * 4 + q]];
+          }
         }
       }
+      xall[r * XS + l] = T{(R)v.x, (R)v.y};
     }
-    xall[l] = T{(R)v.x, (R)v.y};
   }
   __syncthreads();
   if (mode == 1) {
     int nd = mp.nd[s];
     for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-      int l = mp.dloc[s * ND + i];
-      cd m = (double)mp.dsgn[s * ND + i] * mu[mp.dmid[s * ND + i]];
-      xall[l] = xall[l] - T{(R)m.x, (R)m.y};
+      const int l = mp.dloc[s * ND + i], mid = mp.dmid[s * ND + i];
+      const double sg = (double)mp.dsgn[s * ND + i];
+      cd mv[NRT];
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) mv[r] = mu[min(r, nr - 1) * rs.nmu + mid];
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) {
+        cd m = sg * mv[r];
+        xall[r * XS + l] = xall[r * XS + l] - T{(R)m.x, (R)m.y};
+      }
     }
     __syncthreads();
   }
-  line_store<TS>(gbuf[0], n2, greg);
+  // coupling coefficients between consecutive lines (interior rows of the 1D
+  // matrices in the line direction: k = -1/h, m = h/6), masked per use below
+  if (threadIdx.x < ml * 3) {
+    int p = threadIdx.x / 3, d = threadIdx.x % 3, a = p + d - 1;
+    cd e{0.0, 0.0};
+    if (a >= 0 && a < ml) e = g.zloc(p, 1, a, 2);
+    cpl[p][d] = T{(R)e.x, (R)e.y};
+  }
+  line_store<TS>(gbuf, n2, greg[0]);
+  if (LRING < nsteps) line_load<TS>(Gs + (size_t)line_of(LRING) * n2, n2, greg[0]);
   __syncthreads();
-  // forward: z_j = f_j - A_j,j-1 t_j-1 ; t_j = G_j z_j   (t_j overwrites f_j in xall)
-  for (int j = 0; j < ml; ++j) {
-    const int nxt = (j + 1 < ml) ? j + 1 : ml - 2;  // the backward sweep starts at line ml-2
-    line_load<TS>(Gs + (size_t)nxt * n2, n2, greg);
-    if (threadIdx.x < ml) {
-      int p = threadIdx.x;
-      T v = xall[p + ml * j];
-      if (j > 0) {
-        for (int a = max(p - 1, 0); a <= min(p + 1, ml - 1); ++a) {
-          cd e = g.eloc(s, p, j, a, j - 1);
-          v = v - T{(R)e.x, (R)e.y} * xall[a + ml * (j - 1)];
+  for (int t0 = 0; t0 < nsteps; t0 += LRING) {
+#pragma unroll
+    for (int u = 0; u < LRING; ++u) {
+      const int t = t0 + u;
+      if (t < nsteps) {
+        const int j = line_of(t);
+        if (t < ml) {
+          // forward: z_j = f_j - A_j,j-1 t_j-1 ; t_j = G_j z_j (t_j overwrites f_j in xall)
+          if (threadIdx.x < ml * nr) {
+            const int r = threadIdx.x / ml, p = threadIdx.x - r * ml;
+            const T* xr = xall + r * XS;
+            T v = xr[p + ml * j];
+            if (j > 0 && g.rnode(s, p, j)) {
+              for (int a = max(p - 1, 0); a <= min(p + 1, ml - 1); ++a)
+                if (g.rnode(s, a, j - 1)) v = v - cpl[p][a - p + 1] * xr[a + ml * (j - 1)];
+            }
+            zl[r * ML + p] = v;
+          }
+          lds_sync();
+          line_mv<TS, T, NRT>(gbuf, ml, zl, red, xall + ml * j, XS, false, nr);
+        } else {
+          // backward: x_j = t_j - G_j A_j,j+1 x_j+1
+          if (threadIdx.x < ml * nr) {
+            const int r = threadIdx.x / ml, p = threadIdx.x - r * ml;
+            const T* xr = xall + r * XS;
+            T v{0, 0};
+            if (g.rnode(s, p, j)) {
+              for (int a = max(p - 1, 0); a <= min(p + 1, ml - 1); ++a)
+                if (g.rnode(s, a, j + 1)) fma_acc(v, cpl[p][a - p + 1], xr[a + ml * (j + 1)]);
+            }
+            zl[r * ML + p] = v;
+          }
+          lds_sync();
+          line_mv<TS, T, NRT>(gbuf, ml, zl, red, xall + ml * j, XS, true, nr);
         }
+        // stage the next step's line (ring slot (u + 1) % LRING), refill that slot
+        if (t + 1 < nsteps) {
+          line_store<TS>(gbuf, n2, greg[(u + 1) % LRING]);
+          if (t + 1 + LRING < nsteps)
+            line_load<TS>(Gs + (size_t)line_of(t + 1 + LRING) * n2, n2, greg[(u + 1) % LRING]);
+        }
+        lds_sync();
       }
-      zl[p] = v;
     }
-    __syncthreads();
-    line_mv<TS, T>(gbuf[j & 1], ml, zl, red, xall + ml * j, false);
-    line_store<TS>(gbuf[(j + 1) & 1], n2, greg);
-    __syncthreads();
   }
-  // backward: x_j = t_j - G_j A_j,j+1 x_j+1   (line j's factor sits in gbuf[(ml - 1 - j + ml) & 1]
-  // after the forward loop: buffer parity continues from the forward sweep)
-  int par = ml & 1;
-  for (int j = ml - 2; j >= 0; --j) {
-    if (j > 0) line_load<TS>(Gs + (size_t)(j - 1) * n2, n2, greg);
-    if (threadIdx.x < ml) {
-      int p = threadIdx.x;
-      T v{0, 0};
-      for (int a = max(p - 1, 0); a <= min(p + 1, ml - 1); ++a) {
-        cd e = g.eloc(s, p, j, a, j + 1);
-        fma_acc(v, T{(R)e.x, (R)e.y}, xall[a + ml * (j + 1)]);
-      }
-      zl[p] = v;
-    }
-    __syncthreads();
-    line_mv<TS, T>(gbuf[par], ml, zl, red, xall + ml * j, true);
-    par ^= 1;
-    if (j > 0) line_store<TS>(gbuf[par], n2, greg);
-    __syncthreads();
-  }
-  // outputs
+  // outputs (right-hand side r at its stride)
   const int nd = mp.nd[s];
   if (mode == 0) {
-    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-      T x = xall[mp.dloc[s * ND + i]];
-      Xd[(size_t)s * ND + i] = cd{(double)x.x, (double)x.y};
+    for (int t = threadIdx.x; t < nd * nr; t += blockDim.x) {
+      const int r = t / nd, i = t - r * nd;
+      T x = xall[r * XS + mp.dloc[s * ND + i]];
+      Xd[r * rs.sb + (size_t)s * ND + i] = cd{(double)x.x, (double)x.y};
     }
-    if (threadIdx.x < 4) {
-      int q = threadIdx.x;
+    if (threadIdx.x < 4 * nr) {
+      const int r = threadIdx.x / 4, q = threadIdx.x % 4;
       int cl = mp.cloc[s * 4 + q];
       cd acc{0.0, 0.0};
       if (cl >= 0) {
@@ -331,31 +432,42 @@ __global__ void __launch_bounds__(256) k_local_solve(Geo2 g, Maps2 mp, const TS*
         for (int b = max(cb - 1, 0); b <= min(cb + 1, ml - 1); ++b)
           for (int a = max(ca - 1, 0); a <= min(ca + 1, ml - 1); ++a) {
             if (!g.rnode(s, a, b)) continue;
-            T x = xall[a + ml * b];
+            T x = xall[r * XS + a + ml * b];
             fma_acc(acc, g.zloc(ca, cb, a, b), cd{(double)x.x, (double)x.y});
           }
       }
-      Qc[s * 4 + q] = acc;
+      Qc[r * rs.c4 + s * 4 + q] = acc;
     }
   } else {
-    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-      T x = xall[mp.dloc[s * ND + i]];
-      Ubuf[(size_t)s * ND + i] = cd{(double)x.x, (double)x.y};
+    for (int t = threadIdx.x; t < nd * nr; t += blockDim.x) {
+      const int r = t / nd, i = t - r * nd;
+      T x = xall[r * XS + mp.dloc[s * ND + i]];
+      Ubuf[r * rs.sb + (size_t)s * ND + i] = cd{(double)x.x, (double)x.y};
     }
     for (int l = threadIdx.x; l < n2; l += blockDim.x) {
       int a = l % ml, b = l / ml;
       if (a == 0 || a == ml - 1 || b == 0 || b == ml - 1) continue;  // interior only
-      T x = xall[l];
-      cd v{(double)x.x, (double)x.y};
-      xout[g.freeidx(s, a, b)] = conj_out ? conj(v) : v;
+      const int64_t fi = g.freeidx(s, a, b);
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) {
+        if (r >= nr) break;
+        T x = xall[r * XS + l];
+        cd v{(double)x.x, (double)x.y};
+        xout[r * rs.nf + fi] = conj_out ? conj(v) : v;
+      }
     }
   }
 }
 
 // f_c* = f_c - sum_s B_c^T Qc  (one thread per global corner, fixed order)
-__global__ void k_coarse_rhs(Geo2 g, Maps2 mp, const cd* f, int conj_in, const cd* Qc, cd* fcs) {
+__global__ void k_coarse_rhs(Geo2 g, Maps2 mp, RhsStride rs, const cd* f, int conj_in, const cd* Qc,
+                             cd* fcs) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.nC) return;
+  const int64_t r = blockIdx.y;
+  f += r * rs.nf;
+  Qc += r * rs.c4;
+  fcs += r * rs.nc;
   cd v = f[mp.cfree[c]];
   if (conj_in) v = conj(v);
   for (int o = 0; o < 4; ++o) {
@@ -366,8 +478,11 @@ __global__ void k_coarse_rhs(Geo2 g, Maps2 mp, const cd* f, int conj_in, const c
 }
 
 // y = A x (n x n dense FP64 complex), one wavefront per row.
-__global__ void k_dense_mv(int n, const cd* __restrict__ A, const cd* __restrict__ x, cd* y) {
+__global__ void k_dense_mv(int n, int64_t stride, const cd* __restrict__ A, const cd* __restrict__ x,
+                           cd* y) {
   int row = blockIdx.x;
+  x += blockIdx.y * stride;
+  y += blockIdx.y * stride;
   cd acc{0.0, 0.0};
   for (int k = threadIdx.x; k < n; k += 64) fma_acc(acc, A[(size_t)row * n + k], x[k]);
   for (int off = 32; off > 0; off >>= 1) {
@@ -379,9 +494,14 @@ __global__ void k_dense_mv(int n, const cd* __restrict__ A, const cd* __restrict
 
 // d_k = sum over the two subdomains of sign * (Xd - Phi u0)
 template <class TS>
-__global__ void k_fetidp_rhs(Geo2 g, Maps2 mp, const cd* Xd, const TS* Phi, const cd* u0, cd* d) {
+__global__ void k_fetidp_rhs(Geo2 g, Maps2 mp, RhsStride rs, const cd* Xd, const TS* Phi, const cd* u0,
+                             cd* d) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= g.nmu) return;
+  const int64_t r = blockIdx.y;
+  Xd += r * rs.sb;
+  u0 += r * rs.nc;
+  d += r * rs.nmu;
   cd out{0.0, 0.0};
   for (int e = 0; e < 2; ++e) {
     int o = mp.muown[2 * k + e];
@@ -401,10 +521,13 @@ __global__ void k_fetidp_rhs(Geo2 g, Maps2 mp, const cd* Xd, const TS* Phi, cons
 // c^s_q = sum_i Phi[s][i][q] sign_i mu[mid_i]  (F_rc^T mu contributions); one
 // wavefront per (subdomain, corner slot).
 template <class TS>
-__global__ void k_frct(Geo2 g, Maps2 mp, const TS* Phi, const cd* mu, cd* Cbuf) {
+__global__ void k_frct(Geo2 g, Maps2 mp, RhsStride rs, const TS* Phi, const cd* mu, cd* Cbuf) {
   int t = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (t >= g.nsub * 4) return;
+  const int64_t r = blockIdx.y;
+  mu += r * rs.nmu;
+  Cbuf += r * rs.c4;
   int s = t / 4, q = t % 4;
   cd acc{0.0, 0.0};
   if (mp.cloc[s * 4 + q] >= 0) {
@@ -422,9 +545,13 @@ __global__ void k_frct(Geo2 g, Maps2 mp, const TS* Phi, const cd* mu, cd* Cbuf) 
 }
 
 // rhs_c = fcs_c + sum_owners Cbuf
-__global__ void k_corner_sum(Geo2 g, Maps2 mp, const cd* fcs, const cd* Cbuf, cd* out) {
+__global__ void k_corner_sum(Geo2 g, Maps2 mp, RhsStride rs, const cd* fcs, const cd* Cbuf, cd* out) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.nC) return;
+  const int64_t r = blockIdx.y;
+  if (fcs) fcs += r * rs.nc;
+  Cbuf += r * rs.c4;
+  out += r * rs.nc;
   cd v = fcs ? fcs[c] : cd{0.0, 0.0};
   for (int o = 0; o < 4; ++o) {
     int own = mp.cown[c * 4 + o];
@@ -434,8 +561,13 @@ __global__ void k_corner_sum(Geo2 g, Maps2 mp, const cd* fcs, const cd* Cbuf, cd
 }
 
 // primal assembly: Delta nodes average the two subdomain copies, corners take uc
-__global__ void k_assemble(Geo2 g, Maps2 mp, const cd* Ubuf, const cd* uc, cd* x, int conj_out) {
+__global__ void k_assemble(Geo2 g, Maps2 mp, RhsStride rs, const cd* Ubuf, const cd* uc, cd* x,
+                           int conj_out) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  Ubuf += r * rs.sb;
+  uc += r * rs.nc;
+  x += r * rs.nf;
   if (k < g.nmu) {
     cd v = 0.5 * (Ubuf[mp.muown[2 * k]] + Ubuf[mp.muown[2 * k + 1]]);
     x[mp.mufree[k]] = conj_out ? conj(v) : v;
@@ -447,354 +579,557 @@ __global__ void k_assemble(Geo2 g, Maps2 mp, const cd* Ubuf, const cd* uc, cd* x
 }
 
 // ------------------------------------------------------------------------------------------
-// Interface phases (device functions shared by the persistent GMRES kernel and
-// the stand-alone test kernels).
+// Interface phases for NRT right-hand sides at once (device functions shared by
+// the persistent GMRES kernel and the stand-alone test kernels).  Vectors of RHS
+// r are r-major copies: base + r * stride.  A scale of zero switches an RHS off.
 
-// Abuf[s] = S_bb^s x,  x_i = 0.5 * sc * sign_i * vin[mid_i]   (W = 1/2).
-// S_bb is complex64 (packed); it is staged into `buf` unless `resident`.
-template <class TS>
+// y_r = S x_r for r < NRT with S packed in LDS (nd <= 128); thread (i, half)
+// sums half of the k range, half 1 hands its partial sums to half 0 through red,
+// and half 0 stores y_r[i] coherently to out + r * ostride + i.
+template <class TM, class R, int NRT>
+__device__ inline void symv_packed_nr(const TM* A, int nd, const C<R>* xs, C<R>* red, cd* out,
+                                      int64_t ostride, int nr) {
+  const int i = threadIdx.x & 127, half = threadIdx.x >> 7;
+  const int h = (nd + 1) / 2;
+  const int k0 = half ? h : 0, k1 = half ? nd : h;
+  C<R> acc[NRT];
+#pragma unroll
+  for (int r = 0; r < NRT; ++r) acc[r] = C<R>{0, 0};
+  if (i < nd) {
+    const int rb = i * (i + 1) / 2;
+    const int kr = min(k1, i + 1);
+    for (int k = k0; k < kr; ++k) {
+      C<R> a = cvt<R>(A[rb + k]);
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) fma_acc(acc[r], a, xs[k * NRT + r]);
+    }
+    int k = max(k0, i + 1);
+    int cb = k * (k + 1) / 2;
+    for (; k < k1; ++k) {
+      C<R> a = cvt<R>(A[cb + i]);
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) fma_acc(acc[r], a, xs[k * NRT + r]);
+      cb += k + 1;
+    }
+  }
+  if (half == 1 && i < nd) {
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) red[i * NRT + r] = acc[r];
+  }
+  __syncthreads();
+  if (half == 0 && i < nd) {
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      if (r >= nr) break;
+      C<R> v = acc[r] + red[i * NRT + r];
+      st_coh(out + r * ostride + i, cd{(double)v.x, (double)v.y});
+    }
+  }
+  __syncthreads();
+}
+
+// Abuf_r[s] = S_bb^s x_r,  x_r[i] = 0.5 * sc[r] * sign_i * vin_r[mid_i]   (W = 1/2).
+// S_bb is complex64 (packed); staged into `buf` unless `resident`.
+template <class TS, int NRT>
 __device__ void phase_precond(const Geo2& g, const Maps2& mp, const cf* __restrict__ Sbb, int s,
-                              const cd* vin, double sc, cd* Abuf, cf* buf, bool resident,
-                              typename real_of<TS>::type* xs_raw, cd* red, cd* ys) {
+                              const cd* vin, int64_t vstride, const double* sc, cd* Abuf,
+                              int64_t astride, int nr, cf* buf, bool resident,
+                              C<typename real_of<TS>::type>* xs, C<typename real_of<TS>::type>* red) {
   using R = typename real_of<TS>::type;
-  using T = C<R>;
-  T* xs = (T*)xs_raw;
   const int ND = g.ND, nd = mp.nd[s];
   __syncthreads();
   if (!resident) stage_lds(buf, Sbb + (size_t)s * packed_len(ND), packed_len(nd) * (int)sizeof(cf));
-  for (int i = threadIdx.x; i < ND; i += blockDim.x) {
-    T v{0, 0};
-    if (i < nd) {
-      cd m = (0.5 * sc * mp.dsgn[s * ND + i]) * ld_coh(vin + mp.dmid[s * ND + i]);
-      v = T{(R)m.x, (R)m.y};
+  // vin + r * vstride is valid memory for every r < NRT: load all, then select
+  // (a switched-off RHS may hold stale values)
+  for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+    const int mid = mp.dmid[s * ND + i];
+    const double sg = 0.5 * mp.dsgn[s * ND + i];
+    cd m[NRT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) m[r] = ld_coh(vin + r * vstride + mid);
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      cd v = (sg * sc[r]) * m[r];
+      xs[i * NRT + r] = (r < nr && sc[r] != 0.0) ? C<R>{(R)v.x, (R)v.y} : C<R>{0, 0};
     }
-    xs[i] = v;
   }
   __syncthreads();
-  symv_packed<cf, R>(buf, nd, xs, red, ys);
-  for (int i = threadIdx.x; i < nd; i += blockDim.x) st_coh(Abuf + (size_t)s * ND + i, ys[i]);
+  symv_packed_nr<cf, R, NRT>(buf, nd, xs, red, Abuf + (size_t)s * ND, astride, nr);
 }
 
-// Ybuf[s] = Z_rr^-1|Delta x, Cbuf[s] = Phi^T x.   x from Abuf (preconditioned
-// vector, from_abuf) or directly x_i = sign_i * vin[mid_i].  Sinv (packed, in the
-// storage precision) is staged into `buf` unless `resident`.
-template <class TS>
-__device__ void phase_f1(const Geo2& g, const Maps2& mp, const TS* __restrict__ Sinv,
-                         const TS* __restrict__ Phi, int s, bool from_abuf, const cd* Abuf,
-                         const cd* vin, cd* Ybuf, cd* Cbuf, TS* buf, bool resident,
-                         typename real_of<TS>::type* xs_raw, cd* red, cd* ys) {
+// Ybuf_r[s] = Z_rr^-1|Delta x_r,  Cbuf_r[s] = Phi^T x_r.  x_r from Abuf_r (the
+// preconditioned vector, from_abuf) or x_r[i] = sc[r] * sign_i * vin_r[mid_i].
+template <class TS, int NRT>
+__device__ void phase_f1(const Geo2& g, const Maps2& mp, const RhsStride& rs,
+                         const TS* __restrict__ Sinv, const TS* __restrict__ Phi, int s,
+                         bool from_abuf, const cd* Abuf, const cd* vin, const double* sc, cd* Ybuf,
+                         cd* Cbuf, int nr, TS* buf, bool resident,
+                         C<typename real_of<TS>::type>* xs, C<typename real_of<TS>::type>* red) {
   using R = typename real_of<TS>::type;
-  using T = C<R>;
-  T* xs = (T*)xs_raw;
   const int ND = g.ND, nd = mp.nd[s];
   __syncthreads();
   if (!resident) stage_lds(buf, Sinv + (size_t)s * packed_len(ND), packed_len(nd) * (int)sizeof(TS));
-  for (int i = threadIdx.x; i < ND; i += blockDim.x) {
-    T v{0, 0};
-    if (i < nd) {
-      cd m;
-      if (from_abuf) m = 0.5 * (ld_coh(Abuf + (size_t)s * ND + i) - ld_coh(Abuf + mp.dpart[s * ND + i]));
-      else m = (double)mp.dsgn[s * ND + i] * ld_coh(vin + mp.dmid[s * ND + i]);
-      v = T{(R)m.x, (R)m.y};
+  for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+    const int part = mp.dpart[s * ND + i], mid = mp.dmid[s * ND + i];
+    const double sg = mp.dsgn[s * ND + i];
+    cd m[NRT];
+    if (from_abuf) {
+      cd u[NRT], v[NRT];
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) {
+        u[r] = ld_coh(Abuf + r * rs.sb + (size_t)s * ND + i);
+        v[r] = ld_coh(Abuf + r * rs.sb + part);
+      }
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) m[r] = 0.5 * (u[r] - v[r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) m[r] = ld_coh(vin + r * rs.nmu + mid);
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) m[r] = (sg * sc[r]) * m[r];
     }
-    xs[i] = v;
+#pragma unroll
+    for (int r = 0; r < NRT; ++r)
+      xs[i * NRT + r] = (r < nr && sc[r] != 0.0) ? C<R>{(R)m[r].x, (R)m[r].y} : C<R>{0, 0};
   }
   __syncthreads();
-  symv_packed<TS, R>(buf, nd, xs, red, ys);
-  for (int i = threadIdx.x; i < nd; i += blockDim.x) st_coh(Ybuf + (size_t)s * ND + i, ys[i]);
+  symv_packed_nr<TS, R, NRT>(buf, nd, xs, red, Ybuf + (size_t)s * ND, rs.sb, nr);
   // corner products: one wavefront per corner slot
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  cd acc{0.0, 0.0};
+  cd acc[NRT];
+#pragma unroll
+  for (int r = 0; r < NRT; ++r) acc[r] = cd{0.0, 0.0};
   if (mp.cloc[s * 4 + q] >= 0) {
     for (int i = lane; i < nd; i += 64) {
-      T x = xs[i];
-      fma_acc(acc, cvt<double>(Phi[((size_t)s * ND + i) * 4 + q]), cd{(double)x.x, (double)x.y});
+      cd ph = cvt<double>(Phi[((size_t)s * ND + i) * 4 + q]);
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) {
+        C<R> x = xs[i * NRT + r];
+        fma_acc(acc[r], ph, cd{(double)x.x, (double)x.y});
+      }
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    acc.x += __shfl_down(acc.x, off, 64);
-    acc.y += __shfl_down(acc.y, off, 64);
+#pragma unroll
+  for (int r = 0; r < NRT; ++r) {
+    for (int off = 32; off > 0; off >>= 1) {
+      acc[r].x += __shfl_down(acc[r].x, off, 64);
+      acc[r].y += __shfl_down(acc[r].y, off, 64);
+    }
+    if (lane == 0 && r < nr) st_coh(Cbuf + r * rs.c4 + s * 4 + q, acc[r]);
   }
-  if (lane == 0) st_coh(Cbuf + s * 4 + q, acc);
 }
 
-// Ybuf[s] += Phi uc_own with uc = K_cc*^-1 g, g_c = sum of Cbuf over the corner's owners.
-template <class TS>
-__device__ void phase_f2(const Geo2& g, const Maps2& mp, const TS* __restrict__ Phi,
-                         const cd* __restrict__ Kinv, int s, const cd* Cbuf, cd* Ybuf, cd* gsh,
-                         cd* ucs) {
+// Ybuf_r[s] += Phi uc_r with uc_r = K_cc*^-1 g_r on the subdomain's corners and
+// g_r[c] = sum of Cbuf_r over the owners of corner c.  Transposed product:
+// thread t forms g_r[c] for the corners c = t, t + 256, ... and accumulates
+// K_cc*^-1[c_q][c] g_r[c] for the four corner slots q; one block reduction then
+// gives uc_r[q].  wred holds 16 * NRT complex values, ucs 4 * NRT.
+template <class TS, int NRT>
+__device__ void phase_f2(const Geo2& g, const Maps2& mp, const RhsStride& rs,
+                         const TS* __restrict__ Phi, const cd* __restrict__ Kinv, int s,
+                         const cd* Cbuf, cd* Ybuf, int nr, cd* ucs, cd* wred) {
   const int ND = g.ND, nd = mp.nd[s];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __syncthreads();
+  int cq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cq[q] = mp.cgid[s * 4 + q];
+  cd acc[4][NRT];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) acc[q][r] = cd{0.0, 0.0};
   for (int c = threadIdx.x; c < g.nC; c += blockDim.x) {
-    cd v{0.0, 0.0};
-    for (int o = 0; o < 4; ++o) {
-      int own = mp.cown[c * 4 + o];
-      if (own >= 0) v = v + ld_coh(Cbuf + own);
+    const int4 own = *(const int4*)(mp.cown + 4 * c);
+    const int ow[4] = {own.x, own.y, own.z, own.w};
+    cd gc[NRT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      cd t[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) t[o] = ld_coh(Cbuf + r * rs.c4 + max(ow[o], 0));
+      cd v{0.0, 0.0};
+#pragma unroll
+      for (int o = 0; o < 4; ++o) v = v + (ow[o] >= 0 ? t[o] : cd{0.0, 0.0});
+      gc[r] = r < nr ? v : cd{0.0, 0.0};
     }
-    gsh[c] = v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (cq[q] < 0) continue;
+      const cd kv = Kinv[(size_t)cq[q] * g.nC + c];
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) fma_acc(acc[q][r], kv, gc[r]);
+    }
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      cd a = acc[q][r];
+      for (int off = 32; off > 0; off >>= 1) {
+        a.x += __shfl_xor(a.x, off, 64);
+        a.y += __shfl_xor(a.y, off, 64);
+      }
+      if (lane == 0) wred[(wv * 4 + q) * NRT + r] = a;
+    }
   __syncthreads();
-  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  int c = mp.cgid[s * 4 + q];
-  cd acc{0.0, 0.0};
-  if (c >= 0)
-    for (int k = lane; k < g.nC; k += 64) fma_acc(acc, Kinv[(size_t)c * g.nC + k], gsh[k]);
-  for (int off = 32; off > 0; off >>= 1) {
-    acc.x += __shfl_down(acc.x, off, 64);
-    acc.y += __shfl_down(acc.y, off, 64);
+  if (threadIdx.x < 4 * NRT) {
+    const int q = threadIdx.x / NRT, r = threadIdx.x % NRT;
+    ucs[q * NRT + r] = (wred[q * NRT + r] + wred[(4 + q) * NRT + r]) +
+                       (wred[(8 + q) * NRT + r] + wred[(12 + q) * NRT + r]);
   }
-  if (lane == 0) ucs[q] = acc;
   __syncthreads();
   for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-    cd y = ld_coh(Ybuf + (size_t)s * ND + i);
-    for (int qq = 0; qq < 4; ++qq) {
-      if (mp.cgid[s * 4 + qq] < 0) continue;
-      fma_acc(y, cvt<double>(Phi[((size_t)s * ND + i) * 4 + qq]), ucs[qq]);
+    cd ph[4];
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq)
+      ph[qq] = cq[qq] >= 0 ? cvt<double>(Phi[((size_t)s * ND + i) * 4 + qq]) : cd{0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      if (r >= nr) break;
+      cd* yp = Ybuf + r * rs.sb + (size_t)s * ND + i;
+      cd y = ld_coh(yp);
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) fma_acc(y, ph[qq], ucs[qq * NRT + r]);
+      st_coh(yp, y);
     }
-    st_coh(Ybuf + (size_t)s * ND + i, y);
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// Persistent GMRES on F_DP P^-1 t = d.
+// Persistent GMRES on F_DP P^-1 t_r = d_r for nr <= NRT right-hand sides in lockstep.
+// Each RHS has its own Krylov basis, Hessenberg matrix, Givens rotations and
+// stopping test; a converged RHS is switched off (scale 0) while the others go on.
 struct GmresArgs {
-  const cd* d;
-  cd* mu;
-  cd* Abuf;
-  cd* Ybuf;
-  cd* Cbuf;
-  cd* w;
-  cd* Q;      // [(kmax+1)][nmu]
-  cd* H;      // [(kmax+1)][kmax] column j at H[i*kmax + j]
-  cd* part;   // [3][kmax+2][nblocks]
+  RhsStride rs;
+  const cd* d;      // [r][nmu]
+  cd* mu;           // [r][nmu]
+  cd* Abuf;         // [r][nsub*ND]
+  cd* Ybuf;         // [r][nsub*ND]
+  cd* Cbuf;         // [r][nsub*4]
+  cd* w;            // [r][nmu]
+  cd* Q;            // [r][kmax_alloc+1][nmu]
+  cd* H;            // [r][kmax_alloc+1][kmax_alloc], column j at H[i*kstride + j]
+  cd* part;         // [3][NRMAX][kmax+2][nb]
   unsigned* bar;
-  int* flags; // [0] iterations, [1] barrier error
-  double* scal; // [0] final relative residual estimate
+  int* flags;       // [1] barrier error, [3] loop trips, [4] summed iterations
+  int* its_out;     // [r] iterations of RHS r
+  double* scal;     // [r] final relative residual estimate
   double tol;
-  int kmax;
+  int kmax;         // iteration limit of this launch
+  int kstride;      // kmax_alloc (strides of Q and H)
   int chunk;
+  int nr;
   int resident;     // Schur blocks kept in LDS (requires one subdomain per block)
-  int lds_bufA;     // byte offset of the second resident buffer
+  int* its_dst[NRMAX];  // optional extra destination of the iteration count of RHS r
+  // byte offsets into dynamic LDS (gmres_layout)
+  int o_red, o_xs, o_wch, o_hv, o_h2, o_cs, o_sn, o_g, o_ucs, o_S, o_I;
 };
 
-// Dynamic LDS of k_gmres: work arrays, then the Schur-block buffers (two
-// resident blocks, or one staging buffer).
-__host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+static inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
-template <class TS>
+// Dynamic LDS of k_gmres: the work arrays, then the Schur-block buffers (both
+// resident, or one staging buffer shared by the two).  Returns the total size.
+static size_t gmres_layout(int nrt, int kmax, int chunk, size_t tsz, size_t bytesS, size_t bytesI,
+                           bool resident, GmresArgs* a) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align16(bytes); return (int)at; };
+  int red = take(tsz * 128 * nrt), xs = take(tsz * 128 * nrt);
+  int wch = take(sizeof(cd) * nrt * chunk);
+  int hv = take(sizeof(cd) * nrt * (kmax + 1)), h2 = take(sizeof(cd) * nrt * (kmax + 1));
+  int cs = take(sizeof(cd) * nrt * (kmax + 1)), sn = take(sizeof(double) * nrt * (kmax + 1));
+  int g = take(sizeof(cd) * nrt * (kmax + 1)), ucs = take(sizeof(cd) * 4 * nrt);
+  int S = take(resident ? bytesS : std::max(bytesS, bytesI));
+  int I = resident ? take(bytesI) : S;
+  if (a) {
+    a->o_red = red; a->o_xs = xs; a->o_wch = wch; a->o_hv = hv; a->o_h2 = h2; a->o_cs = cs;
+    a->o_sn = sn; a->o_g = g; a->o_ucs = ucs; a->o_S = S; a->o_I = I;
+  }
+  return o;
+}
+
+template <class TS, int NRT>
 __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __restrict__ Sbb,
                                                const TS* __restrict__ Sinv,
                                                const TS* __restrict__ Phi,
                                                const cd* __restrict__ Kinv, GmresArgs a) {
   using R = typename real_of<TS>::type;
+  using T = C<R>;
   extern __shared__ __align__(16) char smem[];
-  // dynamic LDS layout
-  cd* red = (cd*)smem;                          // 256
-  cd* ys = red + 256;                           // ND (<= 256)
-  R* xs = (R*)(ys + 256);                       // 2 * 256 reals
-  cd* gsh = (cd*)(xs + 512);                    // nC
-  cd* wch = gsh + g.nC;                         // chunk
-  cd* hv = wch + a.chunk;                       // kmax + 1
-  cd* h2 = hv + a.kmax + 1;                     // kmax + 1
-  cd* csv = h2 + a.kmax + 1;                    // kmax
-  cd* snv = csv + a.kmax;                       // kmax
-  cd* gv = snv + a.kmax;                        // kmax + 1
-  cd* ucs = gv + a.kmax + 1;                    // 4
-  char* mats = (char*)(ucs + 4);
-  cf* bufS = (cf*)mats;                         // S_bb (resident) or the staging buffer
-  TS* bufI = a.resident ? (TS*)(mats + a.lds_bufA) : (TS*)mats;  // Z_rr^-1|Delta
+  const int kmax = a.kmax, nr = a.nr;
+  T* red = (T*)(smem + a.o_red);
+  T* xs = (T*)(smem + a.o_xs);
+  cd* wch = (cd*)(smem + a.o_wch);
+  cd* hv = (cd*)(smem + a.o_hv);
+  cd* h2 = (cd*)(smem + a.o_h2);
+  cd* csv = (cd*)(smem + a.o_cs);
+  double* snv = (double*)(smem + a.o_sn);
+  cd* gv = (cd*)(smem + a.o_g);
+  cd* ucs = (cd*)(smem + a.o_ucs);
+  cf* bufS = (cf*)(smem + a.o_S);   // S_bb (resident) or staging
+  TS* bufI = (TS*)(smem + a.o_I);   // Z_rr^-1|Delta (resident) or the same staging buffer
+  cd* wred = (cd*)red;              // coarse-phase reduction scratch (16 * NRT values)
+  __shared__ double sc[NRT], beta0[NRT], hnrm[NRT], resid[NRT], nsum[NRT], wsum[4];
+  __shared__ cd nrm2[NRT];
+  __shared__ int active[NRT], its[NRT], ract[NRT], nact_sh;
+
+  const unsigned nb = gridDim.x;
+  const int b = blockIdx.x;
+  unsigned epoch = 0;
+  const int nmu = g.nmu;
+  const RhsStride rs = a.rs;
+  const int k0 = min(nmu, b * a.chunk), k1 = min(nmu, k0 + a.chunk), kn = k1 - k0;
+  // vector phases: RHS rt = threadIdx / TPR is served by TPR threads (whole waves)
+  constexpr int TPR = 256 / NRT;
+  const int rt = threadIdx.x / TPR, lt = threadIdx.x % TPR;
+  const int64_t pstride = (int64_t)(kmax + 2) * nb;  // per-RHS block of partial sums
+  cd* part0 = a.part;
+  cd* part1 = a.part + (size_t)NRMAX * pstride;
+  cd* part2 = a.part + (size_t)2 * NRMAX * pstride;
+  const int64_t qs = (int64_t)(a.kstride + 1) * nmu;   // Krylov basis stride per RHS
+  const int64_t hs = (int64_t)(a.kstride + 1) * a.kstride;
+  const int hst = kmax + 1;                            // LDS stride of the per-RHS arrays
+
   if (a.resident) {
     // one subdomain per block: both Schur blocks stay in LDS for the whole solve
     const int s = blockIdx.x, nd = mp.nd[s];
     stage_lds(bufS, Sbb + (size_t)s * packed_len(g.ND), packed_len(nd) * (int)sizeof(cf));
     stage_lds(bufI, Sinv + (size_t)s * packed_len(g.ND), packed_len(nd) * (int)sizeof(TS));
   }
-  __shared__ double sc_sh[4];
-  __shared__ int stop_sh;
-
-  const unsigned nb = gridDim.x;
-  const int b = blockIdx.x;
-  unsigned epoch = 0;
-  const int nmu = g.nmu, kmax = a.kmax;
-  const int k0 = min(nmu, b * a.chunk), k1 = min(nmu, k0 + a.chunk), kn = k1 - k0;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  cd* part0 = a.part;
-  cd* part1 = a.part + (size_t)(kmax + 2) * nb;
-  cd* part2 = a.part + (size_t)2 * (kmax + 2) * nb;
-
-  // block reduction of a real value into thread 0
-  auto block_sum_real = [&](double v) -> double {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) sc_sh[wv] = v;
+  // the list of right-hand sides still iterating (identical in every block)
+  auto refresh_active = [&]() {
+    if (threadIdx.x == 0) {
+      int n = 0;
+      for (int r = 0; r < nr; ++r)
+        if (active[r]) ract[n++] = r;
+      nact_sh = n;
+    }
     __syncthreads();
-    double t = sc_sh[0] + sc_sh[1] + sc_sh[2] + sc_sh[3];
-    __syncthreads();
-    return t;
   };
 
-  // ---- init: beta0 = ||d||
+  // ---- init: beta0_r = ||d_r||
   {
     double loc = 0.0;
-    for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) loc += abs2(a.d[k]);
-    double t = block_sum_real(loc);
-    if (threadIdx.x == 0) st_coh(part2 + b, cd{t, 0.0});
+    if (rt < nr)
+      for (int k = k0 + lt; k < k1; k += TPR) loc += abs2(a.d[rt * rs.nmu + k]);
+    rhs_block_sums<NRT>(loc, wsum, nsum);
+    if (threadIdx.x < nr) st_coh(part2 + threadIdx.x * pstride + b, cd{nsum[threadIdx.x], 0.0});
   }
-  grid_barrier(a.bar, nb, epoch, a.flags + 1);
-  reduce_partials(part2, nb, 1, ucs);
-  const double beta0 = sqrt(ucs[0].x);
+  if (threadIdx.x < NRT) ract[threadIdx.x] = threadIdx.x;
   __syncthreads();
-  if (threadIdx.x == 0) gv[0] = cd{beta0, 0.0};
-  if (beta0 == 0.0) {
-    for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) a.mu[k] = cd{0.0, 0.0};
-    if (b == 0 && threadIdx.x == 0) { a.flags[0] = 0; a.scal[0] = 0.0; }
-    return;
+  grid_barrier(a.bar, nb, epoch, a.flags + 1);
+  reduce_partials(part2, pstride, nb, 1, nr, ract, nrm2, 1);
+  if (threadIdx.x < NRT) {
+    const int r = threadIdx.x;
+    double b0 = r < nr ? sqrt(nrm2[r].x) : 0.0;
+    beta0[r] = b0;
+    active[r] = b0 > 0.0;
+    its[r] = 0;
+    sc[r] = b0 > 0.0 ? 1.0 / b0 : 0.0;
+    gv[r * hst] = cd{b0, 0.0};
+    resid[r] = b0 > 0.0 ? 1.0 : 0.0;
   }
+  __syncthreads();
+  refresh_active();
   const cd* vin = a.d;
-  double vscale = 1.0 / beta0;
-  int j = 0, iters = 0;
-  double resid = 1.0;
-  for (j = 0; j < kmax; ++j) {
-    // ---- P: Abuf = S_bb (W B^T q_j); also store q_j = vin * vscale
-    for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
-      a.Q[(size_t)j * nmu + k] = vscale * ld_coh(vin + k);
+  int j = 0;
+  for (j = 0; j < kmax && nact_sh > 0; ++j) {
+    const int na = nact_sh;
+    const bool mine = rt < nr && active[rt];
+    // ---- P: Abuf = S_bb (W B^T q_j) for the active RHS; store q_j = sc * vin
+    if (mine)
+      for (int k = k0 + lt; k < k1; k += TPR)
+        a.Q[rt * qs + (size_t)j * nmu + k] = sc[rt] * ld_coh(vin + rt * rs.nmu + k);
     for (int s = b; s < g.nsub; s += nb)
-      phase_precond<TS>(g, mp, Sbb, s, vin, vscale, a.Abuf, bufS, a.resident, xs, red, ys);
+      phase_precond<TS, NRT>(g, mp, Sbb, s, vin, rs.nmu, sc, a.Abuf, rs.sb, nr, bufS, a.resident,
+                             xs, red);
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
     // ---- F1
     for (int s = b; s < g.nsub; s += nb)
-      phase_f1<TS>(g, mp, Sinv, Phi, s, true, a.Abuf, nullptr, a.Ybuf, a.Cbuf, bufI, a.resident, xs,
-                   red, ys);
+      phase_f1<TS, NRT>(g, mp, rs, Sinv, Phi, s, true, a.Abuf, nullptr, sc, a.Ybuf, a.Cbuf, nr, bufI,
+                        a.resident, xs, red);
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
     // ---- F2 (coarse correction)
-    for (int s = b; s < g.nsub; s += nb) phase_f2<TS>(g, mp, Phi, Kinv, s, a.Cbuf, a.Ybuf, gsh, ucs);
+    for (int s = b; s < g.nsub; s += nb)
+      phase_f2<TS, NRT>(g, mp, rs, Phi, Kinv, s, a.Cbuf, a.Ybuf, nr, ucs, wred);
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
-    // ---- O1: w = B_r Y (combine), first Gram-Schmidt projections
-    for (int k = threadIdx.x; k < kn; k += blockDim.x) {
-      int kk = k0 + k;
-      wch[k] = ld_coh(a.Ybuf + mp.muown[2 * kk]) - ld_coh(a.Ybuf + mp.muown[2 * kk + 1]);
-    }
+    // ---- O1: w_r = B_r Y_r (combine), first Gram-Schmidt projections
+    if (mine)
+      for (int k = lt; k < kn; k += TPR) {
+        const int kk = k0 + k;
+        wch[rt * a.chunk + k] = ld_coh(a.Ybuf + rt * rs.sb + mp.muown[2 * kk]) -
+                                ld_coh(a.Ybuf + rt * rs.sb + mp.muown[2 * kk + 1]);
+      }
     __syncthreads();
-    block_dots(a.Q, nmu, k0, kn, j + 1, wch, part0, nb, b);
+    block_dots(a.Q, qs, nmu, k0, kn, j + 1, na, ract, wch, a.chunk, part0, pstride, nb, b);
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
-    // ---- O2: h = sum partials; w -= Q h; second projections
-    reduce_partials(part0, nb, j + 1, hv);
-    for (int k = threadIdx.x; k < kn; k += blockDim.x) {
-      cd v = wch[k];
+    // ---- O2: h = sum of partials; w -= Q h; second projections
+    reduce_partials(part0, pstride, nb, j + 1, na, ract, hv, hst);
+    if (mine) {
+      const cd* Qr = a.Q + rt * qs;
+      const cd* hr = hv + rt * hst;
+      for (int k = lt; k < kn; k += TPR) {
+        cd v = wch[rt * a.chunk + k];
 #pragma unroll 8
-      for (int i = 0; i <= j; ++i) v = v - hv[i] * a.Q[(size_t)i * nmu + k0 + k];
-      wch[k] = v;
+        for (int i = 0; i <= j; ++i) v = v - hr[i] * Qr[(size_t)i * nmu + k0 + k];
+        wch[rt * a.chunk + k] = v;
+      }
     }
     __syncthreads();
-    block_dots(a.Q, nmu, k0, kn, j + 1, wch, part1, nb, b);
+    block_dots(a.Q, qs, nmu, k0, kn, j + 1, na, ract, wch, a.chunk, part1, pstride, nb, b);
     grid_barrier(a.bar, nb, epoch, a.flags + 1);
     // ---- O3: second correction, norm
-    reduce_partials(part1, nb, j + 1, h2);
-    double loc = 0.0;
-    for (int k = threadIdx.x; k < kn; k += blockDim.x) {
-      cd v = wch[k];
+    reduce_partials(part1, pstride, nb, j + 1, na, ract, h2, hst);
+    {
+      double loc = 0.0;
+      if (mine) {
+        const cd* Qr = a.Q + rt * qs;
+        const cd* h2r = h2 + rt * hst;
+        for (int k = lt; k < kn; k += TPR) {
+          cd v = wch[rt * a.chunk + k];
 #pragma unroll 8
-      for (int i = 0; i <= j; ++i) v = v - h2[i] * a.Q[(size_t)i * nmu + k0 + k];
-      st_coh(a.w + k0 + k, v);
-      loc += abs2(v);
-    }
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) hv[i] = hv[i] + h2[i];
-    double t = block_sum_real(loc);
-    if (threadIdx.x == 0) st_coh(part2 + b, cd{t, 0.0});
-    grid_barrier(a.bar, nb, epoch, a.flags + 1);
-    // ---- Arnoldi column j complete: hn, Givens rotations (identical in every block)
-    reduce_partials(part2, nb, 1, ucs);
-    double hn = sqrt(ucs[0].x);
-    if (threadIdx.x == 0) {
-      for (int i = 0; i < j; ++i) {
-        cd c = csv[i], sn = snv[i];
-        cd t0 = c * hv[i] + sn * hv[i + 1];
-        cd t1 = conj(c) * hv[i + 1] - conj(sn) * hv[i];
-        hv[i] = t0;
-        hv[i + 1] = t1;
+          for (int i = 0; i <= j; ++i) v = v - h2r[i] * Qr[(size_t)i * nmu + k0 + k];
+          st_coh(a.w + rt * rs.nmu + k0 + k, v);
+          loc += abs2(v);
+        }
+        for (int i = lt; i <= j; i += TPR) hv[rt * hst + i] = hv[rt * hst + i] + h2[rt * hst + i];
       }
-      cd hj = hv[j];
+      rhs_block_sums<NRT>(loc, wsum, nsum);
+      if (threadIdx.x < nr && active[threadIdx.x])
+        st_coh(part2 + threadIdx.x * pstride + b, cd{nsum[threadIdx.x], 0.0});
+    }
+    grid_barrier(a.bar, nb, epoch, a.flags + 1);
+    // ---- Arnoldi column j complete: norms, Givens rotations (identical in every block)
+    reduce_partials(part2, pstride, nb, 1, na, ract, nrm2, 1);
+    if (threadIdx.x < nr && active[threadIdx.x]) {
+      const int r = threadIdx.x;
+      cd* hr = hv + r * hst;
+      cd* cr = csv + r * hst;
+      double* sr = snv + r * hst;
+      cd* gr = gv + r * hst;
+      const double hn = sqrt(nrm2[r].x);
+      hnrm[r] = hn;
+      // rotation [c s; -s conj(c)] with real s maps (h_j, hn) to (den, 0)
+      for (int i = 0; i < j; ++i) {
+        cd c = cr[i];
+        double sn = sr[i];
+        cd t0 = c * hr[i] + sn * hr[i + 1];
+        cd t1 = conj(c) * hr[i + 1] - sn * hr[i];
+        hr[i] = t0;
+        hr[i + 1] = t1;
+      }
+      cd hj = hr[j];
       double den = sqrt(abs2(hj) + hn * hn);
-      cd c, sn;
-      if (den == 0.0) { c = cd{1.0, 0.0}; sn = cd{0.0, 0.0}; }
-      else { c = (1.0 / den) * conj(hj); sn = cd{hn / den, 0.0}; }
-      csv[j] = c;
-      snv[j] = sn;
-      hv[j] = c * hj + sn * cd{hn, 0.0};
-      cd gj = gv[j];
-      gv[j + 1] = -(conj(sn) * gj);
-      gv[j] = c * gj;
-      double res = sqrt(abs2(gv[j + 1])) / beta0;
-      sc_sh[0] = res;
-      stop_sh = (res <= a.tol || hn == 0.0 || j + 1 == kmax) ? 1 : 0;
+      cd c;
+      double sn;
+      if (den == 0.0) { c = cd{1.0, 0.0}; sn = 0.0; }
+      else { c = (1.0 / den) * conj(hj); sn = hn / den; }
+      cr[j] = c;
+      sr[j] = sn;
+      hr[j] = c * hj + cd{sn * hn, 0.0};
+      cd gj = gr[j];
+      gr[j + 1] = -(sn * gj);
+      gr[j] = c * gj;
+      double res = sqrt(abs2(gr[j + 1])) / beta0[r];
+      resid[r] = res;
+      its[r] = j + 1;
+      if (res <= a.tol || hn == 0.0 || j + 1 == kmax) active[r] = 0;
     }
     __syncthreads();
-    if (b == 0)
-      for (int i = threadIdx.x; i <= j; i += blockDim.x) st_coh(a.H + (size_t)i * kmax + j, hv[i]);
-    resid = sc_sh[0];
-    iters = j + 1;
-    if (stop_sh) break;
+    if (b == 0 && rt < nr && its[rt] == j + 1)
+      for (int i = lt; i <= j; i += TPR) st_coh(a.H + rt * hs + (size_t)i * a.kstride + j, hv[rt * hst + i]);
+    if (threadIdx.x < NRT) {
+      const int r = threadIdx.x;
+      sc[r] = (r < nr && active[r]) ? 1.0 / hnrm[r] : 0.0;
+    }
+    __syncthreads();
+    refresh_active();
     vin = a.w;
-    vscale = 1.0 / hn;
   }
-  // ---- back substitution H y = g (redundant in every block; H columns from block 0)
+  // ---- back substitution H_r y_r = g_r for all RHS together (redundant in every
+  // block; H from block 0), then t_r = Q_r y_r on the chunk
   grid_barrier(a.bar, nb, epoch, a.flags + 1);
-  const int kk = iters;
-  for (int i = threadIdx.x; i < kk; i += blockDim.x) h2[i] = gv[i];
+  int kmx = 0;
+  for (int r = 0; r < nr; ++r) kmx = max(kmx, its[r]);
+  if (rt < nr)
+    for (int i = lt; i < its[rt]; i += TPR) h2[rt * hst + i] = gv[rt * hst + i];
   __syncthreads();
-  for (int i = kk - 1; i >= 0; --i) {
-    if (threadIdx.x == 0) h2[i] = cdiv(h2[i], ld_coh(a.H + (size_t)i * kmax + i));
+  for (int i = kmx - 1; i >= 0; --i) {
+    if (threadIdx.x < nr && i < its[threadIdx.x]) {
+      const int r = threadIdx.x;
+      h2[r * hst + i] = cdiv(h2[r * hst + i], ld_coh(a.H + r * hs + (size_t)i * a.kstride + i));
+    }
     __syncthreads();
-    cd yi = h2[i];
-    for (int t = threadIdx.x; t < i; t += blockDim.x) h2[t] = h2[t] - ld_coh(a.H + (size_t)t * kmax + i) * yi;
+    if (rt < nr && i < its[rt]) {
+      const cd yi = h2[rt * hst + i];
+      for (int t = lt; t < i; t += TPR)
+        h2[rt * hst + t] = h2[rt * hst + t] - ld_coh(a.H + rt * hs + (size_t)t * a.kstride + i) * yi;
+    }
     __syncthreads();
   }
-  // t = Q y on the chunk
-  for (int k = threadIdx.x; k < kn; k += blockDim.x) {
-    cd v{0.0, 0.0};
+  if (rt < nr) {
+    const cd* Qr = a.Q + rt * qs;
+    const cd* yr = h2 + rt * hst;
+    const int kk = its[rt];
+    for (int k = lt; k < kn; k += TPR) {
+      cd v{0.0, 0.0};
 #pragma unroll 8
-    for (int i = 0; i < kk; ++i) fma_acc(v, a.Q[(size_t)i * nmu + k0 + k], h2[i]);
-    st_coh(a.w + k0 + k, v);
+      for (int i = 0; i < kk; ++i) fma_acc(v, Qr[(size_t)i * nmu + k0 + k], yr[i]);
+      st_coh(a.w + rt * rs.nmu + k0 + k, v);
+    }
   }
+  if (threadIdx.x < NRT) sc[threadIdx.x] = (threadIdx.x < nr && its[threadIdx.x] > 0) ? 1.0 : 0.0;
   grid_barrier(a.bar, nb, epoch, a.flags + 1);
-  // mu = P^-1 t
+  // mu_r = P^-1 t_r
   for (int s = b; s < g.nsub; s += nb)
-    phase_precond<TS>(g, mp, Sbb, s, a.w, 1.0, a.Abuf, bufS, a.resident, xs, red, ys);
+    phase_precond<TS, NRT>(g, mp, Sbb, s, a.w, rs.nmu, sc, a.Abuf, rs.sb, nr, bufS, a.resident, xs,
+                           red);
   grid_barrier(a.bar, nb, epoch, a.flags + 1);
-  for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
-    a.mu[k] = 0.5 * (ld_coh(a.Abuf + mp.muown[2 * k]) - ld_coh(a.Abuf + mp.muown[2 * k + 1]));
+  if (rt < nr)
+    for (int k = k0 + lt; k < k1; k += TPR)
+      a.mu[rt * rs.nmu + k] = its[rt] > 0 ? 0.5 * (ld_coh(a.Abuf + rt * rs.sb + mp.muown[2 * k]) -
+                                                   ld_coh(a.Abuf + rt * rs.sb + mp.muown[2 * k + 1]))
+                                          : cd{0.0, 0.0};
   if (b == 0 && threadIdx.x == 0) {
-    a.flags[0] = iters;
-    a.scal[0] = resid;
+    int tot = 0;
+    for (int r = 0; r < nr; ++r) {
+      a.its_out[r] = its[r];
+      if (a.its_dst[r]) *a.its_dst[r] = its[r];
+      a.scal[r] = resid[r];
+      tot += its[r];
+    }
+    a.flags[3] += j;    // loop trips of this launch (the largest count of the group)
+    a.flags[4] += tot;  // iterations summed over its right-hand sides
   }
 }
 
-// Stand-alone interface kernels for testing (one block per subdomain).
+// Stand-alone interface kernels for testing (one block per subdomain, one RHS).
 template <class TS>
 __global__ void __launch_bounds__(256) k_iface_precond(Geo2 g, Maps2 mp, const cf* Sbb, const cd* x,
                                                        cd* Abuf) {
   using R = typename real_of<TS>::type;
   extern __shared__ __align__(16) char smem[];
-  __shared__ cd red[256], ys[256];
-  __shared__ R xs[512];
-  phase_precond<TS>(g, mp, Sbb, blockIdx.x, x, 1.0, Abuf, (cf*)smem, false, xs, red, ys);
+  __shared__ C<R> red[128], xs[128];
+  __shared__ double sc[1];
+  if (threadIdx.x == 0) sc[0] = 1.0;
+  phase_precond<TS, 1>(g, mp, Sbb, blockIdx.x, x, 0, sc, Abuf, 0, 1, (cf*)smem, false, xs, red);
 }
 template <class TS>
-__global__ void __launch_bounds__(256) k_iface_f1(Geo2 g, Maps2 mp, const TS* Sinv, const TS* Phi,
-                                                  const cd* x, cd* Ybuf, cd* Cbuf) {
+__global__ void __launch_bounds__(256) k_iface_f1(Geo2 g, Maps2 mp, RhsStride rs, const TS* Sinv,
+                                                  const TS* Phi, const cd* x, cd* Ybuf, cd* Cbuf) {
   using R = typename real_of<TS>::type;
   extern __shared__ __align__(16) char smem[];
-  __shared__ cd red[256], ys[256];
-  __shared__ R xs[512];
-  phase_f1<TS>(g, mp, Sinv, Phi, blockIdx.x, false, nullptr, x, Ybuf, Cbuf, (TS*)smem, false, xs,
-               red, ys);
+  __shared__ C<R> red[128], xs[128];
+  __shared__ double sc[1];
+  if (threadIdx.x == 0) sc[0] = 1.0;
+  phase_f1<TS, 1>(g, mp, rs, Sinv, Phi, blockIdx.x, false, nullptr, x, sc, Ybuf, Cbuf, 1, (TS*)smem,
+                  false, xs, red);
 }
 template <class TS>
-__global__ void __launch_bounds__(256) k_iface_f2(Geo2 g, Maps2 mp, const TS* Phi, const cd* Kinv,
-                                                  const cd* Cbuf, cd* Ybuf) {
-  extern __shared__ char smem[];
-  cd* gsh = (cd*)smem;
-  __shared__ cd ucs[4];
-  phase_f2<TS>(g, mp, Phi, Kinv, blockIdx.x, Cbuf, Ybuf, gsh, ucs);
+__global__ void __launch_bounds__(256) k_iface_f2(Geo2 g, Maps2 mp, RhsStride rs, const TS* Phi,
+                                                  const cd* Kinv, const cd* Cbuf, cd* Ybuf) {
+  __shared__ cd ucs[4], wred[16];
+  phase_f2<TS, 1>(g, mp, rs, Phi, Kinv, blockIdx.x, Cbuf, Ybuf, 1, ucs, wred);
 }
 __global__ void k_combine(Geo2 g, Maps2 mp, const cd* buf, double scale, cd* out) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -803,81 +1138,117 @@ __global__ void k_combine(Geo2 g, Maps2 mp, const cd* buf, double scale, cd* out
 }
 
 // ------------------------------------------------------------------------------------------
-// launchers
-template <class TS>
+// launchers (nr right-hand sides, r-major buffers of the problem)
+template <class TS, int NRT>
 static hipError_t local_solve_t(const Problem& p, int mode, const cd* f, int conj_in, cd* xout,
-                                int conj_out) {
-  hipLaunchKernelGGL(k_local_solve<TS>, dim3(p.nsub), dim3(256), 0, p.ctx->stream, p.geo(),
-                     p.maps(), (const TS*)p.G, mode, f, conj_in, p.u0, p.mu, p.Xd, p.Qc, p.Ubuf,
-                     xout, conj_out);
+                                int conj_out, int nr) {
+  hipLaunchKernelGGL((k_local_solve<TS, NRT>), dim3(p.nsub), dim3(256), 0, p.ctx->stream, p.geo(),
+                     p.maps(), p.rs(), nr, (const TS*)p.G, mode, f, conj_in, p.u0, p.mu, p.Xd, p.Qc,
+                     p.Ubuf, xout, conj_out);
   return hipGetLastError();
+}
+
+template <class TS>
+static hipError_t local_solve_w(const Problem& p, int mode, const cd* f, int conj_in, cd* xout,
+                                int conj_out, int nr) {
+  if (nr == 1) return local_solve_t<TS, 1>(p, mode, f, conj_in, xout, conj_out, 1);
+  if (nr == 2) return local_solve_t<TS, 2>(p, mode, f, conj_in, xout, conj_out, 2);
+  return local_solve_t<TS, NRMAX>(p, mode, f, conj_in, xout, conj_out, nr);
 }
 
 hipError_t launch_local_solve(const Problem& p, int mode, const cd* f, int conj_in, cd* x_out,
-                              hipStream_t) {
+                              int nr, hipStream_t) {
+  if (nr < 1 || nr > NRMAX) return hipErrorInvalidValue;
   int conj_out = (mode == 1) ? conj_in : 0;
-  if (p.prec == SFDP_MIXED) return local_solve_t<cf>(p, mode, f, conj_in, x_out, conj_out);
-  return local_solve_t<cd>(p, mode, f, conj_in, x_out, conj_out);
+  if (p.g32()) return local_solve_w<cf>(p, mode, f, conj_in, x_out, conj_out, nr);
+  return local_solve_w<cd>(p, mode, f, conj_in, x_out, conj_out, nr);
 }
 
-hipError_t launch_coarse_rhs(const Problem& p, const cd* f, int conj_in, hipStream_t st) {
-  hipLaunchKernelGGL(k_coarse_rhs, dim3((p.nC + 127) / 128), dim3(128), 0, st, p.geo(), p.maps(), f,
-                     conj_in, p.Qc, p.fcs);
-  if (p.nC > 0) hipLaunchKernelGGL(k_dense_mv, dim3(p.nC), dim3(64), 0, st, p.nC, p.Kinv, p.fcs, p.u0);
+hipError_t launch_coarse_rhs(const Problem& p, const cd* f, int conj_in, int nr, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_rhs, dim3((p.nC + 127) / 128, nr), dim3(128), 0, st, p.geo(), p.maps(),
+                     p.rs(), f, conj_in, p.Qc, p.fcs);
+  if (p.nC > 0)
+    hipLaunchKernelGGL(k_dense_mv, dim3(p.nC, nr), dim3(64), 0, st, p.nC, p.rs().nc, p.Kinv, p.fcs,
+                       p.u0);
   return hipGetLastError();
 }
 
-hipError_t launch_fetidp_rhs(const Problem& p, hipStream_t st) {
-  if (p.prec == SFDP_MIXED)
-    hipLaunchKernelGGL(k_fetidp_rhs<cf>, dim3((p.nmu + 255) / 256), dim3(256), 0, st, p.geo(),
-                       p.maps(), p.Xd, (const cf*)p.Phi, p.u0, p.dvec);
+hipError_t launch_fetidp_rhs(const Problem& p, int nr, hipStream_t st) {
+  if (p.s32())
+    hipLaunchKernelGGL(k_fetidp_rhs<cf>, dim3((p.nmu + 255) / 256, nr), dim3(256), 0, st, p.geo(),
+                       p.maps(), p.rs(), p.Xd, (const cf*)p.Phi, p.u0, p.dvec);
   else
-    hipLaunchKernelGGL(k_fetidp_rhs<cd>, dim3((p.nmu + 255) / 256), dim3(256), 0, st, p.geo(),
-                       p.maps(), p.Xd, (const cd*)p.Phi, p.u0, p.dvec);
+    hipLaunchKernelGGL(k_fetidp_rhs<cd>, dim3((p.nmu + 255) / 256, nr), dim3(256), 0, st, p.geo(),
+                       p.maps(), p.rs(), p.Xd, (const cd*)p.Phi, p.u0, p.dvec);
   return hipGetLastError();
 }
 
-static size_t gmres_work_lds(const Problem& p, int kmax, int chunk) {
-  return sizeof(cd) * (256 + 256) + sizeof(double) * 512 +
-         sizeof(cd) * (p.nC + chunk + 5 * (size_t)(kmax + 1) + 4);
-}
-// Total LDS, and the offset of the second resident buffer.
-static size_t gmres_lds(const Problem& p, int kmax, int chunk, bool resident, size_t* offB) {
-  size_t es = p.prec == SFDP_MIXED ? sizeof(cf) : sizeof(cd);
+// Bytes of one subdomain's packed S_bb (complex64) and Z_rr^-1|Delta blocks.
+static void block_bytes(const Problem& p, size_t* bS, size_t* bI) {
   size_t pk = (size_t)packed_len(p.ndmax);
-  size_t a = align16(pk * sizeof(cf)), b = align16(pk * es);
-  if (offB) *offB = a;
-  return align16(gmres_work_lds(p, kmax, chunk)) + (resident ? a + b : std::max(a, b));
+  *bS = pk * sizeof(cf);
+  *bI = pk * (p.s32() ? sizeof(cf) : sizeof(cd));
 }
 
-template <class TS>
-static hipError_t gmres_t(Problem& p, double tol, int kmax) {
-  hipStream_t st = p.ctx->stream;
-  int nb = p.gmres_blocks;
-  int chunk = (p.nmu + nb - 1) / nb;
-  size_t offB = 0;
-  bool resident = p.prec == SFDP_MIXED && nb == p.nsub &&
-                  gmres_lds(p, kmax, chunk, true, &offB) <= (size_t)p.ctx->max_lds;
-  size_t lds = gmres_lds(p, kmax, chunk, resident, &offB);
+// LDS bytes of k_gmres<TS, NRT> for this problem and whether the Schur blocks
+// stay resident (mixed storage, one subdomain per block, and room for both).
+template <class TS, int NRT>
+static size_t gmres_plan(const Problem& p, int kmax, bool* resident, GmresArgs* a) {
+  using R = typename real_of<TS>::type;
+  const int nb = p.gmres_blocks, chunk = (p.nmu + nb - 1) / nb;
+  size_t bS, bI;
+  block_bytes(p, &bS, &bI);
+  bool res = p.s32() && nb == p.nsub &&
+             gmres_layout(NRT, kmax, chunk, sizeof(C<R>), bS, bI, true, nullptr) <= (size_t)p.ctx->max_lds;
+  if (resident) *resident = res;
+  return gmres_layout(NRT, kmax, chunk, sizeof(C<R>), bS, bI, res, a);
+}
+
+// Whether every block of the cooperative grid of k_gmres<TS, NRT> can be
+// co-resident (0) or not (an error code).
+template <class TS, int NRT>
+static hipError_t gmres_fits(const Problem& p, int kmax) {
+  size_t lds = gmres_plan<TS, NRT>(p, kmax, nullptr, nullptr);
   if (lds > (size_t)p.ctx->max_lds) return hipErrorOutOfMemory;
+  const void* fn = (const void*)k_gmres<TS, NRT>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+  if (e != hipSuccess) return e;
+  return (int64_t)per_cu * p.ctx->num_cu >= p.gmres_blocks ? hipSuccess : hipErrorCooperativeLaunchTooLarge;
+}
+
+// One launch for right-hand sides r0 .. r0 + nr - 1 (nr <= NRT).
+template <class TS, int NRT>
+static hipError_t gmres_t(Problem& p, double tol, int kmax, int r0, int nr) {
+  hipStream_t st = p.ctx->stream;
+  const int nb = p.gmres_blocks;
   GmresArgs a;
-  a.d = p.dvec;
-  a.mu = p.mu;
-  a.Abuf = p.Abuf;
-  a.Ybuf = p.Ybuf;
-  a.Cbuf = p.Cbuf;
-  a.w = p.wv;
+  bool resident = false;
+  size_t lds = gmres_plan<TS, NRT>(p, kmax, &resident, &a);
+  const RhsStride rs = p.rs();
+  a.rs = rs;
+  a.d = p.dvec + r0 * rs.nmu;
+  a.mu = p.mu + r0 * rs.nmu;
+  a.Abuf = p.Abuf + r0 * rs.sb;
+  a.Ybuf = p.Ybuf + r0 * rs.sb;
+  a.Cbuf = p.Cbuf + r0 * rs.c4;
+  a.w = p.wv + r0 * rs.nmu;
   a.Q = p.Qk;
   a.H = p.Hk;
   a.part = p.part;
   a.bar = p.bar;
   a.flags = p.flags;
-  a.scal = p.dscal;
+  a.its_out = p.flags + 8 + r0;
+  a.scal = p.dscal + r0;
   a.tol = tol;
   a.kmax = kmax;
-  a.chunk = chunk;
+  a.kstride = p.kmax_alloc;
+  a.chunk = (p.nmu + nb - 1) / nb;
+  a.nr = nr;
   a.resident = resident ? 1 : 0;
-  a.lds_bufA = (int)offB;
+  for (int r = 0; r < NRMAX; ++r) a.its_dst[r] = r < nr ? p.its_dst[r0 + r] : nullptr;
   hipError_t e = launch_fill(p.bar, BAR_WORDS * sizeof(unsigned), st);
   if (e != hipSuccess) return e;
   Geo2 g = p.geo();
@@ -887,54 +1258,66 @@ static hipError_t gmres_t(Problem& p, double tol, int kmax) {
   const TS* Phi = (const TS*)p.Phi;
   const cd* Kinv = p.Kinv;
   void* args[] = {&g, &mp, &Sbb, &Sinv, &Phi, &Kinv, &a};
-  e = hipFuncSetAttribute((const void*)k_gmres<TS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* fn = (const void*)k_gmres<TS, NRT>;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   p.last_resident = resident;
-  return hipLaunchCooperativeKernel((const void*)k_gmres<TS>, dim3(nb), dim3(256), args, lds, st);
+  p.last_nrt = NRT;
+  return hipLaunchCooperativeKernel(fn, dim3(nb), dim3(256), args, lds, st);
 }
 
-hipError_t launch_gmres(Problem& p, double tol, int kmax, hipStream_t) {
-  if (p.prec == SFDP_MIXED) return gmres_t<cf>(p, tol, kmax);
-  return gmres_t<cd>(p, tol, kmax);
-}
-
-int gmres_max_blocks(const Problem& p, int kmax) {
-  int per_cu = 0;
-  int chunk = (p.nmu + p.gmres_blocks - 1) / p.gmres_blocks;
-  size_t lds = gmres_lds(p, kmax, chunk, false, nullptr);
-  hipError_t e;
-  if (p.prec == SFDP_MIXED) {
-    hipFuncSetAttribute((const void*)k_gmres<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_gmres<cf>, 256, lds);
-  } else {
-    hipFuncSetAttribute((const void*)k_gmres<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_gmres<cd>, 256, lds);
+// nr right-hand sides: the widest kernel (4, 2 or 1 right-hand sides per
+// launch) whose LDS layout and grid fit serves them in consecutive launches.
+template <class TS>
+static hipError_t gmres_group(Problem& p, double tol, int kmax, int nr) {
+  int w = 1;
+  if (nr > 2 && gmres_fits<TS, 4>(p, kmax) == hipSuccess) w = 4;
+  else if (nr > 1 && gmres_fits<TS, 2>(p, kmax) == hipSuccess) w = 2;
+  else {
+    hipError_t e = gmres_fits<TS, 1>(p, kmax);
+    if (e != hipSuccess) return e;
   }
-  if (e != hipSuccess || per_cu < 1) return 0;
-  return per_cu * p.ctx->num_cu;
+  for (int r0 = 0; r0 < nr; r0 += w) {
+    const int n = std::min(w, nr - r0);
+    hipError_t e = w == 4 ? gmres_t<TS, 4>(p, tol, kmax, r0, n)
+                 : w == 2 ? gmres_t<TS, 2>(p, tol, kmax, r0, n)
+                          : gmres_t<TS, 1>(p, tol, kmax, r0, 1);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-size_t gmres_lds_bytes(const Problem& p, int kmax, int nb) {
-  return gmres_lds(p, kmax, (p.nmu + nb - 1) / nb, false, nullptr);
+hipError_t launch_gmres(Problem& p, double tol, int kmax, int nr, hipStream_t) {
+  if (nr < 1 || nr > NRMAX) return hipErrorInvalidValue;
+  if (p.s32()) return gmres_group<cf>(p, tol, kmax, nr);
+  return gmres_group<cd>(p, tol, kmax, nr);
 }
 
-hipError_t launch_recover_coarse(const Problem& p, hipStream_t st) {
-  if (p.prec == SFDP_MIXED)
-    hipLaunchKernelGGL(k_frct<cf>, dim3((p.nsub * 4 + 3) / 4), dim3(256), 0, st, p.geo(),
-                       p.maps(), (const cf*)p.Phi, p.mu, p.Cbuf);
+// Whether the one-RHS GMRES kernel fits this problem (the narrowest one).
+hipError_t gmres_check(const Problem& p, int kmax) {
+  if (p.s32()) return gmres_fits<cf, 1>(p, kmax);
+  return gmres_fits<cd, 1>(p, kmax);
+}
+
+hipError_t launch_recover_coarse(const Problem& p, int nr, hipStream_t st) {
+  if (p.s32())
+    hipLaunchKernelGGL(k_frct<cf>, dim3((p.nsub * 4 + 3) / 4, nr), dim3(256), 0, st, p.geo(), p.maps(),
+                       p.rs(), (const cf*)p.Phi, p.mu, p.Cbuf);
   else
-    hipLaunchKernelGGL(k_frct<cd>, dim3((p.nsub * 4 + 3) / 4), dim3(256), 0, st, p.geo(),
-                       p.maps(), (const cd*)p.Phi, p.mu, p.Cbuf);
-  hipLaunchKernelGGL(k_corner_sum, dim3((p.nC + 127) / 128), dim3(128), 0, st, p.geo(), p.maps(),
-                     p.fcs, p.Cbuf, p.ymin);
-  if (p.nC > 0) hipLaunchKernelGGL(k_dense_mv, dim3(p.nC), dim3(64), 0, st, p.nC, p.Kinv, p.ymin, p.u0);
+    hipLaunchKernelGGL(k_frct<cd>, dim3((p.nsub * 4 + 3) / 4, nr), dim3(256), 0, st, p.geo(), p.maps(),
+                       p.rs(), (const cd*)p.Phi, p.mu, p.Cbuf);
+  hipLaunchKernelGGL(k_corner_sum, dim3((p.nC + 127) / 128, nr), dim3(128), 0, st, p.geo(), p.maps(),
+                     p.rs(), p.fcs, p.Cbuf, p.ymin);
+  if (p.nC > 0)
+    hipLaunchKernelGGL(k_dense_mv, dim3(p.nC, nr), dim3(64), 0, st, p.nC, p.rs().nc, p.Kinv, p.ymin,
+                       p.u0);
   return hipGetLastError();
 }
 
-hipError_t launch_assemble_solution(const Problem& p, cd* x, int conj_out, hipStream_t st) {
+hipError_t launch_assemble_solution(const Problem& p, cd* x, int conj_out, int nr, hipStream_t st) {
   int n = p.nmu + p.nC;
-  hipLaunchKernelGGL(k_assemble, dim3((n + 255) / 256), dim3(256), 0, st, p.geo(), p.maps(), p.Ubuf,
-                     p.u0, x, conj_out);
+  hipLaunchKernelGGL(k_assemble, dim3((n + 255) / 256, nr), dim3(256), 0, st, p.geo(), p.maps(), p.rs(),
+                     p.Ubuf, p.u0, x, conj_out);
   return hipGetLastError();
 }
 
@@ -944,20 +1327,22 @@ static hipError_t iface_t(Problem& p, char which, const cd* x, cd* y, hipStream_
   Maps2 mp = p.maps();
   if (which == 'P') {
     size_t bytes = align16((size_t)packed_len(p.ND) * sizeof(cf));
-    hipFuncSetAttribute((const void*)k_iface_precond<TS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)bytes);
+    hipError_t e = hipFuncSetAttribute((const void*)k_iface_precond<TS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_iface_precond<TS>, dim3(p.nsub), dim3(256), bytes, st, g, mp, (const cf*)p.Sbb,
                        x, p.Abuf);
-    // the stand-alone precond kernel scales by 1/2 on the way in; 1/2 on the way out
+    // the precond phase applies one W = 1/2 on the way in; the second on the way out
     hipLaunchKernelGGL(k_combine, dim3((p.nmu + 255) / 256), dim3(256), 0, st, g, mp, p.Abuf, 0.5, y);
   } else if (which == 'F') {
     size_t bytes = align16((size_t)packed_len(p.ND) * sizeof(TS));
-    hipFuncSetAttribute((const void*)k_iface_f1<TS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)bytes);
-    hipLaunchKernelGGL(k_iface_f1<TS>, dim3(p.nsub), dim3(256), bytes, st, g, mp, (const TS*)p.Sinv,
-                       (const TS*)p.Phi, x, p.Ybuf, p.Cbuf);
-    hipLaunchKernelGGL(k_iface_f2<TS>, dim3(p.nsub), dim3(256), sizeof(cd) * (p.nC + 1), st, g, mp,
-                       (const TS*)p.Phi, p.Kinv, p.Cbuf, p.Ybuf);
+    hipError_t e = hipFuncSetAttribute((const void*)k_iface_f1<TS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_iface_f1<TS>, dim3(p.nsub), dim3(256), bytes, st, g, mp, p.rs(),
+                       (const TS*)p.Sinv, (const TS*)p.Phi, x, p.Ybuf, p.Cbuf);
+    hipLaunchKernelGGL(k_iface_f2<TS>, dim3(p.nsub), dim3(256), 0, st, g, mp, p.rs(), (const TS*)p.Phi,
+                       p.Kinv, p.Cbuf, p.Ybuf);
     hipLaunchKernelGGL(k_combine, dim3((p.nmu + 255) / 256), dim3(256), 0, st, g, mp, p.Ybuf, 1.0, y);
   } else {
     return hipErrorInvalidValue;
@@ -966,7 +1351,7 @@ static hipError_t iface_t(Problem& p, char which, const cd* x, cd* y, hipStream_
 }
 
 hipError_t launch_interface_apply(Problem& p, char which, const cd* x, cd* y, hipStream_t st) {
-  if (p.prec == SFDP_MIXED) return iface_t<cf>(p, which, x, y, st);
+  if (p.s32()) return iface_t<cf>(p, which, x, y, st);
   return iface_t<cd>(p, which, x, y, st);
 }
 

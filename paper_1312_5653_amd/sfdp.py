@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsfdp.so")
 
-SFDP_FP64, SFDP_MIXED = 0, 1
+SFDP_FP64, SFDP_MIXED, SFDP_MIXED_IFACE = 0, 1, 2
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_NOCONV", -4: "E_DEVICE", -5: "E_STATE"}
 Q_SINV, Q_SBB, Q_PHI, Q_COARSE = 0, 1, 2, 3
 
@@ -33,7 +33,7 @@ class SfdpError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tol_kkt", ctypes.c_double), ("tol_inner", ctypes.c_double),
-                ("max_outer", ctypes.c_int), ("max_krylov", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("max_krylov", ctypes.c_int), ("batch", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -52,7 +52,8 @@ class Info(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("gmres_ms", ctypes.c_double), ("local_ms", ctypes.c_double),
                 ("gmres_launches", ctypes.c_int64), ("gmres_iters", ctypes.c_int64),
-                ("local_launches", ctypes.c_int64)]
+                ("local_launches", ctypes.c_int64), ("gmres_rhs_iters", ctypes.c_int64),
+                ("gmres_width", ctypes.c_int), ("gmres_resident", ctypes.c_int)]
 
 
 class Sizes(ctypes.Structure):
@@ -114,8 +115,8 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(tol_kkt=0.0, tol_inner=0.0, max_outer=0, max_krylov=0):
-    return Opts(tol_kkt, tol_inner, max_outer, max_krylov)
+def _opts(tol_kkt=0.0, tol_inner=0.0, max_outer=0, max_krylov=0, batch=0):
+    return Opts(tol_kkt, tol_inner, max_outer, max_krylov, batch)
 
 
 class Context:
@@ -196,16 +197,16 @@ class Problem:
         import torch
         nrhs = 1 if r.dim() == 1 else r.shape[0]
         z = torch.empty_like(r) if z is None else z
-        info = Info()
+        infos = (Info * nrhs)()
         o = _opts(**opts)
-        _check(_lib.sfdp_apply_schur_inv(self._h, nrhs, _ptr(r), _ptr(z), ctypes.byref(o), ctypes.byref(info)))
-        return z, info.as_dict()
+        _check(_lib.sfdp_apply_schur_inv(self._h, nrhs, _ptr(r), _ptr(z), ctypes.byref(o), infos))
+        return z, [i.as_dict() for i in infos]
 
     def feti_solve(self, f, conj_z: bool = False, x=None, **opts):
         import torch
         nrhs = 1 if f.dim() == 1 else f.shape[0]
         x = torch.empty_like(f) if x is None else x
-        its = (ctypes.c_int * max(nrhs, 32))()
+        its = (ctypes.c_int * nrhs)()
         o = _opts(**opts)
         _check(_lib.sfdp_feti_solve(self._h, int(conj_z), nrhs, _ptr(f), _ptr(x), ctypes.byref(o), its))
         return x, list(its)[:nrhs]
