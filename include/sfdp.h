@@ -74,14 +74,14 @@ typedef enum {
 
 /* Arithmetic of the subdomain factors and of the interface operator.
  * SFDP_FP64:  complex128 everywhere.
- * SFDP_MIXED: subdomain factors, subdomain solves and the interface
- *             operators in complex64 with FP32 accumulation; the coarse
- *             problem, the Krylov orthogonalisation, the KKT residual and
- *             the outer iterative refinement in FP64.
- * SFDP_MIXED_IFACE: the interface operators of the Krylov iteration
- *             (S_bb, Z_rr^-1 on Delta, Phi) in complex64 as in SFDP_MIXED;
- *             the subdomain line factors and the two full subdomain solves
- *             of every FETI-DP solve in complex128. */
+ * SFDP_MIXED: subdomain line factors and interface operators (Z_rr^-1 on
+ *             Delta, Phi) stored in complex64 and widened to FP64 as they
+ *             are read; vectors, accumulation, the coarse problem, the
+ *             Krylov orthogonalisation, the KKT residual and the outer
+ *             iterative refinement in FP64.
+ * SFDP_MIXED_IFACE: as SFDP_MIXED, but the subdomain line factors (the two
+ *             full subdomain solves of every FETI-DP solve) in complex128.
+ * In every mode the Dirichlet preconditioner's S_bb is stored in complex64. */
 typedef enum { SFDP_FP64 = 0, SFDP_MIXED = 1, SFDP_MIXED_IFACE = 2 } sfdp_precision;
 
 /* Solver controls; zero-initialised fields take the defaults in brackets. */
@@ -89,9 +89,13 @@ typedef struct {
   double tol_kkt;   /* stop when ||b - A x|| / ||b|| of the KKT system <= tol_kkt
                        [1e-10 FP64, 1e-8 MIXED] */
   double tol_inner; /* relative interface residual of each FETI-DP solve
-                       [1e-8 FP64, 1e-6 MIXED] */
+                       [1e-8 FP64, 1e-7 MIXED] */
   int max_outer;    /* outer refinement steps [8] */
-  int max_krylov;   /* GMRES iterations per FETI-DP solve, <= 400 [150] */
+  int max_krylov;   /* GMRES iterations per FETI-DP solve, <= 400 [64]; the GMRES
+                       kernel keeps per-iteration state for this many steps in
+                       LDS, so a smaller cap leaves room to serve more
+                       right-hand sides per launch (a solve that reaches the
+                       cap is continued by the outer refinement) */
   int batch;        /* right-hand sides solved together, 1..4 [4]: each FETI-DP
                        launch sequence (subdomain solves, persistent GMRES)
                        serves up to this many right-hand sides in lockstep,

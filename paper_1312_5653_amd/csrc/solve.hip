@@ -16,6 +16,13 @@
 //                   vectors, orthogonalisation (classical Gram-Schmidt, twice),
 //                   norms and the coarse solve are FP64; the interface
 //                   Schur complements are streamed in the storage precision.
+//
+// Arithmetic is FP64 for both storage precisions: complex64 factors and
+// operators are widened as they are loaded, and every vector and accumulator
+// (line sweeps, Schur-complement products) is FP64.  The kernels are bound by
+// latency, so this costs little, and it makes the complex64 path's solves
+// accurate to the rounding of the stored factors alone; with FP32 vectors the
+// outer refinement needs one step more.
 #include "common.h"
 
 namespace sfdp {
@@ -294,8 +301,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 k_local_solve(Geo2 g, Maps2 mp, RhsStride rs, int nr, const TS* __restrict__ G, int mode,
               const cd* __restrict__ f, int conj_in, const cd* __restrict__ uc,
               const cd* __restrict__ mu, cd* Xd, cd* Qc, cd* Ubuf, cd* xout, int conj_out) {
-  using R = typename real_of<TS>::type;
-  using T = C<R>;
+  using R = double;  // FP64 arithmetic for both storage precisions
+  using T = cd;
   constexpr int XS = ML * ML;
   __shared__ T xall[NRT * XS];
   __shared__ T zl[NRT * ML];
@@ -634,8 +641,8 @@ template <class TS, int NRT>
 __device__ void phase_precond(const Geo2& g, const Maps2& mp, const cf* __restrict__ Sbb, int s,
                               const cd* vin, int64_t vstride, const double* sc, cd* Abuf,
                               int64_t astride, int nr, cf* buf, bool resident,
-                              C<typename real_of<TS>::type>* xs, C<typename real_of<TS>::type>* red) {
-  using R = typename real_of<TS>::type;
+                              cd* xs, cd* red) {
+  using R = double;  // FP64 arithmetic for both storage precisions
   const int ND = g.ND, nd = mp.nd[s];
   __syncthreads();
   if (!resident) stage_lds(buf, Sbb + (size_t)s * packed_len(ND), packed_len(nd) * (int)sizeof(cf));
@@ -664,8 +671,8 @@ __device__ void phase_f1(const Geo2& g, const Maps2& mp, const RhsStride& rs,
                          const TS* __restrict__ Sinv, const TS* __restrict__ Phi, int s,
                          bool from_abuf, const cd* Abuf, const cd* vin, const double* sc, cd* Ybuf,
                          cd* Cbuf, int nr, TS* buf, bool resident,
-                         C<typename real_of<TS>::type>* xs, C<typename real_of<TS>::type>* red) {
-  using R = typename real_of<TS>::type;
+                         cd* xs, cd* red) {
+  using R = double;  // FP64 arithmetic for both storage precisions
   const int ND = g.ND, nd = mp.nd[s];
   __syncthreads();
   if (!resident) stage_lds(buf, Sinv + (size_t)s * packed_len(ND), packed_len(nd) * (int)sizeof(TS));
@@ -761,17 +768,39 @@ __device__ void phase_f2(const Geo2& g, const Maps2& mp, const RhsStride& rs,
       for (int r = 0; r < NRT; ++r) fma_acc(acc[q][r], kv, gc[r]);
     }
   }
+  {
+    // reduce-scatter over the wave: at each halving step a lane keeps half of its
+    // values and adds its partner's copy of them, so V = 4 NRT sums take
+    // V - 1 + log2(64 / V) shuffles instead of 6 V; lane bits 5.. then name
+    // the value a lane holds (value index = (q, r) in row-major order)
+    constexpr int V = 4 * NRT;
+    cd v[V];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int r = 0; r < NRT; ++r) {
-      cd a = acc[q][r];
-      for (int off = 32; off > 0; off >>= 1) {
-        a.x += __shfl_xor(a.x, off, 64);
-        a.y += __shfl_xor(a.y, off, 64);
+      for (int r = 0; r < NRT; ++r) v[q * NRT + r] = acc[q][r];
+    int idx = 0, off = 32;
+#pragma unroll
+    for (int cnt = V; cnt > 1; cnt >>= 1, off >>= 1) {
+      const int half = cnt >> 1;
+      const bool up = (lane & off) != 0;
+#pragma unroll
+      for (int i = 0; i < half; ++i) {
+        const cd send = up ? v[i] : v[half + i];
+        const cd keep = up ? v[half + i] : v[i];
+        cd recv;
+        recv.x = __shfl_xor(send.x, off, 64);
+        recv.y = __shfl_xor(send.y, off, 64);
+        v[i] = keep + recv;
       }
-      if (lane == 0) wred[(wv * 4 + q) * NRT + r] = a;
+      if (up) idx += half;
     }
+    for (; off > 0; off >>= 1) {
+      v[0].x += __shfl_xor(v[0].x, off, 64);
+      v[0].y += __shfl_xor(v[0].y, off, 64);
+    }
+    if ((lane & (64 / V - 1)) == 0) wred[wv * V + idx] = v[0];
+  }
   __syncthreads();
   if (threadIdx.x < 4 * NRT) {
     const int q = threadIdx.x / NRT, r = threadIdx.x % NRT;
@@ -853,8 +882,8 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
                                                const TS* __restrict__ Sinv,
                                                const TS* __restrict__ Phi,
                                                const cd* __restrict__ Kinv, GmresArgs a) {
-  using R = typename real_of<TS>::type;
-  using T = C<R>;
+  using R = double;  // FP64 arithmetic for both storage precisions
+  using T = cd;
   extern __shared__ __align__(16) char smem[];
   const int kmax = a.kmax, nr = a.nr;
   T* red = (T*)(smem + a.o_red);
@@ -1107,7 +1136,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
 template <class TS>
 __global__ void __launch_bounds__(256) k_iface_precond(Geo2 g, Maps2 mp, const cf* Sbb, const cd* x,
                                                        cd* Abuf) {
-  using R = typename real_of<TS>::type;
+  using R = double;  // FP64 arithmetic for both storage precisions
   extern __shared__ __align__(16) char smem[];
   __shared__ C<R> red[128], xs[128];
   __shared__ double sc[1];
@@ -1117,7 +1146,7 @@ __global__ void __launch_bounds__(256) k_iface_precond(Geo2 g, Maps2 mp, const c
 template <class TS>
 __global__ void __launch_bounds__(256) k_iface_f1(Geo2 g, Maps2 mp, RhsStride rs, const TS* Sinv,
                                                   const TS* Phi, const cd* x, cd* Ybuf, cd* Cbuf) {
-  using R = typename real_of<TS>::type;
+  using R = double;  // FP64 arithmetic for both storage precisions
   extern __shared__ __align__(16) char smem[];
   __shared__ C<R> red[128], xs[128];
   __shared__ double sc[1];
@@ -1194,7 +1223,7 @@ static void block_bytes(const Problem& p, size_t* bS, size_t* bI) {
 // stay resident (mixed storage, one subdomain per block, and room for both).
 template <class TS, int NRT>
 static size_t gmres_plan(const Problem& p, int kmax, bool* resident, GmresArgs* a) {
-  using R = typename real_of<TS>::type;
+  using R = double;  // FP64 arithmetic for both storage precisions
   const int nb = p.gmres_blocks, chunk = (p.nmu + nb - 1) / nb;
   size_t bS, bI;
   block_bytes(p, &bS, &bI);
