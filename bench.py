@@ -26,6 +26,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_gmres_traffic_512x512.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1312_5653_amd", "csrc", "solve.hip")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter record
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the same counters on a
+    plain copy of known size), or None when the record is missing or was taken
+    on a different version of the kernel source."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != src or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel]["bytes_per_launch"]
 
 
 def gmres_operator_bytes(N, m, ncorner, elem_bytes):
@@ -61,6 +79,60 @@ def local_solve_bytes(N, m, elem_bytes):
     P = N // m
     ml = m + 1
     return P * P * ml * ml * ml * elem_bytes * 2 + 2 * (N - 1) ** 2 * 16
+
+
+def _kernel_key(name):
+    """'void sfdp::k_gmres<sfdp::C<float>, 4>(sfdp::Geo2, ...)' -> 'k_gmres<C<float>, 4>'."""
+    name = name.replace("void ", "").replace("sfdp::", "")
+    depth = 0
+    for i, ch in enumerate(name):
+        depth += ch == "<"
+        depth -= ch == ">"
+        if ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def write_traffic_record(fetch_dir, write_dir, copy_mib):
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, both with --copy-check copy_mib) into the traffic record: every
+    kernel's mean counter value per dispatch, divided by the factor the same
+    counter reads on the plain copy (copy_mib MiB read, copy_mib MiB written)."""
+    import collections
+    import csv
+    import glob
+    import hashlib
+
+    def per_kernel(d, counter):
+        vals = collections.defaultdict(list)
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(path)):
+                if r.get("Counter_Name") == counter:
+                    vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return vals
+
+    fet, wri = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    copy = [k for k in fet if "Mul" in k]
+    if len(copy) != 1:
+        raise SystemExit(f"expected one calibration copy kernel, found {copy}")
+    kib = copy_mib * 1024.0
+    f_fac = statistics.mean(fet[copy[0]]) / kib
+    w_fac = statistics.mean(wri[copy[0]]) / kib
+    kernels = {}
+    for k in fet:
+        key = _kernel_key(k)
+        if not key.startswith("k_") or k not in wri:
+            continue
+        fb = statistics.mean(fet[k]) / f_fac * 1024.0
+        wb = statistics.mean(wri[k]) / w_fac * 1024.0
+        kernels[key] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                        "bytes_per_launch": fb + wb, "dispatches": len(fet[k])}
+    rec = {"source_sha256": hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest(),
+           "copy_mib": copy_mib, "fetch_factor": f_fac, "write_factor": w_fac, "kernels": kernels}
+    with open(TRAFFIC_RECORD, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+    print(json.dumps({"fetch_factor": f_fac, "write_factor": w_fac,
+                      "k_gmres": {k: v["bytes_per_launch"] for k, v in kernels.items() if "gmres" in k}}))
 
 
 def cpu_baseline(N, m, beta, ybar, budget_s=15.0):
@@ -141,9 +213,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--batch", type=int, default=4, help="targets per step (1..4)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline configuration (for counter runs)")
+    ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-MiB device buffer once (a plain copy of known size that "
+                         "calibrates the HBM byte counters of a profiler run)")
     ap.add_argument("--max-krylov", type=int, default=0,
                     help="GMRES iteration cap per FETI-DP solve (0: library default)")
+    ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB"),
+                    help="write the traffic record from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
+    if args.traffic_record:
+        write_traffic_record(args.traffic_record[0], args.traffic_record[1], int(args.traffic_record[2]))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world > 1:
         print("bench.py runs on one GPU only: the FETI-DP subdomains of an instance are a batch "
@@ -161,16 +243,24 @@ def main():
                      for s in range(B)])
     ybar_t = torch.tensor(ybar, device="cuda:0")
     ybar1_t = ybar_t[:1].contiguous()
+    if args.copy_check > 0:
+        src_buf = torch.ones(args.copy_check << 18, dtype=torch.float32, device="cuda:0")
+        dst_buf = torch.empty_like(src_buf)
+        torch.mul(src_buf, 1.0, out=dst_buf)  # reads and writes MIB MiB once
+        torch.cuda.synchronize()
+        del src_buf, dst_buf
     ctx = sfdp.Context(0)
     tol_kkt = 1e-8
     res = {}
     precs = [("fp64", sfdp.SFDP_FP64, 1e-13)]
     if not args.fp64_only:
         precs.insert(0, ("mixed", sfdp.SFDP_MIXED, 1e-7))
+    if args.headline_only:
+        precs = precs[:1]
     for name, prec, tin in precs:
         res[name] = run_precision(sfdp, torch, ctx, prec, N, m, beta, ybar_t, args.steps, args.warmup,
                                   tol_kkt, tin, B, args.max_krylov)
-        if B > 1:
+        if B > 1 and not args.headline_only:
             res[name + "_b1"] = run_precision(sfdp, torch, ctx, prec, N, m, beta, ybar1_t, args.steps,
                                               args.warmup, tol_kkt, tin, 1, args.max_krylov)
     head = precs[0][0]
@@ -218,7 +308,8 @@ def main():
         "krylov_its_per_solve": r["krylov_per_solve"],
         "roofline": {"bound": "hbm", "kernel": "k_gmres (interface Krylov solve, persistent)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"k_gmres<{'C<float>' if head == 'mixed' else 'C<double>'}, {kt['gmres_width']}>"),
                      "bytes_per_launch": launch_bytes, "operator_bytes_per_trip": op_bytes,
                      "vector_bytes_per_rhs_iteration": vec_bytes, "trips_per_launch": trips,
                      "rhs_iterations_per_launch": rhs_its, "launch_ms": launch_ms,
