@@ -212,6 +212,35 @@ sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out,
  *                right-hand side. */
 sfdp_status sfdp_interface_apply(sfdp_problem* p, char which, const double* x, double* y);
 
+/* ---- Batches of independent instances (uneven sizes, one beta each) ----
+ *
+ * A batch holds `count` 2D instances of the problem class above, instance i
+ * with n_elem[i] cells per side, all with the same sub_elem and precision.
+ * Every step of the set-up and of the solve runs over all instances in one
+ * launch per kernel: the subdomains of all instances form one batch, and the
+ * interface GMRES of every instance runs inside a shared persistent
+ * cooperative launch, each instance with its own Krylov state, reductions and
+ * grid barrier over its share of the blocks (instances whose blocks do not all
+ * fit on the device at once are split over consecutive such launches).
+ * Results are those of solving each instance on its own with the same options. */
+typedef struct sfdp_batch sfdp_batch;
+sfdp_status sfdp_batch_create(sfdp_ctx* ctx, int count, const int* n_elem, int sub_elem,
+                              sfdp_precision prec, sfdp_batch** out);
+void sfdp_batch_destroy(sfdp_batch* b);
+/* Sizes of instance i (as sfdp_problem_sizes). */
+sfdp_status sfdp_batch_sizes(const sfdp_batch* b, int i, sfdp_sizes* out);
+/* Factor every instance for its beta[i] (host array of count values), as
+ * sfdp_set_beta does for one problem. */
+sfdp_status sfdp_batch_set_beta(sfdp_batch* b, const double* beta);
+/* Range-space solves (as sfdp_solve_range_space) of nrhs[i] targets of
+ * instance i.  ybar, yc, y, u, lam are host arrays of count device pointers
+ * (each as in sfdp_solve_range_space; yc or yc[i] may be NULL for zero
+ * Dirichlet data; pointers of instances with nrhs[i] = 0 are not read).
+ * info, if given, has sum(nrhs) entries, instance by instance. */
+sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const double* const* ybar,
+                                         const double* const* yc, double* const* y, double* const* u,
+                                         double* const* lam, const sfdp_opts* opts, sfdp_info* info);
+
 /* Kernel timing with HIP events recorded on the context's stream around the
  * launches of the two hot kernels of every FETI-DP solve: the persistent
  * interface GMRES kernel and the batched subdomain solve kernel (two launches

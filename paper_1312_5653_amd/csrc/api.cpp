@@ -31,17 +31,9 @@ static sfdp_status fail(sfdp_status s, const std::string& msg) {
       return fail(SFDP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-struct sfdp_ctx : public Ctx {};
-struct sfdp_problem : public Problem {};
-
 namespace {
 
 constexpr int KMAX_LIMIT = 400;
-// Device flag words: [1] grid-barrier error, [3] GMRES loop trips, [4] GMRES
-// iterations summed over right-hand sides, [8 + r] last counts per RHS, and
-// from ITLOG a log of 16 counts per group slot (range-space driver).
-constexpr int ITLOG = 64;
-constexpr int FLAG_WORDS = ITLOG + NRMAX * 16;
 
 sfdp_status dalloc(Problem& p, void** ptr, size_t bytes) {
   Ctx* c = p.ctx;
@@ -152,6 +144,7 @@ sfdp_status build_maps(Problem& p) {
   return SFDP_OK;
 }
 
+
 size_t g_size(const Problem& p) { return p.g32() ? sizeof(cf) : sizeof(cd); }  // line factors
 size_t elem_size(const Problem& p) { return p.s32() ? sizeof(cf) : sizeof(cd); }  // Sinv, Phi
 
@@ -168,19 +161,22 @@ void free_factors(Problem& p) {
 }
 
 sfdp_status alloc_workspace(Problem& p, int kmax) {
-  if (p.kmax_alloc >= kmax) return SFDP_OK;
+  if (p.kmax_alloc >= kmax && p.gmres_parts >= p.gmres_blocks) return SFDP_OK;
   // per right-hand side: Krylov basis, Hessenberg matrix, block partial sums
   if (p.kmax_alloc) {
     dfree(p, (void*&)p.Qk, sizeof(cd) * NRMAX * (size_t)(p.kmax_alloc + 1) * p.nmu);
     dfree(p, (void*&)p.Hk, sizeof(cd) * NRMAX * (size_t)(p.kmax_alloc + 1) * p.kmax_alloc);
-    dfree(p, (void*&)p.part, sizeof(cd) * 3 * NRMAX * (size_t)(p.kmax_alloc + 2) * p.gmres_blocks);
+    dfree(p, (void*&)p.part, sizeof(cd) * 3 * NRMAX * (size_t)(p.kmax_alloc + 2) * p.gmres_parts);
+    p.kmax_alloc = 0;
   }
+  kmax = std::max(kmax, p.kmax_alloc);
   sfdp_status s;
   if ((s = dalloc(p, (void**)&p.Qk, sizeof(cd) * NRMAX * (size_t)(kmax + 1) * p.nmu)) ||
       (s = dalloc(p, (void**)&p.Hk, sizeof(cd) * NRMAX * (size_t)(kmax + 1) * kmax)) ||
       (s = dalloc(p, (void**)&p.part, sizeof(cd) * 3 * NRMAX * (size_t)(kmax + 2) * p.gmres_blocks)))
     return s;
   p.kmax_alloc = kmax;
+  p.gmres_parts = p.gmres_blocks;
   return SFDP_OK;
 }
 
@@ -194,25 +190,25 @@ sfdp_status check_launch(Problem& p, int kmax) {
 }
 
 // Event pairs around hot launches (kind 0: GMRES, 1: subdomain solve).
-hipError_t ev_begin(Problem& p, int kind, int* slot) {
+hipError_t ev_begin(Problem* p, int kind, int* slot) {
   *slot = -1;
-  if (!p.timing) return hipSuccess;
-  if (p.ev_used + 2 > (int)p.ev_pool.size()) {
+  if (!p || !p->timing) return hipSuccess;
+  if (p->ev_used + 2 > (int)p->ev_pool.size()) {
     for (int i = 0; i < 64; ++i) {
       hipEvent_t e;
       hipError_t r = hipEventCreate(&e);
       if (r != hipSuccess) return r;
-      p.ev_pool.push_back(e);
+      p->ev_pool.push_back(e);
     }
   }
-  *slot = p.ev_used;
-  p.ev_used += 2;
-  p.ev_pending.push_back({*slot, kind});
-  return hipEventRecord(p.ev_pool[*slot], p.ctx->stream);
+  *slot = p->ev_used;
+  p->ev_used += 2;
+  p->ev_pending.push_back({*slot, kind});
+  return hipEventRecord(p->ev_pool[*slot], p->ctx->stream);
 }
-hipError_t ev_end(Problem& p, int slot) {
+hipError_t ev_end(Problem* p, int slot) {
   if (slot < 0) return hipSuccess;
-  return hipEventRecord(p.ev_pool[slot + 1], p.ctx->stream);
+  return hipEventRecord(p->ev_pool[slot + 1], p->ctx->stream);
 }
 // After a stream synchronisation: fold the recorded pairs into the totals.
 hipError_t ev_harvest(Problem& p) {
@@ -228,35 +224,9 @@ hipError_t ev_harvest(Problem& p) {
   return hipSuccess;
 }
 
-// One FETI-DP solve of Z x_r = f_r (conj_in: conj(Z) x_r = f_r) for nr <= NRMAX
-// right-hand sides together; f and x are r-major with stride n_free.  The
-// iteration count of RHS r also goes to the device int its_dst[r] (if given).
-sfdp_status feti_one(Problem& p, const cd* f, int conj_in, cd* x, double tol, int kmax, int nr,
-                     int* const* its_dst) {
-  hipStream_t st = p.ctx->stream;
-  for (int r = 0; r < NRMAX; ++r) p.its_dst[r] = (its_dst && r < nr) ? its_dst[r] : nullptr;
-  int ev;
-  HIPCHK(ev_begin(p, 1, &ev));
-  HIPCHK(launch_local_solve(p, 0, f, conj_in, nullptr, nr, st));
-  HIPCHK(ev_end(p, ev));
-  HIPCHK(launch_coarse_rhs(p, f, conj_in, nr, st));
-  HIPCHK(launch_fetidp_rhs(p, nr, st));
-  sfdp_status s = check_launch(p, kmax);
-  if (s != SFDP_OK) return s;
-  HIPCHK(ev_begin(p, 0, &ev));
-  HIPCHK(launch_gmres(p, tol, kmax, nr, st));
-  HIPCHK(ev_end(p, ev));
-  HIPCHK(launch_recover_coarse(p, nr, st));
-  HIPCHK(ev_begin(p, 1, &ev));
-  HIPCHK(launch_local_solve(p, 1, f, conj_in, x, nr, st));
-  HIPCHK(ev_end(p, ev));
-  HIPCHK(launch_assemble_solution(p, x, conj_in, nr, st));
-  return SFDP_OK;
-}
-
-void defaults(const Problem& p, const sfdp_opts* o, double& tol_kkt, double& tol_inner, int& max_outer,
+void defaults(sfdp_precision prec, const sfdp_opts* o, double& tol_kkt, double& tol_inner, int& max_outer,
               int& kmax) {
-  bool mixed = p.prec != SFDP_FP64;
+  bool mixed = prec != SFDP_FP64;
   tol_kkt = (o && o->tol_kkt > 0) ? o->tol_kkt : (mixed ? 1e-8 : 1e-10);
   tol_inner = (o && o->tol_inner > 0) ? o->tol_inner : (mixed ? 1e-7 : 1e-8);
   max_outer = (o && o->max_outer > 0) ? o->max_outer : 8;
@@ -283,7 +253,432 @@ sfdp_status alloc_rs(Problem& p) {
   return SFDP_OK;
 }
 
+// A problem of the 2D class (maps, solve workspaces), not yet factored.
+sfdp_status create_problem(Ctx* ctx, int dim, int n_elem, int sub_elem, sfdp_precision prec, Problem** out);
+void destroy_problem(Problem* p);
+
+// Set-up scratch of one problem (FP64), allocated for sfdp_set_beta only.
+sfdp_status alloc_setup(Problem& p) {
+  const int ml = p.ml, ND = p.ND, nsub = p.nsub;
+  size_t es = elem_size(p);
+  size_t nG = (size_t)nsub * ml * ml * ml, nS = (size_t)nsub * ND * ND, nP = (size_t)nsub * ND * 4;
+  const size_t nPK = (size_t)nsub * ND * (ND + 1) / 2;
+  sfdp_status s;
+  if ((s = dalloc(p, &p.G, g_size(p) * nG)) || (s = dalloc(p, &p.Sinv, es * nPK)) ||
+      (s = dalloc(p, &p.Sbb, sizeof(cf) * nPK)) || (s = dalloc(p, &p.Phi, es * nP)) ||
+      (s = dalloc(p, (void**)&p.Kinv, sizeof(cd) * std::max(p.nC * p.nC, 1))) ||
+      (s = dalloc(p, (void**)&p.Kcc, sizeof(cd) * std::max(p.nC * p.nC, 1))))
+    return s;
+  size_t nF = (size_t)nsub * ml * ml * 4, nScr = (size_t)nsub * ml * ml * 32;
+  size_t nK = (size_t)std::max(p.nC * p.nC, 1);
+  if (hipMalloc(&p.G64, sizeof(cd) * nG) || hipMalloc(&p.Sinv64, sizeof(cd) * nS) ||
+      hipMalloc(&p.S64, sizeof(cd) * nS) || hipMalloc(&p.Phi64, sizeof(cd) * nP) ||
+      hipMalloc(&p.PhiFull, sizeof(cd) * nF) || hipMalloc(&p.scr, sizeof(cd) * nScr) ||
+      hipMalloc(&p.Zs, sizeof(cd) * nsub * 16) || hipMalloc(&p.Kwork, sizeof(cd) * nK))
+    return fail(SFDP_E_NOMEM, "setup scratch allocation failed");
+  return SFDP_OK;
+}
+void free_setup(Problem& p) {
+  cd** arr[] = {&p.G64, &p.Sinv64, &p.S64, &p.Phi64, &p.PhiFull, &p.scr, &p.Zs, &p.Kwork};
+  for (cd** a : arr) {
+    if (*a) hipFree(*a);
+    *a = nullptr;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Several problems as one launch target: block maps per launch kind, GMRES launch
+// groups, and the device array of instance views.
+struct Multi {
+  Ctx* ctx = nullptr;
+  std::vector<Problem*> probs;
+  Target t;
+  Dev* ddev = nullptr;
+  Dev* hdev = nullptr;  // pinned mirror
+  size_t dev_cap = 0;
+  int* dmap = nullptr;
+  size_t map_cap = 0;
+  int g_kmax = -1, g_width = -1;
+  Gathered* dgather = nullptr;  // per-instance residual heads and flag words
+  Gathered* hgather = nullptr;
+  ~Multi() {
+    if (ddev) hipFree(ddev);
+    if (hdev) hipHostFree(hdev);
+    if (dmap) hipFree(dmap);
+    if (dgather) hipFree(dgather);
+    if (hgather) hipHostFree(hgather);
+  }
+};
+
+sfdp_status multi_grow(Multi& M, size_t n_inst, size_t n_map) {
+  if (n_inst > M.dev_cap) {
+    if (M.ddev) hipFree(M.ddev);
+    if (M.hdev) hipHostFree(M.hdev);
+    if (M.dgather) hipFree(M.dgather);
+    if (M.hgather) hipHostFree(M.hgather);
+    M.ddev = nullptr;
+    M.hdev = nullptr;
+    M.dgather = nullptr;
+    M.hgather = nullptr;
+    size_t cap = std::max<size_t>(n_inst, 2 * M.dev_cap);
+    if (hipMalloc(&M.ddev, sizeof(Dev) * cap) || hipHostMalloc(&M.hdev, sizeof(Dev) * cap) ||
+        hipMalloc(&M.dgather, sizeof(Gathered) * cap) || hipHostMalloc(&M.hgather, sizeof(Gathered) * cap))
+      return fail(SFDP_E_NOMEM, "batch descriptor allocation failed");
+    M.dev_cap = cap;
+  }
+  if (n_map > M.map_cap) {
+    if (M.dmap) hipFree(M.dmap);
+    M.dmap = nullptr;
+    size_t cap = std::max<size_t>(n_map, 2 * M.map_cap);
+    if (hipMalloc(&M.dmap, sizeof(int) * cap)) return fail(SFDP_E_NOMEM, "batch map allocation failed");
+    M.map_cap = cap;
+  }
+  return SFDP_OK;
+}
+
+// Block maps of every launch kind for the batch's problems (the stream must be
+// idle: the maps are uploaded synchronously).
+sfdp_status multi_maps(Multi& M) {
+  const int n = (int)M.probs.size();
+  Target& t = M.t;
+  t.st = M.ctx->stream;
+  t.one = nullptr;
+  t.probs = M.probs;
+  t.prec = M.probs[0]->prec;
+  std::vector<int> host;
+  size_t off_inst[K_NKIND], off_first[K_NKIND];
+  for (int k = 0; k < K_NKIND; ++k) {
+    off_first[k] = host.size();
+    int tot = 0;
+    for (int i = 0; i < n; ++i) {
+      host.push_back(tot);
+      tot += k == K_GMRES ? 0 : M.probs[i]->blocks(k);
+    }
+    off_inst[k] = host.size();
+    if (k != K_GMRES)
+      for (int i = 0; i < n; ++i)
+        for (int b = 0; b < M.probs[i]->blocks(k); ++b) host.push_back(i);
+    t.total[k] = tot;
+  }
+  sfdp_status s = multi_grow(M, n, host.size());
+  if (s) return s;
+  HIPCHK(hipMemcpy(M.dmap, host.data(), sizeof(int) * host.size(), hipMemcpyHostToDevice));
+  for (int k = 0; k < K_NKIND; ++k) {
+    t.inst[k] = M.dmap + off_inst[k];
+    t.first[k] = M.dmap + off_first[k];
+  }
+  t.devs = M.ddev;
+  t.ggroups.clear();
+  M.g_kmax = M.g_width = -1;
+  return SFDP_OK;
+}
+
+// GMRES launch groups for (kmax, width): instances in order, each group's
+// blocks co-resident.  Written after the kind maps (own device area).
+sfdp_status multi_groups(Multi& M, int kmax, int width, int*& gmap, size_t& gcap) {
+  if (M.g_kmax == kmax && M.g_width == width) return SFDP_OK;
+  Target& t = M.t;
+  const int n = (int)M.probs.size();
+  int cmax = 1;
+  for (Problem* p : M.probs) cmax = std::max(cmax, (p->nmu + p->gmres_blocks - 1) / p->gmres_blocks);
+  const int cap = gmres_capacity(*M.probs[0], kmax, cmax, width);
+  if (cap < 1) return fail(SFDP_E_DEVICE, "GMRES kernel does not fit in LDS (lower max_krylov)");
+  std::vector<int> host(n, 0);  // first block of each instance within its group
+  t.ggroups.clear();
+  std::vector<size_t> g_off;
+  for (int i = 0; i < n;) {
+    Target::GGroup g;
+    g.total = 0;
+    while (i < n && (g.members.empty() || g.total + M.probs[i]->gmres_blocks <= cap)) {
+      if (M.probs[i]->gmres_blocks > cap) return fail(SFDP_E_DEVICE, "instance exceeds the co-resident GMRES grid");
+      host[i] = g.total;
+      g.total += M.probs[i]->gmres_blocks;
+      g.members.push_back(i);
+      ++i;
+    }
+    g_off.push_back(host.size());
+    for (int m : g.members)
+      for (int b = 0; b < M.probs[m]->gmres_blocks; ++b) host.push_back(m);
+    t.ggroups.push_back(g);
+  }
+  if (host.size() > gcap) {
+    if (gmap) hipFree(gmap);
+    gmap = nullptr;
+    gcap = std::max(host.size(), 2 * gcap);
+    if (hipMalloc(&gmap, sizeof(int) * gcap)) return fail(SFDP_E_NOMEM, "batch map allocation failed");
+  }
+  HIPCHK(hipMemcpy(gmap, host.data(), sizeof(int) * host.size(), hipMemcpyHostToDevice));
+  t.first[K_GMRES] = gmap;
+  for (size_t g = 0; g < t.ggroups.size(); ++g) t.ggroups[g].inst = gmap + g_off[g];
+  M.g_kmax = kmax;
+  M.g_width = width;
+  return SFDP_OK;
+}
+
+// Upload the instance views (the stream must be idle).
+sfdp_status multi_upload(Multi& M) {
+  const size_t n = M.probs.size();
+  for (size_t i = 0; i < n; ++i) M.hdev[i] = M.probs[i]->dev();
+  HIPCHK(hipMemcpy(M.ddev, M.hdev, sizeof(Dev) * n, hipMemcpyHostToDevice));
+  return SFDP_OK;
+}
+
+sfdp_status gmres_error(hipError_t e) {
+  if (e == hipErrorOutOfMemory) return fail(SFDP_E_DEVICE, "GMRES kernel does not fit in LDS (lower max_krylov)");
+  if (e == hipErrorCooperativeLaunchTooLarge)
+    return fail(SFDP_E_DEVICE, "cooperative GMRES grid exceeds co-resident blocks");
+  return fail(SFDP_E_DEVICE, std::string("GMRES launch: ") + hipGetErrorString(e));
+}
+
+// One FETI-DP solve of Z x_r = f_r (conj: conj(Z) x_r = f_r) for every
+// instance's group (its view's nr right-hand sides); f and x name instance
+// vectors.  `timed` receives event pairs (single problems only).
+sfdp_status feti_run(const Target& t, Problem* timed, int fsel, int conj, int xsel, double tol, int kmax) {
+  if (t.single()) {
+    sfdp_status s = check_launch(*t.one, kmax);
+    if (s) return s;
+  }
+  int ev;
+  HIPCHK(ev_begin(timed, 1, &ev));
+  HIPCHK(launch_local_solve(t, 0, fsel, conj, xsel));
+  HIPCHK(ev_end(timed, ev));
+  HIPCHK(launch_coarse_rhs(t, fsel, conj));
+  HIPCHK(launch_fetidp_rhs(t));
+  HIPCHK(ev_begin(timed, 0, &ev));
+  hipError_t e = launch_gmres(t, tol, kmax);
+  if (e != hipSuccess) return gmres_error(e);
+  HIPCHK(ev_end(timed, ev));
+  HIPCHK(launch_recover_coarse(t));
+  HIPCHK(ev_begin(timed, 1, &ev));
+  HIPCHK(launch_local_solve(t, 1, fsel, conj, xsel));
+  HIPCHK(ev_end(timed, ev));
+  HIPCHK(launch_assemble_solution(t, xsel, conj));
+  return SFDP_OK;
+}
+
+constexpr unsigned IDENTITY_MAP = 0x03020100u;
+
+// Range-space solves of every problem's group: nr targets in slots 0..nr-1,
+// caller arrays in the problem's ybar, yc, y, u, lam (stride n_free / n_bdry).
+// All unfinished targets take each two-factor step together; each stops on
+// its own test.  info[i] has ps[i]->nr entries.  M is the batch (null for a
+// single problem); dg / hg hold one Gathered record per problem.
+sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Multi* M, Gathered* dg,
+                            Gathered* hg, double tol_kkt, double tol_inner, int max_outer, int kmax,
+                            const std::vector<sfdp_info*>& info) {
+  const size_t n = ps.size();
+  hipStream_t st = t.st;
+  std::vector<int> ng(n);
+  std::vector<std::vector<sfdp_info>> loc(n);
+  std::vector<std::vector<int>> bad(n);  // 0 ok, 1 non-finite, 2 outer limit
+  for (size_t i = 0; i < n; ++i) {
+    ng[i] = ps[i]->nr;
+    ps[i]->map = IDENTITY_MAP;
+    loc[i].assign(ng[i], sfdp_info{});
+    bad[i].assign(ng[i], 0);
+  }
+  Problem* timed = t.single() ? t.one : nullptr;
+  if (M) {
+    sfdp_status s = multi_upload(*M);
+    if (s) return s;
+  }
+  HIPCHK(launch_group_init(t));
+  HIPCHK(launch_fill_flags(t, 0, FLAG_WORDS));
+  for (int step = 0;; ++step) {
+    HIPCHK(launch_kkt_residual(t));
+    HIPCHK(launch_gather(t, dg));
+    HIPCHK(hipMemcpyAsync(hg, dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (timed) HIPCHK(ev_harvest(*timed));
+    bool any = false;
+    for (size_t i = 0; i < n; ++i) {
+      Problem* p = ps[i];
+      unsigned map2 = 0;
+      int nb2 = 0;
+      for (int c = 0; c < p->nr; ++c) {
+        const int q = (p->map >> (8 * c)) & 255;
+        const double rho = hg[i].red[2 * q];
+        sfdp_info& o = loc[i][q];
+        o.rel_kkt = rho;
+        if (step == 1) o.rel_kkt_first = rho;
+        if (step > 0) o.imag_ratio = hg[i].red[2 * q + 1];
+        if (!std::isfinite(rho)) { bad[i][q] = 1; continue; }
+        if (rho <= tol_kkt) continue;
+        if (step >= max_outer) { bad[i][q] = 2; continue; }
+        map2 |= (unsigned)q << (8 * nb2++);
+      }
+      p->nr = nb2;
+      p->map = map2;
+      any = any || nb2 > 0;
+    }
+    if (!any) break;
+    if (M) {
+      sfdp_status s = multi_upload(*M);
+      if (s) return s;
+    }
+    HIPCHK(launch_make_rhs1(t));
+    sfdp_status s = feti_run(t, timed, V_CVEC, 0, V_CVEC2, tol_inner, kmax);
+    if (s) return s;
+    HIPCHK(launch_make_rhs2(t));
+    s = feti_run(t, timed, V_CVEC3, 0, V_CVEC, tol_inner, kmax);
+    if (s) return s;
+    HIPCHK(launch_update(t));
+    for (size_t i = 0; i < n; ++i)
+      for (int c = 0; c < ps[i]->nr; ++c) loc[i][(ps[i]->map >> (8 * c)) & 255].outer_steps = step + 1;
+  }
+  HIPCHK(launch_gather(t, dg));
+  HIPCHK(hipMemcpyAsync(hg, dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  sfdp_status status = SFDP_OK;
+  for (size_t i = 0; i < n; ++i) {
+    const int* fl = hg[i].flags;
+    if (fl[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
+    if (timed && timed->timing) { timed->it_gmres += fl[3]; timed->it_rhs += fl[4]; }
+    for (int q = 0; q < ng[i]; ++q) {
+      sfdp_info& o = loc[i][q];
+      o.n_feti = fl[FLAG_CNT + q];
+      for (int k = 0; k < o.n_feti && k < 16; ++k) {
+        o.krylov_its[k] = fl[FLAG_LOG + 16 * q + k];
+        o.krylov_total += o.krylov_its[k];
+      }
+      if (bad[i][q] == 1) status = fail(SFDP_E_NOCONV, "non-finite residual");
+      if (bad[i][q] == 2) status = fail(SFDP_E_NOCONV, "outer refinement limit reached");
+      if (info[i]) info[i][q] = o;
+    }
+    ps[i]->nr = 0;
+  }
+  return status;
+}
+
+sfdp_status create_problem(Ctx* ctx, int dim, int n_elem, int sub_elem, sfdp_precision prec, Problem** out) {
+  *out = nullptr;
+  if (dim != 2) return fail(SFDP_E_INVALID, "only dim = 2 is implemented");
+  if (sub_elem < 2 || sub_elem > 32) return fail(SFDP_E_INVALID, "sub_elem must be in [2, 32] for dim 2");
+  if (n_elem % sub_elem != 0 || n_elem / sub_elem < 2)
+    return fail(SFDP_E_INVALID, "n_elem must be a multiple of sub_elem with at least 2 subdomains per side");
+  if (prec != SFDP_FP64 && prec != SFDP_MIXED && prec != SFDP_MIXED_IFACE)
+    return fail(SFDP_E_INVALID, "bad precision");
+  HIPCHK(hipSetDevice(ctx->device));
+  Problem* p = new (std::nothrow) Problem();
+  if (!p) return fail(SFDP_E_NOMEM, "host allocation");
+  p->ctx = ctx;
+  p->dim = dim;
+  p->N = n_elem;
+  p->m = sub_elem;
+  p->P = n_elem / sub_elem;
+  p->nsub = p->P * p->P;
+  p->ml = sub_elem + 1;
+  p->L = p->ml * p->ml;
+  p->ND = ((4 * (sub_elem - 1) + 31) / 32) * 32;
+  p->n_free = (int64_t)(n_elem - 1) * (n_elem - 1);
+  p->prec = prec;
+  sfdp_status s = build_maps(*p);
+  if (s != SFDP_OK) { destroy_problem(p); return s; }
+  // solve workspaces, per right-hand side (NRMAX r-major copies, strides of Problem::rs())
+  size_t nsd = (size_t)NRMAX * p->nsub * p->ND;
+  size_t n4 = (size_t)NRMAX * p->nsub * 4;
+  size_t nC = (size_t)NRMAX * std::max(p->nC, 1);
+  size_t nm = (size_t)NRMAX * p->nmu;
+  if ((s = dalloc(*p, (void**)&p->Xd, sizeof(cd) * nsd)) || (s = dalloc(*p, (void**)&p->Ubuf, sizeof(cd) * nsd)) ||
+      (s = dalloc(*p, (void**)&p->Abuf, sizeof(cd) * nsd)) || (s = dalloc(*p, (void**)&p->Ybuf, sizeof(cd) * nsd)) ||
+      (s = dalloc(*p, (void**)&p->Cbuf, sizeof(cd) * n4)) || (s = dalloc(*p, (void**)&p->Qc, sizeof(cd) * n4)) ||
+      (s = dalloc(*p, (void**)&p->fcs, sizeof(cd) * nC)) || (s = dalloc(*p, (void**)&p->u0, sizeof(cd) * nC)) ||
+      (s = dalloc(*p, (void**)&p->ymin, sizeof(cd) * nC)) || (s = dalloc(*p, (void**)&p->dvec, sizeof(cd) * nm)) ||
+      (s = dalloc(*p, (void**)&p->mu, sizeof(cd) * nm)) || (s = dalloc(*p, (void**)&p->wv, sizeof(cd) * nm)) ||
+      (s = dalloc(*p, (void**)&p->dscal, sizeof(double) * 8)) || (s = dalloc(*p, (void**)&p->bar, 4096)) ||
+      (s = dalloc(*p, (void**)&p->flags, sizeof(int) * FLAG_WORDS))) {
+    destroy_problem(p);
+    return s;
+  }
+  p->gmres_blocks = std::min(p->nsub, ctx->num_cu);
+  hipError_t ez = launch_fill(p->flags, sizeof(int) * FLAG_WORDS, ctx->stream);
+  if (ez == hipSuccess) ez = launch_fill(p->bar, 4096, ctx->stream);
+  if (ez == hipSuccess) ez = launch_fill(p->dscal, sizeof(double) * 8, ctx->stream);
+  if (ez == hipSuccess) ez = hipStreamSynchronize(ctx->stream);
+  if (ez != hipSuccess) {
+    destroy_problem(p);
+    return fail(SFDP_E_DEVICE, std::string("init: ") + hipGetErrorString(ez));
+  }
+  *out = p;
+  return SFDP_OK;
+}
+
+void destroy_problem(Problem* p) {
+  if (!p) return;
+  hipSetDevice(p->ctx->device);
+  hipStreamSynchronize(p->ctx->stream);
+  free_factors(*p);
+  free_setup(*p);
+  void* arr[] = {p->dloc, p->dmid, p->dpart, p->nd, p->dsgn, p->cloc, p->cgid, p->muown, p->mufree,
+                 p->cown, p->cfree, p->full2bdry, p->Xd, p->Ubuf, p->Abuf, p->Ybuf, p->Cbuf, p->Qc,
+                 p->fcs, p->u0, p->ymin, p->dvec, p->mu, p->wv, p->Qk, p->Hk, p->part, p->dscal,
+                 p->bar, p->flags, p->r1, p->r2, p->r3, p->red, p->cvec, p->cvec2, p->cvec3};
+  for (void* a : arr)
+    if (a) hipFree(a);
+  for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
+  p->ctx->used -= std::min(p->ctx->used, p->bytes);
+  delete p;
+}
+
+// Factor one or several problems for their betas (one set-up sequence).
+sfdp_status setup_run(const Target& t, const std::vector<Problem*>& ps, Multi* M) {
+  for (Problem* p : ps) {
+    sfdp_status s = alloc_setup(*p);
+    if (s) {
+      for (Problem* q : ps) free_setup(*q);
+      return s;
+    }
+  }
+  if (M) {
+    sfdp_status s = multi_upload(*M);
+    if (s) return s;
+  }
+  hipError_t e = launch_setup(t);
+  if (e == hipSuccess) e = hipStreamSynchronize(t.st);
+  for (Problem* p : ps) free_setup(*p);
+  if (e != hipSuccess) return fail(SFDP_E_DEVICE, std::string("setup: ") + hipGetErrorString(e));
+  for (Problem* p : ps) p->factored = true;
+  return SFDP_OK;
+}
+
+Target single_target(Problem* p) {
+  Target t;
+  t.st = p->ctx->stream;
+  t.one = p;
+  t.prec = p->prec;
+  return t;
+}
+
+// One Gathered record of a single problem (device buffer reused per call).
+struct OneGather {
+  Gathered* d = nullptr;
+  Gathered h;
+  ~OneGather() { if (d) hipFree(d); }
+};
+sfdp_status gather_one(Problem* p, OneGather& g) {
+  if (!g.d && hipMalloc(&g.d, sizeof(Gathered))) return fail(SFDP_E_NOMEM, "gather buffer");
+  Target t = single_target(p);
+  HIPCHK(launch_gather(t, g.d));
+  HIPCHK(hipMemcpyAsync(&g.h, g.d, sizeof(Gathered), hipMemcpyDeviceToHost, t.st));
+  HIPCHK(hipStreamSynchronize(t.st));
+  return SFDP_OK;
+}
+
 }  // namespace
+
+struct sfdp_ctx : public Ctx {};
+struct sfdp_problem : public Problem {};
+struct sfdp_batch {
+  Ctx* ctx = nullptr;
+  std::vector<Problem*> probs;
+  Multi M;
+  int* gmap = nullptr;
+  size_t gcap = 0;
+  ~sfdp_batch() {
+    if (gmap) hipFree(gmap);
+    for (Problem* p : probs) destroy_problem(p);
+  }
+};
 
 extern "C" {
 
@@ -317,61 +712,13 @@ void sfdp_ctx_destroy(sfdp_ctx* c) { delete c; }
 sfdp_status sfdp_problem_create(sfdp_ctx* ctx, int dim, int n_elem, int sub_elem, sfdp_precision prec,
                                 sfdp_problem** out) {
   if (!ctx || !out) return fail(SFDP_E_INVALID, "NULL argument");
-  *out = nullptr;
-  if (dim != 2) return fail(SFDP_E_INVALID, "only dim = 2 is implemented");
-  if (sub_elem < 2 || sub_elem > 32) return fail(SFDP_E_INVALID, "sub_elem must be in [2, 32] for dim 2");
-  if (n_elem % sub_elem != 0 || n_elem / sub_elem < 2)
-    return fail(SFDP_E_INVALID, "n_elem must be a multiple of sub_elem with at least 2 subdomains per side");
-  if (prec != SFDP_FP64 && prec != SFDP_MIXED && prec != SFDP_MIXED_IFACE)
-    return fail(SFDP_E_INVALID, "bad precision");
-  HIPCHK(hipSetDevice(ctx->device));
-  sfdp_problem* p = new (std::nothrow) sfdp_problem();
-  if (!p) return fail(SFDP_E_NOMEM, "host allocation");
-  p->ctx = ctx;
-  p->dim = dim;
-  p->N = n_elem;
-  p->m = sub_elem;
-  p->P = n_elem / sub_elem;
-  p->nsub = p->P * p->P;
-  p->ml = sub_elem + 1;
-  p->L = p->ml * p->ml;
-  p->ND = ((4 * (sub_elem - 1) + 31) / 32) * 32;
-  p->n_free = (int64_t)(n_elem - 1) * (n_elem - 1);
-  p->prec = prec;
-  sfdp_status s = build_maps(*p);
-  if (s != SFDP_OK) { sfdp_problem_destroy(p); return s; }
-  // solve workspaces
-  // per right-hand side (NRMAX r-major copies, strides of Problem::rs())
-  size_t nsd = (size_t)NRMAX * p->nsub * p->ND;
-  size_t n4 = (size_t)NRMAX * p->nsub * 4;
-  size_t nC = (size_t)NRMAX * std::max(p->nC, 1);
-  size_t nm = (size_t)NRMAX * p->nmu;
-  if ((s = dalloc(*p, (void**)&p->Xd, sizeof(cd) * nsd)) || (s = dalloc(*p, (void**)&p->Ubuf, sizeof(cd) * nsd)) ||
-      (s = dalloc(*p, (void**)&p->Abuf, sizeof(cd) * nsd)) || (s = dalloc(*p, (void**)&p->Ybuf, sizeof(cd) * nsd)) ||
-      (s = dalloc(*p, (void**)&p->Cbuf, sizeof(cd) * n4)) || (s = dalloc(*p, (void**)&p->Qc, sizeof(cd) * n4)) ||
-      (s = dalloc(*p, (void**)&p->fcs, sizeof(cd) * nC)) || (s = dalloc(*p, (void**)&p->u0, sizeof(cd) * nC)) ||
-      (s = dalloc(*p, (void**)&p->ymin, sizeof(cd) * nC)) || (s = dalloc(*p, (void**)&p->dvec, sizeof(cd) * nm)) ||
-      (s = dalloc(*p, (void**)&p->mu, sizeof(cd) * nm)) || (s = dalloc(*p, (void**)&p->wv, sizeof(cd) * nm)) ||
-      (s = dalloc(*p, (void**)&p->dscal, sizeof(double) * 8)) || (s = dalloc(*p, (void**)&p->bar, 4096)) ||
-      (s = dalloc(*p, (void**)&p->flags, sizeof(int) * FLAG_WORDS))) {
-    sfdp_problem_destroy(p);
-    return s;
-  }
-  p->gmres_blocks = std::min(p->nsub, ctx->num_cu);
-  hipError_t ez = launch_fill(p->flags, sizeof(int) * FLAG_WORDS, ctx->stream);
-  if (ez == hipSuccess) ez = launch_fill(p->bar, 4096, ctx->stream);
-  if (ez == hipSuccess) ez = launch_fill(p->dscal, sizeof(double) * 8, ctx->stream);
-  if (ez == hipSuccess) ez = hipStreamSynchronize(ctx->stream);
-  if (ez != hipSuccess) {
-    sfdp_problem_destroy(p);
-    return fail(SFDP_E_DEVICE, std::string("init: ") + hipGetErrorString(ez));
-  }
-  *out = p;
-  return SFDP_OK;
+  Problem* p = nullptr;
+  sfdp_status s = create_problem(ctx, dim, n_elem, sub_elem, prec, &p);
+  *out = (sfdp_problem*)p;
+  return s;
 }
 
-sfdp_status sfdp_problem_sizes(const sfdp_problem* p, sfdp_sizes* out) {
-  if (!p || !out) return fail(SFDP_E_INVALID, "NULL argument");
+static void sizes_of(const Problem* p, sfdp_sizes* out) {
   out->n_free = p->n_free;
   out->n_bdry = p->n_bdry;
   out->n_sub = p->nsub;
@@ -379,76 +726,25 @@ sfdp_status sfdp_problem_sizes(const sfdp_problem* p, sfdp_sizes* out) {
   out->n_corner = p->nC;
   out->max_delta = 4 * (p->m - 1);
   out->resident_bytes = (int64_t)p->bytes;
+}
+
+sfdp_status sfdp_problem_sizes(const sfdp_problem* p, sfdp_sizes* out) {
+  if (!p || !out) return fail(SFDP_E_INVALID, "NULL argument");
+  sizes_of(p, out);
   return SFDP_OK;
 }
 
-void sfdp_problem_destroy(sfdp_problem* p) {
-  if (!p) return;
-  hipSetDevice(p->ctx->device);
-  hipStreamSynchronize(p->ctx->stream);
-  free_factors(*p);
-  void* arr[] = {p->dloc, p->dmid, p->dpart, p->nd, p->dsgn, p->cloc, p->cgid, p->muown, p->mufree,
-                 p->cown, p->cfree, p->full2bdry, p->Xd, p->Ubuf, p->Abuf, p->Ybuf, p->Cbuf, p->Qc,
-                 p->fcs, p->u0, p->ymin, p->dvec, p->mu, p->wv, p->Qk, p->Hk, p->part, p->dscal,
-                 p->bar, p->flags, p->r1, p->r2, p->r3, p->red, p->cvec, p->cvec2, p->cvec3, p->Kwork};
-  for (void* a : arr)
-    if (a) hipFree(a);
-  for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
-  p->ctx->used -= std::min(p->ctx->used, p->bytes);
-  delete p;
-}
+void sfdp_problem_destroy(sfdp_problem* p) { destroy_problem(p); }
 
 sfdp_status sfdp_set_beta(sfdp_problem* p, double beta) {
   if (!p) return fail(SFDP_E_INVALID, "null problem");
   if (!(beta > 0) || !std::isfinite(beta)) return fail(SFDP_E_INVALID, "beta must be positive and finite");
   HIPCHK(hipSetDevice(p->ctx->device));
-  hipStream_t st = p->ctx->stream;
   free_factors(*p);
   p->beta = beta;
   p->alpha = 1.0 / std::sqrt(beta);
-  const int ml = p->ml, ND = p->ND, nsub = p->nsub;
-  size_t es = elem_size(*p);
-  size_t nG = (size_t)nsub * ml * ml * ml, nS = (size_t)nsub * ND * ND, nP = (size_t)nsub * ND * 4;
-  const size_t nPK = (size_t)nsub * ND * (ND + 1) / 2;
-  sfdp_status s;
-  if ((s = dalloc(*p, &p->G, g_size(*p) * nG)) || (s = dalloc(*p, &p->Sinv, es * nPK)) ||
-      (s = dalloc(*p, &p->Sbb, sizeof(cf) * nPK)) || (s = dalloc(*p, &p->Phi, es * nP)) ||
-      (s = dalloc(*p, (void**)&p->Kinv, sizeof(cd) * std::max(p->nC * p->nC, 1))) ||
-      (s = dalloc(*p, (void**)&p->Kcc, sizeof(cd) * std::max(p->nC * p->nC, 1))))
-    return s;
-  // FP64 scratch
-  cd *G64 = nullptr, *Sinv64 = nullptr, *S64 = nullptr, *Phi64 = nullptr, *PhiFull = nullptr,
-     *scr = nullptr, *Kw = nullptr;
-  size_t nF = (size_t)nsub * ml * ml * 4, nScr = (size_t)nsub * ml * ml * 32;
-  size_t nK = (size_t)std::max(p->nC * p->nC, 1);
-  auto cleanup = [&]() {
-    hipStreamSynchronize(st);
-    hipFree(G64); hipFree(Sinv64); hipFree(S64); hipFree(Phi64); hipFree(PhiFull); hipFree(scr); hipFree(Kw);
-  };
-  if (hipMalloc(&G64, sizeof(cd) * nG) || hipMalloc(&Sinv64, sizeof(cd) * nS) ||
-      hipMalloc(&S64, sizeof(cd) * nS) || hipMalloc(&Phi64, sizeof(cd) * nP) ||
-      hipMalloc(&PhiFull, sizeof(cd) * nF) || hipMalloc(&scr, sizeof(cd) * nScr) ||
-      hipMalloc(&Kw, sizeof(cd) * nK)) {
-    cleanup();
-    return fail(SFDP_E_NOMEM, "setup scratch allocation failed");
-  }
-  hipError_t e = hipSuccess;
-  if (!e) e = launch_fill(Sinv64, sizeof(cd) * nS, st);
-  if (!e) e = launch_fill(Phi64, sizeof(cd) * nP, st);
-  if (!e) e = launch_factor_lines(*p, G64, st);
-  if (!e) e = launch_multi_solve(*p, G64, Sinv64, Phi64, PhiFull, scr, st);
-  if (!e) e = hipMemcpyAsync(S64, Sinv64, sizeof(cd) * nS, hipMemcpyDeviceToDevice, st);
-  if (!e) e = launch_invert_batched(*p, S64, st);
-  if (!e && p->nC > 0) e = launch_zcc_and_coarse(*p, PhiFull, p->Kcc, st);
-  if (!e && p->nC > 0)
-    e = hipMemcpyAsync(p->Kinv, p->Kcc, sizeof(cd) * p->nC * p->nC, hipMemcpyDeviceToDevice, st);
-  if (!e && p->nC > 0) e = launch_invert_dense(p->nC, p->Kinv, Kw, st);
-  if (!e) e = launch_store_factors(*p, G64, Sinv64, S64, Phi64, st);
-  if (!e) e = hipStreamSynchronize(st);
-  cleanup();
-  if (e) return fail(SFDP_E_DEVICE, std::string("setup: ") + hipGetErrorString(e));
-  p->factored = true;
-  return SFDP_OK;
+  std::vector<Problem*> ps{p};
+  return setup_run(single_target(p), ps, nullptr);
 }
 
 sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double* f, double* x,
@@ -458,28 +754,34 @@ sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double*
   if (nrhs <= 0 || !f || !x) return fail(SFDP_E_INVALID, "bad arguments");
   double tk, ti;
   int mo, kmax;
-  defaults(*p, opts, tk, ti, mo, kmax);
+  defaults(p->prec, opts, tk, ti, mo, kmax);
   const int bsz = batch_of(opts);
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax))) return s;
-  hipStream_t st = p->ctx->stream;
-  HIPCHK(launch_fill(p->flags, sizeof(int) * FLAG_WORDS, st));
-  std::vector<int> its(nrhs, 0);
+  Target t = single_target(p);
+  OneGather g;
+  int trips = 0, rhs_its = 0;
   for (int r0 = 0; r0 < nrhs; r0 += bsz) {
     const int nr = std::min(bsz, nrhs - r0);
-    const cd* fr = (const cd*)f + (size_t)r0 * p->n_free;
-    cd* xr = (cd*)x + (size_t)r0 * p->n_free;
-    if ((s = feti_one(*p, fr, conj_z ? 1 : 0, xr, ti, kmax, nr, nullptr))) return s;
-    HIPCHK(hipMemcpyAsync(its.data() + r0, p->flags + 8, sizeof(int) * nr, hipMemcpyDeviceToHost, st));
+    p->nr = nr;
+    p->map = IDENTITY_MAP;
+    p->uf = (const cd*)f + (size_t)r0 * p->n_free;
+    p->ux = (cd*)x + (size_t)r0 * p->n_free;
+    HIPCHK(launch_fill_flags(t, 0, FLAG_WORDS));
+    s = feti_run(t, p, V_UF, conj_z ? 1 : 0, V_UX, ti, kmax);
+    if (!s) s = gather_one(p, g);
+    p->nr = 0;
+    p->uf = nullptr;
+    p->ux = nullptr;
+    if (s) return s;
+    if (g.h.flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
+    trips += g.h.flags[3];
+    rhs_its += g.h.flags[4];
+    if (krylov_its)
+      for (int c = 0; c < nr; ++c) krylov_its[r0 + c] = g.h.flags[FLAG_ITS + c];
   }
-  int flags[8];
-  HIPCHK(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
   HIPCHK(ev_harvest(*p));
-  if (p->timing) { p->it_gmres += flags[3]; p->it_rhs += flags[4]; }
-  if (krylov_its)
-    for (int r = 0; r < nrhs; ++r) krylov_its[r] = its[r];
+  if (p->timing) { p->it_gmres += trips; p->it_rhs += rhs_its; }
   return SFDP_OK;
 }
 
@@ -500,100 +802,25 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
   HIPCHK(hipSetDevice(p->ctx->device));
   sfdp_status s = alloc_rs(*p);
   if (s) return s;
-  hipStream_t st = p->ctx->stream;
   const size_t n = p->n_free;
+  Target t = single_target(p);
+  OneGather g;
   for (int r0 = 0; r0 < nrhs; r0 += NRMAX) {
     const int nr = std::min(NRMAX, nrhs - r0);
-    const unsigned map = 0x03020100u;  // slot c for the c-th right-hand side
-    double red[2 * NRMAX];
-    HIPCHK(launch_kkt_residual(*p, nr, map, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, y + r0 * n,
-                               u + r0 * n, lam + r0 * n, p->r1, p->r2, p->r3, p->red, st));
-    HIPCHK(hipMemcpyAsync(red, p->red, sizeof(red), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (int c = 0; c < nr; ++c) rel[r0 + c] = red[2 * c];
+    p->nr = nr;
+    p->map = IDENTITY_MAP;
+    p->ybar = ybar + r0 * n;
+    p->yc = yc ? yc + r0 * p->n_bdry : nullptr;
+    p->y = (double*)y + r0 * n;
+    p->u = (double*)u + r0 * n;
+    p->lam = (double*)lam + r0 * n;
+    hipError_t e = launch_kkt_residual(t);
+    s = e == hipSuccess ? gather_one(p, g) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
+    p->nr = 0;
+    if (s) return s;
+    for (int c = 0; c < nr; ++c) rel[r0 + c] = g.h.red[2 * c];
   }
-  HIPCHK(hipStreamSynchronize(st));
   return SFDP_OK;
-}
-
-// Range-space solves of a group of ng <= NRMAX targets (arrays at the group's
-// first RHS, stride n_free / n_bdry).  All unfinished members take each
-// two-factor step together: both FETI-DP solves of a step run the group's
-// active right-hand sides in one launch sequence.
-static sfdp_status range_space_group(sfdp_problem* p, int ng, const double* ybar, const double* yc,
-                                     double* y, double* u, double* lam, double tol_kkt, double tol_inner,
-                                     int max_outer, int kmax, sfdp_info* info) {
-  hipStream_t st = p->ctx->stream;
-  const int64_t n = p->n_free;
-  HIPCHK(launch_copy(ng * n, ybar, y, st));
-  HIPCHK(launch_fill(u, sizeof(double) * ng * n, st));
-  HIPCHK(launch_fill(lam, sizeof(double) * ng * n, st));
-  HIPCHK(launch_fill(p->flags + ITLOG, sizeof(int) * NRMAX * 16, st));
-  sfdp_info loc[NRMAX];
-  memset(loc, 0, sizeof(loc));
-  bool act[NRMAX] = {false, false, false, false};
-  int nfeti[NRMAX] = {0, 0, 0, 0};
-  std::string why[NRMAX];
-  for (int q = 0; q < ng; ++q) act[q] = true;
-  double red[2 * NRMAX];
-  for (int step = 0;; ++step) {
-    unsigned map = 0;
-    int na = 0;
-    for (int q = 0; q < ng; ++q)
-      if (act[q]) map |= (unsigned)q << (8 * na++);
-    if (na == 0) break;
-    HIPCHK(launch_kkt_residual(*p, na, map, ybar, yc, y, u, lam, p->r1, p->r2, p->r3, p->red, st));
-    HIPCHK(hipMemcpyAsync(red, p->red, sizeof(red), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(ev_harvest(*p));
-    unsigned map2 = 0;
-    int nb2 = 0;
-    for (int c = 0; c < na; ++c) {
-      const int q = (map >> (8 * c)) & 255;
-      const double rho = red[2 * q];
-      loc[q].rel_kkt = rho;
-      if (step == 1) loc[q].rel_kkt_first = rho;
-      if (step > 0) loc[q].imag_ratio = red[2 * q + 1];
-      if (!std::isfinite(rho)) { act[q] = false; why[q] = "non-finite residual"; continue; }
-      if (rho <= tol_kkt) { act[q] = false; continue; }
-      if (step >= max_outer) { act[q] = false; why[q] = "outer refinement limit reached"; continue; }
-      map2 |= (unsigned)q << (8 * nb2++);
-    }
-    if (nb2 == 0) break;
-    int* dst[NRMAX];
-    auto set_dst = [&]() {
-      for (int c = 0; c < nb2; ++c) {
-        const int q = (map2 >> (8 * c)) & 255;
-        dst[c] = nfeti[q] < 16 ? p->flags + ITLOG + 16 * q + nfeti[q] : nullptr;
-        ++nfeti[q];
-      }
-    };
-    HIPCHK(launch_make_rhs1(*p, nb2, map2, p->r1, p->r3, p->cvec, st));
-    set_dst();
-    sfdp_status s = feti_one(*p, p->cvec, 0, p->cvec2, tol_inner, kmax, nb2, dst);
-    if (s) return s;
-    HIPCHK(launch_make_rhs2(*p, nb2, map2, p->r1, p->cvec2, p->cvec3, st));
-    set_dst();
-    s = feti_one(*p, p->cvec3, 0, p->cvec, tol_inner, kmax, nb2, dst);
-    if (s) return s;
-    HIPCHK(launch_update(*p, nb2, map2, p->cvec2, p->cvec, y, u, lam, p->red, st));
-    for (int c = 0; c < nb2; ++c) loc[(map2 >> (8 * c)) & 255].outer_steps = step + 1;
-  }
-  int flags[FLAG_WORDS];
-  HIPCHK(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
-  sfdp_status status = SFDP_OK;
-  for (int q = 0; q < ng; ++q) {
-    loc[q].n_feti = nfeti[q];
-    for (int i = 0; i < nfeti[q] && i < 16; ++i) {
-      loc[q].krylov_its[i] = flags[ITLOG + 16 * q + i];
-      loc[q].krylov_total += flags[ITLOG + 16 * q + i];
-    }
-    if (!why[q].empty()) status = fail(SFDP_E_NOCONV, why[q]);
-    if (info) info[q] = loc[q];
-  }
-  return status;
 }
 
 sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar, const double* yc,
@@ -604,26 +831,32 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
   if (nrhs <= 0 || !ybar || !y || !u || !lam) return fail(SFDP_E_INVALID, "bad arguments");
   double tk, ti;
   int mo, kmax;
-  defaults(*p, opts, tk, ti, mo, kmax);
+  defaults(p->prec, opts, tk, ti, mo, kmax);
   const int bsz = batch_of(opts);
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p))) return s;
-  HIPCHK(launch_fill(p->flags, sizeof(int) * FLAG_WORDS, p->ctx->stream));
+  Target t = single_target(p);
+  Gathered* dg = nullptr;
+  if (hipMalloc(&dg, sizeof(Gathered))) return fail(SFDP_E_NOMEM, "gather buffer");
+  Gathered hg;
   sfdp_status worst = SFDP_OK;
   const size_t n = p->n_free;
+  std::vector<Problem*> ps{p};
   for (int r0 = 0; r0 < nrhs; r0 += bsz) {
     const int ng = std::min(bsz, nrhs - r0);
-    s = range_space_group(p, ng, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, y + r0 * n,
-                          u + r0 * n, lam + r0 * n, tk, ti, mo, kmax, info ? info + r0 : nullptr);
+    p->nr = ng;
+    p->ybar = ybar + r0 * n;
+    p->yc = yc ? yc + r0 * p->n_bdry : nullptr;
+    p->y = y + r0 * n;
+    p->u = u + r0 * n;
+    p->lam = lam + r0 * n;
+    std::vector<sfdp_info*> inf{info ? info + r0 : nullptr};
+    s = range_space_run(t, ps, nullptr, dg, &hg, tk, ti, mo, kmax, inf);
+    p->nr = 0;
     if (s == SFDP_E_NOCONV) worst = s;
-    else if (s) return s;
+    else if (s) { hipFree(dg); return s; }
   }
-  if (p->timing) {
-    int f[8];
-    HIPCHK(hipMemcpy(f, p->flags, sizeof(f), hipMemcpyDeviceToHost));
-    p->it_gmres += f[3];
-    p->it_rhs += f[4];
-  }
+  hipFree(dg);
   return worst;
 }
 
@@ -634,51 +867,162 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
   if (nrhs <= 0 || !r || !z) return fail(SFDP_E_INVALID, "bad arguments");
   double tk, ti;
   int mo, kmax;
-  defaults(*p, opts, tk, ti, mo, kmax);
+  defaults(p->prec, opts, tk, ti, mo, kmax);
   const int bsz = batch_of(opts);
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p))) return s;
   hipStream_t st = p->ctx->stream;
-  HIPCHK(launch_fill(p->flags, sizeof(int) * FLAG_WORDS, st));
   const int64_t n = p->n_free;
+  Target t = single_target(p);
+  OneGather g;
   // the middle factor needs r1 = 0: v = conj(0 + M w)
   HIPCHK(launch_fill(p->r1, sizeof(double) * NRMAX * n, st));
-  std::vector<int> its((size_t)2 * nrhs, 0);
   for (int r0 = 0; r0 < nrhs; r0 += bsz) {
     const int nr = std::min(bsz, nrhs - r0);
-    const unsigned map = 0x03020100u;
+    p->nr = nr;
+    p->map = IDENTITY_MAP;
+    HIPCHK(launch_fill_flags(t, 0, FLAG_WORDS));
     // factor 1: w = Z^-1 r ; middle: v = conj(M w) ; factor 2: z = Re conj(Z^-1 v) = Re Z^-1 v
     HIPCHK(launch_copy_real_to_complex(nr * n, r + r0 * n, p->cvec, st));
-    if ((s = feti_one(*p, p->cvec, 0, p->cvec2, ti, kmax, nr, nullptr))) return s;
-    HIPCHK(hipMemcpyAsync(its.data() + 2 * r0, p->flags + 8, sizeof(int) * nr, hipMemcpyDeviceToHost, st));
-    HIPCHK(launch_make_rhs2(*p, nr, map, p->r1, p->cvec2, p->cvec3, st));
-    if ((s = feti_one(*p, p->cvec3, 0, p->cvec, ti, kmax, nr, nullptr))) return s;
-    HIPCHK(hipMemcpyAsync(its.data() + 2 * r0 + nr, p->flags + 8, sizeof(int) * nr, hipMemcpyDeviceToHost,
-                          st));
-    HIPCHK(launch_real_part(nr * n, p->cvec, z + r0 * n, st));
-  }
-  int flags[8];
-  HIPCHK(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
-  HIPCHK(ev_harvest(*p));
-  if (p->timing) { p->it_gmres += flags[3]; p->it_rhs += flags[4]; }
-  if (info) {
-    // its holds, per group of nr, the nr factor-1 counts then the nr factor-2 counts
-    for (int r0 = 0; r0 < nrhs; r0 += bsz) {
-      const int nr = std::min(bsz, nrhs - r0);
+    s = feti_run(t, p, V_CVEC, 0, V_CVEC2, ti, kmax);
+    if (!s) {
+      hipError_t e = launch_make_rhs2(t);
+      s = e == hipSuccess ? feti_run(t, p, V_CVEC3, 0, V_CVEC, ti, kmax) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
+    }
+    if (!s) {
+      hipError_t e = launch_real_part(nr * n, p->cvec, z + r0 * n, st);
+      s = e == hipSuccess ? gather_one(p, g) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
+    }
+    p->nr = 0;
+    if (s) return s;
+    if (g.h.flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
+    if (p->timing) { p->it_gmres += g.h.flags[3]; p->it_rhs += g.h.flags[4]; }
+    if (info)
       for (int c = 0; c < nr; ++c) {
         sfdp_info& o = info[r0 + c];
         memset(&o, 0, sizeof(o));
         o.n_feti = 2;
-        o.krylov_its[0] = its[2 * r0 + c];
-        o.krylov_its[1] = its[2 * r0 + nr + c];
+        o.krylov_its[0] = g.h.flags[FLAG_LOG + 16 * c];
+        o.krylov_its[1] = g.h.flags[FLAG_LOG + 16 * c + 1];
         o.krylov_total = o.krylov_its[0] + o.krylov_its[1];
       }
-    }
   }
+  HIPCHK(ev_harvest(*p));
   return SFDP_OK;
 }
+
+// ---- batches of independent instances ----
+
+sfdp_status sfdp_batch_create(sfdp_ctx* ctx, int count, const int* n_elem, int sub_elem, sfdp_precision prec,
+                              sfdp_batch** out) {
+  if (!ctx || !out || !n_elem || count <= 0) return fail(SFDP_E_INVALID, "bad arguments");
+  *out = nullptr;
+  sfdp_batch* b = new (std::nothrow) sfdp_batch();
+  if (!b) return fail(SFDP_E_NOMEM, "host allocation");
+  b->ctx = ctx;
+  int64_t nsub_tot = 0;
+  for (int i = 0; i < count; ++i) {
+    Problem* p = nullptr;
+    sfdp_status s = create_problem(ctx, 2, n_elem[i], sub_elem, prec, &p);
+    if (s) { delete b; return s; }
+    b->probs.push_back(p);
+    nsub_tot += p->nsub;
+  }
+  // GMRES blocks per instance: one per subdomain when all fit on the device at
+  // once, otherwise enough to keep every block's multiplier chunk <= 192
+  for (Problem* p : b->probs)
+    p->gmres_blocks = nsub_tot <= ctx->num_cu ? p->nsub
+                                              : std::min(p->nsub, std::max(1, (p->nmu + 191) / 192));
+  b->M.ctx = ctx;
+  b->M.probs = b->probs;
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  sfdp_status s = multi_maps(b->M);
+  if (s) { delete b; return s; }
+  *out = b;
+  return SFDP_OK;
+}
+
+void sfdp_batch_destroy(sfdp_batch* b) {
+  if (!b) return;
+  hipSetDevice(b->ctx->device);
+  hipStreamSynchronize(b->ctx->stream);
+  delete b;
+}
+
+sfdp_status sfdp_batch_sizes(const sfdp_batch* b, int i, sfdp_sizes* out) {
+  if (!b || !out || i < 0 || i >= (int)b->probs.size()) return fail(SFDP_E_INVALID, "bad arguments");
+  sizes_of(b->probs[i], out);
+  return SFDP_OK;
+}
+
+sfdp_status sfdp_batch_set_beta(sfdp_batch* b, const double* beta) {
+  if (!b || !beta) return fail(SFDP_E_INVALID, "bad arguments");
+  for (size_t i = 0; i < b->probs.size(); ++i)
+    if (!(beta[i] > 0) || !std::isfinite(beta[i])) return fail(SFDP_E_INVALID, "beta must be positive and finite");
+  HIPCHK(hipSetDevice(b->ctx->device));
+  HIPCHK(hipStreamSynchronize(b->ctx->stream));
+  for (size_t i = 0; i < b->probs.size(); ++i) {
+    Problem* p = b->probs[i];
+    free_factors(*p);
+    p->beta = beta[i];
+    p->alpha = 1.0 / std::sqrt(beta[i]);
+  }
+  return setup_run(b->M.t, b->probs, &b->M);
+}
+
+sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const double* const* ybar,
+                                         const double* const* yc, double* const* y, double* const* u,
+                                         double* const* lam, const sfdp_opts* opts, sfdp_info* info) {
+  if (!b || !nrhs || !ybar || !y || !u || !lam) return fail(SFDP_E_INVALID, "bad arguments");
+  const int n = (int)b->probs.size();
+  int rmax = 0;
+  for (int i = 0; i < n; ++i) {
+    if (nrhs[i] < 0 || (nrhs[i] > 0 && (!ybar[i] || !y[i] || !u[i] || !lam[i])))
+      return fail(SFDP_E_INVALID, "bad arguments");
+    sfdp_status s = check_ready(b->probs[i]);
+    if (s) return s;
+    rmax = std::max(rmax, nrhs[i]);
+  }
+  double tk, ti;
+  int mo, kmax;
+  defaults(b->probs[0]->prec, opts, tk, ti, mo, kmax);
+  const int bsz = batch_of(opts);
+  HIPCHK(hipSetDevice(b->ctx->device));
+  for (Problem* p : b->probs) {
+    sfdp_status s;
+    if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p))) return s;
+  }
+  HIPCHK(hipStreamSynchronize(b->ctx->stream));
+  std::vector<int64_t> ioff(n + 1, 0);
+  for (int i = 0; i < n; ++i) ioff[i + 1] = ioff[i] + nrhs[i];
+  sfdp_status worst = SFDP_OK;
+  for (int r0 = 0; r0 < rmax; r0 += bsz) {
+    int w = 0;
+    std::vector<sfdp_info*> inf(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+      Problem* p = b->probs[i];
+      const int ng = std::max(0, std::min(bsz, nrhs[i] - r0));
+      p->nr = ng;
+      w = std::max(w, ng);
+      if (ng == 0) continue;
+      const size_t nf = p->n_free;
+      p->ybar = ybar[i] + r0 * nf;
+      p->yc = yc && yc[i] ? yc[i] + r0 * p->n_bdry : nullptr;
+      p->y = y[i] + r0 * nf;
+      p->u = u[i] + r0 * nf;
+      p->lam = lam[i] + r0 * nf;
+      inf[i] = info ? info + ioff[i] + r0 : nullptr;
+    }
+    sfdp_status s = multi_groups(b->M, kmax, w == 1 ? 1 : w == 2 ? 2 : 4, b->gmap, b->gcap);
+    if (!s) s = range_space_run(b->M.t, b->probs, &b->M, b->M.dgather, b->M.hgather, tk, ti, mo, kmax, inf);
+    for (Problem* p : b->probs) p->nr = 0;
+    if (s == SFDP_E_NOCONV) worst = s;
+    else if (s) return s;
+  }
+  return worst;
+}
+
 
 sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out, int* rows, int* cols) {
   sfdp_status s = check_ready(p);
@@ -783,10 +1127,16 @@ sfdp_status sfdp_interface_apply(sfdp_problem* p, char which, const double* x, d
   HIPCHK(hipSetDevice(p->ctx->device));
   hipStream_t st = p->ctx->stream;
   if (which == 'D') {
-    const cd* f = (const cd*)x;
-    HIPCHK(launch_local_solve(*p, 0, f, 0, nullptr, 1, st));
-    HIPCHK(launch_coarse_rhs(*p, f, 0, 1, st));
-    HIPCHK(launch_fetidp_rhs(*p, 1, st));
+    Target t = single_target(p);
+    p->nr = 1;
+    p->map = IDENTITY_MAP;
+    p->uf = (const cd*)x;
+    hipError_t e = launch_local_solve(t, 0, V_UF, 0, V_UX);
+    if (e == hipSuccess) e = launch_coarse_rhs(t, V_UF, 0);
+    if (e == hipSuccess) e = launch_fetidp_rhs(t);
+    p->nr = 0;
+    p->uf = nullptr;
+    HIPCHK(e);
     HIPCHK(hipMemcpyAsync(y, p->dvec, sizeof(cd) * p->nmu, hipMemcpyDeviceToDevice, st));
     return SFDP_OK;
   }

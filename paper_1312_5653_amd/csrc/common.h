@@ -173,6 +173,92 @@ struct RhsStride {
   int64_t c4;   // per-subdomain corner buffers (nsub * 4)
 };
 
+// Device flag words of an instance: [1] grid-barrier error, [3] GMRES loop
+// trips, [4] GMRES iterations summed over right-hand sides, [FLAG_ITS + r]
+// iterations of right-hand side r in the last GMRES launch, [FLAG_CNT + slot]
+// FETI-DP solves logged for a group slot, [FLAG_LOG + 16 slot + k] their counts.
+constexpr int FLAG_ITS = 8, FLAG_CNT = 16, FLAG_LOG = 64, FLAG_WORDS = FLAG_LOG + NRMAX * 16;
+
+// Per-instance record gathered to the host after a step: residual heads
+// (red[2 slot]: relative KKT residual, red[2 slot + 1]: imaginary ratio) and
+// the flag words.
+struct Gathered {
+  double red[2 * NRMAX];
+  int flags[FLAG_WORDS];
+};
+
+// Selectors of an instance's complex vectors, passed to kernels so that one
+// launch can address the same vector of every instance it covers.
+enum VecSel : int { V_CVEC = 0, V_CVEC2 = 1, V_CVEC3 = 2, V_UF = 3, V_UX = 4, V_FCS = 5, V_YMIN = 6 };
+
+// Device view of one instance: what every kernel reads about it.  A launch
+// covers one instance (the view is a kernel argument) or many (an array of
+// views in device memory and a block -> instance map).
+struct Dev {
+  Geo2 g;
+  Maps2 mp;
+  RhsStride rs;
+  int g32, s32;       // storage: line factors / interface operators in complex64
+  int nr;             // right-hand sides of the current group (0: instance idle)
+  unsigned map;       // group slot of the c-th right-hand side in byte c
+  int64_t n_free, n_bdry;
+  double beta;
+  const int* full2bdry;
+  // factors
+  void *G, *Sinv, *Phi;
+  cf* Sbb;
+  cd *Kcc, *Kinv;
+  // FETI-DP workspaces (NRMAX r-major copies)
+  cd *Xd, *Ubuf, *Abuf, *Ybuf, *Cbuf, *Qc, *fcs, *u0, *ymin, *dvec, *mu, *wv, *Qk, *Hk, *part;
+  double* dscal;
+  unsigned* bar;
+  int* flags;
+  int kstride;        // allocated Krylov depth (stride of Qk and Hk)
+  // range-space workspaces
+  double *r1, *r2, *r3, *red;
+  cd *cvec, *cvec2, *cvec3;
+  // caller arrays of the current call (device pointers)
+  const cd* uf;       // FETI-DP right-hand sides (stride n_free)
+  cd* ux;             // FETI-DP solutions
+  const double *ybar, *yc;  // range-space targets of the group (stride n_free / n_bdry)
+  double *y, *u, *lam;
+  // share of the GMRES grid: first block, block count, multipliers per block
+  int gb0, gnb, chunk, resident;
+  // FP64 set-up scratch
+  cd *G64, *Sinv64, *S64, *Phi64, *PhiFull, *scr, *Zs;
+};
+
+__host__ __device__ inline cd* dev_vec(const Dev& d, int sel) {
+  switch (sel) {
+    case V_CVEC: return d.cvec;
+    case V_CVEC2: return d.cvec2;
+    case V_CVEC3: return d.cvec3;
+    case V_UF: return const_cast<cd*>(d.uf);
+    case V_UX: return d.ux;
+    case V_FCS: return d.fcs;
+    default: return d.ymin;
+  }
+}
+
+// Block sources.  One: a single instance whose view is the kernel argument,
+// block index = blockIdx.x.  Many: instance = inst[blockIdx.x], block index
+// within it = blockIdx.x - first[instance].
+struct One {
+  Dev d;
+  __device__ inline const Dev& dev() const { return d; }
+  __device__ inline int bx() const { return blockIdx.x; }
+};
+struct Many {
+  const Dev* devs;
+  const int* inst;
+  const int* first;
+  __device__ inline const Dev& dev() const { return devs[inst[blockIdx.x]]; }
+  __device__ inline int bx() const { return blockIdx.x - first[inst[blockIdx.x]]; }
+};
+
+// Launch kinds: how many x-blocks an instance takes in a launch.
+enum Kind : int { K_SUB = 0, K_NC128, K_NC, K_NMU256, K_ASM256, K_NF256, K_SUB16, K_ONE, K_GMRES, K_NKIND };
+
 // Host-side problem.
 struct Ctx;
 struct Problem {
@@ -201,13 +287,21 @@ struct Problem {
   double* dscal = nullptr;    // device scalars
   unsigned* bar = nullptr;    // grid barrier counter
   int* flags = nullptr;       // device flags / outputs of the GMRES kernel
-  int kmax_alloc = 0, gmres_blocks = 0;
-  int* its_dst[NRMAX] = {};  // per-RHS device destinations of the next GMRES launch's counts
+  int kmax_alloc = 0, gmres_blocks = 0, gmres_parts = 0;
   // range-space workspaces (FP64)
   double *r1 = nullptr, *r2 = nullptr, *r3 = nullptr, *red = nullptr;
   cd *cvec = nullptr, *cvec2 = nullptr, *cvec3 = nullptr;
-  int nrhs_alloc = 0;
   size_t bytes = 0;
+  // the current call: group size and slots, caller arrays
+  int nr = 0;
+  unsigned map = 0;
+  const cd* uf = nullptr;
+  cd* ux = nullptr;
+  const double *ybar = nullptr, *yc = nullptr;
+  double *y = nullptr, *u = nullptr, *lam = nullptr;
+  // set-up scratch (valid during sfdp_set_beta only)
+  cd *G64 = nullptr, *Sinv64 = nullptr, *S64 = nullptr, *Phi64 = nullptr, *PhiFull = nullptr,
+     *scr = nullptr, *Zs = nullptr;
   // kernel timing (events recorded around hot kernel launches)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -228,6 +322,45 @@ struct Problem {
   Geo2 geo() const {
     return Geo2{N, m, P, ml, nsub, ND, nmu, nC, 1.0 / N, alpha};
   }
+  // x-blocks of this instance in a launch of the given kind
+  int blocks(int kind) const {
+    switch (kind) {
+      case K_SUB: return nsub;
+      case K_NC128: return (nC + 127) / 128;
+      case K_NC: return nC;
+      case K_NMU256: return (nmu + 255) / 256;
+      case K_ASM256: return (nmu + nC + 255) / 256;
+      case K_NF256: return (int)((n_free + 255) / 256);
+      case K_SUB16: return (nsub * 16 + 255) / 256;
+      case K_ONE: return 1;
+      default: return gmres_blocks;
+    }
+  }
+  Dev dev() const {
+    Dev d;
+    d.g = geo();
+    d.mp = maps();
+    d.rs = rs();
+    d.g32 = g32();
+    d.s32 = s32();
+    d.nr = nr;
+    d.map = map;
+    d.n_free = n_free;
+    d.n_bdry = n_bdry;
+    d.beta = beta;
+    d.full2bdry = full2bdry;
+    d.G = G; d.Sinv = Sinv; d.Phi = Phi; d.Sbb = (cf*)Sbb; d.Kcc = Kcc; d.Kinv = Kinv;
+    d.Xd = Xd; d.Ubuf = Ubuf; d.Abuf = Abuf; d.Ybuf = Ybuf; d.Cbuf = Cbuf; d.Qc = Qc; d.fcs = fcs;
+    d.u0 = u0; d.ymin = ymin; d.dvec = dvec; d.mu = mu; d.wv = wv; d.Qk = Qk; d.Hk = Hk; d.part = part;
+    d.dscal = dscal; d.bar = bar; d.flags = flags; d.kstride = kmax_alloc;
+    d.r1 = r1; d.r2 = r2; d.r3 = r3; d.red = red; d.cvec = cvec; d.cvec2 = cvec2; d.cvec3 = cvec3;
+    d.uf = uf; d.ux = ux; d.ybar = ybar; d.yc = yc; d.y = y; d.u = u; d.lam = lam;
+    d.gb0 = 0; d.gnb = gmres_blocks; d.chunk = (nmu + gmres_blocks - 1) / std::max(gmres_blocks, 1);
+    d.resident = gmres_blocks == nsub;
+    d.G64 = G64; d.Sinv64 = Sinv64; d.S64 = S64; d.Phi64 = Phi64; d.PhiFull = PhiFull; d.scr = scr;
+    d.Zs = Zs;
+    return d;
+  }
 };
 
 struct Ctx {
@@ -238,49 +371,76 @@ struct Ctx {
   int max_lds = 65536;  // bytes of LDS one workgroup may allocate
 };
 
+// The instances one launch covers: a single problem (its view passed by value)
+// or a batch (views in device memory, one block -> instance map per kind).
+struct Target {
+  hipStream_t st = nullptr;
+  Problem* one = nullptr;            // single instance, or
+  std::vector<Problem*> probs;       // the batch's instances (host side)
+  const Dev* devs = nullptr;         // device views of the batch
+  const int* inst[K_NKIND] = {};     // device block -> instance maps
+  const int* first[K_NKIND] = {};    // device first block of each instance
+  int total[K_NKIND] = {};           // x-blocks of a batch launch
+  // batch GMRES: consecutive cooperative launches over groups of instances
+  // whose blocks are co-resident (block -> instance map and block count each)
+  struct GGroup {
+    const int* inst;
+    int total;
+    std::vector<int> members;
+  };
+  std::vector<GGroup> ggroups;
+  sfdp_precision prec = SFDP_FP64;
+  bool single() const { return one != nullptr; }
+  int blocks(int kind) const { return one ? one->blocks(kind) : total[kind]; }
+  One src1() const { return One{one->dev()}; }
+  Many srcN(int kind) const { return Many{devs, inst[kind], first[kind]}; }
+  bool g32() const { return prec == SFDP_MIXED; }
+  bool s32() const { return prec == SFDP_MIXED || prec == SFDP_MIXED_IFACE; }
+};
+
+// One launch over the target with the block map of `kind`.
+template <class KOne, class KMany, class... A>
+static inline void launch2(const Target& t, int kind, KOne k1, KMany kn, int gy, int block, size_t lds,
+                           A... args) {
+  if (t.single())
+    hipLaunchKernelGGL(k1, dim3(t.blocks(kind), gy), dim3(block), lds, t.st, t.src1(), args...);
+  else
+    hipLaunchKernelGGL(kn, dim3(t.blocks(kind), gy), dim3(block), lds, t.st, t.srcN(kind), args...);
+}
+
 // ---- launchers implemented in the .hip files ----
-// setup
-hipError_t launch_factor_lines(const Problem& p, cd* G64, hipStream_t st);
-hipError_t launch_multi_solve(const Problem& p, const cd* G64, cd* Sinv64, cd* Phi64, cd* PhiFull,
-                              cd* scratch, hipStream_t st);
-hipError_t launch_invert_batched(const Problem& p, cd* A64, hipStream_t st);
-hipError_t launch_zcc_and_coarse(const Problem& p, const cd* PhiFull, cd* Kcc, hipStream_t st);
-hipError_t launch_invert_dense(int n, cd* A, cd* work, hipStream_t st);
-hipError_t launch_store_factors(const Problem& p, const cd* G64, const cd* Sinv64, const cd* S64,
-                                const cd* Phi64, hipStream_t st);
-// solve
-// nr <= NRMAX right-hand sides, stored r-major with the strides of Problem::rs()
-hipError_t launch_local_solve(const Problem& p, int mode, const cd* f, int conj_in, cd* x_out,
-                              int nr, hipStream_t st);
-hipError_t launch_coarse_rhs(const Problem& p, const cd* f, int conj_in, int nr, hipStream_t st);
-hipError_t launch_fetidp_rhs(const Problem& p, int nr, hipStream_t st);
-hipError_t launch_gmres(Problem& p, double tol, int kmax, int nr, hipStream_t st);
-hipError_t launch_recover_coarse(const Problem& p, int nr, hipStream_t st);
-hipError_t launch_assemble_solution(const Problem& p, cd* x, int conj_out, int nr, hipStream_t st);
+// set-up (every instance of the target; FP64 scratch in the views)
+hipError_t launch_setup(const Target& t);
+// solve: nr <= NRMAX right-hand sides per instance (the views' nr), r-major
+// buffers with the strides of Problem::rs(); f and x name instance vectors
+hipError_t launch_local_solve(const Target& t, int mode, int f, int conj_in, int x);
+hipError_t launch_coarse_rhs(const Target& t, int f, int conj_in);
+hipError_t launch_fetidp_rhs(const Target& t);
+hipError_t launch_gmres(const Target& t, double tol, int kmax);
+hipError_t launch_recover_coarse(const Target& t);
+hipError_t launch_assemble_solution(const Target& t, int x, int conj_out);
 hipError_t gmres_check(const Problem& p, int kmax);  // the one-RHS kernel fits (hipSuccess)
+int gmres_capacity(const Problem& p, int kmax, int chunk, int width);  // co-resident GMRES blocks
 hipError_t launch_interface_apply(Problem& p, char which, const cd* x, cd* y, hipStream_t st);
 // ops
 hipError_t launch_apply_K(const Problem& p, int nrhs, const double* x, const double* xc, double* y,
                           hipStream_t st);
 hipError_t launch_apply_M(const Problem& p, int nrhs, const double* x, double* y, hipStream_t st);
-// Batched range-space kernels: nr right-hand sides of a group, `map` packs the
+// Batched range-space kernels: the views' nr right-hand sides, `map` packs the
 // group slot of the c-th one in byte c.  red holds (rho, imag ratio) of slot s
 // at red[2 s], red[2 s + 1]; per-block partial sums follow from RED_HEAD.
 constexpr int RED_HEAD = 16;
 int64_t red_pstride(const Problem& p);
-hipError_t launch_kkt_residual(const Problem& p, int nr, unsigned map, const double* ybar,
-                               const double* yc, const double* y, const double* u,
-                               const double* lam, double* r1, double* r2, double* r3, double* red,
-                               hipStream_t st);
-hipError_t launch_make_rhs1(const Problem& p, int nr, unsigned map, const double* r1, const double* r3,
-                            cd* g, hipStream_t st);
-hipError_t launch_make_rhs2(const Problem& p, int nr, unsigned map, const double* r1, const cd* dw,
-                            cd* v, hipStream_t st);
-hipError_t launch_update(const Problem& p, int nr, unsigned map, const cd* dw, const cd* z, double* y,
-                         double* u, double* lam, double* red, hipStream_t st);
-hipError_t launch_real_part(int64_t n, const cd* x, double* y, hipStream_t st);
+hipError_t launch_kkt_residual(const Target& t);
+hipError_t launch_make_rhs1(const Target& t);
+hipError_t launch_make_rhs2(const Target& t);
+hipError_t launch_update(const Target& t);
 hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t st);
+hipError_t launch_fill_flags(const Target& t, int first, int count);
 hipError_t launch_copy_real_to_complex(int64_t n, const double* x, cd* y, hipStream_t st);
 hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t st);
+hipError_t launch_real_part(int64_t n, const cd* x, double* y, hipStream_t st);
+hipError_t launch_group_init(const Target& t);  // y = ybar, u = lam = 0 for the views' groups
+hipError_t launch_gather(const Target& t, Gathered* out);  // out[i]: instance i of the target
 
 }  // namespace sfdp

@@ -61,20 +61,25 @@ __global__ void k_apply_KM(int N, const int* f2b, const double* x, const double*
   if (yM) yM[r * nfree + t] = Mx;
 }
 
-// Batched elementwise kernels: blockIdx.y = c runs over the nr right-hand sides
-// of a group; `map` packs the group slot of c in byte c (slot = map >> 8c & 255).
-// Slot-indexed arrays (KKT iterates, residuals, partial sums) are offset by
-// slot * stride; the FETI-DP vectors (dw, z, g, v) are compact, offset by c * n.
-__device__ inline int slot_of(unsigned map) { return (int)((map >> (8 * blockIdx.y)) & 255u); }
+// Range-space elementwise kernels.  blockIdx.y = c runs over the right-hand sides
+// of an instance's group (blocks with c >= nr return); the view's `map` packs
+// the group slot of the c-th one in byte c.  Slot-indexed arrays (KKT iterates,
+// residuals, partial sums) are offset by slot * stride; the FETI-DP vectors
+// (cvec, cvec2, cvec3) are compact, offset by c * n.
+__device__ inline int slot_of(unsigned map, int c) { return (int)((map >> (8 * c)) & 255u); }
 
-// complex M product: v = conj(r1 + M dw) = r1 + M conj(dw)
-__global__ void k_make_rhs2(int N, unsigned map, const double* r1, const cd* dw, cd* v, int64_t nfree) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// v = conj(r1 + M dw) = r1 + M conj(dw)   (dw = cvec2, v = cvec3)
+template <class Src>
+__global__ void k_make_rhs2(Src src) {
+  const Dev& d = src.dev();
+  const int c = blockIdx.y;
+  if (c >= d.nr) return;
+  const int64_t nfree = d.n_free;
+  int64_t t = (int64_t)src.bx() * blockDim.x + threadIdx.x;
   if (t >= nfree) return;
-  const int c = blockIdx.y, s = slot_of(map);
-  r1 += s * nfree;
-  dw += c * nfree;
-  v += c * nfree;
+  const int N = d.g.N, s = slot_of(d.map, c);
+  const double* r1 = d.r1 + s * nfree;
+  const cd* dw = d.cvec2 + c * nfree;
   int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
   Sten st = make_sten(1.0 / N);
   cd acc{r1[t], 0.0};
@@ -87,29 +92,28 @@ __global__ void k_make_rhs2(int N, unsigned map, const double* r1, const cd* dw,
       acc.x = fma(wm, w.x, acc.x);
       acc.y = fma(-wm, w.y, acc.y);
     }
-  v[t] = acc;
+  d.cvec3[c * nfree + t] = acc;
 }
 
 // per-node KKT residual and its squared norms, block partial sums
-// (part + slot * pstride, pairs (||r||^2, ||b||^2) per block)
-__global__ void __launch_bounds__(256) k_kkt_residual(int N, const int* f2b, double beta, unsigned map,
-                                                      const double* ybar, const double* yc,
-                                                      const double* y, const double* u,
-                                                      const double* lam, double* r1, double* r2,
-                                                      double* r3, double* part, int64_t pstride,
-                                                      int64_t nfree, int64_t nbdry) {
+// (red + RED_HEAD + slot * pstride, pairs (||r||^2, ||b||^2) per block)
+template <class Src>
+__global__ void __launch_bounds__(256) k_kkt_residual(Src src) {
   __shared__ double sh[2][4];
-  const int s = slot_of(map);
-  ybar += s * nfree;
-  if (yc) yc += s * nbdry;
-  y += s * nfree;
-  u += s * nfree;
-  lam += s * nfree;
-  r1 += s * nfree;
-  r2 += s * nfree;
-  r3 += s * nfree;
-  part += s * pstride;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const Dev& d = src.dev();
+  const int c = blockIdx.y;
+  if (c >= d.nr) return;
+  const int N = d.g.N, s = slot_of(d.map, c), bx = src.bx();
+  const int64_t nfree = d.n_free, nbdry = d.n_bdry;
+  const int64_t pstride = 2 * ((nfree + 255) / 256);
+  const int* f2b = d.full2bdry;
+  const double* ybar = d.ybar + s * nfree;
+  const double* yc = d.yc ? d.yc + s * nbdry : nullptr;
+  const double* y = d.y + s * nfree;
+  const double* u = d.u + s * nfree;
+  const double* lam = d.lam + s * nfree;
+  double* part = d.red + RED_HEAD + s * pstride;
+  int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   double rn = 0.0, bn = 0.0;
   if (t < nfree) {
     int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
@@ -131,11 +135,11 @@ __global__ void __launch_bounds__(256) k_kkt_residual(int N, const int* f2b, dou
         }
     }
     double a1 = Mybar - My - Kl;
-    double a2 = -(beta * Mu - Ml);
+    double a2 = -(d.beta * Mu - Ml);
     double a3 = -Kc - Ky + Mu;
-    r1[t] = a1;
-    r2[t] = a2;
-    r3[t] = a3;
+    d.r1[s * nfree + t] = a1;
+    d.r2[s * nfree + t] = a2;
+    d.r3[s * nfree + t] = a3;
     rn = a1 * a1 + a2 * a2 + a3 * a3;
     bn = Mybar * Mybar + Kc * Kc;
   }
@@ -147,18 +151,22 @@ __global__ void __launch_bounds__(256) k_kkt_residual(int N, const int* f2b, dou
   if (lane == 0) { sh[0][wv] = rn; sh[1][wv] = bn; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-    part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    part[2 * bx] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    part[2 * bx + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
   }
 }
 
-// out[2 slot] = sqrt(sum part[2b]) / sqrt(sum part[2b+1])  (fixed order), one
-// block per right-hand side (blockIdx.x = c)
-__global__ void k_reduce_ratio(int nblocks, unsigned map, const double* part, int64_t pstride,
-                               double* out) {
+// red[2 slot + which] = sqrt(sum part[2b]) / sqrt(sum part[2b+1]) in a fixed
+// order; one block per (instance, right-hand side c = blockIdx.y)
+template <class Src>
+__global__ void k_reduce_ratio(Src src, int which) {
   __shared__ double sh[2][256];
-  const int s = (int)((map >> (8 * blockIdx.x)) & 255u);
-  part += s * pstride;
+  const Dev& d = src.dev();
+  const int c = blockIdx.y;
+  if (c >= d.nr) return;
+  const int s = slot_of(d.map, c);
+  const int nblocks = (int)((d.n_free + 255) / 256);
+  const double* part = d.red + RED_HEAD + s * 2 * (int64_t)nblocks;
   double a = 0.0, b = 0.0;
   for (int q = threadIdx.x; q < nblocks; q += 256) {
     a += part[2 * q];
@@ -170,37 +178,45 @@ __global__ void k_reduce_ratio(int nblocks, unsigned map, const double* part, in
   if (threadIdx.x == 0) {
     double sa = 0.0, sb = 0.0;
     for (int q = 0; q < 256; ++q) { sa += sh[0][q]; sb += sh[1][q]; }
-    out[2 * s] = sb > 0.0 ? sqrt(sa) / sqrt(sb) : sqrt(sa);
+    d.red[2 * s + which] = sb > 0.0 ? sqrt(sa) / sqrt(sb) : sqrt(sa);
   }
 }
 
-// g = -r3 - i alpha r1
-__global__ void k_make_rhs1(double alpha, unsigned map, const double* r1, const double* r3, cd* g,
-                            int64_t n) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y, s = slot_of(map);
-  if (t < n) g[c * n + t] = cd{-r3[s * n + t], -alpha * r1[s * n + t]};
+// cvec = -r3 - i alpha r1
+template <class Src>
+__global__ void k_make_rhs1(Src src) {
+  const Dev& d = src.dev();
+  const int c = blockIdx.y;
+  if (c >= d.nr) return;
+  const int64_t n = d.n_free;
+  int64_t t = (int64_t)src.bx() * blockDim.x + threadIdx.x;
+  const int s = slot_of(d.map, c);
+  if (t < n) d.cvec[c * n + t] = cd{-d.r3[s * n + t], -d.g.alpha * d.r1[s * n + t]};
 }
 
-// y -= Re dw; lam += Re z; u = lam / beta; partial sums of |Im z|^2, |Re z|^2
-__global__ void __launch_bounds__(256) k_update(double beta, unsigned map, const cd* dw, const cd* z,
-                                                double* y, double* u, double* lam, double* part,
-                                                int64_t pstride, int64_t n) {
+// y -= Re dw; lam += Re z; u = lam / beta (dw = cvec2, z = cvec); partial sums
+// of |Im z|^2, |Re z|^2
+template <class Src>
+__global__ void __launch_bounds__(256) k_update(Src src) {
   __shared__ double sh[2][4];
-  const int c = blockIdx.y, s = slot_of(map);
-  dw += c * n;
-  z += c * n;
-  y += s * n;
-  u += s * n;
-  lam += s * n;
-  part += s * pstride;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const Dev& d = src.dev();
+  const int c = blockIdx.y;
+  if (c >= d.nr) return;
+  const int s = slot_of(d.map, c), bx = src.bx();
+  const int64_t n = d.n_free, pstride = 2 * ((n + 255) / 256);
+  const cd* dw = d.cvec2 + c * n;
+  const cd* z = d.cvec + c * n;
+  double* y = d.y + s * n;
+  double* u = d.u + s * n;
+  double* lam = d.lam + s * n;
+  double* part = d.red + RED_HEAD + s * pstride;
+  int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   double im = 0.0, re = 0.0;
   if (t < n) {
     y[t] -= dw[t].x;
     double l = lam[t] + z[t].x;
     lam[t] = l;
-    u[t] = l / beta;
+    u[t] = l / d.beta;
     im = z[t].y * z[t].y;
     re = z[t].x * z[t].x;
   }
@@ -212,9 +228,40 @@ __global__ void __launch_bounds__(256) k_update(double beta, unsigned map, const
   if (lane == 0) { sh[0][wv] = im; sh[1][wv] = re; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-    part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    part[2 * bx] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    part[2 * bx + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
   }
+}
+
+// Start of a range-space group: y = ybar, u = 0, lam = 0 for slots c < nr
+// (the group's slots are 0 .. nr-1 here).
+template <class Src>
+__global__ void k_group_init(Src src) {
+  const Dev& d = src.dev();
+  const int c = blockIdx.y;
+  if (c >= d.nr) return;
+  const int64_t n = d.n_free;
+  int64_t t = (int64_t)src.bx() * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  d.y[c * n + t] = d.ybar[c * n + t];
+  d.u[c * n + t] = 0.0;
+  d.lam[c * n + t] = 0.0;
+}
+
+// flags[first .. first + count) = 0 for every instance
+template <class Src>
+__global__ void k_fill_flags(Src src, int first, int count) {
+  const Dev& d = src.dev();
+  for (int i = threadIdx.x; i < count; i += blockDim.x) d.flags[first + i] = 0;
+}
+
+// out[instance] = residual heads and flag words (one block per instance)
+template <class Src>
+__global__ void k_gather(Src src, Gathered* out) {
+  const Dev& d = src.dev();
+  Gathered& o = out[blockIdx.x];
+  if (threadIdx.x < 2 * NRMAX) o.red[threadIdx.x] = d.red ? d.red[threadIdx.x] : 0.0;
+  for (int i = threadIdx.x; i < FLAG_WORDS; i += blockDim.x) o.flags[i] = d.flags[i];
 }
 
 __global__ void k_real_part(int64_t n, const cd* x, double* y) {
@@ -251,37 +298,34 @@ hipError_t launch_apply_M(const Problem& p, int nrhs, const double* x, double* y
 // Partial sums of slot s start at red + RED_HEAD + s * red_pstride(p).
 int64_t red_pstride(const Problem& p) { return 2 * (int64_t)nblk(p.n_free); }
 
-hipError_t launch_kkt_residual(const Problem& p, int nr, unsigned map, const double* ybar,
-                               const double* yc, const double* y, const double* u,
-                               const double* lam, double* r1, double* r2, double* r3, double* red,
-                               hipStream_t st) {
-  unsigned nb = nblk(p.n_free);
-  int64_t ps = red_pstride(p);
-  hipLaunchKernelGGL(k_kkt_residual, dim3(nb, nr), dim3(256), 0, st, p.N, p.full2bdry, p.beta, map,
-                     ybar, yc, y, u, lam, r1, r2, r3, red + RED_HEAD, ps, p.n_free, p.n_bdry);
-  hipLaunchKernelGGL(k_reduce_ratio, dim3(nr), dim3(256), 0, st, (int)nb, map, red + RED_HEAD, ps, red);
+hipError_t launch_kkt_residual(const Target& t) {
+  launch2(t, K_NF256, k_kkt_residual<One>, k_kkt_residual<Many>, NRMAX, 256, 0);
+  launch2(t, K_ONE, k_reduce_ratio<One>, k_reduce_ratio<Many>, NRMAX, 256, 0, 0);
   return hipGetLastError();
 }
-hipError_t launch_make_rhs1(const Problem& p, int nr, unsigned map, const double* r1, const double* r3,
-                            cd* g, hipStream_t st) {
-  hipLaunchKernelGGL(k_make_rhs1, dim3(nblk(p.n_free), nr), dim3(256), 0, st, p.alpha, map, r1, r3, g,
-                     p.n_free);
+hipError_t launch_make_rhs1(const Target& t) {
+  launch2(t, K_NF256, k_make_rhs1<One>, k_make_rhs1<Many>, NRMAX, 256, 0);
   return hipGetLastError();
 }
-hipError_t launch_make_rhs2(const Problem& p, int nr, unsigned map, const double* r1, const cd* dw,
-                            cd* v, hipStream_t st) {
-  hipLaunchKernelGGL(k_make_rhs2, dim3(nblk(p.n_free), nr), dim3(256), 0, st, p.N, map, r1, dw, v,
-                     p.n_free);
+hipError_t launch_make_rhs2(const Target& t) {
+  launch2(t, K_NF256, k_make_rhs2<One>, k_make_rhs2<Many>, NRMAX, 256, 0);
   return hipGetLastError();
 }
-hipError_t launch_update(const Problem& p, int nr, unsigned map, const cd* dw, const cd* z, double* y,
-                         double* u, double* lam, double* red, hipStream_t st) {
-  unsigned nb = nblk(p.n_free);
-  int64_t ps = red_pstride(p);
-  hipLaunchKernelGGL(k_update, dim3(nb, nr), dim3(256), 0, st, p.beta, map, dw, z, y, u, lam,
-                     red + RED_HEAD, ps, p.n_free);
-  hipLaunchKernelGGL(k_reduce_ratio, dim3(nr), dim3(256), 0, st, (int)nb, map, red + RED_HEAD, ps,
-                     red + 1);
+hipError_t launch_update(const Target& t) {
+  launch2(t, K_NF256, k_update<One>, k_update<Many>, NRMAX, 256, 0);
+  launch2(t, K_ONE, k_reduce_ratio<One>, k_reduce_ratio<Many>, NRMAX, 256, 0, 1);
+  return hipGetLastError();
+}
+hipError_t launch_group_init(const Target& t) {
+  launch2(t, K_NF256, k_group_init<One>, k_group_init<Many>, NRMAX, 256, 0);
+  return hipGetLastError();
+}
+hipError_t launch_fill_flags(const Target& t, int first, int count) {
+  launch2(t, K_ONE, k_fill_flags<One>, k_fill_flags<Many>, 1, 64, 0, first, count);
+  return hipGetLastError();
+}
+hipError_t launch_gather(const Target& t, Gathered* out) {
+  launch2(t, K_ONE, k_gather<One>, k_gather<Many>, 1, 128, 0, out);
   return hipGetLastError();
 }
 hipError_t launch_real_part(int64_t n, const cd* x, double* y, hipStream_t st) {

@@ -45,11 +45,15 @@ __device__ void gj_invert_lds(cd* T, int n, cd* rowk, cd* colk) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_factor_lines(Geo2 g, cd* G64) {
+template <class Src>
+__global__ void __launch_bounds__(256) k_factor_lines(Src src) {
   __shared__ cd T[MLMAX * MLMAX];
   __shared__ cd Gp[MLMAX * MLMAX];
   __shared__ cd rowk[MLMAX], colk[MLMAX];
-  const int s = blockIdx.x, ml = g.ml, n2 = ml * ml;
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  cd* G64 = d.G64;
+  const int s = src.bx(), ml = g.ml, n2 = ml * ml;
   for (int j = 0; j < ml; ++j) {
     for (int idx = threadIdx.x; idx < n2; idx += blockDim.x) {
       int p = idx / ml, q = idx % ml;
@@ -95,15 +99,23 @@ __device__ inline cd multi_rhs(const Geo2& g, int s, int a, int b, int col, int 
   return cd{0.0, 0.0};
 }
 
-__global__ void __launch_bounds__(256) k_multi_solve(Geo2 g, Maps2 mp, const cd* G64, cd* Sinv64,
-                                                     cd* Phi64, cd* PhiFull, cd* scratch) {
+template <class Src>
+__global__ void __launch_bounds__(256) k_multi_solve(Src src) {
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  const Maps2& mp = d.mp;
+  const cd* G64 = d.G64;
+  cd* Sinv64 = d.Sinv64;
+  cd* Phi64 = d.Phi64;
+  cd* PhiFull = d.PhiFull;
+  cd* scratch = d.scr;
   __shared__ cd Gl[MLMAX * MLMAX];
   __shared__ cd zb[MLMAX * CW];
   __shared__ cd tb[MLMAX * CW];
   __shared__ int slotmap[MLMAX * MLMAX];
   __shared__ int sdl[128];
   __shared__ int scl[4];
-  const int s = blockIdx.x, ml = g.ml, n2 = ml * ml, ND = g.ND;
+  const int s = src.bx(), ml = g.ml, n2 = ml * ml, ND = g.ND;
   const int nd = mp.nd[s];
   int nc = 0;
   for (int q = 0; q < 4; ++q) nc += (mp.cloc[s * 4 + q] >= 0);
@@ -194,9 +206,13 @@ __global__ void __launch_bounds__(256) k_multi_solve(Geo2 g, Maps2 mp, const cd*
 
 // In-place Gauss-Jordan inverse of the nd_s x nd_s leading block of each
 // subdomain's ND x ND matrix (global memory, one workgroup per subdomain).
-__global__ void __launch_bounds__(1024) k_invert_batched(int ND, const int* ndv, cd* A) {
+template <class Src>
+__global__ void __launch_bounds__(1024) k_invert_batched(Src src) {
   __shared__ cd rowk[512], colk[512];
-  const int s = blockIdx.x, n = ndv[s];
+  const Dev& d = src.dev();
+  const int ND = d.g.ND;
+  cd* A = d.S64;
+  const int s = src.bx(), n = d.mp.nd[s];
   cd* M = A + (size_t)s * ND * ND;
   for (int k = 0; k < n; ++k) {
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
@@ -219,8 +235,14 @@ __global__ void __launch_bounds__(1024) k_invert_batched(int ND, const int* ndv,
 }
 
 // Z_cc*^s = Z_cc - Z_cr Phi  (4 x 4 per subdomain), into Zs[s][4][4].
-__global__ void k_zcc(Geo2 g, Maps2 mp, const cd* PhiFull, cd* Zs) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+template <class Src>
+__global__ void k_zcc(Src src) {
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  const Maps2& mp = d.mp;
+  const cd* PhiFull = d.PhiFull;
+  cd* Zs = d.Zs;
+  int t = src.bx() * blockDim.x + threadIdx.x;
   if (t >= g.nsub * 16) return;
   int s = t / 16, q = (t / 4) % 4, q2 = t % 4;
   int cl = mp.cloc[s * 4 + q], cl2 = mp.cloc[s * 4 + q2];
@@ -241,8 +263,14 @@ __global__ void k_zcc(Geo2 g, Maps2 mp, const cd* PhiFull, cd* Zs) {
 }
 
 // Row c of K_cc* = sum over the subdomains sharing corner c (fixed order).
-__global__ void k_coarse_assemble(Geo2 g, Maps2 mp, const cd* Zs, cd* Kcc) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
+template <class Src>
+__global__ void k_coarse_assemble(Src src) {
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  const Maps2& mp = d.mp;
+  const cd* Zs = d.Zs;
+  cd* Kcc = d.Kcc;
+  int c = src.bx() * blockDim.x + threadIdx.x;
   if (c >= g.nC) return;
   cd* row = Kcc + (size_t)c * g.nC;
   for (int k = 0; k < g.nC; ++k) row[k] = cd{0.0, 0.0};
@@ -272,60 +300,77 @@ __global__ void k_gj_step(int n, int k, const cd* A, cd* B) {
   B[idx] = v;
 }
 
-// Pack the leading nd x nd block of each subdomain's full ND x ND FP64 matrix
-// into lower-triangle row-major storage of the target precision.
-template <class TD>
-__global__ void k_pack(int nsub, int ND, const int* ndv, const cd* src, TD* dst) {
-  const int s = blockIdx.y;
+// K_cc*^-1 of a small coarse matrix (nC <= GJ_LDS_MAX) in LDS, one workgroup per
+// instance: Kinv = GJ(Kcc).
+constexpr int GJ_LDS_MAX = 96;
+template <class Src>
+__global__ void __launch_bounds__(256) k_coarse_inv_lds(Src src) {
+  extern __shared__ __align__(16) char smem[];
+  const Dev& d = src.dev();
+  const int n = d.g.nC;
+  cd* T = (cd*)smem;
+  cd* rowk = T + n * n;
+  cd* colk = rowk + n;
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) T[i] = d.Kcc[i];
+  __syncthreads();
+  gj_invert_lds(T, n, rowk, colk);
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) d.Kinv[i] = T[i];
+}
+
+// Per-subdomain helpers of the set-up (x = subdomain, y = 256-entry chunk).
+// which: 0 Sinv64, 1 Phi64.
+template <class Src>
+__global__ void k_zero_sub(Src src, int which) {
+  const Dev& d = src.dev();
+  const int s = src.bx(), ND = d.g.ND;
+  const size_t per = which == 0 ? (size_t)ND * ND : (size_t)ND * 4;
+  const size_t i = (size_t)blockIdx.y * blockDim.x + threadIdx.x;
+  if (i >= per) return;
+  (which == 0 ? d.Sinv64 : d.Phi64)[(size_t)s * per + i] = cd{0.0, 0.0};
+}
+template <class Src>
+__global__ void k_copy_sub(Src src) {  // S64 = Sinv64
+  const Dev& d = src.dev();
+  const int s = src.bx(), ND = d.g.ND;
+  const size_t per = (size_t)ND * ND;
+  const size_t i = (size_t)blockIdx.y * blockDim.x + threadIdx.x;
+  if (i < per) d.S64[(size_t)s * per + i] = d.Sinv64[(size_t)s * per + i];
+}
+// Storage of the FP64 results: which 0: G64 -> G (ml^3 per subdomain), 1: Phi64 -> Phi.
+template <class TS, class Src>
+__global__ void k_convert(Src src, int which) {
+  const Dev& d = src.dev();
+  const int s = src.bx(), ml = d.g.ml, ND = d.g.ND;
+  const size_t per = which == 0 ? (size_t)ml * ml * ml : (size_t)ND * 4;
+  const size_t i = (size_t)blockIdx.y * blockDim.x + threadIdx.x;
+  if (i >= per) return;
+  const cd v = (which == 0 ? d.G64 : d.Phi64)[(size_t)s * per + i];
+  ((TS*)(which == 0 ? d.G : d.Phi))[(size_t)s * per + i] =
+      TS{(typename real_of<TS>::type)v.x, (typename real_of<TS>::type)v.y};
+}
+// Pack the leading nd x nd block of a subdomain's full ND x ND FP64 matrix into
+// lower-triangle row-major storage (which 0: Sinv64 -> Sinv, 1: S64 -> Sbb).
+template <class TD, class Src>
+__global__ void k_pack(Src src, int which) {
+  const Dev& d = src.dev();
+  const int s = src.bx(), ND = d.g.ND;
   const int PK = ND * (ND + 1) / 2;
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  int idx = blockIdx.y * blockDim.x + threadIdx.x;
   if (idx >= PK) return;
   int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
   while (i * (i + 1) / 2 > idx) --i;
   while ((i + 1) * (i + 2) / 2 <= idx) ++i;
   int k = idx - i * (i + 1) / 2;
-  cd v = (i < ndv[s]) ? src[((size_t)s * ND + i) * ND + k] : cd{0.0, 0.0};
+  const cd* srcm = which == 0 ? d.Sinv64 : d.S64;
+  cd v = (i < d.mp.nd[s]) ? srcm[((size_t)s * ND + i) * ND + k] : cd{0.0, 0.0};
+  TD* dst = which == 0 ? (TD*)d.Sinv : (TD*)d.Sbb;
   dst[(size_t)s * PK + idx] = TD{(typename real_of<TD>::type)v.x, (typename real_of<TD>::type)v.y};
 }
 
-template <class TS>
-__global__ void k_convert(size_t n, const cd* src, TS* dst) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = TS{(typename real_of<TS>::type)src[i].x, (typename real_of<TS>::type)src[i].y};
-}
 
-hipError_t launch_factor_lines(const Problem& p, cd* G64, hipStream_t st) {
-  hipLaunchKernelGGL(k_factor_lines, dim3(p.nsub), dim3(256), 0, st, p.geo(), G64);
-  return hipGetLastError();
-}
-
-hipError_t launch_multi_solve(const Problem& p, const cd* G64, cd* Sinv64, cd* Phi64, cd* PhiFull,
-                              cd* scratch, hipStream_t st) {
-  hipLaunchKernelGGL(k_multi_solve, dim3(p.nsub), dim3(256), 0, st, p.geo(), p.maps(), G64, Sinv64,
-                     Phi64, PhiFull, scratch);
-  return hipGetLastError();
-}
-
-hipError_t launch_invert_batched(const Problem& p, cd* A64, hipStream_t st) {
-  hipLaunchKernelGGL(k_invert_batched, dim3(p.nsub), dim3(1024), 0, st, p.ND, p.nd, A64);
-  return hipGetLastError();
-}
-
-hipError_t launch_zcc_and_coarse(const Problem& p, const cd* PhiFull, cd* Kcc, hipStream_t st) {
-  cd* Zs = nullptr;
-  hipError_t e = hipMallocAsync((void**)&Zs, sizeof(cd) * p.nsub * 16, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zcc, dim3((p.nsub * 16 + 255) / 256), dim3(256), 0, st, p.geo(), p.maps(),
-                     PhiFull, Zs);
-  hipLaunchKernelGGL(k_coarse_assemble, dim3((p.nC + 127) / 128), dim3(128), 0, st, p.geo(),
-                     p.maps(), Zs, Kcc);
-  e = hipGetLastError();
-  hipFreeAsync(Zs, st);
-  return e;
-}
-
-hipError_t launch_invert_dense(int n, cd* A, cd* work, hipStream_t st) {
-  // result ends in A: an even number of ping-pong steps is arranged by a final copy
+static hipError_t invert_dense(int n, cd* A, cd* work, hipStream_t st) {
+  // K_cc*^-1 by one Gauss-Jordan pivot launch per column (large coarse matrices);
+  // the result ends in A (a final copy when the ping-pong ends in work)
   cd* src = A;
   cd* dst = work;
   int nb = (n * n + 255) / 256;
@@ -339,27 +384,57 @@ hipError_t launch_invert_dense(int n, cd* A, cd* work, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_store_factors(const Problem& p, const cd* G64, const cd* Sinv64, const cd* S64,
-                                const cd* Phi64, hipStream_t st) {
-  size_t nG = (size_t)p.nsub * p.ml * p.ml * p.ml;
-  size_t nS = (size_t)p.nsub * p.ND * p.ND;
-  size_t nP = (size_t)p.nsub * p.ND * 4;
-  auto conv = [&](size_t n, const cd* src, void* dst, bool to32) {
-    if (to32)
-      hipLaunchKernelGGL(k_convert<cf>, dim3((n + 255) / 256), dim3(256), 0, st, n, src, (cf*)dst);
-    else
-      hipMemcpyAsync(dst, src, n * sizeof(cd), hipMemcpyDeviceToDevice, st);
-  };
-  conv(nG, G64, p.G, p.g32());
-  conv(nP, Phi64, p.Phi, p.s32());
-  (void)nS;
-  const int PK = p.ND * (p.ND + 1) / 2;
-  dim3 grid((PK + 255) / 256, p.nsub);
-  if (p.s32())
-    hipLaunchKernelGGL(k_pack<cf>, grid, dim3(256), 0, st, p.nsub, p.ND, p.nd, Sinv64, (cf*)p.Sinv);
-  else
-    hipLaunchKernelGGL(k_pack<cd>, grid, dim3(256), 0, st, p.nsub, p.ND, p.nd, Sinv64, (cd*)p.Sinv);
-  hipLaunchKernelGGL(k_pack<cf>, grid, dim3(256), 0, st, p.nsub, p.ND, p.nd, S64, (cf*)p.Sbb);
+// Every step of the set-up for every instance of the target (per-instance FP64
+// scratch named by the views: G64, Sinv64, S64, Phi64, PhiFull, scr, Zs; and
+// Kwork of each problem for large coarse matrices).
+hipError_t launch_setup(const Target& t) {
+  std::vector<Problem*> ps;
+  if (t.single()) ps.push_back(t.one);
+  else ps = t.probs;
+  int ND = 0, ml = 0, ncmax = 0;
+  for (Problem* p : ps) {
+    ND = std::max(ND, p->ND);
+    ml = std::max(ml, p->ml);
+    ncmax = std::max(ncmax, p->nC);
+  }
+  const int yS = (ND * ND + 255) / 256, yP = (ND * 4 + 255) / 256, yG = (ml * ml * ml + 255) / 256;
+  const int yK = (ND * (ND + 1) / 2 + 255) / 256;
+  launch2(t, K_SUB, k_zero_sub<One>, k_zero_sub<Many>, yS, 256, 0, 0);
+  launch2(t, K_SUB, k_zero_sub<One>, k_zero_sub<Many>, yP, 256, 0, 1);
+  launch2(t, K_SUB, k_factor_lines<One>, k_factor_lines<Many>, 1, 256, 0);
+  launch2(t, K_SUB, k_multi_solve<One>, k_multi_solve<Many>, 1, 256, 0);
+  launch2(t, K_SUB, k_copy_sub<One>, k_copy_sub<Many>, yS, 256, 0);
+  launch2(t, K_SUB, k_invert_batched<One>, k_invert_batched<Many>, 1, 1024, 0);
+  launch2(t, K_SUB16, k_zcc<One>, k_zcc<Many>, 1, 256, 0);
+  launch2(t, K_NC128, k_coarse_assemble<One>, k_coarse_assemble<Many>, 1, 128, 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ncmax <= GJ_LDS_MAX) {
+    size_t lds = sizeof(cd) * ((size_t)ncmax * ncmax + 2 * ncmax);
+    e = hipFuncSetAttribute((const void*)k_coarse_inv_lds<One>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_coarse_inv_lds<Many>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    launch2(t, K_ONE, k_coarse_inv_lds<One>, k_coarse_inv_lds<Many>, 1, 256, lds);
+  } else {
+    for (Problem* p : ps) {
+      e = hipMemcpyAsync(p->Kinv, p->Kcc, sizeof(cd) * p->nC * p->nC, hipMemcpyDeviceToDevice, t.st);
+      if (e == hipSuccess) e = invert_dense(p->nC, p->Kinv, p->Kwork, t.st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  if (t.g32()) launch2(t, K_SUB, k_convert<cf, One>, k_convert<cf, Many>, yG, 256, 0, 0);
+  else launch2(t, K_SUB, k_convert<cd, One>, k_convert<cd, Many>, yG, 256, 0, 0);
+  if (t.s32()) {
+    launch2(t, K_SUB, k_convert<cf, One>, k_convert<cf, Many>, yP, 256, 0, 1);
+    launch2(t, K_SUB, k_pack<cf, One>, k_pack<cf, Many>, yK, 256, 0, 0);
+  } else {
+    launch2(t, K_SUB, k_convert<cd, One>, k_convert<cd, Many>, yP, 256, 0, 1);
+    launch2(t, K_SUB, k_pack<cd, One>, k_pack<cd, Many>, yK, 256, 0, 0);
+  }
+  launch2(t, K_SUB, k_pack<cf, One>, k_pack<cf, Many>, yK, 256, 0, 1);
   return hipGetLastError();
 }
 

@@ -46,10 +46,13 @@ __device__ inline void lds_sync() {
 // and the last group publishes the epoch in a generation word that every block
 // polls.  Counters only grow (barrier e completes at e * size), so nothing is
 // reset inside a launch.  A spin limit turns a broken barrier into an error
-// flag instead of a hang.  bar holds BAR_WORDS words.
+// flag instead of a hang.  bar holds BAR_WORDS words.  nblocks and blk are the
+// block count and block index of the group that synchronises (one instance's
+// share of the grid).
 constexpr int BAR_GROUPS = 16, BAR_STRIDE = 32, BAR_TOP = BAR_GROUPS * BAR_STRIDE,
               BAR_GEN = BAR_TOP + BAR_STRIDE, BAR_WORDS = BAR_GEN + BAR_STRIDE;
-__device__ inline void grid_barrier(unsigned* bar, unsigned nblocks, unsigned& epoch, int* err) {
+__device__ inline void grid_barrier(unsigned* bar, unsigned nblocks, unsigned blk, unsigned& epoch,
+                                    int* err) {
   // Data exchanged between blocks uses agent-scope atomic loads and stores
   // (ld_coh / st_coh below), which are coherent across the XCDs' L2 caches
   // without whole-cache write-back or invalidation.  The barrier only has to
@@ -60,7 +63,7 @@ __device__ inline void grid_barrier(unsigned* bar, unsigned nblocks, unsigned& e
   epoch += 1;
   if (threadIdx.x == 0) {
     const unsigned G = nblocks >= 8 * BAR_GROUPS ? BAR_GROUPS : (nblocks + 7) / 8;
-    const unsigned grp = blockIdx.x % G;
+    const unsigned grp = blk % G;
     const unsigned gsize = nblocks / G + (grp < nblocks % G ? 1u : 0u);
     unsigned old = __hip_atomic_fetch_add(bar + grp * BAR_STRIDE, 1u, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
@@ -297,10 +300,11 @@ __device__ inline void line_mv(const TS* Gl, int ml, const T* z, T* red, T* out,
 //   mode 1: load f_r - Z_rc B_c uc - B_r^T mu; output Delta values (Ubuf) and
 //           interior values straight into xout (conjugated if conj_out).
 template <class TS, int NRT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_local_solve(Geo2 g, Maps2 mp, RhsStride rs, int nr, const TS* __restrict__ G, int mode,
-              const cd* __restrict__ f, int conj_in, const cd* __restrict__ uc,
-              const cd* __restrict__ mu, cd* Xd, cd* Qc, cd* Ubuf, cd* xout, int conj_out) {
+__device__ inline void local_solve_body(const Geo2& g, const Maps2& mp, const RhsStride& rs, int nr,
+                                        const TS* __restrict__ G, int mode, const cd* __restrict__ f,
+                                        int conj_in, const cd* __restrict__ uc,
+                                        const cd* __restrict__ mu, cd* Xd, cd* Qc, cd* Ubuf,
+                                        cd* xout, int conj_out, int s) {
   using R = double;  // FP64 arithmetic for both storage precisions
   using T = cd;
   constexpr int XS = ML * ML;
@@ -309,7 +313,7 @@ k_local_solve(Geo2 g, Maps2 mp, RhsStride rs, int nr, const TS* __restrict__ G, 
   __shared__ T red[NRT * 4 * ML];
   __shared__ TS gbuf[ML * ML];
   __shared__ T cpl[ML][3];   // coupling of node p of a line to node p + d - 1 of the next line
-  const int s = blockIdx.x, ml = g.ml, n2 = ml * ml, ND = g.ND;
+  const int ml = g.ml, n2 = ml * ml, ND = g.ND;
   const TS* Gs = G + (size_t)s * ml * n2;
   // The forward sweep visits lines 0..ml-1, the backward sweep ml-2..0: step t
   // uses line (t < ml ? t : 2 ml - 2 - t).  Line factors stream through a ring
@@ -466,12 +470,30 @@ k_local_solve(Geo2 g, Maps2 mp, RhsStride rs, int nr, const TS* __restrict__ G, 
   }
 }
 
+// One workgroup per (instance, subdomain); instances with no group skip.
+template <class TS, int NRT, class Src>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_local_solve(Src src, int mode, int fsel, int conj_in, int xsel) {
+  const Dev& d = src.dev();
+  if (d.nr <= 0) return;
+  local_solve_body<TS, NRT>(d.g, d.mp, d.rs, d.nr, (const TS*)d.G, mode, dev_vec(d, fsel), conj_in,
+                            d.u0, d.mu, d.Xd, d.Qc, d.Ubuf, mode == 1 ? dev_vec(d, xsel) : nullptr,
+                            mode == 1 ? conj_in : 0, src.bx());
+}
+
 // f_c* = f_c - sum_s B_c^T Qc  (one thread per global corner, fixed order)
-__global__ void k_coarse_rhs(Geo2 g, Maps2 mp, RhsStride rs, const cd* f, int conj_in, const cd* Qc,
-                             cd* fcs) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.nC) return;
+template <class Src>
+__global__ void k_coarse_rhs(Src src, int fsel, int conj_in) {
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  const Maps2& mp = d.mp;
+  const RhsStride& rs = d.rs;
+  int c = src.bx() * blockDim.x + threadIdx.x;
+  if (c >= g.nC || (int)blockIdx.y >= d.nr) return;
   const int64_t r = blockIdx.y;
+  const cd* f = dev_vec(d, fsel);
+  const cd* Qc = d.Qc;
+  cd* fcs = d.fcs;
   f += r * rs.nf;
   Qc += r * rs.c4;
   fcs += r * rs.nc;
@@ -484,12 +506,16 @@ __global__ void k_coarse_rhs(Geo2 g, Maps2 mp, RhsStride rs, const cd* f, int co
   fcs[c] = v;
 }
 
-// y = A x (n x n dense FP64 complex), one wavefront per row.
-__global__ void k_dense_mv(int n, int64_t stride, const cd* __restrict__ A, const cd* __restrict__ x,
-                           cd* y) {
-  int row = blockIdx.x;
-  x += blockIdx.y * stride;
-  y += blockIdx.y * stride;
+// u0 = K_cc*^-1 x (x = fcs or ymin), one wavefront per row.
+template <class Src>
+__global__ void k_dense_mv(Src src, int xsel) {
+  const Dev& d = src.dev();
+  if ((int)blockIdx.y >= d.nr) return;
+  const int n = d.g.nC, row = src.bx();
+  const int64_t stride = d.rs.nc;
+  const cd* __restrict__ A = d.Kinv;
+  const cd* x = dev_vec(d, xsel) + blockIdx.y * stride;
+  cd* y = d.u0 + blockIdx.y * stride;
   cd acc{0.0, 0.0};
   for (int k = threadIdx.x; k < n; k += 64) fma_acc(acc, A[(size_t)row * n + k], x[k]);
   for (int off = 32; off > 0; off >>= 1) {
@@ -500,12 +526,19 @@ __global__ void k_dense_mv(int n, int64_t stride, const cd* __restrict__ A, cons
 }
 
 // d_k = sum over the two subdomains of sign * (Xd - Phi u0)
-template <class TS>
-__global__ void k_fetidp_rhs(Geo2 g, Maps2 mp, RhsStride rs, const cd* Xd, const TS* Phi, const cd* u0,
-                             cd* d) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= g.nmu) return;
+template <class TS, class Src>
+__global__ void k_fetidp_rhs(Src src) {
+  const Dev& dv = src.dev();
+  const Geo2& g = dv.g;
+  const Maps2& mp = dv.mp;
+  const RhsStride& rs = dv.rs;
+  int k = src.bx() * blockDim.x + threadIdx.x;
+  if (k >= g.nmu || (int)blockIdx.y >= dv.nr) return;
   const int64_t r = blockIdx.y;
+  const cd* Xd = dv.Xd;
+  const TS* Phi = (const TS*)dv.Phi;
+  const cd* u0 = dv.u0;
+  cd* d = dv.dvec;
   Xd += r * rs.sb;
   u0 += r * rs.nc;
   d += r * rs.nmu;
@@ -527,12 +560,19 @@ __global__ void k_fetidp_rhs(Geo2 g, Maps2 mp, RhsStride rs, const cd* Xd, const
 
 // c^s_q = sum_i Phi[s][i][q] sign_i mu[mid_i]  (F_rc^T mu contributions); one
 // wavefront per (subdomain, corner slot).
-template <class TS>
-__global__ void k_frct(Geo2 g, Maps2 mp, RhsStride rs, const TS* Phi, const cd* mu, cd* Cbuf) {
-  int t = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+template <class TS, class Src>
+__global__ void k_frct(Src src) {
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  const Maps2& mp = d.mp;
+  const RhsStride& rs = d.rs;
+  int t = src.bx() * (blockDim.x / 64) + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
-  if (t >= g.nsub * 4) return;
+  if (t >= g.nsub * 4 || (int)blockIdx.y >= d.nr) return;
   const int64_t r = blockIdx.y;
+  const TS* Phi = (const TS*)d.Phi;
+  const cd* mu = d.mu;
+  cd* Cbuf = d.Cbuf;
   mu += r * rs.nmu;
   Cbuf += r * rs.c4;
   int s = t / 4, q = t % 4;
@@ -551,11 +591,19 @@ __global__ void k_frct(Geo2 g, Maps2 mp, RhsStride rs, const TS* Phi, const cd* 
   if (lane == 0) Cbuf[t] = acc;
 }
 
-// rhs_c = fcs_c + sum_owners Cbuf
-__global__ void k_corner_sum(Geo2 g, Maps2 mp, RhsStride rs, const cd* fcs, const cd* Cbuf, cd* out) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.nC) return;
+// ymin_c = fcs_c + sum_owners Cbuf
+template <class Src>
+__global__ void k_corner_sum(Src src) {
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  const Maps2& mp = d.mp;
+  const RhsStride& rs = d.rs;
+  int c = src.bx() * blockDim.x + threadIdx.x;
+  if (c >= g.nC || (int)blockIdx.y >= d.nr) return;
   const int64_t r = blockIdx.y;
+  const cd* fcs = d.fcs;
+  const cd* Cbuf = d.Cbuf;
+  cd* out = d.ymin;
   if (fcs) fcs += r * rs.nc;
   Cbuf += r * rs.c4;
   out += r * rs.nc;
@@ -568,10 +616,18 @@ __global__ void k_corner_sum(Geo2 g, Maps2 mp, RhsStride rs, const cd* fcs, cons
 }
 
 // primal assembly: Delta nodes average the two subdomain copies, corners take uc
-__global__ void k_assemble(Geo2 g, Maps2 mp, RhsStride rs, const cd* Ubuf, const cd* uc, cd* x,
-                           int conj_out) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
+template <class Src>
+__global__ void k_assemble(Src src, int xsel, int conj_out) {
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  const Maps2& mp = d.mp;
+  const RhsStride& rs = d.rs;
+  int k = src.bx() * blockDim.x + threadIdx.x;
+  if ((int)blockIdx.y >= d.nr) return;
   const int64_t r = blockIdx.y;
+  const cd* Ubuf = d.Ubuf;
+  const cd* uc = d.u0;
+  cd* x = dev_vec(d, xsel);
   Ubuf += r * rs.sb;
   uc += r * rs.nc;
   x += r * rs.nf;
@@ -841,17 +897,24 @@ struct GmresArgs {
   cd* H;            // [r][kmax_alloc+1][kmax_alloc], column j at H[i*kstride + j]
   cd* part;         // [3][NRMAX][kmax+2][nb]
   unsigned* bar;
-  int* flags;       // [1] barrier error, [3] loop trips, [4] summed iterations
-  int* its_out;     // [r] iterations of RHS r
+  int* flags;       // instance flag words (FLAG_*)
   double* scal;     // [r] final relative residual estimate
   double tol;
   int kmax;         // iteration limit of this launch
   int kstride;      // kmax_alloc (strides of Q and H)
   int chunk;
   int nr;
+  int r0;           // first right-hand side of the group served by this launch
+  unsigned map;     // group slot of right-hand side c in byte c (iteration log)
   int resident;     // Schur blocks kept in LDS (requires one subdomain per block)
-  int* its_dst[NRMAX];  // optional extra destination of the iteration count of RHS r
   // byte offsets into dynamic LDS (gmres_layout)
+  int o_red, o_xs, o_wch, o_hv, o_h2, o_cs, o_sn, o_g, o_ucs, o_S, o_I;
+};
+
+// Launch-wide GMRES parameters (the same for every instance of a launch).
+struct GmresLaunch {
+  double tol;
+  int kmax, r0, resident;
   int o_red, o_xs, o_wch, o_hv, o_h2, o_cs, o_sn, o_g, o_ucs, o_S, o_I;
 };
 
@@ -860,7 +923,7 @@ static inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 // Dynamic LDS of k_gmres: the work arrays, then the Schur-block buffers (both
 // resident, or one staging buffer shared by the two).  Returns the total size.
 static size_t gmres_layout(int nrt, int kmax, int chunk, size_t tsz, size_t bytesS, size_t bytesI,
-                           bool resident, GmresArgs* a) {
+                           bool resident, GmresLaunch* a) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align16(bytes); return (int)at; };
   int red = take(tsz * 128 * nrt), xs = take(tsz * 128 * nrt);
@@ -878,10 +941,10 @@ static size_t gmres_layout(int nrt, int kmax, int chunk, size_t tsz, size_t byte
 }
 
 template <class TS, int NRT>
-__global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __restrict__ Sbb,
-                                               const TS* __restrict__ Sinv,
-                                               const TS* __restrict__ Phi,
-                                               const cd* __restrict__ Kinv, GmresArgs a) {
+__device__ inline void gmres_body(const Geo2& g, const Maps2& mp, const cf* __restrict__ Sbb,
+                                  const TS* __restrict__ Sinv, const TS* __restrict__ Phi,
+                                  const cd* __restrict__ Kinv, const GmresArgs& a, const int b,
+                                  const unsigned nb) {
   using R = double;  // FP64 arithmetic for both storage precisions
   using T = cd;
   extern __shared__ __align__(16) char smem[];
@@ -902,8 +965,6 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
   __shared__ cd nrm2[NRT];
   __shared__ int active[NRT], its[NRT], ract[NRT], nact_sh;
 
-  const unsigned nb = gridDim.x;
-  const int b = blockIdx.x;
   unsigned epoch = 0;
   const int nmu = g.nmu;
   const RhsStride rs = a.rs;
@@ -921,7 +982,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
 
   if (a.resident) {
     // one subdomain per block: both Schur blocks stay in LDS for the whole solve
-    const int s = blockIdx.x, nd = mp.nd[s];
+    const int s = b, nd = mp.nd[s];
     stage_lds(bufS, Sbb + (size_t)s * packed_len(g.ND), packed_len(nd) * (int)sizeof(cf));
     stage_lds(bufI, Sinv + (size_t)s * packed_len(g.ND), packed_len(nd) * (int)sizeof(TS));
   }
@@ -946,7 +1007,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
   }
   if (threadIdx.x < NRT) ract[threadIdx.x] = threadIdx.x;
   __syncthreads();
-  grid_barrier(a.bar, nb, epoch, a.flags + 1);
+  grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
   reduce_partials(part2, pstride, nb, 1, nr, ract, nrm2, 1);
   if (threadIdx.x < NRT) {
     const int r = threadIdx.x;
@@ -972,16 +1033,16 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
     for (int s = b; s < g.nsub; s += nb)
       phase_precond<TS, NRT>(g, mp, Sbb, s, vin, rs.nmu, sc, a.Abuf, rs.sb, nr, bufS, a.resident,
                              xs, red);
-    grid_barrier(a.bar, nb, epoch, a.flags + 1);
+    grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
     // ---- F1
     for (int s = b; s < g.nsub; s += nb)
       phase_f1<TS, NRT>(g, mp, rs, Sinv, Phi, s, true, a.Abuf, nullptr, sc, a.Ybuf, a.Cbuf, nr, bufI,
                         a.resident, xs, red);
-    grid_barrier(a.bar, nb, epoch, a.flags + 1);
+    grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
     // ---- F2 (coarse correction)
     for (int s = b; s < g.nsub; s += nb)
       phase_f2<TS, NRT>(g, mp, rs, Phi, Kinv, s, a.Cbuf, a.Ybuf, nr, ucs, wred);
-    grid_barrier(a.bar, nb, epoch, a.flags + 1);
+    grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
     // ---- O1: w_r = B_r Y_r (combine), first Gram-Schmidt projections
     if (mine)
       for (int k = lt; k < kn; k += TPR) {
@@ -991,7 +1052,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
       }
     __syncthreads();
     block_dots(a.Q, qs, nmu, k0, kn, j + 1, na, ract, wch, a.chunk, part0, pstride, nb, b);
-    grid_barrier(a.bar, nb, epoch, a.flags + 1);
+    grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
     // ---- O2: h = sum of partials; w -= Q h; second projections
     reduce_partials(part0, pstride, nb, j + 1, na, ract, hv, hst);
     if (mine) {
@@ -1006,7 +1067,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
     }
     __syncthreads();
     block_dots(a.Q, qs, nmu, k0, kn, j + 1, na, ract, wch, a.chunk, part1, pstride, nb, b);
-    grid_barrier(a.bar, nb, epoch, a.flags + 1);
+    grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
     // ---- O3: second correction, norm
     reduce_partials(part1, pstride, nb, j + 1, na, ract, h2, hst);
     {
@@ -1027,7 +1088,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
       if (threadIdx.x < nr && active[threadIdx.x])
         st_coh(part2 + threadIdx.x * pstride + b, cd{nsum[threadIdx.x], 0.0});
     }
-    grid_barrier(a.bar, nb, epoch, a.flags + 1);
+    grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
     // ---- Arnoldi column j complete: norms, Givens rotations (identical in every block)
     reduce_partials(part2, pstride, nb, 1, na, ract, nrm2, 1);
     if (threadIdx.x < nr && active[threadIdx.x]) {
@@ -1077,7 +1138,7 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
   }
   // ---- back substitution H_r y_r = g_r for all RHS together (redundant in every
   // block; H from block 0), then t_r = Q_r y_r on the chunk
-  grid_barrier(a.bar, nb, epoch, a.flags + 1);
+  grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
   int kmx = 0;
   for (int r = 0; r < nr; ++r) kmx = max(kmx, its[r]);
   if (rt < nr)
@@ -1108,12 +1169,12 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
     }
   }
   if (threadIdx.x < NRT) sc[threadIdx.x] = (threadIdx.x < nr && its[threadIdx.x] > 0) ? 1.0 : 0.0;
-  grid_barrier(a.bar, nb, epoch, a.flags + 1);
+  grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
   // mu_r = P^-1 t_r
   for (int s = b; s < g.nsub; s += nb)
     phase_precond<TS, NRT>(g, mp, Sbb, s, a.w, rs.nmu, sc, a.Abuf, rs.sb, nr, bufS, a.resident, xs,
                            red);
-  grid_barrier(a.bar, nb, epoch, a.flags + 1);
+  grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
   if (rt < nr)
     for (int k = k0 + lt; k < k1; k += TPR)
       a.mu[rt * rs.nmu + k] = its[rt] > 0 ? 0.5 * (ld_coh(a.Abuf + rt * rs.sb + mp.muown[2 * k]) -
@@ -1122,14 +1183,63 @@ __global__ void __launch_bounds__(256) k_gmres(Geo2 g, Maps2 mp, const cf* __res
   if (b == 0 && threadIdx.x == 0) {
     int tot = 0;
     for (int r = 0; r < nr; ++r) {
-      a.its_out[r] = its[r];
-      if (a.its_dst[r]) *a.its_dst[r] = its[r];
+      a.flags[FLAG_ITS + a.r0 + r] = its[r];
+      // append to the log of the right-hand side's group slot
+      const int slot = (int)((a.map >> (8 * (a.r0 + r))) & 255u);
+      const int k = a.flags[FLAG_CNT + slot];
+      if (k < 16) a.flags[FLAG_LOG + 16 * slot + k] = its[r];
+      a.flags[FLAG_CNT + slot] = k + 1;
       a.scal[r] = resid[r];
       tot += its[r];
     }
     a.flags[3] += j;    // loop trips of this launch (the largest count of the group)
     a.flags[4] += tot;  // iterations summed over its right-hand sides
   }
+}
+
+// One cooperative launch; every instance's blocks (its share gb0 .. gb0+gnb-1
+// of the grid) run the Krylov solve of its group's right-hand sides r0 ..
+// r0 + NRT - 1 with their own grid barrier.  Instances with no such
+// right-hand side return at once.
+template <class TS, int NRT, class Src>
+__global__ void __launch_bounds__(256) k_gmres(Src src, GmresLaunch L) {
+  const Dev& d = src.dev();
+  const int nr = min(NRT, d.nr - L.r0);
+  if (nr <= 0) return;
+  const RhsStride rs = d.rs;
+  GmresArgs a;
+  a.rs = rs;
+  a.d = d.dvec + L.r0 * rs.nmu;
+  a.mu = d.mu + L.r0 * rs.nmu;
+  a.Abuf = d.Abuf + L.r0 * rs.sb;
+  a.Ybuf = d.Ybuf + L.r0 * rs.sb;
+  a.Cbuf = d.Cbuf + L.r0 * rs.c4;
+  a.w = d.wv + L.r0 * rs.nmu;
+  a.Q = d.Qk;
+  a.H = d.Hk;
+  a.part = d.part;
+  a.bar = d.bar;
+  a.flags = d.flags;
+  a.scal = d.dscal + L.r0;
+  a.tol = L.tol;
+  a.kmax = L.kmax;
+  a.kstride = d.kstride;
+  a.chunk = d.chunk;
+  a.nr = nr;
+  a.r0 = L.r0;
+  a.map = d.map;
+  a.resident = L.resident && d.resident;
+  a.o_red = L.o_red; a.o_xs = L.o_xs; a.o_wch = L.o_wch; a.o_hv = L.o_hv; a.o_h2 = L.o_h2;
+  a.o_cs = L.o_cs; a.o_sn = L.o_sn; a.o_g = L.o_g; a.o_ucs = L.o_ucs; a.o_S = L.o_S; a.o_I = L.o_I;
+  gmres_body<TS, NRT>(d.g, d.mp, d.Sbb, (const TS*)d.Sinv, (const TS*)d.Phi, d.Kinv, a, src.bx(),
+                      (unsigned)d.gnb);
+}
+
+// Zero every instance's grid-barrier words before a GMRES launch.
+template <class Src>
+__global__ void k_bar_reset(Src src) {
+  const Dev& d = src.dev();
+  for (int i = threadIdx.x; i < BAR_WORDS; i += blockDim.x) d.bar[i] = 0u;
 }
 
 // Stand-alone interface kernels for testing (one block per subdomain, one RHS).
@@ -1168,47 +1278,44 @@ __global__ void k_combine(Geo2 g, Maps2 mp, const cd* buf, double scale, cd* out
 
 // ------------------------------------------------------------------------------------------
 // launchers (nr right-hand sides, r-major buffers of the problem)
+
+static int max_nr(const Target& t) {
+  if (t.single()) return t.one->nr;
+  int n = 0;
+  for (const Problem* p : t.probs) n = std::max(n, p->nr);
+  return n;
+}
+
 template <class TS, int NRT>
-static hipError_t local_solve_t(const Problem& p, int mode, const cd* f, int conj_in, cd* xout,
-                                int conj_out, int nr) {
-  hipLaunchKernelGGL((k_local_solve<TS, NRT>), dim3(p.nsub), dim3(256), 0, p.ctx->stream, p.geo(),
-                     p.maps(), p.rs(), nr, (const TS*)p.G, mode, f, conj_in, p.u0, p.mu, p.Xd, p.Qc,
-                     p.Ubuf, xout, conj_out);
-  return hipGetLastError();
+static void local_solve_t(const Target& t, int mode, int f, int conj_in, int x) {
+  launch2(t, K_SUB, k_local_solve<TS, NRT, One>, k_local_solve<TS, NRT, Many>, 1, 256, 0, mode, f,
+          conj_in, x);
 }
 
 template <class TS>
-static hipError_t local_solve_w(const Problem& p, int mode, const cd* f, int conj_in, cd* xout,
-                                int conj_out, int nr) {
-  if (nr == 1) return local_solve_t<TS, 1>(p, mode, f, conj_in, xout, conj_out, 1);
-  if (nr == 2) return local_solve_t<TS, 2>(p, mode, f, conj_in, xout, conj_out, 2);
-  return local_solve_t<TS, NRMAX>(p, mode, f, conj_in, xout, conj_out, nr);
+static void local_solve_w(const Target& t, int mode, int f, int conj_in, int x, int nr) {
+  if (nr == 1) local_solve_t<TS, 1>(t, mode, f, conj_in, x);
+  else if (nr == 2) local_solve_t<TS, 2>(t, mode, f, conj_in, x);
+  else local_solve_t<TS, NRMAX>(t, mode, f, conj_in, x);
 }
 
-hipError_t launch_local_solve(const Problem& p, int mode, const cd* f, int conj_in, cd* x_out,
-                              int nr, hipStream_t) {
+hipError_t launch_local_solve(const Target& t, int mode, int f, int conj_in, int x) {
+  const int nr = max_nr(t);
   if (nr < 1 || nr > NRMAX) return hipErrorInvalidValue;
-  int conj_out = (mode == 1) ? conj_in : 0;
-  if (p.g32()) return local_solve_w<cf>(p, mode, f, conj_in, x_out, conj_out, nr);
-  return local_solve_w<cd>(p, mode, f, conj_in, x_out, conj_out, nr);
-}
-
-hipError_t launch_coarse_rhs(const Problem& p, const cd* f, int conj_in, int nr, hipStream_t st) {
-  hipLaunchKernelGGL(k_coarse_rhs, dim3((p.nC + 127) / 128, nr), dim3(128), 0, st, p.geo(), p.maps(),
-                     p.rs(), f, conj_in, p.Qc, p.fcs);
-  if (p.nC > 0)
-    hipLaunchKernelGGL(k_dense_mv, dim3(p.nC, nr), dim3(64), 0, st, p.nC, p.rs().nc, p.Kinv, p.fcs,
-                       p.u0);
+  if (t.g32()) local_solve_w<cf>(t, mode, f, conj_in, x, nr);
+  else local_solve_w<cd>(t, mode, f, conj_in, x, nr);
   return hipGetLastError();
 }
 
-hipError_t launch_fetidp_rhs(const Problem& p, int nr, hipStream_t st) {
-  if (p.s32())
-    hipLaunchKernelGGL(k_fetidp_rhs<cf>, dim3((p.nmu + 255) / 256, nr), dim3(256), 0, st, p.geo(),
-                       p.maps(), p.rs(), p.Xd, (const cf*)p.Phi, p.u0, p.dvec);
-  else
-    hipLaunchKernelGGL(k_fetidp_rhs<cd>, dim3((p.nmu + 255) / 256, nr), dim3(256), 0, st, p.geo(),
-                       p.maps(), p.rs(), p.Xd, (const cd*)p.Phi, p.u0, p.dvec);
+hipError_t launch_coarse_rhs(const Target& t, int f, int conj_in) {
+  launch2(t, K_NC128, k_coarse_rhs<One>, k_coarse_rhs<Many>, NRMAX, 128, 0, f, conj_in);
+  launch2(t, K_NC, k_dense_mv<One>, k_dense_mv<Many>, NRMAX, 64, 0, (int)V_FCS);
+  return hipGetLastError();
+}
+
+hipError_t launch_fetidp_rhs(const Target& t) {
+  if (t.s32()) launch2(t, K_NMU256, k_fetidp_rhs<cf, One>, k_fetidp_rhs<cf, Many>, NRMAX, 256, 0);
+  else launch2(t, K_NMU256, k_fetidp_rhs<cd, One>, k_fetidp_rhs<cd, Many>, NRMAX, 256, 0);
   return hipGetLastError();
 }
 
@@ -1219,134 +1326,167 @@ static void block_bytes(const Problem& p, size_t* bS, size_t* bI) {
   *bI = pk * (p.s32() ? sizeof(cf) : sizeof(cd));
 }
 
-// LDS bytes of k_gmres<TS, NRT> for this problem and whether the Schur blocks
-// stay resident (mixed storage, one subdomain per block, and room for both).
-template <class TS, int NRT>
-static size_t gmres_plan(const Problem& p, int kmax, bool* resident, GmresArgs* a) {
-  using R = double;  // FP64 arithmetic for both storage precisions
-  const int nb = p.gmres_blocks, chunk = (p.nmu + nb - 1) / nb;
-  size_t bS, bI;
-  block_bytes(p, &bS, &bI);
-  bool res = p.s32() && nb == p.nsub &&
-             gmres_layout(NRT, kmax, chunk, sizeof(C<R>), bS, bI, true, nullptr) <= (size_t)p.ctx->max_lds;
-  if (resident) *resident = res;
-  return gmres_layout(NRT, kmax, chunk, sizeof(C<R>), bS, bI, res, a);
+// The instances of one GMRES launch: the single problem, or batch group gi.
+static void gmres_members(const Target& t, int gi, std::vector<const Problem*>& out) {
+  out.clear();
+  if (t.single()) out.push_back(t.one);
+  else
+    for (int i : t.ggroups[gi].members) out.push_back(t.probs[i]);
 }
 
-// Whether every block of the cooperative grid of k_gmres<TS, NRT> can be
-// co-resident (0) or not (an error code).
+// LDS bytes of k_gmres<TS, NRT> over the given instances, and whether the
+// Schur blocks stay resident (complex64 interface operators, one subdomain per
+// block for every instance, and room for both blocks).
 template <class TS, int NRT>
-static hipError_t gmres_fits(const Problem& p, int kmax) {
-  size_t lds = gmres_plan<TS, NRT>(p, kmax, nullptr, nullptr);
-  if (lds > (size_t)p.ctx->max_lds) return hipErrorOutOfMemory;
-  const void* fn = (const void*)k_gmres<TS, NRT>;
+static size_t gmres_plan(const std::vector<const Problem*>& ms, int kmax, bool* resident,
+                         GmresLaunch* L) {
+  size_t bS = 0, bI = 0;
+  int chunk = 1;
+  bool all_one = true;
+  for (const Problem* p : ms) {
+    size_t s1, s2;
+    block_bytes(*p, &s1, &s2);
+    bS = std::max(bS, s1);
+    bI = std::max(bI, s2);
+    chunk = std::max(chunk, (p->nmu + p->gmres_blocks - 1) / std::max(p->gmres_blocks, 1));
+    all_one = all_one && p->gmres_blocks == p->nsub;
+  }
+  const Problem* p0 = ms[0];
+  bool res = p0->s32() && all_one &&
+             gmres_layout(NRT, kmax, chunk, sizeof(cd), bS, bI, true, nullptr) <= (size_t)p0->ctx->max_lds;
+  if (resident) *resident = res;
+  return gmres_layout(NRT, kmax, chunk, sizeof(cd), bS, bI, res, L);
+}
+
+// Whether every block of one GMRES launch over these instances can be
+// co-resident (hipSuccess) or not (an error code).
+template <class TS, int NRT>
+static hipError_t gmres_fits(const std::vector<const Problem*>& ms, int kmax, int blocks) {
+  size_t lds = gmres_plan<TS, NRT>(ms, kmax, nullptr, nullptr);
+  const Ctx* ctx = ms[0]->ctx;
+  if (lds > (size_t)ctx->max_lds) return hipErrorOutOfMemory;
+  const void* fn = (const void*)k_gmres<TS, NRT, Many>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_gmres<TS, NRT, One>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
   if (e != hipSuccess) return e;
-  return (int64_t)per_cu * p.ctx->num_cu >= p.gmres_blocks ? hipSuccess : hipErrorCooperativeLaunchTooLarge;
+  return (int64_t)per_cu * ctx->num_cu >= blocks ? hipSuccess : hipErrorCooperativeLaunchTooLarge;
 }
 
-// One launch for right-hand sides r0 .. r0 + nr - 1 (nr <= NRT).
+// One cooperative launch for right-hand sides r0 .. r0 + NRT - 1 of every
+// instance of launch group gi.
 template <class TS, int NRT>
-static hipError_t gmres_t(Problem& p, double tol, int kmax, int r0, int nr) {
-  hipStream_t st = p.ctx->stream;
-  const int nb = p.gmres_blocks;
-  GmresArgs a;
+static hipError_t gmres_t(const Target& t, int gi, double tol, int kmax, int r0) {
+  std::vector<const Problem*> ms;
+  gmres_members(t, gi, ms);
+  GmresLaunch L;
   bool resident = false;
-  size_t lds = gmres_plan<TS, NRT>(p, kmax, &resident, &a);
-  const RhsStride rs = p.rs();
-  a.rs = rs;
-  a.d = p.dvec + r0 * rs.nmu;
-  a.mu = p.mu + r0 * rs.nmu;
-  a.Abuf = p.Abuf + r0 * rs.sb;
-  a.Ybuf = p.Ybuf + r0 * rs.sb;
-  a.Cbuf = p.Cbuf + r0 * rs.c4;
-  a.w = p.wv + r0 * rs.nmu;
-  a.Q = p.Qk;
-  a.H = p.Hk;
-  a.part = p.part;
-  a.bar = p.bar;
-  a.flags = p.flags;
-  a.its_out = p.flags + 8 + r0;
-  a.scal = p.dscal + r0;
-  a.tol = tol;
-  a.kmax = kmax;
-  a.kstride = p.kmax_alloc;
-  a.chunk = (p.nmu + nb - 1) / nb;
-  a.nr = nr;
-  a.resident = resident ? 1 : 0;
-  for (int r = 0; r < NRMAX; ++r) a.its_dst[r] = r < nr ? p.its_dst[r0 + r] : nullptr;
-  hipError_t e = launch_fill(p.bar, BAR_WORDS * sizeof(unsigned), st);
+  size_t lds = gmres_plan<TS, NRT>(ms, kmax, &resident, &L);
+  L.tol = tol;
+  L.kmax = kmax;
+  L.r0 = r0;
+  L.resident = resident ? 1 : 0;
+  launch2(t, K_ONE, k_bar_reset<One>, k_bar_reset<Many>, 1, 256, 0);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  Geo2 g = p.geo();
-  Maps2 mp = p.maps();
-  const cf* Sbb = (const cf*)p.Sbb;
-  const TS* Sinv = (const TS*)p.Sinv;
-  const TS* Phi = (const TS*)p.Phi;
-  const cd* Kinv = p.Kinv;
-  void* args[] = {&g, &mp, &Sbb, &Sinv, &Phi, &Kinv, &a};
-  const void* fn = (const void*)k_gmres<TS, NRT>;
+  for (const Problem* p : ms) {
+    Problem* q = const_cast<Problem*>(p);
+    q->last_resident = resident;
+    q->last_nrt = NRT;
+  }
+  if (t.single()) {
+    One src = t.src1();
+    void* args[] = {&src, &L};
+    const void* fn = (const void*)k_gmres<TS, NRT, One>;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipLaunchCooperativeKernel(fn, dim3(t.one->gmres_blocks), dim3(256), args, lds, t.st);
+  }
+  Many src{t.devs, t.ggroups[gi].inst, t.first[K_GMRES]};
+  void* args[] = {&src, &L};
+  const void* fn = (const void*)k_gmres<TS, NRT, Many>;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  p.last_resident = resident;
-  p.last_nrt = NRT;
-  return hipLaunchCooperativeKernel(fn, dim3(nb), dim3(256), args, lds, st);
+  return hipLaunchCooperativeKernel(fn, dim3(t.ggroups[gi].total), dim3(256), args, lds, t.st);
 }
 
-// nr right-hand sides: the widest kernel (4, 2 or 1 right-hand sides per
-// launch) whose LDS layout and grid fit serves them in consecutive launches.
+// The group's right-hand sides: the widest kernel (4, 2 or 1 right-hand sides
+// per launch) whose LDS layout and grid fit serves them in consecutive launches.
 template <class TS>
-static hipError_t gmres_group(Problem& p, double tol, int kmax, int nr) {
+static hipError_t gmres_group(const Target& t, int gi, double tol, int kmax, int nr) {
+  std::vector<const Problem*> ms;
+  gmres_members(t, gi, ms);
+  const int blocks = t.single() ? t.one->gmres_blocks : t.ggroups[gi].total;
   int w = 1;
-  if (nr > 2 && gmres_fits<TS, 4>(p, kmax) == hipSuccess) w = 4;
-  else if (nr > 1 && gmres_fits<TS, 2>(p, kmax) == hipSuccess) w = 2;
+  if (nr > 2 && gmres_fits<TS, 4>(ms, kmax, blocks) == hipSuccess) w = 4;
+  else if (nr > 1 && gmres_fits<TS, 2>(ms, kmax, blocks) == hipSuccess) w = 2;
   else {
-    hipError_t e = gmres_fits<TS, 1>(p, kmax);
+    hipError_t e = gmres_fits<TS, 1>(ms, kmax, blocks);
     if (e != hipSuccess) return e;
   }
   for (int r0 = 0; r0 < nr; r0 += w) {
-    const int n = std::min(w, nr - r0);
-    hipError_t e = w == 4 ? gmres_t<TS, 4>(p, tol, kmax, r0, n)
-                 : w == 2 ? gmres_t<TS, 2>(p, tol, kmax, r0, n)
-                          : gmres_t<TS, 1>(p, tol, kmax, r0, 1);
+    hipError_t e = w == 4 ? gmres_t<TS, 4>(t, gi, tol, kmax, r0)
+                 : w == 2 ? gmres_t<TS, 2>(t, gi, tol, kmax, r0)
+                          : gmres_t<TS, 1>(t, gi, tol, kmax, r0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch_gmres(Problem& p, double tol, int kmax, int nr, hipStream_t) {
-  if (nr < 1 || nr > NRMAX) return hipErrorInvalidValue;
-  if (p.s32()) return gmres_group<cf>(p, tol, kmax, nr);
-  return gmres_group<cd>(p, tol, kmax, nr);
+hipError_t launch_gmres(const Target& t, double tol, int kmax) {
+  const int ng = t.single() ? 1 : (int)t.ggroups.size();
+  for (int gi = 0; gi < ng; ++gi) {
+    int nr = 0;
+    if (t.single()) nr = t.one->nr;
+    else
+      for (int i : t.ggroups[gi].members) nr = std::max(nr, t.probs[i]->nr);
+    if (nr <= 0) continue;
+    if (nr > NRMAX) return hipErrorInvalidValue;
+    hipError_t e = t.s32() ? gmres_group<cf>(t, gi, tol, kmax, nr) : gmres_group<cd>(t, gi, tol, kmax, nr);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Whether the one-RHS GMRES kernel fits this problem (the narrowest one).
 hipError_t gmres_check(const Problem& p, int kmax) {
-  if (p.s32()) return gmres_fits<cf, 1>(p, kmax);
-  return gmres_fits<cd, 1>(p, kmax);
+  std::vector<const Problem*> ms{&p};
+  if (p.s32()) return gmres_fits<cf, 1>(ms, kmax, p.gmres_blocks);
+  return gmres_fits<cd, 1>(ms, kmax, p.gmres_blocks);
 }
 
-hipError_t launch_recover_coarse(const Problem& p, int nr, hipStream_t st) {
-  if (p.s32())
-    hipLaunchKernelGGL(k_frct<cf>, dim3((p.nsub * 4 + 3) / 4, nr), dim3(256), 0, st, p.geo(), p.maps(),
-                       p.rs(), (const cf*)p.Phi, p.mu, p.Cbuf);
-  else
-    hipLaunchKernelGGL(k_frct<cd>, dim3((p.nsub * 4 + 3) / 4, nr), dim3(256), 0, st, p.geo(), p.maps(),
-                       p.rs(), (const cd*)p.Phi, p.mu, p.Cbuf);
-  hipLaunchKernelGGL(k_corner_sum, dim3((p.nC + 127) / 128, nr), dim3(128), 0, st, p.geo(), p.maps(),
-                     p.rs(), p.fcs, p.Cbuf, p.ymin);
-  if (p.nC > 0)
-    hipLaunchKernelGGL(k_dense_mv, dim3(p.nC, nr), dim3(64), 0, st, p.nC, p.rs().nc, p.Kinv, p.ymin,
-                       p.u0);
+// Co-resident blocks of a GMRES launch of width NRMAX whose blocks hold at most
+// `chunk` multipliers (staged layout), for sizing batch launch groups.
+int gmres_capacity(const Problem& p, int kmax, int chunk, int width) {
+  size_t bS, bI;
+  block_bytes(p, &bS, &bI);
+  size_t lds = gmres_layout(width, kmax, chunk, sizeof(cd), bS, bI, false, nullptr);
+  if (lds > (size_t)p.ctx->max_lds) return 0;
+  const void* fn = p.s32() ? (width == 4 ? (const void*)k_gmres<cf, 4, Many>
+                                         : width == 2 ? (const void*)k_gmres<cf, 2, Many> : (const void*)k_gmres<cf, 1, Many>)
+                           : (width == 4 ? (const void*)k_gmres<cd, 4, Many>
+                                         : width == 2 ? (const void*)k_gmres<cd, 2, Many> : (const void*)k_gmres<cd, 1, Many>);
+  int per_cu = 0;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+  if (e != hipSuccess || per_cu < 1) return 0;
+  return per_cu * p.ctx->num_cu;
+}
+
+hipError_t launch_recover_coarse(const Target& t) {
+  if (t.s32()) launch2(t, K_SUB, k_frct<cf, One>, k_frct<cf, Many>, NRMAX, 256, 0);
+  else launch2(t, K_SUB, k_frct<cd, One>, k_frct<cd, Many>, NRMAX, 256, 0);
+  launch2(t, K_NC128, k_corner_sum<One>, k_corner_sum<Many>, NRMAX, 128, 0);
+  launch2(t, K_NC, k_dense_mv<One>, k_dense_mv<Many>, NRMAX, 64, 0, (int)V_YMIN);
   return hipGetLastError();
 }
 
-hipError_t launch_assemble_solution(const Problem& p, cd* x, int conj_out, int nr, hipStream_t st) {
-  int n = p.nmu + p.nC;
-  hipLaunchKernelGGL(k_assemble, dim3((n + 255) / 256, nr), dim3(256), 0, st, p.geo(), p.maps(), p.rs(),
-                     p.Ubuf, p.u0, x, conj_out);
+hipError_t launch_assemble_solution(const Target& t, int x, int conj_out) {
+  launch2(t, K_ASM256, k_assemble<One>, k_assemble<Many>, NRMAX, 256, 0, x, conj_out);
   return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@ EXPORTS = [
     "sfdp_problem_sizes", "sfdp_problem_destroy", "sfdp_set_beta", "sfdp_solve_range_space",
     "sfdp_apply_schur_inv", "sfdp_feti_solve", "sfdp_apply_operator", "sfdp_kkt_residual",
     "sfdp_inspect", "sfdp_interface_apply", "sfdp_timing_enable", "sfdp_kernel_times",
+    "sfdp_batch_create", "sfdp_batch_destroy", "sfdp_batch_sizes", "sfdp_batch_set_beta",
+    "sfdp_batch_solve_range_space",
 ]
 
 
@@ -92,10 +94,19 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_interface_apply.argtypes = [P, ctypes.c_char, VP, VP]
     lib.sfdp_timing_enable.argtypes = [P, I]
     lib.sfdp_kernel_times.argtypes = [P, ctypes.POINTER(Timing)]
+    lib.sfdp_batch_create.argtypes = [P, I, ctypes.POINTER(I), I, I, ctypes.POINTER(P)]
+    lib.sfdp_batch_destroy.argtypes = [P]
+    lib.sfdp_batch_destroy.restype = None
+    lib.sfdp_batch_sizes.argtypes = [P, I, ctypes.POINTER(Sizes)]
+    lib.sfdp_batch_set_beta.argtypes = [P, ctypes.POINTER(D)]
+    VPP = ctypes.POINTER(ctypes.c_void_p)
+    lib.sfdp_batch_solve_range_space.argtypes = [P, ctypes.POINTER(I), VPP, VPP, VPP, VPP, VPP,
+                                                 ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     for name in ("sfdp_ctx_create", "sfdp_problem_create", "sfdp_problem_sizes", "sfdp_set_beta",
                  "sfdp_solve_range_space", "sfdp_apply_schur_inv", "sfdp_feti_solve",
                  "sfdp_apply_operator", "sfdp_kkt_residual", "sfdp_inspect", "sfdp_interface_apply",
-                 "sfdp_timing_enable", "sfdp_kernel_times"):
+                 "sfdp_timing_enable", "sfdp_kernel_times", "sfdp_batch_create", "sfdp_batch_sizes",
+                 "sfdp_batch_set_beta", "sfdp_batch_solve_range_space"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -246,3 +257,69 @@ class Problem:
         t = Timing()
         _check(_lib.sfdp_kernel_times(self._h, ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in Timing._fields_}
+
+
+class Batch:
+    """Independent 2D instances (n_elem[i] cells per side, one beta each) whose
+    set-up and solves run over all instances in one launch per kernel."""
+
+    def __init__(self, ctx: Context, n_elem, sub_elem: int, precision: int = SFDP_FP64):
+        self.n_elem = [int(v) for v in n_elem]
+        arr = (ctypes.c_int * len(self.n_elem))(*self.n_elem)
+        h = ctypes.c_void_p()
+        _check(_lib.sfdp_batch_create(ctx._h, len(self.n_elem), arr, sub_elem, precision, ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.sizes = []
+        for i in range(len(self.n_elem)):
+            sz = Sizes()
+            _check(_lib.sfdp_batch_sizes(h, i, ctypes.byref(sz)))
+            self.sizes.append({f: getattr(sz, f) for f, _ in Sizes._fields_})
+
+    def close(self):
+        if self._h:
+            _lib.sfdp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_beta(self, betas):
+        arr = (ctypes.c_double * len(self.n_elem))(*[float(b) for b in betas])
+        _check(_lib.sfdp_batch_set_beta(self._h, arr))
+
+    def solve_range_space(self, ybars, ycs=None, **opts):
+        """ybars[i]: (nrhs_i, n_free_i) or (n_free_i,) CUDA tensor, or None for
+        no work; returns lists y, u, lam (like ybars), infos per instance, status."""
+        import torch
+        n = len(self.n_elem)
+        nr = []
+        outs = []
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        P = lambda vals: (ctypes.c_void_p * n)(*vals)
+        for i in range(n):
+            yb = ybars[i]
+            if yb is None:
+                nr.append(0)
+                outs.append((None, None, None))
+                continue
+            if not yb.is_cuda or not yb.is_contiguous():
+                raise ValueError("arrays must be contiguous CUDA tensors")
+            nr.append(1 if yb.dim() == 1 else yb.shape[0])
+            outs.append(tuple(torch.empty_like(yb) for _ in range(3)))
+        yc_p = P([ptr(ycs[i]) if ycs is not None and ycs[i] is not None else None for i in range(n)])
+        infos = (Info * max(sum(nr), 1))()
+        o = _opts(**opts)
+        st = _lib.sfdp_batch_solve_range_space(
+            self._h, (ctypes.c_int * n)(*nr), P([ptr(b) for b in ybars]), yc_p,
+            P([ptr(t[0]) for t in outs]), P([ptr(t[1]) for t in outs]), P([ptr(t[2]) for t in outs]),
+            ctypes.byref(o), infos)
+        _check(st, allow_noconv=True)
+        res, k = [], 0
+        for i in range(n):
+            res.append([infos[k + j].as_dict() for j in range(nr[i])])
+            k += nr[i]
+        return [t[0] for t in outs], [t[1] for t in outs], [t[2] for t in outs], res, st

@@ -1,0 +1,118 @@
+"""Batches of independent instances (uneven sizes, one beta each): every step
+of the set-up and of the solve runs over all instances in one launch per
+kernel, the interface GMRES of all instances inside shared persistent launches
+with a grid barrier per instance.  Each result must be that of solving the
+instance on its own (1e-12 relative: the same arithmetic in a different
+launch), and meet the KKT gate against the oracle.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fem, kkt, solve  # noqa: E402
+from paper_1312_5653_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def sf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1312_5653_amd import sfdp
+    ctx = sfdp.Context(0)
+    yield sfdp, ctx
+    ctx.close()
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _case(N, seed, nrhs):
+    ys, ycs = [], []
+    for r in range(nrhs):
+        if (seed + r) % 3 == 2:
+            y, yc = W.thermal_target(N)
+        else:
+            y, yc = W.sine_target(2, N, *W.modes_for("four2d", seed * 7 + r))
+        ys.append(y)
+        ycs.append(yc)
+    return np.stack(ys), np.stack(ycs)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_matches_single_instances(sf, prec):
+    sfdp, ctx = sf
+    m = 8
+    Ns = [16, 48, 24, 64, 32, 16]
+    betas = [1e-2, 1e-4, 3e-6, 1e-3, 1e-5, 1e-1]
+    nrhs = [1, 2, 0, 3, 1, 4]
+    tol = 1e-10 if prec == 0 else 1e-8
+    data = [_case(N, i, k) if k else (None, None) for i, (N, k) in enumerate(zip(Ns, nrhs))]
+    b = sfdp.Batch(ctx, Ns, m, prec)
+    b.set_beta(betas)
+    ys, us, ls, infos, st = b.solve_range_space(
+        [_t(d[0]) if d[0] is not None else None for d in data],
+        [_t(d[1]) if d[1] is not None else None for d in data], tol_kkt=tol)
+    assert st == 0, infos
+    for i, (N, beta, k) in enumerate(zip(Ns, betas, nrhs)):
+        if k == 0:
+            assert ys[i] is None and infos[i] == []
+            continue
+        ybar, yc = data[i]
+        p = sfdp.Problem(ctx, 2, N, m, prec)
+        p.set_beta(beta)
+        y1, u1, l1, info1, st1 = p.solve_range_space(_t(ybar), _t(yc), tol_kkt=tol)
+        assert st1 == 0
+        A = fem.assemble(fem.Mesh(2, N))
+        for r in range(k):
+            for a, c in ((ys[i][r], y1[r]), (us[i][r], u1[r]), (ls[i][r], l1[r])):
+                assert _rel(a.cpu().numpy(), c.cpu().numpy()) < 1e-12, (i, r)
+            assert infos[i][r]["krylov_its"] == info1[r]["krylov_its"], (i, r)
+            rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar[r], yc[r], ys[i][r].cpu().numpy(),
+                              us[i][r].cpu().numpy(), ls[i][r].cpu().numpy())
+            ref = solve.range_space_two_factor(A["K"], A["M"], A["Kc"], beta, ybar[r], yc[r], paper_y=False)
+            rho_ref = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar[r], yc[r], ref["y"], ref["u"], ref["lam"])
+            assert rho <= max(tol, 2 * rho_ref), (i, r, rho, rho_ref)
+        p.close()
+    b.close()
+
+
+def test_batch_of_many_instances_in_several_launch_groups(sf):
+    """40 instances of 256^2 cells (8 x 8 subdomains of 32^2): more GMRES blocks
+    than fit on the device at once, so the Krylov solves run in several
+    consecutive persistent launches; spot-check instances against single solves."""
+    sfdp, ctx = sf
+    n, N, m = 40, 256, 32
+    rng = np.random.default_rng(5)
+    betas = list(10.0 ** rng.uniform(-6, -1, n))
+    ybars = [W.sine_target(2, N, *W.modes_for("sixteen2d", 100 + i))[0] for i in range(n)]
+    b = sfdp.Batch(ctx, [N] * n, m, sfdp.SFDP_MIXED)
+    b.set_beta(betas)
+    ys, us, ls, infos, st = b.solve_range_space([_t(y) for y in ybars], None, tol_kkt=1e-8)
+    assert st == 0
+    # a lone solve gives the instance more GMRES blocks (other summation orders),
+    # so batch and lone results agree to the solve accuracy, not to rounding
+    A = fem.assemble(fem.Mesh(2, N))
+    z = np.zeros(A["Kc"].shape[1])
+    for i in (0, 17, 39):
+        p = sfdp.Problem(ctx, 2, N, m, sfdp.SFDP_MIXED)
+        p.set_beta(betas[i])
+        y1, u1, l1, info1, st1 = p.solve_range_space(_t(ybars[i]), None, tol_kkt=1e-8)
+        ref = solve.range_space_two_factor(A["K"], A["M"], A["Kc"], betas[i], ybars[i], None, paper_y=False)
+        yb, lb = ys[i].cpu().numpy(), ls[i].cpu().numpy()
+        rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], betas[i], ybars[i], z, yb, us[i].cpu().numpy(), lb)
+        assert rho <= 1e-8, (i, rho)
+        assert _rel(lb, ref["lam"]) < 1e-6 and _rel(yb, ref["y"]) < 1e-6, i
+        assert _rel(lb, l1.cpu().numpy()) < 1e-6 and _rel(yb, y1.cpu().numpy()) < 1e-6, i
+        p.close()
+    # every instance meets the gate by the GPU's own FP64 residual
+    assert all(inf[0]["rel_kkt"] <= 1e-8 for inf in infos)
+    b.close()
