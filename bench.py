@@ -160,6 +160,61 @@ def cpu_baseline(N, m, beta, ybar, budget_s=15.0):
             "factor_s": t_factor, "solve_s": t_solve, "host_threads": os.cpu_count()}
 
 
+def run_instances(sfdp, torch, ctx, count, seed, tol_kkt):
+    """Batched instances: `count` independent 2D instances, N_j in 64..256 (log-uniform,
+    multiple of 32), subdomains of 32x32 cells, beta_j = 10^U[-6,-1], one 16-mode sine target
+    each; every instance has a new beta, so a pass is set-up + solve (end to end)."""
+    from paper_1312_5653_amd import workloads
+    inst = workloads.c4_instances(count, seed)
+    Ns = [d["N"] for d in inst]
+    betas = [d["beta"] for d in inst]
+    ybars = [torch.tensor(workloads.sine_target(2, d["N"], *workloads.modes_for("sixteen2d", d["seed"]))[0],
+                          device="cuda:0") for d in inst]
+    b = sfdp.Batch(ctx, Ns, 32, sfdp.SFDP_MIXED)
+    b.set_beta(betas)
+    b.solve_range_space(ybars, None, tol_kkt=tol_kkt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.set_beta(betas)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, _, _, infos, st = b.solve_range_space(ybars, None, tol_kkt=tol_kkt)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    b.close()
+    if st != 0:
+        raise RuntimeError("batched instances did not converge")
+    rho = max(i[0]["rel_kkt"] for i in infos)
+    return {"instances": count, "seed": seed, "subdomains": sum((N // 32) ** 2 for N in Ns),
+            "dofs": sum((N - 1) ** 2 for N in Ns), "setup_ms": (t1 - t0) * 1e3, "solve_ms": (t2 - t1) * 1e3,
+            "solves_per_s_end_to_end": count / (t2 - t0), "solves_per_s_solve_phase": count / (t2 - t1),
+            "max_rel_kkt": rho, "krylov_its_per_solve": statistics.mean(i[0]["krylov_total"] for i in infos),
+            "precision": "mixed"}
+
+
+def cpu_instances(count, seed, budget_s=10.0):
+    """The oracle on the batched-instance workload: SuperLU factor of Z plus the two-factor
+    solve, instance after instance on one core, for as many instances as fit the budget."""
+    import scipy.sparse.linalg as spla
+    from oracle import fem, solve
+    from paper_1312_5653_amd import workloads
+    inst = workloads.c4_instances(count, seed)
+    t_start = time.perf_counter()
+    done = 0
+    for d in inst:
+        A = fem.assemble(fem.Mesh(2, d["N"]))
+        ybar = workloads.sine_target(2, d["N"], *workloads.modes_for("sixteen2d", d["seed"]))[0]
+        lu = spla.splu(solve.complex_factor(A["K"], A["M"], d["beta"]))
+        solve.range_space_two_factor(A["K"], A["M"], A["Kc"], d["beta"], ybar, None, lu=lu, paper_y=False)
+        done += 1
+        if time.perf_counter() - t_start > budget_s:
+            break
+    el = time.perf_counter() - t_start
+    return {"value": done / el, "unit": "end-to-end solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of the {count} instances (assembly, SuperLU factor of Z and the "
+                      f"two-factor solve each), one core, {el:.1f} s"}
+
+
 def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup, tol_kkt, tol_inner,
                   batch, max_krylov=0):
     p = sfdp.Problem(ctx, 2, N, m, precision)
@@ -218,6 +273,8 @@ def main():
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB device buffer once (a plain copy of known size that "
                          "calibrates the HBM byte counters of a profiler run)")
+    ap.add_argument("--instances", type=int, default=256,
+                    help="batched-instance workload size (0 skips it)")
     ap.add_argument("--max-krylov", type=int, default=0,
                     help="GMRES iteration cap per FETI-DP solve (0: library default)")
     ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB"),
@@ -326,6 +383,10 @@ def main():
         out[k] = {"batch": o["batch"], "solves_per_s": o["solves_per_s"], "ms_per_step": o["ms_per_step"],
                   "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"], "max_rel_kkt": o["max_rel_kkt"],
                   "krylov_its_per_solve": o["krylov_per_solve"], "setup_ms": o["setup_ms"]}
+    if args.instances > 0 and not args.headline_only:
+        out["instances_batch"] = run_instances(sfdp, torch, ctx, args.instances, 0, tol_kkt)
+        if not args.no_cpu:
+            out["instances_batch"]["cpu_baseline"] = cpu_instances(args.instances, 0)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, m, beta, ybar[0])
     ctx.close()

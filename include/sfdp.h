@@ -69,7 +69,8 @@ typedef enum {
   SFDP_E_NOMEM = -2,
   SFDP_E_NOCONV = -3,
   SFDP_E_DEVICE = -4,
-  SFDP_E_STATE = -5
+  SFDP_E_STATE = -5,
+  SFDP_E_ADMIT = -6   /* a served request can never fit the context's memory budget */
 } sfdp_status;
 
 /* Arithmetic of the subdomain factors and of the interface operator.
@@ -240,6 +241,58 @@ sfdp_status sfdp_batch_set_beta(sfdp_batch* b, const double* beta);
 sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const double* const* ybar,
                                          const double* const* yc, double* const* y, double* const* u,
                                          double* const* lam, const sfdp_opts* opts, sfdp_info* info);
+
+/* ---- Serving: continuous batching of range-space requests ----
+ *
+ * A server owns a worker thread that uses the context's stream (the caller
+ * must not use that context from other threads meanwhile).  Requests (one
+ * mesh, one beta, nrhs targets) are admitted while the context's memory
+ * budget allows: a request joins the resident instance of its (mesh, beta)
+ * or a new instance is created and factored (new instances admitted together
+ * are factored in one set-up sequence); idle instances are evicted, least
+ * recently used first, when memory is short, and a request that does not fit
+ * waits until memory frees.  Every instance serves up to four targets at a
+ * time in slots; each worker tick gives every occupied slot of every resident
+ * instance one KKT residual and, if not converged, one two-factor refinement
+ * step, all instances in one launch per kernel (the batch path above).
+ * Targets that finish free their slots, and waiting targets take free slots
+ * at the next tick, so requests that arrive while others run join them on
+ * the device.  A result does not depend on what else is in flight (up to the
+ * rounding of multiply-add contraction, 1e-12 relative). */
+typedef struct sfdp_server sfdp_server;
+typedef struct {
+  int dim;           /* 2 */
+  int n_elem;        /* cells per side */
+  int sub_elem;      /* cells per subdomain side */
+  double beta;
+  int nrhs;          /* targets */
+  const double* ybar;  /* device, n_free x nrhs (as sfdp_solve_range_space) */
+  const double* yc;    /* device, n_bdry x nrhs, or NULL for zero */
+  double *y, *u, *lam; /* device outputs, n_free x nrhs; all arrays stay valid until polled */
+} sfdp_request;
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t setups;      /* instances factored */
+  int64_t evictions;   /* instances evicted for memory */
+  int64_t ticks;       /* worker steps */
+  int64_t resident;    /* instances resident now */
+  int64_t device_bytes;/* device memory held by the context */
+  double mean_ms, p50_ms, p99_ms;  /* latency (submit to result) of completed requests */
+} sfdp_server_info;
+/* opts as for sfdp_solve_range_space (batch is not used: slots hold up to 4). */
+sfdp_status sfdp_server_create(sfdp_ctx* ctx, sfdp_precision prec, const sfdp_opts* opts,
+                               sfdp_server** out);
+/* Queue a request (returns at once) and its ticket. */
+sfdp_status sfdp_server_submit(sfdp_server* s, const sfdp_request* req, uint64_t* ticket);
+/* SFDP_E_STATE while pending when wait = 0; otherwise waits.  On completion
+ * returns the request's status (SFDP_OK, SFDP_E_NOCONV, SFDP_E_ADMIT when it
+ * can never fit the budget, SFDP_E_DEVICE), fills info[nrhs] and the latency
+ * (milliseconds from submit to result) if given, and releases the ticket. */
+sfdp_status sfdp_server_poll(sfdp_server* s, uint64_t ticket, int wait, sfdp_info* info,
+                             double* latency_ms);
+sfdp_status sfdp_server_stats(sfdp_server* s, sfdp_server_info* out);
+/* Finishes every admitted and pending request, then stops. */
+void sfdp_server_destroy(sfdp_server* s);
 
 /* Kernel timing with HIP events recorded on the context's stream around the
  * launches of the two hot kernels of every FETI-DP solve: the persistent

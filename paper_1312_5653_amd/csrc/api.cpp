@@ -2,7 +2,12 @@
 // sequencing, the FETI-DP driver and the range-space refinement loop
 // (Sec. 3.1 Schur system with the Sec. 4 complex factorization).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -257,33 +262,84 @@ sfdp_status alloc_rs(Problem& p) {
 sfdp_status create_problem(Ctx* ctx, int dim, int n_elem, int sub_elem, sfdp_precision prec, Problem** out);
 void destroy_problem(Problem* p);
 
-// Set-up scratch of one problem (FP64), allocated for sfdp_set_beta only.
-sfdp_status alloc_setup(Problem& p) {
+// Factor arrays of one problem in its storage precision (kept across set-ups:
+// their sizes depend on the mesh and the precision only).
+sfdp_status alloc_factors(Problem& p) {
+  if (p.G) return SFDP_OK;
   const int ml = p.ml, ND = p.ND, nsub = p.nsub;
   size_t es = elem_size(p);
-  size_t nG = (size_t)nsub * ml * ml * ml, nS = (size_t)nsub * ND * ND, nP = (size_t)nsub * ND * 4;
+  size_t nG = (size_t)nsub * ml * ml * ml, nP = (size_t)nsub * ND * 4;
   const size_t nPK = (size_t)nsub * ND * (ND + 1) / 2;
   sfdp_status s;
   if ((s = dalloc(p, &p.G, g_size(p) * nG)) || (s = dalloc(p, &p.Sinv, es * nPK)) ||
       (s = dalloc(p, &p.Sbb, sizeof(cf) * nPK)) || (s = dalloc(p, &p.Phi, es * nP)) ||
       (s = dalloc(p, (void**)&p.Kinv, sizeof(cd) * std::max(p.nC * p.nC, 1))) ||
-      (s = dalloc(p, (void**)&p.Kcc, sizeof(cd) * std::max(p.nC * p.nC, 1))))
+      (s = dalloc(p, (void**)&p.Kcc, sizeof(cd) * std::max(p.nC * p.nC, 1)))) {
+    free_factors(p);
     return s;
-  size_t nF = (size_t)nsub * ml * ml * 4, nScr = (size_t)nsub * ml * ml * 32;
-  size_t nK = (size_t)std::max(p.nC * p.nC, 1);
-  if (hipMalloc(&p.G64, sizeof(cd) * nG) || hipMalloc(&p.Sinv64, sizeof(cd) * nS) ||
-      hipMalloc(&p.S64, sizeof(cd) * nS) || hipMalloc(&p.Phi64, sizeof(cd) * nP) ||
-      hipMalloc(&p.PhiFull, sizeof(cd) * nF) || hipMalloc(&p.scr, sizeof(cd) * nScr) ||
-      hipMalloc(&p.Zs, sizeof(cd) * nsub * 16) || hipMalloc(&p.Kwork, sizeof(cd) * nK))
-    return fail(SFDP_E_NOMEM, "setup scratch allocation failed");
+  }
+  return SFDP_OK;
+}
+
+// FP64 set-up scratch of one problem, as element counts of G64, Sinv64, S64,
+// Phi64, PhiFull, scr, Zs, Kwork.
+void setup_counts(size_t nsub, size_t ml, size_t ND, int nC, size_t c[8]) {
+  const size_t nK = (size_t)std::max(nC * nC, 1);
+  c[0] = nsub * ml * ml * ml;
+  c[1] = nsub * ND * ND;
+  c[2] = nsub * ND * ND;
+  c[3] = nsub * ND * 4;
+  c[4] = nsub * ml * ml * 4;
+  c[5] = nsub * ml * ml * 32;
+  c[6] = nsub * 16;
+  c[7] = nK;
+}
+void setup_counts(const Problem& p, size_t c[8]) { setup_counts(p.nsub, p.ml, p.ND, p.nC, c); }
+size_t pad256(size_t b) { return (b + 255) & ~(size_t)255; }
+// Bytes of the pool share of one problem of this mesh.
+size_t setup_bytes(int n_elem, int sub_elem) {
+  const size_t P = n_elem / sub_elem;
+  size_t c[8], b = 0;
+  setup_counts(P * P, sub_elem + 1, ((4 * (sub_elem - 1) + 31) / 32) * 32, (int)((P - 1) * (P - 1)), c);
+  for (int k = 0; k < 8; ++k) b += pad256(c[k] * sizeof(cd));
+  return b;
+}
+
+// Carve every problem's set-up scratch out of the context's pool (grown when
+// too small; the stream must be idle).
+sfdp_status alloc_setup(Ctx* ctx, const std::vector<Problem*>& ps) {
+  size_t total = 0;
+  for (Problem* p : ps) {
+    size_t c[8];
+    setup_counts(*p, c);
+    for (size_t k = 0; k < 8; ++k) total += pad256(c[k] * sizeof(cd));
+  }
+  if (total > ctx->pool_bytes) {
+    if (ctx->pool) {
+      hipFree(ctx->pool);
+      ctx->used -= std::min(ctx->used, ctx->pool_bytes);
+      ctx->pool = nullptr;
+      ctx->pool_bytes = 0;
+    }
+    if (ctx->budget && ctx->used + total > ctx->budget) return fail(SFDP_E_NOMEM, "memory budget exceeded");
+    if (hipMalloc(&ctx->pool, total) != hipSuccess) return fail(SFDP_E_NOMEM, "setup scratch allocation failed");
+    ctx->pool_bytes = total;
+    ctx->used += total;
+  }
+  char* q = (char*)ctx->pool;
+  for (Problem* p : ps) {
+    size_t c[8];
+    setup_counts(*p, c);
+    cd** dst[8] = {&p->G64, &p->Sinv64, &p->S64, &p->Phi64, &p->PhiFull, &p->scr, &p->Zs, &p->Kwork};
+    for (int k = 0; k < 8; ++k) {
+      *dst[k] = (cd*)q;
+      q += pad256(c[k] * sizeof(cd));
+    }
+  }
   return SFDP_OK;
 }
 void free_setup(Problem& p) {
-  cd** arr[] = {&p.G64, &p.Sinv64, &p.S64, &p.Phi64, &p.PhiFull, &p.scr, &p.Zs, &p.Kwork};
-  for (cd** a : arr) {
-    if (*a) hipFree(*a);
-    *a = nullptr;
-  }
+  p.G64 = p.Sinv64 = p.S64 = p.Phi64 = p.PhiFull = p.scr = p.Zs = p.Kwork = nullptr;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -459,7 +515,7 @@ sfdp_status feti_run(const Target& t, Problem* timed, int fsel, int conj, int xs
 constexpr unsigned IDENTITY_MAP = 0x03020100u;
 
 // Range-space solves of every problem's group: nr targets in slots 0..nr-1,
-// caller arrays in the problem's ybar, yc, y, u, lam (stride n_free / n_bdry).
+// caller arrays in the problem's slots.
 // All unfinished targets take each two-factor step together; each stops on
 // its own test.  info[i] has ps[i]->nr entries.  M is the batch (null for a
 // single problem); dg / hg hold one Gathered record per problem.
@@ -474,6 +530,7 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
   for (size_t i = 0; i < n; ++i) {
     ng[i] = ps[i]->nr;
     ps[i]->map = IDENTITY_MAP;
+    ps[i]->init = (1u << ng[i]) - 1u;
     loc[i].assign(ng[i], sfdp_info{});
     bad[i].assign(ng[i], 0);
   }
@@ -484,6 +541,7 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
   }
   HIPCHK(launch_group_init(t));
   HIPCHK(launch_fill_flags(t, 0, FLAG_WORDS));
+  for (Problem* p : ps) p->init = 0;
   for (int step = 0;; ++step) {
     HIPCHK(launch_kkt_residual(t));
     HIPCHK(launch_gather(t, dg));
@@ -620,15 +678,16 @@ void destroy_problem(Problem* p) {
   delete p;
 }
 
-// Factor one or several problems for their betas (one set-up sequence).
+// Factor one or several problems for their betas (one set-up sequence; the
+// stream must be idle).
 sfdp_status setup_run(const Target& t, const std::vector<Problem*>& ps, Multi* M) {
   for (Problem* p : ps) {
-    sfdp_status s = alloc_setup(*p);
-    if (s) {
-      for (Problem* q : ps) free_setup(*q);
-      return s;
-    }
+    sfdp_status s = alloc_factors(*p);
+    if (s) return s;
+    p->factored = false;
   }
+  sfdp_status s0 = alloc_setup(ps[0]->ctx, ps);
+  if (s0) return s0;
   if (M) {
     sfdp_status s = multi_upload(*M);
     if (s) return s;
@@ -707,7 +766,15 @@ sfdp_status sfdp_ctx_create(int device, size_t mem_budget_bytes, void* stream, s
   return SFDP_OK;
 }
 
-void sfdp_ctx_destroy(sfdp_ctx* c) { delete c; }
+void sfdp_ctx_destroy(sfdp_ctx* c) {
+  if (!c) return;
+  if (c->pool) {
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    hipFree(c->pool);
+  }
+  delete c;
+}
 
 sfdp_status sfdp_problem_create(sfdp_ctx* ctx, int dim, int n_elem, int sub_elem, sfdp_precision prec,
                                 sfdp_problem** out) {
@@ -740,7 +807,7 @@ sfdp_status sfdp_set_beta(sfdp_problem* p, double beta) {
   if (!p) return fail(SFDP_E_INVALID, "null problem");
   if (!(beta > 0) || !std::isfinite(beta)) return fail(SFDP_E_INVALID, "beta must be positive and finite");
   HIPCHK(hipSetDevice(p->ctx->device));
-  free_factors(*p);
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
   p->beta = beta;
   p->alpha = 1.0 / std::sqrt(beta);
   std::vector<Problem*> ps{p};
@@ -809,11 +876,8 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
     const int nr = std::min(NRMAX, nrhs - r0);
     p->nr = nr;
     p->map = IDENTITY_MAP;
-    p->ybar = ybar + r0 * n;
-    p->yc = yc ? yc + r0 * p->n_bdry : nullptr;
-    p->y = (double*)y + r0 * n;
-    p->u = (double*)u + r0 * n;
-    p->lam = (double*)lam + r0 * n;
+    p->set_slots(nr, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, (double*)y + r0 * n,
+                 (double*)u + r0 * n, (double*)lam + r0 * n);
     hipError_t e = launch_kkt_residual(t);
     s = e == hipSuccess ? gather_one(p, g) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
     p->nr = 0;
@@ -845,11 +909,8 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
   for (int r0 = 0; r0 < nrhs; r0 += bsz) {
     const int ng = std::min(bsz, nrhs - r0);
     p->nr = ng;
-    p->ybar = ybar + r0 * n;
-    p->yc = yc ? yc + r0 * p->n_bdry : nullptr;
-    p->y = y + r0 * n;
-    p->u = u + r0 * n;
-    p->lam = lam + r0 * n;
+    p->set_slots(ng, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, y + r0 * n, u + r0 * n,
+                 lam + r0 * n);
     std::vector<sfdp_info*> inf{info ? info + r0 : nullptr};
     s = range_space_run(t, ps, nullptr, dg, &hg, tk, ti, mo, kmax, inf);
     p->nr = 0;
@@ -964,7 +1025,6 @@ sfdp_status sfdp_batch_set_beta(sfdp_batch* b, const double* beta) {
   HIPCHK(hipStreamSynchronize(b->ctx->stream));
   for (size_t i = 0; i < b->probs.size(); ++i) {
     Problem* p = b->probs[i];
-    free_factors(*p);
     p->beta = beta[i];
     p->alpha = 1.0 / std::sqrt(beta[i]);
   }
@@ -1007,11 +1067,8 @@ sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const d
       w = std::max(w, ng);
       if (ng == 0) continue;
       const size_t nf = p->n_free;
-      p->ybar = ybar[i] + r0 * nf;
-      p->yc = yc && yc[i] ? yc[i] + r0 * p->n_bdry : nullptr;
-      p->y = y[i] + r0 * nf;
-      p->u = u[i] + r0 * nf;
-      p->lam = lam[i] + r0 * nf;
+      p->set_slots(ng, ybar[i] + r0 * nf, yc && yc[i] ? yc[i] + r0 * p->n_bdry : nullptr, y[i] + r0 * nf,
+                   u[i] + r0 * nf, lam[i] + r0 * nf);
       inf[i] = info ? info + ioff[i] + r0 : nullptr;
     }
     sfdp_status s = multi_groups(b->M, kmax, w == 1 ? 1 : w == 2 ? 2 : 4, b->gmap, b->gcap);
@@ -1143,6 +1200,545 @@ sfdp_status sfdp_interface_apply(sfdp_problem* p, char which, const double* x, d
   if (which != 'F' && which != 'P') return fail(SFDP_E_INVALID, "which must be 'F', 'P' or 'D'");
   HIPCHK(launch_interface_apply(*p, which, (const cd*)x, (cd*)y, st));
   return SFDP_OK;
+}
+
+}  // extern "C"
+
+// ---- serving: continuous batching of range-space requests ----
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct SReq;
+struct SInst;
+
+struct SReq {
+  uint64_t id = 0;
+  int n_elem = 0, sub_elem = 0, nrhs = 0;
+  double beta = 0;
+  const double *ybar = nullptr, *yc = nullptr;
+  double *y = nullptr, *u = nullptr, *lam = nullptr;
+  int next = 0;  // next target to place in a slot
+  int done = 0;  // targets finished
+  std::vector<sfdp_info> info;
+  sfdp_status status = SFDP_OK;
+  double t_submit = 0, t_done = 0;
+  bool complete = false;
+  SInst* inst = nullptr;
+  std::string why;  // reason of a refusal or failure
+};
+
+struct SSlot {
+  SReq* req = nullptr;
+  int k = -1;    // target index within the request
+  int bad = 0;   // 1 non-finite, 2 outer limit
+  sfdp_info info{};
+};
+
+struct SInst {
+  Problem* p = nullptr;
+  int n_elem = 0, sub_elem = 0;
+  double beta = 0;
+  std::deque<SReq*> queue;  // admitted requests with targets left to place
+  SSlot slot[NRMAX];
+  double last_used = 0;
+  bool busy() const {
+    if (!queue.empty()) return true;
+    for (const SSlot& s : slot)
+      if (s.req) return true;
+    return false;
+  }
+};
+
+}  // namespace
+
+struct sfdp_server {
+  Ctx* ctx = nullptr;
+  sfdp_precision prec = SFDP_MIXED;
+  double tol_kkt = 0, tol_inner = 0;
+  int max_outer = 0, kmax = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<SReq*> pending;              // submitted, not admitted
+  std::map<uint64_t, SReq*> reqs;         // every request until polled after completion
+  std::vector<SInst*> insts;              // resident instances
+  std::vector<double> lat;                // completed latencies (ms)
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::thread worker;
+  Multi M;
+  int* gmap = nullptr;
+  size_t gcap = 0;
+  std::vector<Problem*> active_set;       // instances of the current target
+  Gathered* dg = nullptr;
+  Gathered* hg = nullptr;
+  size_t gath_cap = 0;
+  int64_t n_submit = 0, n_complete = 0, n_failed = 0, n_setups = 0, n_evict = 0, n_ticks = 0;
+  std::string worker_error;
+  std::vector<SReq*> finished;  // decided by the worker, published under the lock
+};
+
+namespace {
+
+// Device bytes an instance of this mesh will hold once factored (maps,
+// workspaces, factors), for admission.
+size_t instance_bytes(int n_elem, int sub_elem, sfdp_precision prec) {
+  const size_t P = n_elem / sub_elem, nsub = P * P, ml = sub_elem + 1;
+  const size_t ND = ((4 * (sub_elem - 1) + 31) / 32) * 32, nf = (size_t)(n_elem - 1) * (n_elem - 1);
+  const size_t nmu = 2 * P * (P - 1) * (sub_elem - 1), nC = (P - 1) * (P - 1);
+  const size_t es = prec == SFDP_FP64 ? 16 : 8, gs = prec == SFDP_MIXED ? 8 : 16;
+  size_t b = nsub * ml * ml * ml * gs + nsub * ND * (ND + 1) / 2 * (es + 8) + nsub * ND * 4 * es + 2 * nC * nC * 16;
+  b += NRMAX * (4 * nsub * ND + 2 * nsub * 4 + 3 * nC + 3 * nmu) * 16;  // solve workspaces
+  b += NRMAX * (65 * nmu + 65 * 64) * 16 + 3 * NRMAX * 66 * nsub * 16;  // Krylov state (kmax 64)
+  b += NRMAX * nf * (3 * 8 + 3 * 16);                                    // range-space workspaces
+  b += nsub * ND * 40 + nmu * 12 + (size_t)(n_elem + 1) * (n_elem + 1) * 4;  // maps
+  return b;
+}
+
+
+// The worker decides that a request is over; it becomes visible to pollers when
+// the worker publishes its finished list under the lock.
+void server_finish(sfdp_server* S, SReq* r, sfdp_status st) {
+  if (st) r->status = st;
+  r->t_done = now_ms();
+  S->finished.push_back(r);
+}
+
+// Move pending requests onto resident instances, creating (and later
+// factoring) instances while the memory budget allows; idle instances are
+// evicted oldest first.  Returns the instances created (to be factored).
+std::vector<SInst*> server_admit(sfdp_server* S, std::deque<SReq*>& pend) {
+  std::vector<SInst*> fresh;
+  Ctx* ctx = S->ctx;
+  while (!pend.empty()) {
+    SReq* r = pend.front();
+    SInst* home = nullptr;
+    for (SInst* in : S->insts)
+      if (in->n_elem == r->n_elem && in->sub_elem == r->sub_elem && in->beta == r->beta) home = in;
+    if (!home) {
+      size_t need = instance_bytes(r->n_elem, r->sub_elem, S->prec);
+      size_t pool_need = 0;
+      for (SInst* in : fresh) pool_need += setup_bytes(in->n_elem, in->sub_elem);
+      pool_need += setup_bytes(r->n_elem, r->sub_elem);
+      // growing the pool frees the old one first: only the difference is new
+      size_t pool_grow = pool_need > ctx->pool_bytes ? pool_need - ctx->pool_bytes : 0;
+      auto fits = [&]() { return !ctx->budget || ctx->used + need + pool_grow <= ctx->budget; };
+      // evict the least recently used idle instance (false if none)
+      auto evict_one = [&]() {
+        SInst* victim = nullptr;
+        for (SInst* in : S->insts)
+          if (!in->busy() && std::find(fresh.begin(), fresh.end(), in) == fresh.end() &&
+              (!victim || in->last_used < victim->last_used))
+            victim = in;
+        if (!victim) return false;
+        S->insts.erase(std::find(S->insts.begin(), S->insts.end(), victim));
+        destroy_problem(victim->p);
+        delete victim;
+        S->active_set.clear();  // its address may be reused by a new instance
+        ++S->n_evict;
+        return true;
+      };
+      auto anything_busy = [&]() {
+        bool b = !fresh.empty();
+        for (SInst* in : S->insts) b = b || in->busy();
+        return b;
+      };
+      while (!fits() && evict_one()) {
+      }
+      if (!fits()) {
+        if (anything_busy()) break;  // wait for memory to free up
+        pend.pop_front();
+        r->why = "request can never fit the memory budget: " + std::to_string(ctx->used) + " B held, " +
+                 std::to_string(need) + " B instance + " + std::to_string(pool_grow) + " B set-up scratch needed, budget " +
+                 std::to_string(ctx->budget) + " B";
+        server_finish(S, r, SFDP_E_ADMIT);
+        continue;
+      }
+      // the estimate can be short of the real allocations: on NOMEM evict
+      // more, wait, or refuse
+      Problem* p = nullptr;
+      sfdp_status st;
+      for (;;) {
+        st = create_problem(ctx, 2, r->n_elem, r->sub_elem, S->prec, &p);
+        if (!st) {
+          p->gmres_blocks = std::min(p->nsub, std::max(1, (p->nmu + 127) / 128));
+          if ((st = alloc_workspace(*p, S->kmax)) || (st = alloc_rs(*p))) {
+            destroy_problem(p);
+            p = nullptr;
+          }
+        }
+        if (st != SFDP_E_NOMEM || !evict_one()) break;
+      }
+      if (st == SFDP_E_NOMEM && anything_busy()) break;
+      if (st) {
+        pend.pop_front();
+        r->why = std::string("instance allocation failed: ") + g_err + " (" + std::to_string(ctx->used) +
+                 " B held, budget " + std::to_string(ctx->budget) + " B)";
+        server_finish(S, r, st == SFDP_E_NOMEM ? SFDP_E_ADMIT : st);
+        continue;
+      }
+      home = new SInst();
+      home->p = p;
+      home->n_elem = r->n_elem;
+      home->sub_elem = r->sub_elem;
+      home->beta = r->beta;
+      p->beta = r->beta;
+      p->alpha = 1.0 / std::sqrt(r->beta);
+      S->insts.push_back(home);
+      fresh.push_back(home);
+    }
+    pend.pop_front();
+    r->inst = home;
+    home->queue.push_back(r);
+    home->last_used = now_ms();
+  }
+  return fresh;
+}
+
+// Rebuild the batch target over the instances with occupied slots (the
+// stream must be idle).
+sfdp_status server_target(sfdp_server* S, const std::vector<Problem*>& act) {
+  if (act != S->active_set) {
+    S->M.ctx = S->ctx;
+    S->M.probs = act;
+    sfdp_status s = multi_maps(S->M);
+    if (s) return s;
+    S->active_set = act;
+  }
+  int w = 0;
+  for (Problem* p : act) w = std::max(w, p->nr);
+  w = w <= 1 ? 1 : w == 2 ? 2 : 4;
+  sfdp_status s = multi_groups(S->M, S->kmax, w, S->gmap, S->gcap);
+  if (s) return s;
+  if (act.size() > S->gath_cap) {
+    if (S->dg) hipFree(S->dg);
+    if (S->hg) hipHostFree(S->hg);
+    S->gath_cap = std::max(act.size(), 2 * S->gath_cap);
+    if (hipMalloc(&S->dg, sizeof(Gathered) * S->gath_cap) || hipHostMalloc(&S->hg, sizeof(Gathered) * S->gath_cap))
+      return fail(SFDP_E_NOMEM, "server gather buffers");
+  }
+  return SFDP_OK;
+}
+
+// One tick: new targets take free slots; every occupied slot gets its KKT
+// residual; finished targets leave their slots (and complete their requests);
+// the rest take one two-factor refinement step together.
+sfdp_status server_tick(sfdp_server* S) {
+  hipStream_t st = S->ctx->stream;
+  HIPCHK(hipStreamSynchronize(st));
+  // fill free slots
+  std::vector<Problem*> act;
+  std::vector<SInst*> ains;
+  for (SInst* in : S->insts) {
+    Problem* p = in->p;
+    p->init = 0;
+    for (int s = 0; s < NRMAX; ++s) {
+      SSlot& sl = in->slot[s];
+      if (sl.req || in->queue.empty()) continue;
+      SReq* r = in->queue.front();
+      sl.req = r;
+      sl.k = r->next++;
+      sl.bad = 0;
+      sl.info = sfdp_info{};
+      const size_t nf = p->n_free;
+      p->sl[s] = Slot{r->ybar + sl.k * nf, r->yc ? r->yc + sl.k * p->n_bdry : nullptr, r->y + sl.k * nf,
+                      r->u + sl.k * nf, r->lam + sl.k * nf};
+      p->init |= 1u << s;
+      if (r->next == r->nrhs) in->queue.pop_front();
+    }
+    unsigned map = 0;
+    int nr = 0;
+    for (int s = 0; s < NRMAX; ++s)
+      if (in->slot[s].req) map |= (unsigned)s << (8 * nr++);
+    p->nr = nr;
+    p->map = map;
+    if (nr) {
+      act.push_back(p);
+      ains.push_back(in);
+      in->last_used = now_ms();
+    }
+  }
+  if (act.empty()) return SFDP_OK;
+  sfdp_status s = server_target(S, act);
+  if (s) return s;
+  s = multi_upload(S->M);
+  if (s) return s;
+  const Target& t = S->M.t;
+  const size_t n = act.size();
+  HIPCHK(launch_group_init(t));  // also clears the new slots' iteration logs
+  HIPCHK(launch_kkt_residual(t));
+  HIPCHK(launch_gather(t, S->dg));
+  HIPCHK(hipMemcpyAsync(S->hg, S->dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bool any = false;
+  for (size_t i = 0; i < n; ++i) {
+    SInst* in = ains[i];
+    Problem* p = in->p;
+    const Gathered& g = S->hg[i];
+    if (g.flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
+    unsigned map2 = 0;
+    int nb2 = 0;
+    for (int c = 0; c < p->nr; ++c) {
+      const int q = (p->map >> (8 * c)) & 255;
+      SSlot& sl = in->slot[q];
+      const double rho = g.red[2 * q];
+      const int steps = sl.info.outer_steps;
+      sl.info.rel_kkt = rho;
+      if (steps == 1) sl.info.rel_kkt_first = rho;
+      if (steps > 0) sl.info.imag_ratio = g.red[2 * q + 1];
+      bool finished = false;
+      if (!std::isfinite(rho)) { sl.bad = 1; finished = true; }
+      else if (rho <= S->tol_kkt) finished = true;
+      else if (steps >= S->max_outer) { sl.bad = 2; finished = true; }
+      if (!finished) {
+        map2 |= (unsigned)q << (8 * nb2++);
+        continue;
+      }
+      SReq* r = sl.req;
+      sl.info.n_feti = g.flags[FLAG_CNT + q];
+      for (int k = 0; k < sl.info.n_feti && k < 16; ++k) {
+        sl.info.krylov_its[k] = g.flags[FLAG_LOG + 16 * q + k];
+        sl.info.krylov_total += sl.info.krylov_its[k];
+      }
+      r->info[sl.k] = sl.info;
+      if (sl.bad) r->status = SFDP_E_NOCONV;
+      if (++r->done == r->nrhs) server_finish(S, r, SFDP_OK);
+      sl = SSlot{};
+    }
+    p->nr = nb2;
+    p->map = map2;
+    p->init = 0;
+    any = any || nb2 > 0;
+  }
+  ++S->n_ticks;
+  if (!any) return SFDP_OK;
+  // one refinement step for the slots still running (same instance set; the
+  // GMRES groups follow the new widths)
+  int w = 0;
+  for (Problem* p : act) w = std::max(w, p->nr);
+  s = multi_groups(S->M, S->kmax, w <= 1 ? 1 : w == 2 ? 2 : 4, S->gmap, S->gcap);
+  if (s) return s;
+  s = multi_upload(S->M);
+  if (s) return s;
+  HIPCHK(launch_make_rhs1(t));
+  s = feti_run(t, nullptr, V_CVEC, 0, V_CVEC2, S->tol_inner, S->kmax);
+  if (s) return s;
+  HIPCHK(launch_make_rhs2(t));
+  s = feti_run(t, nullptr, V_CVEC3, 0, V_CVEC, S->tol_inner, S->kmax);
+  if (s) return s;
+  HIPCHK(launch_update(t));
+  for (size_t i = 0; i < n; ++i)
+    for (int c = 0; c < act[i]->nr; ++c) ains[i]->slot[(act[i]->map >> (8 * c)) & 255].info.outer_steps += 1;
+  for (Problem* p : act) p->nr = 0;
+  return SFDP_OK;
+}
+
+void server_loop(sfdp_server* S) {
+  hipSetDevice(S->ctx->device);
+  for (;;) {
+    std::deque<SReq*> pend;
+    bool work = false;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      for (;;) {
+        work = false;
+        for (SInst* in : S->insts) work = work || in->busy();
+        if (work || !S->pending.empty() || S->stop) break;
+        S->cv_work.wait(lk);
+      }
+      if (S->stop && !work && S->pending.empty()) return;
+      pend.swap(S->pending);
+    }
+    hipStreamSynchronize(S->ctx->stream);
+    std::vector<SInst*> fresh = server_admit(S, pend);
+    sfdp_status st = SFDP_OK;
+    if (!fresh.empty()) {
+      std::vector<Problem*> ps;
+      for (SInst* in : fresh) ps.push_back(in->p);
+      Multi Mf;
+      Mf.ctx = S->ctx;
+      Mf.probs = ps;
+      st = multi_maps(Mf);
+      if (!st) st = setup_run(Mf.t, ps, &Mf);
+      if (st == SFDP_E_NOMEM) {
+        // drop the new instances; their requests wait (or are refused when
+        // nothing running could free memory)
+        bool busy = false;
+        for (SInst* in : S->insts)
+          if (std::find(fresh.begin(), fresh.end(), in) == fresh.end()) busy = busy || in->busy();
+        std::vector<SReq*> back;
+        for (SInst* in : fresh) {
+          for (SReq* r : in->queue) back.push_back(r);
+          S->insts.erase(std::find(S->insts.begin(), S->insts.end(), in));
+          destroy_problem(in->p);
+          delete in;
+        }
+        S->active_set.clear();
+        for (auto it = back.rbegin(); it != back.rend(); ++it) {
+          (*it)->inst = nullptr;
+          if (busy) {
+            pend.push_front(*it);
+          } else {
+            (*it)->why = std::string("set-up allocation failed: ") + g_err;
+            server_finish(S, *it, SFDP_E_ADMIT);
+          }
+        }
+        st = SFDP_OK;
+      } else {
+        S->n_setups += (int64_t)fresh.size();
+      }
+    }
+    if (!st) st = server_tick(S);
+    std::lock_guard<std::mutex> lk(S->mu);
+    // requests that could not be admitted yet go back to the front of the queue
+    for (auto it = pend.rbegin(); it != pend.rend(); ++it) S->pending.push_front(*it);
+    if (st) {
+      // a device error ends the service: fail everything that is not complete
+      S->worker_error = g_err;
+      for (auto& kv : S->reqs)
+        if (!kv.second->complete && std::find(S->finished.begin(), S->finished.end(), kv.second) == S->finished.end())
+          server_finish(S, kv.second, st);
+      for (SInst* in : S->insts) {
+        in->queue.clear();
+        for (SSlot& sl : in->slot) sl = SSlot{};
+      }
+      S->pending.clear();
+    }
+    for (SReq* r : S->finished) {
+      r->complete = true;
+      if (r->status == SFDP_OK) {
+        ++S->n_complete;
+        S->lat.push_back(r->t_done - r->t_submit);
+      } else {
+        ++S->n_failed;
+      }
+    }
+    S->finished.clear();
+    S->cv_done.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+sfdp_status sfdp_server_create(sfdp_ctx* ctx, sfdp_precision prec, const sfdp_opts* opts, sfdp_server** out) {
+  if (!ctx || !out) return fail(SFDP_E_INVALID, "NULL argument");
+  if (prec != SFDP_FP64 && prec != SFDP_MIXED && prec != SFDP_MIXED_IFACE) return fail(SFDP_E_INVALID, "bad precision");
+  *out = nullptr;
+  sfdp_server* S = new (std::nothrow) sfdp_server();
+  if (!S) return fail(SFDP_E_NOMEM, "host allocation");
+  S->ctx = ctx;
+  S->prec = prec;
+  defaults(prec, opts, S->tol_kkt, S->tol_inner, S->max_outer, S->kmax);
+  S->worker = std::thread(server_loop, S);
+  *out = S;
+  return SFDP_OK;
+}
+
+sfdp_status sfdp_server_submit(sfdp_server* S, const sfdp_request* rq, uint64_t* ticket) {
+  if (!S || !rq || !ticket) return fail(SFDP_E_INVALID, "NULL argument");
+  if (rq->dim != 2) return fail(SFDP_E_INVALID, "only dim = 2 is implemented");
+  if (rq->sub_elem < 2 || rq->sub_elem > 32 || rq->n_elem % rq->sub_elem != 0 || rq->n_elem / rq->sub_elem < 2)
+    return fail(SFDP_E_INVALID, "bad mesh");
+  if (!(rq->beta > 0) || !std::isfinite(rq->beta)) return fail(SFDP_E_INVALID, "beta must be positive and finite");
+  if (rq->nrhs <= 0 || !rq->ybar || !rq->y || !rq->u || !rq->lam) return fail(SFDP_E_INVALID, "bad arguments");
+  SReq* r = new (std::nothrow) SReq();
+  if (!r) return fail(SFDP_E_NOMEM, "host allocation");
+  r->n_elem = rq->n_elem;
+  r->sub_elem = rq->sub_elem;
+  r->nrhs = rq->nrhs;
+  r->beta = rq->beta;
+  r->ybar = rq->ybar;
+  r->yc = rq->yc;
+  r->y = rq->y;
+  r->u = rq->u;
+  r->lam = rq->lam;
+  r->info.assign(rq->nrhs, sfdp_info{});
+  r->t_submit = now_ms();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) { delete r; return fail(SFDP_E_STATE, "server is stopping"); }
+    r->id = S->next_id++;
+    S->reqs[r->id] = r;
+    S->pending.push_back(r);
+    ++S->n_submit;
+  }
+  S->cv_work.notify_one();
+  *ticket = r->id;
+  return SFDP_OK;
+}
+
+sfdp_status sfdp_server_poll(sfdp_server* S, uint64_t ticket, int wait, sfdp_info* info, double* latency_ms) {
+  if (!S) return fail(SFDP_E_INVALID, "NULL argument");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(SFDP_E_INVALID, "unknown ticket");
+  SReq* r = it->second;
+  if (!r->complete) {
+    if (!wait) return SFDP_E_STATE;
+    S->cv_done.wait(lk, [&] { return r->complete; });
+  }
+  if (info)
+    for (int k = 0; k < r->nrhs; ++k) info[k] = r->info[k];
+  if (latency_ms) *latency_ms = r->t_done - r->t_submit;
+  sfdp_status st = r->status;
+  const std::string why = r->why;
+  S->reqs.erase(it);
+  delete r;
+  if (st == SFDP_E_DEVICE) return fail(st, S->worker_error);
+  if (st == SFDP_E_ADMIT) return fail(st, why.empty() ? "request can never fit the memory budget" : why);
+  if (st == SFDP_E_NOCONV) return fail(st, "a target missed tol_kkt within max_outer steps");
+  if (st) return fail(st, why);
+  return st;
+}
+
+sfdp_status sfdp_server_stats(sfdp_server* S, sfdp_server_info* out) {
+  if (!S || !out) return fail(SFDP_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  memset(out, 0, sizeof(*out));
+  out->submitted = S->n_submit;
+  out->completed = S->n_complete;
+  out->failed = S->n_failed;
+  out->setups = S->n_setups;
+  out->evictions = S->n_evict;
+  out->ticks = S->n_ticks;
+  out->resident = (int64_t)S->insts.size();
+  out->device_bytes = (int64_t)S->ctx->used;
+  if (!S->lat.empty()) {
+    std::vector<double> v = S->lat;
+    std::sort(v.begin(), v.end());
+    auto q = [&](double f) { return v[std::min(v.size() - 1, (size_t)std::llround(f * (v.size() - 1)))]; };
+    out->p50_ms = q(0.5);
+    out->p99_ms = q(0.99);
+    double sum = 0;
+    for (double x : v) sum += x;
+    out->mean_ms = sum / v.size();
+  }
+  return SFDP_OK;
+}
+
+void sfdp_server_destroy(sfdp_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  hipSetDevice(S->ctx->device);
+  hipStreamSynchronize(S->ctx->stream);
+  for (SInst* in : S->insts) {
+    destroy_problem(in->p);
+    delete in;
+  }
+  for (auto& kv : S->reqs) delete kv.second;
+  if (S->gmap) hipFree(S->gmap);
+  if (S->dg) hipFree(S->dg);
+  if (S->hg) hipHostFree(S->hg);
+  delete S;
 }
 
 }  // extern "C"

@@ -191,6 +191,13 @@ struct Gathered {
 // launch can address the same vector of every instance it covers.
 enum VecSel : int { V_CVEC = 0, V_CVEC2 = 1, V_CVEC3 = 2, V_UF = 3, V_UX = 4, V_FCS = 5, V_YMIN = 6 };
 
+// Caller arrays of one range-space slot (device pointers, one target each).
+struct Slot {
+  const double* ybar;
+  const double* yc;  // Dirichlet data or null for zero
+  double *y, *u, *lam;
+};
+
 // Device view of one instance: what every kernel reads about it.  A launch
 // covers one instance (the view is a kernel argument) or many (an array of
 // views in device memory and a block -> instance map).
@@ -220,8 +227,8 @@ struct Dev {
   // caller arrays of the current call (device pointers)
   const cd* uf;       // FETI-DP right-hand sides (stride n_free)
   cd* ux;             // FETI-DP solutions
-  const double *ybar, *yc;  // range-space targets of the group (stride n_free / n_bdry)
-  double *y, *u, *lam;
+  Slot sl[NRMAX];     // range-space caller arrays of each group slot
+  unsigned init;      // slots (bit s) whose iterate starts at (ybar, 0, 0) in group_init
   // share of the GMRES grid: first block, block count, multipliers per block
   int gb0, gnb, chunk, resident;
   // FP64 set-up scratch
@@ -297,8 +304,15 @@ struct Problem {
   unsigned map = 0;
   const cd* uf = nullptr;
   cd* ux = nullptr;
-  const double *ybar = nullptr, *yc = nullptr;
-  double *y = nullptr, *u = nullptr, *lam = nullptr;
+  Slot sl[NRMAX] = {};
+  unsigned init = 0;
+  // caller arrays of slots 0..nr-1 as consecutive targets of stride n_free / n_bdry
+  void set_slots(int nr_, const double* ybar, const double* yc, double* y, double* u, double* lam) {
+    for (int c = 0; c < NRMAX; ++c)
+      sl[c] = c < nr_ ? Slot{ybar + c * n_free, yc ? yc + c * n_bdry : nullptr, y + c * n_free,
+                             u + c * n_free, lam + c * n_free}
+                      : Slot{};
+  }
   // set-up scratch (valid during sfdp_set_beta only)
   cd *G64 = nullptr, *Sinv64 = nullptr, *S64 = nullptr, *Phi64 = nullptr, *PhiFull = nullptr,
      *scr = nullptr, *Zs = nullptr;
@@ -354,7 +368,9 @@ struct Problem {
     d.u0 = u0; d.ymin = ymin; d.dvec = dvec; d.mu = mu; d.wv = wv; d.Qk = Qk; d.Hk = Hk; d.part = part;
     d.dscal = dscal; d.bar = bar; d.flags = flags; d.kstride = kmax_alloc;
     d.r1 = r1; d.r2 = r2; d.r3 = r3; d.red = red; d.cvec = cvec; d.cvec2 = cvec2; d.cvec3 = cvec3;
-    d.uf = uf; d.ux = ux; d.ybar = ybar; d.yc = yc; d.y = y; d.u = u; d.lam = lam;
+    d.uf = uf; d.ux = ux;
+    for (int c = 0; c < NRMAX; ++c) d.sl[c] = sl[c];
+    d.init = init;
     d.gb0 = 0; d.gnb = gmres_blocks; d.chunk = (nmu + gmres_blocks - 1) / std::max(gmres_blocks, 1);
     d.resident = gmres_blocks == nsub;
     d.G64 = G64; d.Sinv64 = Sinv64; d.S64 = S64; d.Phi64 = Phi64; d.PhiFull = PhiFull; d.scr = scr;
@@ -369,6 +385,10 @@ struct Ctx {
   hipStream_t stream = nullptr;
   int num_cu = 0;
   int max_lds = 65536;  // bytes of LDS one workgroup may allocate
+  // FP64 set-up scratch shared by every sfdp_set_beta on this context (grown on
+  // demand, counted in `used`)
+  void* pool = nullptr;
+  size_t pool_bytes = 0;
 };
 
 // The instances one launch covers: a single problem (its view passed by value)
@@ -440,7 +460,7 @@ hipError_t launch_fill_flags(const Target& t, int first, int count);
 hipError_t launch_copy_real_to_complex(int64_t n, const double* x, cd* y, hipStream_t st);
 hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t st);
 hipError_t launch_real_part(int64_t n, const cd* x, double* y, hipStream_t st);
-hipError_t launch_group_init(const Target& t);  // y = ybar, u = lam = 0 for the views' groups
+hipError_t launch_group_init(const Target& t);  // y = ybar, u = lam = 0 for the views' init slots
 hipError_t launch_gather(const Target& t, Gathered* out);  // out[i]: instance i of the target
 
 }  // namespace sfdp

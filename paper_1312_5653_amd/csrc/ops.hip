@@ -107,11 +107,11 @@ __global__ void __launch_bounds__(256) k_kkt_residual(Src src) {
   const int64_t nfree = d.n_free, nbdry = d.n_bdry;
   const int64_t pstride = 2 * ((nfree + 255) / 256);
   const int* f2b = d.full2bdry;
-  const double* ybar = d.ybar + s * nfree;
-  const double* yc = d.yc ? d.yc + s * nbdry : nullptr;
-  const double* y = d.y + s * nfree;
-  const double* u = d.u + s * nfree;
-  const double* lam = d.lam + s * nfree;
+  const double* ybar = d.sl[s].ybar;
+  const double* yc = d.sl[s].yc;
+  const double* y = d.sl[s].y;
+  const double* u = d.sl[s].u;
+  const double* lam = d.sl[s].lam;
   double* part = d.red + RED_HEAD + s * pstride;
   int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   double rn = 0.0, bn = 0.0;
@@ -206,9 +206,9 @@ __global__ void __launch_bounds__(256) k_update(Src src) {
   const int64_t n = d.n_free, pstride = 2 * ((n + 255) / 256);
   const cd* dw = d.cvec2 + c * n;
   const cd* z = d.cvec + c * n;
-  double* y = d.y + s * n;
-  double* u = d.u + s * n;
-  double* lam = d.lam + s * n;
+  double* y = d.sl[s].y;
+  double* u = d.sl[s].u;
+  double* lam = d.sl[s].lam;
   double* part = d.red + RED_HEAD + s * pstride;
   int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   double im = 0.0, re = 0.0;
@@ -233,19 +233,23 @@ __global__ void __launch_bounds__(256) k_update(Src src) {
   }
 }
 
-// Start of a range-space group: y = ybar, u = 0, lam = 0 for slots c < nr
-// (the group's slots are 0 .. nr-1 here).
+// Start of a range-space target: y = ybar, u = 0, lam = 0 (and an empty
+// iteration log) for the slots s (blockIdx.y) whose bit is set in the view's
+// init mask.
 template <class Src>
 __global__ void k_group_init(Src src) {
   const Dev& d = src.dev();
-  const int c = blockIdx.y;
-  if (c >= d.nr) return;
+  const int s = blockIdx.y;
+  if (!((d.init >> s) & 1u)) return;
   const int64_t n = d.n_free;
+  if (src.bx() == 0 && threadIdx.x <= 16)  // the slot's FETI-DP iteration log starts empty
+    d.flags[threadIdx.x == 16 ? FLAG_CNT + s : FLAG_LOG + 16 * s + threadIdx.x] = 0;
   int64_t t = (int64_t)src.bx() * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  d.y[c * n + t] = d.ybar[c * n + t];
-  d.u[c * n + t] = 0.0;
-  d.lam[c * n + t] = 0.0;
+  const Slot& q = d.sl[s];
+  q.y[t] = q.ybar[t];
+  q.u[t] = 0.0;
+  q.lam[t] = 0.0;
 }
 
 // flags[first .. first + count) = 0 for every instance

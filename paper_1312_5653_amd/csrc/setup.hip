@@ -22,6 +22,8 @@ namespace sfdp {
 
 constexpr int MLMAX = 33;  // ml = m + 1 <= 33
 constexpr int CW = 32;     // right-hand-side panel width of multi_solve
+constexpr int RG = 256 / CW;            // row groups of a 256-thread workgroup
+constexpr int MT = (MLMAX + RG - 1) / RG;  // rows per thread in the panel products
 
 // In-place Gauss-Jordan inverse of an n x n complex matrix in LDS (row-major).
 __device__ void gj_invert_lds(cd* T, int n, cd* rowk, cd* colk) {
@@ -147,12 +149,29 @@ __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
         zb[idx] = v;
       }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < ml * CW; idx += blockDim.x) {
-        int p = idx / CW, c = idx % CW;
-        cd acc{0.0, 0.0};
-        for (int k = 0; k < ml; ++k) fma_acc(acc, Gl[k * ml + p], zb[k * CW + c]);
-        tb[idx] = acc;
-        scr[((size_t)j * ml + p) * CW + c] = acc;
+      {
+        // thread (row group rg, column c) forms rows rg, rg + 8, ... of column c:
+        // one LDS read of z per k serves up to five rows
+        const int c = threadIdx.x & (CW - 1), rg = threadIdx.x / CW;
+        cd acc[MT];
+#pragma unroll
+        for (int v = 0; v < MT; ++v) acc[v] = cd{0.0, 0.0};
+        for (int k = 0; k < ml; ++k) {
+          const cd z = zb[k * CW + c];
+#pragma unroll
+          for (int v = 0; v < MT; ++v) {
+            const int p = rg + RG * v;
+            if (p < ml) fma_acc(acc[v], Gl[k * ml + p], z);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < MT; ++v) {
+          const int p = rg + RG * v;
+          if (p < ml) {
+            tb[p * CW + c] = acc[v];
+            scr[((size_t)j * ml + p) * CW + c] = acc[v];
+          }
+        }
       }
       __syncthreads();
     }
@@ -169,14 +188,30 @@ __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
           zb[idx] = v;
         }
         __syncthreads();
-        for (int idx = threadIdx.x; idx < ml * CW; idx += blockDim.x) {
-          int p = idx / CW, c = idx % CW;
-          cd acc = scr[((size_t)j * ml + p) * CW + c];
-          for (int k = 0; k < ml; ++k) {
-            cd t = Gl[k * ml + p] * zb[k * CW + c];
-            acc = acc - t;
+        {
+          const int c = threadIdx.x & (CW - 1), rg = threadIdx.x / CW;
+          cd acc[MT];
+#pragma unroll
+          for (int v = 0; v < MT; ++v) {
+            const int p = rg + RG * v;
+            acc[v] = p < ml ? scr[((size_t)j * ml + p) * CW + c] : cd{0.0, 0.0};
           }
-          tb[idx] = acc;  // safe: zb holds the input of this line
+          for (int k = 0; k < ml; ++k) {
+            const cd z = zb[k * CW + c];
+#pragma unroll
+            for (int v = 0; v < MT; ++v) {
+              const int p = rg + RG * v;
+              if (p < ml) {
+                cd t = Gl[k * ml + p] * z;
+                acc[v] = acc[v] - t;
+              }
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < MT; ++v) {
+            const int p = rg + RG * v;
+            if (p < ml) tb[p * CW + c] = acc[v];  // safe: zb holds the input of this line
+          }
         }
       } else {
         for (int idx = threadIdx.x; idx < ml * CW; idx += blockDim.x) {
@@ -204,33 +239,59 @@ __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
   }
 }
 
-// In-place Gauss-Jordan inverse of the nd_s x nd_s leading block of each
-// subdomain's ND x ND matrix (global memory, one workgroup per subdomain).
+// In-place Gauss-Jordan inverse (no pivoting) of the nd_s x nd_s leading block
+// of each subdomain's ND x ND matrix, one 1024-thread workgroup per subdomain
+// with the matrix in registers: thread t holds row t / 8, columns t % 8 + 8 u
+// (u < 16; nd_s <= 128); row k and column k of each pivot step pass through LDS.
+constexpr int INV_EPT = 16;
 template <class Src>
 __global__ void __launch_bounds__(1024) k_invert_batched(Src src) {
-  __shared__ cd rowk[512], colk[512];
+  __shared__ cd rowk[128], colk[128];
   const Dev& d = src.dev();
   const int ND = d.g.ND;
-  cd* A = d.S64;
   const int s = src.bx(), n = d.mp.nd[s];
-  cd* M = A + (size_t)s * ND * ND;
+  cd* M = d.S64 + (size_t)s * ND * ND;
+  const int i = threadIdx.x >> 3, c8 = threadIdx.x & 7;
+  const bool row_ok = i < n;
+  cd e[INV_EPT];
+#pragma unroll
+  for (int u = 0; u < INV_EPT; ++u) {
+    const int j = c8 + 8 * u;
+    e[u] = (row_ok && j < n) ? M[(size_t)i * ND + j] : cd{0.0, 0.0};
+  }
   for (int k = 0; k < n; ++k) {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      rowk[t] = M[k * ND + t];
-      colk[t] = M[t * ND + k];
+    if (row_ok) {
+#pragma unroll
+      for (int u = 0; u < INV_EPT; ++u) {
+        const int j = c8 + 8 * u;
+        if (i == k && j < n) rowk[j] = e[u];
+        if (j == k) colk[i] = e[u];
+      }
     }
     __syncthreads();
-    cd piv = cdiv(cd{1.0, 0.0}, rowk[k]);
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-      int i = idx / n, j = idx % n;
-      cd v;
-      if (i == k && j == k) v = piv;
-      else if (i == k) v = rowk[j] * piv;
-      else if (j == k) v = -(colk[i] * piv);
-      else v = M[i * ND + j] - colk[i] * (rowk[j] * piv);
-      M[i * ND + j] = v;
+    const cd piv = cdiv(cd{1.0, 0.0}, rowk[k]);
+    if (row_ok) {
+      const cd ci = colk[i];
+#pragma unroll
+      for (int u = 0; u < INV_EPT; ++u) {
+        const int j = c8 + 8 * u;
+        if (j >= n) continue;
+        cd v;
+        if (i == k && j == k) v = piv;
+        else if (i == k) v = rowk[j] * piv;
+        else if (j == k) v = -(ci * piv);
+        else v = e[u] - ci * (rowk[j] * piv);
+        e[u] = v;
+      }
     }
     __syncthreads();
+  }
+  if (row_ok) {
+#pragma unroll
+    for (int u = 0; u < INV_EPT; ++u) {
+      const int j = c8 + 8 * u;
+      if (j < n) M[(size_t)i * ND + j] = e[u];
+    }
   }
 }
 

@@ -23,7 +23,8 @@ EXPORTS = [
     "sfdp_apply_schur_inv", "sfdp_feti_solve", "sfdp_apply_operator", "sfdp_kkt_residual",
     "sfdp_inspect", "sfdp_interface_apply", "sfdp_timing_enable", "sfdp_kernel_times",
     "sfdp_batch_create", "sfdp_batch_destroy", "sfdp_batch_sizes", "sfdp_batch_set_beta",
-    "sfdp_batch_solve_range_space",
+    "sfdp_batch_solve_range_space", "sfdp_server_create", "sfdp_server_submit", "sfdp_server_poll",
+    "sfdp_server_stats", "sfdp_server_destroy",
 ]
 
 
@@ -49,6 +50,20 @@ class Info(ctypes.Structure):
                 "imag_ratio": self.imag_ratio, "outer_steps": self.outer_steps,
                 "krylov_total": self.krylov_total, "n_feti": self.n_feti,
                 "krylov_its": list(self.krylov_its)[: self.n_feti]}
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_elem", ctypes.c_int), ("sub_elem", ctypes.c_int),
+                ("beta", ctypes.c_double), ("nrhs", ctypes.c_int), ("ybar", ctypes.c_void_p),
+                ("yc", ctypes.c_void_p), ("y", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("lam", ctypes.c_void_p)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("setups", ctypes.c_int64), ("evictions", ctypes.c_int64), ("ticks", ctypes.c_int64),
+                ("resident", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("mean_ms", ctypes.c_double),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double)]
 
 
 class Timing(ctypes.Structure):
@@ -102,11 +117,18 @@ def load_library(path: str = LIB_PATH):
     VPP = ctypes.POINTER(ctypes.c_void_p)
     lib.sfdp_batch_solve_range_space.argtypes = [P, ctypes.POINTER(I), VPP, VPP, VPP, VPP, VPP,
                                                  ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    lib.sfdp_server_create.argtypes = [P, I, ctypes.POINTER(Opts), ctypes.POINTER(P)]
+    lib.sfdp_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.sfdp_server_poll.argtypes = [P, ctypes.c_uint64, I, ctypes.POINTER(Info), ctypes.POINTER(D)]
+    lib.sfdp_server_stats.argtypes = [P, ctypes.POINTER(ServerInfo)]
+    lib.sfdp_server_destroy.argtypes = [P]
+    lib.sfdp_server_destroy.restype = None
     for name in ("sfdp_ctx_create", "sfdp_problem_create", "sfdp_problem_sizes", "sfdp_set_beta",
                  "sfdp_solve_range_space", "sfdp_apply_schur_inv", "sfdp_feti_solve",
                  "sfdp_apply_operator", "sfdp_kkt_residual", "sfdp_inspect", "sfdp_interface_apply",
                  "sfdp_timing_enable", "sfdp_kernel_times", "sfdp_batch_create", "sfdp_batch_sizes",
-                 "sfdp_batch_set_beta", "sfdp_batch_solve_range_space"):
+                 "sfdp_batch_set_beta", "sfdp_batch_solve_range_space", "sfdp_server_create",
+                 "sfdp_server_submit", "sfdp_server_poll", "sfdp_server_stats"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -323,3 +345,61 @@ class Batch:
             res.append([infos[k + j].as_dict() for j in range(nr[i])])
             k += nr[i]
         return [t[0] for t in outs], [t[1] for t in outs], [t[2] for t in outs], res, st
+
+
+class Server:
+    """Continuous-batching request loop on one context (a worker thread owns the
+    context's stream while the server lives)."""
+
+    def __init__(self, ctx: Context, precision: int = SFDP_MIXED, **opts):
+        h = ctypes.c_void_p()
+        o = _opts(**opts)
+        _check(_lib.sfdp_server_create(ctx._h, precision, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self._live = {}
+
+    def submit(self, n_elem: int, sub_elem: int, beta: float, ybar, yc=None):
+        """ybar: (nrhs, n_free) or (n_free,) CUDA tensor (kept alive until polled).
+        Returns a ticket; the outputs are allocated here."""
+        import torch
+        if not ybar.is_cuda or not ybar.is_contiguous():
+            raise ValueError("arrays must be contiguous CUDA tensors")
+        nrhs = 1 if ybar.dim() == 1 else ybar.shape[0]
+        y, u, lam = (torch.empty_like(ybar) for _ in range(3))
+        torch.cuda.synchronize()
+        req = Request(2, n_elem, sub_elem, float(beta), nrhs, ybar.data_ptr(),
+                      yc.data_ptr() if yc is not None else None, y.data_ptr(), u.data_ptr(), lam.data_ptr())
+        t = ctypes.c_uint64()
+        _check(_lib.sfdp_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._live[t.value] = (ybar, yc, y, u, lam, nrhs)
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """None while pending (wait=False); else (y, u, lam, infos, latency_ms, status)."""
+        ybar, yc, y, u, lam, nrhs = self._live[ticket]
+        infos = (Info * nrhs)()
+        lat = ctypes.c_double()
+        st = _lib.sfdp_server_poll(self._h, ticket, int(wait), infos, ctypes.byref(lat))
+        if st == -5 and not wait:
+            return None
+        del self._live[ticket]
+        if st not in (0, -3):
+            raise SfdpError(st, _lib.sfdp_last_error().decode())
+        return y, u, lam, [i.as_dict() for i in infos], lat.value, st
+
+    def stats(self):
+        si = ServerInfo()
+        _check(_lib.sfdp_server_stats(self._h, ctypes.byref(si)))
+        return {f: getattr(si, f) for f, _ in ServerInfo._fields_}
+
+    def close(self):
+        if self._h:
+            _lib.sfdp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
