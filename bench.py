@@ -192,6 +192,54 @@ def run_instances(sfdp, torch, ctx, count, seed, tol_kkt):
             "precision": "mixed"}
 
 
+def run_serving(sfdp, torch, count, seed, tol_kkt, budget_gb):
+    """Served request stream (see workloads.c5_requests): requests are submitted at their
+    arrival times to one server (mixed precision, memory budget budget_gb) and polled at the
+    end; latency is submit-to-result per request, throughput counts targets solved."""
+    import numpy as np
+    from paper_1312_5653_amd import workloads
+    reqs = workloads.c5_requests(count, seed)
+    inputs = []
+    for r in reqs:
+        ys = [workloads.sine_target(2, r["N"], *workloads.modes_for("sixteen2d", r["seed"] * 8 + k))[0]
+              for k in range(r["nrhs"])]
+        inputs.append(torch.tensor(np.stack(ys), device="cuda:0"))
+    torch.cuda.synchronize()
+    ctx = sfdp.Context(0, mem_budget=int(budget_gb * (1 << 30)))
+    srv = sfdp.Server(ctx, sfdp.SFDP_MIXED, tol_kkt=tol_kkt)
+    t0 = time.perf_counter()
+    tickets = []
+    for r, x in zip(reqs, inputs):
+        delay = r["arrival_ms"] / 1e3 - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(r["N"], 32, r["beta"], x))
+    lat, rho, fails, errors = [], [], 0, {}
+    for tk in tickets:
+        try:
+            _, _, _, info, l, st = srv.poll(tk)
+            lat.append(l)
+            rho.extend(i["rel_kkt"] for i in info)
+        except sfdp.SfdpError as e:
+            fails += 1
+            errors[str(e)] = errors.get(str(e), 0) + 1
+    wall = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    ctx.close()
+    if not lat:
+        raise RuntimeError(f"every served request failed: {errors}")
+    lat.sort()
+    q = lambda f: lat[min(len(lat) - 1, int(round(f * (len(lat) - 1))))]
+    solved = sum(r["nrhs"] for r in reqs)
+    return {"requests": count, "seed": seed, "targets": solved, "mean_gap_ms": 5.0,
+            "meshes": "2D, N in 128..1024 (m = 32); the stream's 3D and full-space requests are not built",
+            "wall_s": wall, "solves_per_s": solved / wall, "requests_per_s": count / wall,
+            "p50_ms": q(0.5), "p99_ms": q(0.99), "max_rel_kkt": max(rho), "failed": fails, "errors": errors,
+            "setups": stats["setups"], "evictions": stats["evictions"], "ticks": stats["ticks"],
+            "budget_gb": budget_gb, "precision": "mixed"}
+
+
 def cpu_instances(count, seed, budget_s=10.0):
     """The oracle on the batched-instance workload: SuperLU factor of Z plus the two-factor
     solve, instance after instance on one core, for as many instances as fit the budget."""
@@ -275,6 +323,9 @@ def main():
                          "calibrates the HBM byte counters of a profiler run)")
     ap.add_argument("--instances", type=int, default=256,
                     help="batched-instance workload size (0 skips it)")
+    ap.add_argument("--requests", type=int, default=100,
+                    help="served request stream length (0 skips it)")
+    ap.add_argument("--serve-budget-gb", type=float, default=48.0)
     ap.add_argument("--max-krylov", type=int, default=0,
                     help="GMRES iteration cap per FETI-DP solve (0: library default)")
     ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB"),
@@ -387,6 +438,8 @@ def main():
         out["instances_batch"] = run_instances(sfdp, torch, ctx, args.instances, 0, tol_kkt)
         if not args.no_cpu:
             out["instances_batch"]["cpu_baseline"] = cpu_instances(args.instances, 0)
+    if args.requests > 0 and not args.headline_only:
+        out["serving"] = run_serving(sfdp, torch, args.requests, 0, tol_kkt, args.serve_budget_gb)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, m, beta, ybar[0])
     ctx.close()

@@ -97,6 +97,13 @@ typedef struct {
                        LDS, so a smaller cap leaves room to serve more
                        right-hand sides per launch (a solve that reaches the
                        cap is continued by the outer refinement) */
+  int factors;      /* complex solves per refinement step [2]: 2 is the paper's
+                       two-factor form (Z, then conj(Z) by conjugation); 1 uses
+                       that the first factor alone determines the step:
+                       Z (dy + i alpha dlam) = r3 + i alpha r1, so one FETI-DP
+                       solve gives dy = Re, dlam = Im / alpha (the same result,
+                       half the work; sfdp_apply_schur_inv then returns
+                       -Im(Z^-1 r) / alpha) */
   int batch;        /* right-hand sides solved together, 1..4 [4]: each FETI-DP
                        launch sequence (subdomain solves, persistent GMRES)
                        serves up to this many right-hand sides in lockstep,
@@ -249,7 +256,9 @@ sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const d
  * mesh, one beta, nrhs targets) are admitted while the context's memory
  * budget allows: a request joins the resident instance of its (mesh, beta)
  * or a new instance is created and factored (new instances admitted together
- * are factored in one set-up sequence); idle instances are evicted, least
+ * are factored in shared set-up passes whose scratch stays under 1/16 of the
+ * budget, 4 GiB without one, unless a single instance needs more; the
+ * scratch pool stays with the context); idle instances are evicted, least
  * recently used first, when memory is short, and a request that does not fit
  * waits until memory frees.  Every instance serves up to four targets at a
  * time in slots; each worker tick gives every occupied slot of every resident

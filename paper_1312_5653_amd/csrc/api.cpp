@@ -3,6 +3,7 @@
 // (Sec. 3.1 Schur system with the Sec. 4 complex factorization).
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
@@ -238,6 +239,7 @@ void defaults(sfdp_precision prec, const sfdp_opts* o, double& tol_kkt, double& 
   kmax = (o && o->max_krylov > 0) ? std::min(o->max_krylov, KMAX_LIMIT) : 64;
 }
 int batch_of(const sfdp_opts* o) { return (o && o->batch > 0) ? std::min(o->batch, NRMAX) : NRMAX; }
+bool single_of(const sfdp_opts* o) { return o && o->factors == 1; }
 
 sfdp_status check_ready(const Problem* p) {
   if (!p) return fail(SFDP_E_INVALID, "null problem");
@@ -433,11 +435,23 @@ sfdp_status multi_maps(Multi& M) {
 // blocks co-resident.  Written after the kind maps (own device area).
 sfdp_status multi_groups(Multi& M, int kmax, int width, int*& gmap, size_t& gcap) {
   if (M.g_kmax == kmax && M.g_width == width) return SFDP_OK;
+  const int asked = width;
   Target& t = M.t;
   const int n = (int)M.probs.size();
-  int cmax = 1;
-  for (Problem* p : M.probs) cmax = std::max(cmax, (p->nmu + p->gmres_blocks - 1) / p->gmres_blocks);
-  const int cap = gmres_capacity(*M.probs[0], kmax, cmax, width);
+  int cmax = 1, bmax = 1;
+  for (Problem* p : M.probs) {
+    cmax = std::max(cmax, (p->nmu + p->gmres_blocks - 1) / p->gmres_blocks);
+    bmax = std::max(bmax, p->gmres_blocks);
+  }
+  // groups are sized for the widest kernel that holds the largest instance;
+  // the launch then picks the widest kernel each group's grid fits
+  int cap = 0;
+  for (;;) {
+    cap = INT_MAX;
+    for (Problem* p : M.probs) cap = std::min(cap, gmres_capacity(*p, kmax, cmax, width));
+    if (cap >= bmax || width == 1) break;
+    width = width == NRMAX ? 2 : 1;
+  }
   if (cap < 1) return fail(SFDP_E_DEVICE, "GMRES kernel does not fit in LDS (lower max_krylov)");
   std::vector<int> host(n, 0);  // first block of each instance within its group
   t.ggroups.clear();
@@ -467,8 +481,24 @@ sfdp_status multi_groups(Multi& M, int kmax, int width, int*& gmap, size_t& gcap
   t.first[K_GMRES] = gmap;
   for (size_t g = 0; g < t.ggroups.size(); ++g) t.ggroups[g].inst = gmap + g_off[g];
   M.g_kmax = kmax;
-  M.g_width = width;
+  M.g_width = asked;
   return SFDP_OK;
+}
+
+// GMRES blocks of an instance that shares launches with others: enough for
+// every block's multiplier chunk to stay near `chunk`, but no more than one
+// launch can hold at once (the widest kernel if possible, else the narrowest;
+// fewer blocks mean larger chunks and more LDS, hence the re-check).
+int shared_gmres_blocks(const Problem& p, int kmax, int chunk) {
+  int b = std::min(p.nsub, std::max(1, (p.nmu + chunk - 1) / chunk));
+  for (int w : {NRMAX, 1})
+    for (int it = 0; it < 8; ++it) {
+      const int cap = gmres_capacity(p, kmax, (p.nmu + b - 1) / b, w);
+      if (cap >= b) return b;
+      if (cap < 1) break;
+      b = cap;
+    }
+  return b;  // nothing fits: the launch reports it
 }
 
 // Upload the instance views (the stream must be idle).
@@ -521,7 +551,7 @@ constexpr unsigned IDENTITY_MAP = 0x03020100u;
 // single problem); dg / hg hold one Gathered record per problem.
 sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Multi* M, Gathered* dg,
                             Gathered* hg, double tol_kkt, double tol_inner, int max_outer, int kmax,
-                            const std::vector<sfdp_info*>& info) {
+                            const std::vector<sfdp_info*>& info, bool single) {
   const size_t n = ps.size();
   hipStream_t st = t.st;
   std::vector<int> ng(n);
@@ -577,10 +607,12 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
     HIPCHK(launch_make_rhs1(t));
     sfdp_status s = feti_run(t, timed, V_CVEC, 0, V_CVEC2, tol_inner, kmax);
     if (s) return s;
-    HIPCHK(launch_make_rhs2(t));
-    s = feti_run(t, timed, V_CVEC3, 0, V_CVEC, tol_inner, kmax);
-    if (s) return s;
-    HIPCHK(launch_update(t));
+    if (!single) {
+      HIPCHK(launch_make_rhs2(t));
+      s = feti_run(t, timed, V_CVEC3, 0, V_CVEC, tol_inner, kmax);
+      if (s) return s;
+    }
+    HIPCHK(launch_update(t, single ? 1 : 0));
     for (size_t i = 0; i < n; ++i)
       for (int c = 0; c < ps[i]->nr; ++c) loc[i][(ps[i]->map >> (8 * c)) & 255].outer_steps = step + 1;
   }
@@ -912,7 +944,7 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
     p->set_slots(ng, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, y + r0 * n, u + r0 * n,
                  lam + r0 * n);
     std::vector<sfdp_info*> inf{info ? info + r0 : nullptr};
-    s = range_space_run(t, ps, nullptr, dg, &hg, tk, ti, mo, kmax, inf);
+    s = range_space_run(t, ps, nullptr, dg, &hg, tk, ti, mo, kmax, inf, single_of(opts));
     p->nr = 0;
     if (s == SFDP_E_NOCONV) worst = s;
     else if (s) { hipFree(dg); return s; }
@@ -944,15 +976,19 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
     p->map = IDENTITY_MAP;
     HIPCHK(launch_fill_flags(t, 0, FLAG_WORDS));
     // factor 1: w = Z^-1 r ; middle: v = conj(M w) ; factor 2: z = Re conj(Z^-1 v) = Re Z^-1 v
+    // (one solve: z = -Im(w) / alpha)
     HIPCHK(launch_copy_real_to_complex(nr * n, r + r0 * n, p->cvec, st));
     s = feti_run(t, p, V_CVEC, 0, V_CVEC2, ti, kmax);
-    if (!s) {
+    if (!s && single_of(opts)) {
+      hipError_t e = launch_imag_scaled(nr * n, p->cvec2, -1.0 / p->alpha, z + r0 * n, st);
+      s = e == hipSuccess ? gather_one(p, g) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
+    } else if (!s) {
       hipError_t e = launch_make_rhs2(t);
       s = e == hipSuccess ? feti_run(t, p, V_CVEC3, 0, V_CVEC, ti, kmax) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
-    }
-    if (!s) {
-      hipError_t e = launch_real_part(nr * n, p->cvec, z + r0 * n, st);
-      s = e == hipSuccess ? gather_one(p, g) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
+      if (!s) {
+        e = launch_real_part(nr * n, p->cvec, z + r0 * n, st);
+        s = e == hipSuccess ? gather_one(p, g) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
+      }
     }
     p->nr = 0;
     if (s) return s;
@@ -962,10 +998,11 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
       for (int c = 0; c < nr; ++c) {
         sfdp_info& o = info[r0 + c];
         memset(&o, 0, sizeof(o));
-        o.n_feti = 2;
-        o.krylov_its[0] = g.h.flags[FLAG_LOG + 16 * c];
-        o.krylov_its[1] = g.h.flags[FLAG_LOG + 16 * c + 1];
-        o.krylov_total = o.krylov_its[0] + o.krylov_its[1];
+        o.n_feti = single_of(opts) ? 1 : 2;
+        for (int k = 0; k < o.n_feti; ++k) {
+          o.krylov_its[k] = g.h.flags[FLAG_LOG + 16 * c + k];
+          o.krylov_total += o.krylov_its[k];
+        }
       }
   }
   HIPCHK(ev_harvest(*p));
@@ -991,12 +1028,11 @@ sfdp_status sfdp_batch_create(sfdp_ctx* ctx, int count, const int* n_elem, int s
   }
   // GMRES blocks per instance: one per subdomain when all fit on the device at
   // once, otherwise enough to keep every block's multiplier chunk <= 192
+  HIPCHK(hipSetDevice(ctx->device));
   for (Problem* p : b->probs)
-    p->gmres_blocks = nsub_tot <= ctx->num_cu ? p->nsub
-                                              : std::min(p->nsub, std::max(1, (p->nmu + 191) / 192));
+    p->gmres_blocks = nsub_tot <= ctx->num_cu ? p->nsub : shared_gmres_blocks(*p, 64, 192);
   b->M.ctx = ctx;
   b->M.probs = b->probs;
-  HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   sfdp_status s = multi_maps(b->M);
   if (s) { delete b; return s; }
@@ -1072,7 +1108,9 @@ sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const d
       inf[i] = info ? info + ioff[i] + r0 : nullptr;
     }
     sfdp_status s = multi_groups(b->M, kmax, w == 1 ? 1 : w == 2 ? 2 : 4, b->gmap, b->gcap);
-    if (!s) s = range_space_run(b->M.t, b->probs, &b->M, b->M.dgather, b->M.hgather, tk, ti, mo, kmax, inf);
+    if (!s)
+      s = range_space_run(b->M.t, b->probs, &b->M, b->M.dgather, b->M.hgather, tk, ti, mo, kmax, inf,
+                          single_of(opts));
     for (Problem* p : b->probs) p->nr = 0;
     if (s == SFDP_E_NOCONV) worst = s;
     else if (s) return s;
@@ -1259,6 +1297,7 @@ struct sfdp_server {
   sfdp_precision prec = SFDP_MIXED;
   double tol_kkt = 0, tol_inner = 0;
   int max_outer = 0, kmax = 0;
+  bool single = false;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<SReq*> pending;              // submitted, not admitted
@@ -1278,6 +1317,7 @@ struct sfdp_server {
   int64_t n_submit = 0, n_complete = 0, n_failed = 0, n_setups = 0, n_evict = 0, n_ticks = 0;
   std::string worker_error;
   std::vector<SReq*> finished;  // decided by the worker, published under the lock
+  size_t pool_cap = 0;          // set-up scratch of one set-up pass (a larger instance passes alone)
 };
 
 namespace {
@@ -1312,6 +1352,7 @@ void server_finish(sfdp_server* S, SReq* r, sfdp_status st) {
 std::vector<SInst*> server_admit(sfdp_server* S, std::deque<SReq*>& pend) {
   std::vector<SInst*> fresh;
   Ctx* ctx = S->ctx;
+  size_t reserve = 0;  // factor bytes the fresh instances will allocate at set-up
   while (!pend.empty()) {
     SReq* r = pend.front();
     SInst* home = nullptr;
@@ -1319,12 +1360,18 @@ std::vector<SInst*> server_admit(sfdp_server* S, std::deque<SReq*>& pend) {
       if (in->n_elem == r->n_elem && in->sub_elem == r->sub_elem && in->beta == r->beta) home = in;
     if (!home) {
       size_t need = instance_bytes(r->n_elem, r->sub_elem, S->prec);
-      size_t pool_need = 0;
-      for (SInst* in : fresh) pool_need += setup_bytes(in->n_elem, in->sub_elem);
-      pool_need += setup_bytes(r->n_elem, r->sub_elem);
+      // the set-up passes' scratch: at most the pool cap per pass unless one
+      // instance alone needs more (the passes are chunked the same way)
+      size_t sum = setup_bytes(r->n_elem, r->sub_elem), big = sum;
+      for (SInst* in : fresh) {
+        const size_t b = setup_bytes(in->n_elem, in->sub_elem);
+        sum += b;
+        big = std::max(big, b);
+      }
+      const size_t pool_need = std::min(sum, std::max(S->pool_cap, big));
       // growing the pool frees the old one first: only the difference is new
       size_t pool_grow = pool_need > ctx->pool_bytes ? pool_need - ctx->pool_bytes : 0;
-      auto fits = [&]() { return !ctx->budget || ctx->used + need + pool_grow <= ctx->budget; };
+      auto fits = [&]() { return !ctx->budget || ctx->used + reserve + need + pool_grow <= ctx->budget; };
       // evict the least recently used idle instance (false if none)
       auto evict_one = [&]() {
         SInst* victim = nullptr;
@@ -1363,7 +1410,7 @@ std::vector<SInst*> server_admit(sfdp_server* S, std::deque<SReq*>& pend) {
       for (;;) {
         st = create_problem(ctx, 2, r->n_elem, r->sub_elem, S->prec, &p);
         if (!st) {
-          p->gmres_blocks = std::min(p->nsub, std::max(1, (p->nmu + 127) / 128));
+          p->gmres_blocks = shared_gmres_blocks(*p, S->kmax, 128);
           if ((st = alloc_workspace(*p, S->kmax)) || (st = alloc_rs(*p))) {
             destroy_problem(p);
             p = nullptr;
@@ -1379,6 +1426,7 @@ std::vector<SInst*> server_admit(sfdp_server* S, std::deque<SReq*>& pend) {
         server_finish(S, r, st == SFDP_E_NOMEM ? SFDP_E_ADMIT : st);
         continue;
       }
+      reserve += need > p->bytes ? need - p->bytes : 0;
       home = new SInst();
       home->p = p;
       home->n_elem = r->n_elem;
@@ -1525,10 +1573,12 @@ sfdp_status server_tick(sfdp_server* S) {
   HIPCHK(launch_make_rhs1(t));
   s = feti_run(t, nullptr, V_CVEC, 0, V_CVEC2, S->tol_inner, S->kmax);
   if (s) return s;
-  HIPCHK(launch_make_rhs2(t));
-  s = feti_run(t, nullptr, V_CVEC3, 0, V_CVEC, S->tol_inner, S->kmax);
-  if (s) return s;
-  HIPCHK(launch_update(t));
+  if (!S->single) {
+    HIPCHK(launch_make_rhs2(t));
+    s = feti_run(t, nullptr, V_CVEC3, 0, V_CVEC, S->tol_inner, S->kmax);
+    if (s) return s;
+  }
+  HIPCHK(launch_update(t, S->single ? 1 : 0));
   for (size_t i = 0; i < n; ++i)
     for (int c = 0; c < act[i]->nr; ++c) ains[i]->slot[(act[i]->map >> (8 * c)) & 255].info.outer_steps += 1;
   for (Problem* p : act) p->nr = 0;
@@ -1555,21 +1605,36 @@ void server_loop(sfdp_server* S) {
     std::vector<SInst*> fresh = server_admit(S, pend);
     sfdp_status st = SFDP_OK;
     if (!fresh.empty()) {
-      std::vector<Problem*> ps;
-      for (SInst* in : fresh) ps.push_back(in->p);
-      Multi Mf;
-      Mf.ctx = S->ctx;
-      Mf.probs = ps;
-      st = multi_maps(Mf);
-      if (!st) st = setup_run(Mf.t, ps, &Mf);
+      // set-up passes over consecutive fresh instances whose scratch fits the
+      // pool (grown to the pool cap, or to one instance that needs more)
+      const size_t lim = std::max(S->pool_cap, S->ctx->pool_bytes);
+      for (size_t i = 0; i < fresh.size() && !st;) {
+        std::vector<Problem*> ps;
+        size_t sum = 0;
+        for (; i < fresh.size(); ++i) {
+          const size_t b = setup_bytes(fresh[i]->n_elem, fresh[i]->sub_elem);
+          if (!ps.empty() && sum + b > lim) break;
+          ps.push_back(fresh[i]->p);
+          sum += b;
+        }
+        Multi Mf;
+        Mf.ctx = S->ctx;
+        Mf.probs = ps;
+        st = multi_maps(Mf);
+        if (!st) st = setup_run(Mf.t, ps, &Mf);
+        if (!st) S->n_setups += (int64_t)ps.size();
+      }
       if (st == SFDP_E_NOMEM) {
-        // drop the new instances; their requests wait (or are refused when
-        // nothing running could free memory)
+        // drop the new instances that did not get their factors; their
+        // requests wait (or are refused when nothing running could free memory)
+        std::vector<SInst*> lost;
+        for (SInst* in : fresh)
+          if (!in->p->factored) lost.push_back(in);
         bool busy = false;
         for (SInst* in : S->insts)
-          if (std::find(fresh.begin(), fresh.end(), in) == fresh.end()) busy = busy || in->busy();
+          if (std::find(lost.begin(), lost.end(), in) == lost.end()) busy = busy || in->busy();
         std::vector<SReq*> back;
-        for (SInst* in : fresh) {
+        for (SInst* in : lost) {
           for (SReq* r : in->queue) back.push_back(r);
           S->insts.erase(std::find(S->insts.begin(), S->insts.end(), in));
           destroy_problem(in->p);
@@ -1586,8 +1651,6 @@ void server_loop(sfdp_server* S) {
           }
         }
         st = SFDP_OK;
-      } else {
-        S->n_setups += (int64_t)fresh.size();
       }
     }
     if (!st) st = server_tick(S);
@@ -1633,6 +1696,8 @@ sfdp_status sfdp_server_create(sfdp_ctx* ctx, sfdp_precision prec, const sfdp_op
   S->ctx = ctx;
   S->prec = prec;
   defaults(prec, opts, S->tol_kkt, S->tol_inner, S->max_outer, S->kmax);
+  S->single = single_of(opts);
+  S->pool_cap = ctx->budget ? ctx->budget / 16 : (size_t)4 << 30;
   S->worker = std::thread(server_loop, S);
   *out = S;
   return SFDP_OK;

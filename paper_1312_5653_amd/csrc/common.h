@@ -454,12 +454,13 @@ int64_t red_pstride(const Problem& p);
 hipError_t launch_kkt_residual(const Target& t);
 hipError_t launch_make_rhs1(const Target& t);
 hipError_t launch_make_rhs2(const Target& t);
-hipError_t launch_update(const Target& t);
+hipError_t launch_update(const Target& t, int single);  // single: one complex solve per step
 hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t st);
 hipError_t launch_fill_flags(const Target& t, int first, int count);
 hipError_t launch_copy_real_to_complex(int64_t n, const double* x, cd* y, hipStream_t st);
 hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t st);
 hipError_t launch_real_part(int64_t n, const cd* x, double* y, hipStream_t st);
+hipError_t launch_imag_scaled(int64_t n, const cd* x, double s, double* y, hipStream_t st);  // y = s Im x
 hipError_t launch_group_init(const Target& t);  // y = ybar, u = lam = 0 for the views' init slots
 hipError_t launch_gather(const Target& t, Gathered* out);  // out[i]: instance i of the target
 

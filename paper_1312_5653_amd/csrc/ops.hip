@@ -195,9 +195,10 @@ __global__ void k_make_rhs1(Src src) {
 }
 
 // y -= Re dw; lam += Re z; u = lam / beta (dw = cvec2, z = cvec); partial sums
-// of |Im z|^2, |Re z|^2
+// of |Im z|^2, |Re z|^2.  single: one complex solve per step, lam -= Im dw / alpha
+// (no second factor; the partial sums are zero).
 template <class Src>
-__global__ void __launch_bounds__(256) k_update(Src src) {
+__global__ void __launch_bounds__(256) k_update(Src src, int single) {
   __shared__ double sh[2][4];
   const Dev& d = src.dev();
   const int c = blockIdx.y;
@@ -214,11 +215,13 @@ __global__ void __launch_bounds__(256) k_update(Src src) {
   double im = 0.0, re = 0.0;
   if (t < n) {
     y[t] -= dw[t].x;
-    double l = lam[t] + z[t].x;
+    double l = single ? lam[t] - dw[t].y / d.g.alpha : lam[t] + z[t].x;
     lam[t] = l;
     u[t] = l / d.beta;
-    im = z[t].y * z[t].y;
-    re = z[t].x * z[t].x;
+    if (!single) {
+      im = z[t].y * z[t].y;
+      re = z[t].x * z[t].x;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     im += __shfl_down(im, off, 64);
@@ -268,6 +271,11 @@ __global__ void k_gather(Src src, Gathered* out) {
   for (int i = threadIdx.x; i < FLAG_WORDS; i += blockDim.x) o.flags[i] = d.flags[i];
 }
 
+__global__ void k_imag_scaled(int64_t n, const cd* x, double s, double* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = s * x[i].y;
+}
+
 __global__ void k_real_part(int64_t n, const cd* x, double* y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = x[i].x;
@@ -315,8 +323,8 @@ hipError_t launch_make_rhs2(const Target& t) {
   launch2(t, K_NF256, k_make_rhs2<One>, k_make_rhs2<Many>, NRMAX, 256, 0);
   return hipGetLastError();
 }
-hipError_t launch_update(const Target& t) {
-  launch2(t, K_NF256, k_update<One>, k_update<Many>, NRMAX, 256, 0);
+hipError_t launch_update(const Target& t, int single) {
+  launch2(t, K_NF256, k_update<One>, k_update<Many>, NRMAX, 256, 0, single);
   launch2(t, K_ONE, k_reduce_ratio<One>, k_reduce_ratio<Many>, NRMAX, 256, 0, 1);
   return hipGetLastError();
 }
@@ -330,6 +338,10 @@ hipError_t launch_fill_flags(const Target& t, int first, int count) {
 }
 hipError_t launch_gather(const Target& t, Gathered* out) {
   launch2(t, K_ONE, k_gather<One>, k_gather<Many>, 1, 128, 0, out);
+  return hipGetLastError();
+}
+hipError_t launch_imag_scaled(int64_t n, const cd* x, double s, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_imag_scaled, dim3(nblk(n)), dim3(256), 0, st, n, x, s, y);
   return hipGetLastError();
 }
 hipError_t launch_real_part(int64_t n, const cd* x, double* y, hipStream_t st) {

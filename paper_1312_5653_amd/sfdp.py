@@ -36,7 +36,8 @@ class SfdpError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tol_kkt", ctypes.c_double), ("tol_inner", ctypes.c_double),
-                ("max_outer", ctypes.c_int), ("max_krylov", ctypes.c_int), ("batch", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("max_krylov", ctypes.c_int), ("factors", ctypes.c_int),
+                ("batch", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -148,8 +149,8 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(tol_kkt=0.0, tol_inner=0.0, max_outer=0, max_krylov=0, batch=0):
-    return Opts(tol_kkt, tol_inner, max_outer, max_krylov, batch)
+def _opts(tol_kkt=0.0, tol_inner=0.0, max_outer=0, max_krylov=0, batch=0, factors=0):
+    return Opts(tol_kkt, tol_inner, max_outer, max_krylov, factors, batch)
 
 
 class Context:
@@ -360,14 +361,14 @@ class Server:
         self._live = {}
 
     def submit(self, n_elem: int, sub_elem: int, beta: float, ybar, yc=None):
-        """ybar: (nrhs, n_free) or (n_free,) CUDA tensor (kept alive until polled).
+        """ybar: (nrhs, n_free) or (n_free,) CUDA tensor whose values are ready
+        (the caller synchronises after producing them); kept alive until polled.
         Returns a ticket; the outputs are allocated here."""
         import torch
         if not ybar.is_cuda or not ybar.is_contiguous():
             raise ValueError("arrays must be contiguous CUDA tensors")
         nrhs = 1 if ybar.dim() == 1 else ybar.shape[0]
         y, u, lam = (torch.empty_like(ybar) for _ in range(3))
-        torch.cuda.synchronize()
         req = Request(2, n_elem, sub_elem, float(beta), nrhs, ybar.data_ptr(),
                       yc.data_ptr() if yc is not None else None, y.data_ptr(), u.data_ptr(), lam.data_ptr())
         t = ctypes.c_uint64()

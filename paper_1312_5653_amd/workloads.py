@@ -105,3 +105,21 @@ def c4_instances(count: int, seed: int, sub_elem: int = 32):
         beta = float(10.0 ** rng.uniform(-6, -1))
         out.append({"N": max(N, 2 * sub_elem), "beta": beta, "seed": seed * 100003 + j})
     return out
+
+
+def c5_requests(count: int, seed: int, mean_gap_ms: float = 5.0, sub_elem: int = 32):
+    """Served request stream: exponential inter-arrival gaps (mean mean_gap_ms),
+    2D meshes N = sub_elem * round(exp(U[ln 128, ln 1024]) / sub_elem), beta =
+    10^U[-6,-1], nrhs uniform in 1..8, targets of 16 sine modes seeded by
+    (seed, request)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for j in range(count):
+        t += float(rng.exponential(mean_gap_ms))
+        N = int(sub_elem * round(np.exp(rng.uniform(np.log(128), np.log(1024))) / sub_elem))
+        beta = float(10.0 ** rng.uniform(-6, -1))
+        nrhs = int(rng.integers(1, 9))
+        out.append({"arrival_ms": t, "N": max(N, 2 * sub_elem), "beta": beta, "nrhs": nrhs,
+                    "seed": seed * 100003 + j})
+    return out

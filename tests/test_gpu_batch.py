@@ -183,3 +183,44 @@ def test_mixed_iface_mode(sf):
         rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar[q], yc[q], y[q], u[q], lam[q])
         assert rho <= 1e-9, (q, rho, info[q])
     prob.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_single_solve_variant(sf, prec):
+    """opts.factors = 1: Z (dy + i alpha dlam) = r3 + i alpha r1, one FETI-DP solve per
+    refinement step (the first factor alone): the same solution as the two-factor
+    form, half the FETI-DP solves."""
+    sfdp, ctx = sf
+    N, m, beta = 64, 8, 1e-4
+    tol = 1e-10 if prec == 0 else 1e-8
+    ybar, yc = _targets(N)
+    ybar, yc = ybar[[0, 1, 3]], yc[[0, 1, 3]]
+    mesh = fem.Mesh(2, N)
+    A = fem.assemble(mesh)
+    prob = sfdp.Problem(ctx, 2, N, m, prec)
+    prob.set_beta(beta)
+    y2, u2, l2, info2, st2 = prob.solve_range_space(_t(ybar), _t(yc), tol_kkt=tol)
+    y1, u1, l1, info1, st1 = prob.solve_range_space(_t(ybar), _t(yc), tol_kkt=tol, factors=1)
+    assert st1 == 0 and st2 == 0
+    for q in range(3):
+        assert info1[q]["n_feti"] == info1[q]["outer_steps"] and info2[q]["n_feti"] == 2 * info2[q]["outer_steps"]
+        ya, ua, la = y1[q].cpu().numpy(), u1[q].cpu().numpy(), l1[q].cpu().numpy()
+        rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar[q], yc[q], ya, ua, la)
+        ref = solve.range_space_one_solve(A["K"], A["M"], A["Kc"], beta, ybar[q], yc[q])
+        rho_ref = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar[q], yc[q], ref["y"], ref["u"], ref["lam"])
+        assert rho <= max(tol, 2 * rho_ref), (q, rho)
+        bound = 1e-9 if prec == 0 else 1e-5
+        assert _rel(la, l2[q].cpu().numpy()) < bound and _rel(ya, y2[q].cpu().numpy()) < bound, q
+    # S^-1 r = -Im(Z^-1 r) / alpha with one solve
+    S = solve.dense_schur(fem.assemble(fem.Mesh(2, 16))["K"], fem.assemble(fem.Mesh(2, 16))["M"], 3e-3)
+    p16 = sfdp.Problem(ctx, 2, 16, 4, prec)
+    p16.set_beta(3e-3)
+    r = np.stack([W.random_vector(225, 50 + q) for q in range(3)])
+    z, info = p16.apply_schur_inv(_t(r), tol_inner=1e-13, factors=1)
+    assert all(i["n_feti"] == 1 for i in info)
+    for q in range(3):
+        # Im(w) is the smaller part of w for rough r (Re w = M^-1 K lam), so the
+        # complex64 operators' rounding shows more in it
+        assert _rel(z[q].cpu().numpy(), np.linalg.solve(S, r[q])) < (1e-8 if prec == 0 else 1e-4)
+    p16.close()
+    prob.close()

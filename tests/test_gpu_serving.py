@@ -135,3 +135,28 @@ def test_memory_admission(sfdp):
     assert e.value.status == -6
     srv.close()
     ctx.close()
+
+
+def test_large_instances_share_launches(sfdp):
+    """A 1024^2 mesh (32 x 32 subdomains, 61504 multipliers) in the same ticks as
+    smaller ones: every instance takes no more GMRES blocks than one launch can
+    hold at once, and the shared launches narrow their width when the largest
+    instance needs it."""
+    ctx = sfdp.Context(0)
+    srv = sfdp.Server(ctx, sfdp.SFDP_MIXED, tol_kkt=1e-8)
+    reqs = [(1024, 32, 1e-4, 2), (768, 32, 1e-6, 1), (128, 32, 1e-2, 3)]
+    data = [_targets(N, 40 + i, k) for i, (N, m, b, k) in enumerate(reqs)]
+    tickets = [srv.submit(N, m, b, _t(d[0])) for (N, m, b, k), d in zip(reqs, data)]
+    for (N, m, b, k), d, tk in zip(reqs, data, tickets):
+        y, u, lam, info, lat, st = srv.poll(tk)
+        assert st == 0, (N, info)
+        A = fem.assemble(fem.Mesh(2, N))
+        z = np.zeros(A["Kc"].shape[1])
+        for r in range(k):
+            rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], b, d[0][r], z, y[r].cpu().numpy(), u[r].cpu().numpy(),
+                              lam[r].cpu().numpy())
+            assert rho <= 1e-8, (N, r, rho, info[r])
+    s = srv.stats()
+    assert s["completed"] == 3 and s["failed"] == 0, s
+    srv.close()
+    ctx.close()
