@@ -646,46 +646,54 @@ __global__ void k_assemble(Src src, int xsel, int conj_out) {
 // the persistent GMRES kernel and the stand-alone test kernels).  Vectors of RHS
 // r are r-major copies: base + r * stride.  A scale of zero switches an RHS off.
 
-// y_r = S x_r for r < NRT with S packed in LDS (nd <= 128); thread (i, half)
-// sums half of the k range, half 1 hands its partial sums to half 0 through red,
-// and half 0 stores y_r[i] coherently to out + r * ostride + i.
+// y_r = S x_r for r < NRT with S complex symmetric, packed by rows in LDS
+// (entry (i, k), k <= i, at i (i + 1) / 2 + k; nd <= 128).  Row i belongs to the
+// lane pair 2i, 2i + 1 of one wave: lane parity p sums the terms k = p, p + 2, ...
+// (the entry at row i for k <= i, else at row k), so every lane runs the same
+// number of steps.  Steps go in groups of U whose LDS loads are all issued
+// before the group's arithmetic (a step past the end reloads a valid entry and
+// contributes zero).  A shuffle adds the pair, and the even lane stores y_r[i]
+// coherently to out + r * ostride + i.
 template <class TM, class R, int NRT>
-__device__ inline void symv_packed_nr(const TM* A, int nd, const C<R>* xs, C<R>* red, cd* out,
-                                      int64_t ostride, int nr) {
-  const int i = threadIdx.x & 127, half = threadIdx.x >> 7;
-  const int h = (nd + 1) / 2;
-  const int k0 = half ? h : 0, k1 = half ? nd : h;
+__device__ inline void symv_packed_nr(const TM* A, int nd, const C<R>* xs, cd* out, int64_t ostride,
+                                      int nr) {
+  constexpr int U = NRT >= 4 ? 2 : 4;
+  const int i = threadIdx.x >> 1, p = threadIdx.x & 1;
   C<R> acc[NRT];
 #pragma unroll
   for (int r = 0; r < NRT; ++r) acc[r] = C<R>{0, 0};
   if (i < nd) {
     const int rb = i * (i + 1) / 2;
-    const int kr = min(k1, i + 1);
-    for (int k = k0; k < kr; ++k) {
-      C<R> a = cvt<R>(A[rb + k]);
+    const int steps = (nd - p + 1) >> 1;  // k = p + 2 t for t < steps
+    for (int t0 = 0; t0 < steps; t0 += U) {
+      TM araw[U];
+      C<R> x[U][NRT];
 #pragma unroll
-      for (int r = 0; r < NRT; ++r) fma_acc(acc[r], a, xs[k * NRT + r]);
-    }
-    int k = max(k0, i + 1);
-    int cb = k * (k + 1) / 2;
-    for (; k < k1; ++k) {
-      C<R> a = cvt<R>(A[cb + i]);
+      for (int u = 0; u < U; ++u) {
+        const int k = p + 2 * min(t0 + u, steps - 1);
+        araw[u] = A[k <= i ? rb + k : ((k * (k + 1)) >> 1) + i];
 #pragma unroll
-      for (int r = 0; r < NRT; ++r) fma_acc(acc[r], a, xs[k * NRT + r]);
-      cb += k + 1;
+        for (int r = 0; r < NRT; ++r) x[u][r] = xs[k * NRT + r];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        C<R> a = cvt<R>(araw[u]);
+        if (t0 + u >= steps) a = C<R>{0, 0};
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) fma_acc(acc[r], a, x[u][r]);
+      }
     }
   }
-  if (half == 1 && i < nd) {
 #pragma unroll
-    for (int r = 0; r < NRT; ++r) red[i * NRT + r] = acc[r];
+  for (int r = 0; r < NRT; ++r) {
+    acc[r].x += __shfl_xor(acc[r].x, 1, 64);
+    acc[r].y += __shfl_xor(acc[r].y, 1, 64);
   }
-  __syncthreads();
-  if (half == 0 && i < nd) {
+  if (p == 0 && i < nd) {
 #pragma unroll
     for (int r = 0; r < NRT; ++r) {
       if (r >= nr) break;
-      C<R> v = acc[r] + red[i * NRT + r];
-      st_coh(out + r * ostride + i, cd{(double)v.x, (double)v.y});
+      st_coh(out + r * ostride + i, cd{(double)acc[r].x, (double)acc[r].y});
     }
   }
   __syncthreads();
@@ -717,7 +725,7 @@ __device__ void phase_precond(const Geo2& g, const Maps2& mp, const cf* __restri
     }
   }
   __syncthreads();
-  symv_packed_nr<cf, R, NRT>(buf, nd, xs, red, Abuf + (size_t)s * ND, astride, nr);
+  symv_packed_nr<cf, R, NRT>(buf, nd, xs, Abuf + (size_t)s * ND, astride, nr);
 }
 
 // Ybuf_r[s] = Z_rr^-1|Delta x_r,  Cbuf_r[s] = Phi^T x_r.  x_r from Abuf_r (the
@@ -756,15 +764,26 @@ __device__ void phase_f1(const Geo2& g, const Maps2& mp, const RhsStride& rs,
       xs[i * NRT + r] = (r < nr && sc[r] != 0.0) ? C<R>{(R)m[r].x, (R)m[r].y} : C<R>{0, 0};
   }
   __syncthreads();
-  symv_packed_nr<TS, R, NRT>(buf, nd, xs, red, Ybuf + (size_t)s * ND, rs.sb, nr);
-  // corner products: one wavefront per corner slot
+  // corner products: one wavefront per corner slot; lane l takes rows l and
+  // l + 64 (nd <= 128), whose F_rc entries load under the Schur product
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const bool has_q = mp.cloc[s * 4 + q] >= 0;
+  TS phr[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = lane + 64 * h;
+    phr[h] = (has_q && i < nd) ? Phi[((size_t)s * ND + i) * 4 + q] : TS{0, 0};
+  }
+  symv_packed_nr<TS, R, NRT>(buf, nd, xs, Ybuf + (size_t)s * ND, rs.sb, nr);
   cd acc[NRT];
 #pragma unroll
   for (int r = 0; r < NRT; ++r) acc[r] = cd{0.0, 0.0};
-  if (mp.cloc[s * 4 + q] >= 0) {
-    for (int i = lane; i < nd; i += 64) {
-      cd ph = cvt<double>(Phi[((size_t)s * ND + i) * 4 + q]);
+  if (has_q) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      if (i >= nd) break;
+      const cd ph = cvt<double>(phr[h]);
 #pragma unroll
       for (int r = 0; r < NRT; ++r) {
         C<R> x = xs[i * NRT + r];
@@ -797,6 +816,16 @@ __device__ void phase_f2(const Geo2& g, const Maps2& mp, const RhsStride& rs,
   int cq[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) cq[q] = mp.cgid[s * 4 + q];
+  // thread i < nd (nd <= ND <= 128 < blockDim) updates Delta row i at the end: its
+  // F_rc row and the F1 result are loaded now, under the coarse product
+  const int i = threadIdx.x;
+  cd ph[4], yv[NRT];
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq)
+    ph[qq] = (i < nd && cq[qq] >= 0) ? cvt<double>(Phi[((size_t)s * ND + i) * 4 + qq]) : cd{0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < NRT; ++r)
+    yv[r] = (i < nd && r < nr) ? ld_coh(Ybuf + r * rs.sb + (size_t)s * ND + i) : cd{0.0, 0.0};
   cd acc[4][NRT];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
@@ -864,19 +893,14 @@ __device__ void phase_f2(const Geo2& g, const Maps2& mp, const RhsStride& rs,
                        (wred[(8 + q) * NRT + r] + wred[(12 + q) * NRT + r]);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-    cd ph[4];
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq)
-      ph[qq] = cq[qq] >= 0 ? cvt<double>(Phi[((size_t)s * ND + i) * 4 + qq]) : cd{0.0, 0.0};
+  if (i < nd) {
 #pragma unroll
     for (int r = 0; r < NRT; ++r) {
       if (r >= nr) break;
-      cd* yp = Ybuf + r * rs.sb + (size_t)s * ND + i;
-      cd y = ld_coh(yp);
+      cd y = yv[r];
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) fma_acc(y, ph[qq], ucs[qq * NRT + r]);
-      st_coh(yp, y);
+      st_coh(Ybuf + r * rs.sb + (size_t)s * ND + i, y);
     }
   }
 }
