@@ -646,14 +646,26 @@ __global__ void k_assemble(Src src, int xsel, int conj_out) {
 // the persistent GMRES kernel and the stand-alone test kernels).  Vectors of RHS
 // r are r-major copies: base + r * stride.  A scale of zero switches an RHS off.
 
+// Rows of the x staging array of the interface products: nd <= 128 plus the
+// zero rows [nd, nd + 16) that the pipelined product reads past the end.
+constexpr int XS_ROWS = 144;
+
+// Zero rows nd .. nd + 15 of xs (NRT values per row).
+template <class R, int NRT>
+__device__ inline void xs_zero_tail(C<R>* xs, int nd) {
+  for (int t = threadIdx.x; t < 16 * NRT; t += blockDim.x) xs[nd * NRT + t] = C<R>{0, 0};
+}
+
 // y_r = S x_r for r < NRT with S complex symmetric, packed by rows in LDS
 // (entry (i, k), k <= i, at i (i + 1) / 2 + k; nd <= 128).  Row i belongs to the
 // lane pair 2i, 2i + 1 of one wave: lane parity p sums the terms k = p, p + 2, ...
 // (the entry at row i for k <= i, else at row k), so every lane runs the same
-// number of steps.  Steps go in groups of U whose LDS loads are all issued
-// before the group's arithmetic (a step past the end reloads a valid entry and
-// contributes zero).  A shuffle adds the pair, and the even lane stores y_r[i]
-// coherently to out + r * ostride + i.
+// number of steps.  Steps go in groups of U, software-pipelined over two
+// register buffers: the LDS loads of the next group are in flight while the
+// current group's multiply-adds run.  Steps past the end read the zero rows of
+// xs at an entry offset clamped to the last valid one, so they add nothing.  A
+// shuffle adds the pair, and the even lane stores y_r[i] coherently to
+// out + r * ostride + i.
 template <class TM, class R, int NRT>
 __device__ inline void symv_packed_nr(const TM* A, int nd, const C<R>* xs, cd* out, int64_t ostride,
                                       int nr) {
@@ -664,24 +676,35 @@ __device__ inline void symv_packed_nr(const TM* A, int nd, const C<R>* xs, cd* o
   for (int r = 0; r < NRT; ++r) acc[r] = C<R>{0, 0};
   if (i < nd) {
     const int rb = i * (i + 1) / 2;
-    const int steps = (nd - p + 1) >> 1;  // k = p + 2 t for t < steps
-    for (int t0 = 0; t0 < steps; t0 += U) {
-      TM araw[U];
-      C<R> x[U][NRT];
+    const int steps = (nd - p + 1) >> 1;  // k = p + 2 t for t < steps; k < nd + 4 U - 2 is read
+    TM aA[U], aB[U];
+    C<R> xA[U][NRT], xB[U][NRT];
+    auto load = [&](int t0, TM* ar, C<R> (*x)[NRT]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int k = p + 2 * min(t0 + u, steps - 1);
-        araw[u] = A[k <= i ? rb + k : ((k * (k + 1)) >> 1) + i];
+        const int k = p + 2 * (t0 + u);
+        const int kc = min(k, nd - 1);
+        const int lo = rb + kc, hi = (int)(__umul24((unsigned)kc, (unsigned)kc + 1u) >> 1) + i;
+        ar[u] = A[kc <= i ? lo : hi];
 #pragma unroll
         for (int r = 0; r < NRT; ++r) x[u][r] = xs[k * NRT + r];
       }
+    };
+    auto madd = [&](const TM* ar, const C<R> (*x)[NRT]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        C<R> a = cvt<R>(araw[u]);
-        if (t0 + u >= steps) a = C<R>{0, 0};
+        const C<R> a = cvt<R>(ar[u]);
 #pragma unroll
         for (int r = 0; r < NRT; ++r) fma_acc(acc[r], a, x[u][r]);
       }
+    };
+    load(0, aA, xA);
+    for (int t0 = 0; t0 < steps; t0 += 2 * U) {
+      load(t0 + U, aB, xB);
+      madd(aA, xA);
+      if (t0 + U >= steps) break;
+      load(t0 + 2 * U, aA, xA);
+      madd(aB, xB);
     }
   }
 #pragma unroll
@@ -724,6 +747,7 @@ __device__ void phase_precond(const Geo2& g, const Maps2& mp, const cf* __restri
       xs[i * NRT + r] = (r < nr && sc[r] != 0.0) ? C<R>{(R)v.x, (R)v.y} : C<R>{0, 0};
     }
   }
+  xs_zero_tail<R, NRT>(xs, nd);
   __syncthreads();
   symv_packed_nr<cf, R, NRT>(buf, nd, xs, Abuf + (size_t)s * ND, astride, nr);
 }
@@ -763,6 +787,7 @@ __device__ void phase_f1(const Geo2& g, const Maps2& mp, const RhsStride& rs,
     for (int r = 0; r < NRT; ++r)
       xs[i * NRT + r] = (r < nr && sc[r] != 0.0) ? C<R>{(R)m[r].x, (R)m[r].y} : C<R>{0, 0};
   }
+  xs_zero_tail<R, NRT>(xs, nd);
   __syncthreads();
   // corner products: one wavefront per corner slot; lane l takes rows l and
   // l + 64 (nd <= 128), whose F_rc entries load under the Schur product
@@ -950,7 +975,7 @@ static size_t gmres_layout(int nrt, int kmax, int chunk, size_t tsz, size_t byte
                            bool resident, GmresLaunch* a) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align16(bytes); return (int)at; };
-  int red = take(tsz * 128 * nrt), xs = take(tsz * 128 * nrt);
+  int red = take(sizeof(cd) * 16 * nrt), xs = take(tsz * XS_ROWS * nrt);
   int wch = take(sizeof(cd) * nrt * chunk);
   int hv = take(sizeof(cd) * nrt * (kmax + 1)), h2 = take(sizeof(cd) * nrt * (kmax + 1));
   int cs = take(sizeof(cd) * nrt * (kmax + 1)), sn = take(sizeof(double) * nrt * (kmax + 1));
@@ -1272,7 +1297,7 @@ __global__ void __launch_bounds__(256) k_iface_precond(Geo2 g, Maps2 mp, const c
                                                        cd* Abuf) {
   using R = double;  // FP64 arithmetic for both storage precisions
   extern __shared__ __align__(16) char smem[];
-  __shared__ C<R> red[128], xs[128];
+  __shared__ C<R> red[128], xs[XS_ROWS];
   __shared__ double sc[1];
   if (threadIdx.x == 0) sc[0] = 1.0;
   phase_precond<TS, 1>(g, mp, Sbb, blockIdx.x, x, 0, sc, Abuf, 0, 1, (cf*)smem, false, xs, red);
@@ -1282,7 +1307,7 @@ __global__ void __launch_bounds__(256) k_iface_f1(Geo2 g, Maps2 mp, RhsStride rs
                                                   const TS* Phi, const cd* x, cd* Ybuf, cd* Cbuf) {
   using R = double;  // FP64 arithmetic for both storage precisions
   extern __shared__ __align__(16) char smem[];
-  __shared__ C<R> red[128], xs[128];
+  __shared__ C<R> red[128], xs[XS_ROWS];
   __shared__ double sc[1];
   if (threadIdx.x == 0) sc[0] = 1.0;
   phase_f1<TS, 1>(g, mp, rs, Sinv, Phi, blockIdx.x, false, nullptr, x, sc, Ybuf, Cbuf, 1, (TS*)smem,
