@@ -577,7 +577,6 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
     HIPCHK(launch_gather(t, dg));
     HIPCHK(hipMemcpyAsync(hg, dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (timed) HIPCHK(ev_harvest(*timed));
     bool any = false;
     for (size_t i = 0; i < n; ++i) {
       Problem* p = ps[i];
@@ -619,6 +618,7 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
   HIPCHK(launch_gather(t, dg));
   HIPCHK(hipMemcpyAsync(hg, dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  if (timed) HIPCHK(ev_harvest(*timed));
   sfdp_status status = SFDP_OK;
   for (size_t i = 0; i < n; ++i) {
     const int* fl = hg[i].flags;
@@ -705,6 +705,8 @@ void destroy_problem(Problem* p) {
                  p->bar, p->flags, p->r1, p->r2, p->r3, p->red, p->cvec, p->cvec2, p->cvec3};
   for (void* a : arr)
     if (a) hipFree(a);
+  if (p->gd) hipFree(p->gd);
+  if (p->gh) hipHostFree(p->gh);
   for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
   p->ctx->used -= std::min(p->ctx->used, p->bytes);
   delete p;
@@ -740,17 +742,26 @@ Target single_target(Problem* p) {
   return t;
 }
 
-// One Gathered record of a single problem (device buffer reused per call).
-struct OneGather {
-  Gathered* d = nullptr;
-  Gathered h;
-  ~OneGather() { if (d) hipFree(d); }
-};
-sfdp_status gather_one(Problem* p, OneGather& g) {
-  if (!g.d && hipMalloc(&g.d, sizeof(Gathered))) return fail(SFDP_E_NOMEM, "gather buffer");
+// The problem's gather buffers (device record and its pinned host copy),
+// allocated on first use and kept until the problem is destroyed.
+sfdp_status gather_buffers(Problem& p) {
+  if (p.gd) return SFDP_OK;
+  sfdp_status s = dalloc(p, (void**)&p.gd, sizeof(Gathered));
+  if (s) return s;
+  if (hipHostMalloc((void**)&p.gh, sizeof(Gathered)) != hipSuccess) {
+    p.gh = nullptr;
+    return fail(SFDP_E_NOMEM, "pinned gather buffer");
+  }
+  return SFDP_OK;
+}
+
+// One Gathered record of a single problem into p->gh (waits for the stream).
+sfdp_status gather_one(Problem* p) {
+  sfdp_status s = gather_buffers(*p);
+  if (s) return s;
   Target t = single_target(p);
-  HIPCHK(launch_gather(t, g.d));
-  HIPCHK(hipMemcpyAsync(&g.h, g.d, sizeof(Gathered), hipMemcpyDeviceToHost, t.st));
+  HIPCHK(launch_gather(t, p->gd));
+  HIPCHK(hipMemcpyAsync(p->gh, p->gd, sizeof(Gathered), hipMemcpyDeviceToHost, t.st));
   HIPCHK(hipStreamSynchronize(t.st));
   return SFDP_OK;
 }
@@ -858,7 +869,6 @@ sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double*
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax))) return s;
   Target t = single_target(p);
-  OneGather g;
   int trips = 0, rhs_its = 0;
   for (int r0 = 0; r0 < nrhs; r0 += bsz) {
     const int nr = std::min(bsz, nrhs - r0);
@@ -868,16 +878,16 @@ sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double*
     p->ux = (cd*)x + (size_t)r0 * p->n_free;
     HIPCHK(launch_fill_flags(t, 0, FLAG_WORDS));
     s = feti_run(t, p, V_UF, conj_z ? 1 : 0, V_UX, ti, kmax);
-    if (!s) s = gather_one(p, g);
+    if (!s) s = gather_one(p);
     p->nr = 0;
     p->uf = nullptr;
     p->ux = nullptr;
     if (s) return s;
-    if (g.h.flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
-    trips += g.h.flags[3];
-    rhs_its += g.h.flags[4];
+    if (p->gh->flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
+    trips += p->gh->flags[3];
+    rhs_its += p->gh->flags[4];
     if (krylov_its)
-      for (int c = 0; c < nr; ++c) krylov_its[r0 + c] = g.h.flags[FLAG_ITS + c];
+      for (int c = 0; c < nr; ++c) krylov_its[r0 + c] = p->gh->flags[FLAG_ITS + c];
   }
   HIPCHK(ev_harvest(*p));
   if (p->timing) { p->it_gmres += trips; p->it_rhs += rhs_its; }
@@ -903,7 +913,6 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
   if (s) return s;
   const size_t n = p->n_free;
   Target t = single_target(p);
-  OneGather g;
   for (int r0 = 0; r0 < nrhs; r0 += NRMAX) {
     const int nr = std::min(NRMAX, nrhs - r0);
     p->nr = nr;
@@ -911,10 +920,10 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
     p->set_slots(nr, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, (double*)y + r0 * n,
                  (double*)u + r0 * n, (double*)lam + r0 * n);
     hipError_t e = launch_kkt_residual(t);
-    s = e == hipSuccess ? gather_one(p, g) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
+    s = e == hipSuccess ? gather_one(p) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
     p->nr = 0;
     if (s) return s;
-    for (int c = 0; c < nr; ++c) rel[r0 + c] = g.h.red[2 * c];
+    for (int c = 0; c < nr; ++c) rel[r0 + c] = p->gh->red[2 * c];
   }
   return SFDP_OK;
 }
@@ -931,10 +940,8 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
   const int bsz = batch_of(opts);
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p))) return s;
+  if ((s = gather_buffers(*p))) return s;
   Target t = single_target(p);
-  Gathered* dg = nullptr;
-  if (hipMalloc(&dg, sizeof(Gathered))) return fail(SFDP_E_NOMEM, "gather buffer");
-  Gathered hg;
   sfdp_status worst = SFDP_OK;
   const size_t n = p->n_free;
   std::vector<Problem*> ps{p};
@@ -944,12 +951,11 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
     p->set_slots(ng, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, y + r0 * n, u + r0 * n,
                  lam + r0 * n);
     std::vector<sfdp_info*> inf{info ? info + r0 : nullptr};
-    s = range_space_run(t, ps, nullptr, dg, &hg, tk, ti, mo, kmax, inf, single_of(opts));
+    s = range_space_run(t, ps, nullptr, p->gd, p->gh, tk, ti, mo, kmax, inf, single_of(opts));
     p->nr = 0;
     if (s == SFDP_E_NOCONV) worst = s;
-    else if (s) { hipFree(dg); return s; }
+    else if (s) return s;
   }
-  hipFree(dg);
   return worst;
 }
 
@@ -967,7 +973,6 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
   hipStream_t st = p->ctx->stream;
   const int64_t n = p->n_free;
   Target t = single_target(p);
-  OneGather g;
   // the middle factor needs r1 = 0: v = conj(0 + M w)
   HIPCHK(launch_fill(p->r1, sizeof(double) * NRMAX * n, st));
   for (int r0 = 0; r0 < nrhs; r0 += bsz) {
@@ -981,26 +986,26 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
     s = feti_run(t, p, V_CVEC, 0, V_CVEC2, ti, kmax);
     if (!s && single_of(opts)) {
       hipError_t e = launch_imag_scaled(nr * n, p->cvec2, -1.0 / p->alpha, z + r0 * n, st);
-      s = e == hipSuccess ? gather_one(p, g) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
+      s = e == hipSuccess ? gather_one(p) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
     } else if (!s) {
       hipError_t e = launch_make_rhs2(t);
       s = e == hipSuccess ? feti_run(t, p, V_CVEC3, 0, V_CVEC, ti, kmax) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
       if (!s) {
         e = launch_real_part(nr * n, p->cvec, z + r0 * n, st);
-        s = e == hipSuccess ? gather_one(p, g) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
+        s = e == hipSuccess ? gather_one(p) : fail(SFDP_E_DEVICE, hipGetErrorString(e));
       }
     }
     p->nr = 0;
     if (s) return s;
-    if (g.h.flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
-    if (p->timing) { p->it_gmres += g.h.flags[3]; p->it_rhs += g.h.flags[4]; }
+    if (p->gh->flags[1]) return fail(SFDP_E_DEVICE, "grid barrier timed out");
+    if (p->timing) { p->it_gmres += p->gh->flags[3]; p->it_rhs += p->gh->flags[4]; }
     if (info)
       for (int c = 0; c < nr; ++c) {
         sfdp_info& o = info[r0 + c];
         memset(&o, 0, sizeof(o));
         o.n_feti = single_of(opts) ? 1 : 2;
         for (int k = 0; k < o.n_feti; ++k) {
-          o.krylov_its[k] = g.h.flags[FLAG_LOG + 16 * c + k];
+          o.krylov_its[k] = p->gh->flags[FLAG_LOG + 16 * c + k];
           o.krylov_total += o.krylov_its[k];
         }
       }

@@ -316,6 +316,8 @@ struct Problem {
   // set-up scratch (valid during sfdp_set_beta only)
   cd *G64 = nullptr, *Sinv64 = nullptr, *S64 = nullptr, *Phi64 = nullptr, *PhiFull = nullptr,
      *scr = nullptr, *Zs = nullptr;
+  Gathered* gd = nullptr;  // gather record (device) and its pinned host copy
+  Gathered* gh = nullptr;
   // kernel timing (events recorded around hot kernel launches)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -439,7 +441,10 @@ hipError_t launch_fetidp_rhs(const Target& t);
 hipError_t launch_gmres(const Target& t, double tol, int kmax);
 hipError_t launch_recover_coarse(const Target& t);
 hipError_t launch_assemble_solution(const Target& t, int x, int conj_out);
-hipError_t gmres_check(const Problem& p, int kmax);  // the one-RHS kernel fits (hipSuccess)
+hipError_t gmres_check(const Problem& p, int kmax);
+// Raise the dynamic-LDS limit of kernel fn on the current device to at least
+// lds bytes (cached: no runtime call when already high enough).
+hipError_t ensure_lds(const void* fn, size_t lds);  // the one-RHS kernel fits (hipSuccess)
 int gmres_capacity(const Problem& p, int kmax, int chunk, int width);  // co-resident GMRES blocks
 hipError_t launch_interface_apply(Problem& p, char which, const cd* x, cd* y, hipStream_t st);
 // ops

@@ -472,11 +472,8 @@ hipError_t launch_setup(const Target& t) {
   if (e != hipSuccess) return e;
   if (ncmax <= GJ_LDS_MAX) {
     size_t lds = sizeof(cd) * ((size_t)ncmax * ncmax + 2 * ncmax);
-    e = hipFuncSetAttribute((const void*)k_coarse_inv_lds<One>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_coarse_inv_lds<Many>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    e = ensure_lds((const void*)k_coarse_inv_lds<One>, lds);
+    if (e == hipSuccess) e = ensure_lds((const void*)k_coarse_inv_lds<Many>, lds);
     if (e != hipSuccess) return e;
     launch2(t, K_ONE, k_coarse_inv_lds<One>, k_coarse_inv_lds<Many>, 1, 256, lds);
   } else {

@@ -25,6 +25,10 @@
 // outer refinement needs one step more.
 #include "common.h"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace sfdp {
 
 constexpr int ML = 33;
@@ -1407,6 +1411,46 @@ static size_t gmres_plan(const std::vector<const Problem*>& ms, int kmax, bool* 
   return gmres_layout(NRT, kmax, chunk, sizeof(cd), bS, bI, res, L);
 }
 
+// Launch attributes of the kernels with large dynamic LDS, cached per device
+// and kernel: the dynamic-LDS limit is raised only when a launch needs more,
+// and the co-resident blocks per CU are queried once per LDS size, so that
+// repeated launches make no runtime queries.  Several host threads may launch
+// (a server's worker and callers of other problems).
+namespace {
+std::mutex g_attr_mu;
+std::map<std::pair<int, const void*>, int> g_lds_set;
+std::map<std::tuple<int, const void*, size_t>, int> g_per_cu;
+}  // namespace
+
+hipError_t ensure_lds(const void* fn, size_t lds) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  int& cur = g_lds_set[{dev, fn}];
+  if ((int)lds <= cur) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) cur = (int)lds;
+  return e;
+}
+
+static hipError_t blocks_per_cu(const void* fn, size_t lds, int* per_cu) {
+  hipError_t e = ensure_lds(fn, lds);
+  if (e != hipSuccess) return e;
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  const auto key = std::make_tuple(dev, fn, lds);
+  auto it = g_per_cu.find(key);
+  if (it != g_per_cu.end()) {
+    *per_cu = it->second;
+    return hipSuccess;
+  }
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, 256, lds);
+  if (e == hipSuccess) g_per_cu[key] = *per_cu;
+  return e;
+}
+
 // Whether every block of one GMRES launch over these instances can be
 // co-resident (hipSuccess) or not (an error code).
 template <class TS, int NRT>
@@ -1415,13 +1459,10 @@ static hipError_t gmres_fits(const std::vector<const Problem*>& ms, int kmax, in
   const Ctx* ctx = ms[0]->ctx;
   if (lds > (size_t)ctx->max_lds) return hipErrorOutOfMemory;
   const void* fn = (const void*)k_gmres<TS, NRT, Many>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_gmres<TS, NRT, One>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+  hipError_t e = ensure_lds((const void*)k_gmres<TS, NRT, One>, lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+  e = blocks_per_cu(fn, lds, &per_cu);
   if (e != hipSuccess) return e;
   return (int64_t)per_cu * ctx->num_cu >= blocks ? hipSuccess : hipErrorCooperativeLaunchTooLarge;
 }
@@ -1451,14 +1492,14 @@ static hipError_t gmres_t(const Target& t, int gi, double tol, int kmax, int r0)
     One src = t.src1();
     void* args[] = {&src, &L};
     const void* fn = (const void*)k_gmres<TS, NRT, One>;
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    e = ensure_lds(fn, lds);
     if (e != hipSuccess) return e;
     return hipLaunchCooperativeKernel(fn, dim3(t.one->gmres_blocks), dim3(256), args, lds, t.st);
   }
   Many src{t.devs, t.ggroups[gi].inst, t.first[K_GMRES]};
   void* args[] = {&src, &L};
   const void* fn = (const void*)k_gmres<TS, NRT, Many>;
-  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  e = ensure_lds(fn, lds);
   if (e != hipSuccess) return e;
   return hipLaunchCooperativeKernel(fn, dim3(t.ggroups[gi].total), dim3(256), args, lds, t.st);
 }
@@ -1520,8 +1561,7 @@ int gmres_capacity(const Problem& p, int kmax, int chunk, int width) {
                            : (width == 4 ? (const void*)k_gmres<cd, 4, Many>
                                          : width == 2 ? (const void*)k_gmres<cd, 2, Many> : (const void*)k_gmres<cd, 1, Many>);
   int per_cu = 0;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+  hipError_t e = blocks_per_cu(fn, lds, &per_cu);
   if (e != hipSuccess || per_cu < 1) return 0;
   return per_cu * p.ctx->num_cu;
 }
