@@ -233,3 +233,119 @@ def fetidp_solve_dense(dec: Decomposition, alpha: float, f_free):
     x_full = acc / np.maximum(cnt, 1)
     x_full[dec.corner_full] = uc
     return x_full[mesh.free_full], {"mu": mu, "d": d, "F": F, "ops": ops}
+
+
+# ---------------------------------------------------------------------------
+# Edge augmentation of the coarse problem (Sec. 5, the FETI-DPH augmentation
+# compared in Table 1).  For a scalar problem the edge modes are averages:
+# Q has one column per pair of subdomains that share multipliers (an interface
+# edge in 2D), with ones on those multipliers.  The constraint Q^T B_r u_r = 0
+# is enforced exactly at every iterate through extra coarse unknowns nu (one per
+# column of Q), eliminated with the corners.  From the subdomain equations
+#   Z_rr u_r + Z_rc B_c u_c + B_r^T (mu + Q nu) = f_r
+# and the corner and augmentation equations one gets, with
+#   G  = [F_rc, F_rr Q],
+#   Kt = [[K_cc*, -F_rc^T Q], [-Q^T F_rc, -Q^T F_rr Q]],
+#   c0 = [f_c*; -Q^T d_r],  d_r = sum_s B_r Z_rr^-1 f_r,
+# the interface problem  F_aug mu = d_aug  with
+#   F_aug = F_rr + G Kt^-1 G^T,   d_aug = d_r - G Kt^-1 c0,
+# the coarse solution (u_c; nu) = Kt^-1 (c0 + G^T mu), and the subdomain
+# solution u_r = Z_rr^-1 (f_r - Z_rc B_c u_c - B_r^T (mu + Q nu)).
+
+def edge_space(dec: Decomposition):
+    """Q: one column per pair (s_a, s_b) of subdomains sharing multipliers, in
+    increasing pair order, with ones on the pair's multipliers."""
+    pairs = {}
+    for k, (_, sa, sb) in enumerate(dec.mults):
+        pairs.setdefault((sa, sb), []).append(k)
+    keys = sorted(pairs)
+    Q = np.zeros((dec.nmu, len(keys)))
+    for e, key in enumerate(keys):
+        Q[pairs[key], e] = 1.0
+    return Q, keys
+
+
+def fetidp_aug_operators(ops, Q):
+    """G and the augmented coarse matrix Kt (definitions above)."""
+    Frr, Frc, Kcc = ops["Frr"], ops["Frc"], ops["Kcc"]
+    G = np.hstack([Frc, Frr @ Q])
+    Kt = np.block([[Kcc, -Frc.T @ Q], [-Q.T @ Frc, -Q.T @ Frr @ Q]])
+    return {"G": G, "Kt": Kt, "Q": Q}
+
+
+def fetidp_aug_apply(ops, aug, mu):
+    """F_aug mu = F_rr mu + G Kt^-1 G^T mu (plain transposes: complex symmetric)."""
+    G = aug["G"]
+    return ops["Frr"] @ mu + G @ np.linalg.solve(aug["Kt"], G.T @ mu)
+
+
+def fetidp_aug_rhs(dec: Decomposition, ops, aug, f_free):
+    """d_aug and c0 of the augmented interface problem."""
+    fr, fc = dec.split_rhs(f_free)
+    dr = np.zeros(dec.nmu, dtype=np.complex128)
+    fcs = fc.astype(np.complex128).copy()
+    for sd, pc, f in zip(dec.subs, ops["pieces"], fr):
+        x = pc["Zrr_inv"] @ f
+        dr += sd["Br"] @ x
+        fcs -= sd["Bc"].T @ (pc["Zrc"].T @ x)
+    c0 = np.concatenate([fcs, -aug["Q"].T @ dr])
+    d = dr - aug["G"] @ np.linalg.solve(aug["Kt"], c0)
+    return d, c0, fr
+
+
+def fetidp_aug_solve_dense(dec: Decomposition, alpha: float, f_free):
+    """Solve Z x = f by edge-augmented FETI-DP with a dense solve of F_aug mu = d_aug."""
+    ops = fetidp_operators(dec, alpha)
+    Q, _ = edge_space(dec)
+    aug = fetidp_aug_operators(ops, Q)
+    d, c0, fr = fetidp_aug_rhs(dec, ops, aug, f_free)
+    F = ops["Frr"] + aug["G"] @ np.linalg.solve(aug["Kt"], aug["G"].T)
+    mu = np.linalg.lstsq(F, d, rcond=None)[0]
+    co = np.linalg.solve(aug["Kt"], c0 + aug["G"].T @ mu)
+    uc, nu = co[:dec.nC], co[dec.nC:]
+    lam = mu + Q @ nu
+    mesh = dec.mesh
+    acc = np.zeros(mesh.n_full, dtype=np.complex128)
+    for sd, pc, f in zip(dec.subs, ops["pieces"], fr):
+        ur = pc["Zrr_inv"] @ (f - pc["Zrc"] @ (sd["Bc"] @ uc) - sd["Br"].T @ lam)
+        acc[sd["full"][sd["r"]]] += ur
+    cnt = dec.mult.astype(np.float64)
+    x_full = acc / np.maximum(cnt, 1)
+    x_full[dec.corner_full] = uc
+    return x_full[mesh.free_full], {"mu": mu, "d": d, "F": F, "ops": ops, "aug": aug, "nu": nu}
+
+
+def gmres_iterations(A, Pinv, b, tol, kmax=300):
+    """Iterations of right-preconditioned GMRES (zero start, Gram-Schmidt twice)
+    until the residual estimate ||b - A x|| / ||b|| <= tol (dense, small cases)."""
+    n = b.size
+    beta = np.linalg.norm(b)
+    Qb = np.zeros((n, kmax + 1), dtype=np.complex128)
+    H = np.zeros((kmax + 1, kmax), dtype=np.complex128)
+    Qb[:, 0] = b / beta
+    g = np.zeros(kmax + 1, dtype=np.complex128)
+    g[0] = beta
+    cs, sn = [], []
+    for j in range(kmax):
+        w = A @ (Pinv @ Qb[:, j])
+        for _ in range(2):
+            h = Qb[:, :j + 1].conj().T @ w
+            w = w - Qb[:, :j + 1] @ h
+            H[:j + 1, j] += h
+        H[j + 1, j] = np.linalg.norm(w)
+        Qb[:, j + 1] = w / H[j + 1, j]
+        for i in range(j):
+            t0 = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+            H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + np.conj(cs[i]) * H[i + 1, j]
+            H[i, j] = t0
+        den = np.hypot(abs(H[j, j]), abs(H[j + 1, j]))
+        c, s = np.conj(H[j, j] / den), np.conj(H[j + 1, j] / den)
+        cs.append(c)
+        sn.append(s)
+        H[j, j] = c * H[j, j] + s * H[j + 1, j]
+        H[j + 1, j] = 0
+        g[j + 1] = -np.conj(s) * g[j]
+        g[j] = c * g[j]
+        if abs(g[j + 1]) / beta <= tol:
+            return j + 1
+    return kmax
