@@ -128,9 +128,11 @@ typedef struct {
   int64_t n_bdry;        /* Dirichlet dofs */
   int64_t n_sub;         /* subdomains */
   int64_t n_mult;        /* interface multipliers */
-  int64_t n_corner;      /* coarse (corner) dofs */
+  int64_t n_corner;      /* corner dofs */
   int64_t max_delta;     /* largest number of interface (Delta) dofs of a subdomain */
   int64_t resident_bytes;/* device bytes held by the problem after sfdp_set_beta */
+  int64_t n_coarse;      /* coarse unknowns in use: corners, plus one per interface edge
+                            when the coarse space is edge-augmented (the default) */
 } sfdp_sizes;
 
 /* Create a context on HIP device `device`; all work is ordered on `stream`
@@ -146,6 +148,18 @@ sfdp_status sfdp_problem_create(sfdp_ctx* ctx, int dim, int n_elem, int sub_elem
                                 sfdp_precision prec, sfdp_problem** out);
 sfdp_status sfdp_problem_sizes(const sfdp_problem* p, sfdp_sizes* out);
 void sfdp_problem_destroy(sfdp_problem* p);
+
+/* Coarse space of the FETI-DP solves (Sec. 5; the augmentation compared in
+ * Table 1).  edge_averages = 1: the corners plus one average per interface
+ * edge, the constraint Q^T B_r u_r = 0 (Q: one column of ones on the
+ * multipliers of each edge) enforced exactly at every Krylov iterate through
+ * the extra coarse unknowns; 0: corners only.  The solution is the same; the
+ * iteration counts differ.  Default: edge averages while the augmented coarse
+ * problem has at most 1024 unknowns (up to 19 x 19 subdomains), corners only
+ * beyond (its dense inverse would dominate the set-up).  Takes effect at the
+ * next sfdp_set_beta (the problem must be set up again: SFDP_E_STATE until then).
+ * SFDP_E_INVALID for values other than 0 and 1. */
+sfdp_status sfdp_set_coarse_space(sfdp_problem* p, int edge_averages);
 
 /* Fix beta (Sec. 2 regularisation) and build the FETI-DP operators of
  * Z = K + i beta^(-1/2) M (Sec. 4 factor, Sec. 5 solver): per subdomain the
@@ -203,9 +217,14 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
  *                Delta dofs, in increasing local node index a + (m+1) b
  *                [+ (m+1)^2 c]; n_d is returned in *rows and *cols);
  *   SFDP_Q_SBB   sub s: n_d x n_d  interface Schur complement (Sec. 5, S_bb);
- *   SFDP_Q_PHI   sub s: n_d x n_c  (Z_rr^-1 Z_rc restricted to Delta rows,
- *                corners in increasing local index);
- *   SFDP_Q_COARSE     : n_corner x n_corner coarse matrix K_cc*;
+ *   SFDP_Q_PHI   sub s: n_d x n_c  coarse basis on Delta rows: Z_rr^-1 Z_rc
+ *                for the subdomain's corners (increasing local index), then,
+ *                when edge-augmented, Z_rr^-1 B_r^T q_e for its edges in the
+ *                order left, right, bottom, top side;
+ *   SFDP_Q_COARSE     : n_coarse x n_coarse coarse matrix: K_cc*, or with edge
+ *                averages [[K_cc*, -F_rc^T Q], [-Q^T F_rc, -Q^T F_rr Q]] over
+ *                the corners (increasing node id) then the edges (increasing
+ *                pair of adjacent subdomains);
  * out may be NULL to query the shape only. */
 typedef enum { SFDP_Q_SINV = 0, SFDP_Q_SBB = 1, SFDP_Q_PHI = 2, SFDP_Q_COARSE = 3 } sfdp_query;
 sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out, int* rows, int* cols);

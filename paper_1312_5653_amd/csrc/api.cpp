@@ -70,11 +70,14 @@ void dfree(Problem& p, void*& ptr, size_t bytes) {
 }
 
 // Build the 2D partition and interface maps on the host.
+// Largest coarse problem for which the edge-augmented space is the default.
+constexpr int KAUG_DEFAULT_MAX = 1024;
+
 sfdp_status build_maps(Problem& p) {
   const int N = p.N, m = p.m, P = p.P, ml = p.ml, ND = p.ND, nsub = p.nsub;
   std::vector<int> dloc(nsub * ND, -1), dmid(nsub * ND, 0), dpart(nsub * ND, 0), ndv(nsub, 0);
   std::vector<float> dsgn(nsub * ND, 0.f);
-  std::vector<int> cloc(nsub * 4, -1), cgid(nsub * 4, -1);
+  std::vector<int> cloc(nsub * 4, -1), cgid(nsub * NQ, -1), dedge(nsub * ND, -1);
   // Delta nodes grouped by full id
   std::map<long, std::vector<std::pair<int, int>>> owners;  // full id -> (s, slot)
   for (int s = 0; s < nsub; ++s) {
@@ -88,11 +91,11 @@ sfdp_status build_maps(Problem& p) {
       if (dir) continue;
       if (vert) {
         cloc[s * 4 + nc] = l;
-        cgid[s * 4 + nc] = (gi / m - 1) + (P - 1) * (gj / m - 1);
         ++nc;
       } else if (!inter) {
         if (nd >= ND) return fail(SFDP_E_INVALID, "interface slot overflow");
         dloc[s * ND + nd] = l;
+        dedge[s * ND + nd] = a == 0 ? 4 : a == m ? 5 : b == 0 ? 6 : 7;  // side of the subdomain
         owners[(long)gi + (long)(N + 1) * gj].push_back({s, nd});
         ++nd;
       }
@@ -100,8 +103,17 @@ sfdp_status build_maps(Problem& p) {
     ndv[s] = nd;
     p.ndmax = std::max(p.ndmax, nd);
   }
+  // interface edges in increasing (lower, upper) subdomain-pair order: for each
+  // s, the edge to s + 1 (its right side), then the edge to s + P (its top)
+  std::vector<int> eright(nsub, -1), etop(nsub, -1);
+  int ne = 0;
+  for (int s = 0; s < nsub; ++s) {
+    if (s % P < P - 1) eright[s] = ne++;
+    if (s / P < P - 1) etop[s] = ne++;
+  }
+  p.nE = ne;
   int nmu = 0;
-  std::vector<int> muown, mufree;
+  std::vector<int> muown, mufree, muedge;
   for (auto& kv : owners) {
     auto& v = kv.second;
     if (v.size() != 2) return fail(SFDP_E_INVALID, "2D interface node not shared by two subdomains");
@@ -120,18 +132,38 @@ sfdp_status build_maps(Problem& p) {
     muown.push_back(sa * ND + ia);
     muown.push_back(sb * ND + ib);
     mufree.push_back((gi - 1) + (N - 1) * (gj - 1));
+    const int e = sb == sa + 1 ? eright[sa] : etop[sa];
+    if (e < 0 || (sb != sa + 1 && sb != sa + P)) return fail(SFDP_E_INVALID, "interface pair is not an edge");
+    muedge.push_back(e);
   }
   p.nmu = nmu;
   p.nC = (P - 1) * (P - 1);
-  std::vector<int> cown(std::max(p.nC, 1) * 4, -1), cfree(std::max(p.nC, 1), 0), cnt(std::max(p.nC, 1), 0);
   for (int s = 0; s < nsub; ++s)
     for (int q = 0; q < 4; ++q) {
-      int c = cgid[s * 4 + q];
+      const int l = cloc[s * 4 + q];
+      if (l < 0) continue;
+      const int gi = (s % P) * m + l % ml, gj = (s / P) * m + l / ml;
+      cgid[s * NQ + q] = (gi / m - 1) + (P - 1) * (gj / m - 1);
+    }
+  for (int s = 0; s < nsub; ++s) {
+    if (eright[s] >= 0) cgid[s * NQ + 5] = cgid[(s + 1) * NQ + 4] = p.nC + eright[s];
+    if (etop[s] >= 0) cgid[s * NQ + 7] = cgid[(s + P) * NQ + 6] = p.nC + etop[s];
+  }
+  // edge-augmented coarse space by default while the augmented coarse problem
+  // stays small enough for its dense inverse (up to 19 x 19 subdomains)
+  p.nK = p.nC + p.nE <= KAUG_DEFAULT_MAX ? p.nC + p.nE : p.nC;
+  const int nk = std::max(p.nKmax(), 1);
+  std::vector<int> cown(nk * 4, -1), cfree(std::max(p.nC, 1), 0), cnt(nk, 0);
+  for (int s = 0; s < nsub; ++s)
+    for (int q = 0; q < NQ; ++q) {
+      const int c = cgid[s * NQ + q];
       if (c < 0) continue;
-      cown[c * 4 + cnt[c]++] = s * 4 + q;
-      int l = cloc[s * 4 + q];
-      int gi = (s % P) * m + l % ml, gj = (s / P) * m + l / ml;
-      cfree[c] = (gi - 1) + (N - 1) * (gj - 1);
+      cown[c * 4 + cnt[c]++] = s * NQ + q;
+      if (q < 4) {
+        const int l = cloc[s * 4 + q];
+        const int gi = (s % P) * m + l % ml, gj = (s / P) * m + l / ml;
+        cfree[c] = (gi - 1) + (N - 1) * (gj - 1);
+      }
     }
   std::vector<int> f2b((size_t)(N + 1) * (N + 1), -1);
   int nbd = 0;
@@ -145,7 +177,8 @@ sfdp_status build_maps(Problem& p) {
       (s = dupload(p, &p.dsgn, dsgn)) || (s = dupload(p, &p.cloc, cloc)) ||
       (s = dupload(p, &p.cgid, cgid)) || (s = dupload(p, &p.muown, muown)) ||
       (s = dupload(p, &p.mufree, mufree)) || (s = dupload(p, &p.cown, cown)) ||
-      (s = dupload(p, &p.cfree, cfree)) || (s = dupload(p, &p.full2bdry, f2b)))
+      (s = dupload(p, &p.cfree, cfree)) || (s = dupload(p, &p.full2bdry, f2b)) ||
+      (s = dupload(p, &p.dedge, dedge)) || (s = dupload(p, &p.muedge, muedge)))
     return s;
   return SFDP_OK;
 }
@@ -160,9 +193,10 @@ void free_factors(Problem& p) {
   const size_t PK = (size_t)p.ND * (p.ND + 1) / 2;
   dfree(p, p.Sinv, es * p.nsub * PK);
   dfree(p, p.Sbb, sizeof(cf) * p.nsub * PK);
-  dfree(p, p.Phi, es * p.nsub * p.ND * 4);
-  dfree(p, (void*&)p.Kinv, sizeof(cd) * p.nC * p.nC);
-  dfree(p, (void*&)p.Kcc, sizeof(cd) * p.nC * p.nC);
+  const size_t nk2 = (size_t)std::max(p.nKmax() * p.nKmax(), 1);
+  dfree(p, p.Phi, es * p.nsub * p.ND * NQ);
+  dfree(p, (void*&)p.Kinv, sizeof(cd) * nk2);
+  dfree(p, (void*&)p.Kcc, sizeof(cd) * nk2);
   p.factored = false;
 }
 
@@ -270,13 +304,13 @@ sfdp_status alloc_factors(Problem& p) {
   if (p.G) return SFDP_OK;
   const int ml = p.ml, ND = p.ND, nsub = p.nsub;
   size_t es = elem_size(p);
-  size_t nG = (size_t)nsub * ml * ml * ml, nP = (size_t)nsub * ND * 4;
+  size_t nG = (size_t)nsub * ml * ml * ml, nP = (size_t)nsub * ND * NQ;
+  const size_t nk2 = (size_t)std::max(p.nKmax() * p.nKmax(), 1);
   const size_t nPK = (size_t)nsub * ND * (ND + 1) / 2;
   sfdp_status s;
   if ((s = dalloc(p, &p.G, g_size(p) * nG)) || (s = dalloc(p, &p.Sinv, es * nPK)) ||
       (s = dalloc(p, &p.Sbb, sizeof(cf) * nPK)) || (s = dalloc(p, &p.Phi, es * nP)) ||
-      (s = dalloc(p, (void**)&p.Kinv, sizeof(cd) * std::max(p.nC * p.nC, 1))) ||
-      (s = dalloc(p, (void**)&p.Kcc, sizeof(cd) * std::max(p.nC * p.nC, 1)))) {
+      (s = dalloc(p, (void**)&p.Kinv, sizeof(cd) * nk2)) || (s = dalloc(p, (void**)&p.Kcc, sizeof(cd) * nk2))) {
     free_factors(p);
     return s;
   }
@@ -285,24 +319,24 @@ sfdp_status alloc_factors(Problem& p) {
 
 // FP64 set-up scratch of one problem, as element counts of G64, Sinv64, S64,
 // Phi64, PhiFull, scr, Zs, Kwork.
-void setup_counts(size_t nsub, size_t ml, size_t ND, int nC, size_t c[8]) {
-  const size_t nK = (size_t)std::max(nC * nC, 1);
+void setup_counts(size_t nsub, size_t ml, size_t ND, int nK, size_t c[8]) {
   c[0] = nsub * ml * ml * ml;
   c[1] = nsub * ND * ND;
   c[2] = nsub * ND * ND;
-  c[3] = nsub * ND * 4;
+  c[3] = nsub * ND * NQ;
   c[4] = nsub * ml * ml * 4;
   c[5] = nsub * ml * ml * 32;
-  c[6] = nsub * 16;
-  c[7] = nK;
+  c[6] = nsub * NQ * NQ;
+  c[7] = (size_t)std::max(nK * nK, 1);
 }
-void setup_counts(const Problem& p, size_t c[8]) { setup_counts(p.nsub, p.ml, p.ND, p.nC, c); }
+void setup_counts(const Problem& p, size_t c[8]) { setup_counts(p.nsub, p.ml, p.ND, p.nKmax(), c); }
 size_t pad256(size_t b) { return (b + 255) & ~(size_t)255; }
 // Bytes of the pool share of one problem of this mesh.
 size_t setup_bytes(int n_elem, int sub_elem) {
   const size_t P = n_elem / sub_elem;
   size_t c[8], b = 0;
-  setup_counts(P * P, sub_elem + 1, ((4 * (sub_elem - 1) + 31) / 32) * 32, (int)((P - 1) * (P - 1)), c);
+  const int nK = (int)((P - 1) * (P - 1) + 2 * P * (P - 1));
+  setup_counts(P * P, sub_elem + 1, ((4 * (sub_elem - 1) + 31) / 32) * 32, nK, c);
   for (int k = 0; k < 8; ++k) b += pad256(c[k] * sizeof(cd));
   return b;
 }
@@ -666,8 +700,8 @@ sfdp_status create_problem(Ctx* ctx, int dim, int n_elem, int sub_elem, sfdp_pre
   if (s != SFDP_OK) { destroy_problem(p); return s; }
   // solve workspaces, per right-hand side (NRMAX r-major copies, strides of Problem::rs())
   size_t nsd = (size_t)NRMAX * p->nsub * p->ND;
-  size_t n4 = (size_t)NRMAX * p->nsub * 4;
-  size_t nC = (size_t)NRMAX * std::max(p->nC, 1);
+  size_t n4 = (size_t)NRMAX * p->nsub * NQ;
+  size_t nC = (size_t)NRMAX * std::max(p->nKmax(), 1);
   size_t nm = (size_t)NRMAX * p->nmu;
   if ((s = dalloc(*p, (void**)&p->Xd, sizeof(cd) * nsd)) || (s = dalloc(*p, (void**)&p->Ubuf, sizeof(cd) * nsd)) ||
       (s = dalloc(*p, (void**)&p->Abuf, sizeof(cd) * nsd)) || (s = dalloc(*p, (void**)&p->Ybuf, sizeof(cd) * nsd)) ||
@@ -700,7 +734,7 @@ void destroy_problem(Problem* p) {
   free_factors(*p);
   free_setup(*p);
   void* arr[] = {p->dloc, p->dmid, p->dpart, p->nd, p->dsgn, p->cloc, p->cgid, p->muown, p->mufree,
-                 p->cown, p->cfree, p->full2bdry, p->Xd, p->Ubuf, p->Abuf, p->Ybuf, p->Cbuf, p->Qc,
+                 p->cown, p->cfree, p->dedge, p->muedge, p->full2bdry, p->Xd, p->Ubuf, p->Abuf, p->Ybuf, p->Cbuf, p->Qc,
                  p->fcs, p->u0, p->ymin, p->dvec, p->mu, p->wv, p->Qk, p->Hk, p->part, p->dscal,
                  p->bar, p->flags, p->r1, p->r2, p->r3, p->red, p->cvec, p->cvec2, p->cvec3};
   for (void* a : arr)
@@ -834,8 +868,20 @@ static void sizes_of(const Problem* p, sfdp_sizes* out) {
   out->n_sub = p->nsub;
   out->n_mult = p->nmu;
   out->n_corner = p->nC;
+  out->n_coarse = p->nK;
   out->max_delta = 4 * (p->m - 1);
   out->resident_bytes = (int64_t)p->bytes;
+}
+
+sfdp_status sfdp_set_coarse_space(sfdp_problem* p, int edge_averages) {
+  if (!p) return fail(SFDP_E_INVALID, "NULL argument");
+  if (edge_averages != 0 && edge_averages != 1) return fail(SFDP_E_INVALID, "edge_averages must be 0 or 1");
+  const int nk = edge_averages ? p->nC + p->nE : p->nC;
+  if (nk != p->nK) {
+    p->nK = nk;
+    p->factored = false;  // the coarse matrix changes: sfdp_set_beta again
+  }
+  return SFDP_OK;
 }
 
 sfdp_status sfdp_problem_sizes(const sfdp_problem* p, sfdp_sizes* out) {
@@ -1128,18 +1174,20 @@ sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out,
   sfdp_status s = check_ready(p);
   if (s) return s;
   HIPCHK(hipSetDevice(p->ctx->device));
-  std::vector<int> ndv(p->nsub), cl(4 * p->nsub);
+  std::vector<int> ndv(p->nsub), cg(NQ * p->nsub);
   HIPCHK(hipMemcpy(ndv.data(), p->nd, sizeof(int) * p->nsub, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(cl.data(), p->cloc, sizeof(int) * 4 * p->nsub, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(cg.data(), p->cgid, sizeof(int) * NQ * p->nsub, hipMemcpyDeviceToHost));
   int r = 0, c = 0;
+  std::vector<int> qcols;  // coarse slots returned as columns (SFDP_Q_PHI)
   if (what == SFDP_Q_COARSE) {
-    r = c = p->nC;
+    r = c = p->nK;
   } else {
     if (sub < 0 || sub >= p->nsub) return fail(SFDP_E_INVALID, "sub out of range");
     r = ndv[sub];
     if (what == SFDP_Q_PHI) {
-      c = 0;
-      for (int q = 0; q < 4; ++q) c += cl[4 * sub + q] >= 0;
+      for (int q = 0; q < NQ; ++q)
+        if (cg[NQ * sub + q] >= 0 && cg[NQ * sub + q] < p->nK) qcols.push_back(q);
+      c = (int)qcols.size();
     } else if (what == SFDP_Q_SINV || what == SFDP_Q_SBB) {
       c = r;
     } else {
@@ -1156,12 +1204,12 @@ sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out,
     HIPCHK(hipMemcpy(host.data(), p->Kcc, sizeof(cd) * host.size(), hipMemcpyDeviceToHost));
   } else if (what == SFDP_Q_PHI) {
     size_t es = elem_size(*p);
-    std::vector<char> raw((size_t)p->ND * 4 * es);
-    HIPCHK(hipMemcpy(raw.data(), (const char*)p->Phi + (size_t)sub * p->ND * 4 * es, raw.size(),
+    std::vector<char> raw((size_t)p->ND * NQ * es);
+    HIPCHK(hipMemcpy(raw.data(), (const char*)p->Phi + (size_t)sub * p->ND * NQ * es, raw.size(),
                      hipMemcpyDeviceToHost));
     for (int i = 0; i < r; ++i)
       for (int j = 0; j < c; ++j) {
-        size_t idx = (size_t)i * 4 + j;
+        size_t idx = (size_t)i * NQ + qcols[j];
         if (es == sizeof(cf)) {
           cf v = ((const cf*)raw.data())[idx];
           host[(size_t)i * c + j] = cd{v.x, v.y};
@@ -1332,10 +1380,10 @@ namespace {
 size_t instance_bytes(int n_elem, int sub_elem, sfdp_precision prec) {
   const size_t P = n_elem / sub_elem, nsub = P * P, ml = sub_elem + 1;
   const size_t ND = ((4 * (sub_elem - 1) + 31) / 32) * 32, nf = (size_t)(n_elem - 1) * (n_elem - 1);
-  const size_t nmu = 2 * P * (P - 1) * (sub_elem - 1), nC = (P - 1) * (P - 1);
+  const size_t nmu = 2 * P * (P - 1) * (sub_elem - 1), nC = (P - 1) * (P - 1) + 2 * P * (P - 1);
   const size_t es = prec == SFDP_FP64 ? 16 : 8, gs = prec == SFDP_MIXED ? 8 : 16;
-  size_t b = nsub * ml * ml * ml * gs + nsub * ND * (ND + 1) / 2 * (es + 8) + nsub * ND * 4 * es + 2 * nC * nC * 16;
-  b += NRMAX * (4 * nsub * ND + 2 * nsub * 4 + 3 * nC + 3 * nmu) * 16;  // solve workspaces
+  size_t b = nsub * ml * ml * ml * gs + nsub * ND * (ND + 1) / 2 * (es + 8) + nsub * ND * NQ * es + 2 * nC * nC * 16;
+  b += NRMAX * (4 * nsub * ND + 2 * nsub * NQ + 3 * nC + 3 * nmu) * 16;  // solve workspaces
   b += NRMAX * (65 * nmu + 65 * 64) * 16 + 3 * NRMAX * 66 * nsub * 16;  // Krylov state (kmax 64)
   b += NRMAX * nf * (3 * 8 + 3 * 16);                                    // range-space workspaces
   b += nsub * ND * 40 + nmu * 12 + (size_t)(n_elem + 1) * (n_elem + 1) * 4;  // maps

@@ -17,8 +17,11 @@
 //                            (PK = ND (ND + 1) / 2; storage precision)
 //   Sbb  [nsub][PK]          interface Schur complement (its inverse), packed,
 //                            complex64 on both paths (preconditioner only)
-//   Phi  [nsub][ND][4]       Z_rr^-1 Z_rc on Delta rows
-//   Kinv [nC][nC]            inverse of the coarse matrix K_cc* (FP64)
+//   Phi  [nsub][ND][NQ]      coarse basis on Delta rows: Z_rr^-1 Z_rc for the
+//                            four corner slots, Z_rr^-1 B_r^T q_e for the four
+//                            edge slots (the edge averages of the augmentation)
+//   Kinv [nK][nK]            inverse of the coarse matrix (FP64): K_cc*, or the
+//                            edge-augmented matrix over corners then edges
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -105,9 +108,14 @@ struct Line1D {
   }
 };
 
+// Coarse slots of a subdomain: 0..3 its corners, 4..7 the edges on its sides
+// (left, right, bottom, top).  Global coarse unknowns: the nC corners, then
+// the interface edges (when the coarse space is edge-augmented).
+constexpr int NQ = 8;
+
 // Geometry of one 2D instance, passed by value to kernels.
 struct Geo2 {
-  int N, m, P, ml, nsub, ND, nmu, nC;
+  int N, m, P, ml, nsub, ND, nmu, nC, nK;  // nK: coarse unknowns (nC, or nC + edges)
   double h, alpha;
   // subdomain coordinates
   __device__ __host__ inline int sx(int s) const { return s % P; }
@@ -155,11 +163,13 @@ struct Maps2 {
   const int* dpart;  // [nsub][ND] partner slot (t * ND + slot_t)
   const int* nd;     // [nsub] Delta count
   const int* cloc;   // [nsub][4] local node of corner slot, -1 pad
-  const int* cgid;   // [nsub][4] global corner id, -1 pad
+  const int* cgid;   // [nsub][NQ] global coarse id of each slot (edges from nC), -1 pad
   const int* muown;  // [nmu][2] (s+ * ND + slot+), (s- * ND + slot-)
   const int* mufree; // [nmu] free index of the multiplier's node
-  const int* cown;   // [nC][4] (s * 4 + slot) of the sharing subdomains, -1 pad
+  const int* cown;   // [nC + nE][4] (s * NQ + slot) of the sharing subdomains, -1 pad
   const int* cfree;  // [nC] free index of each global corner
+  const int* dedge;  // [nsub][ND] edge slot (4..7) of a Delta slot, -1 pad
+  const int* muedge; // [nmu] interface edge of a multiplier
 };
 
 // Right-hand sides processed together by one FETI-DP solve (r-major copies of
@@ -167,10 +177,10 @@ struct Maps2 {
 constexpr int NRMAX = 4;
 struct RhsStride {
   int64_t nf;   // free-node vectors
-  int64_t nc;   // coarse (corner) vectors
+  int64_t nc;   // coarse vectors (nK)
   int64_t nmu;  // multiplier vectors
   int64_t sb;   // per-subdomain Delta-slot buffers (nsub * ND)
-  int64_t c4;   // per-subdomain corner buffers (nsub * 4)
+  int64_t cq;   // per-subdomain coarse-slot buffers (nsub * NQ)
 };
 
 // Device flag words of an instance: [1] grid-barrier error, [3] GMRES loop
@@ -264,6 +274,8 @@ struct Many {
 };
 
 // Launch kinds: how many x-blocks an instance takes in a launch.
+// K_NC128 / K_NC: 128 coarse unknowns per block / one per block; K_SUB16:
+// NQ x NQ entries per subdomain in 256-entry blocks.
 enum Kind : int { K_SUB = 0, K_NC128, K_NC, K_NMU256, K_ASM256, K_NF256, K_SUB16, K_ONE, K_GMRES, K_NKIND };
 
 // Host-side problem.
@@ -271,6 +283,9 @@ struct Ctx;
 struct Problem {
   Ctx* ctx = nullptr;
   int dim = 2, N = 0, m = 0, P = 0, nsub = 0, ml = 0, L = 0, ND = 0, nC = 0, nmu = 0, ndmax = 0;
+  int nE = 0;          // interface edges
+  int nK = 0;          // coarse unknowns in use: nC + nE (edge-augmented) or nC
+  int nKmax() const { return nC + nE; }
   bool last_resident = false;  // last GMRES launch kept the Schur blocks in LDS
   int last_nrt = 0;            // right-hand-side width of the last GMRES kernel
   int64_t n_free = 0, n_bdry = 0;
@@ -279,7 +294,8 @@ struct Problem {
   bool factored = false;
   // index maps (device)
   int *dloc = nullptr, *dmid = nullptr, *dpart = nullptr, *nd = nullptr, *cloc = nullptr,
-      *cgid = nullptr, *muown = nullptr, *mufree = nullptr, *cown = nullptr, *cfree = nullptr;
+      *cgid = nullptr, *muown = nullptr, *mufree = nullptr, *cown = nullptr, *cfree = nullptr,
+      *dedge = nullptr, *muedge = nullptr;
   float* dsgn = nullptr;
   int* full2bdry = nullptr;  // [(N+1)^2] boundary index of a full-grid node, -1 if free
   // factors (storage precision: cd for FP64, cf for MIXED)
@@ -326,28 +342,28 @@ struct Problem {
   double t_gmres_ms = 0, t_local_ms = 0;
   int64_t n_gmres = 0, n_local = 0, it_gmres = 0, it_rhs = 0;
   Maps2 maps() const {
-    return Maps2{dloc, dmid, dsgn, dpart, nd, cloc, cgid, muown, mufree, cown, cfree};
+    return Maps2{dloc, dmid, dsgn, dpart, nd, cloc, cgid, muown, mufree, cown, cfree, dedge, muedge};
   }
   // storage precision: line factors G (g32) and interface operators Sinv, Phi (s32)
   bool g32() const { return prec == SFDP_MIXED; }
   bool s32() const { return prec == SFDP_MIXED || prec == SFDP_MIXED_IFACE; }
   RhsStride rs() const {
-    return RhsStride{n_free, (int64_t)(nC > 0 ? nC : 1), (int64_t)nmu, (int64_t)nsub * ND,
-                     (int64_t)nsub * 4};
+    return RhsStride{n_free, (int64_t)std::max(nKmax(), 1), (int64_t)nmu, (int64_t)nsub * ND,
+                     (int64_t)nsub * NQ};
   }
   Geo2 geo() const {
-    return Geo2{N, m, P, ml, nsub, ND, nmu, nC, 1.0 / N, alpha};
+    return Geo2{N, m, P, ml, nsub, ND, nmu, nC, nK, 1.0 / N, alpha};
   }
   // x-blocks of this instance in a launch of the given kind
   int blocks(int kind) const {
     switch (kind) {
       case K_SUB: return nsub;
-      case K_NC128: return (nC + 127) / 128;
-      case K_NC: return nC;
+      case K_NC128: return (nK + 127) / 128;
+      case K_NC: return nK;
       case K_NMU256: return (nmu + 255) / 256;
       case K_ASM256: return (nmu + nC + 255) / 256;
       case K_NF256: return (int)((n_free + 255) / 256);
-      case K_SUB16: return (nsub * 16 + 255) / 256;
+      case K_SUB16: return (nsub * NQ * NQ + 255) / 256;
       case K_ONE: return 1;
       default: return gmres_blocks;
     }

@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
           if (slot >= 0) Sinv64[((size_t)s * ND + slot) * ND + col] = x;
         } else if (col < ncol) {
           int q = col - nd;
-          if (slot >= 0) Phi64[((size_t)s * ND + slot) * 4 + q] = x;
+          if (slot >= 0) Phi64[((size_t)s * ND + slot) * NQ + q] = x;
           PhiFull[((size_t)s * n2 + l) * 4 + q] = x;
         }
       }
@@ -295,7 +295,42 @@ __global__ void __launch_bounds__(1024) k_invert_batched(Src src) {
   }
 }
 
-// Z_cc*^s = Z_cc - Z_cr Phi  (4 x 4 per subdomain), into Zs[s][4][4].
+// Edge columns of the coarse basis: Phi64[s][i][4 + j] = sum over the Delta
+// slots k on side j of the subdomain of Z_rr^-1|Delta[i][k] sign_k, i.e.
+// Z_rr^-1 B_r^T q_e on Delta rows for the edge e on that side (q_e: ones on
+// the edge's multipliers).  One workgroup per subdomain, thread i = row i.
+template <class Src>
+__global__ void __launch_bounds__(256) k_edge_basis(Src src) {
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  const Maps2& mp = d.mp;
+  const int s = src.bx(), ND = g.ND, nd = mp.nd[s];
+  __shared__ int side[128];
+  __shared__ float sg[128];
+  for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+    side[k] = mp.dedge[s * ND + k] - 4;
+    sg[k] = mp.dsgn[s * ND + k];
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i >= nd) return;
+  const cd* row = d.Sinv64 + ((size_t)s * ND + i) * ND;
+  cd acc[4] = {cd{0.0, 0.0}, cd{0.0, 0.0}, cd{0.0, 0.0}, cd{0.0, 0.0}};
+  for (int k = 0; k < nd; ++k) {
+    const cd v = (double)sg[k] * row[k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (side[k] == j) acc[j] = acc[j] + v;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) d.Phi64[((size_t)s * ND + i) * NQ + 4 + j] = acc[j];
+}
+
+// Per-subdomain coarse blocks Zs[s][NQ][NQ] over the coarse slots:
+//   corner x corner: Z_cc*^s = Z_cc - Z_cr Phi;
+//   with an edge slot e: -q_e^T X, X the other slot's basis column (Z_rr^-1
+//   Z_rc for a corner, Z_rr^-1 B_r^T q_f for an edge f), q_e the signs on
+//   the side's Delta slots.  Entries of absent slots are zero.
 template <class Src>
 __global__ void k_zcc(Src src) {
   const Dev& d = src.dev();
@@ -304,26 +339,35 @@ __global__ void k_zcc(Src src) {
   const cd* PhiFull = d.PhiFull;
   cd* Zs = d.Zs;
   int t = src.bx() * blockDim.x + threadIdx.x;
-  if (t >= g.nsub * 16) return;
-  int s = t / 16, q = (t / 4) % 4, q2 = t % 4;
-  int cl = mp.cloc[s * 4 + q], cl2 = mp.cloc[s * 4 + q2];
+  if (t >= g.nsub * NQ * NQ) return;
+  const int s = t / (NQ * NQ), q = (t / NQ) % NQ, q2 = t % NQ;
   cd v{0.0, 0.0};
-  if (cl >= 0 && cl2 >= 0) {
-    int ca = cl % g.ml, cb = cl / g.ml, ca2 = cl2 % g.ml, cb2 = cl2 / g.ml;
-    v = g.zloc(ca, cb, ca2, cb2);
-    const int n2 = g.ml * g.ml;
-    for (int b = max(cb - 1, 0); b <= min(cb + 1, g.ml - 1); ++b)
-      for (int a = max(ca - 1, 0); a <= min(ca + 1, g.ml - 1); ++a) {
-        if (!g.rnode(s, a, b)) continue;
-        cd z = g.zloc(ca, cb, a, b);
-        cd ph = PhiFull[((size_t)s * n2 + a + g.ml * b) * 4 + q2];
-        v = v - z * ph;
-      }
+  if (mp.cgid[s * NQ + q] >= 0 && mp.cgid[s * NQ + q2] >= 0) {
+    if (q < 4 && q2 < 4) {
+      const int cl = mp.cloc[s * 4 + q], cl2 = mp.cloc[s * 4 + q2];
+      int ca = cl % g.ml, cb = cl / g.ml, ca2 = cl2 % g.ml, cb2 = cl2 / g.ml;
+      v = g.zloc(ca, cb, ca2, cb2);
+      const int n2 = g.ml * g.ml;
+      for (int b = max(cb - 1, 0); b <= min(cb + 1, g.ml - 1); ++b)
+        for (int a = max(ca - 1, 0); a <= min(ca + 1, g.ml - 1); ++a) {
+          if (!g.rnode(s, a, b)) continue;
+          cd z = g.zloc(ca, cb, a, b);
+          cd ph = PhiFull[((size_t)s * n2 + a + g.ml * b) * 4 + q2];
+          v = v - z * ph;
+        }
+    } else {
+      const int e = q >= 4 ? q : q2, other = q >= 4 ? q2 : q;
+      const int nd = mp.nd[s];
+      for (int i = 0; i < nd; ++i)
+        if (mp.dedge[s * g.ND + i] == e)
+          v = v - (double)mp.dsgn[s * g.ND + i] * d.Phi64[((size_t)s * g.ND + i) * NQ + other];
+    }
   }
   Zs[t] = v;
 }
 
-// Row c of K_cc* = sum over the subdomains sharing corner c (fixed order).
+// Row c of the coarse matrix (c < nK) = sum over the subdomains sharing coarse
+// unknown c (fixed order) of their block rows; slots beyond nK are left out.
 template <class Src>
 __global__ void k_coarse_assemble(Src src) {
   const Dev& d = src.dev();
@@ -331,18 +375,19 @@ __global__ void k_coarse_assemble(Src src) {
   const Maps2& mp = d.mp;
   const cd* Zs = d.Zs;
   cd* Kcc = d.Kcc;
+  const int n = g.nK;
   int c = src.bx() * blockDim.x + threadIdx.x;
-  if (c >= g.nC) return;
-  cd* row = Kcc + (size_t)c * g.nC;
-  for (int k = 0; k < g.nC; ++k) row[k] = cd{0.0, 0.0};
+  if (c >= n) return;
+  cd* row = Kcc + (size_t)c * n;
+  for (int k = 0; k < n; ++k) row[k] = cd{0.0, 0.0};
   for (int o = 0; o < 4; ++o) {
     int own = mp.cown[c * 4 + o];
     if (own < 0) continue;
-    int s = own / 4, slot = own % 4;
-    for (int q = 0; q < 4; ++q) {
-      int c2 = mp.cgid[s * 4 + q];
-      if (c2 < 0) continue;
-      row[c2] = row[c2] + Zs[((size_t)s * 4 + slot) * 4 + q];
+    int s = own / NQ, slot = own % NQ;
+    for (int q = 0; q < NQ; ++q) {
+      int c2 = mp.cgid[s * NQ + q];
+      if (c2 < 0 || c2 >= n) continue;
+      row[c2] = row[c2] + Zs[((size_t)s * NQ + slot) * NQ + q];
     }
   }
 }
@@ -361,14 +406,15 @@ __global__ void k_gj_step(int n, int k, const cd* A, cd* B) {
   B[idx] = v;
 }
 
-// K_cc*^-1 of a small coarse matrix (nC <= GJ_LDS_MAX) in LDS, one workgroup per
-// instance: Kinv = GJ(Kcc).
+// Inverse of a small coarse matrix (nK <= GJ_LDS_MAX) in LDS, one workgroup per
+// instance: Kinv = GJ(Kcc); instances with larger coarse matrices return.
 constexpr int GJ_LDS_MAX = 96;
 template <class Src>
 __global__ void __launch_bounds__(256) k_coarse_inv_lds(Src src) {
   extern __shared__ __align__(16) char smem[];
   const Dev& d = src.dev();
-  const int n = d.g.nC;
+  const int n = d.g.nK;
+  if (n > GJ_LDS_MAX) return;
   cd* T = (cd*)smem;
   cd* rowk = T + n * n;
   cd* colk = rowk + n;
@@ -378,13 +424,60 @@ __global__ void __launch_bounds__(256) k_coarse_inv_lds(Src src) {
   for (int i = threadIdx.x; i < n * n; i += blockDim.x) d.Kinv[i] = T[i];
 }
 
+// Coarse inverse of a mid-size coarse matrix (GJ_LDS_MAX < nK <= GJ_BLOCK_MAX)
+// by Gauss-Jordan without pivoting in global memory, one 1024-thread workgroup
+// per instance: Kinv = GJ(Kcc), corners first.  Row k and column k of each
+// step are copied to LDS; every other entry is read and written by one thread.
+// Accesses to Kinv are coherent (device scope) and every wave waits for its
+// memory operations before each barrier.
+constexpr int GJ_BLOCK_MAX = 256;
+__device__ inline cd gl_ld(const cd* p) {
+  double x = __hip_atomic_load((const double*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double y = __hip_atomic_load((const double*)p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return cd{x, y};
+}
+__device__ inline void gl_st(cd* p, cd v) {
+  __hip_atomic_store((double*)p, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((double*)p + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class Src>
+__global__ void __launch_bounds__(1024) k_coarse_inv_block(Src src) {
+  const Dev& d = src.dev();
+  const int n = d.g.nK;
+  if (n <= GJ_LDS_MAX || n > GJ_BLOCK_MAX) return;
+  __shared__ cd rowk[GJ_BLOCK_MAX], colk[GJ_BLOCK_MAX];
+  cd* T = d.Kinv;
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) gl_st(T + i, d.Kcc[i]);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      rowk[t] = gl_ld(T + (size_t)k * n + t);
+      colk[t] = gl_ld(T + (size_t)t * n + k);
+    }
+    __syncthreads();
+    const cd piv = cdiv(cd{1.0, 0.0}, rowk[k]);
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+      const int i = idx / n, j = idx % n;
+      cd v;
+      if (i == k && j == k) v = piv;
+      else if (i == k) v = rowk[j] * piv;
+      else if (j == k) v = -(colk[i] * piv);
+      else v = gl_ld(T + idx) - colk[i] * (rowk[j] * piv);
+      gl_st(T + idx, v);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+}
+
 // Per-subdomain helpers of the set-up (x = subdomain, y = 256-entry chunk).
 // which: 0 Sinv64, 1 Phi64.
 template <class Src>
 __global__ void k_zero_sub(Src src, int which) {
   const Dev& d = src.dev();
   const int s = src.bx(), ND = d.g.ND;
-  const size_t per = which == 0 ? (size_t)ND * ND : (size_t)ND * 4;
+  const size_t per = which == 0 ? (size_t)ND * ND : (size_t)ND * NQ;
   const size_t i = (size_t)blockIdx.y * blockDim.x + threadIdx.x;
   if (i >= per) return;
   (which == 0 ? d.Sinv64 : d.Phi64)[(size_t)s * per + i] = cd{0.0, 0.0};
@@ -402,7 +495,7 @@ template <class TS, class Src>
 __global__ void k_convert(Src src, int which) {
   const Dev& d = src.dev();
   const int s = src.bx(), ml = d.g.ml, ND = d.g.ND;
-  const size_t per = which == 0 ? (size_t)ml * ml * ml : (size_t)ND * 4;
+  const size_t per = which == 0 ? (size_t)ml * ml * ml : (size_t)ND * NQ;
   const size_t i = (size_t)blockIdx.y * blockDim.x + threadIdx.x;
   if (i >= per) return;
   const cd v = (which == 0 ? d.G64 : d.Phi64)[(size_t)s * per + i];
@@ -456,32 +549,39 @@ hipError_t launch_setup(const Target& t) {
   for (Problem* p : ps) {
     ND = std::max(ND, p->ND);
     ml = std::max(ml, p->ml);
-    ncmax = std::max(ncmax, p->nC);
+    ncmax = std::max(ncmax, p->nK);
   }
-  const int yS = (ND * ND + 255) / 256, yP = (ND * 4 + 255) / 256, yG = (ml * ml * ml + 255) / 256;
+  const int yS = (ND * ND + 255) / 256, yP = (ND * NQ + 255) / 256, yG = (ml * ml * ml + 255) / 256;
   const int yK = (ND * (ND + 1) / 2 + 255) / 256;
   launch2(t, K_SUB, k_zero_sub<One>, k_zero_sub<Many>, yS, 256, 0, 0);
   launch2(t, K_SUB, k_zero_sub<One>, k_zero_sub<Many>, yP, 256, 0, 1);
   launch2(t, K_SUB, k_factor_lines<One>, k_factor_lines<Many>, 1, 256, 0);
   launch2(t, K_SUB, k_multi_solve<One>, k_multi_solve<Many>, 1, 256, 0);
+  launch2(t, K_SUB, k_edge_basis<One>, k_edge_basis<Many>, 1, 256, 0);
   launch2(t, K_SUB, k_copy_sub<One>, k_copy_sub<Many>, yS, 256, 0);
   launch2(t, K_SUB, k_invert_batched<One>, k_invert_batched<Many>, 1, 1024, 0);
   launch2(t, K_SUB16, k_zcc<One>, k_zcc<Many>, 1, 256, 0);
   launch2(t, K_NC128, k_coarse_assemble<One>, k_coarse_assemble<Many>, 1, 128, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (ncmax <= GJ_LDS_MAX) {
-    size_t lds = sizeof(cd) * ((size_t)ncmax * ncmax + 2 * ncmax);
+  // coarse inverses: small ones in LDS and mid-size ones by one workgroup each,
+  // every instance in one launch per kind (each kernel skips the other sizes);
+  // large ones by one launch per pivot
+  {
+    const int nl = std::min(ncmax, GJ_LDS_MAX);
+    size_t lds = sizeof(cd) * ((size_t)nl * nl + 2 * nl);
     e = ensure_lds((const void*)k_coarse_inv_lds<One>, lds);
     if (e == hipSuccess) e = ensure_lds((const void*)k_coarse_inv_lds<Many>, lds);
     if (e != hipSuccess) return e;
     launch2(t, K_ONE, k_coarse_inv_lds<One>, k_coarse_inv_lds<Many>, 1, 256, lds);
-  } else {
-    for (Problem* p : ps) {
-      e = hipMemcpyAsync(p->Kinv, p->Kcc, sizeof(cd) * p->nC * p->nC, hipMemcpyDeviceToDevice, t.st);
-      if (e == hipSuccess) e = invert_dense(p->nC, p->Kinv, p->Kwork, t.st);
-      if (e != hipSuccess) return e;
-    }
+  }
+  if (ncmax > GJ_LDS_MAX) launch2(t, K_ONE, k_coarse_inv_block<One>, k_coarse_inv_block<Many>, 1, 1024, 0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (Problem* p : ps) {
+    if (p->nK <= GJ_BLOCK_MAX) continue;
+    e = hipMemcpyAsync(p->Kinv, p->Kcc, sizeof(cd) * p->nK * p->nK, hipMemcpyDeviceToDevice, t.st);
+    if (e == hipSuccess) e = invert_dense(p->nK, p->Kinv, p->Kwork, t.st);
+    if (e != hipSuccess) return e;
   }
   if (t.g32()) launch2(t, K_SUB, k_convert<cf, One>, k_convert<cf, Many>, yG, 256, 0, 0);
   else launch2(t, K_SUB, k_convert<cd, One>, k_convert<cd, Many>, yG, 256, 0, 0);

@@ -350,7 +350,7 @@ __device__ inline void local_solve_body(const Geo2& g, const Maps2& mp, const Rh
             if (cl < 0) continue;
             int ca = cl % ml, cb = cl / ml;
             if (abs(ca - a) > 1 || abs(cb - b) > 1) continue;
-            v = v - g.zloc(a, b, ca, cb) * uc[min(r, nr - 1) * rs.nc + mp.cgid[s * 4 + q]];
+            v = v - g.zloc(a, b, ca, cb) * uc[min(r, nr - 1) * rs.nc + mp.cgid[s * NQ + q]];
           }
         }
       }
@@ -451,7 +451,7 @@ __device__ inline void local_solve_body(const Geo2& g, const Maps2& mp, const Rh
             fma_acc(acc, g.zloc(ca, cb, a, b), cd{(double)x.x, (double)x.y});
           }
       }
-      Qc[r * rs.c4 + s * 4 + q] = acc;
+      Qc[r * rs.cq + s * NQ + q] = acc;
     }
   } else {
     for (int t = threadIdx.x; t < nd * nr; t += blockDim.x) {
@@ -485,7 +485,31 @@ k_local_solve(Src src, int mode, int fsel, int conj_in, int xsel) {
                             mode == 1 ? conj_in : 0, src.bx());
 }
 
-// f_c* = f_c - sum_s B_c^T Qc  (one thread per global corner, fixed order)
+// Edge slots of Qc: Qc[s][4 + j] = sum over the Delta slots on side j of
+// sign * Xd, subdomain s's share of q_e^T d_r (d_r = sum_s B_r Z_rr^-1 f_r).
+// One workgroup per subdomain; wave j sums side j.
+template <class Src>
+__global__ void k_edge_rhs(Src src) {
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  const Maps2& mp = d.mp;
+  const RhsStride& rs = d.rs;
+  if ((int)blockIdx.y >= d.nr) return;
+  const int s = src.bx(), lane = threadIdx.x & 63, j = threadIdx.x >> 6, nd = mp.nd[s];
+  const int64_t r = blockIdx.y;
+  const cd* Xd = d.Xd + r * rs.sb + (size_t)s * g.ND;
+  cd acc{0.0, 0.0};
+  for (int i = lane; i < nd; i += 64)
+    if (mp.dedge[s * g.ND + i] == 4 + j) acc = acc + (double)mp.dsgn[s * g.ND + i] * Xd[i];
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.x += __shfl_down(acc.x, off, 64);
+    acc.y += __shfl_down(acc.y, off, 64);
+  }
+  if (lane == 0) d.Qc[r * rs.cq + s * NQ + 4 + j] = acc;
+}
+
+// Coarse right-hand side c0 (one thread per coarse unknown, fixed order):
+// corners f_c* = f_c - sum_s B_c^T Z_cr Z_rr^-1 f_r; edges -q_e^T d_r.
 template <class Src>
 __global__ void k_coarse_rhs(Src src, int fsel, int conj_in) {
   const Dev& d = src.dev();
@@ -493,16 +517,19 @@ __global__ void k_coarse_rhs(Src src, int fsel, int conj_in) {
   const Maps2& mp = d.mp;
   const RhsStride& rs = d.rs;
   int c = src.bx() * blockDim.x + threadIdx.x;
-  if (c >= g.nC || (int)blockIdx.y >= d.nr) return;
+  if (c >= g.nK || (int)blockIdx.y >= d.nr) return;
   const int64_t r = blockIdx.y;
   const cd* f = dev_vec(d, fsel);
   const cd* Qc = d.Qc;
   cd* fcs = d.fcs;
   f += r * rs.nf;
-  Qc += r * rs.c4;
+  Qc += r * rs.cq;
   fcs += r * rs.nc;
-  cd v = f[mp.cfree[c]];
-  if (conj_in) v = conj(v);
+  cd v{0.0, 0.0};
+  if (c < g.nC) {
+    v = f[mp.cfree[c]];
+    if (conj_in) v = conj(v);
+  }
   for (int o = 0; o < 4; ++o) {
     int own = mp.cown[c * 4 + o];
     if (own >= 0) v = v - Qc[own];
@@ -510,12 +537,12 @@ __global__ void k_coarse_rhs(Src src, int fsel, int conj_in) {
   fcs[c] = v;
 }
 
-// u0 = K_cc*^-1 x (x = fcs or ymin), one wavefront per row.
+// u0 = Kinv x (x = fcs or ymin; coarse inverse over nK unknowns), one wavefront per row.
 template <class Src>
 __global__ void k_dense_mv(Src src, int xsel) {
   const Dev& d = src.dev();
   if ((int)blockIdx.y >= d.nr) return;
-  const int n = d.g.nC, row = src.bx();
+  const int n = d.g.nK, row = src.bx();
   const int64_t stride = d.rs.nc;
   const cd* __restrict__ A = d.Kinv;
   const cd* x = dev_vec(d, xsel) + blockIdx.y * stride;
@@ -529,7 +556,7 @@ __global__ void k_dense_mv(Src src, int xsel) {
   if (threadIdx.x == 0) y[row] = acc;
 }
 
-// d_k = sum over the two subdomains of sign * (Xd - Phi u0)
+// d_k = sum over the two subdomains of sign * (Xd - sum over coarse slots Phi u0)
 template <class TS, class Src>
 __global__ void k_fetidp_rhs(Src src) {
   const Dev& dv = src.dev();
@@ -551,10 +578,10 @@ __global__ void k_fetidp_rhs(Src src) {
     int o = mp.muown[2 * k + e];
     int s = o / g.ND, slot = o % g.ND;
     cd v = Xd[o];
-    for (int q = 0; q < 4; ++q) {
-      int c = mp.cgid[s * 4 + q];
-      if (c < 0) continue;
-      cd ph = cvt<double>(Phi[((size_t)s * g.ND + slot) * 4 + q]);
+    for (int q = 0; q < NQ; ++q) {
+      int c = mp.cgid[s * NQ + q];
+      if (c < 0 || c >= g.nK) continue;
+      cd ph = cvt<double>(Phi[((size_t)s * g.ND + slot) * NQ + q]);
       v = v - ph * u0[c];
     }
     out = e == 0 ? out + v : out - v;
@@ -562,8 +589,9 @@ __global__ void k_fetidp_rhs(Src src) {
   d[k] = out;
 }
 
-// c^s_q = sum_i Phi[s][i][q] sign_i mu[mid_i]  (F_rc^T mu contributions); one
-// wavefront per (subdomain, corner slot).
+// c^s_q = sum_i Phi[s][i][q] sign_i mu[mid_i]  (G^T mu contributions: F_rc^T mu
+// for corner slots, Q^T F_rr mu for edge slots); one wavefront per (subdomain,
+// coarse slot), launched with NQ waves per block.
 template <class TS, class Src>
 __global__ void k_frct(Src src) {
   const Dev& d = src.dev();
@@ -572,20 +600,21 @@ __global__ void k_frct(Src src) {
   const RhsStride& rs = d.rs;
   int t = src.bx() * (blockDim.x / 64) + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
-  if (t >= g.nsub * 4 || (int)blockIdx.y >= d.nr) return;
+  if (t >= g.nsub * NQ || (int)blockIdx.y >= d.nr) return;
   const int64_t r = blockIdx.y;
   const TS* Phi = (const TS*)d.Phi;
   const cd* mu = d.mu;
   cd* Cbuf = d.Cbuf;
   mu += r * rs.nmu;
-  Cbuf += r * rs.c4;
-  int s = t / 4, q = t % 4;
+  Cbuf += r * rs.cq;
+  int s = t / NQ, q = t % NQ;
   cd acc{0.0, 0.0};
-  if (mp.cloc[s * 4 + q] >= 0) {
+  const int c = mp.cgid[s * NQ + q];
+  if (c >= 0 && c < g.nK) {
     int nd = mp.nd[s];
     for (int i = lane; i < nd; i += 64) {
       cd x = (double)mp.dsgn[s * g.ND + i] * mu[mp.dmid[s * g.ND + i]];
-      fma_acc(acc, cvt<double>(Phi[((size_t)s * g.ND + i) * 4 + q]), x);
+      fma_acc(acc, cvt<double>(Phi[((size_t)s * g.ND + i) * NQ + q]), x);
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -595,7 +624,7 @@ __global__ void k_frct(Src src) {
   if (lane == 0) Cbuf[t] = acc;
 }
 
-// ymin_c = fcs_c + sum_owners Cbuf
+// ymin_c = fcs_c + sum_owners Cbuf  (every coarse unknown c < nK)
 template <class Src>
 __global__ void k_corner_sum(Src src) {
   const Dev& d = src.dev();
@@ -603,13 +632,13 @@ __global__ void k_corner_sum(Src src) {
   const Maps2& mp = d.mp;
   const RhsStride& rs = d.rs;
   int c = src.bx() * blockDim.x + threadIdx.x;
-  if (c >= g.nC || (int)blockIdx.y >= d.nr) return;
+  if (c >= g.nK || (int)blockIdx.y >= d.nr) return;
   const int64_t r = blockIdx.y;
   const cd* fcs = d.fcs;
   const cd* Cbuf = d.Cbuf;
   cd* out = d.ymin;
   if (fcs) fcs += r * rs.nc;
-  Cbuf += r * rs.c4;
+  Cbuf += r * rs.cq;
   out += r * rs.nc;
   cd v = fcs ? fcs[c] : cd{0.0, 0.0};
   for (int o = 0; o < 4; ++o) {
@@ -617,6 +646,18 @@ __global__ void k_corner_sum(Src src) {
     if (own >= 0) v = v + Cbuf[own];
   }
   out[c] = v;
+}
+
+// Multipliers of the subdomain solves with edge augmentation: mu_k += nu_e for
+// the edge e of multiplier k (nu = the edge part of the coarse solution u0).
+template <class Src>
+__global__ void k_add_edge_mult(Src src) {
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  int k = src.bx() * blockDim.x + threadIdx.x;
+  if (k >= g.nmu || (int)blockIdx.y >= d.nr || g.nK == g.nC) return;
+  const int64_t r = blockIdx.y;
+  d.mu[r * d.rs.nmu + k] = d.mu[r * d.rs.nmu + k] + d.u0[r * d.rs.nc + g.nC + d.mp.muedge[k]];
 }
 
 // primal assembly: Delta nodes average the two subdomain copies, corners take uc
@@ -793,142 +834,161 @@ __device__ void phase_f1(const Geo2& g, const Maps2& mp, const RhsStride& rs,
   }
   xs_zero_tail<R, NRT>(xs, nd);
   __syncthreads();
-  // corner products: one wavefront per corner slot; lane l takes rows l and
-  // l + 64 (nd <= 128), whose F_rc entries load under the Schur product
-  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const bool has_q = mp.cloc[s * 4 + q] >= 0;
-  TS phr[2];
+  // coarse-slot products: wave w takes slots w (a corner) and w + 4 (an edge);
+  // lane l takes rows l and l + 64 (nd <= 128), whose coarse-basis entries
+  // load under the Schur product
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  bool has[2];
+  TS phr[2][2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int i = lane + 64 * h;
-    phr[h] = (has_q && i < nd) ? Phi[((size_t)s * ND + i) * 4 + q] : TS{0, 0};
+  for (int u = 0; u < 2; ++u) {
+    const int q = wv + 4 * u, c = mp.cgid[s * NQ + q];
+    has[u] = c >= 0 && c < g.nK;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      phr[u][h] = (has[u] && i < nd) ? Phi[((size_t)s * ND + i) * NQ + q] : TS{0, 0};
+    }
   }
   symv_packed_nr<TS, R, NRT>(buf, nd, xs, Ybuf + (size_t)s * ND, rs.sb, nr);
-  cd acc[NRT];
 #pragma unroll
-  for (int r = 0; r < NRT; ++r) acc[r] = cd{0.0, 0.0};
-  if (has_q) {
+  for (int u = 0; u < 2; ++u) {
+    if (!has[u]) continue;  // uniform over the wave
+    cd acc[NRT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) acc[r] = cd{0.0, 0.0};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int i = lane + 64 * h;
       if (i >= nd) break;
-      const cd ph = cvt<double>(phr[h]);
+      const cd ph = cvt<double>(phr[u][h]);
 #pragma unroll
       for (int r = 0; r < NRT; ++r) {
         C<R> x = xs[i * NRT + r];
         fma_acc(acc[r], ph, cd{(double)x.x, (double)x.y});
       }
     }
-  }
 #pragma unroll
-  for (int r = 0; r < NRT; ++r) {
-    for (int off = 32; off > 0; off >>= 1) {
-      acc[r].x += __shfl_down(acc[r].x, off, 64);
-      acc[r].y += __shfl_down(acc[r].y, off, 64);
+    for (int r = 0; r < NRT; ++r) {
+      for (int off = 32; off > 0; off >>= 1) {
+        acc[r].x += __shfl_down(acc[r].x, off, 64);
+        acc[r].y += __shfl_down(acc[r].y, off, 64);
+      }
+      if (lane == 0 && r < nr) st_coh(Cbuf + r * rs.cq + s * NQ + wv + 4 * u, acc[r]);
     }
-    if (lane == 0 && r < nr) st_coh(Cbuf + r * rs.c4 + s * 4 + q, acc[r]);
   }
 }
 
-// Ybuf_r[s] += Phi uc_r with uc_r = K_cc*^-1 g_r on the subdomain's corners and
-// g_r[c] = sum of Cbuf_r over the owners of corner c.  Transposed product:
-// thread t forms g_r[c] for the corners c = t, t + 256, ... and accumulates
-// K_cc*^-1[c_q][c] g_r[c] for the four corner slots q; one block reduction then
-// gives uc_r[q].  wred holds 16 * NRT complex values, ucs 4 * NRT.
+// Ybuf_r[s] += Phi uc_r over the subdomain's coarse slots, uc_r = Kinv g_r on
+// those slots and g_r[c] = sum of Cbuf_r over the owners of coarse unknown c.
+// Transposed product: thread t forms g_r[c] for c = t, t + 256, ... and
+// accumulates Kinv[c_q][c] g_r[c] for four slots q at a time (corner slots,
+// then, with an edge-augmented coarse space, edge slots); one block reduction
+// per pass gives uc_r[q].  wred holds 16 * NRT complex values, ucs NQ * NRT.
 template <class TS, int NRT>
 __device__ void phase_f2(const Geo2& g, const Maps2& mp, const RhsStride& rs,
                          const TS* __restrict__ Phi, const cd* __restrict__ Kinv, int s,
                          const cd* Cbuf, cd* Ybuf, int nr, cd* ucs, cd* wred) {
-  const int ND = g.ND, nd = mp.nd[s];
+  const int ND = g.ND, nd = mp.nd[s], nK = g.nK;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __syncthreads();
-  int cq[4];
+  int cq[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) cq[q] = mp.cgid[s * 4 + q];
+  for (int q = 0; q < NQ; ++q) {
+    const int c = mp.cgid[s * NQ + q];
+    cq[q] = (c >= 0 && c < nK) ? c : -1;
+  }
   // thread i < nd (nd <= ND <= 128 < blockDim) updates Delta row i at the end: its
-  // F_rc row and the F1 result are loaded now, under the coarse product
+  // coarse-basis row and the F1 result are loaded now, under the coarse product
   const int i = threadIdx.x;
-  cd ph[4], yv[NRT];
+  cd ph[NQ], yv[NRT];
 #pragma unroll
-  for (int qq = 0; qq < 4; ++qq)
-    ph[qq] = (i < nd && cq[qq] >= 0) ? cvt<double>(Phi[((size_t)s * ND + i) * 4 + qq]) : cd{0.0, 0.0};
+  for (int qq = 0; qq < NQ; ++qq)
+    ph[qq] = (i < nd && cq[qq] >= 0) ? cvt<double>(Phi[((size_t)s * ND + i) * NQ + qq]) : cd{0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < NRT; ++r)
     yv[r] = (i < nd && r < nr) ? ld_coh(Ybuf + r * rs.sb + (size_t)s * ND + i) : cd{0.0, 0.0};
-  cd acc[4][NRT];
+  const int npass = nK > g.nC ? 2 : 1;
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int r = 0; r < NRT; ++r) acc[q][r] = cd{0.0, 0.0};
-  for (int c = threadIdx.x; c < g.nC; c += blockDim.x) {
-    const int4 own = *(const int4*)(mp.cown + 4 * c);
-    const int ow[4] = {own.x, own.y, own.z, own.w};
-    cd gc[NRT];
-#pragma unroll
-    for (int r = 0; r < NRT; ++r) {
-      cd t[4];
-#pragma unroll
-      for (int o = 0; o < 4; ++o) t[o] = ld_coh(Cbuf + r * rs.c4 + max(ow[o], 0));
-      cd v{0.0, 0.0};
-#pragma unroll
-      for (int o = 0; o < 4; ++o) v = v + (ow[o] >= 0 ? t[o] : cd{0.0, 0.0});
-      gc[r] = r < nr ? v : cd{0.0, 0.0};
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (cq[q] < 0) continue;
-      const cd kv = Kinv[(size_t)cq[q] * g.nC + c];
-#pragma unroll
-      for (int r = 0; r < NRT; ++r) fma_acc(acc[q][r], kv, gc[r]);
-    }
-  }
-  {
-    // reduce-scatter over the wave: at each halving step a lane keeps half of its
-    // values and adds its partner's copy of them, so V = 4 NRT sums take
-    // V - 1 + log2(64 / V) shuffles instead of 6 V; lane bits 5.. then name
-    // the value a lane holds (value index = (q, r) in row-major order)
-    constexpr int V = 4 * NRT;
-    cd v[V];
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass >= npass) break;  // uniform: edge slots only with an augmented coarse space
+    cd acc[4][NRT];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int r = 0; r < NRT; ++r) v[q * NRT + r] = acc[q][r];
-    int idx = 0, off = 32;
+      for (int r = 0; r < NRT; ++r) acc[q][r] = cd{0.0, 0.0};
+    for (int c = threadIdx.x; c < nK; c += blockDim.x) {
+      const int4 own = *(const int4*)(mp.cown + 4 * c);
+      const int ow[4] = {own.x, own.y, own.z, own.w};
+      cd gc[NRT];
 #pragma unroll
-    for (int cnt = V; cnt > 1; cnt >>= 1, off >>= 1) {
-      const int half = cnt >> 1;
-      const bool up = (lane & off) != 0;
+      for (int r = 0; r < NRT; ++r) {
+        cd t[4];
 #pragma unroll
-      for (int i = 0; i < half; ++i) {
-        const cd send = up ? v[i] : v[half + i];
-        const cd keep = up ? v[half + i] : v[i];
-        cd recv;
-        recv.x = __shfl_xor(send.x, off, 64);
-        recv.y = __shfl_xor(send.y, off, 64);
-        v[i] = keep + recv;
+        for (int o = 0; o < 4; ++o) t[o] = ld_coh(Cbuf + r * rs.cq + max(ow[o], 0));
+        cd v{0.0, 0.0};
+#pragma unroll
+        for (int o = 0; o < 4; ++o) v = v + (ow[o] >= 0 ? t[o] : cd{0.0, 0.0});
+        gc[r] = r < nr ? v : cd{0.0, 0.0};
       }
-      if (up) idx += half;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cqq = cq[4 * pass + q];
+        if (cqq < 0) continue;
+        const cd kv = Kinv[(size_t)cqq * nK + c];
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) fma_acc(acc[q][r], kv, gc[r]);
+      }
     }
-    for (; off > 0; off >>= 1) {
-      v[0].x += __shfl_xor(v[0].x, off, 64);
-      v[0].y += __shfl_xor(v[0].y, off, 64);
+    {
+      // reduce-scatter over the wave: at each halving step a lane keeps half of its
+      // values and adds its partner's copy of them, so V = 4 NRT sums take
+      // V - 1 + log2(64 / V) shuffles instead of 6 V; lane bits 5.. then name
+      // the value a lane holds (value index = (q, r) in row-major order)
+      constexpr int V = 4 * NRT;
+      cd v[V];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) v[q * NRT + r] = acc[q][r];
+      int idx = 0, off = 32;
+#pragma unroll
+      for (int cnt = V; cnt > 1; cnt >>= 1, off >>= 1) {
+        const int half = cnt >> 1;
+        const bool up = (lane & off) != 0;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+          const cd send = up ? v[k] : v[half + k];
+          const cd keep = up ? v[half + k] : v[k];
+          cd recv;
+          recv.x = __shfl_xor(send.x, off, 64);
+          recv.y = __shfl_xor(send.y, off, 64);
+          v[k] = keep + recv;
+        }
+        if (up) idx += half;
+      }
+      for (; off > 0; off >>= 1) {
+        v[0].x += __shfl_xor(v[0].x, off, 64);
+        v[0].y += __shfl_xor(v[0].y, off, 64);
+      }
+      if ((lane & (64 / V - 1)) == 0) wred[wv * V + idx] = v[0];
     }
-    if ((lane & (64 / V - 1)) == 0) wred[wv * V + idx] = v[0];
+    __syncthreads();
+    if (threadIdx.x < 4 * NRT) {
+      const int q = threadIdx.x / NRT, r = threadIdx.x % NRT;
+      ucs[(4 * pass + q) * NRT + r] = (wred[q * NRT + r] + wred[(4 + q) * NRT + r]) +
+                                      (wred[(8 + q) * NRT + r] + wred[(12 + q) * NRT + r]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x < 4 * NRT) {
-    const int q = threadIdx.x / NRT, r = threadIdx.x % NRT;
-    ucs[q * NRT + r] = (wred[q * NRT + r] + wred[(4 + q) * NRT + r]) +
-                       (wred[(8 + q) * NRT + r] + wred[(12 + q) * NRT + r]);
-  }
-  __syncthreads();
   if (i < nd) {
 #pragma unroll
     for (int r = 0; r < NRT; ++r) {
       if (r >= nr) break;
       cd y = yv[r];
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq) fma_acc(y, ph[qq], ucs[qq * NRT + r]);
+      for (int qq = 0; qq < NQ; ++qq)
+        if (cq[qq] >= 0) fma_acc(y, ph[qq], ucs[qq * NRT + r]);
       st_coh(Ybuf + r * rs.sb + (size_t)s * ND + i, y);
     }
   }
@@ -983,7 +1043,7 @@ static size_t gmres_layout(int nrt, int kmax, int chunk, size_t tsz, size_t byte
   int wch = take(sizeof(cd) * nrt * chunk);
   int hv = take(sizeof(cd) * nrt * (kmax + 1)), h2 = take(sizeof(cd) * nrt * (kmax + 1));
   int cs = take(sizeof(cd) * nrt * (kmax + 1)), sn = take(sizeof(double) * nrt * (kmax + 1));
-  int g = take(sizeof(cd) * nrt * (kmax + 1)), ucs = take(sizeof(cd) * 4 * nrt);
+  int g = take(sizeof(cd) * nrt * (kmax + 1)), ucs = take(sizeof(cd) * NQ * nrt);
   int S = take(resident ? bytesS : std::max(bytesS, bytesI));
   int I = resident ? take(bytesI) : S;
   if (a) {
@@ -1266,7 +1326,7 @@ __global__ void __launch_bounds__(256) k_gmres(Src src, GmresLaunch L) {
   a.mu = d.mu + L.r0 * rs.nmu;
   a.Abuf = d.Abuf + L.r0 * rs.sb;
   a.Ybuf = d.Ybuf + L.r0 * rs.sb;
-  a.Cbuf = d.Cbuf + L.r0 * rs.c4;
+  a.Cbuf = d.Cbuf + L.r0 * rs.cq;
   a.w = d.wv + L.r0 * rs.nmu;
   a.Q = d.Qk;
   a.H = d.Hk;
@@ -1320,7 +1380,7 @@ __global__ void __launch_bounds__(256) k_iface_f1(Geo2 g, Maps2 mp, RhsStride rs
 template <class TS>
 __global__ void __launch_bounds__(256) k_iface_f2(Geo2 g, Maps2 mp, RhsStride rs, const TS* Phi,
                                                   const cd* Kinv, const cd* Cbuf, cd* Ybuf) {
-  __shared__ cd ucs[4], wred[16];
+  __shared__ cd ucs[NQ], wred[16];
   phase_f2<TS, 1>(g, mp, rs, Phi, Kinv, blockIdx.x, Cbuf, Ybuf, 1, ucs, wred);
 }
 __global__ void k_combine(Geo2 g, Maps2 mp, const cd* buf, double scale, cd* out) {
@@ -1361,6 +1421,7 @@ hipError_t launch_local_solve(const Target& t, int mode, int f, int conj_in, int
 }
 
 hipError_t launch_coarse_rhs(const Target& t, int f, int conj_in) {
+  launch2(t, K_SUB, k_edge_rhs<One>, k_edge_rhs<Many>, NRMAX, 256, 0);
   launch2(t, K_NC128, k_coarse_rhs<One>, k_coarse_rhs<Many>, NRMAX, 128, 0, f, conj_in);
   launch2(t, K_NC, k_dense_mv<One>, k_dense_mv<Many>, NRMAX, 64, 0, (int)V_FCS);
   return hipGetLastError();
@@ -1567,10 +1628,12 @@ int gmres_capacity(const Problem& p, int kmax, int chunk, int width) {
 }
 
 hipError_t launch_recover_coarse(const Target& t) {
-  if (t.s32()) launch2(t, K_SUB, k_frct<cf, One>, k_frct<cf, Many>, NRMAX, 256, 0);
-  else launch2(t, K_SUB, k_frct<cd, One>, k_frct<cd, Many>, NRMAX, 256, 0);
+  // NQ waves per block: one per (subdomain, coarse slot)
+  if (t.s32()) launch2(t, K_SUB, k_frct<cf, One>, k_frct<cf, Many>, NRMAX, 64 * NQ, 0);
+  else launch2(t, K_SUB, k_frct<cd, One>, k_frct<cd, Many>, NRMAX, 64 * NQ, 0);
   launch2(t, K_NC128, k_corner_sum<One>, k_corner_sum<Many>, NRMAX, 128, 0);
   launch2(t, K_NC, k_dense_mv<One>, k_dense_mv<Many>, NRMAX, 64, 0, (int)V_YMIN);
+  launch2(t, K_NMU256, k_add_edge_mult<One>, k_add_edge_mult<Many>, NRMAX, 256, 0);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ EXPORTS = [
     "sfdp_inspect", "sfdp_interface_apply", "sfdp_timing_enable", "sfdp_kernel_times",
     "sfdp_batch_create", "sfdp_batch_destroy", "sfdp_batch_sizes", "sfdp_batch_set_beta",
     "sfdp_batch_solve_range_space", "sfdp_server_create", "sfdp_server_submit", "sfdp_server_poll",
-    "sfdp_server_stats", "sfdp_server_destroy",
+    "sfdp_server_stats", "sfdp_server_destroy", "sfdp_set_coarse_space",
 ]
 
 
@@ -77,7 +77,8 @@ class Timing(ctypes.Structure):
 class Sizes(ctypes.Structure):
     _fields_ = [("n_free", ctypes.c_int64), ("n_bdry", ctypes.c_int64), ("n_sub", ctypes.c_int64),
                 ("n_mult", ctypes.c_int64), ("n_corner", ctypes.c_int64),
-                ("max_delta", ctypes.c_int64), ("resident_bytes", ctypes.c_int64)]
+                ("max_delta", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
+                ("n_coarse", ctypes.c_int64)]
 
 
 _lib = None
@@ -98,6 +99,7 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_last_error.restype = ctypes.c_char_p
     lib.sfdp_problem_create.argtypes = [P, I, I, I, I, ctypes.POINTER(P)]
     lib.sfdp_problem_sizes.argtypes = [P, ctypes.POINTER(Sizes)]
+    lib.sfdp_set_coarse_space.argtypes = [P, I]
     lib.sfdp_problem_destroy.argtypes = [P]
     lib.sfdp_problem_destroy.restype = None
     lib.sfdp_set_beta.argtypes = [P, D]
@@ -209,6 +211,11 @@ class Problem:
         _check(_lib.sfdp_problem_sizes(self._h, ctypes.byref(s)))
         self.sizes = {f: getattr(s, f) for f, _ in Sizes._fields_}
         return self.sizes
+
+    def set_coarse_space(self, edge_averages: bool):
+        """Edge-augmented (True, the default) or corner-only coarse space; takes
+        effect at the next set_beta."""
+        _check(_lib.sfdp_set_coarse_space(self._h, int(bool(edge_averages))))
 
     def set_beta(self, beta: float):
         _check(_lib.sfdp_set_beta(self._h, float(beta)))

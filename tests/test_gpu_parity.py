@@ -59,15 +59,36 @@ def test_apply_operator_matches_oracle(sf, N, m):
     prob.close()
 
 
+def _edge_columns(dec, ops, Q, keys, s, isd):
+    """Expected edge columns of subdomain s's coarse basis, in the library's slot
+    order (left, right, bottom, top side): Z_rr^-1 B_r^T q_e on the Delta rows."""
+    P, pc, Br = dec.P, ops["pieces"][s], dec.subs[s]["Br"]
+    sx, sy = s % P, s // P
+    cols = []
+    for ok, pair in ((sx > 0, (s - 1, s)), (sx < P - 1, (s, s + 1)), (sy > 0, (s - P, s)),
+                     (sy < P - 1, (s, s + P))):
+        if ok:
+            e = keys.index(pair)
+            cols.append((pc["Zrr_inv"] @ (Br.T @ Q[:, e]))[isd])
+    return cols
+
+
 @pytest.mark.parametrize("N,m,beta", [(12, 4, 1e-3), (32, 8, 1e-4), (24, 6, 1e-6)])
-def test_local_operators_and_coarse_match_definitions(sf, N, m, beta):
-    """Z_rr^-1|Delta, S_bb, Phi per subdomain and the coarse matrix (Sec. 5) vs dense definitions."""
+@pytest.mark.parametrize("edges", [True, False])
+def test_local_operators_and_coarse_match_definitions(sf, N, m, beta, edges):
+    """Z_rr^-1|Delta, S_bb, the coarse basis per subdomain and the coarse matrix (Sec. 5) vs
+    dense definitions; with edge averages (the default) the basis adds Z_rr^-1 B_r^T q_e and
+    the coarse matrix is the augmented one."""
     sfdp, ctx = sf
     mesh = fem.Mesh(2, N)
     dec = feti.Decomposition(mesh, m)
     ops = feti.fetidp_operators(dec, beta ** -0.5)
+    Q, keys = feti.edge_space(dec)
+    aug = feti.fetidp_aug_operators(ops, Q)
     prob = sfdp.Problem(ctx, 2, N, m)
+    prob.set_coarse_space(edges)
     prob.set_beta(beta)
+    assert prob.refresh_sizes()["n_coarse"] == dec.nC + (Q.shape[1] if edges else 0)
     for s, pc in enumerate(ops["pieces"]):
         isd = pc["is_delta"]
         sinv = prob.inspect(sfdp.Q_SINV, s).cpu().numpy()
@@ -79,32 +100,42 @@ def test_local_operators_and_coarse_match_definitions(sf, N, m, beta):
         # S_bb is stored in complex64 on both paths (it only preconditions)
         assert np.abs(sbb - pc["Sbb"]).max() / np.abs(pc["Sbb"]).max() < 1e-6
         ref_phi = pc["Phi"][isd]
+        if edges:
+            ref_phi = np.column_stack([ref_phi] + _edge_columns(dec, ops, Q, keys, s, isd))
+        assert phi.shape == ref_phi.shape
         assert np.abs(phi - ref_phi).max() / np.abs(ref_phi).max() < 1e-12
     kc = prob.inspect(sfdp.Q_COARSE).cpu().numpy()
-    assert np.abs(kc - ops["Kcc"]).max() / np.abs(ops["Kcc"]).max() < 1e-12
+    ref_k = aug["Kt"] if edges else ops["Kcc"]
+    assert kc.shape == ref_k.shape
+    assert np.abs(kc - ref_k).max() / np.abs(ref_k).max() < 1e-12
     prob.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_interface_operators_match_definitions(sf, precision):
-    """F_DP, Dirichlet P^-1 and the right-hand side d (Sec. 5) on multiplier vectors."""
+@pytest.mark.parametrize("precision,edges", [(0, True), (1, True), (0, False)])
+def test_interface_operators_match_definitions(sf, precision, edges):
+    """F_DP (or F_aug), Dirichlet P^-1 and the right-hand side d (or d_aug) (Sec. 5) on
+    multiplier vectors."""
     sfdp, ctx = sf
     N, m, beta = 16, 4, 1e-3
     mesh = fem.Mesh(2, N)
     dec = feti.Decomposition(mesh, m)
     ops = feti.fetidp_operators(dec, beta ** -0.5)
+    Q, _ = feti.edge_space(dec)
+    aug = feti.fetidp_aug_operators(ops, Q)
     prob = sfdp.Problem(ctx, 2, N, m, precision)
+    prob.set_coarse_space(edges)
     prob.set_beta(beta)
     tol = 1e-12 if precision == 0 else 1e-5
     mu = W.random_vector(dec.nmu, 5, complex_=True)
     F = prob.interface_apply("F", _t(mu)).cpu().numpy()
-    assert _rel(F, feti.fetidp_apply(ops, mu)) < tol
+    Fref = feti.fetidp_aug_apply(ops, aug, mu) if edges else feti.fetidp_apply(ops, mu)
+    assert _rel(F, Fref) < tol
     P = prob.interface_apply("P", _t(mu)).cpu().numpy()
     # the preconditioner's S_bb is complex64 on both paths
     assert _rel(P, feti.dirichlet_preconditioner(dec, ops) @ mu) < 1e-5
     f = W.random_vector(mesh.n, 6, complex_=True)
     d = prob.interface_apply("D", _t(f)).cpu().numpy()
-    dref, _, _ = feti.fetidp_rhs(dec, ops, f)
+    dref = feti.fetidp_aug_rhs(dec, ops, aug, f)[0] if edges else feti.fetidp_rhs(dec, ops, f)[0]
     assert _rel(d, dref) < tol
     prob.close()
 
@@ -128,6 +159,32 @@ def test_feti_solve_matches_direct(sf, N, m, beta, conj_z):
         xr = lu.solve(f[r])
         assert _rel(x[r], xr) < 1e-9, (its, _rel(x[r], xr))
         assert 0 < its[r] < 300
+    prob.close()
+
+
+@pytest.mark.parametrize("N,m,beta", [(64, 8, 1e-4), (128, 16, 1e-2)])
+def test_edge_augmentation_same_solution_fewer_iterations(sf, N, m, beta):
+    """The edge-augmented coarse space (default) and the corner-only one give the same
+    FETI-DP solution (both against SuperLU); the augmented one takes fewer GMRES iterations."""
+    sfdp, ctx = sf
+    mesh = fem.Mesh(2, N)
+    A = fem.assemble(mesh)
+    Z = solve.complex_factor(A["K"], A["M"], beta)
+    f = np.stack([W.random_vector(mesh.n, 21 + r, complex_=True) for r in range(2)])
+    prob = sfdp.Problem(ctx, 2, N, m)
+    res = {}
+    for edges in (False, True):
+        prob.set_coarse_space(edges)
+        prob.set_beta(beta)
+        x, its = prob.feti_solve(_t(f), tol_inner=1e-10)
+        res[edges] = (x.cpu().numpy(), its)
+    lu = spla.splu(Z.tocsc())
+    for r in range(2):
+        xr = lu.solve(f[r])
+        for edges in (False, True):
+            assert _rel(res[edges][0][r], xr) < 1e-8, (edges, r)
+    print("iterations corner-only", res[False][1], "edge-augmented", res[True][1])
+    assert all(a < b for a, b in zip(res[True][1], res[False][1])), (res[True][1], res[False][1])
     prob.close()
 
 
