@@ -46,20 +46,23 @@ def measured_traffic(kernel):
     return rec["kernels"][kernel]["bytes_per_launch"]
 
 
-def gmres_operator_bytes(N, m, ncorner, elem_bytes):
+def gmres_operator_bytes(N, m, ncoarse, edges, elem_bytes):
     """Operator bytes one GMRES loop trip must pass over, shared by all the
     right-hand sides of the launch: per subdomain the packed symmetric
     interface Schur complement (complex64) and the packed Z_rr^-1|Delta
-    (storage precision), n_d (n_d + 1) / 2 entries each, and Phi (n_d x n_c,
-    storage precision); the coarse inverse once (n_C^2 FP64 complex)."""
+    (storage precision), n_d (n_d + 1) / 2 entries each, and the coarse basis
+    (n_d x (corners + edges when edge-augmented), storage precision); the
+    coarse inverse once (n_K^2 FP64 complex)."""
     P = N // m
     tot = 0
     for sy in range(P):
         for sx in range(P):
-            nd = sum(m - 1 for side in (sx > 0, sx < P - 1, sy > 0, sy < P - 1) if side)
+            sides = sum(1 for side in (sx > 0, sx < P - 1, sy > 0, sy < P - 1) if side)
+            nd = (m - 1) * sides
             nc = sum(1 for cx in (sx, sx + 1) for cy in (sy, sy + 1) if 0 < cx < P and 0 < cy < P)
-            tot += nd * (nd + 1) // 2 * (8 + elem_bytes) + nd * nc * elem_bytes
-    return tot + ncorner * ncorner * 16
+            nq = nc + (sides if edges else 0)
+            tot += nd * (nd + 1) // 2 * (8 + elem_bytes) + nd * nq * elem_bytes
+    return tot + ncoarse * ncoarse * 16
 
 
 def gmres_vector_bytes(nmu, mean_its):
@@ -264,8 +267,10 @@ def cpu_instances(count, seed, budget_s=10.0):
 
 
 def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup, tol_kkt, tol_inner,
-                  batch, max_krylov=0, factors=0):
+                  batch, max_krylov=0, factors=0, edges=None):
     p = sfdp.Problem(ctx, 2, N, m, precision)
+    if edges is not None:
+        p.set_coarse_space(edges)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     p.set_beta(beta)
@@ -379,13 +384,16 @@ def main():
         hp, htin = precs[0][1], precs[0][2]
         res[head + "_single_solve"] = run_precision(sfdp, torch, ctx, hp, N, m, beta, ybar_t, args.steps,
                                                     args.warmup, tol_kkt, htin, B, args.max_krylov, factors=1)
+        # the corner-only coarse space, for the effect of the edge augmentation
+        res[head + "_corners_only"] = run_precision(sfdp, torch, ctx, hp, N, m, beta, ybar_t, args.steps,
+                                                    args.warmup, tol_kkt, htin, B, args.max_krylov, edges=False)
     r = res[head]
     kt = r["kernel_times"]
     sz = r["sizes"]
     trips = kt["gmres_iters"] / max(kt["gmres_launches"], 1)          # loop trips per launch
     rhs_its = kt["gmres_rhs_iters"] / max(kt["gmres_launches"], 1)    # RHS iterations per launch
     ebytes = 8 if head == "mixed" else 16
-    op_bytes = gmres_operator_bytes(N, m, sz["n_corner"], ebytes)
+    op_bytes = gmres_operator_bytes(N, m, sz["n_coarse"], sz["n_coarse"] > sz["n_corner"], ebytes)
     vec_bytes = gmres_vector_bytes(sz["n_mult"], rhs_its / B)
     launch_bytes = trips * op_bytes + rhs_its * vec_bytes
     launch_ms = kt["gmres_ms"] / max(kt["gmres_launches"], 1)
@@ -409,6 +417,8 @@ def main():
                                f"{m}x{m}, beta={beta:g}, 16-mode sine targets (seeds 0..{B - 1}), "
                                f"{B} targets per step sharing every launch",
                    "precision": head, "tol_kkt": tol_kkt, "batch": B,
+                   "coarse_space": "corners + interface-edge averages"
+                   if sz["n_coarse"] > sz["n_corner"] else "corners",
                    "storage": "c64 factors and interface operators, FP64 arithmetic"
                    if head == "mixed" else "c128",
                    "max_krylov": args.max_krylov or 64,

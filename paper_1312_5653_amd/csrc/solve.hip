@@ -908,38 +908,41 @@ __device__ void phase_f2(const Geo2& g, const Maps2& mp, const RhsStride& rs,
 #pragma unroll
   for (int r = 0; r < NRT; ++r)
     yv[r] = (i < nd && r < nr) ? ld_coh(Ybuf + r * rs.sb + (size_t)s * ND + i) : cd{0.0, 0.0};
-  const int npass = nK > g.nC ? 2 : 1;
+  // one sweep over the coarse unknowns for all slots: g_r[c] is gathered once
+  cd acc[NQ][NRT];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) acc[q][r] = cd{0.0, 0.0};
+  const bool edges = nK > g.nC;
+  for (int c = threadIdx.x; c < nK; c += blockDim.x) {
+    const int4 own = *(const int4*)(mp.cown + 4 * c);
+    const int ow[4] = {own.x, own.y, own.z, own.w};
+    cd gc[NRT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      cd t[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) t[o] = ld_coh(Cbuf + r * rs.cq + max(ow[o], 0));
+      cd v{0.0, 0.0};
+#pragma unroll
+      for (int o = 0; o < 4; ++o) v = v + (ow[o] >= 0 ? t[o] : cd{0.0, 0.0});
+      gc[r] = r < nr ? v : cd{0.0, 0.0};
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int cqq = cq[q];
+      if (cqq < 0) continue;
+      const cd kv = Kinv[(size_t)cqq * nK + c];
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) fma_acc(acc[q][r], kv, gc[r]);
+    }
+  }
+  // block sums of the slot values, four slots at a time (the corner slots, then
+  // the edge slots when the coarse space has them)
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
-    if (pass >= npass) break;  // uniform: edge slots only with an augmented coarse space
-    cd acc[4][NRT];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int r = 0; r < NRT; ++r) acc[q][r] = cd{0.0, 0.0};
-    for (int c = threadIdx.x; c < nK; c += blockDim.x) {
-      const int4 own = *(const int4*)(mp.cown + 4 * c);
-      const int ow[4] = {own.x, own.y, own.z, own.w};
-      cd gc[NRT];
-#pragma unroll
-      for (int r = 0; r < NRT; ++r) {
-        cd t[4];
-#pragma unroll
-        for (int o = 0; o < 4; ++o) t[o] = ld_coh(Cbuf + r * rs.cq + max(ow[o], 0));
-        cd v{0.0, 0.0};
-#pragma unroll
-        for (int o = 0; o < 4; ++o) v = v + (ow[o] >= 0 ? t[o] : cd{0.0, 0.0});
-        gc[r] = r < nr ? v : cd{0.0, 0.0};
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int cqq = cq[4 * pass + q];
-        if (cqq < 0) continue;
-        const cd kv = Kinv[(size_t)cqq * nK + c];
-#pragma unroll
-        for (int r = 0; r < NRT; ++r) fma_acc(acc[q][r], kv, gc[r]);
-      }
-    }
+    if (pass == 1 && !edges) break;  // uniform
     {
       // reduce-scatter over the wave: at each halving step a lane keeps half of its
       // values and adds its partner's copy of them, so V = 4 NRT sums take
@@ -950,7 +953,7 @@ __device__ void phase_f2(const Geo2& g, const Maps2& mp, const RhsStride& rs,
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int r = 0; r < NRT; ++r) v[q * NRT + r] = acc[q][r];
+        for (int r = 0; r < NRT; ++r) v[q * NRT + r] = acc[4 * pass + q][r];
       int idx = 0, off = 32;
 #pragma unroll
       for (int cnt = V; cnt > 1; cnt >>= 1, off >>= 1) {
