@@ -368,7 +368,7 @@ def main():
     res = {}
     precs = [("fp64", sfdp.SFDP_FP64, 1e-13)]
     if not args.fp64_only:
-        precs.insert(0, ("mixed", sfdp.SFDP_MIXED, 1e-7))
+        precs.insert(0, ("mixed", sfdp.SFDP_MIXED, 3e-7))
     if args.headline_only:
         precs = precs[:1]
     for name, prec, tin in precs:

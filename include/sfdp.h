@@ -90,7 +90,8 @@ typedef struct {
   double tol_kkt;   /* stop when ||b - A x|| / ||b|| of the KKT system <= tol_kkt
                        [1e-10 FP64, 1e-8 MIXED] */
   double tol_inner; /* relative interface residual of each FETI-DP solve
-                       [1e-8 FP64, 1e-7 MIXED] */
+                       [1e-8 FP64, 3e-7 MIXED; with complex64 operators GMRES
+                       stagnates below about 5e-8] */
   int max_outer;    /* outer refinement steps [8] */
   int max_krylov;   /* GMRES iterations per FETI-DP solve, <= 400 [64]; the GMRES
                        kernel keeps per-iteration state for this many steps in

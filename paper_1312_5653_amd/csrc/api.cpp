@@ -268,7 +268,7 @@ void defaults(sfdp_precision prec, const sfdp_opts* o, double& tol_kkt, double& 
               int& kmax) {
   bool mixed = prec != SFDP_FP64;
   tol_kkt = (o && o->tol_kkt > 0) ? o->tol_kkt : (mixed ? 1e-8 : 1e-10);
-  tol_inner = (o && o->tol_inner > 0) ? o->tol_inner : (mixed ? 1e-7 : 1e-8);
+  tol_inner = (o && o->tol_inner > 0) ? o->tol_inner : (mixed ? 3e-7 : 1e-8);
   max_outer = (o && o->max_outer > 0) ? o->max_outer : 8;
   kmax = (o && o->max_krylov > 0) ? std::min(o->max_krylov, KMAX_LIMIT) : 64;
 }
