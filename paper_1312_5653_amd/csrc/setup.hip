@@ -43,6 +43,7 @@ __device__ void gj_invert_lds(cd* T, int n, cd* rowk, cd* colk) {
       else v = T[idx] - colk[i] * (rowk[j] * piv);
       T[idx] = v;
     }
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 }
@@ -426,19 +427,16 @@ __global__ void __launch_bounds__(256) k_coarse_inv_lds(Src src) {
 
 // Coarse inverse of a mid-size coarse matrix (GJ_LDS_MAX < nK <= GJ_BLOCK_MAX)
 // by Gauss-Jordan without pivoting in global memory, one 1024-thread workgroup
-// per instance: Kinv = GJ(Kcc), corners first.  Row k and column k of each
-// step are copied to LDS; every other entry is read and written by one thread.
-// Accesses to Kinv are coherent (device scope) and every wave waits for its
-// memory operations before each barrier.
+// per instance: Kinv = GJ(Kcc), corners first.  Every entry is read and
+// written by one owner thread (plain accesses, so a thread's loads of a step
+// are in flight together); row k and column k, written by other threads, are
+// copied to LDS through coherent loads after every wave has waited for its
+// stores and passed the barrier.
 constexpr int GJ_BLOCK_MAX = 256;
 __device__ inline cd gl_ld(const cd* p) {
   double x = __hip_atomic_load((const double*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   double y = __hip_atomic_load((const double*)p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return cd{x, y};
-}
-__device__ inline void gl_st(cd* p, cd v) {
-  __hip_atomic_store((double*)p, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store((double*)p + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <class Src>
 __global__ void __launch_bounds__(1024) k_coarse_inv_block(Src src) {
@@ -447,7 +445,7 @@ __global__ void __launch_bounds__(1024) k_coarse_inv_block(Src src) {
   if (n <= GJ_LDS_MAX || n > GJ_BLOCK_MAX) return;
   __shared__ cd rowk[GJ_BLOCK_MAX], colk[GJ_BLOCK_MAX];
   cd* T = d.Kinv;
-  for (int i = threadIdx.x; i < n * n; i += blockDim.x) gl_st(T + i, d.Kcc[i]);
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) T[i] = d.Kcc[i];
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int k = 0; k < n; ++k) {
@@ -463,8 +461,8 @@ __global__ void __launch_bounds__(1024) k_coarse_inv_block(Src src) {
       if (i == k && j == k) v = piv;
       else if (i == k) v = rowk[j] * piv;
       else if (j == k) v = -(colk[i] * piv);
-      else v = gl_ld(T + idx) - colk[i] * (rowk[j] * piv);
-      gl_st(T + idx, v);
+      else v = T[idx] - colk[i] * (rowk[j] * piv);
+      T[idx] = v;
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
