@@ -74,14 +74,14 @@ def gmres_vector_bytes(nmu, mean_its):
     return (4 * (jmean + 1) + 6) * nmu * 16
 
 
-def local_solve_bytes(N, m, elem_bytes):
-    """Bytes one subdomain-solve launch must read per right-hand side: the
-    line factors of every subdomain (m + 1 lines of (m + 1)^2 entries), once
-    in the forward and once in the backward sweep, plus the load vector and
-    the result (FP64 complex)."""
+def local_solve_bytes(N, m, elem_bytes, nrhs):
+    """Bytes one subdomain-solve launch must move for nrhs right-hand sides: the
+    line factors of every subdomain (m + 1 lines of (m + 1)^2 entries) once in
+    the forward and once in the backward sweep, shared by all right-hand sides,
+    plus each right-hand side's load vector and result (FP64 complex)."""
     P = N // m
     ml = m + 1
-    return P * P * ml * ml * ml * elem_bytes * 2 + 2 * (N - 1) ** 2 * 16
+    return P * P * ml * ml * ml * elem_bytes * 2 + nrhs * 2 * (N - 1) ** 2 * 16
 
 
 def _kernel_key(name):
@@ -399,7 +399,7 @@ def main():
     launch_ms = kt["gmres_ms"] / max(kt["gmres_launches"], 1)
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
     local_ms = kt["local_ms"] / max(kt["local_launches"], 1)
-    local_gbs = B * local_solve_bytes(N, m, ebytes) / (local_ms * 1e-3) / 1e9
+    local_gbs = local_solve_bytes(N, m, ebytes, B) / (local_ms * 1e-3) / 1e9
     out = {
         "metric": "Schur solves/sec at rel. KKT residual 1e-8 (512² Q1); p50/p99 solve latency",
         "value": r["solves_per_s"],
