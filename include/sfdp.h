@@ -226,8 +226,10 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
  *                averages [[K_cc*, -F_rc^T Q], [-Q^T F_rc, -Q^T F_rr Q]] over
  *                the corners (increasing node id) then the edges (increasing
  *                pair of adjacent subdomains);
+ *   SFDP_Q_COARSE_INV : its inverse as used by the solves (Gauss-Jordan
+ *                without pivoting, corners first);
  * out may be NULL to query the shape only. */
-typedef enum { SFDP_Q_SINV = 0, SFDP_Q_SBB = 1, SFDP_Q_PHI = 2, SFDP_Q_COARSE = 3 } sfdp_query;
+typedef enum { SFDP_Q_SINV = 0, SFDP_Q_SBB = 1, SFDP_Q_PHI = 2, SFDP_Q_COARSE = 3, SFDP_Q_COARSE_INV = 4 } sfdp_query;
 sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out, int* rows, int* cols);
 
 /* Interface-level products for testing, on multiplier vectors (complex,

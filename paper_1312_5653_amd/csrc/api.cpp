@@ -1179,7 +1179,7 @@ sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out,
   HIPCHK(hipMemcpy(cg.data(), p->cgid, sizeof(int) * NQ * p->nsub, hipMemcpyDeviceToHost));
   int r = 0, c = 0;
   std::vector<int> qcols;  // coarse slots returned as columns (SFDP_Q_PHI)
-  if (what == SFDP_Q_COARSE) {
+  if (what == SFDP_Q_COARSE || what == SFDP_Q_COARSE_INV) {
     r = c = p->nK;
   } else {
     if (sub < 0 || sub >= p->nsub) return fail(SFDP_E_INVALID, "sub out of range");
@@ -1200,8 +1200,9 @@ sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out,
   hipStream_t st = p->ctx->stream;
   HIPCHK(hipStreamSynchronize(st));
   std::vector<cd> host((size_t)r * c);
-  if (what == SFDP_Q_COARSE) {
-    HIPCHK(hipMemcpy(host.data(), p->Kcc, sizeof(cd) * host.size(), hipMemcpyDeviceToHost));
+  if (what == SFDP_Q_COARSE || what == SFDP_Q_COARSE_INV) {
+    HIPCHK(hipMemcpy(host.data(), what == SFDP_Q_COARSE ? p->Kcc : p->Kinv, sizeof(cd) * host.size(),
+                     hipMemcpyDeviceToHost));
   } else if (what == SFDP_Q_PHI) {
     size_t es = elem_size(*p);
     std::vector<char> raw((size_t)p->ND * NQ * es);

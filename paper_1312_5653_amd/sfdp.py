@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libsfdp.so")
 
 SFDP_FP64, SFDP_MIXED, SFDP_MIXED_IFACE = 0, 1, 2
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_NOCONV", -4: "E_DEVICE", -5: "E_STATE"}
-Q_SINV, Q_SBB, Q_PHI, Q_COARSE = 0, 1, 2, 3
+Q_SINV, Q_SBB, Q_PHI, Q_COARSE, Q_COARSE_INV = 0, 1, 2, 3, 4
 
 EXPORTS = [
     "sfdp_ctx_create", "sfdp_ctx_destroy", "sfdp_last_error", "sfdp_problem_create",

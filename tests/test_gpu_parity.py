@@ -111,6 +111,24 @@ def test_local_operators_and_coarse_match_definitions(sf, N, m, beta, edges):
     prob.close()
 
 
+@pytest.mark.parametrize("N,m", [(32, 8), (64, 8), (96, 8)])
+def test_coarse_inverse_paths(sf, N, m):
+    """The coarse inverse by each of its three paths -- in LDS (33 unknowns), one
+    workgroup in global memory (161) and one launch per pivot (385) -- equals the
+    inverse of the assembled coarse matrix."""
+    sfdp, ctx = sf
+    prob = sfdp.Problem(ctx, 2, N, m)
+    prob.set_beta(1e-4)
+    k = prob.inspect(sfdp.Q_COARSE).cpu().numpy()
+    kinv = prob.inspect(sfdp.Q_COARSE_INV).cpu().numpy()
+    P = N // m
+    assert k.shape[0] == (P - 1) ** 2 + 2 * P * (P - 1)
+    ref = np.linalg.inv(k)
+    assert np.abs(kinv - ref).max() / np.abs(ref).max() < 1e-11
+    assert np.abs(kinv @ k - np.eye(k.shape[0])).max() < 1e-10
+    prob.close()
+
+
 @pytest.mark.parametrize("precision,edges", [(0, True), (1, True), (0, False)])
 def test_interface_operators_match_definitions(sf, precision, edges):
     """F_DP (or F_aug), Dirichlet P^-1 and the right-hand side d (or d_aug) (Sec. 5) on
