@@ -262,6 +262,12 @@ sfdp_status sfdp_batch_sizes(const sfdp_batch* b, int i, sfdp_sizes* out);
 /* Factor every instance for its beta[i] (host array of count values), as
  * sfdp_set_beta does for one problem. */
 sfdp_status sfdp_batch_set_beta(sfdp_batch* b, const double* beta);
+/* The set-up operators of instance i after sfdp_batch_set_beta, as sfdp_inspect
+ * returns them for one problem (same queries, shapes and errors); a batch may
+ * take other set-up paths than a lone problem (the coarse inverse of several
+ * mid-size instances, one workgroup each). */
+sfdp_status sfdp_batch_inspect(sfdp_batch* b, int i, sfdp_query what, int sub, double* out, int* rows,
+                               int* cols);
 /* Range-space solves (as sfdp_solve_range_space) of nrhs[i] targets of
  * instance i.  ybar, yc, y, u, lam are host arrays of count device pointers
  * (each as in sfdp_solve_range_space; yc or yc[i] may be NULL for zero

@@ -803,6 +803,77 @@ sfdp_status gather_one(Problem* p) {
 }  // namespace
 
 struct sfdp_ctx : public Ctx {};
+static sfdp_status inspect_problem(Problem* p, sfdp_query what, int sub, double* out, int* rows, int* cols) {
+  sfdp_status s = check_ready(p);
+  if (s) return s;
+  HIPCHK(hipSetDevice(p->ctx->device));
+  std::vector<int> ndv(p->nsub), cg(NQ * p->nsub);
+  HIPCHK(hipMemcpy(ndv.data(), p->nd, sizeof(int) * p->nsub, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(cg.data(), p->cgid, sizeof(int) * NQ * p->nsub, hipMemcpyDeviceToHost));
+  int r = 0, c = 0;
+  std::vector<int> qcols;  // coarse slots returned as columns (SFDP_Q_PHI)
+  if (what == SFDP_Q_COARSE || what == SFDP_Q_COARSE_INV) {
+    r = c = p->nK;
+  } else {
+    if (sub < 0 || sub >= p->nsub) return fail(SFDP_E_INVALID, "sub out of range");
+    r = ndv[sub];
+    if (what == SFDP_Q_PHI) {
+      for (int q = 0; q < NQ; ++q)
+        if (cg[NQ * sub + q] >= 0 && cg[NQ * sub + q] < p->nK) qcols.push_back(q);
+      c = (int)qcols.size();
+    } else if (what == SFDP_Q_SINV || what == SFDP_Q_SBB) {
+      c = r;
+    } else {
+      return fail(SFDP_E_INVALID, "unknown query");
+    }
+  }
+  if (rows) *rows = r;
+  if (cols) *cols = c;
+  if (!out) return SFDP_OK;
+  hipStream_t st = p->ctx->stream;
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<cd> host((size_t)r * c);
+  if (what == SFDP_Q_COARSE || what == SFDP_Q_COARSE_INV) {
+    HIPCHK(hipMemcpy(host.data(), what == SFDP_Q_COARSE ? p->Kcc : p->Kinv, sizeof(cd) * host.size(),
+                     hipMemcpyDeviceToHost));
+  } else if (what == SFDP_Q_PHI) {
+    size_t es = elem_size(*p);
+    std::vector<char> raw((size_t)p->ND * NQ * es);
+    HIPCHK(hipMemcpy(raw.data(), (const char*)p->Phi + (size_t)sub * p->ND * NQ * es, raw.size(),
+                     hipMemcpyDeviceToHost));
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < c; ++j) {
+        size_t idx = (size_t)i * NQ + qcols[j];
+        if (es == sizeof(cf)) {
+          cf v = ((const cf*)raw.data())[idx];
+          host[(size_t)i * c + j] = cd{v.x, v.y};
+        } else {
+          host[(size_t)i * c + j] = ((const cd*)raw.data())[idx];
+        }
+      }
+  } else {
+    // packed lower triangles: Sinv in the storage precision, Sbb in complex64
+    size_t es = (what == SFDP_Q_SBB) ? sizeof(cf) : elem_size(*p);
+    size_t PK = (size_t)p->ND * (p->ND + 1) / 2;
+    const char* base = (const char*)(what == SFDP_Q_SINV ? p->Sinv : p->Sbb);
+    std::vector<char> raw(PK * es);
+    HIPCHK(hipMemcpy(raw.data(), base + (size_t)sub * PK * es, raw.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < c; ++j) {
+        int a = std::max(i, j), b = std::min(i, j);
+        size_t idx = (size_t)a * (a + 1) / 2 + b;
+        if (es == sizeof(cf)) {
+          cf v = ((const cf*)raw.data())[idx];
+          host[(size_t)i * c + j] = cd{v.x, v.y};
+        } else {
+          host[(size_t)i * c + j] = ((const cd*)raw.data())[idx];
+        }
+      }
+  }
+  HIPCHK(hipMemcpy(out, host.data(), sizeof(cd) * host.size(), hipMemcpyHostToDevice));
+  return SFDP_OK;
+}
+
 struct sfdp_problem : public Problem {};
 struct sfdp_batch {
   Ctx* ctx = nullptr;
@@ -1104,6 +1175,12 @@ sfdp_status sfdp_batch_sizes(const sfdp_batch* b, int i, sfdp_sizes* out) {
   return SFDP_OK;
 }
 
+sfdp_status sfdp_batch_inspect(sfdp_batch* b, int i, sfdp_query what, int sub, double* out, int* rows,
+                               int* cols) {
+  if (!b || i < 0 || i >= (int)b->probs.size()) return fail(SFDP_E_INVALID, "bad arguments");
+  return inspect_problem(b->probs[i], what, sub, out, rows, cols);
+}
+
 sfdp_status sfdp_batch_set_beta(sfdp_batch* b, const double* beta) {
   if (!b || !beta) return fail(SFDP_E_INVALID, "bad arguments");
   for (size_t i = 0; i < b->probs.size(); ++i)
@@ -1171,74 +1248,7 @@ sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const d
 
 
 sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out, int* rows, int* cols) {
-  sfdp_status s = check_ready(p);
-  if (s) return s;
-  HIPCHK(hipSetDevice(p->ctx->device));
-  std::vector<int> ndv(p->nsub), cg(NQ * p->nsub);
-  HIPCHK(hipMemcpy(ndv.data(), p->nd, sizeof(int) * p->nsub, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(cg.data(), p->cgid, sizeof(int) * NQ * p->nsub, hipMemcpyDeviceToHost));
-  int r = 0, c = 0;
-  std::vector<int> qcols;  // coarse slots returned as columns (SFDP_Q_PHI)
-  if (what == SFDP_Q_COARSE || what == SFDP_Q_COARSE_INV) {
-    r = c = p->nK;
-  } else {
-    if (sub < 0 || sub >= p->nsub) return fail(SFDP_E_INVALID, "sub out of range");
-    r = ndv[sub];
-    if (what == SFDP_Q_PHI) {
-      for (int q = 0; q < NQ; ++q)
-        if (cg[NQ * sub + q] >= 0 && cg[NQ * sub + q] < p->nK) qcols.push_back(q);
-      c = (int)qcols.size();
-    } else if (what == SFDP_Q_SINV || what == SFDP_Q_SBB) {
-      c = r;
-    } else {
-      return fail(SFDP_E_INVALID, "unknown query");
-    }
-  }
-  if (rows) *rows = r;
-  if (cols) *cols = c;
-  if (!out) return SFDP_OK;
-  hipStream_t st = p->ctx->stream;
-  HIPCHK(hipStreamSynchronize(st));
-  std::vector<cd> host((size_t)r * c);
-  if (what == SFDP_Q_COARSE || what == SFDP_Q_COARSE_INV) {
-    HIPCHK(hipMemcpy(host.data(), what == SFDP_Q_COARSE ? p->Kcc : p->Kinv, sizeof(cd) * host.size(),
-                     hipMemcpyDeviceToHost));
-  } else if (what == SFDP_Q_PHI) {
-    size_t es = elem_size(*p);
-    std::vector<char> raw((size_t)p->ND * NQ * es);
-    HIPCHK(hipMemcpy(raw.data(), (const char*)p->Phi + (size_t)sub * p->ND * NQ * es, raw.size(),
-                     hipMemcpyDeviceToHost));
-    for (int i = 0; i < r; ++i)
-      for (int j = 0; j < c; ++j) {
-        size_t idx = (size_t)i * NQ + qcols[j];
-        if (es == sizeof(cf)) {
-          cf v = ((const cf*)raw.data())[idx];
-          host[(size_t)i * c + j] = cd{v.x, v.y};
-        } else {
-          host[(size_t)i * c + j] = ((const cd*)raw.data())[idx];
-        }
-      }
-  } else {
-    // packed lower triangles: Sinv in the storage precision, Sbb in complex64
-    size_t es = (what == SFDP_Q_SBB) ? sizeof(cf) : elem_size(*p);
-    size_t PK = (size_t)p->ND * (p->ND + 1) / 2;
-    const char* base = (const char*)(what == SFDP_Q_SINV ? p->Sinv : p->Sbb);
-    std::vector<char> raw(PK * es);
-    HIPCHK(hipMemcpy(raw.data(), base + (size_t)sub * PK * es, raw.size(), hipMemcpyDeviceToHost));
-    for (int i = 0; i < r; ++i)
-      for (int j = 0; j < c; ++j) {
-        int a = std::max(i, j), b = std::min(i, j);
-        size_t idx = (size_t)a * (a + 1) / 2 + b;
-        if (es == sizeof(cf)) {
-          cf v = ((const cf*)raw.data())[idx];
-          host[(size_t)i * c + j] = cd{v.x, v.y};
-        } else {
-          host[(size_t)i * c + j] = ((const cd*)raw.data())[idx];
-        }
-      }
-  }
-  HIPCHK(hipMemcpy(out, host.data(), sizeof(cd) * host.size(), hipMemcpyHostToDevice));
-  return SFDP_OK;
+  return inspect_problem(p, what, sub, out, rows, cols);
 }
 
 sfdp_status sfdp_timing_enable(sfdp_problem* p, int enable) {

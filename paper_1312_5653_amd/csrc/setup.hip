@@ -15,7 +15,10 @@
 //      used by the Dirichlet preconditioner (Sec. 5).
 //   4. zcc_and_coarse: Z_cc* = Z_cc - Z_cr Phi per subdomain and the assembled
 //      coarse matrix K_cc* = sum_s B_c^T Z_cc* B_c.
-//   5. invert_dense: K_cc*^-1 by Gauss-Jordan (FP64), one launch per pivot.
+//   5. the coarse inverse by Gauss-Jordan without pivoting (FP64): in LDS for
+//      small coarse matrices, one workgroup each for mid-size ones when several
+//      are set up together, and otherwise by panels of 32 pivots over the whole
+//      device.
 #include "common.h"
 
 namespace sfdp {
@@ -393,20 +396,6 @@ __global__ void k_coarse_assemble(Src src) {
   }
 }
 
-// One Gauss-Jordan pivot step B = step_k(A) of an n x n matrix (out of place).
-__global__ void k_gj_step(int n, int k, const cd* A, cd* B) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * n) return;
-  int i = idx / n, j = idx % n;
-  cd piv = cdiv(cd{1.0, 0.0}, A[(size_t)k * n + k]);
-  cd v;
-  if (i == k && j == k) v = piv;
-  else if (i == k) v = A[(size_t)k * n + j] * piv;
-  else if (j == k) v = -(A[(size_t)i * n + k] * piv);
-  else v = A[idx] - A[(size_t)i * n + k] * (A[(size_t)k * n + j] * piv);
-  B[idx] = v;
-}
-
 // Inverse of a small coarse matrix (nK <= GJ_LDS_MAX) in LDS, one workgroup per
 // instance: Kinv = GJ(Kcc); instances with larger coarse matrices return.
 constexpr int GJ_LDS_MAX = 96;
@@ -433,6 +422,7 @@ __global__ void __launch_bounds__(256) k_coarse_inv_lds(Src src) {
 // copied to LDS through coherent loads after every wave has waited for its
 // stores and passed the barrier.
 constexpr int GJ_BLOCK_MAX = 256;
+constexpr int GJ_BLOCK_BATCH = 4;  // fewest mid-size matrices for the one-workgroup path
 __device__ inline cd gl_ld(const cd* p) {
   double x = __hip_atomic_load((const double*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   double y = __hip_atomic_load((const double*)p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -520,19 +510,198 @@ __global__ void k_pack(Src src, int which) {
 }
 
 
-static hipError_t invert_dense(int n, cd* A, cd* work, hipStream_t st) {
-  // K_cc*^-1 by one Gauss-Jordan pivot launch per column (large coarse matrices);
-  // the result ends in A (a final copy when the ping-pong ends in work)
-  cd* src = A;
-  cd* dst = work;
-  int nb = (n * n + 255) / 256;
-  for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_gj_step, dim3(nb), dim3(256), 0, st, n, k, src, dst);
-    cd* t = src;
-    src = dst;
-    dst = t;
+// Blocked Gauss-Jordan inverse (no pivoting) of a large n x n matrix in place:
+// for each panel K of GJ_PB consecutive pivots (D = A_KK^-1),
+//   A_ij -= (A_iK D) A_Kj   for i, j outside K,
+//   A_iK  = -(A_iK D)       for i outside K,
+//   A_Kj  = D A_Kj,  A_KK = D,
+// which is the scalar Gauss-Jordan step applied a panel at a time.  Three
+// launches per panel: the pivot block's inverse, the update outside the
+// panel's rows and columns (which reads the old panel), then the panel's rows
+// and columns.
+constexpr int GJ_PB = 32;     // pivots per panel
+constexpr int GJ_RT = 16;     // rows per workgroup of the outer update
+constexpr int GJ_CT = 128;    // columns (or rows) per workgroup staged in LDS
+// D = inverse of the b x b block of A at (k0, k0) (b <= GJ_PB, D row stride b) by
+// Gauss-Jordan without pivoting, 256 threads: thread t keeps row t / 8, columns
+// t % 8 + 8 r (r < 4) in registers; the pivot row and column pass through two
+// alternating LDS buffers (L: 4 GJ_PB entries), so each pivot costs one barrier.
+__device__ void gj_pivot_block(const cd* A, int n, int k0, int b, cd* D, cd* L) {
+  const int i = threadIdx.x >> 3, jl = threadIdx.x & 7;
+  cd v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = jl + 8 * r;
+    v[r] = (i < b && j < b) ? A[(size_t)(k0 + i) * n + k0 + j] : cd{0.0, 0.0};
   }
-  if (src != A) hipMemcpyAsync(A, src, sizeof(cd) * n * n, hipMemcpyDeviceToDevice, st);
+#pragma unroll
+  for (int k = 0; k < GJ_PB; ++k) {
+    if (k >= b) continue;  // b is uniform over the workgroup; a break would keep
+                           // the loop rolled and v[k >> 3] dynamically indexed
+    cd* rk = L + (k & 1) * 2 * GJ_PB;
+    cd* ck = rk + GJ_PB;
+    if (i == k) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rk[jl + 8 * r] = v[r];
+    }
+    if (jl == (k & 7)) ck[i] = v[k >> 3];
+    __syncthreads();
+    const cd piv = cdiv(cd{1.0, 0.0}, rk[k]);
+    const cd cp = ck[i] * piv;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = jl + 8 * r;
+      const cd rj = rk[j];
+      if (i == k) v[r] = (j == k) ? piv : rj * piv;
+      else if (j == k) v[r] = -cp;
+      else v[r] = v[r] - cp * rj;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = jl + 8 * r;
+    if (i < b && j < b) D[i * b + j] = v[r];
+  }
+}
+__global__ void __launch_bounds__(256) k_gj_pivot(int n, int k0, int b, const cd* A, cd* D) {
+  __shared__ cd L[4 * GJ_PB];
+  gj_pivot_block(A, n, k0, b, D, L);
+}
+// D into LDS with row stride GJ_PB, zero outside b x b.
+__device__ inline void gj_load_d(cd* Dl, const cd* D, int b) {
+  for (int t = threadIdx.x; t < GJ_PB * GJ_PB; t += blockDim.x) {
+    const int r = t / GJ_PB, c = t % GJ_PB;
+    Dl[t] = (r < b && c < b) ? D[r * b + c] : cd{0.0, 0.0};
+  }
+}
+// Entries outside the panel's rows and columns: workgroup (x, y) takes rows
+// GJ_RT y .. (+GJ_RT) and columns GJ_CT x .. (+GJ_CT).  U = A_iK D for its
+// rows and the panel rows A_Kj of its columns go to LDS; thread (half, column)
+// then updates 8 rows of one column: A_ij -= U_i A_Kj.
+__global__ void __launch_bounds__(256) k_gj_rows(int n, int k0, int b, cd* A, const cd* D) {
+  __shared__ cd Dl[GJ_PB * GJ_PB], Ul[GJ_RT * GJ_PB], Ak[GJ_RT * GJ_PB], Ck[GJ_PB * GJ_CT];
+  const int i0 = blockIdx.y * GJ_RT, j0 = blockIdx.x * GJ_CT;
+  const int nr = min(GJ_RT, n - i0);
+  const int cc = threadIdx.x % GJ_CT, half = threadIdx.x / GJ_CT, j = j0 + cc;
+  const bool active = j < n && (j < k0 || j >= k0 + b);
+  cd v[8];  // this thread's entries, loaded before the staging so the latencies overlap
+#pragma unroll
+  for (int rr = 0; rr < 8; ++rr) {
+    const int r = half * 8 + rr;
+    v[rr] = (active && r < nr) ? A[(size_t)(i0 + r) * n + j] : cd{0.0, 0.0};
+  }
+  gj_load_d(Dl, D, b);
+  for (int t = threadIdx.x; t < GJ_RT * GJ_PB; t += blockDim.x) {
+    const int r = t / GJ_PB, c = t % GJ_PB, i = i0 + r;
+    const bool in = r < nr && c < b && (i < k0 || i >= k0 + b);
+    Ak[t] = in ? A[(size_t)i * n + k0 + c] : cd{0.0, 0.0};
+  }
+  for (int t = threadIdx.x; t < GJ_PB * GJ_CT; t += blockDim.x) {
+    const int q = t / GJ_CT, jq = j0 + t % GJ_CT;
+    Ck[t] = (q < b && jq < n) ? A[(size_t)(k0 + q) * n + jq] : cd{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < GJ_RT * GJ_PB; t += blockDim.x) {
+    const int r = t / GJ_PB, c = t % GJ_PB;
+    cd u{0.0, 0.0};
+    for (int q = 0; q < b; ++q) fma_acc(u, Ak[r * GJ_PB + q], Dl[q * GJ_PB + c]);
+    Ul[t] = u;  // zero for rows of the panel, beyond nr, and columns beyond b
+  }
+  __syncthreads();
+  if (!active) return;
+  for (int q = 0; q < b; ++q) {
+    const cd ck = Ck[q * GJ_CT + cc];
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) v[rr] = v[rr] - Ul[(half * 8 + rr) * GJ_PB + q] * ck;
+  }
+#pragma unroll
+  for (int rr = 0; rr < 8; ++rr) {
+    const int r = half * 8 + rr, i = i0 + r;
+    if (r < nr && (i < k0 || i >= k0 + b)) A[(size_t)i * n + j] = v[rr];
+  }
+}
+// The panel itself, after k_gj_rows (old panel values staged in LDS before any
+// write): blocks [0, gx) take GJ_CT columns j each (the panel rows: A_Kj = D A_Kj,
+// A_KK = D), blocks [gx, 2 gx) take GJ_CT rows i each outside the panel
+// (A_iK = -A_iK D).  The two sets of entries are disjoint.  Block 2 gx inverts
+// the next panel's pivot block into Dn: k_gj_rows has already given it its final
+// value, and nothing here writes it.
+__global__ void __launch_bounds__(256) k_gj_panel(int n, int k0, int b, int gx, cd* A, const cd* D, cd* Dn) {
+  __shared__ cd Dl[GJ_PB * GJ_PB], S[GJ_CT * (GJ_PB + 1)];
+  if ((int)blockIdx.x == 2 * gx) {
+    const int k1 = k0 + b;
+    if (k1 < n) gj_pivot_block(A, n, k1, min(GJ_PB, n - k1), Dn, S);
+    return;
+  }
+  gj_load_d(Dl, D, b);
+  const int half = threadIdx.x / GJ_CT, lo = threadIdx.x % GJ_CT;
+  if ((int)blockIdx.x < gx) {
+    const int j0 = blockIdx.x * GJ_CT;
+    for (int t = threadIdx.x; t < GJ_PB * GJ_CT; t += blockDim.x) {
+      const int q = t / GJ_CT, cc = t % GJ_CT, j = j0 + cc;
+      S[q * GJ_CT + cc] = (q < b && j < n) ? A[(size_t)(k0 + q) * n + j] : cd{0.0, 0.0};
+    }
+    __syncthreads();
+    const int j = j0 + lo;
+    if (j >= n) return;
+    if (j >= k0 && j < k0 + b) {
+      for (int tt = 0; tt < 16; ++tt) {
+        const int t = half * 16 + tt;
+        if (t < b) A[(size_t)(k0 + t) * n + j] = Dl[t * GJ_PB + (j - k0)];
+      }
+      return;
+    }
+    cd v[16];
+#pragma unroll
+    for (int tt = 0; tt < 16; ++tt) v[tt] = cd{0.0, 0.0};
+    for (int q = 0; q < b; ++q) {
+      const cd old = S[q * GJ_CT + lo];
+#pragma unroll
+      for (int tt = 0; tt < 16; ++tt) fma_acc(v[tt], Dl[(half * 16 + tt) * GJ_PB + q], old);
+    }
+#pragma unroll
+    for (int tt = 0; tt < 16; ++tt) {
+      const int t = half * 16 + tt;
+      if (t < b) A[(size_t)(k0 + t) * n + j] = v[tt];
+    }
+  } else {
+    const int i00 = (blockIdx.x - gx) * GJ_CT;
+    for (int t = threadIdx.x; t < GJ_CT * GJ_PB; t += blockDim.x) {
+      const int rr = t / GJ_PB, q = t % GJ_PB, i = i00 + rr;
+      S[rr * (GJ_PB + 1) + q] = (q < b && i < n) ? A[(size_t)i * n + k0 + q] : cd{0.0, 0.0};
+    }
+    __syncthreads();
+    const int i = i00 + lo;
+    if (i >= n || (i >= k0 && i < k0 + b)) return;
+    cd u[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) u[cc] = cd{0.0, 0.0};
+    for (int q = 0; q < b; ++q) {
+      const cd a = S[lo * (GJ_PB + 1) + q];
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) fma_acc(u[cc], a, Dl[q * GJ_PB + half * 16 + cc]);
+    }
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = half * 16 + cc;
+      if (c < b) A[(size_t)i * n + k0 + c] = -u[cc];
+    }
+  }
+}
+
+static hipError_t invert_dense(int n, cd* A, cd* work, hipStream_t st) {
+  // A^-1 in place by the blocked Gauss-Jordan steps above (n > 64: work holds
+  // at least 2 GJ_PB^2 entries)
+  // work holds two pivot inverses: the current panel's and the next one's
+  const int gx = (n + GJ_CT - 1) / GJ_CT, gy = (n + GJ_RT - 1) / GJ_RT;
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, st, n, 0, std::min(GJ_PB, n), (const cd*)A, work);
+  for (int k0 = 0, p = 0; k0 < n; k0 += GJ_PB, ++p) {
+    const int b = std::min(GJ_PB, n - k0);
+    cd* D = work + (p & 1) * GJ_PB * GJ_PB;
+    cd* Dn = work + ((p + 1) & 1) * GJ_PB * GJ_PB;
+    hipLaunchKernelGGL(k_gj_rows, dim3(gx, gy), dim3(256), 0, st, n, k0, b, A, (const cd*)D);
+    hipLaunchKernelGGL(k_gj_panel, dim3(2 * gx + 1), dim3(256), 0, st, n, k0, b, gx, A, (const cd*)D, Dn);
+  }
   return hipGetLastError();
 }
 
@@ -543,12 +712,16 @@ hipError_t launch_setup(const Target& t) {
   std::vector<Problem*> ps;
   if (t.single()) ps.push_back(t.one);
   else ps = t.probs;
-  int ND = 0, ml = 0, ncmax = 0;
+  int ND = 0, ml = 0, ncmax = 0, nmid = 0;
   for (Problem* p : ps) {
     ND = std::max(ND, p->ND);
     ml = std::max(ml, p->ml);
     ncmax = std::max(ncmax, p->nK);
+    nmid += p->nK > GJ_LDS_MAX && p->nK <= GJ_BLOCK_MAX;
   }
+  // one workgroup per mid-size coarse matrix pays off only when several run
+  // side by side; a few go panel by panel over the whole device instead
+  const bool mid_block = nmid >= GJ_BLOCK_BATCH;
   const int yS = (ND * ND + 255) / 256, yP = (ND * NQ + 255) / 256, yG = (ml * ml * ml + 255) / 256;
   const int yK = (ND * (ND + 1) / 2 + 255) / 256;
   launch2(t, K_SUB, k_zero_sub<One>, k_zero_sub<Many>, yS, 256, 0, 0);
@@ -562,9 +735,10 @@ hipError_t launch_setup(const Target& t) {
   launch2(t, K_NC128, k_coarse_assemble<One>, k_coarse_assemble<Many>, 1, 128, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // coarse inverses: small ones in LDS and mid-size ones by one workgroup each,
-  // every instance in one launch per kind (each kernel skips the other sizes);
-  // large ones by one launch per pivot
+  // coarse inverses: small ones in LDS, every instance in one launch; mid-size
+  // ones by one workgroup each in one launch when there are several (the kernel
+  // skips the other sizes); the rest by panels of GJ_PB pivots, one matrix after
+  // another
   {
     const int nl = std::min(ncmax, GJ_LDS_MAX);
     size_t lds = sizeof(cd) * ((size_t)nl * nl + 2 * nl);
@@ -573,10 +747,10 @@ hipError_t launch_setup(const Target& t) {
     if (e != hipSuccess) return e;
     launch2(t, K_ONE, k_coarse_inv_lds<One>, k_coarse_inv_lds<Many>, 1, 256, lds);
   }
-  if (ncmax > GJ_LDS_MAX) launch2(t, K_ONE, k_coarse_inv_block<One>, k_coarse_inv_block<Many>, 1, 1024, 0);
+  if (mid_block) launch2(t, K_ONE, k_coarse_inv_block<One>, k_coarse_inv_block<Many>, 1, 1024, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (Problem* p : ps) {
-    if (p->nK <= GJ_BLOCK_MAX) continue;
+    if (p->nK <= GJ_LDS_MAX || (mid_block && p->nK <= GJ_BLOCK_MAX)) continue;
     e = hipMemcpyAsync(p->Kinv, p->Kcc, sizeof(cd) * p->nK * p->nK, hipMemcpyDeviceToDevice, t.st);
     if (e == hipSuccess) e = invert_dense(p->nK, p->Kinv, p->Kwork, t.st);
     if (e != hipSuccess) return e;

@@ -24,7 +24,7 @@ EXPORTS = [
     "sfdp_inspect", "sfdp_interface_apply", "sfdp_timing_enable", "sfdp_kernel_times",
     "sfdp_batch_create", "sfdp_batch_destroy", "sfdp_batch_sizes", "sfdp_batch_set_beta",
     "sfdp_batch_solve_range_space", "sfdp_server_create", "sfdp_server_submit", "sfdp_server_poll",
-    "sfdp_server_stats", "sfdp_server_destroy", "sfdp_set_coarse_space",
+    "sfdp_server_stats", "sfdp_server_destroy", "sfdp_set_coarse_space", "sfdp_batch_inspect",
 ]
 
 
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_batch_destroy.argtypes = [P]
     lib.sfdp_batch_destroy.restype = None
     lib.sfdp_batch_sizes.argtypes = [P, I, ctypes.POINTER(Sizes)]
+    lib.sfdp_batch_inspect.argtypes = [P, I, I, I, VP, ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.sfdp_batch_set_beta.argtypes = [P, ctypes.POINTER(D)]
     VPP = ctypes.POINTER(ctypes.c_void_p)
     lib.sfdp_batch_solve_range_space.argtypes = [P, ctypes.POINTER(I), VPP, VPP, VPP, VPP, VPP,
@@ -320,6 +321,15 @@ class Batch:
     def set_beta(self, betas):
         arr = (ctypes.c_double * len(self.n_elem))(*[float(b) for b in betas])
         _check(_lib.sfdp_batch_set_beta(self._h, arr))
+
+    def inspect(self, i: int, what: int, sub: int = 0):
+        """Set-up operator of instance i (as Problem.inspect)."""
+        import torch
+        r, c = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.sfdp_batch_inspect(self._h, i, what, sub, None, ctypes.byref(r), ctypes.byref(c)))
+        out = torch.zeros((r.value, c.value), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
+        _check(_lib.sfdp_batch_inspect(self._h, i, what, sub, _ptr(out), ctypes.byref(r), ctypes.byref(c)))
+        return out
 
     def solve_range_space(self, ybars, ycs=None, **opts):
         """ybars[i]: (nrhs_i, n_free_i) or (n_free_i,) CUDA tensor, or None for

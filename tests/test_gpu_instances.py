@@ -116,3 +116,31 @@ def test_batch_of_many_instances_in_several_launch_groups(sf):
     # every instance meets the gate by the GPU's own FP64 residual
     assert all(inf[0]["rel_kkt"] <= 1e-8 for inf in infos)
     b.close()
+
+
+@pytest.mark.parametrize("Ns", [[64, 64, 16, 64, 64], [64, 48, 64]])
+def test_batch_coarse_inverses(sf, Ns):
+    """Coarse inverses of the instances of a batch: with four mid-size coarse
+    matrices (161 unknowns, 8 x 8 subdomains with edge averages) each takes one
+    workgroup of a shared launch; with two they go panel by panel.  Either way
+    each is the inverse of its assembled coarse matrix, which is the one the
+    instance assembles on its own."""
+    sfdp, ctx = sf
+    m = 8
+    betas = [10.0 ** (-2 - i) for i in range(len(Ns))]
+    b = sfdp.Batch(ctx, Ns, m)
+    b.set_beta(betas)
+    for i, (N, beta) in enumerate(zip(Ns, betas)):
+        k = b.inspect(i, sfdp.Q_COARSE).cpu().numpy()
+        kinv = b.inspect(i, sfdp.Q_COARSE_INV).cpu().numpy()
+        P = N // m
+        assert k.shape[0] == (P - 1) ** 2 + 2 * P * (P - 1)
+        ref = np.linalg.inv(k)
+        assert np.abs(kinv - ref).max() / np.abs(ref).max() < 1e-11, (i, N)
+        assert np.abs(kinv @ k - np.eye(k.shape[0])).max() < 1e-10, (i, N)
+        p = sfdp.Problem(ctx, 2, N, m)
+        p.set_beta(beta)
+        k1 = p.inspect(sfdp.Q_COARSE).cpu().numpy()
+        assert np.abs(k1 - k).max() <= 1e-13 * np.abs(k).max(), (i, N)
+        p.close()
+    b.close()

@@ -113,9 +113,9 @@ def test_local_operators_and_coarse_match_definitions(sf, N, m, beta, edges):
 
 @pytest.mark.parametrize("N,m", [(32, 8), (64, 8), (96, 8)])
 def test_coarse_inverse_paths(sf, N, m):
-    """The coarse inverse by each of its three paths -- in LDS (33 unknowns), one
-    workgroup in global memory (161) and one launch per pivot (385) -- equals the
-    inverse of the assembled coarse matrix."""
+    """The coarse inverse of a lone problem -- in LDS (33 unknowns), and by panels
+    of 32 pivots over the device (161: six panels, the last ragged; 385) -- equals
+    the inverse of the assembled coarse matrix."""
     sfdp, ctx = sf
     prob = sfdp.Problem(ctx, 2, N, m)
     prob.set_beta(1e-4)
