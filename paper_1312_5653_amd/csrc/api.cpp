@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "common.h"
+#include "three.h"
 
 namespace sfdp {
 }  // namespace sfdp
@@ -200,7 +201,9 @@ void free_factors(Problem& p) {
   p.factored = false;
 }
 
+sfdp_status alloc_workspace3(Problem& p, int kmax);
 sfdp_status alloc_workspace(Problem& p, int kmax) {
+  if (p.dim == 3) return alloc_workspace3(p, kmax);
   if (p.kmax_alloc >= kmax && p.gmres_parts >= p.gmres_blocks) return SFDP_OK;
   // per right-hand side: Krylov basis, Hessenberg matrix, block partial sums
   if (p.kmax_alloc) {
@@ -265,12 +268,13 @@ hipError_t ev_harvest(Problem& p) {
 }
 
 void defaults(sfdp_precision prec, const sfdp_opts* o, double& tol_kkt, double& tol_inner, int& max_outer,
-              int& kmax) {
+              int& kmax, int dim = 2) {
   bool mixed = prec != SFDP_FP64;
   tol_kkt = (o && o->tol_kkt > 0) ? o->tol_kkt : (mixed ? 1e-8 : 1e-10);
   tol_inner = (o && o->tol_inner > 0) ? o->tol_inner : (mixed ? 3e-7 : 1e-8);
   max_outer = (o && o->max_outer > 0) ? o->max_outer : 8;
-  kmax = (o && o->max_krylov > 0) ? std::min(o->max_krylov, KMAX_LIMIT) : 64;
+  // corner-only FETI-DP in 3D needs more iterations than the 2D default allows
+  kmax = (o && o->max_krylov > 0) ? std::min(o->max_krylov, KMAX_LIMIT) : (dim == 3 ? 300 : 64);
 }
 int batch_of(const sfdp_opts* o) { return (o && o->batch > 0) ? std::min(o->batch, NRMAX) : NRMAX; }
 bool single_of(const sfdp_opts* o) { return o && o->factors == 1; }
@@ -376,6 +380,237 @@ sfdp_status alloc_setup(Ctx* ctx, const std::vector<Problem*>& ps) {
 }
 void free_setup(Problem& p) {
   p.G64 = p.Sinv64 = p.S64 = p.Phi64 = p.PhiFull = p.scr = p.Zs = p.Kwork = nullptr;
+}
+
+// ---------------------------------------------------------------------------------------
+// 3D instances: partition and interface maps, factors and workspaces (kernels in
+// three.hip).  Multipliers are fully redundant and ordered by the full id of
+// their node, then by the pair of subdomains (s_a < s_b), signed +1 on s_a.
+sfdp_status build_maps3(Problem& p) {
+  Three& T = *p.t3;
+  Geo3& g = T.g;
+  const int N = p.N, m = p.m, P = p.P, ml = p.ml, nsub = p.nsub, nl = ml * ml * ml;
+  g.N = N; g.m = m; g.P = P; g.ml = ml; g.nsub = nsub; g.nl = nl;
+  g.nI = (m - 1) * (m - 1) * (m - 1);
+  g.NR = nl - 8;
+  g.ND = g.NR - g.nI;
+  g.nC = (P - 1) * (P - 1) * (P - 1);
+  g.h = 1.0 / N;
+  g.alpha = 0.0;
+  const int NR = g.NR, ND = g.ND, nI = g.nI;
+  std::vector<int> rl((size_t)nsub * NR, -1), rpos((size_t)nsub * nl, -1), nds(nsub, 0), cg(nsub * 8, -1);
+  struct Inc {
+    int64_t full;
+    int s, d;
+  };
+  std::vector<Inc> inc;
+  const int64_t n1 = N + 1;
+  for (int s = 0; s < nsub; ++s) {
+    int gi0, gj0, gk0;
+    g.base(s, gi0, gj0, gk0);
+    int nr = 0, nd = 0;
+    for (int l = 0; l < nl; ++l) {
+      int a, b, c;
+      g.loc(l, a, b, c);
+      if (a > 0 && a < m && b > 0 && b < m && c > 0 && c < m) {
+        rl[(size_t)s * NR + nr] = l;
+        rpos[(size_t)s * nl + l] = nr++;
+      }
+    }
+    for (int l = 0; l < nl; ++l) {
+      int a, b, c;
+      g.loc(l, a, b, c);
+      const bool inter = a > 0 && a < m && b > 0 && b < m && c > 0 && c < m;
+      const bool vert = (a == 0 || a == m) && (b == 0 || b == m) && (c == 0 || c == m);
+      if (inter || vert || g.dirich(s, a, b, c)) continue;
+      if (nd >= ND) return fail(SFDP_E_INVALID, "interface slot overflow");
+      rl[(size_t)s * NR + nI + nd] = l;
+      rpos[(size_t)s * nl + l] = nI + nd;
+      inc.push_back({(gi0 + a) + n1 * ((gj0 + b) + n1 * (int64_t)(gk0 + c)), s, nd});
+      ++nd;
+    }
+    nds[s] = nd;
+    p.ndmax = std::max(p.ndmax, nd);
+    for (int q = 0; q < 8; ++q) {
+      int a, b, c;
+      g.loc(g.vertex(q), a, b, c);
+      if (g.dirich(s, a, b, c)) continue;
+      cg[s * 8 + q] = ((gi0 + a) / m - 1) + (P - 1) * (((gj0 + b) / m - 1) + (P - 1) * ((gk0 + c) / m - 1));
+    }
+  }
+  std::vector<int> cown((size_t)std::max(g.nC, 1) * 8, -1), cnt(std::max(g.nC, 1), 0);
+  for (int s = 0; s < nsub; ++s)
+    for (int q = 0; q < 8; ++q) {
+      const int c = cg[s * 8 + q];
+      if (c >= 0) cown[(size_t)c * 8 + cnt[c]++] = s * 8 + q;
+    }
+  std::stable_sort(inc.begin(), inc.end(), [](const Inc& x, const Inc& y) {
+    return x.full != y.full ? x.full < y.full : x.s < y.s;
+  });
+  std::vector<int> dmu((size_t)nsub * ND * 3, -1), muown;
+  std::vector<float> dsg((size_t)nsub * ND * 3, 0.f);
+  auto add = [&](int s, int d, int k, float sign) {
+    const size_t base = ((size_t)s * ND + d) * 3;
+    for (int j = 0; j < 3; ++j)
+      if (dmu[base + j] < 0) {
+        dmu[base + j] = k;
+        dsg[base + j] = sign;
+        return true;
+      }
+    return false;
+  };
+  for (size_t i0 = 0; i0 < inc.size();) {
+    size_t i1 = i0;
+    while (i1 < inc.size() && inc[i1].full == inc[i0].full) ++i1;
+    for (size_t a = i0; a < i1; ++a)
+      for (size_t b = a + 1; b < i1; ++b) {
+        const int k = (int)(muown.size() / 2);
+        muown.push_back(inc[a].s * ND + inc[a].d);
+        muown.push_back(inc[b].s * ND + inc[b].d);
+        if (!add(inc[a].s, inc[a].d, k, 1.f) || !add(inc[b].s, inc[b].d, k, -1.f))
+          return fail(SFDP_E_INVALID, "more than three multipliers on a node");
+      }
+    i0 = i1;
+  }
+  g.nmu = (int)(muown.size() / 2);
+  p.nmu = g.nmu;
+  p.nC = g.nC;
+  p.nK = g.nC;
+  p.nE = 0;
+  p.ND = ND;
+  std::vector<int> f2b((size_t)n1 * n1 * n1, -1);
+  int nbd = 0;
+  for (int k = 0; k <= N; ++k)
+    for (int j = 0; j <= N; ++j)
+      for (int i = 0; i <= N; ++i)
+        if (i == 0 || j == 0 || k == 0 || i == N || j == N || k == N) f2b[i + n1 * (j + n1 * (size_t)k)] = nbd++;
+  p.n_bdry = nbd;
+  sfdp_status s;
+  if ((s = dupload(p, &T.rl, rl)) || (s = dupload(p, &T.rpos, rpos)) || (s = dupload(p, &T.nds, nds)) ||
+      (s = dupload(p, &T.dmu, dmu)) || (s = dupload(p, &T.dsg, dsg)) || (s = dupload(p, &T.muown, muown)) ||
+      (s = dupload(p, &T.cg, cg)) || (s = dupload(p, &T.cown, cown)) || (s = dupload(p, &p.full2bdry, f2b)))
+    return s;
+  return SFDP_OK;
+}
+
+// Factor arrays of a 3D problem (storage precision of the interface operators
+// for Z_rr^-1, its Delta block, S_bb and Phi).
+void free_factors3(Problem& p) {
+  Three& T = *p.t3;
+  const Geo3& g = T.g;
+  const size_t es = elem_size(p), ns = g.nsub;
+  dfree(p, T.Zinv, es * ns * g.NR * g.NR);
+  dfree(p, T.Sinv, es * ns * g.ND * g.ND);
+  dfree(p, T.Sbb, es * ns * g.ND * g.ND);
+  dfree(p, T.Phi, es * ns * g.ND * 8);
+  dfree(p, (void*&)T.PhiFull, sizeof(cd) * ns * g.NR * 8);
+  dfree(p, (void*&)T.Zcc, sizeof(cd) * ns * 64);
+  const size_t nc2 = (size_t)std::max(g.nC * g.nC, 1);
+  dfree(p, (void*&)p.Kinv, sizeof(cd) * nc2);
+  dfree(p, (void*&)p.Kcc, sizeof(cd) * nc2);
+  p.factored = false;
+}
+sfdp_status alloc_factors3(Problem& p) {
+  Three& T = *p.t3;
+  if (T.Zinv) return SFDP_OK;
+  const Geo3& g = T.g;
+  const size_t es = elem_size(p), ns = g.nsub;
+  const size_t nc2 = (size_t)std::max(g.nC * g.nC, 1);
+  sfdp_status s;
+  if ((s = dalloc(p, &T.Zinv, es * ns * g.NR * g.NR)) || (s = dalloc(p, &T.Sinv, es * ns * g.ND * g.ND)) ||
+      (s = dalloc(p, &T.Sbb, es * ns * g.ND * g.ND)) || (s = dalloc(p, &T.Phi, es * ns * g.ND * 8)) ||
+      (s = dalloc(p, (void**)&T.PhiFull, sizeof(cd) * ns * g.NR * 8)) ||
+      (s = dalloc(p, (void**)&T.Zcc, sizeof(cd) * ns * 64)) || (s = dalloc(p, (void**)&p.Kinv, sizeof(cd) * nc2)) ||
+      (s = dalloc(p, (void**)&p.Kcc, sizeof(cd) * nc2))) {
+    free_factors3(p);
+    return s;
+  }
+  return SFDP_OK;
+}
+
+// Set-up of a 3D problem for its beta: the extended local matrices (FP64) and
+// the pivot-inverse buffers exist only during the call.
+sfdp_status setup3(Problem& p) {
+  sfdp_status s = alloc_factors3(p);
+  if (s) return s;
+  p.factored = false;
+  const Geo3& g = p.t3->g;
+  const size_t eb = sizeof(cd) * (size_t)g.nsub * g.NR * g.NR, wb = sizeof(cd) * (size_t)g.nsub * 2 * 32 * 32;
+  void *E = nullptr, *W = nullptr;
+  if ((s = dalloc(p, &E, eb)) || (s = dalloc(p, &W, wb))) {
+    dfree(p, E, eb);
+    return s;
+  }
+  hipError_t e = launch_setup3(p, (cd*)E, (cd*)W);
+  if (e == hipSuccess) e = hipStreamSynchronize(p.ctx->stream);
+  dfree(p, E, eb);
+  dfree(p, W, wb);
+  if (e != hipSuccess) return fail(SFDP_E_DEVICE, std::string("setup: ") + hipGetErrorString(e));
+  p.factored = true;
+  return SFDP_OK;
+}
+
+void free_workspace3(Problem& p) {
+  Three& T = *p.t3;
+  if (!T.kalloc) return;
+  const Geo3& g = T.g;
+  const size_t nm = g.nmu, nb = (nm + 255) / 256, kk = T.kalloc + 1;
+  dfree(p, (void*&)T.T, sizeof(cd) * g.nsub * g.NR);
+  dfree(p, (void*&)T.Y, sizeof(cd) * g.nsub * g.ND);
+  dfree(p, (void*&)T.Wc, sizeof(cd) * g.nsub * 8);
+  for (cd** v : {&T.fcs, &T.uc, &T.gc}) dfree(p, (void*&)*v, sizeof(cd) * std::max(g.nC, 1));
+  for (cd** v : {&T.d, &T.mu, &T.z, &T.w}) dfree(p, (void*&)*v, sizeof(cd) * nm);
+  dfree(p, (void*&)T.V, sizeof(cd) * kk * nm);
+  dfree(p, (void*&)T.part, sizeof(cd) * kk * nb);
+  dfree(p, (void*&)T.hd, sizeof(cd) * (2 * kk + 1));
+  dfree(p, (void*&)T.npart, sizeof(double) * nb);
+  if (T.hh) hipHostFree(T.hh);
+  T.hh = nullptr;
+  T.kalloc = 0;
+}
+sfdp_status alloc_workspace3(Problem& p, int kmax) {
+  Three& T = *p.t3;
+  if (T.kalloc >= kmax) return SFDP_OK;
+  free_workspace3(p);
+  const Geo3& g = T.g;
+  const size_t nm = g.nmu, nb = (nm + 255) / 256, kk = kmax + 1;
+  sfdp_status s;
+  if ((s = dalloc(p, (void**)&T.T, sizeof(cd) * g.nsub * g.NR)) ||
+      (s = dalloc(p, (void**)&T.Y, sizeof(cd) * g.nsub * g.ND)) ||
+      (s = dalloc(p, (void**)&T.Wc, sizeof(cd) * g.nsub * 8)))
+    return s;
+  for (cd** v : {&T.fcs, &T.uc, &T.gc})
+    if ((s = dalloc(p, (void**)v, sizeof(cd) * std::max(g.nC, 1)))) return s;
+  for (cd** v : {&T.d, &T.mu, &T.z, &T.w})
+    if ((s = dalloc(p, (void**)v, sizeof(cd) * nm))) return s;
+  if ((s = dalloc(p, (void**)&T.V, sizeof(cd) * kk * nm)) || (s = dalloc(p, (void**)&T.part, sizeof(cd) * kk * nb)) ||
+      (s = dalloc(p, (void**)&T.hd, sizeof(cd) * (2 * kk + 1))) ||
+      (s = dalloc(p, (void**)&T.npart, sizeof(double) * nb)))
+    return s;
+  if (hipHostMalloc((void**)&T.hh, sizeof(cd) * (2 * kk + 1)) != hipSuccess) {
+    T.hh = nullptr;
+    return fail(SFDP_E_NOMEM, "pinned host allocation");
+  }
+  T.kalloc = kmax;
+  return SFDP_OK;
+}
+
+// FETI-DP solves of the view's nr right-hand sides (vectors f, x of Dev, c-th
+// at offset c n_free), one after another; each logs its iteration count in
+// the flag words of its group slot.
+sfdp_status feti_run3(Problem& p, int fsel, int conj, int xsel, double tol, int kmax) {
+  sfdp_status s = alloc_workspace3(p, kmax);
+  if (s) return s;
+  const Dev d = p.dev();
+  for (int c = 0; c < p.nr; ++c) {
+    const cd* f = dev_vec(d, fsel) + (size_t)c * p.n_free;
+    cd* x = dev_vec(d, xsel) + (size_t)c * p.n_free;
+    int its = 0;
+    hipError_t e = feti3(p, f, x, conj, tol, kmax, &its);
+    if (e == hipSuccess) e = launch_log3(p, c, (int)((p.map >> (8 * c)) & 255u), its);
+    if (e != hipSuccess) return fail(SFDP_E_DEVICE, std::string("3D FETI-DP: ") + hipGetErrorString(e));
+  }
+  return SFDP_OK;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -554,6 +789,7 @@ sfdp_status gmres_error(hipError_t e) {
 // instance's group (its view's nr right-hand sides); f and x name instance
 // vectors.  `timed` receives event pairs (single problems only).
 sfdp_status feti_run(const Target& t, Problem* timed, int fsel, int conj, int xsel, double tol, int kmax) {
+  if (t.single() && t.one->dim == 3) return feti_run3(*t.one, fsel, conj, xsel, tol, kmax);
   if (t.single()) {
     sfdp_status s = check_launch(*t.one, kmax);
     if (s) return s;
@@ -674,9 +910,54 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
   return status;
 }
 
+// A 3D problem: P^3 subdomains of sub_elem^3 cells (sub_elem <= 9: a
+// subdomain's r nodes fit one workgroup of the sweep, at most 992).
+sfdp_status create_problem3(Ctx* ctx, int n_elem, int sub_elem, sfdp_precision prec, Problem** out) {
+  if (sub_elem < 2 || sub_elem > 9) return fail(SFDP_E_INVALID, "sub_elem must be in [2, 9] for dim 3");
+  if (n_elem % sub_elem != 0 || n_elem / sub_elem < 2)
+    return fail(SFDP_E_INVALID, "n_elem must be a multiple of sub_elem with at least 2 subdomains per side");
+  const int P = n_elem / sub_elem;
+  if ((int64_t)P * P * P > 65535) return fail(SFDP_E_INVALID, "at most 65535 subdomains in 3D");
+  if (prec != SFDP_FP64 && prec != SFDP_MIXED && prec != SFDP_MIXED_IFACE)
+    return fail(SFDP_E_INVALID, "bad precision");
+  HIPCHK(hipSetDevice(ctx->device));
+  Problem* p = new (std::nothrow) Problem();
+  if (!p) return fail(SFDP_E_NOMEM, "host allocation");
+  p->t3 = new (std::nothrow) Three();
+  if (!p->t3) {
+    delete p;
+    return fail(SFDP_E_NOMEM, "host allocation");
+  }
+  p->ctx = ctx;
+  p->dim = 3;
+  p->N = n_elem;
+  p->m = sub_elem;
+  p->P = P;
+  p->nsub = P * P * P;
+  p->ml = sub_elem + 1;
+  p->L = p->ml * p->ml * p->ml;
+  p->n_free = (int64_t)(n_elem - 1) * (n_elem - 1) * (n_elem - 1);
+  p->prec = prec;
+  sfdp_status s = build_maps3(*p);
+  if (!s) s = dalloc(*p, (void**)&p->flags, sizeof(int) * FLAG_WORDS);
+  if (s) {
+    destroy_problem(p);
+    return s;
+  }
+  hipError_t ez = launch_fill(p->flags, sizeof(int) * FLAG_WORDS, ctx->stream);
+  if (ez == hipSuccess) ez = hipStreamSynchronize(ctx->stream);
+  if (ez != hipSuccess) {
+    destroy_problem(p);
+    return fail(SFDP_E_DEVICE, std::string("init: ") + hipGetErrorString(ez));
+  }
+  *out = p;
+  return SFDP_OK;
+}
+
 sfdp_status create_problem(Ctx* ctx, int dim, int n_elem, int sub_elem, sfdp_precision prec, Problem** out) {
   *out = nullptr;
-  if (dim != 2) return fail(SFDP_E_INVALID, "only dim = 2 is implemented");
+  if (dim == 3) return create_problem3(ctx, n_elem, sub_elem, prec, out);
+  if (dim != 2) return fail(SFDP_E_INVALID, "dim must be 2 or 3");
   if (sub_elem < 2 || sub_elem > 32) return fail(SFDP_E_INVALID, "sub_elem must be in [2, 32] for dim 2");
   if (n_elem % sub_elem != 0 || n_elem / sub_elem < 2)
     return fail(SFDP_E_INVALID, "n_elem must be a multiple of sub_elem with at least 2 subdomains per side");
@@ -731,6 +1012,15 @@ void destroy_problem(Problem* p) {
   if (!p) return;
   hipSetDevice(p->ctx->device);
   hipStreamSynchronize(p->ctx->stream);
+  if (Three* T = p->t3) {
+    free_factors3(*p);
+    free_workspace3(*p);
+    void* maps3[] = {T->rl, T->rpos, T->nds, T->dmu, T->dsg, T->muown, T->cg, T->cown};
+    for (void* a : maps3)
+      if (a) hipFree(a);
+    delete T;
+    p->t3 = nullptr;
+  }
   free_factors(*p);
   free_setup(*p);
   void* arr[] = {p->dloc, p->dmid, p->dpart, p->nd, p->dsgn, p->cloc, p->cgid, p->muown, p->mufree,
@@ -749,6 +1039,7 @@ void destroy_problem(Problem* p) {
 // Factor one or several problems for their betas (one set-up sequence; the
 // stream must be idle).
 sfdp_status setup_run(const Target& t, const std::vector<Problem*>& ps, Multi* M) {
+  if (ps.size() == 1 && ps[0]->dim == 3) return setup3(*ps[0]);
   for (Problem* p : ps) {
     sfdp_status s = alloc_factors(*p);
     if (s) return s;
@@ -803,10 +1094,66 @@ sfdp_status gather_one(Problem* p) {
 }  // namespace
 
 struct sfdp_ctx : public Ctx {};
+// 3D: Sinv and S_bb are stored full (ND x ND), Phi with the 8 vertex slots.
+static sfdp_status inspect3(Problem* p, sfdp_query what, int sub, double* out, int* rows, int* cols) {
+  const Three& T = *p->t3;
+  const Geo3& g = T.g;
+  int r = 0, c = 0;
+  std::vector<int> qcols;
+  if (what == SFDP_Q_COARSE || what == SFDP_Q_COARSE_INV) {
+    r = c = g.nC;
+  } else {
+    if (sub < 0 || sub >= g.nsub) return fail(SFDP_E_INVALID, "sub out of range");
+    HIPCHK(hipMemcpy(&r, T.nds + sub, sizeof(int), hipMemcpyDeviceToHost));
+    if (what == SFDP_Q_PHI) {
+      int cg[8];
+      HIPCHK(hipMemcpy(cg, T.cg + 8 * sub, sizeof(cg), hipMemcpyDeviceToHost));
+      for (int q = 0; q < 8; ++q)
+        if (cg[q] >= 0) qcols.push_back(q);
+      c = (int)qcols.size();
+    } else if (what == SFDP_Q_SINV || what == SFDP_Q_SBB) {
+      c = r;
+    } else {
+      return fail(SFDP_E_INVALID, "unknown query");
+    }
+  }
+  if (rows) *rows = r;
+  if (cols) *cols = c;
+  if (!out) return SFDP_OK;
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  std::vector<cd> host((size_t)r * c);
+  const size_t es = elem_size(*p);
+  auto get = [&](const std::vector<char>& raw, size_t idx) {
+    if (es == sizeof(cf)) {
+      const cf v = ((const cf*)raw.data())[idx];
+      return cd{v.x, v.y};
+    }
+    return ((const cd*)raw.data())[idx];
+  };
+  if (what == SFDP_Q_COARSE || what == SFDP_Q_COARSE_INV) {
+    HIPCHK(hipMemcpy(host.data(), what == SFDP_Q_COARSE ? p->Kcc : p->Kinv, sizeof(cd) * host.size(),
+                     hipMemcpyDeviceToHost));
+  } else if (what == SFDP_Q_PHI) {
+    std::vector<char> raw((size_t)g.ND * 8 * es);
+    HIPCHK(hipMemcpy(raw.data(), (const char*)T.Phi + (size_t)sub * raw.size(), raw.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < c; ++j) host[(size_t)i * c + j] = get(raw, (size_t)i * 8 + qcols[j]);
+  } else {
+    std::vector<char> raw((size_t)g.ND * g.ND * es);
+    const char* base = (const char*)(what == SFDP_Q_SINV ? T.Sinv : T.Sbb);
+    HIPCHK(hipMemcpy(raw.data(), base + (size_t)sub * raw.size(), raw.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < c; ++j) host[(size_t)i * c + j] = get(raw, (size_t)i * g.ND + j);
+  }
+  HIPCHK(hipMemcpy(out, host.data(), sizeof(cd) * host.size(), hipMemcpyHostToDevice));
+  return SFDP_OK;
+}
+
 static sfdp_status inspect_problem(Problem* p, sfdp_query what, int sub, double* out, int* rows, int* cols) {
   sfdp_status s = check_ready(p);
   if (s) return s;
   HIPCHK(hipSetDevice(p->ctx->device));
+  if (p->dim == 3) return inspect3(p, what, sub, out, rows, cols);
   std::vector<int> ndv(p->nsub), cg(NQ * p->nsub);
   HIPCHK(hipMemcpy(ndv.data(), p->nd, sizeof(int) * p->nsub, hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(cg.data(), p->cgid, sizeof(int) * NQ * p->nsub, hipMemcpyDeviceToHost));
@@ -940,13 +1287,14 @@ static void sizes_of(const Problem* p, sfdp_sizes* out) {
   out->n_mult = p->nmu;
   out->n_corner = p->nC;
   out->n_coarse = p->nK;
-  out->max_delta = 4 * (p->m - 1);
+  out->max_delta = p->dim == 3 ? p->ndmax : 4 * (p->m - 1);
   out->resident_bytes = (int64_t)p->bytes;
 }
 
 sfdp_status sfdp_set_coarse_space(sfdp_problem* p, int edge_averages) {
   if (!p) return fail(SFDP_E_INVALID, "NULL argument");
   if (edge_averages != 0 && edge_averages != 1) return fail(SFDP_E_INVALID, "edge_averages must be 0 or 1");
+  if (p->dim == 3 && edge_averages) return fail(SFDP_E_INVALID, "3D problems use the corner coarse space");
   const int nk = edge_averages ? p->nC + p->nE : p->nC;
   if (nk != p->nK) {
     p->nK = nk;
@@ -981,7 +1329,7 @@ sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double*
   if (nrhs <= 0 || !f || !x) return fail(SFDP_E_INVALID, "bad arguments");
   double tk, ti;
   int mo, kmax;
-  defaults(p->prec, opts, tk, ti, mo, kmax);
+  defaults(p->prec, opts, tk, ti, mo, kmax, p->dim);
   const int bsz = batch_of(opts);
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax))) return s;
@@ -1053,7 +1401,7 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
   if (nrhs <= 0 || !ybar || !y || !u || !lam) return fail(SFDP_E_INVALID, "bad arguments");
   double tk, ti;
   int mo, kmax;
-  defaults(p->prec, opts, tk, ti, mo, kmax);
+  defaults(p->prec, opts, tk, ti, mo, kmax, p->dim);
   const int bsz = batch_of(opts);
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p))) return s;
@@ -1083,7 +1431,7 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
   if (nrhs <= 0 || !r || !z) return fail(SFDP_E_INVALID, "bad arguments");
   double tk, ti;
   int mo, kmax;
-  defaults(p->prec, opts, tk, ti, mo, kmax);
+  defaults(p->prec, opts, tk, ti, mo, kmax, p->dim);
   const int bsz = batch_of(opts);
   HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p))) return s;
@@ -1285,6 +1633,12 @@ sfdp_status sfdp_interface_apply(sfdp_problem* p, char which, const double* x, d
   if (!x || !y) return fail(SFDP_E_INVALID, "bad arguments");
   HIPCHK(hipSetDevice(p->ctx->device));
   hipStream_t st = p->ctx->stream;
+  if (p->dim == 3) {
+    if (which != 'F' && which != 'P' && which != 'D') return fail(SFDP_E_INVALID, "which must be 'F', 'P' or 'D'");
+    if ((s = alloc_workspace3(*p, 1))) return s;
+    HIPCHK(interface3(*p, which, (const cd*)x, (cd*)y));
+    return SFDP_OK;
+  }
   if (which == 'D') {
     Target t = single_target(p);
     p->nr = 1;

@@ -117,6 +117,7 @@ constexpr int NQ = 8;
 struct Geo2 {
   int N, m, P, ml, nsub, ND, nmu, nC, nK;  // nK: coarse unknowns (nC, or nC + edges)
   double h, alpha;
+  int dim;  // 3: the free-node kernels of the range-space loop use the 3D grid
   // subdomain coordinates
   __device__ __host__ inline int sx(int s) const { return s % P; }
   __device__ __host__ inline int sy(int s) const { return s / P; }
@@ -280,6 +281,7 @@ enum Kind : int { K_SUB = 0, K_NC128, K_NC, K_NMU256, K_ASM256, K_NF256, K_SUB16
 
 // Host-side problem.
 struct Ctx;
+struct Three;  // state of a 3D instance (three.h)
 struct Problem {
   Ctx* ctx = nullptr;
   int dim = 2, N = 0, m = 0, P = 0, nsub = 0, ml = 0, L = 0, ND = 0, nC = 0, nmu = 0, ndmax = 0;
@@ -292,6 +294,7 @@ struct Problem {
   sfdp_precision prec = SFDP_FP64;
   double beta = 0, alpha = 0;
   bool factored = false;
+  Three* t3 = nullptr;  // dim = 3: maps, factors and workspaces of the 3D path
   // index maps (device)
   int *dloc = nullptr, *dmid = nullptr, *dpart = nullptr, *nd = nullptr, *cloc = nullptr,
       *cgid = nullptr, *muown = nullptr, *mufree = nullptr, *cown = nullptr, *cfree = nullptr,
@@ -352,7 +355,7 @@ struct Problem {
                      (int64_t)nsub * NQ};
   }
   Geo2 geo() const {
-    return Geo2{N, m, P, ml, nsub, ND, nmu, nC, nK, 1.0 / N, alpha};
+    return Geo2{N, m, P, ml, nsub, ND, nmu, nC, nK, 1.0 / N, alpha, dim};
   }
   // x-blocks of this instance in a launch of the given kind
   int blocks(int kind) const {

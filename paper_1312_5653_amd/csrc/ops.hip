@@ -1,8 +1,9 @@
-// FP64 operators on the free-node grid of a 2D instance (Sec. 2 matrices),
+// FP64 operators on the free-node grid of an instance (Sec. 2 matrices),
 // matrix free: on a uniform grid the Q1 stiffness and mass rows are the
-// 9-point stencils  K = k1 (x) m1 + m1 (x) k1,  M = m1 (x) m1  with the 1D P1
-// rows k1 = (1/h)(-1, 2, -1), m1 = (h/6)(1, 4, 1).  K_c couples free nodes to
-// their boundary neighbours with the same stencil.
+// 9-point stencils  K = k1 (x) m1 + m1 (x) k1,  M = m1 (x) m1  (2D; in 3D the
+// 27-point Kronecker sums of three factors) with the 1D P1 rows
+// k1 = (1/h)(-1, 2, -1), m1 = (h/6)(1, 4, 1).  K_c couples free nodes to their
+// boundary neighbours with the same stencil.
 //
 // The KKT residual (Sec. 2 KKT system) of (y, u, lam):
 //   r1 = M ybar - M y - K lam,  r2 = -(beta M u - M lam),  r3 = -Kc yc - K y + M u,
@@ -47,16 +48,60 @@ __device__ inline void stencil_KM(const Sten& st, int N, const int* f2b, const F
     }
 }
 
-__global__ void k_apply_KM(int N, const int* f2b, const double* x, const double* xc, double* yK,
+// 3D: free index t -> grid coordinates (1-based), values and the 27-point
+// stencils K = k1 (x) m1 (x) m1 + m1 (x) k1 (x) m1 + m1 (x) m1 (x) k1, M = m1 (x) m1 (x) m1.
+__device__ inline void ijk3(int64_t t, int N, int& i, int& j, int& k) {
+  const int64_t n1 = N - 1;
+  i = (int)(t % n1) + 1;
+  j = (int)((t / n1) % n1) + 1;
+  k = (int)(t / (n1 * n1)) + 1;
+}
+__device__ inline bool free3(int N, int i, int j, int k) {
+  return i > 0 && j > 0 && k > 0 && i < N && j < N && k < N;
+}
+__device__ inline int64_t fidx3(int N, int i, int j, int k) {
+  const int64_t n1 = N - 1;
+  return (i - 1) + n1 * ((j - 1) + n1 * (int64_t)(k - 1));
+}
+__device__ inline int64_t full3(int N, int i, int j, int k) {
+  const int64_t n1 = N + 1;
+  return i + n1 * (j + n1 * (int64_t)k);
+}
+__device__ inline void stencil_KM3(const Sten& st, int N, const int* f2b, const Field& f, int i, int j, int k,
+                                   double& Kx, double& Mx) {
+  Kx = 0.0;
+  Mx = 0.0;
+  for (int dk = -1; dk <= 1; ++dk)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = i + di, jj = j + dj, kk = k + dk;
+        double v;
+        if (free3(N, ii, jj, kk)) v = f.x[fidx3(N, ii, jj, kk)];
+        else if (f.xc) v = f.xc[f2b[full3(N, ii, jj, kk)]];
+        else continue;
+        const double mi = st.m[di + 1], mj = st.m[dj + 1], mk = st.m[dk + 1];
+        const double wk = st.k[di + 1] * mj * mk + mi * st.k[dj + 1] * mk + mi * mj * st.k[dk + 1];
+        Kx = fma(wk, v, Kx);
+        Mx = fma(mi * mj * mk, v, Mx);
+      }
+}
+
+__global__ void k_apply_KM(int N, int dim, const int* f2b, const double* x, const double* xc, double* yK,
                            double* yM, int64_t nfree, int64_t nbdry) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int r = blockIdx.y;
   if (t >= nfree) return;
-  int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
   Sten st = make_sten(1.0 / N);
   Field f{x + r * nfree, xc ? xc + r * nbdry : nullptr};
   double Kx, Mx;
-  stencil_KM(st, N, f2b, f, i, j, Kx, Mx);
+  if (dim == 3) {
+    int i, j, k;
+    ijk3(t, N, i, j, k);
+    stencil_KM3(st, N, f2b, f, i, j, k, Kx, Mx);
+  } else {
+    int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
+    stencil_KM(st, N, f2b, f, i, j, Kx, Mx);
+  }
   if (yK) yK[r * nfree + t] = Kx;
   if (yM) yM[r * nfree + t] = Mx;
 }
@@ -80,9 +125,24 @@ __global__ void k_make_rhs2(Src src) {
   const int N = d.g.N, s = slot_of(d.map, c);
   const double* r1 = d.r1 + s * nfree;
   const cd* dw = d.cvec2 + c * nfree;
-  int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
   Sten st = make_sten(1.0 / N);
   cd acc{r1[t], 0.0};
+  if (d.g.dim == 3) {
+    int i, j, k;
+    ijk3(t, N, i, j, k);
+    for (int dk = -1; dk <= 1; ++dk)
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          if (!free3(N, i + di, j + dj, k + dk)) continue;
+          const cd w = dw[fidx3(N, i + di, j + dj, k + dk)];
+          const double wm = st.m[di + 1] * st.m[dj + 1] * st.m[dk + 1];
+          acc.x = fma(wm, w.x, acc.x);
+          acc.y = fma(-wm, w.y, acc.y);
+        }
+    d.cvec3[c * nfree + t] = acc;
+    return;
+  }
+  int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
   for (int dj = -1; dj <= 1; ++dj)
     for (int di = -1; di <= 1; ++di) {
       int ii = i + di, jj = j + dj;
@@ -116,9 +176,28 @@ __global__ void __launch_bounds__(256) k_kkt_residual(Src src) {
   int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   double rn = 0.0, bn = 0.0;
   if (t < nfree) {
-    int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
     Sten st = make_sten(1.0 / N);
     double Kyb_unused, Mybar, Ky, My, Kl, Ml, Ku_unused, Mu, Kc;
+    if (d.g.dim == 3) {
+      int i, j, k;
+      ijk3(t, N, i, j, k);
+      stencil_KM3(st, N, f2b, Field{ybar, nullptr}, i, j, k, Kyb_unused, Mybar);
+      stencil_KM3(st, N, f2b, Field{y, nullptr}, i, j, k, Ky, My);
+      stencil_KM3(st, N, f2b, Field{lam, nullptr}, i, j, k, Kl, Ml);
+      stencil_KM3(st, N, f2b, Field{u, nullptr}, i, j, k, Ku_unused, Mu);
+      Kc = 0.0;
+      if (yc)
+        for (int dk = -1; dk <= 1; ++dk)
+          for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di) {
+              const int ii = i + di, jj = j + dj, kk = k + dk;
+              if (free3(N, ii, jj, kk)) continue;
+              const double mi = st.m[di + 1], mj = st.m[dj + 1], mk = st.m[dk + 1];
+              const double wk = st.k[di + 1] * mj * mk + mi * st.k[dj + 1] * mk + mi * mj * st.k[dk + 1];
+              Kc = fma(wk, yc[f2b[full3(N, ii, jj, kk)]], Kc);
+            }
+    } else {
+    int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
     stencil_KM(st, N, f2b, Field{ybar, nullptr}, i, j, Kyb_unused, Mybar);
     stencil_KM(st, N, f2b, Field{y, nullptr}, i, j, Ky, My);
     stencil_KM(st, N, f2b, Field{lam, nullptr}, i, j, Kl, Ml);
@@ -133,6 +212,7 @@ __global__ void __launch_bounds__(256) k_kkt_residual(Src src) {
           double wk = st.k[di + 1] * st.m[dj + 1] + st.m[di + 1] * st.k[dj + 1];
           Kc = fma(wk, yc[f2b[ii + (N + 1) * jj]], Kc);
         }
+    }
     }
     double a1 = Mybar - My - Kl;
     double a2 = -(d.beta * Mu - Ml);
@@ -298,12 +378,12 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_apply_K(const Problem& p, int nrhs, const double* x, const double* xc, double* y,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_apply_KM, dim3(nblk(p.n_free), nrhs), dim3(256), 0, st, p.N, p.full2bdry, x,
+  hipLaunchKernelGGL(k_apply_KM, dim3(nblk(p.n_free), nrhs), dim3(256), 0, st, p.N, p.dim, p.full2bdry, x,
                      xc, y, (double*)nullptr, p.n_free, p.n_bdry);
   return hipGetLastError();
 }
 hipError_t launch_apply_M(const Problem& p, int nrhs, const double* x, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_apply_KM, dim3(nblk(p.n_free), nrhs), dim3(256), 0, st, p.N, p.full2bdry, x,
+  hipLaunchKernelGGL(k_apply_KM, dim3(nblk(p.n_free), nrhs), dim3(256), 0, st, p.N, p.dim, p.full2bdry, x,
                      (const double*)nullptr, (double*)nullptr, y, p.n_free, p.n_bdry);
   return hipGetLastError();
 }

@@ -563,9 +563,12 @@ __device__ void gj_pivot_block(const cd* A, int n, int k0, int b, cd* D, cd* L) 
     if (i < b && j < b) D[i * b + j] = v[r];
   }
 }
-__global__ void __launch_bounds__(256) k_gj_pivot(int n, int k0, int b, const cd* A, cd* D) {
+// The kernels below take a batch of matrices: blockIdx.z selects A + z sA and
+// its pivot-inverse buffers D + z sD.
+__global__ void __launch_bounds__(256) k_gj_pivot(int n, int k0, int b, const cd* A, cd* D, size_t sA,
+                                                  size_t sD) {
   __shared__ cd L[4 * GJ_PB];
-  gj_pivot_block(A, n, k0, b, D, L);
+  gj_pivot_block(A + blockIdx.z * sA, n, k0, b, D + blockIdx.z * sD, L);
 }
 // D into LDS with row stride GJ_PB, zero outside b x b.
 __device__ inline void gj_load_d(cd* Dl, const cd* D, int b) {
@@ -578,8 +581,11 @@ __device__ inline void gj_load_d(cd* Dl, const cd* D, int b) {
 // GJ_RT y .. (+GJ_RT) and columns GJ_CT x .. (+GJ_CT).  U = A_iK D for its
 // rows and the panel rows A_Kj of its columns go to LDS; thread (half, column)
 // then updates 8 rows of one column: A_ij -= U_i A_Kj.
-__global__ void __launch_bounds__(256) k_gj_rows(int n, int k0, int b, cd* A, const cd* D) {
+__global__ void __launch_bounds__(256) k_gj_rows(int n, int k0, int b, cd* A, const cd* D, size_t sA,
+                                                 size_t sD) {
   __shared__ cd Dl[GJ_PB * GJ_PB], Ul[GJ_RT * GJ_PB], Ak[GJ_RT * GJ_PB], Ck[GJ_PB * GJ_CT];
+  A += blockIdx.z * sA;
+  D += blockIdx.z * sD;
   const int i0 = blockIdx.y * GJ_RT, j0 = blockIdx.x * GJ_CT;
   const int nr = min(GJ_RT, n - i0);
   const int cc = threadIdx.x % GJ_CT, half = threadIdx.x / GJ_CT, j = j0 + cc;
@@ -624,13 +630,17 @@ __global__ void __launch_bounds__(256) k_gj_rows(int n, int k0, int b, cd* A, co
 // write): blocks [0, gx) take GJ_CT columns j each (the panel rows: A_Kj = D A_Kj,
 // A_KK = D), blocks [gx, 2 gx) take GJ_CT rows i each outside the panel
 // (A_iK = -A_iK D).  The two sets of entries are disjoint.  Block 2 gx inverts
-// the next panel's pivot block into Dn: k_gj_rows has already given it its final
-// value, and nothing here writes it.
-__global__ void __launch_bounds__(256) k_gj_panel(int n, int k0, int b, int gx, cd* A, const cd* D, cd* Dn) {
+// the next panel's pivot block (pivots below kend) into Dn: k_gj_rows has
+// already given it its final value, and nothing here writes it.
+__global__ void __launch_bounds__(256) k_gj_panel(int n, int k0, int b, int gx, int kend, cd* A, const cd* D,
+                                                  cd* Dn, size_t sA, size_t sD) {
   __shared__ cd Dl[GJ_PB * GJ_PB], S[GJ_CT * (GJ_PB + 1)];
+  A += blockIdx.z * sA;
+  D += blockIdx.z * sD;
+  Dn += blockIdx.z * sD;
   if ((int)blockIdx.x == 2 * gx) {
     const int k1 = k0 + b;
-    if (k1 < n) gj_pivot_block(A, n, k1, min(GJ_PB, n - k1), Dn, S);
+    if (k1 < kend) gj_pivot_block(A, n, k1, min(GJ_PB, kend - k1), Dn, S);
     return;
   }
   gj_load_d(Dl, D, b);
@@ -689,21 +699,27 @@ __global__ void __launch_bounds__(256) k_gj_panel(int n, int k0, int b, int gx, 
   }
 }
 
-static hipError_t invert_dense(int n, cd* A, cd* work, hipStream_t st) {
-  // A^-1 in place by the blocked Gauss-Jordan steps above (n > 64: work holds
-  // at least 2 GJ_PB^2 entries)
-  // work holds two pivot inverses: the current panel's and the next one's
+// Gauss-Jordan pivots [kb, ke) of `batch` n x n matrices A + z sA in place
+// (blocked steps above; work + z sW holds two pivot inverses, 2 GJ_PB^2
+// entries).  Pivots [0, kb) must already have been taken.
+hipError_t gj_range(int n, int kb, int ke, cd* A, size_t sA, cd* work, size_t sW, int batch, hipStream_t st) {
+  if (ke <= kb) return hipSuccess;
   const int gx = (n + GJ_CT - 1) / GJ_CT, gy = (n + GJ_RT - 1) / GJ_RT;
-  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, st, n, 0, std::min(GJ_PB, n), (const cd*)A, work);
-  for (int k0 = 0, p = 0; k0 < n; k0 += GJ_PB, ++p) {
-    const int b = std::min(GJ_PB, n - k0);
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, batch), dim3(256), 0, st, n, kb, std::min(GJ_PB, ke - kb),
+                     (const cd*)A, work, sA, sW);
+  for (int k0 = kb, p = 0; k0 < ke; k0 += GJ_PB, ++p) {
+    const int b = std::min(GJ_PB, ke - k0);
     cd* D = work + (p & 1) * GJ_PB * GJ_PB;
     cd* Dn = work + ((p + 1) & 1) * GJ_PB * GJ_PB;
-    hipLaunchKernelGGL(k_gj_rows, dim3(gx, gy), dim3(256), 0, st, n, k0, b, A, (const cd*)D);
-    hipLaunchKernelGGL(k_gj_panel, dim3(2 * gx + 1), dim3(256), 0, st, n, k0, b, gx, A, (const cd*)D, Dn);
+    hipLaunchKernelGGL(k_gj_rows, dim3(gx, gy, batch), dim3(256), 0, st, n, k0, b, A, (const cd*)D, sA, sW);
+    hipLaunchKernelGGL(k_gj_panel, dim3(2 * gx + 1, 1, batch), dim3(256), 0, st, n, k0, b, gx, ke, A,
+                       (const cd*)D, Dn, sA, sW);
   }
   return hipGetLastError();
 }
+
+// A^-1 in place (n > 64: work holds at least 2 GJ_PB^2 entries)
+hipError_t invert_dense(int n, cd* A, cd* work, hipStream_t st) { return gj_range(n, 0, n, A, 0, work, 0, 1, st); }
 
 // Every step of the set-up for every instance of the target (per-instance FP64
 // scratch named by the views: G64, Sinv64, S64, Phi64, PhiFull, scr, Zs; and

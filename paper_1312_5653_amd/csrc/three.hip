@@ -1,0 +1,690 @@
+// FETI-DP for 3D instances (Sec. 5; definitions of F_DP, d, the coarse
+// problem and the Dirichlet preconditioner as for 2D):
+//
+//   set-up   E^s (Z_rr^s padded with the identity, interior nodes first) is
+//            inverted as one batch by blocked Gauss-Jordan (FP64).  After the
+//            interior pivots the trailing Delta block holds the Schur complement
+//            S_bb of the Dirichlet preconditioner; after all pivots E^s holds
+//            Z_rr^-1, whose Delta block is the local interface operator.
+//            Phi = Z_rr^-1 Z_rc, Z_cc* = Z_cc - Z_cr Phi, K_cc* = sum B_c^T Z_cc* B_c
+//            and its inverse (FP64).
+//   solve    full sweeps t = Z_rr^-1 f_r (the right-hand side d and the
+//            recovery), and right-preconditioned GMRES on F_DP mu = d with
+//            classical Gram-Schmidt applied twice, FP64, its Hessenberg matrix
+//            and Givens rotations on the host (one synchronisation per
+//            iteration).  F_DP = F_rr + F_rc K_cc*^-1 F_rc^T is applied per
+//            subdomain from Z_rr^-1|Delta and Phi; the preconditioner
+//            W B_r S_bb B_r^T W with multiplicity scaling.
+//
+// Multipliers are fully redundant (one per pair of subdomains sharing a Delta
+// node), so W = (sum B_r B_r^T)^+ is B B^T / k^2 on the k copies of a node;
+// since the signed copies of a multiplier cancel, B_r^T W mu = B_r^T mu / k and
+// W B_r y = (y_+ - y_-) / k per multiplier: the preconditioner is a 1 / k
+// scaling on both sides of S_bb (k = 2 on faces, 4 on edges).
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "three.h"
+
+namespace sfdp {
+
+namespace {
+
+constexpr int GJW = 2 * 32 * 32;  // pivot-inverse buffers per matrix of gj_range
+
+__device__ inline cd wsum(cd a) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a.x += __shfl_xor(a.x, off, 64);
+    a.y += __shfl_xor(a.y, off, 64);
+  }
+  return a;
+}
+__device__ inline double wsum(double a) {
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  return a;
+}
+template <class TS>
+__device__ inline cd ld64(const TS& v) { return cvt<double>(v); }
+
+unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- set-up --
+
+// E^s on r positions: Z^s between r nodes, identity on the padding.
+__global__ void k3_build_E(Geo3 g, const int* rl, cd* E) {
+  const int s = blockIdx.y;
+  const int64_t NR2 = (int64_t)g.NR * g.NR;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NR2) return;
+  const int p = (int)(t / g.NR), q = (int)(t % g.NR);
+  const int lp = rl[s * g.NR + p], lq = rl[s * g.NR + q];
+  cd v{0.0, 0.0};
+  if (lp < 0 || lq < 0) {
+    if (p == q) v.x = 1.0;
+  } else {
+    v = g.zloc(lp, lq);
+  }
+  E[(size_t)s * NR2 + t] = v;
+}
+
+// out[s][i][j] = E[s][off + i][off + j], i, j < n, in storage precision
+template <class TS>
+__global__ void k3_take(const cd* E, int NR, int off, int n, TS* out) {
+  using R = typename real_of<TS>::type;
+  const int s = blockIdx.y;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t % n);
+  out[(size_t)s * n * n + t] = cvt<R>(E[(size_t)s * NR * NR + (size_t)(off + i) * NR + off + j]);
+}
+
+// Neighbours of vertex slot q inside the subdomain: the other 7 nodes of the
+// element at that vertex, e = 1..7.
+__device__ inline int vertex_nbr(const Geo3& g, int q, int e) {
+  const int a0 = (q & 1) * g.m, b0 = ((q >> 1) & 1) * g.m, c0 = ((q >> 2) & 1) * g.m;
+  const int a = a0 + (a0 ? -1 : 1) * (e & 1), b = b0 + (b0 ? -1 : 1) * ((e >> 1) & 1),
+            c = c0 + (c0 ? -1 : 1) * ((e >> 2) & 1);
+  return a + g.ml * (b + g.ml * c);
+}
+
+// PhiFull[s][p][q] = (Z_rr^-1 Z_rc)[p][q] from the inverted E (row p of E^-1
+// against the vertex's coupling to its element's r nodes)
+__global__ void k3_phi(Geo3 g, Maps3 mp, const cd* E, cd* PhiFull) {
+  const int s = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.NR * 8) return;
+  const int p = t >> 3, q = t & 7;
+  cd acc{0.0, 0.0};
+  if (mp.cg[s * 8 + q] >= 0) {
+    const int lv = g.vertex(q);
+    const cd* Er = E + (size_t)s * g.NR * g.NR + (size_t)p * g.NR;
+    for (int e = 1; e < 8; ++e) {
+      const int l = vertex_nbr(g, q, e);
+      const int r = mp.rpos[s * g.nl + l];
+      if (r >= 0) fma_acc(acc, Er[r], g.zloc(l, lv));
+    }
+  }
+  PhiFull[((size_t)s * g.NR + p) * 8 + q] = acc;
+}
+
+template <class TS>
+__global__ void k3_phi_delta(Geo3 g, const cd* PhiFull, TS* Phi) {
+  using R = typename real_of<TS>::type;
+  const int s = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ND * 8) return;
+  const int dl = t >> 3, q = t & 7;
+  Phi[((size_t)s * g.ND + dl) * 8 + q] = cvt<R>(PhiFull[((size_t)s * g.NR + g.nI + dl) * 8 + q]);
+}
+
+// Z_cc*^s = Z_cc - Z_cr Phi on the subdomain's corner slots (zero elsewhere);
+// one block of 64 threads per subdomain
+__global__ void k3_zcc(Geo3 g, Maps3 mp, const cd* PhiFull, cd* Zcc) {
+  const int s = blockIdx.x, t = threadIdx.x;
+  const int q = t >> 3, q2 = t & 7;
+  cd v{0.0, 0.0};
+  if (mp.cg[s * 8 + q] >= 0 && mp.cg[s * 8 + q2] >= 0) {
+    const int lv = g.vertex(q);
+    if (q == q2) v = g.zloc(lv, lv);
+    for (int e = 1; e < 8; ++e) {
+      const int l = vertex_nbr(g, q, e);
+      const int r = mp.rpos[s * g.nl + l];
+      if (r >= 0) v = v - g.zloc(lv, l) * PhiFull[((size_t)s * g.NR + r) * 8 + q2];
+    }
+  }
+  Zcc[s * 64 + t] = v;
+}
+
+// K_cc*[c][c2] = sum over the subdomains of corner c of their Z_cc* entries
+// (owners in increasing subdomain order)
+__global__ void k3_coarse_assemble(Geo3 g, Maps3 mp, const cd* Zcc, cd* Kcc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nC = g.nC;
+  if (t >= (int64_t)nC * nC) return;
+  const int c = (int)(t / nC), c2 = (int)(t % nC);
+  cd acc{0.0, 0.0};
+  for (int o = 0; o < 8; ++o) {
+    const int own = mp.cown[c * 8 + o];
+    if (own < 0) continue;
+    const int s = own >> 3, q = own & 7;
+    for (int q2 = 0; q2 < 8; ++q2)
+      if (mp.cg[s * 8 + q2] == c2) acc = acc + Zcc[s * 64 + q * 8 + q2];
+  }
+  Kcc[t] = acc;
+}
+
+hipError_t launch_setup3(Problem& p, cd* E, cd* work) {
+  Three& T = *p.t3;
+  T.g.alpha = p.alpha;
+  const Geo3 g = T.g;
+  const Maps3 mp = T.maps();
+  hipStream_t st = p.ctx->stream;
+  const int64_t NR2 = (int64_t)g.NR * g.NR;
+  const bool s32 = p.s32();
+  hipLaunchKernelGGL(k3_build_E, dim3(nb256(NR2), g.nsub), dim3(256), 0, st, g, (const int*)T.rl, E);
+  hipError_t e = gj_range(g.NR, 0, g.nI, E, NR2, work, GJW, g.nsub, st);
+  if (e != hipSuccess) return e;
+  const dim3 gD(nb256((int64_t)g.ND * g.ND), g.nsub), gR(nb256(NR2), g.nsub);
+  if (s32) hipLaunchKernelGGL(k3_take<cf>, gD, dim3(256), 0, st, (const cd*)E, g.NR, g.nI, g.ND, (cf*)T.Sbb);
+  else hipLaunchKernelGGL(k3_take<cd>, gD, dim3(256), 0, st, (const cd*)E, g.NR, g.nI, g.ND, (cd*)T.Sbb);
+  if ((e = gj_range(g.NR, g.nI, g.NR, E, NR2, work, GJW, g.nsub, st)) != hipSuccess) return e;
+  if (s32) {
+    hipLaunchKernelGGL(k3_take<cf>, gR, dim3(256), 0, st, (const cd*)E, g.NR, 0, g.NR, (cf*)T.Zinv);
+    hipLaunchKernelGGL(k3_take<cf>, gD, dim3(256), 0, st, (const cd*)E, g.NR, g.nI, g.ND, (cf*)T.Sinv);
+  } else {
+    hipLaunchKernelGGL(k3_take<cd>, gR, dim3(256), 0, st, (const cd*)E, g.NR, 0, g.NR, (cd*)T.Zinv);
+    hipLaunchKernelGGL(k3_take<cd>, gD, dim3(256), 0, st, (const cd*)E, g.NR, g.nI, g.ND, (cd*)T.Sinv);
+  }
+  hipLaunchKernelGGL(k3_phi, dim3(nb256(g.NR * 8), g.nsub), dim3(256), 0, st, g, mp, (const cd*)E, T.PhiFull);
+  const dim3 gP(nb256(g.ND * 8), g.nsub);
+  if (s32) hipLaunchKernelGGL(k3_phi_delta<cf>, gP, dim3(256), 0, st, g, (const cd*)T.PhiFull, (cf*)T.Phi);
+  else hipLaunchKernelGGL(k3_phi_delta<cd>, gP, dim3(256), 0, st, g, (const cd*)T.PhiFull, (cd*)T.Phi);
+  hipLaunchKernelGGL(k3_zcc, dim3(g.nsub), dim3(64), 0, st, g, mp, (const cd*)T.PhiFull, T.Zcc);
+  const int64_t nc2 = (int64_t)g.nC * g.nC;
+  hipLaunchKernelGGL(k3_coarse_assemble, dim3(nb256(nc2)), dim3(256), 0, st, g, mp, (const cd*)T.Zcc, p.Kcc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(p.Kinv, p.Kcc, sizeof(cd) * nc2, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+  return invert_dense(g.nC, p.Kinv, work, st);
+}
+
+// ----------------------------------------------------------------- solve --
+
+// Local right-hand side at r position p: f / mult (conj: of conj f); mode 1
+// subtracts Z_rc B_c u_c and B_r^T mu.
+__device__ inline cd local_rhs(const Geo3& g, const Maps3& mp, int s, int p, const cd* f, int conj, int mode,
+                               const cd* uc, const cd* mu) {
+  const int l = mp.rl[s * g.NR + p];
+  if (l < 0) return cd{0.0, 0.0};
+  int a, b, c;
+  g.loc(l, a, b, c);
+  cd v = f[g.freeidx(s, a, b, c)];
+  if (conj) v.y = -v.y;
+  v = (1.0 / g.mult(a, b, c)) * v;
+  if (mode == 1) {
+    for (int q = 0; q < 8; ++q) {
+      const int cq = mp.cg[s * 8 + q];
+      if (cq < 0) continue;
+      const cd z = g.zloc(l, g.vertex(q));  // zero unless l lies in the vertex's element
+      if (z.x != 0.0 || z.y != 0.0) v = v - z * uc[cq];
+    }
+    if (p >= g.nI) {
+      const int base = (s * g.ND + p - g.nI) * 3;
+      for (int j = 0; j < 3; ++j) {
+        const int k = mp.dmu[base + j];
+        if (k >= 0) v = v - (double)mp.dsg[base + j] * mu[k];
+      }
+    }
+  }
+  return v;
+}
+
+// Full sweep T_s = Z_rr^-1 f~_s (one workgroup per subdomain, a thread per row;
+// Z_rr^-1 is symmetric, so row i is read as column i: coalesced).  mode 0 also
+// gives the subdomain's corner terms Wc[s][q] = f_q / 8 - (Phi^T f~)_q of f_c*.
+template <class TS>
+__global__ void __launch_bounds__(1024) k3_sweep(Geo3 g, Maps3 mp, const TS* __restrict__ Zinv,
+                                                 const cd* PhiFull, const cd* f, int conj, int mode,
+                                                 const cd* uc, const cd* mu, cd* T, cd* Wc) {
+  extern __shared__ cd ft[];
+  const int s = blockIdx.x, NR = g.NR;
+  for (int p = threadIdx.x; p < NR; p += blockDim.x) ft[p] = local_rhs(g, mp, s, p, f, conj, mode, uc, mu);
+  __syncthreads();
+  const TS* Z = Zinv + (size_t)s * NR * NR;
+  for (int i = threadIdx.x; i < NR; i += blockDim.x) {
+    cd a0{0.0, 0.0}, a1{0.0, 0.0}, a2{0.0, 0.0}, a3{0.0, 0.0};
+    int k = 0;
+    for (; k + 3 < NR; k += 4) {
+      fma_acc(a0, ld64(Z[(size_t)k * NR + i]), ft[k]);
+      fma_acc(a1, ld64(Z[(size_t)(k + 1) * NR + i]), ft[k + 1]);
+      fma_acc(a2, ld64(Z[(size_t)(k + 2) * NR + i]), ft[k + 2]);
+      fma_acc(a3, ld64(Z[(size_t)(k + 3) * NR + i]), ft[k + 3]);
+    }
+    for (; k < NR; ++k) fma_acc(a0, ld64(Z[(size_t)k * NR + i]), ft[k]);
+    T[(size_t)s * NR + i] = (a0 + a1) + (a2 + a3);
+  }
+  if (mode == 0) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wv < 8) {
+      const int q = wv;
+      cd acc{0.0, 0.0};
+      for (int p = lane; p < NR; p += 64) fma_acc(acc, PhiFull[((size_t)s * NR + p) * 8 + q], ft[p]);
+      acc = wsum(acc);
+      if (lane == 0) {
+        cd v{0.0, 0.0};
+        if (mp.cg[s * 8 + q] >= 0) {
+          int a, b, c;
+          g.loc(g.vertex(q), a, b, c);
+          cd fv = f[g.freeidx(s, a, b, c)];
+          if (conj) fv.y = -fv.y;
+          v = 0.125 * fv - acc;  // a vertex is shared by 8 subdomains
+        }
+        Wc[s * 8 + q] = v;
+      }
+    }
+  }
+}
+
+// Interface product on one subdomain: xs = B_r^T x on its Delta nodes (scaled
+// by 1 / multiplicity when `scale`), Y_s = Mat xs, Wc_s = Phi^T xs.
+template <class TS>
+__global__ void __launch_bounds__(1024) k3_local(Geo3 g, Maps3 mp, const TS* __restrict__ Mat,
+                                                 const TS* __restrict__ Phi, int scale, const cd* x, cd* Y,
+                                                 cd* Wc) {
+  extern __shared__ cd xs[];
+  const int s = blockIdx.x, ND = g.ND, nd = mp.nds[s];
+  for (int i = threadIdx.x; i < ND; i += blockDim.x) {
+    cd v{0.0, 0.0};
+    if (i < nd) {
+      const int base = (s * ND + i) * 3;
+      for (int j = 0; j < 3; ++j) {
+        const int k = mp.dmu[base + j];
+        if (k >= 0) v = v + (double)mp.dsg[base + j] * x[k];
+      }
+      if (scale) {
+        int a, b, c;
+        g.loc(mp.rl[s * g.NR + g.nI + i], a, b, c);
+        v = (1.0 / g.mult(a, b, c)) * v;
+      }
+    }
+    xs[i] = v;
+  }
+  __syncthreads();
+  if (Mat) {
+    const TS* A = Mat + (size_t)s * ND * ND;
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+      cd a0{0.0, 0.0}, a1{0.0, 0.0}, a2{0.0, 0.0}, a3{0.0, 0.0};
+      int k = 0;
+      for (; k + 3 < nd; k += 4) {
+        fma_acc(a0, ld64(A[(size_t)k * ND + i]), xs[k]);
+        fma_acc(a1, ld64(A[(size_t)(k + 1) * ND + i]), xs[k + 1]);
+        fma_acc(a2, ld64(A[(size_t)(k + 2) * ND + i]), xs[k + 2]);
+        fma_acc(a3, ld64(A[(size_t)(k + 3) * ND + i]), xs[k + 3]);
+      }
+      for (; k < nd; ++k) fma_acc(a0, ld64(A[(size_t)k * ND + i]), xs[k]);
+      Y[(size_t)s * ND + i] = (a0 + a1) + (a2 + a3);
+    }
+  }
+  if (Phi) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wv < 8) {
+      cd acc{0.0, 0.0};
+      for (int i = lane; i < nd; i += 64) fma_acc(acc, ld64(Phi[((size_t)s * ND + i) * 8 + wv]), xs[i]);
+      acc = wsum(acc);
+      if (lane == 0) Wc[s * 8 + wv] = acc;
+    }
+  }
+}
+
+// out[c] = add[c] + sum of Wc over the corner's owners (fixed order)
+__global__ void k3_corner_sum(int nC, const int* cown, const cd* Wc, const cd* add, cd* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nC) return;
+  cd acc = add ? add[c] : cd{0.0, 0.0};
+  for (int o = 0; o < 8; ++o) {
+    const int own = cown[c * 8 + o];
+    if (own >= 0) acc = acc + Wc[own];
+  }
+  out[c] = acc;
+}
+
+// y = A x (n x n, FP64), one wave per row
+__global__ void k3_dense_mv(int n, const cd* A, const cd* x, cd* y) {
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;
+  cd acc{0.0, 0.0};
+  for (int j = lane; j < n; j += 64) fma_acc(acc, A[(size_t)row * n + j], x[j]);
+  acc = wsum(acc);
+  if (lane == 0) y[row] = acc;
+}
+
+// Per multiplier k with owners (s+, d+) and (s-, d-):
+//   out_k = sc_k ((v+ ) - (v-)),  v = Y[s ystride + yoff + d] + phis (Phi_s[d] . u_c(B_c s))
+// with sc_k = 1 / multiplicity when `scale`, else 1.
+template <class TS>
+__global__ void k3_scatter(Geo3 g, Maps3 mp, const cd* Y, int ystride, int yoff, const TS* Phi, const cd* uc,
+                           double phis, int scale, cd* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.nmu) return;
+  cd acc{0.0, 0.0};
+  int own = 0;
+  for (int side = 0; side < 2; ++side) {
+    own = mp.muown[2 * k + side];
+    const int s = own / g.ND, dl = own % g.ND;
+    cd v = Y ? Y[(size_t)s * ystride + yoff + dl] : cd{0.0, 0.0};
+    if (Phi) {
+      cd pc{0.0, 0.0};
+      for (int q = 0; q < 8; ++q) {
+        const int cq = mp.cg[s * 8 + q];
+        if (cq >= 0) fma_acc(pc, ld64(Phi[((size_t)s * g.ND + dl) * 8 + q]), uc[cq]);
+      }
+      v = v + phis * pc;
+    }
+    acc = side == 0 ? acc + v : acc - v;
+  }
+  if (scale) {
+    const int s = own / g.ND, dl = own % g.ND;
+    int a, b, c;
+    g.loc(mp.rl[s * g.NR + g.nI + dl], a, b, c);
+    acc = (1.0 / g.mult(a, b, c)) * acc;
+  }
+  out[k] = acc;
+}
+
+// Primal solution on the free nodes: corners from u_c, every other node the
+// average of its subdomain copies (conj: conjugated)
+__global__ void k3_assemble(Geo3 g, Maps3 mp, const cd* T, const cd* uc, int conj, cd* x) {
+  const int64_t n1 = g.N - 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n1 * n1 * n1) return;
+  const int gi = (int)(t % n1) + 1, gj = (int)((t / n1) % n1) + 1, gk = (int)(t / (n1 * n1)) + 1;
+  const int m = g.m, P = g.P;
+  cd v{0.0, 0.0};
+  if (gi % m == 0 && gj % m == 0 && gk % m == 0) {
+    v = uc[(gi / m - 1) + (P - 1) * ((gj / m - 1) + (P - 1) * (gk / m - 1))];
+  } else {
+    // owning subdomains along each axis: one, or two when on a subdomain face
+    const int ni = gi % m ? 1 : 2, nj = gj % m ? 1 : 2, nk = gk % m ? 1 : 2;
+    int cnt = 0;
+    for (int ai = 0; ai < ni; ++ai)
+      for (int aj = 0; aj < nj; ++aj)
+        for (int ak = 0; ak < nk; ++ak) {
+          const int sx = gi / m - (ni == 2 ? 1 - ai : 0), sy = gj / m - (nj == 2 ? 1 - aj : 0),
+                    sz = gk / m - (nk == 2 ? 1 - ak : 0);
+          const int s = sx + P * (sy + P * sz);
+          const int l = (gi - sx * m) + g.ml * ((gj - sy * m) + g.ml * (gk - sz * m));
+          v = v + T[(size_t)s * g.NR + mp.rpos[s * g.nl + l]];
+          ++cnt;
+        }
+    v = (1.0 / cnt) * v;
+  }
+  if (conj) v.y = -v.y;
+  x[t] = v;
+}
+
+// ---- Krylov vector kernels (length n, FP64 complex) ----
+// part[i * nb + block] = sum over the block's entries of conj(V_i) w, i < nv
+__global__ void __launch_bounds__(256) k3_dots(int64_t n, int nv, const cd* V, int64_t vs, const cd* w,
+                                               cd* part) {
+  __shared__ cd sh[4];
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const cd wv = t < n ? w[t] : cd{0.0, 0.0};
+  const int lane = threadIdx.x & 63, wi = threadIdx.x >> 6;
+  for (int i = 0; i < nv; ++i) {
+    cd a{0.0, 0.0};
+    if (t < n) fma_conj_acc(a, V[i * vs + t], wv);
+    a = wsum(a);
+    if (lane == 0) sh[wi] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(int64_t)i * gridDim.x + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+  }
+}
+// h[i] = sum_b part[i * nb + b] in a fixed order (one block per i)
+__global__ void __launch_bounds__(256) k3_reduce(int nb, const cd* part, cd* h) {
+  __shared__ cd sh[256];
+  const int i = blockIdx.x;
+  cd a{0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += 256) a = a + part[(int64_t)i * nb + b];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) h[i] = sh[0];
+}
+// w -= sum_i h[i] V_i ; npart[block] = sum |w|^2 over the block
+__global__ void __launch_bounds__(256) k3_axpy(int64_t n, int nv, const cd* V, int64_t vs, const cd* h, cd* w,
+                                               double* npart) {
+  __shared__ double sh[4];
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double q = 0.0;
+  if (t < n) {
+    cd a = w[t];
+    for (int i = 0; i < nv; ++i) a = a - h[i] * V[i * vs + t];
+    w[t] = a;
+    q = abs2(a);
+  }
+  q = wsum(q);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) npart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+// out[0] = sum of npart[0 .. nb) in a fixed order
+__global__ void __launch_bounds__(256) k3_sum(int nb, const double* npart, double* out) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) a += npart[b];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+// v = w / sqrt(nrm[0]) (zero when the norm is zero)
+__global__ void k3_normalize(int64_t n, const cd* w, const double* nrm, cd* v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double r = nrm[0] > 0.0 ? 1.0 / sqrt(nrm[0]) : 0.0;
+  v[t] = r * w[t];
+}
+// out = sum_i y[i] V_i
+__global__ void k3_combine(int64_t n, int nv, const cd* V, int64_t vs, const cd* y, cd* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  cd a{0.0, 0.0};
+  for (int i = 0; i < nv; ++i) fma_acc(a, y[i], V[i * vs + t]);
+  out[t] = a;
+}
+
+namespace {
+
+struct Ops3 {
+  Problem& p;
+  Three& T;
+  Geo3 g;
+  Maps3 mp;
+  hipStream_t st;
+  bool s32;
+  unsigned threads_local, threads_sweep;
+  explicit Ops3(Problem& pp)
+      : p(pp), T(*pp.t3), g(pp.t3->g), mp(pp.t3->maps()), st(pp.ctx->stream), s32(pp.s32()) {
+    threads_local = (unsigned)std::min(1024, std::max(512, (g.ND + 63) / 64 * 64));
+    threads_sweep = (unsigned)std::min(1024, std::max(512, (g.NR + 63) / 64 * 64));
+  }
+  template <class TS>
+  void local_t(const void* Mat, const void* Phi, int scale, const cd* x, cd* Y, cd* Wc) {
+    hipLaunchKernelGGL(k3_local<TS>, dim3(g.nsub), dim3(threads_local), sizeof(cd) * g.ND, st, g, mp,
+                       (const TS*)Mat, (const TS*)Phi, scale, x, Y, Wc);
+  }
+  void local(const void* Mat, const void* Phi, int scale, const cd* x, cd* Y, cd* Wc) {
+    if (s32) local_t<cf>(Mat, Phi, scale, x, Y, Wc);
+    else local_t<cd>(Mat, Phi, scale, x, Y, Wc);
+  }
+  void scatter(const cd* Y, int ystride, int yoff, bool phi, const cd* uc, double phis, int scale, cd* out) {
+    const unsigned nb = nb256(g.nmu);
+    if (s32)
+      hipLaunchKernelGGL(k3_scatter<cf>, dim3(nb), dim3(256), 0, st, g, mp, Y, ystride, yoff,
+                         phi ? (const cf*)T.Phi : (const cf*)nullptr, uc, phis, scale, out);
+    else
+      hipLaunchKernelGGL(k3_scatter<cd>, dim3(nb), dim3(256), 0, st, g, mp, Y, ystride, yoff,
+                         phi ? (const cd*)T.Phi : (const cd*)nullptr, uc, phis, scale, out);
+  }
+  void sweep(const cd* f, int conj, int mode) {
+    const size_t lds = sizeof(cd) * g.NR;
+    if (s32)
+      hipLaunchKernelGGL(k3_sweep<cf>, dim3(g.nsub), dim3(threads_sweep), lds, st, g, mp, (const cf*)T.Zinv,
+                         (const cd*)T.PhiFull, f, conj, mode, (const cd*)T.uc, (const cd*)T.mu, T.T, T.Wc);
+    else
+      hipLaunchKernelGGL(k3_sweep<cd>, dim3(g.nsub), dim3(threads_sweep), lds, st, g, mp, (const cd*)T.Zinv,
+                         (const cd*)T.PhiFull, f, conj, mode, (const cd*)T.uc, (const cd*)T.mu, T.T, T.Wc);
+  }
+  // uc = K_cc*^-1 (add + sum of Wc)
+  void coarse(const cd* add) {
+    hipLaunchKernelGGL(k3_corner_sum, dim3(nb256(g.nC)), dim3(256), 0, st, g.nC, (const int*)T.cown,
+                       (const cd*)T.Wc, add, T.gc);
+    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4), dim3(256), 0, st, g.nC, (const cd*)p.Kinv,
+                       (const cd*)T.gc, T.uc);
+  }
+  // out = F_DP x
+  void apply_F(const cd* x, cd* out) {
+    local(T.Sinv, T.Phi, 0, x, T.Y, T.Wc);
+    coarse(nullptr);
+    scatter(T.Y, g.ND, 0, true, T.uc, 1.0, 0, out);
+  }
+  // out = W B_r S_bb B_r^T W x
+  void apply_P(const cd* x, cd* out) {
+    local(T.Sbb, nullptr, 1, x, T.Y, nullptr);
+    scatter(T.Y, g.ND, 0, false, nullptr, 0.0, 1, out);
+  }
+  // d = sum B_r (Z_rr^-1 f_r)|Delta - F_rc K_cc*^-1 f_c*  (leaves f_c* in fcs)
+  void rhs(const cd* f, int conj) {
+    sweep(f, conj, 0);
+    hipLaunchKernelGGL(k3_corner_sum, dim3(nb256(g.nC)), dim3(256), 0, st, g.nC, (const int*)T.cown,
+                       (const cd*)T.Wc, (const cd*)nullptr, T.fcs);
+    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4), dim3(256), 0, st, g.nC, (const cd*)p.Kinv,
+                       (const cd*)T.fcs, T.uc);
+    scatter(T.T, g.NR, g.nI, true, T.uc, -1.0, 0, T.d);
+  }
+};
+
+// Right-preconditioned GMRES on F_DP mu = d from mu = 0 (relative residual tol
+// of the unpreconditioned system, at most kmax iterations).
+hipError_t gmres3(Ops3& o, double tol, int kmax, int* its) {
+  Three& T = o.T;
+  hipStream_t st = o.st;
+  const int64_t n = o.g.nmu, vs = n;
+  const unsigned nb = nb256(n);
+  const int ks = T.kalloc + 1;  // stride of the two coefficient sets in hd
+  cd* V = T.V;
+  double* dn = (double*)(T.hd + 2 * ks);
+  hipLaunchKernelGGL(k3_axpy, dim3(nb), dim3(256), 0, st, n, 0, (const cd*)V, vs, (const cd*)T.hd, T.d,
+                     T.npart);
+  hipLaunchKernelGGL(k3_sum, dim3(1), dim3(256), 0, st, (int)nb, (const double*)T.npart, dn);
+  hipError_t e = hipMemcpyAsync(T.hh, T.hd, sizeof(cd) * (2 * ks + 1), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  const double beta = std::sqrt(((double*)(T.hh + 2 * ks))[0]);
+  *its = 0;
+  if (!(beta > 0.0)) {
+    hipLaunchKernelGGL(k3_combine, dim3(nb), dim3(256), 0, st, n, 0, (const cd*)V, vs, (const cd*)T.hd, T.mu);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k3_normalize, dim3(nb), dim3(256), 0, st, n, (const cd*)T.d, (const double*)dn, V);
+  using cx = std::complex<double>;
+  const int km = std::min(kmax, T.kalloc);
+  std::vector<cx> H((size_t)(km + 1) * km), cs(km), sn(km), gv(km + 1, cx(0.0));
+  gv[0] = beta;
+  int j = 0;
+  for (; j < km; ++j) {
+    cd* vj = V + (int64_t)j * vs;
+    cd* vn = V + (int64_t)(j + 1) * vs;
+    o.apply_P(vj, T.z);
+    o.apply_F(T.z, vn);
+    for (int pass = 0; pass < 2; ++pass) {
+      cd* h = T.hd + pass * ks;
+      hipLaunchKernelGGL(k3_dots, dim3(nb), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, (const cd*)vn, T.part);
+      hipLaunchKernelGGL(k3_reduce, dim3(j + 1), dim3(256), 0, st, (int)nb, (const cd*)T.part, h);
+      hipLaunchKernelGGL(k3_axpy, dim3(nb), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, (const cd*)h, vn,
+                         T.npart);
+    }
+    hipLaunchKernelGGL(k3_sum, dim3(1), dim3(256), 0, st, (int)nb, (const double*)T.npart, dn);
+    hipLaunchKernelGGL(k3_normalize, dim3(nb), dim3(256), 0, st, n, (const cd*)vn, (const double*)dn, vn);
+    e = hipMemcpyAsync(T.hh, T.hd, sizeof(cd) * (2 * ks + 1), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    // column j of the Hessenberg matrix, rotated by the previous rotations
+    cx* Hj = H.data() + (size_t)j * (km + 1);
+    for (int i = 0; i <= j; ++i) Hj[i] = cx(T.hh[i].x + T.hh[ks + i].x, T.hh[i].y + T.hh[ks + i].y);
+    const double hn = std::sqrt(((double*)(T.hh + 2 * ks))[0]);
+    for (int i = 0; i < j; ++i) {
+      const cx a = Hj[i], b = Hj[i + 1];
+      Hj[i] = cs[i] * a + sn[i] * b;
+      Hj[i + 1] = -std::conj(sn[i]) * a + cs[i] * b;
+    }
+    const cx a = Hj[j];
+    const double ra = std::abs(a), rho = std::sqrt(ra * ra + hn * hn);
+    if (ra == 0.0) {
+      cs[j] = 0.0;
+      sn[j] = 1.0;
+    } else {
+      cs[j] = ra / rho;
+      sn[j] = (a / ra) * hn / rho;
+    }
+    Hj[j] = cs[j] * a + sn[j] * hn;
+    gv[j + 1] = -std::conj(sn[j]) * gv[j];
+    gv[j] = cs[j] * gv[j];
+    if (std::abs(gv[j + 1]) <= tol * beta || !(hn > 0.0)) {
+      ++j;
+      break;
+    }
+  }
+  const int mk = j;
+  *its = mk;
+  // y = H^-1 g (upper triangular), mu = P^-1 (V y)
+  std::vector<cx> y(mk);
+  for (int i = mk - 1; i >= 0; --i) {
+    cx s = gv[i];
+    for (int c = i + 1; c < mk; ++c) s -= H[(size_t)c * (km + 1) + i] * y[c];
+    y[i] = s / H[(size_t)i * (km + 1) + i];
+  }
+  for (int i = 0; i < mk; ++i) T.hh[i] = cd{y[i].real(), y[i].imag()};
+  e = hipMemcpyAsync(T.hd, T.hh, sizeof(cd) * std::max(mk, 1), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k3_combine, dim3(nb), dim3(256), 0, st, n, mk, (const cd*)V, vs, (const cd*)T.hd, T.w);
+  o.apply_P(T.w, T.mu);
+  // the host copy above must land before hh is reused
+  e = hipStreamSynchronize(st);
+  return e == hipSuccess ? hipGetLastError() : e;
+}
+
+}  // namespace
+
+hipError_t feti3(Problem& p, const cd* f, cd* x, int conj, double tol, int kmax, int* its) {
+  Ops3 o(p);
+  Three& T = o.T;
+  o.rhs(f, conj);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = gmres3(o, tol, kmax, its)) != hipSuccess) return e;
+  // u_c = K_cc*^-1 (f_c* + F_rc^T mu), u_r = Z_rr^-1 (f_r - Z_rc B_c u_c - B_r^T mu)
+  o.local(nullptr, T.Phi, 0, T.mu, nullptr, T.Wc);
+  o.coarse(T.fcs);
+  o.sweep(f, conj, 1);
+  const int64_t n1 = o.g.N - 1;
+  hipLaunchKernelGGL(k3_assemble, dim3(nb256(n1 * n1 * n1)), dim3(256), 0, o.st, o.g, o.mp, (const cd*)T.T,
+                     (const cd*)T.uc, conj, x);
+  return hipGetLastError();
+}
+
+__global__ void k3_log(int* flags, int c, int q, int its) {
+  flags[FLAG_ITS + c] = its;
+  const int k = flags[FLAG_CNT + q];
+  if (k < 16) flags[FLAG_LOG + 16 * q + k] = its;
+  flags[FLAG_CNT + q] = k + 1;
+  flags[3] += its;
+  flags[4] += its;
+}
+hipError_t launch_log3(Problem& p, int c, int q, int its) {
+  hipLaunchKernelGGL(k3_log, dim3(1), dim3(1), 0, p.ctx->stream, p.flags, c, q, its);
+  return hipGetLastError();
+}
+
+hipError_t interface3(Problem& p, char which, const cd* x, cd* y) {
+  Ops3 o(p);
+  if (which == 'F') o.apply_F(x, y);
+  else if (which == 'P') o.apply_P(x, y);
+  else {
+    o.rhs(x, 0);
+    hipError_t e = hipMemcpyAsync(y, o.T.d, sizeof(cd) * o.g.nmu, hipMemcpyDeviceToDevice, o.st);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sfdp
