@@ -267,8 +267,8 @@ def cpu_instances(count, seed, budget_s=10.0):
 
 
 def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup, tol_kkt, tol_inner,
-                  batch, max_krylov=0, factors=0, edges=None):
-    p = sfdp.Problem(ctx, 2, N, m, precision)
+                  batch, max_krylov=0, factors=0, edges=None, dim=2):
+    p = sfdp.Problem(ctx, dim, N, m, precision)
     if edges is not None:
         p.set_coarse_space(edges)
     torch.cuda.synchronize()
@@ -311,6 +311,26 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
             "kernel_times": kt, "sizes": sizes}
 
 
+def run_c3(sfdp, torch, ctx, N, beta, steps, tol_kkt, m=8, B=4):
+    """The 3D configuration: Q1 trilinear Poisson control on N^3 cells in
+    (N/m)^3 subdomains of m^3, B eight-mode product-of-sines targets per step,
+    mixed precision (complex64 local operators, FP64 coarse problem, Krylov and
+    refinement)."""
+    import numpy as np
+    from paper_1312_5653_amd import workloads
+    ybar = np.stack([workloads.sine_target(3, N, *workloads.modes_for("eight3d", s))[0] for s in range(B)])
+    yt = torch.tensor(ybar, device="cuda:0")
+    r = run_precision(sfdp, torch, ctx, sfdp.SFDP_MIXED, N, m, beta, yt, steps, 1, tol_kkt, 3e-7, B, dim=3)
+    sz = r["sizes"]
+    return {"workload": f"3D Q1 Poisson control {N}^3 cells, {N // m}^3 subdomains of {m}^3, beta={beta:g}, "
+                        f"8-mode product-of-sines targets (seeds 0..{B - 1}), {B} targets per step",
+            "precision": "mixed", "solves_per_s": r["solves_per_s"], "ms_per_step": r["ms_per_step"],
+            "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "setup_ms": r["setup_ms"],
+            "max_rel_kkt": r["max_rel_kkt"], "krylov_its_per_solve": r["krylov_per_solve"],
+            "dofs": (N - 1) ** 3, "n_mult": sz["n_mult"], "n_corner": sz["n_corner"],
+            "resident_bytes": sz["resident_bytes"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,6 +354,10 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
     ap.add_argument("--max-krylov", type=int, default=0,
                     help="GMRES iteration cap per FETI-DP solve (0: library default)")
+    ap.add_argument("--c3", type=int, default=64, metavar="N",
+                    help="3D configuration: N^3 cells in subdomains of 8^3 (0 skips it)")
+    ap.add_argument("--c3-only", action="store_true", help="only the 3D configuration (for profiles)")
+    ap.add_argument("--c3-steps", type=int, default=5)
     ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB"),
                     help="write the traffic record from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
@@ -365,6 +389,10 @@ def main():
         del src_buf, dst_buf
     ctx = sfdp.Context(0)
     tol_kkt = 1e-8
+    if args.c3_only:
+        print(json.dumps({"c3_3d": run_c3(sfdp, torch, ctx, args.c3, beta, args.c3_steps, tol_kkt)}), flush=True)
+        ctx.close()
+        return
     res = {}
     precs = [("fp64", sfdp.SFDP_FP64, 1e-13)]
     if not args.fp64_only:
@@ -458,6 +486,8 @@ def main():
             out["instances_batch"]["cpu_baseline"] = cpu_instances(args.instances, 0)
     if args.requests > 0 and not args.headline_only:
         out["serving"] = run_serving(sfdp, torch, args.requests, 0, tol_kkt, args.serve_budget_gb)
+    if args.c3 > 0 and not args.headline_only:
+        out["c3_3d"] = run_c3(sfdp, torch, ctx, args.c3, beta, args.c3_steps, tol_kkt)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, m, beta, ybar[0])
     ctx.close()
