@@ -554,18 +554,21 @@ void free_workspace3(Problem& p) {
   Three& T = *p.t3;
   if (!T.kalloc) return;
   const Geo3& g = T.g;
-  const size_t nm = g.nmu, nb = (nm + 255) / 256, kk = T.kalloc + 1;
-  dfree(p, (void*&)T.T, sizeof(cd) * g.nsub * g.NR);
-  dfree(p, (void*&)T.Y, sizeof(cd) * g.nsub * g.ND);
-  dfree(p, (void*&)T.Wc, sizeof(cd) * g.nsub * 8);
-  for (cd** v : {&T.fcs, &T.uc, &T.gc}) dfree(p, (void*&)*v, sizeof(cd) * std::max(g.nC, 1));
-  for (cd** v : {&T.d, &T.mu, &T.z, &T.w}) dfree(p, (void*&)*v, sizeof(cd) * nm);
-  dfree(p, (void*&)T.V, sizeof(cd) * kk * nm);
-  dfree(p, (void*&)T.part, sizeof(cd) * kk * nb);
-  dfree(p, (void*&)T.hd, sizeof(cd) * (2 * kk + 1));
-  dfree(p, (void*&)T.npart, sizeof(double) * nb);
+  const size_t R = NRMAX, nm = g.nmu, nb = (nm + 255) / 256, kk = T.kalloc + 1;
+  dfree(p, (void*&)T.T, sizeof(cd) * R * g.nsub * g.NR);
+  dfree(p, (void*&)T.Y, sizeof(cd) * R * g.nsub * g.ND);
+  dfree(p, (void*&)T.Wc, sizeof(cd) * R * g.nsub * 8);
+  for (cd** v : {&T.fcs, &T.uc, &T.gc}) dfree(p, (void*&)*v, sizeof(cd) * R * std::max(g.nC, 1));
+  for (cd** v : {&T.d, &T.mu, &T.z, &T.w}) dfree(p, (void*&)*v, sizeof(cd) * R * nm);
+  dfree(p, (void*&)T.V, sizeof(cd) * R * kk * nm);
+  dfree(p, (void*&)T.part, sizeof(cd) * R * kk * nb);
+  dfree(p, (void*&)T.hd, sizeof(cd) * R * (2 * kk + 1));
+  dfree(p, (void*&)T.npart, sizeof(double) * R * nb);
+  dfree(p, (void*&)T.nvd, sizeof(int) * R);
   if (T.hh) hipHostFree(T.hh);
+  if (T.nvh) hipHostFree(T.nvh);
   T.hh = nullptr;
+  T.nvh = nullptr;
   T.kalloc = 0;
 }
 sfdp_status alloc_workspace3(Problem& p, int kmax) {
@@ -573,43 +576,40 @@ sfdp_status alloc_workspace3(Problem& p, int kmax) {
   if (T.kalloc >= kmax) return SFDP_OK;
   free_workspace3(p);
   const Geo3& g = T.g;
-  const size_t nm = g.nmu, nb = (nm + 255) / 256, kk = kmax + 1;
+  const size_t R = NRMAX, nm = g.nmu, nb = (nm + 255) / 256, kk = kmax + 1;
   sfdp_status s;
-  if ((s = dalloc(p, (void**)&T.T, sizeof(cd) * g.nsub * g.NR)) ||
-      (s = dalloc(p, (void**)&T.Y, sizeof(cd) * g.nsub * g.ND)) ||
-      (s = dalloc(p, (void**)&T.Wc, sizeof(cd) * g.nsub * 8)))
+  if ((s = dalloc(p, (void**)&T.T, sizeof(cd) * R * g.nsub * g.NR)) ||
+      (s = dalloc(p, (void**)&T.Y, sizeof(cd) * R * g.nsub * g.ND)) ||
+      (s = dalloc(p, (void**)&T.Wc, sizeof(cd) * R * g.nsub * 8)))
     return s;
   for (cd** v : {&T.fcs, &T.uc, &T.gc})
-    if ((s = dalloc(p, (void**)v, sizeof(cd) * std::max(g.nC, 1)))) return s;
+    if ((s = dalloc(p, (void**)v, sizeof(cd) * R * std::max(g.nC, 1)))) return s;
   for (cd** v : {&T.d, &T.mu, &T.z, &T.w})
-    if ((s = dalloc(p, (void**)v, sizeof(cd) * nm))) return s;
-  if ((s = dalloc(p, (void**)&T.V, sizeof(cd) * kk * nm)) || (s = dalloc(p, (void**)&T.part, sizeof(cd) * kk * nb)) ||
-      (s = dalloc(p, (void**)&T.hd, sizeof(cd) * (2 * kk + 1))) ||
-      (s = dalloc(p, (void**)&T.npart, sizeof(double) * nb)))
+    if ((s = dalloc(p, (void**)v, sizeof(cd) * R * nm))) return s;
+  if ((s = dalloc(p, (void**)&T.V, sizeof(cd) * R * kk * nm)) ||
+      (s = dalloc(p, (void**)&T.part, sizeof(cd) * R * kk * nb)) ||
+      (s = dalloc(p, (void**)&T.hd, sizeof(cd) * R * (2 * kk + 1))) ||
+      (s = dalloc(p, (void**)&T.npart, sizeof(double) * R * nb)) || (s = dalloc(p, (void**)&T.nvd, sizeof(int) * R)))
     return s;
-  if (hipHostMalloc((void**)&T.hh, sizeof(cd) * (2 * kk + 1)) != hipSuccess) {
-    T.hh = nullptr;
+  if (hipHostMalloc((void**)&T.hh, sizeof(cd) * R * (2 * kk + 1)) != hipSuccess ||
+      hipHostMalloc((void**)&T.nvh, sizeof(int) * R) != hipSuccess) {
     return fail(SFDP_E_NOMEM, "pinned host allocation");
   }
   T.kalloc = kmax;
   return SFDP_OK;
 }
 
-// FETI-DP solves of the view's nr right-hand sides (vectors f, x of Dev, c-th
-// at offset c n_free), one after another; each logs its iteration count in
-// the flag words of its group slot.
+// FETI-DP solves of the view's nr right-hand sides together (vectors f, x of
+// Dev, c-th at offset c n_free); each logs its iteration count in the flag
+// words of its group slot.
 sfdp_status feti_run3(Problem& p, int fsel, int conj, int xsel, double tol, int kmax) {
   sfdp_status s = alloc_workspace3(p, kmax);
   if (s) return s;
   const Dev d = p.dev();
-  for (int c = 0; c < p.nr; ++c) {
-    const cd* f = dev_vec(d, fsel) + (size_t)c * p.n_free;
-    cd* x = dev_vec(d, xsel) + (size_t)c * p.n_free;
-    int its = 0;
-    hipError_t e = feti3(p, f, x, conj, tol, kmax, &its);
-    if (e == hipSuccess) e = launch_log3(p, c, (int)((p.map >> (8 * c)) & 255u), its);
-    if (e != hipSuccess) return fail(SFDP_E_DEVICE, std::string("3D FETI-DP: ") + hipGetErrorString(e));
-  }
+  int its[NRMAX] = {};
+  hipError_t e = feti3(p, p.nr, dev_vec(d, fsel), dev_vec(d, xsel), conj, tol, kmax, its);
+  for (int c = 0; c < p.nr && e == hipSuccess; ++c) e = launch_log3(p, c, (int)((p.map >> (8 * c)) & 255u), its[c]);
+  if (e != hipSuccess) return fail(SFDP_E_DEVICE, std::string("3D FETI-DP: ") + hipGetErrorString(e));
   return SFDP_OK;
 }
 

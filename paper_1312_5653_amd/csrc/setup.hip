@@ -579,11 +579,13 @@ __device__ inline void gj_load_d(cd* Dl, const cd* D, int b) {
 }
 // Entries outside the panel's rows and columns: workgroup (x, y) takes rows
 // GJ_RT y .. (+GJ_RT) and columns GJ_CT x .. (+GJ_CT).  U = A_iK D for its
-// rows and the panel rows A_Kj of its columns go to LDS; thread (half, column)
-// then updates 8 rows of one column: A_ij -= U_i A_Kj.
+// rows goes to LDS; thread (half, column) then updates 8 rows of one column,
+// A_ij -= U_i A_Kj, reading the panel rows A_Kj of its column straight from
+// memory (shared by every row block, so mostly cache hits; eight loads in
+// flight).  32 KB of LDS lets several workgroups share a CU.
 __global__ void __launch_bounds__(256) k_gj_rows(int n, int k0, int b, cd* A, const cd* D, size_t sA,
                                                  size_t sD) {
-  __shared__ cd Dl[GJ_PB * GJ_PB], Ul[GJ_RT * GJ_PB], Ak[GJ_RT * GJ_PB], Ck[GJ_PB * GJ_CT];
+  __shared__ cd Dl[GJ_PB * GJ_PB], Ul[GJ_RT * GJ_PB], Ak[GJ_RT * GJ_PB];
   A += blockIdx.z * sA;
   D += blockIdx.z * sD;
   const int i0 = blockIdx.y * GJ_RT, j0 = blockIdx.x * GJ_CT;
@@ -602,10 +604,6 @@ __global__ void __launch_bounds__(256) k_gj_rows(int n, int k0, int b, cd* A, co
     const bool in = r < nr && c < b && (i < k0 || i >= k0 + b);
     Ak[t] = in ? A[(size_t)i * n + k0 + c] : cd{0.0, 0.0};
   }
-  for (int t = threadIdx.x; t < GJ_PB * GJ_CT; t += blockDim.x) {
-    const int q = t / GJ_CT, jq = j0 + t % GJ_CT;
-    Ck[t] = (q < b && jq < n) ? A[(size_t)(k0 + q) * n + jq] : cd{0.0, 0.0};
-  }
   __syncthreads();
   for (int t = threadIdx.x; t < GJ_RT * GJ_PB; t += blockDim.x) {
     const int r = t / GJ_PB, c = t % GJ_PB;
@@ -615,10 +613,15 @@ __global__ void __launch_bounds__(256) k_gj_rows(int n, int k0, int b, cd* A, co
   }
   __syncthreads();
   if (!active) return;
-  for (int q = 0; q < b; ++q) {
-    const cd ck = Ck[q * GJ_CT + cc];
+  const cd* Ak0 = A + (size_t)k0 * n + j;  // A_Kj, q-th at Ak0 + q n
+  for (int q0 = 0; q0 < b; q0 += 8) {
+    cd ck[8];
 #pragma unroll
-    for (int rr = 0; rr < 8; ++rr) v[rr] = v[rr] - Ul[(half * 8 + rr) * GJ_PB + q] * ck;
+    for (int u = 0; u < 8; ++u) ck[u] = q0 + u < b ? Ak0[(size_t)(q0 + u) * n] : cd{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) v[rr] = v[rr] - Ul[(half * 8 + rr) * GJ_PB + q0 + u] * ck[u];
   }
 #pragma unroll
   for (int rr = 0; rr < 8; ++rr) {

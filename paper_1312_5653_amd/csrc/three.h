@@ -90,12 +90,16 @@ struct Three {
   // factors (storage precision for Zinv, Sinv, Sbb, Phi)
   void *Zinv = nullptr, *Sinv = nullptr, *Sbb = nullptr, *Phi = nullptr;
   cd *PhiFull = nullptr, *Zcc = nullptr;
-  // solve workspaces (FP64 complex): local vectors, interface and coarse vectors,
-  // Krylov basis (kalloc + 1 vectors) and reduction buffers
+  // solve workspaces (FP64 complex), NRMAX r-major copies: local vectors,
+  // interface and coarse vectors, Krylov basis (kalloc + 1 vectors each) and
+  // reduction buffers; hd holds per right-hand side the two Gram-Schmidt
+  // coefficient sets and the squared norm (2 (kalloc + 1) + 1 entries)
   cd *T = nullptr, *Y = nullptr, *Wc = nullptr, *fcs = nullptr, *uc = nullptr, *gc = nullptr, *d = nullptr,
      *mu = nullptr, *z = nullptr, *w = nullptr, *V = nullptr, *part = nullptr, *hd = nullptr;
   double* npart = nullptr;
-  cd* hh = nullptr;  // pinned host copy of hd
+  cd* hh = nullptr;    // pinned host copy of hd
+  int* nvd = nullptr;  // basis lengths of the final combination (device, pinned host)
+  int* nvh = nullptr;
   int kalloc = 0;
   Maps3 maps() const { return Maps3{rl, rpos, nds, dmu, dsg, muown, cg, cown}; }
 };
@@ -103,9 +107,9 @@ struct Three {
 // ---- launchers (three.hip) ----
 // set-up of a 3D problem: E (FP64 scratch, nsub NR^2) and work (nsub 2 GJ_PB^2)
 hipError_t launch_setup3(Problem& p, cd* E, cd* work);
-// one FETI-DP solve per right-hand side: x = Z^-1 f (conj: x = conj(Z^-1 conj f));
-// its: GMRES iterations (host)
-hipError_t feti3(Problem& p, const cd* f, cd* x, int conj, double tol, int kmax, int* its);
+// FETI-DP solves of nr <= NRMAX right-hand sides together (f, x with stride
+// n_free): x = Z^-1 f (conj: x = conj(Z^-1 conj f)); its[r]: GMRES iterations
+hipError_t feti3(Problem& p, int nr, const cd* f, cd* x, int conj, double tol, int kmax, int* its);
 // interface products for testing: 'F' F_DP x, 'P' preconditioner, 'D' d for
 // the right-hand side x (a complex free-node vector)
 hipError_t interface3(Problem& p, char which, const cd* x, cd* y);

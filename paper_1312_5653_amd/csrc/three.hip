@@ -191,9 +191,54 @@ hipError_t launch_setup3(Problem& p, cd* E, cd* work) {
 }
 
 // ----------------------------------------------------------------- solve --
+//
+// Up to R3 = NRMAX right-hand sides run together: per-subdomain kernels read
+// each operator once for all of them (R3 accumulators per row), vector kernels
+// take the right-hand side from blockIdx.y.  Buffers are r-major with the
+// strides of Str3.
+constexpr int R3 = NRMAX;
 
-// Local right-hand side at r position p: f / mult (conj: of conj f); mode 1
-// subtracts Z_rc B_c u_c and B_r^T mu.
+struct Str3 {
+  int64_t f;    // free-node vectors (input f, output x)
+  int64_t t;    // local r vectors T: nsub NR
+  int64_t y;    // local Delta vectors Y: nsub ND
+  int64_t w;    // corner terms Wc: nsub 8
+  int64_t c;    // coarse vectors: nC
+  int64_t mu;   // interface vectors: nmu
+};
+
+// Row i of the symmetric matrix A (n x n, leading dimension ld, read as column
+// i: coalesced over i) against the R3 vectors xs[k][r] (LDS): U entries are
+// loaded before they are used, so each thread keeps U loads in flight (more
+// registers: the sweep, with more rows per workgroup, keeps U = 2).
+template <int U, class TS>
+__device__ inline void symcol_r3(const TS* __restrict__ A, int ld, int n, int i, const cd* xs, cd (&out)[R3]) {
+  cd a[2][R3];
+#pragma unroll
+  for (int r = 0; r < R3; ++r) a[0][r] = a[1][r] = cd{0.0, 0.0};
+  int k = 0;
+  for (; k + U - 1 < n; k += U) {
+    TS z[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) z[u] = A[(size_t)(k + u) * ld + i];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const cd zu = ld64(z[u]);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) fma_acc(a[u & 1][r], zu, xs[(k + u) * R3 + r]);
+    }
+  }
+  for (; k < n; ++k) {
+    const cd zu = ld64(A[(size_t)k * ld + i]);
+#pragma unroll
+    for (int r = 0; r < R3; ++r) fma_acc(a[0][r], zu, xs[k * R3 + r]);
+  }
+#pragma unroll
+  for (int r = 0; r < R3; ++r) out[r] = a[0][r] + a[1][r];
+}
+
+// Local right-hand side at r position p for right-hand side r: f / mult
+// (conj: of conj f); mode 1 subtracts Z_rc B_c u_c and B_r^T mu.
 __device__ inline cd local_rhs(const Geo3& g, const Maps3& mp, int s, int p, const cd* f, int conj, int mode,
                                const cd* uc, const cd* mu) {
   const int l = mp.rl[s * g.NR + p];
@@ -221,139 +266,171 @@ __device__ inline cd local_rhs(const Geo3& g, const Maps3& mp, int s, int p, con
   return v;
 }
 
-// Full sweep T_s = Z_rr^-1 f~_s (one workgroup per subdomain, a thread per row;
-// Z_rr^-1 is symmetric, so row i is read as column i: coalesced).  mode 0 also
-// gives the subdomain's corner terms Wc[s][q] = f_q / 8 - (Phi^T f~)_q of f_c*.
+// Full sweeps T_s,r = Z_rr^-1 f~_s,r (one workgroup per subdomain, a thread
+// per row; Z_rr^-1 is symmetric, so row i is read as column i: coalesced, and
+// once for all nr right-hand sides).  mode 0 also gives the subdomain's corner
+// terms Wc[s][q] = f_q / 8 - (Phi^T f~)_q of f_c*.
 template <class TS>
-__global__ void __launch_bounds__(1024) k3_sweep(Geo3 g, Maps3 mp, const TS* __restrict__ Zinv,
+__global__ void __launch_bounds__(1024) k3_sweep(Geo3 g, Maps3 mp, Str3 st, int nr, const TS* __restrict__ Zinv,
                                                  const cd* PhiFull, const cd* f, int conj, int mode,
                                                  const cd* uc, const cd* mu, cd* T, cd* Wc) {
-  extern __shared__ cd ft[];
+  extern __shared__ cd ft[];  // [NR][R3]
   const int s = blockIdx.x, NR = g.NR;
-  for (int p = threadIdx.x; p < NR; p += blockDim.x) ft[p] = local_rhs(g, mp, s, p, f, conj, mode, uc, mu);
+  for (int t = threadIdx.x; t < NR * R3; t += blockDim.x) {
+    const int p = t / R3, r = t % R3;
+    ft[t] = r < nr ? local_rhs(g, mp, s, p, f + r * st.f, conj, mode, uc + r * st.c, mu + r * st.mu)
+                   : cd{0.0, 0.0};
+  }
   __syncthreads();
   const TS* Z = Zinv + (size_t)s * NR * NR;
   for (int i = threadIdx.x; i < NR; i += blockDim.x) {
-    cd a0{0.0, 0.0}, a1{0.0, 0.0}, a2{0.0, 0.0}, a3{0.0, 0.0};
-    int k = 0;
-    for (; k + 3 < NR; k += 4) {
-      fma_acc(a0, ld64(Z[(size_t)k * NR + i]), ft[k]);
-      fma_acc(a1, ld64(Z[(size_t)(k + 1) * NR + i]), ft[k + 1]);
-      fma_acc(a2, ld64(Z[(size_t)(k + 2) * NR + i]), ft[k + 2]);
-      fma_acc(a3, ld64(Z[(size_t)(k + 3) * NR + i]), ft[k + 3]);
-    }
-    for (; k < NR; ++k) fma_acc(a0, ld64(Z[(size_t)k * NR + i]), ft[k]);
-    T[(size_t)s * NR + i] = (a0 + a1) + (a2 + a3);
+    cd y[R3];
+    symcol_r3<2>(Z, NR, NR, i, ft, y);
+#pragma unroll
+    for (int r = 0; r < R3; ++r)
+      if (r < nr) T[r * st.t + (size_t)s * NR + i] = y[r];
   }
   if (mode == 0) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (wv < 8) {
       const int q = wv;
-      cd acc{0.0, 0.0};
-      for (int p = lane; p < NR; p += 64) fma_acc(acc, PhiFull[((size_t)s * NR + p) * 8 + q], ft[p]);
-      acc = wsum(acc);
+      cd acc[R3];
+#pragma unroll
+      for (int r = 0; r < R3; ++r) acc[r] = cd{0.0, 0.0};
+      for (int p = lane; p < NR; p += 64) {
+        const cd ph = PhiFull[((size_t)s * NR + p) * 8 + q];
+#pragma unroll
+        for (int r = 0; r < R3; ++r) fma_acc(acc[r], ph, ft[p * R3 + r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R3; ++r) acc[r] = wsum(acc[r]);
       if (lane == 0) {
-        cd v{0.0, 0.0};
-        if (mp.cg[s * 8 + q] >= 0) {
-          int a, b, c;
-          g.loc(g.vertex(q), a, b, c);
-          cd fv = f[g.freeidx(s, a, b, c)];
-          if (conj) fv.y = -fv.y;
-          v = 0.125 * fv - acc;  // a vertex is shared by 8 subdomains
+        const bool corner = mp.cg[s * 8 + q] >= 0;
+        int a = 0, b = 0, c = 0;
+        g.loc(g.vertex(q), a, b, c);
+#pragma unroll
+        for (int r = 0; r < R3; ++r) {
+          if (r >= nr) continue;
+          cd v{0.0, 0.0};
+          if (corner) {
+            cd fv = f[r * st.f + g.freeidx(s, a, b, c)];
+            if (conj) fv.y = -fv.y;
+            v = 0.125 * fv - acc[r];  // a vertex is shared by 8 subdomains
+          }
+          Wc[r * st.w + s * 8 + q] = v;
         }
-        Wc[s * 8 + q] = v;
       }
     }
   }
 }
 
-// Interface product on one subdomain: xs = B_r^T x on its Delta nodes (scaled
-// by 1 / multiplicity when `scale`), Y_s = Mat xs, Wc_s = Phi^T xs.
+// Interface product on one subdomain for nr right-hand sides: xs = B_r^T x on
+// its Delta nodes (scaled by 1 / multiplicity when `scale`), Y_s = Mat xs,
+// Wc_s = Phi^T xs; Mat is read once for all of them.
 template <class TS>
-__global__ void __launch_bounds__(1024) k3_local(Geo3 g, Maps3 mp, const TS* __restrict__ Mat,
-                                                 const TS* __restrict__ Phi, int scale, const cd* x, cd* Y,
-                                                 cd* Wc) {
-  extern __shared__ cd xs[];
+__global__ void __launch_bounds__(1024) k3_local(Geo3 g, Maps3 mp, Str3 st, int nr, const TS* __restrict__ Mat,
+                                                 const TS* __restrict__ Phi, int scale, const cd* x, int64_t xr,
+                                                 cd* Y, cd* Wc) {
+  extern __shared__ cd xs[];  // [ND][R3]
   const int s = blockIdx.x, ND = g.ND, nd = mp.nds[s];
   for (int i = threadIdx.x; i < ND; i += blockDim.x) {
-    cd v{0.0, 0.0};
+    cd v[R3];
+#pragma unroll
+    for (int r = 0; r < R3; ++r) v[r] = cd{0.0, 0.0};
     if (i < nd) {
       const int base = (s * ND + i) * 3;
       for (int j = 0; j < 3; ++j) {
         const int k = mp.dmu[base + j];
-        if (k >= 0) v = v + (double)mp.dsg[base + j] * x[k];
+        if (k < 0) continue;
+        const double sg = mp.dsg[base + j];
+#pragma unroll
+        for (int r = 0; r < R3; ++r)
+          if (r < nr) v[r] = v[r] + sg * x[r * xr + k];
       }
       if (scale) {
         int a, b, c;
         g.loc(mp.rl[s * g.NR + g.nI + i], a, b, c);
-        v = (1.0 / g.mult(a, b, c)) * v;
+        const double w = 1.0 / g.mult(a, b, c);
+#pragma unroll
+        for (int r = 0; r < R3; ++r) v[r] = w * v[r];
       }
     }
-    xs[i] = v;
+#pragma unroll
+    for (int r = 0; r < R3; ++r) xs[i * R3 + r] = v[r];
   }
   __syncthreads();
   if (Mat) {
     const TS* A = Mat + (size_t)s * ND * ND;
     for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-      cd a0{0.0, 0.0}, a1{0.0, 0.0}, a2{0.0, 0.0}, a3{0.0, 0.0};
-      int k = 0;
-      for (; k + 3 < nd; k += 4) {
-        fma_acc(a0, ld64(A[(size_t)k * ND + i]), xs[k]);
-        fma_acc(a1, ld64(A[(size_t)(k + 1) * ND + i]), xs[k + 1]);
-        fma_acc(a2, ld64(A[(size_t)(k + 2) * ND + i]), xs[k + 2]);
-        fma_acc(a3, ld64(A[(size_t)(k + 3) * ND + i]), xs[k + 3]);
-      }
-      for (; k < nd; ++k) fma_acc(a0, ld64(A[(size_t)k * ND + i]), xs[k]);
-      Y[(size_t)s * ND + i] = (a0 + a1) + (a2 + a3);
+      cd y[R3];
+      symcol_r3<8>(A, ND, nd, i, xs, y);
+#pragma unroll
+      for (int r = 0; r < R3; ++r)
+        if (r < nr) Y[r * st.y + (size_t)s * ND + i] = y[r];
     }
   }
   if (Phi) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (wv < 8) {
-      cd acc{0.0, 0.0};
-      for (int i = lane; i < nd; i += 64) fma_acc(acc, ld64(Phi[((size_t)s * ND + i) * 8 + wv]), xs[i]);
-      acc = wsum(acc);
-      if (lane == 0) Wc[s * 8 + wv] = acc;
+      cd acc[R3];
+#pragma unroll
+      for (int r = 0; r < R3; ++r) acc[r] = cd{0.0, 0.0};
+      for (int i = lane; i < nd; i += 64) {
+        const cd ph = ld64(Phi[((size_t)s * ND + i) * 8 + wv]);
+#pragma unroll
+        for (int r = 0; r < R3; ++r) fma_acc(acc[r], ph, xs[i * R3 + r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R3; ++r) acc[r] = wsum(acc[r]);
+      if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < R3; ++r)
+          if (r < nr) Wc[r * st.w + s * 8 + wv] = acc[r];
+      }
     }
   }
 }
 
-// out[c] = add[c] + sum of Wc over the corner's owners (fixed order)
-__global__ void k3_corner_sum(int nC, const int* cown, const cd* Wc, const cd* add, cd* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// out[c] = add[c] + sum of Wc over the corner's owners (fixed order); r = blockIdx.y
+__global__ void k3_corner_sum(int nC, Str3 st, const int* cown, const cd* Wc, const cd* add, cd* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
   if (c >= nC) return;
-  cd acc = add ? add[c] : cd{0.0, 0.0};
+  cd acc = add ? add[r * st.c + c] : cd{0.0, 0.0};
   for (int o = 0; o < 8; ++o) {
     const int own = cown[c * 8 + o];
-    if (own >= 0) acc = acc + Wc[own];
+    if (own >= 0) acc = acc + Wc[r * st.w + own];
   }
-  out[c] = acc;
+  out[r * st.c + c] = acc;
 }
 
-// y = A x (n x n, FP64), one wave per row
-__global__ void k3_dense_mv(int n, const cd* A, const cd* x, cd* y) {
+// y_r = A x_r (n x n, FP64), one wave per row; r = blockIdx.y
+__global__ void k3_dense_mv(int n, int64_t stride, const cd* A, const cd* x, cd* y) {
   const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (row >= n) return;
+  x += blockIdx.y * stride;
   cd acc{0.0, 0.0};
   for (int j = lane; j < n; j += 64) fma_acc(acc, A[(size_t)row * n + j], x[j]);
   acc = wsum(acc);
-  if (lane == 0) y[row] = acc;
+  if (lane == 0) y[blockIdx.y * stride + row] = acc;
 }
 
-// Per multiplier k with owners (s+, d+) and (s-, d-):
-//   out_k = sc_k ((v+ ) - (v-)),  v = Y[s ystride + yoff + d] + phis (Phi_s[d] . u_c(B_c s))
-// with sc_k = 1 / multiplicity when `scale`, else 1.
+// Per multiplier k with owners (s+, d+) and (s-, d-), right-hand side r = blockIdx.y:
+//   out_k = sc_k (v+ - v-),  v = Y[s ystride + yoff + d] + phis (Phi_s[d] . u_c(B_c s))
+// with sc_k = 1 / multiplicity when `scale`, else 1.  Y has right-hand-side
+// stride yr, out stride orr.
 template <class TS>
-__global__ void k3_scatter(Geo3 g, Maps3 mp, const cd* Y, int ystride, int yoff, const TS* Phi, const cd* uc,
-                           double phis, int scale, cd* out) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k3_scatter(Geo3 g, Maps3 mp, Str3 st, const cd* Y, int64_t yr, int ystride, int yoff,
+                           const TS* Phi, const cd* uc, double phis, int scale, cd* out, int64_t orr) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
   if (k >= g.nmu) return;
+  Y += r * yr;
+  uc += r * st.c;
   cd acc{0.0, 0.0};
   int own = 0;
   for (int side = 0; side < 2; ++side) {
     own = mp.muown[2 * k + side];
     const int s = own / g.ND, dl = own % g.ND;
-    cd v = Y ? Y[(size_t)s * ystride + yoff + dl] : cd{0.0, 0.0};
+    cd v = Y[(size_t)s * ystride + yoff + dl];
     if (Phi) {
       cd pc{0.0, 0.0};
       for (int q = 0; q < 8; ++q) {
@@ -370,15 +447,18 @@ __global__ void k3_scatter(Geo3 g, Maps3 mp, const cd* Y, int ystride, int yoff,
     g.loc(mp.rl[s * g.NR + g.nI + dl], a, b, c);
     acc = (1.0 / g.mult(a, b, c)) * acc;
   }
-  out[k] = acc;
+  out[r * orr + k] = acc;
 }
 
 // Primal solution on the free nodes: corners from u_c, every other node the
-// average of its subdomain copies (conj: conjugated)
-__global__ void k3_assemble(Geo3 g, Maps3 mp, const cd* T, const cd* uc, int conj, cd* x) {
+// average of its subdomain copies (conj: conjugated); r = blockIdx.y
+__global__ void k3_assemble(Geo3 g, Maps3 mp, Str3 st, const cd* T, const cd* uc, int conj, cd* x) {
   const int64_t n1 = g.N - 1;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n1 * n1 * n1) return;
+  const int r = blockIdx.y;
+  T += r * st.t;
+  uc += r * st.c;
   const int gi = (int)(t % n1) + 1, gj = (int)((t / n1) % n1) + 1, gk = (int)(t / (n1 * n1)) + 1;
   const int m = g.m, P = g.P;
   cd v{0.0, 0.0};
@@ -401,14 +481,20 @@ __global__ void k3_assemble(Geo3 g, Maps3 mp, const cd* T, const cd* uc, int con
     v = (1.0 / cnt) * v;
   }
   if (conj) v.y = -v.y;
-  x[t] = v;
+  x[r * st.f + t] = v;
 }
 
-// ---- Krylov vector kernels (length n, FP64 complex) ----
+// ---- Krylov vector kernels (length n, FP64 complex; right-hand side r =
+// blockIdx.y: vectors at + r * vr, coefficients at + r * hr, partial sums at
+// + r * pr) ----
 // part[i * nb + block] = sum over the block's entries of conj(V_i) w, i < nv
-__global__ void __launch_bounds__(256) k3_dots(int64_t n, int nv, const cd* V, int64_t vs, const cd* w,
-                                               cd* part) {
+__global__ void __launch_bounds__(256) k3_dots(int64_t n, int nv, const cd* V, int64_t vs, int64_t vr,
+                                               const cd* w, int64_t wr, cd* part, int64_t pr) {
   __shared__ cd sh[4];
+  const int r = blockIdx.y;
+  V += r * vr;
+  w += r * wr;
+  part += r * pr;
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const cd wv = t < n ? w[t] : cd{0.0, 0.0};
   const int lane = threadIdx.x & 63, wi = threadIdx.x >> 6;
@@ -422,10 +508,11 @@ __global__ void __launch_bounds__(256) k3_dots(int64_t n, int nv, const cd* V, i
     __syncthreads();
   }
 }
-// h[i] = sum_b part[i * nb + b] in a fixed order (one block per i)
-__global__ void __launch_bounds__(256) k3_reduce(int nb, const cd* part, cd* h) {
+// h[i] = sum_b part[i * nb + b] in a fixed order (block x = i, y = r)
+__global__ void __launch_bounds__(256) k3_reduce(int nb, const cd* part, int64_t pr, cd* h, int64_t hr) {
   __shared__ cd sh[256];
-  const int i = blockIdx.x;
+  const int i = blockIdx.x, r = blockIdx.y;
+  part += r * pr;
   cd a{0.0, 0.0};
   for (int b = threadIdx.x; b < nb; b += 256) a = a + part[(int64_t)i * nb + b];
   sh[threadIdx.x] = a;
@@ -434,12 +521,17 @@ __global__ void __launch_bounds__(256) k3_reduce(int nb, const cd* part, cd* h) 
     if ((int)threadIdx.x < off) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) h[i] = sh[0];
+  if (threadIdx.x == 0) h[r * hr + i] = sh[0];
 }
 // w -= sum_i h[i] V_i ; npart[block] = sum |w|^2 over the block
-__global__ void __launch_bounds__(256) k3_axpy(int64_t n, int nv, const cd* V, int64_t vs, const cd* h, cd* w,
-                                               double* npart) {
+__global__ void __launch_bounds__(256) k3_axpy(int64_t n, int nv, const cd* V, int64_t vs, int64_t vr,
+                                               const cd* h, int64_t hr, cd* w, int64_t wr, double* npart,
+                                               int64_t nr_) {
   __shared__ double sh[4];
+  const int r = blockIdx.y;
+  V += r * vr;
+  h += r * hr;
+  w += r * wr;
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double q = 0.0;
   if (t < n) {
@@ -451,215 +543,42 @@ __global__ void __launch_bounds__(256) k3_axpy(int64_t n, int nv, const cd* V, i
   q = wsum(q);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = q;
   __syncthreads();
-  if (threadIdx.x == 0) npart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  if (threadIdx.x == 0) npart[r * nr_ + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
-// out[0] = sum of npart[0 .. nb) in a fixed order
-__global__ void __launch_bounds__(256) k3_sum(int nb, const double* npart, double* out) {
+// out[r * hr] = sum of npart[r * pr + 0 .. nb) in a fixed order (as a double)
+__global__ void __launch_bounds__(256) k3_sum(int nb, const double* npart, int64_t pr, cd* out, int64_t hr) {
   __shared__ double sh[256];
+  const int r = blockIdx.x;
   double a = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 256) a += npart[b];
+  for (int b = threadIdx.x; b < nb; b += 256) a += npart[r * pr + b];
   sh[threadIdx.x] = a;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sh[0];
+  if (threadIdx.x == 0) out[r * hr] = cd{sh[0], 0.0};
 }
-// v = w / sqrt(nrm[0]) (zero when the norm is zero)
-__global__ void k3_normalize(int64_t n, const cd* w, const double* nrm, cd* v) {
+// v = w / sqrt(nrm) (zero when the norm is zero); nrm of r at nrm + r * hr
+__global__ void k3_normalize(int64_t n, const cd* w, int64_t wr, const cd* nrm, int64_t hr, cd* v, int64_t vr) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
   if (t >= n) return;
-  const double r = nrm[0] > 0.0 ? 1.0 / sqrt(nrm[0]) : 0.0;
-  v[t] = r * w[t];
+  const double q = nrm[r * hr].x;
+  const double s = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+  v[r * vr + t] = s * w[r * wr + t];
 }
-// out = sum_i y[i] V_i
-__global__ void k3_combine(int64_t n, int nv, const cd* V, int64_t vs, const cd* y, cd* out) {
+// out = sum_{i < nv[r]} y[i] V_i
+__global__ void k3_combine(int64_t n, const int* nv, const cd* V, int64_t vs, int64_t vr, const cd* y,
+                           int64_t hr, cd* out, int64_t orr) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
   if (t >= n) return;
+  V += r * vr;
+  y += r * hr;
   cd a{0.0, 0.0};
-  for (int i = 0; i < nv; ++i) fma_acc(a, y[i], V[i * vs + t]);
-  out[t] = a;
-}
-
-namespace {
-
-struct Ops3 {
-  Problem& p;
-  Three& T;
-  Geo3 g;
-  Maps3 mp;
-  hipStream_t st;
-  bool s32;
-  unsigned threads_local, threads_sweep;
-  explicit Ops3(Problem& pp)
-      : p(pp), T(*pp.t3), g(pp.t3->g), mp(pp.t3->maps()), st(pp.ctx->stream), s32(pp.s32()) {
-    threads_local = (unsigned)std::min(1024, std::max(512, (g.ND + 63) / 64 * 64));
-    threads_sweep = (unsigned)std::min(1024, std::max(512, (g.NR + 63) / 64 * 64));
-  }
-  template <class TS>
-  void local_t(const void* Mat, const void* Phi, int scale, const cd* x, cd* Y, cd* Wc) {
-    hipLaunchKernelGGL(k3_local<TS>, dim3(g.nsub), dim3(threads_local), sizeof(cd) * g.ND, st, g, mp,
-                       (const TS*)Mat, (const TS*)Phi, scale, x, Y, Wc);
-  }
-  void local(const void* Mat, const void* Phi, int scale, const cd* x, cd* Y, cd* Wc) {
-    if (s32) local_t<cf>(Mat, Phi, scale, x, Y, Wc);
-    else local_t<cd>(Mat, Phi, scale, x, Y, Wc);
-  }
-  void scatter(const cd* Y, int ystride, int yoff, bool phi, const cd* uc, double phis, int scale, cd* out) {
-    const unsigned nb = nb256(g.nmu);
-    if (s32)
-      hipLaunchKernelGGL(k3_scatter<cf>, dim3(nb), dim3(256), 0, st, g, mp, Y, ystride, yoff,
-                         phi ? (const cf*)T.Phi : (const cf*)nullptr, uc, phis, scale, out);
-    else
-      hipLaunchKernelGGL(k3_scatter<cd>, dim3(nb), dim3(256), 0, st, g, mp, Y, ystride, yoff,
-                         phi ? (const cd*)T.Phi : (const cd*)nullptr, uc, phis, scale, out);
-  }
-  void sweep(const cd* f, int conj, int mode) {
-    const size_t lds = sizeof(cd) * g.NR;
-    if (s32)
-      hipLaunchKernelGGL(k3_sweep<cf>, dim3(g.nsub), dim3(threads_sweep), lds, st, g, mp, (const cf*)T.Zinv,
-                         (const cd*)T.PhiFull, f, conj, mode, (const cd*)T.uc, (const cd*)T.mu, T.T, T.Wc);
-    else
-      hipLaunchKernelGGL(k3_sweep<cd>, dim3(g.nsub), dim3(threads_sweep), lds, st, g, mp, (const cd*)T.Zinv,
-                         (const cd*)T.PhiFull, f, conj, mode, (const cd*)T.uc, (const cd*)T.mu, T.T, T.Wc);
-  }
-  // uc = K_cc*^-1 (add + sum of Wc)
-  void coarse(const cd* add) {
-    hipLaunchKernelGGL(k3_corner_sum, dim3(nb256(g.nC)), dim3(256), 0, st, g.nC, (const int*)T.cown,
-                       (const cd*)T.Wc, add, T.gc);
-    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4), dim3(256), 0, st, g.nC, (const cd*)p.Kinv,
-                       (const cd*)T.gc, T.uc);
-  }
-  // out = F_DP x
-  void apply_F(const cd* x, cd* out) {
-    local(T.Sinv, T.Phi, 0, x, T.Y, T.Wc);
-    coarse(nullptr);
-    scatter(T.Y, g.ND, 0, true, T.uc, 1.0, 0, out);
-  }
-  // out = W B_r S_bb B_r^T W x
-  void apply_P(const cd* x, cd* out) {
-    local(T.Sbb, nullptr, 1, x, T.Y, nullptr);
-    scatter(T.Y, g.ND, 0, false, nullptr, 0.0, 1, out);
-  }
-  // d = sum B_r (Z_rr^-1 f_r)|Delta - F_rc K_cc*^-1 f_c*  (leaves f_c* in fcs)
-  void rhs(const cd* f, int conj) {
-    sweep(f, conj, 0);
-    hipLaunchKernelGGL(k3_corner_sum, dim3(nb256(g.nC)), dim3(256), 0, st, g.nC, (const int*)T.cown,
-                       (const cd*)T.Wc, (const cd*)nullptr, T.fcs);
-    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4), dim3(256), 0, st, g.nC, (const cd*)p.Kinv,
-                       (const cd*)T.fcs, T.uc);
-    scatter(T.T, g.NR, g.nI, true, T.uc, -1.0, 0, T.d);
-  }
-};
-
-// Right-preconditioned GMRES on F_DP mu = d from mu = 0 (relative residual tol
-// of the unpreconditioned system, at most kmax iterations).
-hipError_t gmres3(Ops3& o, double tol, int kmax, int* its) {
-  Three& T = o.T;
-  hipStream_t st = o.st;
-  const int64_t n = o.g.nmu, vs = n;
-  const unsigned nb = nb256(n);
-  const int ks = T.kalloc + 1;  // stride of the two coefficient sets in hd
-  cd* V = T.V;
-  double* dn = (double*)(T.hd + 2 * ks);
-  hipLaunchKernelGGL(k3_axpy, dim3(nb), dim3(256), 0, st, n, 0, (const cd*)V, vs, (const cd*)T.hd, T.d,
-                     T.npart);
-  hipLaunchKernelGGL(k3_sum, dim3(1), dim3(256), 0, st, (int)nb, (const double*)T.npart, dn);
-  hipError_t e = hipMemcpyAsync(T.hh, T.hd, sizeof(cd) * (2 * ks + 1), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return e;
-  const double beta = std::sqrt(((double*)(T.hh + 2 * ks))[0]);
-  *its = 0;
-  if (!(beta > 0.0)) {
-    hipLaunchKernelGGL(k3_combine, dim3(nb), dim3(256), 0, st, n, 0, (const cd*)V, vs, (const cd*)T.hd, T.mu);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k3_normalize, dim3(nb), dim3(256), 0, st, n, (const cd*)T.d, (const double*)dn, V);
-  using cx = std::complex<double>;
-  const int km = std::min(kmax, T.kalloc);
-  std::vector<cx> H((size_t)(km + 1) * km), cs(km), sn(km), gv(km + 1, cx(0.0));
-  gv[0] = beta;
-  int j = 0;
-  for (; j < km; ++j) {
-    cd* vj = V + (int64_t)j * vs;
-    cd* vn = V + (int64_t)(j + 1) * vs;
-    o.apply_P(vj, T.z);
-    o.apply_F(T.z, vn);
-    for (int pass = 0; pass < 2; ++pass) {
-      cd* h = T.hd + pass * ks;
-      hipLaunchKernelGGL(k3_dots, dim3(nb), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, (const cd*)vn, T.part);
-      hipLaunchKernelGGL(k3_reduce, dim3(j + 1), dim3(256), 0, st, (int)nb, (const cd*)T.part, h);
-      hipLaunchKernelGGL(k3_axpy, dim3(nb), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, (const cd*)h, vn,
-                         T.npart);
-    }
-    hipLaunchKernelGGL(k3_sum, dim3(1), dim3(256), 0, st, (int)nb, (const double*)T.npart, dn);
-    hipLaunchKernelGGL(k3_normalize, dim3(nb), dim3(256), 0, st, n, (const cd*)vn, (const double*)dn, vn);
-    e = hipMemcpyAsync(T.hh, T.hd, sizeof(cd) * (2 * ks + 1), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
-    // column j of the Hessenberg matrix, rotated by the previous rotations
-    cx* Hj = H.data() + (size_t)j * (km + 1);
-    for (int i = 0; i <= j; ++i) Hj[i] = cx(T.hh[i].x + T.hh[ks + i].x, T.hh[i].y + T.hh[ks + i].y);
-    const double hn = std::sqrt(((double*)(T.hh + 2 * ks))[0]);
-    for (int i = 0; i < j; ++i) {
-      const cx a = Hj[i], b = Hj[i + 1];
-      Hj[i] = cs[i] * a + sn[i] * b;
-      Hj[i + 1] = -std::conj(sn[i]) * a + cs[i] * b;
-    }
-    const cx a = Hj[j];
-    const double ra = std::abs(a), rho = std::sqrt(ra * ra + hn * hn);
-    if (ra == 0.0) {
-      cs[j] = 0.0;
-      sn[j] = 1.0;
-    } else {
-      cs[j] = ra / rho;
-      sn[j] = (a / ra) * hn / rho;
-    }
-    Hj[j] = cs[j] * a + sn[j] * hn;
-    gv[j + 1] = -std::conj(sn[j]) * gv[j];
-    gv[j] = cs[j] * gv[j];
-    if (std::abs(gv[j + 1]) <= tol * beta || !(hn > 0.0)) {
-      ++j;
-      break;
-    }
-  }
-  const int mk = j;
-  *its = mk;
-  // y = H^-1 g (upper triangular), mu = P^-1 (V y)
-  std::vector<cx> y(mk);
-  for (int i = mk - 1; i >= 0; --i) {
-    cx s = gv[i];
-    for (int c = i + 1; c < mk; ++c) s -= H[(size_t)c * (km + 1) + i] * y[c];
-    y[i] = s / H[(size_t)i * (km + 1) + i];
-  }
-  for (int i = 0; i < mk; ++i) T.hh[i] = cd{y[i].real(), y[i].imag()};
-  e = hipMemcpyAsync(T.hd, T.hh, sizeof(cd) * std::max(mk, 1), hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k3_combine, dim3(nb), dim3(256), 0, st, n, mk, (const cd*)V, vs, (const cd*)T.hd, T.w);
-  o.apply_P(T.w, T.mu);
-  // the host copy above must land before hh is reused
-  e = hipStreamSynchronize(st);
-  return e == hipSuccess ? hipGetLastError() : e;
-}
-
-}  // namespace
-
-hipError_t feti3(Problem& p, const cd* f, cd* x, int conj, double tol, int kmax, int* its) {
-  Ops3 o(p);
-  Three& T = o.T;
-  o.rhs(f, conj);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if ((e = gmres3(o, tol, kmax, its)) != hipSuccess) return e;
-  // u_c = K_cc*^-1 (f_c* + F_rc^T mu), u_r = Z_rr^-1 (f_r - Z_rc B_c u_c - B_r^T mu)
-  o.local(nullptr, T.Phi, 0, T.mu, nullptr, T.Wc);
-  o.coarse(T.fcs);
-  o.sweep(f, conj, 1);
-  const int64_t n1 = o.g.N - 1;
-  hipLaunchKernelGGL(k3_assemble, dim3(nb256(n1 * n1 * n1)), dim3(256), 0, o.st, o.g, o.mp, (const cd*)T.T,
-                     (const cd*)T.uc, conj, x);
-  return hipGetLastError();
+  for (int i = 0; i < nv[r]; ++i) fma_acc(a, y[i], V[i * vs + t]);
+  out[r * orr + t] = a;
 }
 
 __global__ void k3_log(int* flags, int c, int q, int its) {
@@ -670,15 +589,228 @@ __global__ void k3_log(int* flags, int c, int q, int its) {
   flags[3] += its;
   flags[4] += its;
 }
+
+namespace {
+
+struct Ops3 {
+  Problem& p;
+  Three& T;
+  Geo3 g;
+  Maps3 mp;
+  Str3 sr;
+  hipStream_t st;
+  bool s32;
+  int nr;
+  unsigned threads_local, threads_sweep;
+  Ops3(Problem& pp, int nr_)
+      : p(pp), T(*pp.t3), g(pp.t3->g), mp(pp.t3->maps()), st(pp.ctx->stream), s32(pp.s32()), nr(nr_) {
+    threads_local = (unsigned)std::min(1024, std::max(512, (g.ND + 63) / 64 * 64));
+    threads_sweep = (unsigned)std::min(1024, std::max(512, (g.NR + 63) / 64 * 64));
+    sr = Str3{pp.n_free, (int64_t)g.nsub * g.NR, (int64_t)g.nsub * g.ND, (int64_t)g.nsub * 8,
+              (int64_t)std::max(g.nC, 1), (int64_t)g.nmu};
+  }
+  template <class TS>
+  void local_t(const void* Mat, const void* Phi, int scale, const cd* x, int64_t xr, cd* Y, cd* Wc) {
+    hipLaunchKernelGGL(k3_local<TS>, dim3(g.nsub), dim3(threads_local), sizeof(cd) * g.ND * R3, st, g, mp, sr,
+                       nr, (const TS*)Mat, (const TS*)Phi, scale, x, xr, Y, Wc);
+  }
+  void local(const void* Mat, const void* Phi, int scale, const cd* x, int64_t xr, cd* Y, cd* Wc) {
+    if (s32) local_t<cf>(Mat, Phi, scale, x, xr, Y, Wc);
+    else local_t<cd>(Mat, Phi, scale, x, xr, Y, Wc);
+  }
+  void scatter(const cd* Y, int64_t yr, int ystride, int yoff, bool phi, double phis, int scale, cd* out,
+               int64_t orr) {
+    const dim3 grid(nb256(g.nmu), nr);
+    if (s32)
+      hipLaunchKernelGGL(k3_scatter<cf>, grid, dim3(256), 0, st, g, mp, sr, Y, yr, ystride, yoff,
+                         phi ? (const cf*)T.Phi : (const cf*)nullptr, (const cd*)T.uc, phis, scale, out, orr);
+    else
+      hipLaunchKernelGGL(k3_scatter<cd>, grid, dim3(256), 0, st, g, mp, sr, Y, yr, ystride, yoff,
+                         phi ? (const cd*)T.Phi : (const cd*)nullptr, (const cd*)T.uc, phis, scale, out, orr);
+  }
+  void sweep(const cd* f, int conj, int mode) {
+    const size_t lds = sizeof(cd) * g.NR * R3;
+    if (s32)
+      hipLaunchKernelGGL(k3_sweep<cf>, dim3(g.nsub), dim3(threads_sweep), lds, st, g, mp, sr, nr, (const cf*)T.Zinv,
+                         (const cd*)T.PhiFull, f, conj, mode, (const cd*)T.uc, (const cd*)T.mu, T.T, T.Wc);
+    else
+      hipLaunchKernelGGL(k3_sweep<cd>, dim3(g.nsub), dim3(threads_sweep), lds, st, g, mp, sr, nr, (const cd*)T.Zinv,
+                         (const cd*)T.PhiFull, f, conj, mode, (const cd*)T.uc, (const cd*)T.mu, T.T, T.Wc);
+  }
+  // out = K_cc*^-1 (add + sum of Wc)
+  void coarse(const cd* add, cd* out) {
+    hipLaunchKernelGGL(k3_corner_sum, dim3(nb256(g.nC), nr), dim3(256), 0, st, g.nC, sr, (const int*)T.cown,
+                       (const cd*)T.Wc, add, T.gc);
+    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4, nr), dim3(256), 0, st, g.nC, sr.c, (const cd*)p.Kinv,
+                       (const cd*)T.gc, out);
+  }
+  // out = F_DP x (x and out with right-hand-side strides xr, orr)
+  void apply_F(const cd* x, int64_t xr, cd* out, int64_t orr) {
+    local(T.Sinv, T.Phi, 0, x, xr, T.Y, T.Wc);
+    coarse(nullptr, T.uc);
+    scatter(T.Y, sr.y, g.ND, 0, true, 1.0, 0, out, orr);
+  }
+  // out = W B_r S_bb B_r^T W x
+  void apply_P(const cd* x, int64_t xr, cd* out, int64_t orr) {
+    local(T.Sbb, nullptr, 1, x, xr, T.Y, nullptr);
+    scatter(T.Y, sr.y, g.ND, 0, false, 0.0, 1, out, orr);
+  }
+  // d = sum B_r (Z_rr^-1 f_r)|Delta - F_rc K_cc*^-1 f_c*  (leaves f_c* in fcs)
+  void rhs(const cd* f, int conj) {
+    sweep(f, conj, 0);
+    hipLaunchKernelGGL(k3_corner_sum, dim3(nb256(g.nC), nr), dim3(256), 0, st, g.nC, sr, (const int*)T.cown,
+                       (const cd*)T.Wc, (const cd*)nullptr, T.fcs);
+    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4, nr), dim3(256), 0, st, g.nC, sr.c, (const cd*)p.Kinv,
+                       (const cd*)T.fcs, T.uc);
+    scatter(T.T, sr.t, g.NR, g.nI, true, -1.0, 0, T.d, sr.mu);
+  }
+};
+
+// Right-preconditioned GMRES on F_DP mu_r = d_r from mu = 0 for the nr
+// right-hand sides together (relative residual tol of the unpreconditioned
+// system, at most kmax iterations each).  Every right-hand side keeps its own
+// basis, Hessenberg matrix and stopping test; one that has stopped still rides
+// along in the shared launches, but its later vectors are never used, so its
+// result is that of a solve on its own.
+hipError_t gmres3(Ops3& o, double tol, int kmax, int* its) {
+  Three& T = o.T;
+  hipStream_t st = o.st;
+  const int nr = o.nr;
+  const int64_t n = o.g.nmu, vs = n;
+  const unsigned nb = nb256(n);
+  const int ks = T.kalloc + 1;       // stride of the two coefficient sets in a right-hand side's hd
+  const int64_t hr = 2 * ks + 1;     // hd per right-hand side: h (pass 0), h (pass 1), squared norm
+  const int64_t vr = (int64_t)ks * n, pr = (int64_t)ks * nb;
+  cd* V = T.V;
+  cd* dn = T.hd + 2 * ks;            // squared norm of right-hand side r at dn[r * hr]
+  auto sync_h = [&]() {
+    hipError_t e = hipMemcpyAsync(T.hh, T.hd, sizeof(cd) * hr * nr, hipMemcpyDeviceToHost, st);
+    return e == hipSuccess ? hipStreamSynchronize(st) : e;
+  };
+  hipLaunchKernelGGL(k3_axpy, dim3(nb, nr), dim3(256), 0, st, n, 0, (const cd*)V, vs, vr, (const cd*)T.hd, hr,
+                     T.d, n, T.npart, (int64_t)nb);
+  hipLaunchKernelGGL(k3_sum, dim3(nr), dim3(256), 0, st, (int)nb, (const double*)T.npart, (int64_t)nb, dn, hr);
+  hipLaunchKernelGGL(k3_normalize, dim3(nb, nr), dim3(256), 0, st, n, (const cd*)T.d, n, (const cd*)dn, hr, V, vr);
+  hipError_t e = sync_h();
+  if (e != hipSuccess) return e;
+  using cx = std::complex<double>;
+  const int km = std::min(kmax, T.kalloc);
+  std::vector<std::vector<cx>> H(nr), cs(nr), sn(nr), gv(nr);
+  std::vector<double> beta(nr);
+  std::vector<int> done(nr, 0), mk(nr, 0);
+  int ndone = 0;
+  for (int r = 0; r < nr; ++r) {
+    H[r].assign((size_t)(km + 1) * km, 0.0);
+    cs[r].assign(km, 0.0);
+    sn[r].assign(km, 0.0);
+    gv[r].assign(km + 1, 0.0);
+    beta[r] = std::sqrt(T.hh[r * hr + 2 * ks].x);
+    gv[r][0] = beta[r];
+    if (!(beta[r] > 0.0)) {
+      done[r] = 1;
+      ++ndone;
+    }
+  }
+  for (int j = 0; j < km && ndone < nr; ++j) {
+    cd* vj = V + (int64_t)j * vs;
+    cd* vn = V + (int64_t)(j + 1) * vs;
+    o.apply_P(vj, vr, T.z, n);
+    o.apply_F(T.z, n, vn, vr);
+    for (int pass = 0; pass < 2; ++pass) {
+      cd* h = T.hd + pass * ks;
+      hipLaunchKernelGGL(k3_dots, dim3(nb, nr), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, vr, (const cd*)vn,
+                         vr, T.part, pr);
+      hipLaunchKernelGGL(k3_reduce, dim3(j + 1, nr), dim3(256), 0, st, (int)nb, (const cd*)T.part, pr, h, hr);
+      hipLaunchKernelGGL(k3_axpy, dim3(nb, nr), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, vr, (const cd*)h, hr,
+                         vn, vr, T.npart, (int64_t)nb);
+    }
+    hipLaunchKernelGGL(k3_sum, dim3(nr), dim3(256), 0, st, (int)nb, (const double*)T.npart, (int64_t)nb, dn, hr);
+    hipLaunchKernelGGL(k3_normalize, dim3(nb, nr), dim3(256), 0, st, n, (const cd*)vn, vr, (const cd*)dn, hr, vn,
+                       vr);
+    if ((e = sync_h()) != hipSuccess) return e;
+    for (int r = 0; r < nr; ++r) {
+      if (done[r]) continue;
+      // column j of the Hessenberg matrix, rotated by the previous rotations
+      const cd* hh = T.hh + r * hr;
+      cx* Hj = H[r].data() + (size_t)j * (km + 1);
+      for (int i = 0; i <= j; ++i) Hj[i] = cx(hh[i].x + hh[ks + i].x, hh[i].y + hh[ks + i].y);
+      const double hn = std::sqrt(hh[2 * ks].x);
+      for (int i = 0; i < j; ++i) {
+        const cx a = Hj[i], b = Hj[i + 1];
+        Hj[i] = cs[r][i] * a + sn[r][i] * b;
+        Hj[i + 1] = -std::conj(sn[r][i]) * a + cs[r][i] * b;
+      }
+      const cx a = Hj[j];
+      const double ra = std::abs(a), rho = std::sqrt(ra * ra + hn * hn);
+      if (ra == 0.0) {
+        cs[r][j] = 0.0;
+        sn[r][j] = 1.0;
+      } else {
+        cs[r][j] = ra / rho;
+        sn[r][j] = (a / ra) * hn / rho;
+      }
+      Hj[j] = cs[r][j] * a + sn[r][j] * hn;
+      gv[r][j + 1] = -std::conj(sn[r][j]) * gv[r][j];
+      gv[r][j] = cs[r][j] * gv[r][j];
+      mk[r] = j + 1;
+      if (std::abs(gv[r][j + 1]) <= tol * beta[r] || !(hn > 0.0)) {
+        done[r] = 1;
+        ++ndone;
+      }
+    }
+  }
+  // y_r = H_r^-1 g_r (upper triangular), mu_r = P^-1 (V_r y_r)
+  for (int r = 0; r < nr; ++r) {
+    its[r] = mk[r];
+    std::vector<cx> y(mk[r]);
+    for (int i = mk[r] - 1; i >= 0; --i) {
+      cx s = gv[r][i];
+      for (int c = i + 1; c < mk[r]; ++c) s -= H[r][(size_t)c * (km + 1) + i] * y[c];
+      y[i] = s / H[r][(size_t)i * (km + 1) + i];
+    }
+    for (int i = 0; i < mk[r]; ++i) T.hh[r * hr + i] = cd{y[i].real(), y[i].imag()};
+    T.nvh[r] = mk[r];
+  }
+  e = hipMemcpyAsync(T.hd, T.hh, sizeof(cd) * hr * nr, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(T.nvd, T.nvh, sizeof(int) * nr, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k3_combine, dim3(nb, nr), dim3(256), 0, st, n, (const int*)T.nvd, (const cd*)V, vs, vr,
+                     (const cd*)T.hd, hr, T.w, n);
+  o.apply_P(T.w, n, T.mu, n);
+  // the host copies above must land before hh and nvh are reused
+  e = hipStreamSynchronize(st);
+  return e == hipSuccess ? hipGetLastError() : e;
+}
+
+}  // namespace
+
+hipError_t feti3(Problem& p, int nr, const cd* f, cd* x, int conj, double tol, int kmax, int* its) {
+  Ops3 o(p, nr);
+  Three& T = o.T;
+  o.rhs(f, conj);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = gmres3(o, tol, kmax, its)) != hipSuccess) return e;
+  // u_c = K_cc*^-1 (f_c* + F_rc^T mu), u_r = Z_rr^-1 (f_r - Z_rc B_c u_c - B_r^T mu)
+  o.local(nullptr, T.Phi, 0, T.mu, o.sr.mu, nullptr, T.Wc);
+  o.coarse(T.fcs, T.uc);
+  o.sweep(f, conj, 1);
+  const int64_t n1 = o.g.N - 1;
+  hipLaunchKernelGGL(k3_assemble, dim3(nb256(n1 * n1 * n1), nr), dim3(256), 0, o.st, o.g, o.mp, o.sr,
+                     (const cd*)T.T, (const cd*)T.uc, conj, x);
+  return hipGetLastError();
+}
+
 hipError_t launch_log3(Problem& p, int c, int q, int its) {
   hipLaunchKernelGGL(k3_log, dim3(1), dim3(1), 0, p.ctx->stream, p.flags, c, q, its);
   return hipGetLastError();
 }
 
 hipError_t interface3(Problem& p, char which, const cd* x, cd* y) {
-  Ops3 o(p);
-  if (which == 'F') o.apply_F(x, y);
-  else if (which == 'P') o.apply_P(x, y);
+  Ops3 o(p, 1);
+  const int64_t n = o.g.nmu;
+  if (which == 'F') o.apply_F(x, n, y, n);
+  else if (which == 'P') o.apply_P(x, n, y, n);
   else {
     o.rhs(x, 0);
     hipError_t e = hipMemcpyAsync(y, o.T.d, sizeof(cd) * o.g.nmu, hipMemcpyDeviceToDevice, o.st);

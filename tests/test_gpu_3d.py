@@ -166,3 +166,29 @@ def test_range_space_3d_subdomains_of_the_64_cube_shape(sf):
     print(f"3D 32^3 / 8^3 mixed: rho={rho:.2e} info={info[0]}")
     assert rho <= 1e-8
     prob.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_range_space_3d_grouping_invariance(sf, prec):
+    """Three targets solved one per group and all in one group (every operator
+    read once for the group; each right-hand side keeps its own Krylov basis,
+    Hessenberg matrix and stopping test): the same iterates, to 1e-12."""
+    sfdp, ctx = sf
+    N, m, beta = 12, 4, 1e-4
+    ybar = np.stack([_target(N, 10 + s)[0] for s in range(3)])
+    ybar[1] *= 1e3
+    prob = sfdp.Problem(ctx, 3, N, m, prec)
+    prob.set_beta(beta)
+    tol = 1e-10 if prec == 0 else 1e-8
+    runs = {}
+    for batch in (1, 4):
+        y, u, lam, info, st = prob.solve_range_space(_t(ybar), None, tol_kkt=tol, batch=batch)
+        assert st == 0, (batch, info)
+        runs[batch] = [v.cpu().numpy() for v in (y, u, lam)], info
+    (y1, u1, l1), i1 = runs[1]
+    (y4, u4, l4), i4 = runs[4]
+    for q in range(3):
+        for a, b in ((y4[q], y1[q]), (u4[q], u1[q]), (l4[q], l1[q])):
+            assert _rel(a, b) < 1e-12, q
+        assert i4[q]["krylov_its"] == i1[q]["krylov_its"], q
+    prob.close()
