@@ -24,7 +24,11 @@
  * n_elem^dim Q1 cells, unit conductivity, Dirichlet data on the whole
  * boundary, split into (n_elem / sub_elem)^dim subdomains of sub_elem^dim
  * cells each.  Supported: dim 2 with 2 <= sub_elem <= 32; dim 3 with
- * 2 <= sub_elem <= 8; n_elem % sub_elem == 0 and n_elem / sub_elem >= 2.
+ * 2 <= sub_elem <= 9 and at most 65535 subdomains; n_elem % sub_elem == 0
+ * and n_elem / sub_elem >= 2.  In 3D the corners are the subdomain vertices
+ * (no edge averages), a Delta node shared by k subdomains carries one
+ * multiplier per pair (fully redundant), and 3D problems are solved through
+ * the single-problem calls only (not sfdp_batch_* or the server).
  *
  * Dof numbering (all vectors):
  *   free node (i, j[, k]), 1 <= i, j, k <= n_elem - 1, has index
@@ -228,6 +232,8 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
  *                pair of adjacent subdomains);
  *   SFDP_Q_COARSE_INV : its inverse as used by the solves (Gauss-Jordan
  *                without pivoting, corners first);
+ * (3D: the same queries; the corners of SFDP_Q_PHI are the non-Dirichlet
+ * vertices of the subdomain in increasing local index.)
  * out may be NULL to query the shape only. */
 typedef enum { SFDP_Q_SINV = 0, SFDP_Q_SBB = 1, SFDP_Q_PHI = 2, SFDP_Q_COARSE = 3, SFDP_Q_COARSE_INV = 4 } sfdp_query;
 sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out, int* rows, int* cols);
