@@ -12,6 +12,9 @@ O2  ``reduced_saddle``: the 2n real saddle system left after eliminating u
 O3  ``dense_kkt``: numpy.linalg.solve of the full 3n system (tiny meshes).
 O4  ``closed_form_sines``: exact discrete solution for targets made of
     discrete sine modes, which are common eigenvectors of K and M.
+O5  ``full_space_minres``: the full-space method (Sec. 3.2): MINRES on the
+    KKT system with the block-diagonal preconditioner P_mgw = blkdiag(V,
+    phi V, S) of Murphy, Golub and Wathen, S^-1 by the two complex factors.
 """
 from __future__ import annotations
 
@@ -165,3 +168,71 @@ def closed_form_sines(mesh, beta: float, modes, coefs):
         y += a * (muM ** 2 / beta) / den * s
         w += a * muK / (muK + 1j * alpha * muM) * s
     return {"y": y, "u": lam / beta, "lam": lam, "w": w}
+
+
+def schur_inverse_two_factor(lu, M, r):
+    """S^-1 r for real r by the complex factorization (Sec. 4): with
+    S = Z M^-1 conj(Z), S^-1 = conj(Z)^-1 M Z^-1, and for real r the result
+    is real: conj(Z^-1 conj(M Z^-1 r)) taken with the LU of Z."""
+    w = lu.solve(np.asarray(r, dtype=np.complex128))
+    v = M @ w
+    return np.conj(lu.solve(np.conj(v))).real
+
+
+def full_space_minres(K, M, Kc, beta, ybar, yc=None, tol=1e-12, maxit=50, lu=None):
+    """O5: preconditioned MINRES (Paige and Saunders) on A x = b, the KKT system
+    of Sec. 2, with P = blkdiag(M, beta M, S) (Sec. 3.2, the preconditioner of
+    Murphy, Golub and Wathen, under which A has at most three distinct
+    eigenvalues).  Starts from x = 0; stops when the preconditioned residual
+    estimate falls below tol times its initial value.  Returns (y, u, lam) and
+    the iteration count."""
+    n = K.shape[0]
+    A = _kkt.kkt_matrix(K, M, beta)
+    b = _kkt.kkt_rhs(M, Kc, ybar, yc)
+    if lu is None:
+        lu = spla.splu(complex_factor(K, M, beta))
+    mlu = spla.splu(M.tocsc())
+
+    def pinv(r):
+        return np.concatenate([mlu.solve(r[:n]), mlu.solve(r[n:2 * n]) / beta,
+                               schur_inverse_two_factor(lu, M, r[2 * n:])])
+
+    x = np.zeros(3 * n)
+    r1 = b.copy()
+    y = pinv(r1)
+    beta1 = np.sqrt(r1 @ y)
+    # Lanczos on P^-1 A in the P-inner product, QR of the tridiagonal matrix
+    # by Givens rotations, and the update of x by the search directions w.
+    bet, oldb = beta1, 0.0
+    dbar = epsln = 0.0
+    phibar = beta1
+    cs, sn = -1.0, 0.0
+    w = np.zeros(3 * n)
+    w2 = np.zeros(3 * n)
+    r2 = r1.copy()
+    its = 0
+    for its in range(1, maxit + 1):
+        v = y / bet
+        y = A @ v
+        if its >= 2:
+            y = y - (bet / oldb) * r1
+        alfa = v @ y
+        y = y - (alfa / bet) * r2
+        r1, r2 = r2, y
+        y = pinv(r2)
+        oldb, bet = bet, np.sqrt(r2 @ y)
+        oldeps = epsln
+        delta = cs * dbar + sn * alfa
+        gbar = sn * dbar - cs * alfa
+        epsln = sn * bet
+        dbar = -cs * bet
+        gamma = max(np.hypot(gbar, bet), np.finfo(float).tiny)
+        cs, sn = gbar / gamma, bet / gamma
+        phi = cs * phibar
+        phibar = sn * phibar
+        w1, w2 = w2, w
+        w = (v - oldeps * w1 - delta * w2) / gamma
+        x = x + phi * w
+        if phibar <= tol * beta1:
+            break
+    return x[:n], x[n:2 * n], x[2 * n:], its

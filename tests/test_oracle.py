@@ -329,3 +329,43 @@ def test_paper_tables_fixture_minus_plus_close():
     t = json.load(open(os.path.join(GOLDEN, "paper_tables.json")))
     for a, b in zip(t["table1"]["minus"], t["table1"]["plus"]):
         assert abs(a - b) <= 0.15 * max(a, b)
+
+
+def test_mgw_preconditioned_kkt_has_three_eigenvalues():
+    """Sec. 3.2: with P_mgw = blkdiag(V, phi V, S), P^-1 A has only the
+    eigenvalues 1 and (1 +- sqrt 5) / 2 (Murphy, Golub and Wathen) -- a check of
+    the KKT blocks and of S = K M^-1 K + M / beta together."""
+    N, beta = 6, 3e-3
+    A = fem.assemble(fem.Mesh(2, N))
+    K, M = A["K"].toarray(), A["M"].toarray()
+    n = K.shape[0]
+    Kkt = kkt.kkt_matrix(A["K"], A["M"], beta).toarray()
+    P = np.zeros_like(Kkt)
+    P[:n, :n] = M
+    P[n:2 * n, n:2 * n] = beta * M
+    P[2 * n:, 2 * n:] = solve.dense_schur(A["K"], A["M"], beta)
+    ev = np.linalg.eigvals(np.linalg.solve(P, Kkt))
+    targets = np.array([1.0, (1 + np.sqrt(5)) / 2, (1 - np.sqrt(5)) / 2])
+    dist = np.abs(ev[:, None] - targets[None, :])
+    assert dist.min(axis=1).max() < 1e-8
+    assert all((dist.argmin(axis=1) == k).any() for k in range(3))
+    # a dropped term in S (M / beta) spreads the spectrum
+    P[2 * n:, 2 * n:] = K @ np.linalg.solve(M, K)
+    ev = np.linalg.eigvals(np.linalg.solve(P, Kkt))
+    assert np.abs(ev[:, None] - targets[None, :]).min(axis=1).max() > 1e-3
+
+
+@pytest.mark.parametrize("dim,N", [(2, 16), (3, 6)])
+def test_full_space_minres_converges_in_three_iterations(dim, N):
+    """Three distinct eigenvalues: MINRES with P_mgw and exact S^-1 (two complex
+    factors) ends after three iterations at the KKT solution."""
+    beta = 1e-3
+    mesh = fem.Mesh(dim, N)
+    A = fem.assemble(mesh)
+    modes, coefs = W.modes_for("four2d" if dim == 2 else "eight3d", 2)
+    ybar, yc = W.sine_target(dim, N, modes, coefs)
+    y, u, lam, its = solve.full_space_minres(A["K"], A["M"], A["Kc"], beta, ybar, yc, tol=1e-12)
+    assert its <= 3, its
+    ref = solve.range_space_two_factor(A["K"], A["M"], A["Kc"], beta, ybar, yc, paper_y=False)
+    assert np.linalg.norm(lam - ref["lam"]) <= 1e-9 * np.linalg.norm(ref["lam"])
+    assert kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc, y, u, lam) < 1e-10
