@@ -125,6 +125,8 @@ typedef struct {
   int krylov_total;      /* GMRES iterations over all FETI-DP solves */
   int krylov_its[16];    /* per FETI-DP solve, in order (factor 1, factor 2, ...) */
   int n_feti;            /* FETI-DP solves done */
+  int minres_its;        /* sfdp_solve_full_space: MINRES iterations over all
+                            refinement steps (0 for the range-space calls) */
 } sfdp_info;
 
 /* Sizes of a problem. */
@@ -205,9 +207,26 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
 sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double* f, double* x,
                             const sfdp_opts* opts, int* krylov_its);
 
+/* Full-space method (Sec. 3.2): the KKT system A x = b solved by MINRES with
+ * the block-diagonal preconditioner P_mgw = blkdiag(V, phi V, S) (Murphy,
+ * Golub and Wathen: P_mgw^-1 A has at most three distinct eigenvalues), with
+ * V^-1 exact (Kronecker product of 1D tridiagonal solves) and S^-1 through
+ * the complex factorization (as sfdp_apply_schur_inv: opts->tol_inner and
+ * opts->factors apply), inside FP64 iterative refinement on the KKT
+ * residual: each refinement step runs MINRES on A dx = b - A x to a relative
+ * preconditioned residual of 1e-6 (at most 30 iterations).  Arguments,
+ * layout, the start (ybar, 0, 0) and the stopping test (opts->tol_kkt) are
+ * those of sfdp_solve_range_space; right-hand sides are solved one after
+ * another.  info->outer_steps counts refinement steps, info->minres_its the
+ * MINRES iterations, info->n_feti and info->krylov_* the FETI-DP solves.
+ * Requires n_elem <= 1025. */
+sfdp_status sfdp_solve_full_space(sfdp_problem* p, int nrhs, const double* ybar, const double* yc, double* y,
+                                  double* u, double* lam, const sfdp_opts* opts, sfdp_info* info);
+
 /* FP64 products with the assembled matrices (Sec. 2): which = 'K' gives
- * y = K x + Kc xc (xc may be NULL), 'M' gives y = M x.  x, y: n_free x nrhs
- * real; xc: n_bdry x nrhs. */
+ * y = K x + Kc xc (xc may be NULL), 'M' gives y = M x, 'I' gives y = M^-1 x
+ * (the V block of the full-space preconditioner; n_elem <= 1025).  x, y:
+ * n_free x nrhs real; xc: n_bdry x nrhs. */
 sfdp_status sfdp_apply_operator(sfdp_problem* p, char which, int nrhs, const double* x,
                                 const double* xc, double* y);
 

@@ -1031,6 +1031,8 @@ void destroy_problem(Problem* p) {
     if (a) hipFree(a);
   if (p->gd) hipFree(p->gd);
   if (p->gh) hipHostFree(p->gh);
+  if (p->fsw) hipFree(p->fsw);
+  if (p->fsh) hipHostFree(p->fsh);
   for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
   p->ctx->used -= std::min(p->ctx->used, p->bytes);
   delete p;
@@ -1365,7 +1367,13 @@ sfdp_status sfdp_apply_operator(sfdp_problem* p, char which, int nrhs, const dou
   HIPCHK(hipSetDevice(p->ctx->device));
   if (which == 'K') HIPCHK(launch_apply_K(*p, nrhs, x, xc, y, p->ctx->stream));
   else if (which == 'M') HIPCHK(launch_apply_M(*p, nrhs, x, y, p->ctx->stream));
-  else return fail(SFDP_E_INVALID, "which must be 'K' or 'M'");
+  else if (which == 'I') {
+    if (p->N > 1025) return fail(SFDP_E_INVALID, "the mass inverse needs n_elem <= 1025");
+    for (int r = 0; r < nrhs; ++r)
+      HIPCHK(launch_mass_inverse(*p, x + r * p->n_free, 1.0, y + r * p->n_free, p->ctx->stream));
+  } else {
+    return fail(SFDP_E_INVALID, "which must be 'K', 'M' or 'I'");
+  }
   return SFDP_OK;
 }
 
@@ -1425,6 +1433,104 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
 }
 
 sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, double* z,
+                                 const sfdp_opts* opts, sfdp_info* info);
+
+// ---- full-space method: MINRES with P_mgw inside FP64 refinement ----
+namespace {
+constexpr double FS_MINRES_TOL = 1e-6;
+constexpr int FS_MINRES_MAXIT = 30;
+
+struct FsCtx {
+  sfdp_problem* p;
+  hipStream_t st;
+  int64_t n, n3;
+  double *part, *dot;  // device block sums and result
+  double* host;        // pinned
+  sfdp_opts inner;
+  sfdp_info* log;
+};
+
+sfdp_status fs_dot(FsCtx& c, const double* x, const double* y, double& out) {
+  HIPCHK(launch_dot(c.n3, x, y, c.part, c.dot, c.st));
+  HIPCHK(hipMemcpyAsync(c.host, c.dot, sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+  out = c.host[0];
+  return SFDP_OK;
+}
+
+// out = P_mgw^-1 r: V^-1 r1, (phi V)^-1 r2, S^-1 r3 (two FETI-DP solves, or one)
+sfdp_status fs_pinv(FsCtx& c, const double* r, double* out) {
+  Problem* p = c.p;
+  HIPCHK(launch_mass_inverse(*p, r, 1.0, out, c.st));
+  HIPCHK(launch_mass_inverse(*p, r + c.n, 1.0 / p->beta, out + c.n, c.st));
+  sfdp_info inf{};
+  sfdp_status s = sfdp_apply_schur_inv(c.p, 1, r + 2 * c.n, out + 2 * c.n, &c.inner, &inf);
+  if (s) return s;
+  sfdp_info& o = *c.log;
+  for (int k = 0; k < inf.n_feti; ++k) {
+    if (o.n_feti < 16) o.krylov_its[o.n_feti] = inf.krylov_its[k];
+    ++o.n_feti;
+    o.krylov_total += inf.krylov_its[k];
+  }
+  return SFDP_OK;
+}
+
+// MINRES (Paige and Saunders) on A dx = rr with the preconditioner P_mgw, from
+// dx = 0: Lanczos in the P-inner product, Givens QR of its tridiagonal matrix,
+// search directions w.  V holds 8 device vectors of length 3n.
+sfdp_status fs_minres(FsCtx& c, double* V, const double* rr, double* dx, int& its) {
+  const int64_t n3 = c.n3;
+  hipStream_t st = c.st;
+  double *r1 = V, *r2 = V + n3, *y = V + 2 * n3, *v = V + 3 * n3, *w = V + 4 * n3, *w1 = V + 5 * n3,
+         *w2 = V + 6 * n3;
+  HIPCHK(launch_lin3(n3, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, dx, st));
+  HIPCHK(launch_lin3(n3, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, w, st));
+  HIPCHK(launch_lin3(n3, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, w2, st));
+  HIPCHK(launch_lin3(n3, 1.0, rr, 0.0, nullptr, 0.0, nullptr, r1, st));
+  HIPCHK(launch_lin3(n3, 1.0, rr, 0.0, nullptr, 0.0, nullptr, r2, st));
+  sfdp_status s = fs_pinv(c, r1, y);
+  double b1 = 0.0;
+  if (s || (s = fs_dot(c, r1, y, b1))) return s;
+  its = 0;
+  if (!(b1 > 0.0)) return SFDP_OK;
+  const double beta1 = std::sqrt(b1);
+  double bet = beta1, oldb = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta1, cs = -1.0, sn = 0.0;
+  for (int k = 1; k <= FS_MINRES_MAXIT; ++k) {
+    its = k;
+    HIPCHK(launch_lin3(n3, 1.0 / bet, y, 0.0, nullptr, 0.0, nullptr, v, st));
+    HIPCHK(launch_kkt_apply(*c.p, v, y, st));
+    if (k >= 2) HIPCHK(launch_lin3(n3, 1.0, y, -bet / oldb, r1, 0.0, nullptr, y, st));
+    double alfa = 0.0;
+    if ((s = fs_dot(c, v, y, alfa))) return s;
+    HIPCHK(launch_lin3(n3, 1.0, y, -alfa / bet, r2, 0.0, nullptr, y, st));
+    std::swap(r1, r2);  // r1 <- r2, r2 <- y, and the old r1 buffer receives P^-1 r2
+    std::swap(r2, y);
+    if ((s = fs_pinv(c, r2, y))) return s;
+    double q = 0.0;
+    if ((s = fs_dot(c, r2, y, q))) return s;
+    if (q < 0.0 || !std::isfinite(q)) break;  // the preconditioner is not positive definite
+    oldb = bet;
+    bet = std::sqrt(q);  // zero: the Krylov space is exhausted, this step is the last
+    const double oldeps = epsln;
+    const double delta = cs * dbar + sn * alfa, gbar = sn * dbar - cs * alfa;
+    epsln = sn * bet;
+    dbar = -cs * bet;
+    const double gamma = std::max(std::hypot(gbar, bet), 1e-300);
+    cs = gbar / gamma;
+    sn = bet / gamma;
+    const double phi = cs * phibar;
+    phibar = sn * phibar;
+    std::swap(w1, w2);  // w1 <- w2, w2 <- w, w <- (v - oldeps w1 - delta w2) / gamma
+    std::swap(w2, w);
+    HIPCHK(launch_lin3(n3, 1.0 / gamma, v, -oldeps / gamma, w1, -delta / gamma, w2, w, st));
+    HIPCHK(launch_lin3(n3, 1.0, dx, phi, w, 0.0, nullptr, dx, st));
+    if (phibar <= FS_MINRES_TOL * beta1 || !(bet > 0.0)) break;
+  }
+  return SFDP_OK;
+}
+}  // namespace
+
+sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, double* z,
                                  const sfdp_opts* opts, sfdp_info* info) {
   sfdp_status s = check_ready(p);
   if (s) return s;
@@ -1477,6 +1583,80 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
   }
   HIPCHK(ev_harvest(*p));
   return SFDP_OK;
+}
+
+sfdp_status sfdp_solve_full_space(sfdp_problem* p, int nrhs, const double* ybar, const double* yc, double* y,
+                                  double* u, double* lam, const sfdp_opts* opts, sfdp_info* info) {
+  sfdp_status s = check_ready(p);
+  if (s) return s;
+  if (nrhs <= 0 || !ybar || !y || !u || !lam) return fail(SFDP_E_INVALID, "bad arguments");
+  if (p->N > 1025) return fail(SFDP_E_INVALID, "the full-space method needs n_elem <= 1025");
+  double tk, ti;
+  int mo, kmax;
+  defaults(p->prec, opts, tk, ti, mo, kmax, p->dim);
+  HIPCHK(hipSetDevice(p->ctx->device));
+  if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p)) || (s = gather_buffers(*p))) return s;
+  const int64_t n = p->n_free, n3 = 3 * n, nb = (n3 + 255) / 256;
+  if (!p->fsw) {
+    if ((s = dalloc(*p, (void**)&p->fsw, sizeof(double) * (10 * n3 + nb + 8)))) return s;
+    if (hipHostMalloc((void**)&p->fsh, sizeof(double) * 8) != hipSuccess) {
+      p->fsh = nullptr;
+      return fail(SFDP_E_NOMEM, "pinned host allocation");
+    }
+  }
+  FsCtx c{p, p->ctx->stream, n, n3, p->fsw + 10 * n3, p->fsw + 10 * n3 + nb, p->fsh, {}, nullptr};
+  if (opts) c.inner = *opts;
+  c.inner.batch = 1;
+  double* Vw = p->fsw;            // 8 MINRES vectors
+  double* dx = p->fsw + 8 * n3;
+  double* rr = p->fsw + 9 * n3;
+  Target t = single_target(p);
+  hipStream_t st = c.st;
+  sfdp_status worst = SFDP_OK;
+  for (int q = 0; q < nrhs; ++q) {
+    sfdp_info o{};
+    c.log = &o;
+    double* yq = y + q * n;
+    double* uq = u + q * n;
+    double* lq = lam + q * n;
+    p->nr = 1;
+    p->map = IDENTITY_MAP;
+    p->set_slots(1, ybar + q * n, yc ? yc + q * p->n_bdry : nullptr, yq, uq, lq);
+    p->init = 1u;
+    HIPCHK(launch_group_init(t));
+    p->init = 0;
+    bool bad = false;
+    for (int step = 0;; ++step) {
+      p->nr = 1;
+      p->map = IDENTITY_MAP;
+      HIPCHK(launch_kkt_residual(t));
+      if ((s = gather_one(p))) return s;
+      const double rho = p->gh->red[0];
+      o.rel_kkt = rho;
+      if (step == 1) o.rel_kkt_first = rho;
+      if (!std::isfinite(rho) || step >= mo) {
+        bad = rho > tk || !std::isfinite(rho);
+        break;
+      }
+      if (rho <= tk) break;
+      // rr = b - A x (the residual blocks of slot 0), then x += MINRES(A, rr)
+      HIPCHK(hipMemcpyAsync(rr, p->r1, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(rr + n, p->r2, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(rr + 2 * n, p->r3, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      int its = 0;
+      if ((s = fs_minres(c, Vw, rr, dx, its))) return s;
+      o.minres_its += its;
+      HIPCHK(launch_lin3(n, 1.0, yq, 1.0, dx, 0.0, nullptr, yq, st));
+      HIPCHK(launch_lin3(n, 1.0, uq, 1.0, dx + n, 0.0, nullptr, uq, st));
+      HIPCHK(launch_lin3(n, 1.0, lq, 1.0, dx + 2 * n, 0.0, nullptr, lq, st));
+      o.outer_steps = step + 1;
+    }
+    p->nr = 0;
+    if (info) info[q] = o;
+    if (bad) worst = fail(SFDP_E_NOCONV, "full-space refinement did not reach tol_kkt");
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return worst;
 }
 
 // ---- batches of independent instances ----

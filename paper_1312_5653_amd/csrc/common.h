@@ -295,6 +295,8 @@ struct Problem {
   double beta = 0, alpha = 0;
   bool factored = false;
   Three* t3 = nullptr;  // dim = 3: maps, factors and workspaces of the 3D path
+  double* fsw = nullptr;   // full-space method: device vectors (9 x 3 n_free + sums)
+  double* fsh = nullptr;   // and its pinned host scalars
   // index maps (device)
   int *dloc = nullptr, *dmid = nullptr, *dpart = nullptr, *nd = nullptr, *cloc = nullptr,
       *cgid = nullptr, *muown = nullptr, *mufree = nullptr, *cown = nullptr, *cfree = nullptr,
@@ -486,6 +488,13 @@ hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t st);
 hipError_t launch_real_part(int64_t n, const cd* x, double* y, hipStream_t st);
 hipError_t launch_imag_scaled(int64_t n, const cd* x, double s, double* y, hipStream_t st);  // y = s Im x
 hipError_t launch_group_init(const Target& t);  // y = ybar, u = lam = 0 for the views' init slots
+// full-space method: out = A x (x, out: three free-node blocks); out = scale M^-1 x;
+// out = a x + b y + c z; out[0] = x . y (part: (n + 255) / 256 block sums)
+hipError_t launch_kkt_apply(const Problem& p, const double* x, double* out, hipStream_t st);
+hipError_t launch_mass_inverse(const Problem& p, const double* x, double scale, double* out, hipStream_t st);
+hipError_t launch_lin3(int64_t n, double a, const double* x, double b, const double* y, double c, const double* z,
+                       double* out, hipStream_t st);
+hipError_t launch_dot(int64_t n, const double* x, const double* y, double* part, double* out, hipStream_t st);
 hipError_t launch_gather(const Target& t, Gathered* out);  // out[i]: instance i of the target
 
 }  // namespace sfdp

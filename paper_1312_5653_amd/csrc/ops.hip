@@ -374,6 +374,113 @@ __global__ void k_copy(int64_t n, const double* x, double* y) {
   if (i < n) y[i] = x[i];
 }
 
+// ---- full-space method (Sec. 3.2): KKT operator, mass inverse, vector ops ----
+
+// out = A x for x = (y, u, lam), three free-node blocks of length n (Sec. 2 KKT
+// matrix): out1 = M y + K lam, out2 = beta M u - M lam, out3 = K y - M u.
+__global__ void k_kkt_apply(int N, int dim, double beta, const double* x, double* out, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const Sten st = make_sten(1.0 / N);
+  double Ky, My, Ku, Mu, Kl, Ml;
+  if (dim == 3) {
+    int i, j, k;
+    ijk3(t, N, i, j, k);
+    stencil_KM3(st, N, nullptr, Field{x, nullptr}, i, j, k, Ky, My);
+    stencil_KM3(st, N, nullptr, Field{x + n, nullptr}, i, j, k, Ku, Mu);
+    stencil_KM3(st, N, nullptr, Field{x + 2 * n, nullptr}, i, j, k, Kl, Ml);
+  } else {
+    const int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
+    stencil_KM(st, N, nullptr, Field{x, nullptr}, i, j, Ky, My);
+    stencil_KM(st, N, nullptr, Field{x + n, nullptr}, i, j, Ku, Mu);
+    stencil_KM(st, N, nullptr, Field{x + 2 * n, nullptr}, i, j, Kl, Ml);
+  }
+  out[t] = My + Kl;
+  out[n + t] = beta * Mu - Ml;
+  out[2 * n + t] = Ky - Mu;
+}
+
+// One factor of M^-1: the free-node mass matrix is m1 (x) m1 [(x) m1] with
+// m1 = (h/6) tridiag(1, 4, 1) of order N - 1, so M^-1 is the product of
+// tridiagonal solves along each axis.  Thread per grid line along `axis`
+// (Thomas algorithm; m1 is diagonally dominant), out = scale m1^-1 in (in may
+// equal out).  The elimination coefficients are the same for every line.
+__global__ void __launch_bounds__(256) k_mass_lines(int N, int dim, int axis, double scale, const double* in,
+                                                    double* out) {
+  __shared__ double cp[1024];
+  const int n1 = N - 1;
+  const double h = 1.0 / N, a = h / 6.0, b = 4.0 * h / 6.0;
+  if (threadIdx.x == 0) {
+    cp[0] = a / b;
+    for (int i = 1; i < n1; ++i) cp[i] = a / (b - a * cp[i - 1]);
+  }
+  __syncthreads();
+  const int64_t lines = dim == 3 ? (int64_t)n1 * n1 : n1;
+  const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= lines) return;
+  int64_t base, stride;
+  if (axis == 0) {
+    base = line * n1;
+    stride = 1;
+  } else if (axis == 1) {
+    base = dim == 3 ? (line % n1) + (line / n1) * (int64_t)n1 * n1 : line;
+    stride = n1;
+  } else {
+    base = line;
+    stride = (int64_t)n1 * n1;
+  }
+  double dprev = in[base] / b;
+  out[base] = dprev;
+  for (int i = 1; i < n1; ++i) {
+    const int64_t o = base + i * stride;
+    dprev = (in[o] - a * dprev) / (b - a * cp[i - 1]);
+    out[o] = dprev;
+  }
+  double xn = out[base + (n1 - 1) * stride];
+  out[base + (n1 - 1) * stride] = scale * xn;
+  for (int i = n1 - 2; i >= 0; --i) {
+    const int64_t o = base + i * stride;
+    xn = out[o] - cp[i] * xn;
+    out[o] = scale * xn;
+  }
+}
+
+// out = a x + b y + c z (null operands count as zero)
+__global__ void k_lin3(int64_t n, double a, const double* x, double b, const double* y, double c, const double* z,
+                       double* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double v = 0.0;
+  if (x) v = a * x[t];
+  if (y) v = fma(b, y[t], v);
+  if (z) v = fma(c, z[t], v);
+  out[t] = v;
+}
+
+// part[block] = sum of x y over the block's entries
+__global__ void __launch_bounds__(256) k_dot_part(int64_t n, const double* x, const double* y, double* part) {
+  __shared__ double sh[4];
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double v = t < n ? x[t] * y[t] : 0.0;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+// out[0] = sum of part[0 .. nb) in a fixed order
+__global__ void __launch_bounds__(256) k_sum_parts(int nb, const double* part, double* out) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int q = threadIdx.x; q < nb; q += 256) a += part[q];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_apply_K(const Problem& p, int nrhs, const double* x, const double* xc, double* y,
@@ -439,6 +546,29 @@ hipError_t launch_copy_real_to_complex(int64_t n, const double* x, cd* y, hipStr
 }
 hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_copy, dim3(nblk(n)), dim3(256), 0, st, n, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_kkt_apply(const Problem& p, const double* x, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_kkt_apply, dim3(nblk(p.n_free)), dim3(256), 0, st, p.N, p.dim, p.beta, x, out, p.n_free);
+  return hipGetLastError();
+}
+hipError_t launch_mass_inverse(const Problem& p, const double* x, double scale, double* out, hipStream_t st) {
+  const int n1 = p.N - 1;
+  const int64_t lines = p.dim == 3 ? (int64_t)n1 * n1 : n1;
+  for (int axis = 0; axis < p.dim; ++axis)
+    hipLaunchKernelGGL(k_mass_lines, dim3(nblk(lines)), dim3(256), 0, st, p.N, p.dim, axis,
+                       axis == p.dim - 1 ? scale : 1.0, axis == 0 ? x : (const double*)out, out);
+  return hipGetLastError();
+}
+hipError_t launch_lin3(int64_t n, double a, const double* x, double b, const double* y, double c, const double* z,
+                       double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_lin3, dim3(nblk(n)), dim3(256), 0, st, n, a, x, b, y, c, z, out);
+  return hipGetLastError();
+}
+hipError_t launch_dot(int64_t n, const double* x, const double* y, double* part, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_part, dim3(nblk(n)), dim3(256), 0, st, n, x, y, part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, (int)nblk(n), (const double*)part, out);
   return hipGetLastError();
 }
 

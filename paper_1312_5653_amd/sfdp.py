@@ -25,6 +25,7 @@ EXPORTS = [
     "sfdp_batch_create", "sfdp_batch_destroy", "sfdp_batch_sizes", "sfdp_batch_set_beta",
     "sfdp_batch_solve_range_space", "sfdp_server_create", "sfdp_server_submit", "sfdp_server_poll",
     "sfdp_server_stats", "sfdp_server_destroy", "sfdp_set_coarse_space", "sfdp_batch_inspect",
+    "sfdp_solve_full_space",
 ]
 
 
@@ -44,13 +45,14 @@ class Info(ctypes.Structure):
     _fields_ = [("rel_kkt", ctypes.c_double), ("rel_kkt_first", ctypes.c_double),
                 ("imag_ratio", ctypes.c_double), ("outer_steps", ctypes.c_int),
                 ("krylov_total", ctypes.c_int), ("krylov_its", ctypes.c_int * 16),
-                ("n_feti", ctypes.c_int)]
+                ("n_feti", ctypes.c_int), ("minres_its", ctypes.c_int)]
 
     def as_dict(self):
         return {"rel_kkt": self.rel_kkt, "rel_kkt_first": self.rel_kkt_first,
                 "imag_ratio": self.imag_ratio, "outer_steps": self.outer_steps,
                 "krylov_total": self.krylov_total, "n_feti": self.n_feti,
-                "krylov_its": list(self.krylov_its)[: self.n_feti]}
+                "krylov_its": list(self.krylov_its)[: min(self.n_feti, 16)],
+                "minres_its": self.minres_its}
 
 
 class Request(ctypes.Structure):
@@ -104,6 +106,7 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_problem_destroy.restype = None
     lib.sfdp_set_beta.argtypes = [P, D]
     lib.sfdp_solve_range_space.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    lib.sfdp_solve_full_space.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.sfdp_apply_schur_inv.argtypes = [P, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.sfdp_feti_solve.argtypes = [P, I, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(I)]
     lib.sfdp_apply_operator.argtypes = [P, ctypes.c_char, I, VP, VP, VP]
@@ -232,6 +235,21 @@ class Problem:
         o = _opts(**opts)
         st = _lib.sfdp_solve_range_space(self._h, nrhs, _ptr(ybar), _ptr(yc), _ptr(y), _ptr(u), _ptr(lam),
                                          ctypes.byref(o), infos)
+        _check(st, allow_noconv=True)
+        return y, u, lam, [i.as_dict() for i in infos], st
+
+    def solve_full_space(self, ybar, yc=None, y=None, u=None, lam=None, **opts):
+        """Full-space method: MINRES with the block-diagonal Schur preconditioner
+        inside FP64 refinement (same arguments and results as solve_range_space)."""
+        import torch
+        nrhs = 1 if ybar.dim() == 1 else ybar.shape[0]
+        y = torch.empty_like(ybar) if y is None else y
+        u = torch.empty_like(ybar) if u is None else u
+        lam = torch.empty_like(ybar) if lam is None else lam
+        infos = (Info * nrhs)()
+        o = _opts(**opts)
+        st = _lib.sfdp_solve_full_space(self._h, nrhs, _ptr(ybar), _ptr(yc), _ptr(y), _ptr(u), _ptr(lam),
+                                        ctypes.byref(o), infos)
         _check(st, allow_noconv=True)
         return y, u, lam, [i.as_dict() for i in infos], st
 
