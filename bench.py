@@ -267,7 +267,7 @@ def cpu_instances(count, seed, budget_s=10.0):
 
 
 def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup, tol_kkt, tol_inner,
-                  batch, max_krylov=0, factors=0, edges=None, dim=2):
+                  batch, max_krylov=0, factors=0, edges=None, dim=2, full_space=False):
     p = sfdp.Problem(ctx, dim, N, m, precision)
     if edges is not None:
         p.set_coarse_space(edges)
@@ -280,21 +280,23 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
     u = torch.empty_like(ybar_t)
     lam = torch.empty_like(ybar_t)
     nb = ybar_t.shape[0]
+    solve = p.solve_full_space if full_space else p.solve_range_space
     for _ in range(warmup):
-        p.solve_range_space(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch,
-                            max_krylov=max_krylov, factors=factors)
+        solve(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch,
+              max_krylov=max_krylov, factors=factors)
     p.timing_enable(True)
-    lat, rhos, its = [], [], []
+    lat, rhos, its, feti, minres = [], [], [], [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for _ in range(steps):
         t0 = time.perf_counter()
-        _, _, _, info, st = p.solve_range_space(ybar_t, None, y, u, lam, tol_kkt=tol_kkt,
-                                                tol_inner=tol_inner, batch=batch, max_krylov=max_krylov,
-                                                factors=factors)
+        _, _, _, info, st = solve(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch,
+                                  max_krylov=max_krylov, factors=factors)
         lat.append(time.perf_counter() - t0)
         rhos.extend(i["rel_kkt"] for i in info)
         its.extend(i["krylov_total"] for i in info)
+        feti.extend(i["n_feti"] for i in info)
+        minres.extend(i["minres_its"] for i in info)
         if st != 0:
             raise RuntimeError(f"solve did not converge: {info}")
     torch.cuda.synchronize()
@@ -308,6 +310,7 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
     return {"solves_per_s": nb * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps, "batch": nb,
             "p50_ms": q(0.5), "p99_ms": q(0.99), "setup_ms": setup_ms,
             "max_rel_kkt": max(rhos), "krylov_per_solve": statistics.mean(its),
+            "feti_per_solve": statistics.mean(feti), "minres_per_solve": statistics.mean(minres),
             "kernel_times": kt, "sizes": sizes}
 
 
@@ -415,6 +418,11 @@ def main():
         # the corner-only coarse space, for the effect of the edge augmentation
         res[head + "_corners_only"] = run_precision(sfdp, torch, ctx, hp, N, m, beta, ybar_t, args.steps,
                                                     args.warmup, tol_kkt, htin, B, args.max_krylov, edges=False)
+        # the full-space method with the same S^-1 as its preconditioner block
+        # (Sec. 3.2; targets one after another)
+        res[head + "_full_space"] = run_precision(sfdp, torch, ctx, hp, N, m, beta, ybar_t,
+                                                  max(2, args.steps // 5), 1, tol_kkt, htin, B, args.max_krylov,
+                                                  full_space=True)
     r = res[head]
     kt = r["kernel_times"]
     sz = r["sizes"]
@@ -462,7 +470,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_gmres (interface Krylov solve, persistent)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"k_gmres<{'C<float>' if head == 'mixed' else 'C<double>'}, {kt['gmres_width']}>"),
+                     "traffic": measured_traffic(f"k_gmres<{'C<float>' if head == 'mixed' else 'C<double>'}, {kt['gmres_width']}, One>"),
                      "bytes_per_launch": launch_bytes, "operator_bytes_per_trip": op_bytes,
                      "vector_bytes_per_rhs_iteration": vec_bytes, "trips_per_launch": trips,
                      "rhs_iterations_per_launch": rhs_its, "launch_ms": launch_ms,
@@ -479,7 +487,11 @@ def main():
         out[k] = {"batch": o["batch"], "solves_per_s": o["solves_per_s"], "ms_per_step": o["ms_per_step"],
                   "factors": 1 if k.endswith("_single_solve") else 2,
                   "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"], "max_rel_kkt": o["max_rel_kkt"],
-                  "krylov_its_per_solve": o["krylov_per_solve"], "setup_ms": o["setup_ms"]}
+                  "krylov_its_per_solve": o["krylov_per_solve"], "feti_solves_per_solve": o["feti_per_solve"],
+                  "setup_ms": o["setup_ms"]}
+        if k.endswith("_full_space"):
+            out[k]["method"] = "full-space MINRES, P_mgw with S^-1 by the complex factorization"
+            out[k]["minres_its_per_solve"] = o["minres_per_solve"]
     if args.instances > 0 and not args.headline_only:
         out["instances_batch"] = run_instances(sfdp, torch, ctx, args.instances, 0, tol_kkt)
         if not args.no_cpu:
