@@ -302,7 +302,7 @@ sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const d
                                          const double* const* yc, double* const* y, double* const* u,
                                          double* const* lam, const sfdp_opts* opts, sfdp_info* info);
 
-/* ---- Serving: continuous batching of range-space requests ----
+/* ---- Serving: continuous batching of requests ----
  *
  * A server owns a worker thread that uses the context's stream (the caller
  * must not use that context from other threads meanwhile).  Requests (one
@@ -320,10 +320,16 @@ sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const d
  * Targets that finish free their slots, and waiting targets take free slots
  * at the next tick, so requests that arrive while others run join them on
  * the device.  A result does not depend on what else is in flight (up to the
- * rounding of multiply-add contraction, 1e-12 relative). */
+ * rounding of multiply-add contraction, 1e-12 relative).
+ * 3D requests and full-space requests (mode 1) take a solo lane: after each
+ * tick the worker solves one of them whole, in arrival order, on a resident
+ * single problem of its (dim, mesh, beta) (at most two are kept, least
+ * recently used dropped first; on a memory shortage the idle batched
+ * instances are evicted and the set-up tried once more, else the request is
+ * refused with SFDP_E_ADMIT). */
 typedef struct sfdp_server sfdp_server;
 typedef struct {
-  int dim;           /* 2 */
+  int dim;           /* 2 or 3 */
   int n_elem;        /* cells per side */
   int sub_elem;      /* cells per subdomain side */
   double beta;
@@ -331,6 +337,7 @@ typedef struct {
   const double* ybar;  /* device, n_free x nrhs (as sfdp_solve_range_space) */
   const double* yc;    /* device, n_bdry x nrhs, or NULL for zero */
   double *y, *u, *lam; /* device outputs, n_free x nrhs; all arrays stay valid until polled */
+  int mode;          /* 0: range-space method; 1: full-space method (sfdp_solve_full_space) */
 } sfdp_request;
 typedef struct {
   int64_t submitted, completed, failed;

@@ -1852,6 +1852,7 @@ struct SInst;
 
 struct SReq {
   uint64_t id = 0;
+  int dim = 2, mode = 0;  // mode 1: full-space method
   int n_elem = 0, sub_elem = 0, nrhs = 0;
   double beta = 0;
   const double *ybar = nullptr, *yc = nullptr;
@@ -1888,6 +1889,16 @@ struct SInst {
   }
 };
 
+// A single problem of the solo lane (3D or full-space requests), resident for
+// the requests that follow with the same mesh and beta.
+struct SSolo {
+  Problem* p = nullptr;
+  int dim = 2, n_elem = 0, sub_elem = 0;
+  double beta = 0;
+  double last_used = 0;
+};
+constexpr size_t SOLO_KEEP = 2;  // solo problems kept resident at most
+
 }  // namespace
 
 struct sfdp_server {
@@ -1916,6 +1927,9 @@ struct sfdp_server {
   std::string worker_error;
   std::vector<SReq*> finished;  // decided by the worker, published under the lock
   size_t pool_cap = 0;          // set-up scratch of one set-up pass (a larger instance passes alone)
+  int user_kmax = 0;            // opts->max_krylov as given (0: each path's default)
+  std::deque<SReq*> solo;       // admitted 3D and full-space requests (worker only)
+  std::vector<SSolo> solos;     // their resident problems
 };
 
 namespace {
@@ -2183,6 +2197,82 @@ sfdp_status server_tick(sfdp_server* S) {
   return SFDP_OK;
 }
 
+// One request of the solo lane, solved whole on its (mesh, beta) problem: a 3D
+// instance cannot share the batched 2D launches, and a full-space request
+// runs MINRES with the factored Schur complement.  On a memory shortage the
+// idle batched instances and the other solo problems are dropped and the
+// set-up is tried once more.  Returns only device errors; everything else
+// finishes the request.
+sfdp_status server_solo(sfdp_server* S, SReq* r) {
+  SSolo* home = nullptr;
+  for (SSolo& so : S->solos)
+    if (so.dim == r->dim && so.n_elem == r->n_elem && so.sub_elem == r->sub_elem && so.beta == r->beta) home = &so;
+  if (!home) {
+    auto drop_lru = [&]() {
+      if (S->solos.empty()) return false;
+      size_t v = 0;
+      for (size_t i = 1; i < S->solos.size(); ++i)
+        if (S->solos[i].last_used < S->solos[v].last_used) v = i;
+      destroy_problem(S->solos[v].p);
+      S->solos.erase(S->solos.begin() + v);
+      return true;
+    };
+    while (S->solos.size() >= SOLO_KEEP) drop_lru();
+    Problem* p = nullptr;
+    sfdp_status st = SFDP_OK;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      st = create_problem(S->ctx, r->dim, r->n_elem, r->sub_elem, S->prec, &p);
+      if (!st) {
+        st = sfdp_set_beta((sfdp_problem*)p, r->beta);
+        if (st) {
+          destroy_problem(p);
+          p = nullptr;
+        }
+      }
+      if (st != SFDP_E_NOMEM || attempt) break;
+      while (drop_lru()) {
+      }
+      for (size_t i = 0; i < S->insts.size();) {
+        SInst* in = S->insts[i];
+        if (in->busy()) {
+          ++i;
+          continue;
+        }
+        S->insts.erase(S->insts.begin() + i);
+        destroy_problem(in->p);
+        delete in;
+        ++S->n_evict;
+      }
+      S->active_set.clear();
+    }
+    if (st == SFDP_E_DEVICE) return st;
+    if (st) {
+      r->why = std::string("solo set-up failed: ") + g_err;
+      server_finish(S, r, st == SFDP_E_NOMEM ? SFDP_E_ADMIT : st);
+      return SFDP_OK;
+    }
+    ++S->n_setups;
+    S->solos.push_back(SSolo{p, r->dim, r->n_elem, r->sub_elem, r->beta, 0.0});
+    home = &S->solos.back();
+  }
+  home->last_used = now_ms();
+  sfdp_opts o{};
+  o.tol_kkt = S->tol_kkt;
+  o.tol_inner = S->tol_inner;
+  o.max_outer = S->max_outer;
+  o.max_krylov = S->user_kmax;
+  o.factors = S->single ? 1 : 2;
+  sfdp_problem* sp = (sfdp_problem*)home->p;
+  sfdp_status st = r->mode == 1
+                       ? sfdp_solve_full_space(sp, r->nrhs, r->ybar, r->yc, r->y, r->u, r->lam, &o, r->info.data())
+                       : sfdp_solve_range_space(sp, r->nrhs, r->ybar, r->yc, r->y, r->u, r->lam, &o, r->info.data());
+  if (st == SFDP_E_DEVICE) return st;
+  r->done = r->nrhs;
+  if (st) r->why = g_err;
+  server_finish(S, r, st);
+  return SFDP_OK;
+}
+
 void server_loop(sfdp_server* S) {
   hipSetDevice(S->ctx->device);
   for (;;) {
@@ -2191,7 +2281,7 @@ void server_loop(sfdp_server* S) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       for (;;) {
-        work = false;
+        work = !S->solo.empty();
         for (SInst* in : S->insts) work = work || in->busy();
         if (work || !S->pending.empty() || S->stop) break;
         S->cv_work.wait(lk);
@@ -2200,6 +2290,15 @@ void server_loop(sfdp_server* S) {
       pend.swap(S->pending);
     }
     hipStreamSynchronize(S->ctx->stream);
+    // 3D and full-space requests take the solo lane, in arrival order
+    for (auto it = pend.begin(); it != pend.end();) {
+      if ((*it)->dim == 3 || (*it)->mode == 1) {
+        S->solo.push_back(*it);
+        it = pend.erase(it);
+      } else {
+        ++it;
+      }
+    }
     std::vector<SInst*> fresh = server_admit(S, pend);
     sfdp_status st = SFDP_OK;
     if (!fresh.empty()) {
@@ -2252,6 +2351,12 @@ void server_loop(sfdp_server* S) {
       }
     }
     if (!st) st = server_tick(S);
+    // then one request of the solo lane, so batched targets keep moving between them
+    if (!st && !S->solo.empty()) {
+      SReq* r = S->solo.front();
+      S->solo.pop_front();
+      st = server_solo(S, r);
+    }
     std::lock_guard<std::mutex> lk(S->mu);
     // requests that could not be admitted yet go back to the front of the queue
     for (auto it = pend.rbegin(); it != pend.rend(); ++it) S->pending.push_front(*it);
@@ -2266,6 +2371,7 @@ void server_loop(sfdp_server* S) {
         for (SSlot& sl : in->slot) sl = SSlot{};
       }
       S->pending.clear();
+      S->solo.clear();
     }
     for (SReq* r : S->finished) {
       r->complete = true;
@@ -2294,6 +2400,7 @@ sfdp_status sfdp_server_create(sfdp_ctx* ctx, sfdp_precision prec, const sfdp_op
   S->ctx = ctx;
   S->prec = prec;
   defaults(prec, opts, S->tol_kkt, S->tol_inner, S->max_outer, S->kmax);
+  S->user_kmax = (opts && opts->max_krylov > 0) ? opts->max_krylov : 0;
   S->single = single_of(opts);
   S->pool_cap = ctx->budget ? ctx->budget / 16 : (size_t)4 << 30;
   S->worker = std::thread(server_loop, S);
@@ -2303,13 +2410,18 @@ sfdp_status sfdp_server_create(sfdp_ctx* ctx, sfdp_precision prec, const sfdp_op
 
 sfdp_status sfdp_server_submit(sfdp_server* S, const sfdp_request* rq, uint64_t* ticket) {
   if (!S || !rq || !ticket) return fail(SFDP_E_INVALID, "NULL argument");
-  if (rq->dim != 2) return fail(SFDP_E_INVALID, "only dim = 2 is implemented");
-  if (rq->sub_elem < 2 || rq->sub_elem > 32 || rq->n_elem % rq->sub_elem != 0 || rq->n_elem / rq->sub_elem < 2)
+  if (rq->dim != 2 && rq->dim != 3) return fail(SFDP_E_INVALID, "dim must be 2 or 3");
+  if (rq->mode != 0 && rq->mode != 1) return fail(SFDP_E_INVALID, "mode must be 0 (range space) or 1 (full space)");
+  if (rq->sub_elem < 2 || rq->sub_elem > (rq->dim == 3 ? 9 : 32) || rq->n_elem % rq->sub_elem != 0 ||
+      rq->n_elem / rq->sub_elem < 2)
     return fail(SFDP_E_INVALID, "bad mesh");
+  if (rq->mode == 1 && rq->n_elem > 1025) return fail(SFDP_E_INVALID, "the full-space method needs n_elem <= 1025");
   if (!(rq->beta > 0) || !std::isfinite(rq->beta)) return fail(SFDP_E_INVALID, "beta must be positive and finite");
   if (rq->nrhs <= 0 || !rq->ybar || !rq->y || !rq->u || !rq->lam) return fail(SFDP_E_INVALID, "bad arguments");
   SReq* r = new (std::nothrow) SReq();
   if (!r) return fail(SFDP_E_NOMEM, "host allocation");
+  r->dim = rq->dim;
+  r->mode = rq->mode;
   r->n_elem = rq->n_elem;
   r->sub_elem = rq->sub_elem;
   r->nrhs = rq->nrhs;
@@ -2397,6 +2509,7 @@ void sfdp_server_destroy(sfdp_server* S) {
     destroy_problem(in->p);
     delete in;
   }
+  for (SSolo& so : S->solos) destroy_problem(so.p);
   for (auto& kv : S->reqs) delete kv.second;
   if (S->gmap) hipFree(S->gmap);
   if (S->dg) hipFree(S->dg);

@@ -59,7 +59,7 @@ class Request(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n_elem", ctypes.c_int), ("sub_elem", ctypes.c_int),
                 ("beta", ctypes.c_double), ("nrhs", ctypes.c_int), ("ybar", ctypes.c_void_p),
                 ("yc", ctypes.c_void_p), ("y", ctypes.c_void_p), ("u", ctypes.c_void_p),
-                ("lam", ctypes.c_void_p)]
+                ("lam", ctypes.c_void_p), ("mode", ctypes.c_int)]
 
 
 class ServerInfo(ctypes.Structure):
@@ -395,17 +395,20 @@ class Server:
         self.ctx = ctx
         self._live = {}
 
-    def submit(self, n_elem: int, sub_elem: int, beta: float, ybar, yc=None):
+    def submit(self, n_elem: int, sub_elem: int, beta: float, ybar, yc=None, dim: int = 2,
+               full_space: bool = False):
         """ybar: (nrhs, n_free) or (n_free,) CUDA tensor whose values are ready
         (the caller synchronises after producing them); kept alive until polled.
+        dim 3 or full_space (the full-space method) take the server's solo lane.
         Returns a ticket; the outputs are allocated here."""
         import torch
         if not ybar.is_cuda or not ybar.is_contiguous():
             raise ValueError("arrays must be contiguous CUDA tensors")
         nrhs = 1 if ybar.dim() == 1 else ybar.shape[0]
         y, u, lam = (torch.empty_like(ybar) for _ in range(3))
-        req = Request(2, n_elem, sub_elem, float(beta), nrhs, ybar.data_ptr(),
-                      yc.data_ptr() if yc is not None else None, y.data_ptr(), u.data_ptr(), lam.data_ptr())
+        req = Request(dim, n_elem, sub_elem, float(beta), nrhs, ybar.data_ptr(),
+                      yc.data_ptr() if yc is not None else None, y.data_ptr(), u.data_ptr(), lam.data_ptr(),
+                      int(full_space))
         t = ctypes.c_uint64()
         _check(_lib.sfdp_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         self._live[t.value] = (ybar, yc, y, u, lam, nrhs)

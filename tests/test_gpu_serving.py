@@ -160,3 +160,53 @@ def test_large_instances_share_launches(sfdp):
     assert s["completed"] == 3 and s["failed"] == 0, s
     srv.close()
     ctx.close()
+
+
+def test_solo_lane_3d_and_full_space(sfdp):
+    """3D requests and full-space requests (MINRES with the factored Schur
+    complement) join the same stream as 2D range-space requests: the worker
+    solves them whole between ticks.  Every result meets the KKT gate, and a
+    3D result equals that of a lone problem solved with the same options."""
+    ctx = sfdp.Context(0)
+    srv = sfdp.Server(ctx, sfdp.SFDP_MIXED, tol_kkt=1e-8)
+    reqs = [  # dim, n_elem, sub_elem, beta, nrhs, full space
+        (2, 64, 8, 1e-4, 2, False),
+        (3, 12, 4, 1e-3, 2, False),
+        (2, 48, 8, 1e-3, 1, True),
+        (3, 12, 4, 1e-3, 1, True),
+        (2, 64, 8, 1e-4, 1, False),
+        (3, 16, 4, 1e-5, 3, False),
+    ]
+    data = []
+    for i, (dim, N, m, b, k, fs) in enumerate(reqs):
+        kind = "four2d" if dim == 2 else "eight3d"
+        ys = np.stack([W.sine_target(dim, N, *W.modes_for(kind, 30 + 5 * i + r))[0] for r in range(k)])
+        data.append(ys)
+    tickets = [srv.submit(N, m, b, _t(data[i]), dim=dim, full_space=fs)
+               for i, (dim, N, m, b, k, fs) in enumerate(reqs)]
+    out = []
+    for (dim, N, m, b, k, fs), ys, tk in zip(reqs, data, tickets):
+        y, u, lam, info, lat, st = srv.poll(tk)
+        assert st == 0, (dim, N, fs, info)
+        A = fem.assemble(fem.Mesh(dim, N))
+        z = np.zeros(A["Kc"].shape[1])
+        for r in range(k):
+            rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], b, ys[r], z, y[r].cpu().numpy(), u[r].cpu().numpy(),
+                              lam[r].cpu().numpy())
+            assert rho <= 1e-8, (dim, N, fs, r, rho, info[r])
+            if fs:
+                assert info[r]["minres_its"] > 0, info[r]
+        out.append((y.cpu().numpy(), info))
+    s = srv.stats()
+    assert s["completed"] == len(reqs) and s["failed"] == 0, s
+    srv.close()
+    # the 3D range-space request against a lone problem with the same options
+    p = sfdp.Problem(ctx, 3, 16, 4, sfdp.SFDP_MIXED)
+    p.set_beta(1e-5)
+    y1, _, _, info1, st1 = p.solve_range_space(_t(data[5]), None, tol_kkt=1e-8)
+    assert st1 == 0
+    for r in range(3):
+        assert np.linalg.norm(y1[r].cpu().numpy() - out[5][0][r]) <= 1e-12 * np.linalg.norm(out[5][0][r])
+        assert info1[r]["krylov_its"] == out[5][1][r]["krylov_its"]
+    p.close()
+    ctx.close()
