@@ -204,7 +204,8 @@ def run_serving(sfdp, torch, count, seed, tol_kkt, budget_gb):
     reqs = workloads.c5_requests(count, seed)
     inputs = []
     for r in reqs:
-        ys = [workloads.sine_target(2, r["N"], *workloads.modes_for("sixteen2d", r["seed"] * 8 + k))[0]
+        kind = "sixteen2d" if r["dim"] == 2 else "eight3d"
+        ys = [workloads.sine_target(r["dim"], r["N"], *workloads.modes_for(kind, r["seed"] * 8 + k))[0]
               for k in range(r["nrhs"])]
         inputs.append(torch.tensor(np.stack(ys), device="cuda:0"))
     torch.cuda.synchronize()
@@ -216,13 +217,16 @@ def run_serving(sfdp, torch, count, seed, tol_kkt, budget_gb):
         delay = r["arrival_ms"] / 1e3 - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        tickets.append(srv.submit(r["N"], 32, r["beta"], x))
+        tickets.append(srv.submit(r["N"], r["m"], r["beta"], x, dim=r["dim"], full_space=r["full_space"]))
     lat, rho, fails, errors = [], [], 0, {}
-    for tk in tickets:
+    by_kind = {}
+    for r, tk in zip(reqs, tickets):
         try:
             _, _, _, info, l, st = srv.poll(tk)
             lat.append(l)
             rho.extend(i["rel_kkt"] for i in info)
+            kind = f"{r['dim']}d_{'full' if r['full_space'] else 'range'}"
+            by_kind.setdefault(kind, []).append(l)
         except sfdp.SfdpError as e:
             fails += 1
             errors[str(e)] = errors.get(str(e), 0) + 1
@@ -235,8 +239,11 @@ def run_serving(sfdp, torch, count, seed, tol_kkt, budget_gb):
     lat.sort()
     q = lambda f: lat[min(len(lat) - 1, int(round(f * (len(lat) - 1))))]
     solved = sum(r["nrhs"] for r in reqs)
+    kinds = {k: {"requests": len(v), "p50_ms": sorted(v)[len(v) // 2]} for k, v in sorted(by_kind.items())}
     return {"requests": count, "seed": seed, "targets": solved, "mean_gap_ms": 5.0,
-            "meshes": "2D, N in 128..1024 (m = 32); the stream's 3D and full-space requests are not built",
+            "meshes": "2D N in 128..1024 (m = 32) with probability 0.75, else 3D N in 32..64 (m = 8); "
+                      "a quarter of the requests use the full-space method",
+            "kinds": kinds,
             "wall_s": wall, "solves_per_s": solved / wall, "requests_per_s": count / wall,
             "p50_ms": q(0.5), "p99_ms": q(0.99), "max_rel_kkt": max(rho), "failed": fails, "errors": errors,
             "setups": stats["setups"], "evictions": stats["evictions"], "ticks": stats["ticks"],

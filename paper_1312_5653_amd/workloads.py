@@ -108,18 +108,26 @@ def c4_instances(count: int, seed: int, sub_elem: int = 32):
 
 
 def c5_requests(count: int, seed: int, mean_gap_ms: float = 5.0, sub_elem: int = 32):
-    """Served request stream: exponential inter-arrival gaps (mean mean_gap_ms),
-    2D meshes N = sub_elem * round(exp(U[ln 128, ln 1024]) / sub_elem), beta =
-    10^U[-6,-1], nrhs uniform in 1..8, targets of 16 sine modes seeded by
-    (seed, request)."""
+    """Served request stream: exponential inter-arrival gaps (mean mean_gap_ms);
+    each request is 2D with probability 0.75, N = sub_elem round(exp(U[ln 128,
+    ln 1024]) / sub_elem) with subdomains of sub_elem^2, else 3D, N = 8
+    round(exp(U[ln 32, ln 64]) / 8) with subdomains of 8^3; with probability
+    0.25 it asks for the full-space method; beta = 10^U[-6,-1], nrhs uniform in
+    1..8, targets of 16 (2D) or 8 (3D) sine modes seeded by (seed, request)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
     for j in range(count):
         t += float(rng.exponential(mean_gap_ms))
-        N = int(sub_elem * round(np.exp(rng.uniform(np.log(128), np.log(1024))) / sub_elem))
+        dim = 2 if rng.uniform() < 0.75 else 3
+        if dim == 2:
+            N = int(sub_elem * round(np.exp(rng.uniform(np.log(128), np.log(1024))) / sub_elem))
+            N, m = max(N, 2 * sub_elem), sub_elem
+        else:
+            N, m = int(8 * round(np.exp(rng.uniform(np.log(32), np.log(64))) / 8)), 8
+        full_space = bool(rng.uniform() < 0.25)
         beta = float(10.0 ** rng.uniform(-6, -1))
         nrhs = int(rng.integers(1, 9))
-        out.append({"arrival_ms": t, "N": max(N, 2 * sub_elem), "beta": beta, "nrhs": nrhs,
-                    "seed": seed * 100003 + j})
+        out.append({"arrival_ms": t, "dim": dim, "N": N, "m": m, "full_space": full_space, "beta": beta,
+                    "nrhs": nrhs, "seed": seed * 100003 + j})
     return out
