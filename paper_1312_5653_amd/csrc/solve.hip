@@ -897,16 +897,39 @@ __device__ void phase_f1(const Geo2& g, const Maps2& mp, const RhsStride& rs,
   }
 }
 
+// g_r[c] = sum of Cbuf_r over the owners of coarse unknown c, for the coarse
+// unknowns c = b, b + nb, ... of block b of nb (each assembled once; a grid
+// barrier separates this from phase_f2, which reads all of them).
+template <int NRT>
+__device__ void phase_gco(const Maps2& mp, const RhsStride& rs, int nK, const cd* Cbuf, cd* gco, int nr, int b,
+                          int nb) {
+  for (int c = b + nb * (int)threadIdx.x; c < nK; c += nb * (int)blockDim.x) {
+    const int4 own = *(const int4*)(mp.cown + 4 * c);
+    const int ow[4] = {own.x, own.y, own.z, own.w};
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      if (r >= nr) break;
+      cd t[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) t[o] = ld_coh(Cbuf + r * rs.cq + max(ow[o], 0));
+      cd v{0.0, 0.0};
+#pragma unroll
+      for (int o = 0; o < 4; ++o) v = v + (ow[o] >= 0 ? t[o] : cd{0.0, 0.0});
+      st_coh(gco + r * rs.nc + c, v);
+    }
+  }
+}
+
 // Ybuf_r[s] += Phi uc_r over the subdomain's coarse slots, uc_r = Kinv g_r on
-// those slots and g_r[c] = sum of Cbuf_r over the owners of coarse unknown c.
-// Transposed product: thread t forms g_r[c] for c = t, t + 256, ... and
-// accumulates Kinv[c_q][c] g_r[c] for four slots q at a time (corner slots,
-// then, with an edge-augmented coarse space, edge slots); one block reduction
-// per pass gives uc_r[q].  wred holds 16 * NRT complex values, ucs NQ * NRT.
+// those slots, g_r the assembled coarse vector (phase_gco).  Transposed
+// product: thread t loads g_r[c] for c = t, t + 256, ... and accumulates
+// Kinv[c_q][c] g_r[c] for four slots q at a time (corner slots, then, with an
+// edge-augmented coarse space, edge slots); one block reduction per pass gives
+// uc_r[q].  wred holds 16 * NRT complex values, ucs NQ * NRT.
 template <class TS, int NRT>
 __device__ void phase_f2(const Geo2& g, const Maps2& mp, const RhsStride& rs,
                          const TS* __restrict__ Phi, const cd* __restrict__ Kinv, int s,
-                         const cd* Cbuf, cd* Ybuf, int nr, cd* ucs, cd* wred) {
+                         const cd* gco, cd* Ybuf, int nr, cd* ucs, cd* wred) {
   const int ND = g.ND, nd = mp.nd[s], nK = g.nK;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __syncthreads();
@@ -934,19 +957,9 @@ __device__ void phase_f2(const Geo2& g, const Maps2& mp, const RhsStride& rs,
     for (int r = 0; r < NRT; ++r) acc[q][r] = cd{0.0, 0.0};
   const bool edges = nK > g.nC;
   for (int c = threadIdx.x; c < nK; c += blockDim.x) {
-    const int4 own = *(const int4*)(mp.cown + 4 * c);
-    const int ow[4] = {own.x, own.y, own.z, own.w};
     cd gc[NRT];
 #pragma unroll
-    for (int r = 0; r < NRT; ++r) {
-      cd t[4];
-#pragma unroll
-      for (int o = 0; o < 4; ++o) t[o] = ld_coh(Cbuf + r * rs.cq + max(ow[o], 0));
-      cd v{0.0, 0.0};
-#pragma unroll
-      for (int o = 0; o < 4; ++o) v = v + (ow[o] >= 0 ? t[o] : cd{0.0, 0.0});
-      gc[r] = r < nr ? v : cd{0.0, 0.0};
-    }
+    for (int r = 0; r < NRT; ++r) gc[r] = r < nr ? ld_coh(gco + r * rs.nc + c) : cd{0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int cqq = cq[q];
@@ -1026,6 +1039,7 @@ struct GmresArgs {
   cd* Abuf;         // [r][nsub*ND]
   cd* Ybuf;         // [r][nsub*ND]
   cd* Cbuf;         // [r][nsub*4]
+  cd* gco;          // [r][nK] assembled coarse vector of the current iteration
   cd* w;            // [r][nmu]
   cd* Q;            // [r][kmax_alloc+1][nmu]
   cd* H;            // [r][kmax_alloc+1][kmax_alloc], column j at H[i*kstride + j]
@@ -1173,9 +1187,12 @@ __device__ inline void gmres_body(const Geo2& g, const Maps2& mp, const cf* __re
       phase_f1<TS, NRT>(g, mp, rs, Sinv, Phi, s, true, a.Abuf, nullptr, sc, a.Ybuf, a.Cbuf, nr, bufI,
                         a.resident, xs, red);
     grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
-    // ---- F2 (coarse correction)
+    // ---- F2 (coarse correction): assemble the coarse vector once, then every
+    // block applies the coarse inverse on its slots
+    phase_gco<NRT>(mp, rs, g.nK, a.Cbuf, a.gco, nr, b, nb);
+    grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
     for (int s = b; s < g.nsub; s += nb)
-      phase_f2<TS, NRT>(g, mp, rs, Phi, Kinv, s, a.Cbuf, a.Ybuf, nr, ucs, wred);
+      phase_f2<TS, NRT>(g, mp, rs, Phi, Kinv, s, a.gco, a.Ybuf, nr, ucs, wred);
     grid_barrier(a.bar, nb, b, epoch, a.flags + 1);
     // ---- O1: w_r = B_r Y_r (combine), first Gram-Schmidt projections
     if (mine)
@@ -1348,6 +1365,7 @@ __global__ void __launch_bounds__(256) k_gmres(Src src, GmresLaunch L) {
   a.Abuf = d.Abuf + L.r0 * rs.sb;
   a.Ybuf = d.Ybuf + L.r0 * rs.sb;
   a.Cbuf = d.Cbuf + L.r0 * rs.cq;
+  a.gco = d.ymin + L.r0 * rs.nc;  // ymin is free until the recovery
   a.w = d.wv + L.r0 * rs.nmu;
   a.Q = d.Qk;
   a.H = d.Hk;
@@ -1398,11 +1416,14 @@ __global__ void __launch_bounds__(256) k_iface_f1(Geo2 g, Maps2 mp, RhsStride rs
   phase_f1<TS, 1>(g, mp, rs, Sinv, Phi, blockIdx.x, false, nullptr, x, sc, Ybuf, Cbuf, 1, (TS*)smem,
                   false, xs, red);
 }
+__global__ void __launch_bounds__(256) k_iface_gco(Geo2 g, Maps2 mp, RhsStride rs, const cd* Cbuf, cd* gco) {
+  phase_gco<1>(mp, rs, g.nK, Cbuf, gco, 1, blockIdx.x, gridDim.x);
+}
 template <class TS>
 __global__ void __launch_bounds__(256) k_iface_f2(Geo2 g, Maps2 mp, RhsStride rs, const TS* Phi,
-                                                  const cd* Kinv, const cd* Cbuf, cd* Ybuf) {
+                                                  const cd* Kinv, const cd* gco, cd* Ybuf) {
   __shared__ cd ucs[NQ], wred[16];
-  phase_f2<TS, 1>(g, mp, rs, Phi, Kinv, blockIdx.x, Cbuf, Ybuf, 1, ucs, wred);
+  phase_f2<TS, 1>(g, mp, rs, Phi, Kinv, blockIdx.x, gco, Ybuf, 1, ucs, wred);
 }
 __global__ void k_combine(Geo2 g, Maps2 mp, const cd* buf, double scale, cd* out) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1689,8 +1710,9 @@ static hipError_t iface_t(Problem& p, char which, const cd* x, cd* y, hipStream_
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_iface_f1<TS>, dim3(p.nsub), dim3(256), bytes, st, g, mp, p.rs(),
                        (const TS*)p.Sinv, (const TS*)p.Phi, x, p.Ybuf, p.Cbuf);
+    hipLaunchKernelGGL(k_iface_gco, dim3(p.nsub), dim3(256), 0, st, g, mp, p.rs(), (const cd*)p.Cbuf, p.ymin);
     hipLaunchKernelGGL(k_iface_f2<TS>, dim3(p.nsub), dim3(256), 0, st, g, mp, p.rs(), (const TS*)p.Phi,
-                       p.Kinv, p.Cbuf, p.Ybuf);
+                       p.Kinv, (const cd*)p.ymin, p.Ybuf);
     hipLaunchKernelGGL(k_combine, dim3((p.nmu + 255) / 256), dim3(256), 0, st, g, mp, p.Ybuf, 1.0, y);
   } else {
     return hipErrorInvalidValue;
