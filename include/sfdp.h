@@ -129,6 +129,17 @@ typedef struct {
                             refinement steps (0 for the range-space calls) */
 } sfdp_info;
 
+/* Launch-variant autotuning (enable = 1, the default): kernels with variants
+ * that compute the same results in different launch shapes (the 2D subdomain
+ * solve with several right-hand sides: one workgroup for all or one per
+ * right-hand side; the 3D sweeps and interface products: the depth of their
+ * load pipeline) time every variant on the real operands the first time they
+ * run for a (kernel, shape, precision, right-hand sides) key on a device, and
+ * keep the fastest for the process.  enable = 0 runs fixed defaults.  Either
+ * call forgets the choices made so far.  Results do not depend on it beyond
+ * the rounding of multiply-add contraction (1e-12 relative). */
+sfdp_status sfdp_set_tuning(int enable);
+
 /* Sizes of a problem. */
 typedef struct {
   int64_t n_free;        /* unconstrained dofs (n_elem-1)^dim */

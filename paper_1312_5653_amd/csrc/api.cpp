@@ -1293,6 +1293,12 @@ static void sizes_of(const Problem* p, sfdp_sizes* out) {
   out->resident_bytes = (int64_t)p->bytes;
 }
 
+sfdp_status sfdp_set_tuning(int enable) {
+  if (enable != 0 && enable != 1) return fail(SFDP_E_INVALID, "enable must be 0 or 1");
+  tune_set_enabled(enable != 0);
+  return SFDP_OK;
+}
+
 sfdp_status sfdp_set_coarse_space(sfdp_problem* p, int edge_averages) {
   if (!p) return fail(SFDP_E_INVALID, "NULL argument");
   if (edge_averages != 0 && edge_averages != 1) return fail(SFDP_E_INVALID, "edge_averages must be 0 or 1");

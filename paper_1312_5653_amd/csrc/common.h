@@ -27,6 +27,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -450,6 +451,24 @@ static inline void launch2(const Target& t, int kind, KOne k1, KMany kn, int gy,
   else
     hipLaunchKernelGGL(kn, dim3(t.blocks(kind), gy), dim3(block), lds, t.st, t.srcN(kind), args...);
 }
+
+// ---- launch-variant autotuning (tune.cpp) ----
+enum TuneFamily : int { TUNE_LOCAL_SOLVE = 1, TUNE_K3_LOCAL = 2, TUNE_K3_SWEEP = 3 };
+struct TuneKey {
+  int family, device, k0, k1, k2, k3;  // kernel family, device, shape and precision fields
+  bool operator<(const TuneKey& o) const;
+};
+struct TuneEntry {
+  TuneKey key;
+  int choice;
+};
+// The variant to run for key: on the first call every candidate 0..ncand-1 is
+// launched (launch(c); candidates must compute the same results and may run
+// repeatedly) and timed on stream st; later calls return the kept choice.
+// fallback when tuning is off or timing fails.
+int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, const std::function<void(int)>& launch);
+void tune_set_enabled(bool on);            // also forgets every choice
+int tune_table(TuneEntry* out, int cap);   // choices made so far (returns their count)
 
 // ---- launchers implemented in the .hip files ----
 // set-up (every instance of the target; FP64 scratch in the views)

@@ -1447,17 +1447,33 @@ static void local_solve_t(const Target& t, int mode, int f, int conj_in, int x) 
           conj_in, x);
 }
 
-// Several right-hand sides: complex64 line factors go one workgroup per
-// right-hand side (the factors are re-read from L2; 134 vs 154 us at 512^2 with
-// four), complex128 ones one workgroup for all (their ring of prefetched lines
-// only stays in registers at one wave per SIMD).
+// Several right-hand sides: one workgroup per subdomain for all of them
+// (candidate 0), or one per subdomain and right-hand side (candidate 1: more
+// workgroups per CU, the line factors re-read from L2).  The autotuner picks;
+// without it, complex64 factors take candidate 1 (134 vs 154 us at 512^2 with
+// four) and complex128 ones candidate 0 (their ring of prefetched lines only
+// stays in registers at one wave per SIMD).
 template <class TS>
 static void local_solve_w(const Target& t, int mode, int f, int conj_in, int x, int nr) {
-  if (nr == 1) local_solve_t<TS, 1>(t, mode, f, conj_in, x);
-  else if (sizeof(TS) == sizeof(cf))
-    launch2(t, K_SUB, k_local_solve_rhs<TS, One>, k_local_solve_rhs<TS, Many>, nr, 256, 0, mode, f, conj_in, x);
-  else if (nr == 2) local_solve_t<TS, 2>(t, mode, f, conj_in, x);
-  else local_solve_t<TS, NRMAX>(t, mode, f, conj_in, x);
+  if (nr == 1) {
+    local_solve_t<TS, 1>(t, mode, f, conj_in, x);
+    return;
+  }
+  auto run = [&](int c) {
+    if (c == 1)
+      launch2(t, K_SUB, k_local_solve_rhs<TS, One>, k_local_solve_rhs<TS, Many>, nr, 256, 0, mode, f, conj_in, x);
+    else if (nr == 2)
+      local_solve_t<TS, 2>(t, mode, f, conj_in, x);
+    else
+      local_solve_t<TS, NRMAX>(t, mode, f, conj_in, x);
+  };
+  int dev = 0, ml = 0;
+  (void)hipGetDevice(&dev);
+  if (t.single()) ml = t.one->ml;
+  else
+    for (const Problem* p : t.probs) ml = std::max(ml, p->ml);
+  const TuneKey key{TUNE_LOCAL_SOLVE, dev, ml, t.blocks(K_SUB), (int)sizeof(TS), nr};
+  run(tune_choice(key, 2, sizeof(TS) == sizeof(cf) ? 1 : 0, t.st, run));
 }
 
 hipError_t launch_local_solve(const Target& t, int mode, int f, int conj_in, int x) {

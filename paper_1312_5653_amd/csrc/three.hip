@@ -270,7 +270,7 @@ __device__ inline cd local_rhs(const Geo3& g, const Maps3& mp, int s, int p, con
 // per row; Z_rr^-1 is symmetric, so row i is read as column i: coalesced, and
 // once for all nr right-hand sides).  mode 0 also gives the subdomain's corner
 // terms Wc[s][q] = f_q / 8 - (Phi^T f~)_q of f_c*.
-template <class TS>
+template <class TS, int U>
 __global__ void __launch_bounds__(1024) k3_sweep(Geo3 g, Maps3 mp, Str3 st, int nr, const TS* __restrict__ Zinv,
                                                  const cd* PhiFull, const cd* f, int conj, int mode,
                                                  const cd* uc, const cd* mu, cd* T, cd* Wc) {
@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(1024) k3_sweep(Geo3 g, Maps3 mp, Str3 st, int 
   const TS* Z = Zinv + (size_t)s * NR * NR;
   for (int i = threadIdx.x; i < NR; i += blockDim.x) {
     cd y[R3];
-    symcol_r3<2>(Z, NR, NR, i, ft, y);
+    symcol_r3<U>(Z, NR, NR, i, ft, y);
 #pragma unroll
     for (int r = 0; r < R3; ++r)
       if (r < nr) T[r * st.t + (size_t)s * NR + i] = y[r];
@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(1024) k3_sweep(Geo3 g, Maps3 mp, Str3 st, int 
 // Interface product on one subdomain for nr right-hand sides: xs = B_r^T x on
 // its Delta nodes (scaled by 1 / multiplicity when `scale`), Y_s = Mat xs,
 // Wc_s = Phi^T xs; Mat is read once for all of them.
-template <class TS>
+template <class TS, int U>
 __global__ void __launch_bounds__(1024) k3_local(Geo3 g, Maps3 mp, Str3 st, int nr, const TS* __restrict__ Mat,
                                                  const TS* __restrict__ Phi, int scale, const cd* x, int64_t xr,
                                                  cd* Y, cd* Wc) {
@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(1024) k3_local(Geo3 g, Maps3 mp, Str3 st, int 
     const TS* A = Mat + (size_t)s * ND * ND;
     for (int i = threadIdx.x; i < nd; i += blockDim.x) {
       cd y[R3];
-      symcol_r3<8>(A, ND, nd, i, xs, y);
+      symcol_r3<U>(A, ND, nd, i, xs, y);
 #pragma unroll
       for (int r = 0; r < R3; ++r)
         if (r < nr) Y[r * st.y + (size_t)s * ND + i] = y[r];
@@ -609,10 +609,25 @@ struct Ops3 {
     sr = Str3{pp.n_free, (int64_t)g.nsub * g.NR, (int64_t)g.nsub * g.ND, (int64_t)g.nsub * 8,
               (int64_t)std::max(g.nC, 1), (int64_t)g.nmu};
   }
+  // interface products: eight (candidate 0) or four loads in flight per thread
   template <class TS>
   void local_t(const void* Mat, const void* Phi, int scale, const cd* x, int64_t xr, cd* Y, cd* Wc) {
-    hipLaunchKernelGGL(k3_local<TS>, dim3(g.nsub), dim3(threads_local), sizeof(cd) * g.ND * R3, st, g, mp, sr,
-                       nr, (const TS*)Mat, (const TS*)Phi, scale, x, xr, Y, Wc);
+    auto run = [&](int c) {
+      if (c == 0)
+        hipLaunchKernelGGL((k3_local<TS, 8>), dim3(g.nsub), dim3(threads_local), sizeof(cd) * g.ND * R3, st, g, mp,
+                           sr, nr, (const TS*)Mat, (const TS*)Phi, scale, x, xr, Y, Wc);
+      else
+        hipLaunchKernelGGL((k3_local<TS, 4>), dim3(g.nsub), dim3(threads_local), sizeof(cd) * g.ND * R3, st, g, mp,
+                           sr, nr, (const TS*)Mat, (const TS*)Phi, scale, x, xr, Y, Wc);
+    };
+    if (!Mat) {
+      run(0);
+      return;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const TuneKey key{TUNE_K3_LOCAL, dev, g.ND, g.nsub, (int)sizeof(TS), nr};
+    run(tune_choice(key, 2, 0, st, run));
   }
   void local(const void* Mat, const void* Phi, int scale, const cd* x, int64_t xr, cd* Y, cd* Wc) {
     if (s32) local_t<cf>(Mat, Phi, scale, x, xr, Y, Wc);
@@ -628,14 +643,28 @@ struct Ops3 {
       hipLaunchKernelGGL(k3_scatter<cd>, grid, dim3(256), 0, st, g, mp, sr, Y, yr, ystride, yoff,
                          phi ? (const cd*)T.Phi : (const cd*)nullptr, (const cd*)T.uc, phis, scale, out, orr);
   }
-  void sweep(const cd* f, int conj, int mode) {
+  // full sweeps: two (candidate 0) or four loads in flight per thread
+  template <class TS>
+  void sweep_t(const cd* f, int conj, int mode) {
     const size_t lds = sizeof(cd) * g.NR * R3;
-    if (s32)
-      hipLaunchKernelGGL(k3_sweep<cf>, dim3(g.nsub), dim3(threads_sweep), lds, st, g, mp, sr, nr, (const cf*)T.Zinv,
-                         (const cd*)T.PhiFull, f, conj, mode, (const cd*)T.uc, (const cd*)T.mu, T.T, T.Wc);
-    else
-      hipLaunchKernelGGL(k3_sweep<cd>, dim3(g.nsub), dim3(threads_sweep), lds, st, g, mp, sr, nr, (const cd*)T.Zinv,
-                         (const cd*)T.PhiFull, f, conj, mode, (const cd*)T.uc, (const cd*)T.mu, T.T, T.Wc);
+    auto run = [&](int c) {
+      if (c == 0)
+        hipLaunchKernelGGL((k3_sweep<TS, 2>), dim3(g.nsub), dim3(threads_sweep), lds, st, g, mp, sr, nr,
+                           (const TS*)T.Zinv, (const cd*)T.PhiFull, f, conj, mode, (const cd*)T.uc, (const cd*)T.mu,
+                           T.T, T.Wc);
+      else
+        hipLaunchKernelGGL((k3_sweep<TS, 4>), dim3(g.nsub), dim3(threads_sweep), lds, st, g, mp, sr, nr,
+                           (const TS*)T.Zinv, (const cd*)T.PhiFull, f, conj, mode, (const cd*)T.uc, (const cd*)T.mu,
+                           T.T, T.Wc);
+    };
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const TuneKey key{TUNE_K3_SWEEP, dev, g.NR, g.nsub, (int)sizeof(TS), nr * 2 + mode};
+    run(tune_choice(key, 2, 0, st, run));
+  }
+  void sweep(const cd* f, int conj, int mode) {
+    if (s32) sweep_t<cf>(f, conj, mode);
+    else sweep_t<cd>(f, conj, mode);
   }
   // out = K_cc*^-1 (add + sum of Wc)
   void coarse(const cd* add, cd* out) {

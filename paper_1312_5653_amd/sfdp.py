@@ -25,7 +25,7 @@ EXPORTS = [
     "sfdp_batch_create", "sfdp_batch_destroy", "sfdp_batch_sizes", "sfdp_batch_set_beta",
     "sfdp_batch_solve_range_space", "sfdp_server_create", "sfdp_server_submit", "sfdp_server_poll",
     "sfdp_server_stats", "sfdp_server_destroy", "sfdp_set_coarse_space", "sfdp_batch_inspect",
-    "sfdp_solve_full_space",
+    "sfdp_solve_full_space", "sfdp_set_tuning",
 ]
 
 
@@ -106,6 +106,7 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_problem_destroy.restype = None
     lib.sfdp_set_beta.argtypes = [P, D]
     lib.sfdp_solve_range_space.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    lib.sfdp_set_tuning.argtypes = [I]
     lib.sfdp_solve_full_space.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.sfdp_apply_schur_inv.argtypes = [P, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.sfdp_feti_solve.argtypes = [P, I, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(I)]
@@ -442,3 +443,9 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def set_tuning(enable: bool):
+    """Launch-variant autotuning on (default) or off; either forgets earlier choices."""
+    load_library()
+    _check(_lib.sfdp_set_tuning(int(bool(enable))))
