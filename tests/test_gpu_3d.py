@@ -192,3 +192,23 @@ def test_range_space_3d_grouping_invariance(sf, prec):
             assert _rel(a, b) < 1e-12, q
         assert i4[q]["krylov_its"] == i1[q]["krylov_its"], q
     prob.close()
+
+
+def test_range_space_3d_full_configuration(sf):
+    """The 3D bench configuration itself: 64^3 cells, 8^3 subdomains of 8^3,
+    beta = 1e-4, four 8-mode targets in one group, mixed precision; every
+    result against the KKT gate of the oracle's assembled system."""
+    sfdp, ctx = sf
+    N, m, beta = 64, 8, 1e-4
+    A = fem.assemble(fem.Mesh(3, N))
+    ybar = np.stack([_target(N, s)[0] for s in range(4)])
+    prob = sfdp.Problem(ctx, 3, N, m, sfdp.SFDP_MIXED)
+    prob.set_beta(beta)
+    y, u, lam, info, st = prob.solve_range_space(_t(ybar), None, tol_kkt=1e-8)
+    assert st == 0, info
+    z = np.zeros(A["Kc"].shape[1])
+    for q in range(4):
+        rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar[q], z, *(v[q].cpu().numpy() for v in (y, u, lam)))
+        assert rho <= 1e-8, (q, rho, info[q])
+        assert info[q]["rel_kkt"] <= 1e-8, info[q]
+    prob.close()
