@@ -561,7 +561,7 @@ void free_workspace3(Problem& p) {
   for (cd** v : {&T.fcs, &T.uc, &T.gc}) dfree(p, (void*&)*v, sizeof(cd) * R * std::max(g.nC, 1));
   for (cd** v : {&T.d, &T.mu, &T.z, &T.w}) dfree(p, (void*&)*v, sizeof(cd) * R * nm);
   dfree(p, (void*&)T.V, sizeof(cd) * R * kk * nm);
-  dfree(p, (void*&)T.part, sizeof(cd) * R * kk * nb);
+  dfree(p, (void*&)T.part, sizeof(cd) * R * kk * 4 * nb);
   dfree(p, (void*&)T.hd, sizeof(cd) * R * (2 * kk + 1));
   dfree(p, (void*&)T.npart, sizeof(double) * R * nb);
   dfree(p, (void*&)T.nvd, sizeof(int) * R);
@@ -587,7 +587,7 @@ sfdp_status alloc_workspace3(Problem& p, int kmax) {
   for (cd** v : {&T.d, &T.mu, &T.z, &T.w})
     if ((s = dalloc(p, (void**)v, sizeof(cd) * R * nm))) return s;
   if ((s = dalloc(p, (void**)&T.V, sizeof(cd) * R * kk * nm)) ||
-      (s = dalloc(p, (void**)&T.part, sizeof(cd) * R * kk * nb)) ||
+      (s = dalloc(p, (void**)&T.part, sizeof(cd) * R * kk * 4 * nb)) ||
       (s = dalloc(p, (void**)&T.hd, sizeof(cd) * R * (2 * kk + 1))) ||
       (s = dalloc(p, (void**)&T.npart, sizeof(double) * R * nb)) || (s = dalloc(p, (void**)&T.nvd, sizeof(int) * R)))
     return s;

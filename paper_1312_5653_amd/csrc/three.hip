@@ -487,25 +487,37 @@ __global__ void k3_assemble(Geo3 g, Maps3 mp, Str3 st, const cd* T, const cd* uc
 // ---- Krylov vector kernels (length n, FP64 complex; right-hand side r =
 // blockIdx.y: vectors at + r * vr, coefficients at + r * hr, partial sums at
 // + r * pr) ----
-// part[i * nb + block] = sum over the block's entries of conj(V_i) w, i < nv
+// part[i * np + p] = sum over the entries of wave p (np = 4 gridDim.x waves) of
+// conj(V_i) w, i < nv: per-wave partial sums, no workgroup barrier
 __global__ void __launch_bounds__(256) k3_dots(int64_t n, int nv, const cd* V, int64_t vs, int64_t vr,
                                                const cd* w, int64_t wr, cd* part, int64_t pr) {
-  __shared__ cd sh[4];
   const int r = blockIdx.y;
   V += r * vr;
   w += r * wr;
   part += r * pr;
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const cd wv = t < n ? w[t] : cd{0.0, 0.0};
-  const int lane = threadIdx.x & 63, wi = threadIdx.x >> 6;
-  for (int i = 0; i < nv; ++i) {
+  const bool in = t < n;
+  const cd wv = in ? w[t] : cd{0.0, 0.0};
+  const int lane = threadIdx.x & 63;
+  const int64_t np = 4 * (int64_t)gridDim.x, pw = 4 * (int64_t)blockIdx.x + (threadIdx.x >> 6);
+  int i = 0;
+  for (; i + 3 < nv; i += 4) {
+    cd v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = in ? V[(i + u) * vs + t] : cd{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      cd a{0.0, 0.0};
+      fma_conj_acc(a, v[u], wv);
+      a = wsum(a);
+      if (lane == 0) part[(int64_t)(i + u) * np + pw] = a;
+    }
+  }
+  for (; i < nv; ++i) {
     cd a{0.0, 0.0};
-    if (t < n) fma_conj_acc(a, V[i * vs + t], wv);
+    if (in) fma_conj_acc(a, V[i * vs + t], wv);
     a = wsum(a);
-    if (lane == 0) sh[wi] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) part[(int64_t)i * gridDim.x + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    __syncthreads();
+    if (lane == 0) part[(int64_t)i * np + pw] = a;
   }
 }
 // h[i] = sum_b part[i * nb + b] in a fixed order (block x = i, y = r)
@@ -536,6 +548,7 @@ __global__ void __launch_bounds__(256) k3_axpy(int64_t n, int nv, const cd* V, i
   double q = 0.0;
   if (t < n) {
     cd a = w[t];
+#pragma unroll 4
     for (int i = 0; i < nv; ++i) a = a - h[i] * V[i * vs + t];
     w[t] = a;
     q = abs2(a);
@@ -709,7 +722,7 @@ hipError_t gmres3(Ops3& o, double tol, int kmax, int* its) {
   const unsigned nb = nb256(n);
   const int ks = T.kalloc + 1;       // stride of the two coefficient sets in a right-hand side's hd
   const int64_t hr = 2 * ks + 1;     // hd per right-hand side: h (pass 0), h (pass 1), squared norm
-  const int64_t vr = (int64_t)ks * n, pr = (int64_t)ks * nb;
+  const int64_t vr = (int64_t)ks * n, pr = (int64_t)ks * 4 * nb;  // part: 4 wave sums per block
   cd* V = T.V;
   cd* dn = T.hd + 2 * ks;            // squared norm of right-hand side r at dn[r * hr]
   auto sync_h = [&]() {
@@ -749,7 +762,7 @@ hipError_t gmres3(Ops3& o, double tol, int kmax, int* its) {
       cd* h = T.hd + pass * ks;
       hipLaunchKernelGGL(k3_dots, dim3(nb, nr), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, vr, (const cd*)vn,
                          vr, T.part, pr);
-      hipLaunchKernelGGL(k3_reduce, dim3(j + 1, nr), dim3(256), 0, st, (int)nb, (const cd*)T.part, pr, h, hr);
+      hipLaunchKernelGGL(k3_reduce, dim3(j + 1, nr), dim3(256), 0, st, (int)(4 * nb), (const cd*)T.part, pr, h, hr);
       hipLaunchKernelGGL(k3_axpy, dim3(nb, nr), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, vr, (const cd*)h, hr,
                          vn, vr, T.npart, (int64_t)nb);
     }
