@@ -14,7 +14,10 @@ O4  ``closed_form_sines``: exact discrete solution for targets made of
     discrete sine modes, which are common eigenvectors of K and M.
 O5  ``full_space_minres``: the full-space method (Sec. 3.2): MINRES on the
     KKT system with the block-diagonal preconditioner P_mgw = blkdiag(V,
-    phi V, S) of Murphy, Golub and Wathen, S^-1 by the two complex factors.
+    phi V, S) of Murphy, Golub and Wathen, S^-1 by the two complex factors,
+    or with S replaced by the approximation S_p of Pearson and Wathen.
+O6  ``pearson_wathen_inverse``: S_p^-1 r, S_p = F V^-1 F with the real
+    factor F = K + phi^(-1/2) V (Sec. 3.2, the equation of S_p).
 """
 from __future__ import annotations
 
@@ -179,23 +182,49 @@ def schur_inverse_two_factor(lu, M, r):
     return np.conj(lu.solve(np.conj(v))).real
 
 
-def full_space_minres(K, M, Kc, beta, ybar, yc=None, tol=1e-12, maxit=50, lu=None):
+def pearson_wathen_factor(K, M, beta: float):
+    """F = K + beta^(-1/2) M: the outer factor of the approximation
+    S_p = F M^-1 F of Pearson and Wathen (Sec. 3.2; phi is beta, V is M).
+    Real and symmetric positive definite, unlike the complex factor Z."""
+    return (K + beta ** -0.5 * M).tocsc()
+
+
+def pearson_wathen_inverse(lu_p, M, r):
+    """O6: S_p^-1 r = F^-1 M F^-1 r, with lu_p the LU of F
+    (``pearson_wathen_factor``).  S_p = S + 2 beta^(-1/2) K (the second form of
+    the same equation), so S_p^-1 S has its eigenvalues in [1/2, 1]."""
+    return lu_p.solve(M @ lu_p.solve(np.asarray(r, dtype=np.float64)))
+
+
+def full_space_minres(K, M, Kc, beta, ybar, yc=None, tol=1e-12, maxit=50, lu=None, schur="exact"):
     """O5: preconditioned MINRES (Paige and Saunders) on A x = b, the KKT system
     of Sec. 2, with P = blkdiag(M, beta M, S) (Sec. 3.2, the preconditioner of
     Murphy, Golub and Wathen, under which A has at most three distinct
-    eigenvalues).  Starts from x = 0; stops when the preconditioned residual
-    estimate falls below tol times its initial value.  Returns (y, u, lam) and
-    the iteration count."""
+    eigenvalues).  schur = "exact" applies S^-1 by the two complex factors;
+    "pearson_wathen" puts S_p in place of S (Sec. 3.2, compared with the
+    complex factorization in Table 7).  Starts from x = 0; stops when the
+    preconditioned residual estimate falls below tol times its initial value.
+    Returns (y, u, lam) and the iteration count."""
     n = K.shape[0]
     A = _kkt.kkt_matrix(K, M, beta)
     b = _kkt.kkt_rhs(M, Kc, ybar, yc)
-    if lu is None:
-        lu = spla.splu(complex_factor(K, M, beta))
     mlu = spla.splu(M.tocsc())
+    if schur == "exact":
+        if lu is None:
+            lu = spla.splu(complex_factor(K, M, beta))
+
+        def s_inv(r):
+            return schur_inverse_two_factor(lu, M, r)
+    elif schur == "pearson_wathen":
+        lu_p = spla.splu(pearson_wathen_factor(K, M, beta))
+
+        def s_inv(r):
+            return pearson_wathen_inverse(lu_p, M, r)
+    else:
+        raise ValueError(schur)
 
     def pinv(r):
-        return np.concatenate([mlu.solve(r[:n]), mlu.solve(r[n:2 * n]) / beta,
-                               schur_inverse_two_factor(lu, M, r[2 * n:])])
+        return np.concatenate([mlu.solve(r[:n]), mlu.solve(r[n:2 * n]) / beta, s_inv(r[2 * n:])])
 
     x = np.zeros(3 * n)
     r1 = b.copy()

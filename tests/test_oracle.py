@@ -369,3 +369,72 @@ def test_full_space_minres_converges_in_three_iterations(dim, N):
     ref = solve.range_space_two_factor(A["K"], A["M"], A["Kc"], beta, ybar, yc, paper_y=False)
     assert np.linalg.norm(lam - ref["lam"]) <= 1e-9 * np.linalg.norm(ref["lam"])
     assert kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc, y, u, lam) < 1e-10
+
+
+@pytest.mark.parametrize("dim,N", [(2, 12), (3, 6)])
+@pytest.mark.parametrize("beta", [1e-2, 1e-6])
+def test_pearson_wathen_on_sine_modes(dim, N, beta):
+    """Sec. 3.2, S_p = (K + phi^-1/2 V) V^-1 (K + phi^-1/2 V): each discrete sine
+    mode s_k is an eigenvector of K and M (eigenvalues a = mu_K, mu_M), so
+    S_p^-1 S s_k = (a^2 + c^2) / (a + c)^2 s_k with c = beta^-1/2 mu_M, a
+    number in [1/2, 1] (the bound of Pearson and Wathen).  A wrong sign of the
+    shift, a dropped M^-1 or a shift by beta instead of beta^-1/2 changes it."""
+    mesh = fem.Mesh(dim, N)
+    A = fem.assemble(mesh)
+    K, M = A["K"], A["M"]
+    xyz = mesh.node_xyz("free")
+    lu_p = spla.splu(solve.pearson_wathen_factor(K, M, beta))
+    ks = [(1, 1), (2, 3), (N - 1, 1), (N - 1, N - 1)] if dim == 2 else [(1, 1, 1), (2, 1, 3), (N - 1, N - 1, 1)]
+    seen = []
+    for kvec in ks:
+        s = np.ones(mesh.n)
+        for d, k in enumerate(kvec):
+            s = s * np.sin(k * np.pi * xyz[d])
+        muK, muM = solve.sine_mode_eigs(N, kvec)
+        Ss = muK * muK / muM * s + muM / beta * s  # S s = (mu_K^2 / mu_M + mu_M / beta) s
+        got = solve.pearson_wathen_inverse(lu_p, M, Ss)
+        c = beta ** -0.5 * muM
+        ratio = (muK ** 2 + c ** 2) / (muK + c) ** 2
+        assert np.linalg.norm(got - ratio * s) <= 1e-9 * np.linalg.norm(s), (kvec, ratio)
+        assert 0.5 - 1e-12 <= ratio <= 1.0
+        seen.append(ratio)
+    assert min(seen) < 0.99  # S_p is an approximation, not S
+
+
+def test_pearson_wathen_second_form_and_spectrum():
+    """S_p = S + 2 phi^-1/2 K (Sec. 3.2): S_p^-1 applied to that dense matrix
+    gives the identity, and S_p^-1 S has real eigenvalues in [1/2, 1] on a
+    whole small mesh (not only on sine modes)."""
+    N, beta = 6, 1e-4
+    A = fem.assemble(fem.Mesh(2, N))
+    K, M = A["K"], A["M"]
+    n = K.shape[0]
+    S = solve.dense_schur(K, M, beta)
+    Sp = S + 2 * beta ** -0.5 * K.toarray()
+    lu_p = spla.splu(solve.pearson_wathen_factor(K, M, beta))
+    X = np.column_stack([solve.pearson_wathen_inverse(lu_p, M, Sp[:, j]) for j in range(n)])
+    assert np.abs(X - np.eye(n)).max() < 1e-9
+    T = np.column_stack([solve.pearson_wathen_inverse(lu_p, M, S[:, j]) for j in range(n)])
+    ev = np.linalg.eigvals(T)
+    assert np.abs(ev.imag).max() < 1e-9
+    assert ev.real.min() >= 0.5 - 1e-9 and ev.real.max() <= 1.0 + 1e-9
+    assert ev.real.min() < 0.6  # the lower bound is nearly reached at beta = 1e-4
+
+
+@pytest.mark.parametrize("dim,N", [(2, 16), (3, 6)])
+def test_full_space_minres_with_pearson_wathen(dim, N):
+    """MINRES with S_p in place of S (Sec. 3.2, Table 7's comparison): the same
+    KKT solution, in more iterations than the exact S's three (a target with
+    every mode present: with a few sine modes the Krylov space is small)."""
+    beta = 1e-6
+    A = fem.assemble(fem.Mesh(dim, N))
+    ybar = W.random_vector(A["K"].shape[0], 4)
+    yc = W.random_vector(A["Kc"].shape[1], 5)
+    y, u, lam, its = solve.full_space_minres(A["K"], A["M"], A["Kc"], beta, ybar, yc, tol=1e-12,
+                                             maxit=200, schur="pearson_wathen")
+    _, _, _, its_exact = solve.full_space_minres(A["K"], A["M"], A["Kc"], beta, ybar, yc, tol=1e-12)
+    assert its_exact <= 3 and 10 < its < 60, (its, its_exact)
+    assert kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc, y, u, lam) < 1e-9
+    ref = solve.dense_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc) if dim == 2 else None
+    if ref is not None:
+        assert np.linalg.norm(lam - ref["lam"]) <= 1e-8 * np.linalg.norm(ref["lam"])
