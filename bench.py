@@ -274,7 +274,7 @@ def cpu_instances(count, seed, budget_s=10.0):
 
 
 def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup, tol_kkt, tol_inner,
-                  batch, max_krylov=0, factors=0, edges=None, dim=2, full_space=False):
+                  batch, max_krylov=0, factors=0, edges=None, dim=2, full_space=False, schur_block=0):
     p = sfdp.Problem(ctx, dim, N, m, precision)
     if edges is not None:
         p.set_coarse_space(edges)
@@ -288,9 +288,10 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
     lam = torch.empty_like(ybar_t)
     nb = ybar_t.shape[0]
     solve = p.solve_full_space if full_space else p.solve_range_space
+    sb = {"schur_block": schur_block} if schur_block else {}  # S_p factors: built in the first warmup call
     for _ in range(warmup):
         solve(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch,
-              max_krylov=max_krylov, factors=factors)
+              max_krylov=max_krylov, factors=factors, **sb)
     p.timing_enable(True)
     lat, rhos, its, feti, minres = [], [], [], [], []
     torch.cuda.synchronize()
@@ -298,7 +299,7 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
     for _ in range(steps):
         t0 = time.perf_counter()
         _, _, _, info, st = solve(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch,
-                                  max_krylov=max_krylov, factors=factors)
+                                  max_krylov=max_krylov, factors=factors, **sb)
         lat.append(time.perf_counter() - t0)
         rhos.extend(i["rel_kkt"] for i in info)
         its.extend(i["krylov_total"] for i in info)
@@ -430,6 +431,11 @@ def main():
         res[head + "_full_space"] = run_precision(sfdp, torch, ctx, hp, N, m, beta, ybar_t,
                                                   max(2, args.steps // 5), 1, tol_kkt, htin, B, args.max_krylov,
                                                   full_space=True)
+        # the same with the approximation S_p of Pearson and Wathen as the S
+        # block (Sec. 3.2, the comparison of Table 7)
+        res[head + "_full_space_pw"] = run_precision(sfdp, torch, ctx, hp, N, m, beta, ybar_t,
+                                                     max(2, args.steps // 5), 1, tol_kkt, htin, B, args.max_krylov,
+                                                     full_space=True, schur_block=1)
     r = res[head]
     kt = r["kernel_times"]
     sz = r["sizes"]
@@ -498,6 +504,9 @@ def main():
                   "setup_ms": o["setup_ms"]}
         if k.endswith("_full_space"):
             out[k]["method"] = "full-space MINRES, P_mgw with S^-1 by the complex factorization"
+            out[k]["minres_its_per_solve"] = o["minres_per_solve"]
+        if k.endswith("_full_space_pw"):
+            out[k]["method"] = "full-space MINRES, P_mgw with S_p (Pearson-Wathen) in place of S"
             out[k]["minres_its_per_solve"] = o["minres_per_solve"]
     if args.instances > 0 and not args.headline_only:
         out["instances_batch"] = run_instances(sfdp, torch, ctx, args.instances, 0, tol_kkt)

@@ -114,6 +114,16 @@ typedef struct {
                        serves up to this many right-hand sides in lockstep,
                        sharing every grid barrier and every pass over the
                        subdomain operators; results do not depend on it */
+  int schur_block;  /* the S block of sfdp_apply_schur_inv and of the full-space
+                       preconditioner [0]: 0 the exact S through its complex
+                       factorization (Sec. 4); 1 the approximation
+                       S_p = F M^-1 F, F = K + beta^-1/2 M, of Pearson and
+                       Wathen (Sec. 3.2; S_p^-1 S has its eigenvalues in
+                       [1/2, 1]).  S_p^-1 takes two FETI-DP solves with the
+                       real factor F, whose factors a twin of the problem
+                       holds (built on first use, and again after beta or the
+                       coarse space changes; its memory counts against the
+                       context's budget); opts->factors does not apply */
 } sfdp_opts;
 
 /* Per-solve report. */
@@ -208,8 +218,9 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
 
 /* z = S^-1 r for real r (n_free x nrhs), through the two complex factors
  * (Sec. 4): z = Re conj(Z^-1 conj(M Z^-1 r)).  This is the S block of the
- * block-diagonal preconditioner of Sec. 3.2.  info, if given, has nrhs
- * entries (two FETI-DP solves each). */
+ * block-diagonal preconditioner of Sec. 3.2.  With opts->schur_block = 1,
+ * z = S_p^-1 r = F^-1 M F^-1 r instead (Sec. 3.2, F = K + beta^-1/2 M).
+ * info, if given, has nrhs entries (two FETI-DP solves each). */
 sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, double* z,
                                  const sfdp_opts* opts, sfdp_info* info);
 
@@ -223,9 +234,11 @@ sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double*
  * Golub and Wathen: P_mgw^-1 A has at most three distinct eigenvalues), with
  * V^-1 exact (Kronecker product of 1D tridiagonal solves) and S^-1 through
  * the complex factorization (as sfdp_apply_schur_inv: opts->tol_inner and
- * opts->factors apply), inside FP64 iterative refinement on the KKT
- * residual: each refinement step runs MINRES on A dx = b - A x to a relative
- * preconditioned residual of 1e-6 (at most 30 iterations).  Arguments,
+ * opts->factors apply; opts->schur_block = 1 puts the approximation S_p of
+ * Pearson and Wathen in place of S, the comparison of Table 7), inside FP64
+ * iterative refinement on the KKT residual: each refinement step runs MINRES
+ * on A dx = b - A x to a relative preconditioned residual of 1e-6 (at most 30
+ * iterations with S, 100 with S_p).  Arguments,
  * layout, the start (ybar, 0, 0) and the stopping test (opts->tol_kkt) are
  * those of sfdp_solve_range_space; right-hand sides are solved one after
  * another.  info->outer_steps counts refinement steps, info->minres_its the

@@ -397,6 +397,7 @@ sfdp_status build_maps3(Problem& p) {
   g.nC = (P - 1) * (P - 1) * (P - 1);
   g.h = 1.0 / N;
   g.alpha = 0.0;
+  g.rshift = 0;
   const int NR = g.NR, ND = g.ND, nI = g.nI;
   std::vector<int> rl((size_t)nsub * NR, -1), rpos((size_t)nsub * nl, -1), nds(nsub, 0), cg(nsub * 8, -1);
   struct Inc {
@@ -1012,6 +1013,10 @@ void destroy_problem(Problem* p) {
   if (!p) return;
   hipSetDevice(p->ctx->device);
   hipStreamSynchronize(p->ctx->stream);
+  if (p->pw) {
+    destroy_problem(p->pw);
+    p->pw = nullptr;
+  }
   if (Three* T = p->t3) {
     free_factors3(*p);
     free_workspace3(*p);
@@ -1441,10 +1446,39 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
 sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, double* z,
                                  const sfdp_opts* opts, sfdp_info* info);
 
+namespace {
+// The twin of a problem that holds the FETI-DP factors of the real matrix
+// F = K + alpha M, the outer factor of the approximation S_p = F M^-1 F of
+// Pearson and Wathen (Sec. 3.2): the same mesh, subdomains, precision and
+// coarse space; created the first time S_p is used, factored again when beta
+// or the coarse space of the problem has changed since.
+sfdp_status ensure_pw(Problem* p) {
+  if (!p->pw) {
+    Problem* q = nullptr;
+    sfdp_status s = create_problem(p->ctx, p->dim, p->N, p->m, p->prec, &q);
+    if (s) return s;
+    q->rshift = true;
+    p->pw = q;
+  }
+  Problem* q = p->pw;
+  if (q->nK != p->nK) {
+    q->nK = p->nK;
+    q->factored = false;
+  }
+  if (q->factored && q->beta == p->beta) return SFDP_OK;
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  q->beta = p->beta;
+  q->alpha = p->alpha;
+  std::vector<Problem*> ps{q};
+  return setup_run(single_target(q), ps, nullptr);
+}
+}  // namespace
+
 // ---- full-space method: MINRES with P_mgw inside FP64 refinement ----
 namespace {
 constexpr double FS_MINRES_TOL = 1e-6;
-constexpr int FS_MINRES_MAXIT = 30;
+constexpr int FS_MINRES_MAXIT = 30;      // exact S: three distinct eigenvalues
+constexpr int FS_MINRES_MAXIT_SP = 100;  // S_p: eigenvalues of S_p^-1 S in [1/2, 1]
 
 struct FsCtx {
   sfdp_problem* p;
@@ -1454,6 +1488,7 @@ struct FsCtx {
   double* host;        // pinned
   sfdp_opts inner;
   sfdp_info* log;
+  int maxit;
 };
 
 sfdp_status fs_dot(FsCtx& c, const double* x, const double* y, double& out) {
@@ -1464,7 +1499,8 @@ sfdp_status fs_dot(FsCtx& c, const double* x, const double* y, double& out) {
   return SFDP_OK;
 }
 
-// out = P_mgw^-1 r: V^-1 r1, (phi V)^-1 r2, S^-1 r3 (two FETI-DP solves, or one)
+// out = P_mgw^-1 r: V^-1 r1, (phi V)^-1 r2, S^-1 r3 (two FETI-DP solves, or one;
+// with S_p in place of S: two solves with its real factor)
 sfdp_status fs_pinv(FsCtx& c, const double* r, double* out) {
   Problem* p = c.p;
   HIPCHK(launch_mass_inverse(*p, r, 1.0, out, c.st));
@@ -1501,7 +1537,7 @@ sfdp_status fs_minres(FsCtx& c, double* V, const double* rr, double* dx, int& it
   if (!(b1 > 0.0)) return SFDP_OK;
   const double beta1 = std::sqrt(b1);
   double bet = beta1, oldb = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta1, cs = -1.0, sn = 0.0;
-  for (int k = 1; k <= FS_MINRES_MAXIT; ++k) {
+  for (int k = 1; k <= c.maxit; ++k) {
     its = k;
     HIPCHK(launch_lin3(n3, 1.0 / bet, y, 0.0, nullptr, 0.0, nullptr, v, st));
     HIPCHK(launch_kkt_apply(*c.p, v, y, st));
@@ -1541,6 +1577,17 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
   sfdp_status s = check_ready(p);
   if (s) return s;
   if (nrhs <= 0 || !r || !z) return fail(SFDP_E_INVALID, "bad arguments");
+  if (opts && opts->schur_block != 0 && opts->schur_block != 1) return fail(SFDP_E_INVALID, "schur_block must be 0 or 1");
+  if (opts && opts->schur_block == 1) {
+    // S_p^-1 r = F^-1 M F^-1 r: the two-factor sequence on the twin, whose
+    // factor is real (so the conjugations and the real part change nothing)
+    HIPCHK(hipSetDevice(p->ctx->device));
+    if ((s = ensure_pw(p))) return s;
+    sfdp_opts o = *opts;
+    o.schur_block = 0;
+    o.factors = 2;
+    return sfdp_apply_schur_inv((sfdp_problem*)p->pw, nrhs, r, z, &o, info);
+  }
   double tk, ti;
   int mo, kmax;
   defaults(p->prec, opts, tk, ti, mo, kmax, p->dim);
@@ -1610,7 +1657,11 @@ sfdp_status sfdp_solve_full_space(sfdp_problem* p, int nrhs, const double* ybar,
       return fail(SFDP_E_NOMEM, "pinned host allocation");
     }
   }
-  FsCtx c{p, p->ctx->stream, n, n3, p->fsw + 10 * n3, p->fsw + 10 * n3 + nb, p->fsh, {}, nullptr};
+  if (opts && opts->schur_block != 0 && opts->schur_block != 1) return fail(SFDP_E_INVALID, "schur_block must be 0 or 1");
+  const bool sp = opts && opts->schur_block == 1;
+  if (sp && (s = ensure_pw(p))) return s;
+  FsCtx c{p, p->ctx->stream, n, n3, p->fsw + 10 * n3, p->fsw + 10 * n3 + nb, p->fsh, {}, nullptr,
+          sp ? FS_MINRES_MAXIT_SP : FS_MINRES_MAXIT};
   if (opts) c.inner = *opts;
   c.inner.batch = 1;
   double* Vw = p->fsw;            // 8 MINRES vectors

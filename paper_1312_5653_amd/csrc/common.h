@@ -118,7 +118,8 @@ constexpr int NQ = 8;
 struct Geo2 {
   int N, m, P, ml, nsub, ND, nmu, nC, nK;  // nK: coarse unknowns (nC, or nC + edges)
   double h, alpha;
-  int dim;  // 3: the free-node kernels of the range-space loop use the 3D grid
+  int dim;     // 3: the free-node kernels of the range-space loop use the 3D grid
+  int rshift;  // 1: the factor is the real K + alpha M (the outer factor of S_p)
   // subdomain coordinates
   __device__ __host__ inline int sx(int s) const { return s % P; }
   __device__ __host__ inline int sy(int s) const { return s / P; }
@@ -142,11 +143,13 @@ struct Geo2 {
   __device__ __host__ inline int mult(int a, int b) const {
     return ((a == 0 || a == m) ? 2 : 1) * ((b == 0 || b == m) ? 2 : 1);
   }
-  // local Neumann matrix entry Z((a,b),(a2,b2)) = K + i alpha M
+  // local Neumann matrix entry Z((a,b),(a2,b2)) = K + i alpha M (K + alpha M
+  // when rshift)
   __device__ __host__ inline cd zloc(int a, int b, int a2, int b2) const {
     Line1D L{h, m};
     double kx = L.k(a, a2), mx = L.mm(a, a2), ky = L.k(b, b2), my = L.mm(b, b2);
-    return cd{kx * my + mx * ky, alpha * mx * my};
+    const double kk = kx * my + mx * ky, mm = alpha * mx * my;
+    return rshift ? cd{kk + mm, 0.0} : cd{kk, mm};
   }
   // extended matrix E: Z on r x r, identity elsewhere
   __device__ __host__ inline cd eloc(int s, int a, int b, int a2, int b2) const {
@@ -295,6 +298,8 @@ struct Problem {
   sfdp_precision prec = SFDP_FP64;
   double beta = 0, alpha = 0;
   bool factored = false;
+  bool rshift = false;    // factors of K + alpha M instead of K + i alpha M
+  Problem* pw = nullptr;  // twin with rshift, built on first use of S_p (Sec. 3.2)
   Three* t3 = nullptr;  // dim = 3: maps, factors and workspaces of the 3D path
   double* fsw = nullptr;   // full-space method: device vectors (9 x 3 n_free + sums)
   double* fsh = nullptr;   // and its pinned host scalars
@@ -358,7 +363,7 @@ struct Problem {
                      (int64_t)nsub * NQ};
   }
   Geo2 geo() const {
-    return Geo2{N, m, P, ml, nsub, ND, nmu, nC, nK, 1.0 / N, alpha, dim};
+    return Geo2{N, m, P, ml, nsub, ND, nmu, nC, nK, 1.0 / N, alpha, dim, rshift ? 1 : 0};
   }
   // x-blocks of this instance in a launch of the given kind
   int blocks(int kind) const {

@@ -26,6 +26,7 @@ namespace sfdp {
 struct Geo3 {
   int N, m, P, ml, nsub, nl, nI, NR, ND, nmu, nC;
   double h, alpha;
+  int rshift;  // 1: the factor is the real K + alpha M (the outer factor of S_p)
   __host__ __device__ inline void loc(int l, int& a, int& b, int& c) const {
     a = l % ml;
     b = (l / ml) % ml;
@@ -56,7 +57,8 @@ struct Geo3 {
   __host__ __device__ inline int vertex(int q) const {
     return (q & 1) * m + ml * (((q >> 1) & 1) * m) + ml * ml * (((q >> 2) & 1) * m);
   }
-  // local Neumann matrix entry Z(l, l2) = K + i alpha M of the subdomain's elements
+  // local Neumann matrix entry Z(l, l2) = K + i alpha M of the subdomain's
+  // elements (K + alpha M when rshift)
   __host__ __device__ inline cd zloc(int l, int l2) const {
     int a, b, c, a2, b2, c2;
     loc(l, a, b, c);
@@ -65,7 +67,8 @@ struct Geo3 {
     Line1D L{h, m};
     const double kx = L.k(a, a2), mx = L.mm(a, a2), ky = L.k(b, b2), my = L.mm(b, b2), kz = L.k(c, c2),
                  mz = L.mm(c, c2);
-    return cd{kx * my * mz + mx * ky * mz + mx * my * kz, alpha * mx * my * mz};
+    const double kk = kx * my * mz + mx * ky * mz + mx * my * kz, mm = alpha * mx * my * mz;
+    return rshift ? cd{kk + mm, 0.0} : cd{kk, mm};
   }
 };
 

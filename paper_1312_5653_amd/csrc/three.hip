@@ -159,6 +159,7 @@ __global__ void k3_coarse_assemble(Geo3 g, Maps3 mp, const cd* Zcc, cd* Kcc) {
 hipError_t launch_setup3(Problem& p, cd* E, cd* work) {
   Three& T = *p.t3;
   T.g.alpha = p.alpha;
+  T.g.rshift = p.rshift ? 1 : 0;
   const Geo3 g = T.g;
   const Maps3 mp = T.maps();
   hipStream_t st = p.ctx->stream;

@@ -38,7 +38,7 @@ class SfdpError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("tol_kkt", ctypes.c_double), ("tol_inner", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("max_krylov", ctypes.c_int), ("factors", ctypes.c_int),
-                ("batch", ctypes.c_int)]
+                ("batch", ctypes.c_int), ("schur_block", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -156,8 +156,8 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(tol_kkt=0.0, tol_inner=0.0, max_outer=0, max_krylov=0, batch=0, factors=0):
-    return Opts(tol_kkt, tol_inner, max_outer, max_krylov, factors, batch)
+def _opts(tol_kkt=0.0, tol_inner=0.0, max_outer=0, max_krylov=0, batch=0, factors=0, schur_block=0):
+    return Opts(tol_kkt, tol_inner, max_outer, max_krylov, factors, batch, schur_block)
 
 
 class Context:
@@ -241,7 +241,8 @@ class Problem:
 
     def solve_full_space(self, ybar, yc=None, y=None, u=None, lam=None, **opts):
         """Full-space method: MINRES with the block-diagonal Schur preconditioner
-        inside FP64 refinement (same arguments and results as solve_range_space)."""
+        inside FP64 refinement (same arguments and results as solve_range_space);
+        schur_block=1 uses the Pearson-Wathen approximation S_p for its S block."""
         import torch
         nrhs = 1 if ybar.dim() == 1 else ybar.shape[0]
         y = torch.empty_like(ybar) if y is None else y
@@ -255,6 +256,7 @@ class Problem:
         return y, u, lam, [i.as_dict() for i in infos], st
 
     def apply_schur_inv(self, r, z=None, **opts):
+        """z = S^-1 r (schur_block=1: z = S_p^-1 r) for real r."""
         import torch
         nrhs = 1 if r.dim() == 1 else r.shape[0]
         z = torch.empty_like(r) if z is None else z

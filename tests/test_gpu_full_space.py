@@ -82,3 +82,73 @@ def test_mass_inverse(sf, dim, N):
     for r in range(2):
         assert _rel(z[r], lu.solve(x[r])) < 1e-12, r
     prob.close()
+
+
+@pytest.mark.parametrize("dim,N,m,prec", [(2, 64, 8, 0), (2, 64, 8, 1), (3, 12, 4, 0), (3, 12, 4, 1)])
+def test_pearson_wathen_inverse_against_oracle(sf, dim, N, m, prec):
+    """S_p^-1 r = F^-1 M F^-1 r with F = K + beta^-1/2 M (Sec. 3.2), two FETI-DP
+    solves with the real factor on the problem's twin, element by element
+    against the oracle's sparse direct solves; and, for w = S r, the quotient
+    (w, S_p^-1 w) / (w, S^-1 w) = (w, S_p^-1 w) / (w, r) lies in [1/2, 1]
+    (the eigenvalue bound of S_p^-1 S)."""
+    import scipy.sparse.linalg as spla
+    sfdp, ctx = sf
+    beta = 1e-4
+    A = fem.assemble(fem.Mesh(dim, N))
+    n = A["K"].shape[0]
+    r = np.stack([W.random_vector(n, 40 + q) for q in range(3)])
+    prob = sfdp.Problem(ctx, dim, N, m, prec)
+    prob.set_beta(beta)
+    tin = 1e-10 if prec == 0 else 3e-7
+    z, info = prob.apply_schur_inv(_t(r), schur_block=1, tol_inner=tin)
+    z = z.cpu().numpy()
+    lu_p = spla.splu(solve.pearson_wathen_factor(A["K"], A["M"], beta))
+    for q in range(3):
+        ref = solve.pearson_wathen_inverse(lu_p, A["M"], r[q])
+        assert _rel(z[q], ref) < (1e-8 if prec == 0 else 2e-5), (q, info[q])
+        assert info[q]["n_feti"] == 2, info[q]
+    mlu = spla.splu(A["M"].tocsc())
+    w = A["K"] @ mlu.solve(A["K"] @ r[0]) + A["M"] @ r[0] / beta
+    zw, _ = prob.apply_schur_inv(_t(w[None]), schur_block=1, tol_inner=tin)
+    ratio = float(w @ zw.cpu().numpy()[0]) / float(w @ r[0])
+    assert 0.5 - 1e-5 <= ratio <= 1.0 + 1e-5, ratio
+    # the exact S block is still what schur_block = 0 gives on the same problem
+    ze, _ = prob.apply_schur_inv(_t(r[:1]), tol_inner=tin)
+    lu = spla.splu(solve.complex_factor(A["K"], A["M"], beta).tocsc())
+    ref = solve.schur_inverse_two_factor(lu, A["M"], r[0])
+    assert _rel(ze.cpu().numpy()[0], ref) < (1e-8 if prec == 0 else 2e-5)
+    prob.close()
+
+
+@pytest.mark.parametrize("dim,N,m,prec", [(2, 64, 8, 0), (2, 64, 8, 1), (3, 12, 4, 1)])
+def test_full_space_with_pearson_wathen(sf, dim, N, m, prec):
+    """Full-space MINRES with S_p in place of S (Table 7's comparison): the
+    same KKT solution as with the exact S, in more MINRES iterations (the
+    spectrum is no longer three points)."""
+    sfdp, ctx = sf
+    beta = 1e-6
+    A = fem.assemble(fem.Mesh(dim, N))
+    n = A["K"].shape[0]
+    ybar = np.stack([W.random_vector(n, 50), W.sine_target(dim, N, *W.modes_for(
+        "four2d" if dim == 2 else "eight3d", 1))[0]])
+    prob = sfdp.Problem(ctx, dim, N, m, prec)
+    prob.set_beta(beta)
+    tol = 1e-10 if prec == 0 else 1e-8
+    res = {}
+    for sb in (0, 1):
+        y, u, lam, info, st = prob.solve_full_space(_t(ybar), None, tol_kkt=tol, schur_block=sb)
+        assert st == 0, (sb, info)
+        res[sb] = [v.cpu().numpy() for v in (y, u, lam)], info
+    z = np.zeros(A["Kc"].shape[1])
+    (y, u, lam), info = res[1]
+    (ye, ue, le), info_e = res[0]
+    for q in range(2):
+        rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar[q], z, y[q], u[q], lam[q])
+        assert rho <= tol, (q, rho, info[q])
+        assert _rel(lam[q], le[q]) < (1e-8 if prec == 0 else 1e-6), q
+        print(f"dim={dim} N={N} prec={prec} q={q}: S_p {info[q]['minres_its']} MINRES its "
+              f"({info[q]['n_feti']} FETI-DP solves), exact S {info_e[q]['minres_its']} "
+              f"({info_e[q]['n_feti']})")
+    # a target with every mode present needs more iterations with S_p
+    assert info[0]["minres_its"] > info_e[0]["minres_its"], (info[0], info_e[0])
+    prob.close()
