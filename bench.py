@@ -322,6 +322,48 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
             "kernel_times": kt, "sizes": sizes}
 
 
+def run_schur_blocks(sfdp, torch, ctx, precision, N, m, betas, ybar_t, tol_kkt, tol_inner):
+    """The comparison of Table 7 on this path: for each beta, the full-space
+    method with the exact S (complex factorization) and with S_p (Pearson and
+    Wathen) as the S block: set-up time of the factors (B), time of one S-block
+    application (S), MINRES iterations (NI; the paper's NI counts outer Krylov
+    iterations), FETI-DP solves and the time of one full-space solve (T)."""
+    rows = []
+    y0 = ybar_t[:1].contiguous()
+    for beta in betas:
+        p = sfdp.Problem(ctx, 2, N, m, precision)
+        sync = torch.cuda.synchronize
+        sync()
+        t0 = time.perf_counter()
+        p.set_beta(beta)
+        sync()
+        row = {"beta": beta, "exact": {"B_ms": (time.perf_counter() - t0) * 1e3},
+               "pearson_wathen": {}}
+        # the first S_p application also factors F = K + beta^-1/2 M (the twin)
+        t0 = time.perf_counter()
+        p.apply_schur_inv(y0, schur_block=1, tol_inner=tol_inner)
+        sync()
+        first = time.perf_counter() - t0
+        for key, sb in (("exact", 0), ("pearson_wathen", 1)):
+            t0 = time.perf_counter()
+            p.apply_schur_inv(y0, schur_block=sb, tol_inner=tol_inner)
+            sync()
+            row[key]["S_ms"] = (time.perf_counter() - t0) * 1e3
+        row["pearson_wathen"]["B_ms"] = first * 1e3 - row["pearson_wathen"]["S_ms"]
+        for key, sb in (("exact", 0), ("pearson_wathen", 1)):
+            t0 = time.perf_counter()
+            _, _, _, info, st = p.solve_full_space(y0, None, tol_kkt=tol_kkt, tol_inner=tol_inner, schur_block=sb)
+            sync()
+            row[key].update({"T_ms": (time.perf_counter() - t0) * 1e3, "NI": info[0]["minres_its"],
+                             "refinement_steps": info[0]["outer_steps"], "feti_solves": info[0]["n_feti"],
+                             "rel_kkt": info[0]["rel_kkt"], "status": st})
+        p.close()
+        rows.append(row)
+    return {"workload": f"{N}x{N} Q1, {(N // m) ** 2} subdomains of {m}x{m}, one target, "
+                        f"{'mixed' if precision == sfdp.SFDP_MIXED else 'fp64'}",
+            "rows": rows}
+
+
 def run_c3(sfdp, torch, ctx, N, beta, steps, tol_kkt, m=8, B=4):
     """The 3D configuration: Q1 trilinear Poisson control on N^3 cells in
     (N/m)^3 subdomains of m^3, B eight-mode product-of-sines targets per step,
@@ -369,6 +411,8 @@ def main():
                     help="3D configuration: N^3 cells in subdomains of 8^3 (0 skips it)")
     ap.add_argument("--c3-only", action="store_true", help="only the 3D configuration (for profiles)")
     ap.add_argument("--c3-steps", type=int, default=5)
+    ap.add_argument("--schur-betas", type=str, default="1e-2,1e-4,1e-6,1e-8,1e-10",
+                    help="betas of the S versus S_p full-space comparison ('' to skip)")
     ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB"),
                     help="write the traffic record from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
@@ -516,6 +560,10 @@ def main():
         out["serving"] = run_serving(sfdp, torch, args.requests, 0, tol_kkt, args.serve_budget_gb)
     if args.c3 > 0 and not args.headline_only:
         out["c3_3d"] = run_c3(sfdp, torch, ctx, args.c3, beta, args.c3_steps, tol_kkt)
+    if args.schur_betas and not args.headline_only:
+        betas = [float(b) for b in args.schur_betas.split(",")]
+        out["schur_block_comparison"] = run_schur_blocks(sfdp, torch, ctx, precs[0][1], N, m, betas, ybar_t,
+                                                         tol_kkt, precs[0][2])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, m, beta, ybar[0])
     ctx.close()
