@@ -265,7 +265,8 @@ __device__ inline void line_store(TS* dst, int n2, const TS (&reg)[GPT]) {
 // t_r[p] = sum_k G(p,k) z_r[k] for one line and nr <= NRT right-hand sides; G in
 // LDS stored transposed (G(p,k) at Gl[k*ml + p]); four wave groups split k,
 // partial sums reduced through LDS (red: [NRT][4][ML]).  z_r = z + r * ML,
-// out_r = out + r * xstride.
+// out_r = out + r * xstride.  Gl and z are no longer read when it returns; out
+// and red are, until the caller's next barrier.
 template <class TS, class T, int NRT>
 __device__ inline void line_mv(const TS* Gl, int ml, const T* z, T* red, T* out, int xstride,
                                bool subtract, int nr) {
@@ -275,9 +276,16 @@ __device__ inline void line_mv(const TS* Gl, int ml, const T* z, T* red, T* out,
 #pragma unroll
   for (int r = 0; r < NRT; ++r) acc[r] = T{0, 0};
   if (lane < ml) {
-    int k0 = wv * kq, k1 = min(ml, k0 + kq);
-    for (int k = k0; k < k1; ++k) {
-      const auto gk = cvt<typename real_of<T>::type>(Gl[k * ml + lane]);
+    // fixed trip count (kq <= KQ), clamped indices and out-of-range terms
+    // selected to zero: the wave issues its LDS reads back to back instead of
+    // waiting for each k's operands before the next (k0, k1 are wave-uniform)
+    constexpr int KQ = (ML + 3) / 4;
+    const int k0 = wv * kq, k1 = min(ml, k0 + kq);
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) {
+      const int k = min(k0 + u, ml - 1);
+      auto gk = cvt<typename real_of<T>::type>(Gl[k * ml + lane]);
+      if (k0 + u >= k1) gk = decltype(gk){0, 0};
 #pragma unroll
       for (int r = 0; r < NRT; ++r) fma_acc(acc[r], gk, z[r * ML + k]);
     }
@@ -294,7 +302,8 @@ __device__ inline void line_mv(const TS* Gl, int ml, const T* z, T* red, T* out,
     T* o = out + r * xstride + p;
     *o = subtract ? *o - s : s;
   }
-  lds_sync();
+  // no closing barrier: the caller's next barrier orders these writes (and the
+  // reads of red) before anything reads out or writes red again
 }
 
 // ------------------------------------------------------------------------------------------
@@ -420,7 +429,9 @@ __device__ inline void local_solve_body(const Geo2& g, const Maps2& mp, const Rh
           lds_sync();
           line_mv<TS, T, NRT>(gbuf, ml, zl, red, xall + ml * j, XS, true, nr);
         }
-        // stage the next step's line (ring slot (u + 1) % LRING), refill that slot
+        // stage the next step's line (ring slot (u + 1) % LRING), refill that slot:
+        // gbuf is free since line_mv's partial products, so one barrier orders
+        // both this store and line_mv's row sums before the next step
         if (t + 1 < nsteps) {
           line_store<TS>(gbuf, n2, greg[(u + 1) % LRING]);
           if (t + 1 + LRING < nsteps)
