@@ -95,7 +95,7 @@ typedef struct {
                        [1e-10 FP64, 1e-8 MIXED] */
   double tol_inner; /* relative interface residual of each FETI-DP solve
                        [1e-8 FP64, 3e-7 MIXED; with complex64 operators GMRES
-                       stagnates below about 5e-8] */
+                       stagnates below about 5e-8]; see also tol_inner_first */
   int max_outer;    /* outer refinement steps [8] */
   int max_krylov;   /* GMRES iterations per FETI-DP solve, <= 400 [64]; the GMRES
                        kernel keeps per-iteration state for this many steps in
@@ -124,6 +124,14 @@ typedef struct {
                        holds (built on first use, and again after beta or the
                        coarse space changes; its memory counts against the
                        context's budget); opts->factors does not apply */
+  double tol_inner_first; /* tol_inner of the first refinement step of
+                       sfdp_solve_range_space and sfdp_batch_solve_range_space
+                       [FP64: tol_inner; mixed: max(tol_inner, 1e-5)].  With
+                       complex64 interface operators the first step ends near
+                       a relative KKT residual of 5e-3 whether its solves stop
+                       at 3e-7 or 1e-5, and the second step corrects it, so a
+                       looser first solve saves GMRES iterations; set it to
+                       tol_inner for the same tolerance in every step */
 } sfdp_opts;
 
 /* Per-solve report. */

@@ -277,6 +277,15 @@ void defaults(sfdp_precision prec, const sfdp_opts* o, double& tol_kkt, double& 
   kmax = (o && o->max_krylov > 0) ? std::min(o->max_krylov, KMAX_LIMIT) : (dim == 3 ? 300 : 64);
 }
 int batch_of(const sfdp_opts* o) { return (o && o->batch > 0) ? std::min(o->batch, NRMAX) : NRMAX; }
+// Inner tolerance of the first refinement step: with complex64 interface
+// operators that step ends near a relative KKT residual of 5e-3 whether its
+// FETI-DP solves stop at 3e-7 or 1e-5, so it defaults to 1e-5 there (never
+// tighter than tol_inner); FP64 reaches the gate in one step and keeps tol_inner.
+constexpr double MIXED_FIRST_TOL = 1e-5;
+double first_tol(sfdp_precision prec, const sfdp_opts* o, double tol_inner) {
+  if (o && o->tol_inner_first > 0) return o->tol_inner_first;
+  return prec == SFDP_FP64 ? tol_inner : std::max(tol_inner, MIXED_FIRST_TOL);
+}
 bool single_of(const sfdp_opts* o) { return o && o->factors == 1; }
 
 sfdp_status check_ready(const Problem* p) {
@@ -821,8 +830,8 @@ constexpr unsigned IDENTITY_MAP = 0x03020100u;
 // its own test.  info[i] has ps[i]->nr entries.  M is the batch (null for a
 // single problem); dg / hg hold one Gathered record per problem.
 sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Multi* M, Gathered* dg,
-                            Gathered* hg, double tol_kkt, double tol_inner, int max_outer, int kmax,
-                            const std::vector<sfdp_info*>& info, bool single) {
+                            Gathered* hg, double tol_kkt, double tol_first, double tol_inner, int max_outer,
+                            int kmax, const std::vector<sfdp_info*>& info, bool single) {
   const size_t n = ps.size();
   hipStream_t st = t.st;
   std::vector<int> ng(n);
@@ -870,16 +879,18 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
       any = any || nb2 > 0;
     }
     if (!any) break;
+    // the first step's inner tolerance may be looser (tol_inner_first)
+    const double tin = step == 0 ? tol_first : tol_inner;
     if (M) {
       sfdp_status s = multi_upload(*M);
       if (s) return s;
     }
     HIPCHK(launch_make_rhs1(t));
-    sfdp_status s = feti_run(t, timed, V_CVEC, 0, V_CVEC2, tol_inner, kmax);
+    sfdp_status s = feti_run(t, timed, V_CVEC, 0, V_CVEC2, tin, kmax);
     if (s) return s;
     if (!single) {
       HIPCHK(launch_make_rhs2(t));
-      s = feti_run(t, timed, V_CVEC3, 0, V_CVEC, tol_inner, kmax);
+      s = feti_run(t, timed, V_CVEC3, 0, V_CVEC, tin, kmax);
       if (s) return s;
     }
     HIPCHK(launch_update(t, single ? 1 : 0));
@@ -1435,7 +1446,8 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
     p->set_slots(ng, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, y + r0 * n, u + r0 * n,
                  lam + r0 * n);
     std::vector<sfdp_info*> inf{info ? info + r0 : nullptr};
-    s = range_space_run(t, ps, nullptr, p->gd, p->gh, tk, ti, mo, kmax, inf, single_of(opts));
+    s = range_space_run(t, ps, nullptr, p->gd, p->gh, tk, first_tol(p->prec, opts, ti), ti, mo, kmax, inf,
+                        single_of(opts));
     p->nr = 0;
     if (s == SFDP_E_NOCONV) worst = s;
     else if (s) return s;
@@ -1822,7 +1834,8 @@ sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const d
     }
     sfdp_status s = multi_groups(b->M, kmax, w == 1 ? 1 : w == 2 ? 2 : 4, b->gmap, b->gcap);
     if (!s)
-      s = range_space_run(b->M.t, b->probs, &b->M, b->M.dgather, b->M.hgather, tk, ti, mo, kmax, inf,
+      s = range_space_run(b->M.t, b->probs, &b->M, b->M.dgather, b->M.hgather, tk,
+                          first_tol(b->probs[0]->prec, opts, ti), ti, mo, kmax, inf,
                           single_of(opts));
     for (Problem* p : b->probs) p->nr = 0;
     if (s == SFDP_E_NOCONV) worst = s;

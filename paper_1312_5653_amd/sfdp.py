@@ -38,7 +38,7 @@ class SfdpError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("tol_kkt", ctypes.c_double), ("tol_inner", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("max_krylov", ctypes.c_int), ("factors", ctypes.c_int),
-                ("batch", ctypes.c_int), ("schur_block", ctypes.c_int)]
+                ("batch", ctypes.c_int), ("schur_block", ctypes.c_int), ("tol_inner_first", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -156,8 +156,9 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(tol_kkt=0.0, tol_inner=0.0, max_outer=0, max_krylov=0, batch=0, factors=0, schur_block=0):
-    return Opts(tol_kkt, tol_inner, max_outer, max_krylov, factors, batch, schur_block)
+def _opts(tol_kkt=0.0, tol_inner=0.0, max_outer=0, max_krylov=0, batch=0, factors=0, schur_block=0,
+          tol_inner_first=0.0):
+    return Opts(tol_kkt, tol_inner, max_outer, max_krylov, factors, batch, schur_block, tol_inner_first)
 
 
 class Context:
