@@ -224,3 +224,41 @@ def test_single_solve_variant(sf, prec):
         assert _rel(z[q].cpu().numpy(), np.linalg.solve(S, r[q])) < (1e-8 if prec == 0 else 1e-4)
     p16.close()
     prob.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_first_step_inner_tolerance(sf, prec):
+    """opts.tol_inner_first: the mixed path solves its first refinement step to
+    1e-5 by default (that step's result is bounded near 5e-3 by the complex64
+    operators), FP64 keeps tol_inner.  Default and tol_inner_first = tol_inner
+    both meet the KKT gate of the oracle's assembled system; on the mixed path
+    the default takes fewer GMRES iterations in the first step's solves and the
+    same number of steps; on FP64 the two runs are the same solve."""
+    sfdp, ctx = sf
+    N, m, beta = 128, 16, 1e-4
+    A = fem.assemble(fem.Mesh(2, N))
+    ybar = np.stack([W.sine_target(2, N, *W.modes_for("sixteen2d", s))[0] for s in range(3)])
+    prob = sfdp.Problem(ctx, 2, N, m, prec)
+    prob.set_beta(beta)
+    tin = 1e-10 if prec == 0 else 3e-7
+    runs = {}
+    for key, kw in (("default", {}), ("same", {"tol_inner_first": tin})):
+        y, u, lam, info, st = prob.solve_range_space(_t(ybar), None, tol_kkt=1e-8, tol_inner=tin, **kw)
+        assert st == 0, (key, info)
+        runs[key] = [v.cpu().numpy() for v in (y, u, lam)], info
+    z = np.zeros(A["Kc"].shape[1])
+    for key, ((y, u, lam), info) in runs.items():
+        for q in range(3):
+            rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar[q], z, y[q], u[q], lam[q])
+            assert rho <= 1e-8, (key, q, rho, info[q])
+    d, s = runs["default"][1], runs["same"][1]
+    for q in range(3):
+        if prec == 0:
+            assert d[q]["krylov_its"] == s[q]["krylov_its"], (d[q], s[q])
+        else:
+            assert d[q]["outer_steps"] == s[q]["outer_steps"], (d[q], s[q])
+            assert d[q]["krylov_its"][0] < s[q]["krylov_its"][0], (d[q], s[q])
+            assert d[q]["krylov_total"] < s[q]["krylov_total"], (d[q], s[q])
+        print(f"prec={prec} q={q}: default {d[q]['krylov_its'][:d[q]['n_feti']]} rho={d[q]['rel_kkt']:.1e}; "
+              f"tol_inner throughout {s[q]['krylov_its'][:s[q]['n_feti']]} rho={s[q]['rel_kkt']:.1e}")
+    prob.close()
