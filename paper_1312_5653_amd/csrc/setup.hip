@@ -90,21 +90,6 @@ __global__ void __launch_bounds__(256) k_factor_lines(Src src) {
   }
 }
 
-// Right-hand side column `col` of the multi-solve at local node (a, b).
-__device__ inline cd multi_rhs(const Geo2& g, int s, int a, int b, int col, int nd, int nc,
-                               const int* dloc, const int* cloc) {
-  if (!g.rnode(s, a, b)) return cd{0.0, 0.0};
-  int l = a + g.ml * b;
-  if (col < nd) return (dloc[col] == l) ? cd{1.0, 0.0} : cd{0.0, 0.0};
-  if (col < nd + nc) {
-    int cl = cloc[col - nd];
-    int ca = cl % g.ml, cb = cl / g.ml;
-    if (abs(ca - a) > 1 || abs(cb - b) > 1) return cd{0.0, 0.0};
-    return g.zloc(a, b, ca, cb);
-  }
-  return cd{0.0, 0.0};
-}
-
 template <class Src>
 __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
   const Dev& d = src.dev();
@@ -121,11 +106,41 @@ __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
   __shared__ int slotmap[MLMAX * MLMAX];
   __shared__ int sdl[128];
   __shared__ int scl[4];
+  // per-subdomain tables, so that each panel entry takes lookups instead of
+  // node classes and 1D element values: the r-node mask of the local nodes;
+  // the coupling of node p of a line to node p + d - 1 of the next or the
+  // previous line (the same for every pair of lines, masked per use); and the
+  // Z entries between each corner and the 3 x 3 nodes around it
+  __shared__ unsigned char rmk[MLMAX * MLMAX];
+  __shared__ cd cpl[MLMAX][3];
+  __shared__ cd cst[4][9];
+  __shared__ int cab[4][2];
   const int s = src.bx(), ml = g.ml, n2 = ml * ml, ND = g.ND;
   const int nd = mp.nd[s];
   int nc = 0;
   for (int q = 0; q < 4; ++q) nc += (mp.cloc[s * 4 + q] >= 0);
-  for (int l = threadIdx.x; l < n2; l += blockDim.x) slotmap[l] = -1;
+  for (int l = threadIdx.x; l < n2; l += blockDim.x) {
+    slotmap[l] = -1;
+    rmk[l] = g.rnode(s, l % ml, l / ml) ? 1 : 0;
+  }
+  if (threadIdx.x < ml * 3) {
+    const int p = threadIdx.x / 3, d = threadIdx.x % 3, a = p + d - 1;
+    cpl[p][d] = (a >= 0 && a < ml) ? g.zloc(p, 1, a, 0) : cd{0.0, 0.0};
+  }
+  if (threadIdx.x < 36) {
+    const int q = threadIdx.x / 9, e = threadIdx.x % 9;
+    const int cl = mp.cloc[s * 4 + q];  // corners are listed first (compact)
+    cd v{0.0, 0.0};
+    if (cl >= 0) {
+      const int ca = cl % ml, cb = cl / ml, a = ca + e % 3 - 1, b = cb + e / 3 - 1;
+      if (a >= 0 && a < ml && b >= 0 && b < ml) v = g.zloc(a, b, ca, cb);
+      if (e == 0) {
+        cab[q][0] = ca;
+        cab[q][1] = cb;
+      }
+    }
+    cst[q][e] = v;
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < nd; i += blockDim.x) {
     int l = mp.dloc[s * ND + i];
@@ -142,13 +157,22 @@ __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
       const cd* Gj = G64 + ((size_t)s * ml + j) * n2;
       for (int idx = threadIdx.x; idx < n2; idx += blockDim.x) Gl[idx] = Gj[idx];
       for (int idx = threadIdx.x; idx < ml * CW; idx += blockDim.x) {
-        int p = idx / CW, c = idx % CW;
-        cd v = multi_rhs(g, s, p, j, c0 + c, nd, nc, sdl, scl);
-        if (j > 0) {
-          for (int a = max(p - 1, 0); a <= min(p + 1, ml - 1); ++a) {
-            cd e = g.eloc(s, p, j, a, j - 1);
-            v = v - e * tb[a * CW + c];
+        const int p = idx / CW, c = idx % CW, col = c0 + c;
+        // rhs: the unit vector of a Delta column or Z_rc of a corner column on
+        // r rows; minus the coupling to the previous line's r nodes
+        cd v{0.0, 0.0};
+        if (rmk[p + ml * j]) {
+          if (col < nd) {
+            if (sdl[col] == p + ml * j) v = cd{1.0, 0.0};
+          } else if (col < nd + nc) {
+            const int q = col - nd, da = p - cab[q][0] + 1, db = j - cab[q][1] + 1;
+            if (da >= 0 && da < 3 && db >= 0 && db < 3) v = cst[q][da + 3 * db];
           }
+          if (j > 0)
+            for (int d = 0; d < 3; ++d) {
+              const int a = p + d - 1;
+              if (a >= 0 && a < ml && rmk[a + ml * (j - 1)]) v = v - cpl[p][d] * tb[a * CW + c];
+            }
         }
         zb[idx] = v;
       }
@@ -185,10 +209,13 @@ __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
         const cd* Gj = G64 + ((size_t)s * ml + j) * n2;
         for (int idx = threadIdx.x; idx < n2; idx += blockDim.x) Gl[idx] = Gj[idx];
         for (int idx = threadIdx.x; idx < ml * CW; idx += blockDim.x) {
-          int p = idx / CW, c = idx % CW;
+          const int p = idx / CW, c = idx % CW;
           cd v{0.0, 0.0};
-          for (int a = max(p - 1, 0); a <= min(p + 1, ml - 1); ++a)
-            fma_acc(v, g.eloc(s, p, j, a, j + 1), tb[a * CW + c]);
+          if (rmk[p + ml * j])
+            for (int d = 0; d < 3; ++d) {
+              const int a = p + d - 1;
+              if (a >= 0 && a < ml && rmk[a + ml * (j + 1)]) fma_acc(v, cpl[p][d], tb[a * CW + c]);
+            }
           zb[idx] = v;
         }
         __syncthreads();
