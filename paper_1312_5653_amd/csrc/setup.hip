@@ -56,24 +56,50 @@ __global__ void __launch_bounds__(256) k_factor_lines(Src src) {
   __shared__ cd T[MLMAX * MLMAX];
   __shared__ cd Gp[MLMAX * MLMAX];
   __shared__ cd rowk[MLMAX], colk[MLMAX];
+  // per-subdomain tables: r-node mask; the coupling of node p of a line to
+  // node p + d - 1 of the neighbouring line (the same for every pair of lines
+  // and, the 1D matrices being symmetric, in both directions); Z between nodes
+  // p and p + d - 1 of one line, for the two boundary lines [0] and the
+  // interior lines [1] (E is Z on r x r and the identity elsewhere)
+  __shared__ unsigned char rmk[MLMAX * MLMAX];
+  __shared__ cd cpl[MLMAX][3];
+  __shared__ cd dgl[2][MLMAX][3];
   const Dev& d = src.dev();
   const Geo2& g = d.g;
   cd* G64 = d.G64;
   const int s = src.bx(), ml = g.ml, n2 = ml * ml;
+  for (int l = threadIdx.x; l < n2; l += blockDim.x) rmk[l] = g.rnode(s, l % ml, l / ml) ? 1 : 0;
+  if (threadIdx.x < ml * 3) {
+    const int p = threadIdx.x / 3, e = threadIdx.x % 3, a = p + e - 1;
+    const bool ok = a >= 0 && a < ml;
+    cpl[p][e] = ok ? g.zloc(p, 1, a, 0) : cd{0.0, 0.0};
+    dgl[0][p][e] = ok ? g.zloc(p, 0, a, 0) : cd{0.0, 0.0};
+    dgl[1][p][e] = ok ? g.zloc(p, 1, a, 1) : cd{0.0, 0.0};
+  }
+  __syncthreads();
   for (int j = 0; j < ml; ++j) {
+    const int lt = (j == 0 || j == ml - 1) ? 0 : 1;
     for (int idx = threadIdx.x; idx < n2; idx += blockDim.x) {
-      int p = idx / ml, q = idx % ml;
-      cd v = g.eloc(s, p, j, q, j);
-      if (j > 0) {
-        for (int a = max(p - 1, 0); a <= min(p + 1, ml - 1); ++a) {
-          cd ea = g.eloc(s, p, j, a, j - 1);
-          if (ea.x == 0.0 && ea.y == 0.0) continue;
+      const int p = idx / ml, q = idx % ml;
+      // E_jj - E_j,j-1 G_j-1 E_j-1,j (masked couplings skipped, same order)
+      const bool rp = rmk[p + ml * j], rq = rmk[q + ml * j];
+      cd v{0.0, 0.0};
+      if (rp && rq) {
+        if (q >= p - 1 && q <= p + 1) v = dgl[lt][p][q - p + 1];
+      } else if (p == q) {
+        v = cd{1.0, 0.0};
+      }
+      if (j > 0 && rp && rq) {
+        for (int e = 0; e < 3; ++e) {
+          const int a = p + e - 1;
+          if (a < 0 || a >= ml || !rmk[a + ml * (j - 1)]) continue;
           cd acc{0.0, 0.0};
-          for (int b = max(q - 1, 0); b <= min(q + 1, ml - 1); ++b) {
-            cd eb = g.eloc(s, b, j - 1, q, j);
-            fma_acc(acc, Gp[a * ml + b], eb);
+          for (int f = 0; f < 3; ++f) {
+            const int b = q + f - 1;
+            if (b < 0 || b >= ml || !rmk[b + ml * (j - 1)]) continue;
+            fma_acc(acc, Gp[a * ml + b], cpl[b][q - b + 1]);
           }
-          v = v - ea * acc;
+          v = v - cpl[p][e] * acc;
         }
       }
       T[idx] = v;
