@@ -152,3 +152,27 @@ def test_full_space_with_pearson_wathen(sf, dim, N, m, prec):
     # a target with every mode present needs more iterations with S_p
     assert info[0]["minres_its"] > info_e[0]["minres_its"], (info[0], info_e[0])
     prob.close()
+
+
+def test_pearson_wathen_twin_follows_beta_and_coarse_space(sf):
+    """The factors of F = K + beta^-1/2 M live in a twin of the problem: after
+    sfdp_set_beta with a new beta, and after a change of the coarse space,
+    S_p^-1 r must be that of the new beta (against the oracle's direct solves
+    each time); schur_block values other than 0 and 1 are rejected."""
+    import scipy.sparse.linalg as spla
+    sfdp, ctx = sf
+    N, m = 64, 8
+    A = fem.assemble(fem.Mesh(2, N))
+    r = W.random_vector(A["K"].shape[0], 81)
+    prob = sfdp.Problem(ctx, 2, N, m, sfdp.SFDP_FP64)
+    for beta, edges in ((1e-4, True), (1e-7, True), (1e-7, False), (1e-2, False)):
+        if not edges:
+            prob.set_coarse_space(False)
+        prob.set_beta(beta)
+        z, info = prob.apply_schur_inv(_t(r[None]), schur_block=1, tol_inner=1e-11)
+        lu_p = spla.splu(solve.pearson_wathen_factor(A["K"], A["M"], beta))
+        ref = solve.pearson_wathen_inverse(lu_p, A["M"], r)
+        assert _rel(z.cpu().numpy()[0], ref) < 1e-8, (beta, edges, info)
+    with pytest.raises(sfdp.SfdpError):
+        prob.apply_schur_inv(_t(r[None]), schur_block=2)
+    prob.close()
