@@ -320,6 +320,31 @@ def test_error_codes(sf):
     prob.close()
 
 
+def test_argument_checks(sf):
+    """Arguments the C ABI rejects with SFDP_E_INVALID before any launch: 3D
+    subdomains of more than 9 cells a side, edge averages on a 3D problem, an
+    empty batch of right-hand sides, schur_block outside {0, 1}."""
+    sfdp, ctx = sf
+    with pytest.raises(sfdp.SfdpError) as e:
+        sfdp.Problem(ctx, 3, 40, 10)
+    assert e.value.status == -1
+    p3 = sfdp.Problem(ctx, 3, 8, 4)
+    with pytest.raises(sfdp.SfdpError) as e:
+        p3.set_coarse_space(True)
+    assert e.value.status == -1
+    p3.close()
+    prob = sfdp.Problem(ctx, 2, 32, 8)
+    prob.set_beta(1e-4)
+    with pytest.raises(sfdp.SfdpError) as e:
+        prob.apply_schur_inv(torch.empty((0, prob.n_free), dtype=torch.float64, device=DEV))
+    assert e.value.status == -1
+    for bad in (-1, 2):
+        with pytest.raises(sfdp.SfdpError) as e:
+            prob.solve_full_space(_t(np.ones(prob.n_free)), schur_block=bad)
+        assert e.value.status == -1
+    prob.close()
+
+
 def test_solves_are_deterministic(sf):
     sfdp, ctx = sf
     N, modes, coefs, ybar, yc = _c1_inputs()
