@@ -245,6 +245,20 @@ __device__ inline void stage_lds(void* dst, const void* __restrict__ src, int by
   __syncthreads();
 }
 
+// Column a of subdomain s's local grid as a bit mask over the lines b = 0..m:
+// bit b set when node (a, b) is in the r set (neither on the Dirichlet boundary
+// nor a subdomain vertex); 0 when a is outside 0..m or on the Dirichlet boundary.
+__device__ inline uint64_t rnode_column(const Geo2& g, int s, int a) {
+  if (a < 0 || a > g.m) return 0;
+  const int gi = g.sx(s) * g.m + a, j0 = g.sy(s) * g.m;
+  if (gi == 0 || gi == g.N) return 0;
+  uint64_t msk = (1ull << (g.m + 1)) - 1;
+  if (j0 == 0) msk &= ~1ull;
+  if (j0 + g.m == g.N) msk &= ~(1ull << g.m);
+  if (a == 0 || a == g.m) msk &= ~(1ull | (1ull << g.m));
+  return msk;
+}
+
 // Bulk copy of one line factor (ml * ml entries, <= 33 * 33) global -> registers:
 // every thread issues its (at most 5) loads back to back.
 constexpr int GPT = (ML * ML + 255) / 256;
@@ -393,6 +407,13 @@ __device__ inline void local_solve_body(const Geo2& g, const Maps2& mp, const Rh
   }
   line_store<TS>(gbuf, n2, greg[0]);
   if (LRING < nsteps) line_load<TS>(Gs + (size_t)line_of(LRING) * n2, n2, greg[0]);
+  // thread (zr, zp) forms z for right-hand side zr at node zp of the line;
+  // bit b of zmk[d]: local node (zp + d - 1, b) is in the r set (0 off the line)
+  const int zr = threadIdx.x / ml, zp = threadIdx.x - zr * ml;
+  const bool zon = (int)threadIdx.x < ml * nr;
+  uint64_t zmk[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) zmk[d] = zon ? rnode_column(g, s, zp + d - 1) : 0;
   __syncthreads();
   for (int t0 = 0; t0 < nsteps; t0 += LRING) {
 #pragma unroll
@@ -402,13 +423,14 @@ __device__ inline void local_solve_body(const Geo2& g, const Maps2& mp, const Rh
         const int j = line_of(t);
         if (t < ml) {
           // forward: z_j = f_j - A_j,j-1 t_j-1 ; t_j = G_j z_j (t_j overwrites f_j in xall)
-          if (threadIdx.x < ml * nr) {
-            const int r = threadIdx.x / ml, p = threadIdx.x - r * ml;
+          if (zon) {
+            const int r = zr, p = zp;
             const T* xr = xall + r * XS;
             T v = xr[p + ml * j];
-            if (j > 0 && g.rnode(s, p, j)) {
-              for (int a = max(p - 1, 0); a <= min(p + 1, ml - 1); ++a)
-                if (g.rnode(s, a, j - 1)) v = v - cpl[p][a - p + 1] * xr[a + ml * (j - 1)];
+            if (j > 0 && ((zmk[1] >> j) & 1)) {
+#pragma unroll
+              for (int d = 0; d < 3; ++d)
+                if ((zmk[d] >> (j - 1)) & 1) v = v - cpl[p][d] * xr[p + d - 1 + ml * (j - 1)];
             }
             zl[r * ML + p] = v;
           }
@@ -416,13 +438,14 @@ __device__ inline void local_solve_body(const Geo2& g, const Maps2& mp, const Rh
           line_mv<TS, T, NRT>(gbuf, ml, zl, red, xall + ml * j, XS, false, nr);
         } else {
           // backward: x_j = t_j - G_j A_j,j+1 x_j+1
-          if (threadIdx.x < ml * nr) {
-            const int r = threadIdx.x / ml, p = threadIdx.x - r * ml;
+          if (zon) {
+            const int r = zr, p = zp;
             const T* xr = xall + r * XS;
             T v{0, 0};
-            if (g.rnode(s, p, j)) {
-              for (int a = max(p - 1, 0); a <= min(p + 1, ml - 1); ++a)
-                if (g.rnode(s, a, j + 1)) fma_acc(v, cpl[p][a - p + 1], xr[a + ml * (j + 1)]);
+            if ((zmk[1] >> j) & 1) {
+#pragma unroll
+              for (int d = 0; d < 3; ++d)
+                if ((zmk[d] >> (j + 1)) & 1) fma_acc(v, cpl[p][d], xr[p + d - 1 + ml * (j + 1)]);
             }
             zl[r * ML + p] = v;
           }
