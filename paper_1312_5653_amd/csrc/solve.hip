@@ -990,7 +990,6 @@ __device__ void phase_f2(const Geo2& g, const Maps2& mp, const RhsStride& rs,
 #pragma unroll
     for (int r = 0; r < NRT; ++r) acc[q][r] = cd{0.0, 0.0};
   const bool edges = nK > g.nC;
-#pragma unroll 2
   for (int c = threadIdx.x; c < nK; c += blockDim.x) {
     cd gc[NRT];
 #pragma unroll
