@@ -438,3 +438,123 @@ def test_full_space_minres_with_pearson_wathen(dim, N):
     ref = solve.dense_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc) if dim == 2 else None
     if ref is not None:
         assert np.linalg.norm(lam - ref["lam"]) <= 1e-8 * np.linalg.norm(ref["lam"])
+
+
+def _partially_assembled(dec, alpha):
+    """The FETI-DP primal system of Sec. 5 written as one dense matrix: every
+    subdomain keeps its own copy of its remainder nodes, the corners are shared
+    global unknowns (partial assembly), and B~ = [B_r^1 ... B_r^S, 0] glues the
+    copies.  Eliminating the primal unknowns from [[A~, B~^T], [B~, 0]] gives the
+    interface problem, so F_DP = B~ A~^-1 B~^T and d = B~ A~^-1 f~ without any
+    per-subdomain inverse, Schur complement or coarse condensation."""
+    loc = dec.local_matrices(alpha)
+    off = np.concatenate([[0], np.cumsum([sd["r"].size for sd in dec.subs])])
+    nr = int(off[-1])
+    A = np.zeros((nr + dec.nC, nr + dec.nC), dtype=np.complex128)
+    Bt = np.zeros((dec.nmu, nr + dec.nC))
+    for s, (sd, L) in enumerate(zip(dec.subs, loc)):
+        i = np.arange(off[s], off[s + 1])
+        cg = nr + np.array([dec.corner_id[int(sd["full"][l])] for l in sd["c"]], dtype=np.int64)
+        A[np.ix_(i, i)] += L["rr"]
+        A[np.ix_(i, cg)] += L["rc"]
+        A[np.ix_(cg, i)] += L["rc"].T
+        A[np.ix_(cg, cg)] += L["cc"]
+        Bt[:, i] = sd["Br"]
+    return A, Bt, off
+
+
+@pytest.mark.parametrize("dim,N,m", [(2, 12, 4), (2, 16, 4), (3, 8, 4)])
+def test_fetidp_apply_and_rhs_equal_the_partially_assembled_elimination(dim, N, m):
+    """F_DP mu and d (Sec. 5) against the dense elimination of the partially assembled
+    saddle system.  F_DP is complex symmetric, not Hermitian: a conjugate transpose in
+    place of a transpose anywhere in the coarse correction fails this."""
+    mesh = fem.Mesh(dim, N)
+    beta = 1e-3
+    alpha = beta ** -0.5
+    dec = feti.Decomposition(mesh, m)
+    ops = feti.fetidp_operators(dec, alpha)
+    A, Bt, off = _partially_assembled(dec, alpha)
+    F_ref = Bt @ np.linalg.solve(A, Bt.T)
+    for seed in (5, 6):
+        mu = W.random_vector(dec.nmu, seed, complex_=True)
+        y = feti.fetidp_apply(ops, mu)
+        assert np.linalg.norm(y - F_ref @ mu) / np.linalg.norm(F_ref @ mu) < 1e-12
+    f = W.random_vector(mesh.n, 7, complex_=True)
+    d, fcs, fr = feti.fetidp_rhs(dec, ops, f)
+    ft = np.zeros(A.shape[0], dtype=np.complex128)
+    for s in range(dec.nsub):
+        ft[off[s]:off[s + 1]] = fr[s]
+    _, fc = dec.split_rhs(f)
+    ft[off[-1]:] = fc
+    d_ref = Bt @ np.linalg.solve(A, ft)
+    assert np.linalg.norm(d - d_ref) / np.linalg.norm(d_ref) < 1e-12
+    assert np.linalg.norm(F_ref - F_ref.T) / np.linalg.norm(F_ref) < 1e-12
+    assert np.linalg.norm(F_ref - F_ref.conj().T) / np.linalg.norm(F_ref) > 1e-3
+
+
+@pytest.mark.parametrize("dim,N,m", [(2, 12, 4), (2, 16, 4), (3, 8, 4)])
+def test_fetidp_aug_apply_and_rhs_equal_the_augmented_elimination(dim, N, m):
+    """F_aug mu and d_aug (the edge-augmented coarse space of Sec. 5) against the dense
+    elimination of the partially assembled system with the extra unknowns nu that enforce
+    Q^T B~ u = 0: A^ = [[A~, B~^T Q], [Q^T B~, 0]], F_aug = B^ A^-1 B^^T, d_aug = B^ A^-1 f^."""
+    mesh = fem.Mesh(dim, N)
+    beta = 1e-3
+    alpha = beta ** -0.5
+    dec = feti.Decomposition(mesh, m)
+    ops = feti.fetidp_operators(dec, alpha)
+    Q, _ = feti.edge_space(dec)
+    aug = feti.fetidp_aug_operators(ops, Q)
+    A, Bt, off = _partially_assembled(dec, alpha)
+    n, nE = A.shape[0], Q.shape[1]
+    Ah = np.zeros((n + nE, n + nE), dtype=np.complex128)
+    Ah[:n, :n] = A
+    Ah[:n, n:] = Bt.T @ Q
+    Ah[n:, :n] = Q.T @ Bt
+    Bh = np.hstack([Bt, np.zeros((dec.nmu, nE))])
+    F_ref = Bh @ np.linalg.solve(Ah, Bh.T)
+    for seed in (8, 9):
+        mu = W.random_vector(dec.nmu, seed, complex_=True)
+        y = feti.fetidp_aug_apply(ops, aug, mu)
+        assert np.linalg.norm(y - F_ref @ mu) / np.linalg.norm(F_ref @ mu) < 1e-11
+    f = W.random_vector(mesh.n, 10, complex_=True)
+    d, c0, fr = feti.fetidp_aug_rhs(dec, ops, aug, f)
+    fh = np.zeros(n + nE, dtype=np.complex128)
+    for s in range(dec.nsub):
+        fh[off[s]:off[s + 1]] = fr[s]
+    _, fc = dec.split_rhs(f)
+    fh[off[-1]:n] = fc
+    d_ref = Bh @ np.linalg.solve(Ah, fh)
+    assert np.linalg.norm(d - d_ref) / np.linalg.norm(d_ref) < 1e-11
+
+
+def test_constraint_violation_and_eta_blk_by_hand():
+    """The Sec. 6.2 relative constraint violation ||K y + K_c y_c - V u|| / ||K y|| and the
+    blockwise backward error on the 2 x 2-cell mesh, whose single free node has the textbook
+    Q1 values K = 8/3, V = 1/9 and K_c = -1/3 towards each of the 8 boundary nodes."""
+    A = fem.assemble(fem.Mesh(2, 2))
+    K, M, Kc = A["K"], A["M"], A["Kc"]
+    one = np.ones(1)
+    yc = 0.5 * np.ones(8)                       # K_c y_c = -4/3, |K_c| |y_c| = 4/3
+    # y = 1, u = 3: K y + K_c y_c - V u = 8/3 - 4/3 - 1/3 = 1, ||K y|| = 8/3
+    assert abs(kkt.constraint_violation(K, M, Kc, yc, one, 3 * one) - 3 / 8) < 1e-15
+    assert abs(kkt.constraint_violation(K, M, Kc, None, one, 3 * one) - (7 / 3) / (8 / 3)) < 1e-15
+    beta = 0.1
+    # ybar = 2, y = 1, u = 3, lam = 1/2, y_c = 0:
+    #   r1 = V(ybar - y) - K lam = 1/9 - 4/3 = -11/9,  |V||y| + |K||lam| + |V ybar| = 15/9
+    #   r2 = V lam - beta V u = 0.2/9,                 beta |V||u| + |V||lam|       = 0.8/9
+    #   r3 = -(K y - V u) = -7/3,                       |K||y| + |V||u|              = 3
+    e = kkt.eta_blk(K, M, Kc, beta, 2 * one, None, one, 3 * one, 0.5 * one)
+    assert abs(e - 7 / 9) < 1e-15
+    # ybar = 2, y = 1, lam = 2, u = lam / beta = 20: r2 = 0;
+    #   r1 = 1/9 - 16/3 = -47/9 over 51/9;  r3 = -(8/3 - 20/9) = -4/9 over 44/9
+    e = kkt.eta_blk(K, M, Kc, beta, 2 * one, None, one, 20 * one, 2 * one)
+    assert abs(e - 47 / 51) < 1e-15
+    # ybar = 25, y = 1, lam = 1 (r1 = 0), u = 10 (r2 = 0), y_c = 1/2:
+    #   r3 = 4/3 - (8/3 - 10/9) = -2/9 over 8/3 + 10/9 + 4/3 = 46/9
+    e = kkt.eta_blk(K, M, Kc, beta, 25 * one, yc, one, 10 * one, one)
+    assert abs(e - 1 / 23) < 1e-15
+    # x = 0 on a larger mesh: every residual block equals its right-hand side block
+    B = fem.assemble(fem.Mesh(2, 8))
+    ybar, ycb = W.thermal_target(8)
+    z = np.zeros(B["K"].shape[0])
+    assert abs(kkt.eta_blk(B["K"], B["M"], B["Kc"], beta, ybar, ycb, z, z, z) - 1.0) < 1e-15
