@@ -138,10 +138,75 @@ def write_traffic_record(fetch_dir, write_dir, copy_mib):
                       "k_gmres": {k: v["bytes_per_launch"] for k, v in kernels.items() if "gmres" in k}}))
 
 
+# ---- cpu_baseline leg: the CPU oracle on the same workloads --------------------------------
+# The only code in this script that imports or runs oracle/: it times the oracle (cpu_baseline)
+# and provides the oracle's solutions of the very inputs the GPU lines solve, against which
+# each line's forward error is stated.
+
+
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo) and the cores this process may use."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": name, "os_cpu_count": os.cpu_count(), "usable_cores": usable}
+
+
+class OracleLeg:
+    """Oracle references of the GPU lines' inputs: O1 (SuperLU of Z, the paper's two-factor
+    solve, FP64; one factorization per (dim, N, beta), kept) and, for sine-mode targets, the
+    closed form of the exact discrete solution."""
+
+    def __init__(self):
+        self.lu = {}
+        self.mats = {}
+
+    def _mats(self, dim, N):
+        from oracle import fem
+        if (dim, N) not in self.mats:
+            self.mats[(dim, N)] = fem.assemble(fem.Mesh(dim, N))
+        return self.mats[(dim, N)]
+
+    def o1(self, dim, N, beta, ybars):
+        import scipy.sparse.linalg as spla
+        from oracle import solve
+        A = self._mats(dim, N)
+        key = (dim, N, beta)
+        if key not in self.lu:
+            self.lu = {key: spla.splu(solve.complex_factor(A["K"], A["M"], beta))}  # keep one factor
+        return [solve.range_space_two_factor(A["K"], A["M"], A["Kc"], beta, yb, None, lu=self.lu[key],
+                                             paper_y=False) for yb in ybars]
+
+    @staticmethod
+    def closed(dim, N, beta, modes_coefs):
+        from oracle import fem, solve
+        mesh = fem.Mesh(dim, N)
+        return [solve.closed_form_sines(mesh, beta, m, c) for m, c in modes_coefs]
+
+
+def fwd_err(outs, refs):
+    """Max over targets and over y, u, lam of the relative 2-norm error of the GPU result."""
+    if refs is None:
+        return None
+    worst = 0.0
+    for (y, u, lam), r in zip(outs, refs):
+        for a, b in ((y, r["y"]), (u, r["u"]), (lam, r["lam"])):
+            worst = max(worst, float(((a - b) ** 2).sum() ** 0.5 / max((b ** 2).sum() ** 0.5, 1e-300)))
+    return worst
+
+
 def cpu_baseline(N, m, beta, ybar, budget_s=15.0):
     """The CPU oracle (SciPy SuperLU of Z, two-factor solve) on the same workload."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
-    import numpy as np
     import scipy.sparse.linalg as spla
     from oracle import fem, solve
     A = fem.assemble(fem.Mesh(2, N))
@@ -160,7 +225,47 @@ def cpu_baseline(N, m, beta, ybar, budget_s=15.0):
     return {"value": 1.0 / t_solve, "unit": "Schur solves/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(times)} two-factor solves with one resident SuperLU factor of Z at 512^2 "
                       f"(median {t_solve:.3f} s each); the factorization itself took {t_factor:.2f} s",
-            "factor_s": t_factor, "solve_s": t_solve, "host_threads": os.cpu_count()}
+            "factor_s": t_factor, "solve_s": t_solve, "cpu": cpu_model()}
+
+
+def _c4_oracle_one(d):
+    """One batched instance on the oracle: assembly, SuperLU factor of Z, two-factor solve."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import scipy.sparse.linalg as spla
+    from oracle import fem, solve
+    from paper_1312_5653_amd import workloads
+    A = fem.assemble(fem.Mesh(2, d["N"]))
+    ybar = workloads.sine_target(2, d["N"], *workloads.modes_for("sixteen2d", d["seed"]))[0]
+    lu = spla.splu(solve.complex_factor(A["K"], A["M"], d["beta"]))
+    r = solve.range_space_two_factor(A["K"], A["M"], A["Kc"], d["beta"], ybar, None, lu=lu, paper_y=False)
+    return d["j"], r["y"], r["u"], r["lam"]
+
+
+def cpu_instances(count, seed, budget_s=12.0):
+    """The oracle on the batched-instance workload, one process per usable host core (at most
+    16) over independent instances, for about budget_s seconds: end-to-end solves/s = instances
+    finished / wall time.  Returns the figure and the oracle solutions it produced."""
+    import multiprocessing as mp
+    from paper_1312_5653_amd import workloads
+    inst = workloads.c4_instances(count, seed)
+    for j, d in enumerate(inst):
+        d["j"] = j
+    info = cpu_model()
+    cores = max(1, min(16, info["usable_cores"] or 1))
+    sols = {}
+    t_start = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        t_start = time.perf_counter()
+        for j, y, u, lam in pool.imap_unordered(_c4_oracle_one, inst):
+            sols[j] = (y, u, lam)
+            if time.perf_counter() - t_start > budget_s:
+                break
+        el = time.perf_counter() - t_start
+        pool.terminate()
+    return {"value": len(sols) / el, "unit": "end-to-end solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(sols)} of the {count} instances (assembly, SuperLU factor of Z and the "
+                      f"two-factor solve each) on {cores} processes, {el:.1f} s",
+            "cpu": info}, sols
 
 
 def run_instances(sfdp, torch, ctx, count, seed, tol_kkt):
@@ -174,25 +279,34 @@ def run_instances(sfdp, torch, ctx, count, seed, tol_kkt):
     ybars = [torch.tensor(workloads.sine_target(2, d["N"], *workloads.modes_for("sixteen2d", d["seed"]))[0],
                           device="cuda:0") for d in inst]
     b = sfdp.Batch(ctx, Ns, 32, sfdp.SFDP_MIXED)
-    b.set_beta(betas)
-    b.solve_range_space(ybars, None, tol_kkt=tol_kkt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.set_beta(betas)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    _, _, _, infos, st = b.solve_range_space(ybars, None, tol_kkt=tol_kkt)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    b.close()
+    try:
+        b.set_beta(betas)
+        b.solve_range_space(ybars, None, tol_kkt=tol_kkt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.set_beta(betas)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    except BaseException:
+        b.close()
+        raise
+    try:
+        ys, us, ls, infos, st = b.solve_range_space(ybars, None, tol_kkt=tol_kkt)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    finally:
+        b.close()
     if st != 0:
         raise RuntimeError("batched instances did not converge")
+    outs = [(y.cpu().numpy(), u.cpu().numpy(), l.cpu().numpy()) for y, u, l in zip(ys, us, ls)]
     rho = max(i[0]["rel_kkt"] for i in infos)
     return {"instances": count, "seed": seed, "subdomains": sum((N // 32) ** 2 for N in Ns),
             "dofs": sum((N - 1) ** 2 for N in Ns), "setup_ms": (t1 - t0) * 1e3, "solve_ms": (t2 - t1) * 1e3,
             "solves_per_s_end_to_end": count / (t2 - t0), "solves_per_s_solve_phase": count / (t2 - t1),
-            "max_rel_kkt": rho, "krylov_its_per_solve": statistics.mean(i[0]["krylov_total"] for i in infos),
-            "precision": "mixed"}
+            "max_rel_kkt": rho, "max_constr_viol": max(i[0]["constr_viol"] for i in infos),
+            "max_eta_blk": max(i[0]["eta_blk"] for i in infos),
+            "krylov_its_per_solve": statistics.mean(i[0]["krylov_total"] for i in infos),
+            "precision": "mixed"}, outs
 
 
 def run_serving(sfdp, torch, count, seed, tol_kkt, budget_gb):
@@ -250,32 +364,18 @@ def run_serving(sfdp, torch, count, seed, tol_kkt, budget_gb):
             "budget_gb": budget_gb, "precision": "mixed"}
 
 
-def cpu_instances(count, seed, budget_s=10.0):
-    """The oracle on the batched-instance workload: SuperLU factor of Z plus the two-factor
-    solve, instance after instance on one core, for as many instances as fit the budget."""
-    import scipy.sparse.linalg as spla
-    from oracle import fem, solve
-    from paper_1312_5653_amd import workloads
-    inst = workloads.c4_instances(count, seed)
-    t_start = time.perf_counter()
-    done = 0
-    for d in inst:
-        A = fem.assemble(fem.Mesh(2, d["N"]))
-        ybar = workloads.sine_target(2, d["N"], *workloads.modes_for("sixteen2d", d["seed"]))[0]
-        lu = spla.splu(solve.complex_factor(A["K"], A["M"], d["beta"]))
-        solve.range_space_two_factor(A["K"], A["M"], A["Kc"], d["beta"], ybar, None, lu=lu, paper_y=False)
-        done += 1
-        if time.perf_counter() - t_start > budget_s:
-            break
-    el = time.perf_counter() - t_start
-    return {"value": done / el, "unit": "end-to-end solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of the {count} instances (assembly, SuperLU factor of Z and the "
-                      f"two-factor solve each), one core, {el:.1f} s"}
-
-
 def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup, tol_kkt, tol_inner,
                   batch, max_krylov=0, factors=0, edges=None, dim=2, full_space=False, schur_block=0):
     p = sfdp.Problem(ctx, dim, N, m, precision)
+    try:
+        return _run_precision(sfdp, torch, p, beta, ybar_t, steps, warmup, tol_kkt, tol_inner, batch,
+                              max_krylov, factors, edges, full_space, schur_block)
+    finally:
+        p.close()
+
+
+def _run_precision(sfdp, torch, p, beta, ybar_t, steps, warmup, tol_kkt, tol_inner, batch, max_krylov,
+                   factors, edges, full_space, schur_block):
     if edges is not None:
         p.set_coarse_space(edges)
     torch.cuda.synchronize()
@@ -293,7 +393,7 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
         solve(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch,
               max_krylov=max_krylov, factors=factors, **sb)
     p.timing_enable(True)
-    lat, rhos, its, feti, minres = [], [], [], [], []
+    lat, rhos, its, feti, minres, cvs, etas = [], [], [], [], [], [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for _ in range(steps):
@@ -305,6 +405,8 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
         its.extend(i["krylov_total"] for i in info)
         feti.extend(i["n_feti"] for i in info)
         minres.extend(i["minres_its"] for i in info)
+        cvs.extend(i["constr_viol"] for i in info)
+        etas.extend(i["eta_blk"] for i in info)
         if st != 0:
             raise RuntimeError(f"solve did not converge: {info}")
     torch.cuda.synchronize()
@@ -312,14 +414,15 @@ def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup
     kt = p.kernel_times()
     sizes = p.refresh_sizes()
     p.timing_enable(False)
-    p.close()
+    outs = [(y[r].cpu().numpy(), u[r].cpu().numpy(), lam[r].cpu().numpy()) for r in range(nb)]
     lat_ms = sorted(x * 1e3 for x in lat)
     q = lambda f: lat_ms[min(len(lat_ms) - 1, int(round(f * (len(lat_ms) - 1))))]
     return {"solves_per_s": nb * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps, "batch": nb,
             "p50_ms": q(0.5), "p99_ms": q(0.99), "setup_ms": setup_ms,
-            "max_rel_kkt": max(rhos), "krylov_per_solve": statistics.mean(its),
+            "max_rel_kkt": max(rhos), "max_constr_viol": max(cvs), "max_eta_blk": max(etas),
+            "krylov_per_solve": statistics.mean(its),
             "feti_per_solve": statistics.mean(feti), "minres_per_solve": statistics.mean(minres),
-            "kernel_times": kt, "sizes": sizes}
+            "kernel_times": kt, "sizes": sizes, "outs": outs, "beta": beta}
 
 
 def run_schur_blocks(sfdp, torch, ctx, precision, N, m, betas, ybar_t, tol_kkt, tol_inner):
@@ -332,6 +435,17 @@ def run_schur_blocks(sfdp, torch, ctx, precision, N, m, betas, ybar_t, tol_kkt, 
     y0 = ybar_t[:1].contiguous()
     for beta in betas:
         p = sfdp.Problem(ctx, 2, N, m, precision)
+        try:
+            rows.append(_schur_block_row(p, torch, beta, y0, tol_kkt, tol_inner))
+        finally:
+            p.close()
+    return {"workload": f"{N}x{N} Q1, {(N // m) ** 2} subdomains of {m}x{m}, one target, "
+                        f"{'mixed' if precision == sfdp.SFDP_MIXED else 'fp64'}",
+            "rows": rows}
+
+
+def _schur_block_row(p, torch, beta, y0, tol_kkt, tol_inner):
+    if True:
         sync = torch.cuda.synchronize
         sync()
         t0 = time.perf_counter()
@@ -357,30 +471,31 @@ def run_schur_blocks(sfdp, torch, ctx, precision, N, m, betas, ybar_t, tol_kkt, 
             row[key].update({"T_ms": (time.perf_counter() - t0) * 1e3, "NI": info[0]["minres_its"],
                              "refinement_steps": info[0]["outer_steps"], "feti_solves": info[0]["n_feti"],
                              "rel_kkt": info[0]["rel_kkt"], "status": st})
-        p.close()
-        rows.append(row)
-    return {"workload": f"{N}x{N} Q1, {(N // m) ** 2} subdomains of {m}x{m}, one target, "
-                        f"{'mixed' if precision == sfdp.SFDP_MIXED else 'fp64'}",
-            "rows": rows}
+        return row
 
 
-def run_c3(sfdp, torch, ctx, N, beta, steps, tol_kkt, m=8, B=4):
+def run_c3(sfdp, torch, ctx, N, beta, steps, tol_kkt, oracle=None, m=8, B=4):
     """The 3D configuration: Q1 trilinear Poisson control on N^3 cells in
     (N/m)^3 subdomains of m^3, B eight-mode product-of-sines targets per step,
     mixed precision (complex64 local operators, FP64 coarse problem, Krylov and
     refinement)."""
     import numpy as np
     from paper_1312_5653_amd import workloads
-    ybar = np.stack([workloads.sine_target(3, N, *workloads.modes_for("eight3d", s))[0] for s in range(B)])
+    mc = [workloads.modes_for("eight3d", s) for s in range(B)]
+    ybar = np.stack([workloads.sine_target(3, N, *x)[0] for x in mc])
     yt = torch.tensor(ybar, device="cuda:0")
     r = run_precision(sfdp, torch, ctx, sfdp.SFDP_MIXED, N, m, beta, yt, steps, 1, tol_kkt, 3e-7, B, dim=3)
     sz = r["sizes"]
+    # the 3D sparse LU of the oracle runs for minutes at this size: the closed form of the
+    # exact discrete solution (sine targets) is the oracle reference here
+    fe = {"closed_form": fwd_err(r["outs"], OracleLeg.closed(3, N, beta, mc))} if oracle else None
     return {"workload": f"3D Q1 Poisson control {N}^3 cells, {N // m}^3 subdomains of {m}^3, beta={beta:g}, "
                         f"8-mode product-of-sines targets (seeds 0..{B - 1}), {B} targets per step",
             "precision": "mixed", "solves_per_s": r["solves_per_s"], "ms_per_step": r["ms_per_step"],
             "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "setup_ms": r["setup_ms"],
-            "max_rel_kkt": r["max_rel_kkt"], "krylov_its_per_solve": r["krylov_per_solve"],
-            "dofs": (N - 1) ** 3, "n_mult": sz["n_mult"], "n_corner": sz["n_corner"],
+            "max_rel_kkt": r["max_rel_kkt"], "max_constr_viol": r["max_constr_viol"],
+            "max_eta_blk": r["max_eta_blk"], "fwd_err_vs_oracle": fe,
+            "krylov_its_per_solve": r["krylov_per_solve"], "dofs": (N - 1) ** 3, "n_mult": sz["n_mult"], "n_corner": sz["n_corner"],
             "resident_bytes": sz["resident_bytes"]}
 
 
@@ -461,10 +576,15 @@ def main():
             res[name + "_b1"] = run_precision(sfdp, torch, ctx, prec, N, m, beta, ybar1_t, args.steps,
                                               args.warmup, tol_kkt, tin, 1, args.max_krylov)
     head = precs[0][0]
+    hp, htin = precs[0][1], precs[0][2]
     if not args.headline_only:
+        # the same configuration at the other two betas of the 512^2 workload (Table 1's phi range)
+        for ob in (1e-2, 1e-6):
+            if ob != beta:
+                res[f"{head}_beta{ob:g}"] = run_precision(sfdp, torch, ctx, hp, N, m, ob, ybar_t, args.steps,
+                                                         args.warmup, tol_kkt, htin, B, args.max_krylov)
         # the one-solve range-space form (same result, half the FETI-DP solves):
         # measured beside the two-factor form, never in its place
-        hp, htin = precs[0][1], precs[0][2]
         res[head + "_single_solve"] = run_precision(sfdp, torch, ctx, hp, N, m, beta, ybar_t, args.steps,
                                                     args.warmup, tol_kkt, htin, B, args.max_krylov, factors=1)
         # the corner-only coarse space, for the effect of the edge augmentation
@@ -523,6 +643,9 @@ def main():
         "step_p99_ms": r["p99_ms"],
         "setup_ms": r["setup_ms"],
         "max_rel_kkt": r["max_rel_kkt"],
+        "max_constr_viol": r["max_constr_viol"],
+        "max_eta_blk": r["max_eta_blk"],
+        "fwd_err_vs_oracle": None,
         "krylov_its_per_solve": r["krylov_per_solve"],
         "roofline": {"bound": "hbm", "kernel": "k_gmres (interface Krylov solve, persistent)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -541,9 +664,11 @@ def main():
     other = [k for k in res if k != head]
     for k in other:
         o = res[k]
-        out[k] = {"batch": o["batch"], "solves_per_s": o["solves_per_s"], "ms_per_step": o["ms_per_step"],
-                  "factors": 1 if k.endswith("_single_solve") else 2,
+        out[k] = {"batch": o["batch"], "beta": o["beta"], "solves_per_s": o["solves_per_s"],
+                  "ms_per_step": o["ms_per_step"], "factors": 1 if k.endswith("_single_solve") else 2,
                   "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"], "max_rel_kkt": o["max_rel_kkt"],
+                  "max_constr_viol": o["max_constr_viol"], "max_eta_blk": o["max_eta_blk"],
+                  "fwd_err_vs_oracle": None,
                   "krylov_its_per_solve": o["krylov_per_solve"], "feti_solves_per_solve": o["feti_per_solve"],
                   "setup_ms": o["setup_ms"]}
         if k.endswith("_full_space"):
@@ -552,21 +677,37 @@ def main():
         if k.endswith("_full_space_pw"):
             out[k]["method"] = "full-space MINRES, P_mgw with S_p (Pearson-Wathen) in place of S"
             out[k]["minres_its_per_solve"] = o["minres_per_solve"]
+    oracle = None if args.no_cpu else OracleLeg()
+    inst_outs = None
     if args.instances > 0 and not args.headline_only:
-        out["instances_batch"] = run_instances(sfdp, torch, ctx, args.instances, 0, tol_kkt)
-        if not args.no_cpu:
-            out["instances_batch"]["cpu_baseline"] = cpu_instances(args.instances, 0)
+        out["instances_batch"], inst_outs = run_instances(sfdp, torch, ctx, args.instances, 0, tol_kkt)
     if args.requests > 0 and not args.headline_only:
         out["serving"] = run_serving(sfdp, torch, args.requests, 0, tol_kkt, args.serve_budget_gb)
     if args.c3 > 0 and not args.headline_only:
-        out["c3_3d"] = run_c3(sfdp, torch, ctx, args.c3, beta, args.c3_steps, tol_kkt)
+        out["c3_3d"] = run_c3(sfdp, torch, ctx, args.c3, beta, args.c3_steps, tol_kkt, oracle)
     if args.schur_betas and not args.headline_only:
         betas = [float(b) for b in args.schur_betas.split(",")]
         out["schur_block_comparison"] = run_schur_blocks(sfdp, torch, ctx, precs[0][1], N, m, betas, ybar_t,
                                                          tol_kkt, precs[0][2])
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(N, m, beta, ybar[0])
     ctx.close()
+    if oracle is not None:
+        # the oracle leg: solutions of every line's inputs (forward error of each line) and the
+        # timed baselines
+        mc = [workloads.modes_for("sixteen2d", s) for s in range(B)]
+        for k in sorted(res, key=lambda k: res[k]["beta"]):
+            o = res[k]
+            refs = oracle.o1(2, N, o["beta"], [ybar[j] for j in range(o["batch"])])
+            fe = {"O1": fwd_err(o["outs"], refs),
+                  "closed_form": fwd_err(o["outs"], OracleLeg.closed(2, N, o["beta"], mc[:o["batch"]]))}
+            (out if k == head else out[k])["fwd_err_vs_oracle"] = fe
+        out["cpu_baseline"] = cpu_baseline(N, m, beta, ybar[0])
+        if inst_outs is not None:
+            base, sols = cpu_instances(args.instances, 0)
+            out["instances_batch"]["cpu_baseline"] = base
+            out["instances_batch"]["fwd_err_vs_oracle"] = {
+                "O1": fwd_err([inst_outs[j] for j in sorted(sols)], [dict(zip(("y", "u", "lam"), sols[j]))
+                                                                    for j in sorted(sols)]),
+                "instances_compared": len(sols)}
     print(json.dumps(out), flush=True)
 
 

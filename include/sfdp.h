@@ -145,6 +145,16 @@ typedef struct {
   int n_feti;            /* FETI-DP solves done */
   int minres_its;        /* sfdp_solve_full_space: MINRES iterations over all
                             refinement steps (0 for the range-space calls) */
+  double constr_viol;    /* relative constraint violation of the result (Sec. 6.2):
+                            ||K y + Kc yc - M u|| / ||K y||, FP64 on the GPU */
+  double eta_blk;        /* blockwise backward error of the result:
+                            max_i ||r_i|| / (sum_j || |A_ij| |x_j| || + ||b_i||) over
+                            the three block rows of the KKT system, |.| entrywise;
+                            both metrics are -1 where not computed (served requests) */
+  double t_setup_ms;     /* host time of the problem's last sfdp_set_beta (its
+                            instance's set-up for batches; 0 for served requests) */
+  double t_solve_ms;     /* host time of the call that produced this result (for
+                            several targets per call: the whole call) */
 } sfdp_info;
 
 /* Launch-variant autotuning (enable = 1, the default): kernels with variants
@@ -175,7 +185,10 @@ typedef struct {
  * (a hipStream_t, NULL for the default stream).  mem_budget_bytes = 0 means
  * no limit beyond the device's memory. */
 sfdp_status sfdp_ctx_create(int device, size_t mem_budget_bytes, void* stream, sfdp_ctx** out);
-void sfdp_ctx_destroy(sfdp_ctx* ctx);
+/* Frees the context.  Problems, batches and servers keep a pointer to their
+ * context, so it refuses with SFDP_E_STATE (and frees nothing) while any of
+ * them is alive: destroy those first.  NULL is a no-op (SFDP_OK). */
+sfdp_status sfdp_ctx_destroy(sfdp_ctx* ctx);
 const char* sfdp_last_error(void);
 
 /* Set up the mesh, the subdomain partition and the interface maps (Sec. 5:

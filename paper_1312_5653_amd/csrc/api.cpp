@@ -26,6 +26,18 @@ using namespace sfdp;
 
 static thread_local std::string g_err;
 
+// A report with the accuracy metrics marked as not computed.
+static sfdp_info blank_info() {
+  sfdp_info o{};
+  o.constr_viol = -1.0;
+  o.eta_blk = -1.0;
+  return o;
+}
+
+static double wall_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 static sfdp_status fail(sfdp_status s, const std::string& msg) {
   g_err = msg;
   return s;
@@ -297,7 +309,7 @@ sfdp_status check_ready(const Problem* p) {
 sfdp_status alloc_rs(Problem& p) {
   if (p.r1) return SFDP_OK;
   size_t n = (size_t)NRMAX * p.n_free;
-  size_t nred = RED_HEAD + NRMAX * (size_t)red_pstride(p);
+  size_t nred = RED_HEAD + NRMAX * (size_t)red_pstride(p) * (2 + MET_N) / 2;
   sfdp_status s;
   if ((s = dalloc(p, (void**)&p.r1, sizeof(double) * n)) || (s = dalloc(p, (void**)&p.r2, sizeof(double) * n)) ||
       (s = dalloc(p, (void**)&p.r3, sizeof(double) * n)) || (s = dalloc(p, (void**)&p.red, sizeof(double) * nred)) ||
@@ -897,6 +909,16 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
     for (size_t i = 0; i < n; ++i)
       for (int c = 0; c < ps[i]->nr; ++c) loc[i][(ps[i]->map >> (8 * c)) & 255].outer_steps = step + 1;
   }
+  // accuracy metrics of every target of the group at its final iterate
+  for (size_t i = 0; i < n; ++i) {
+    ps[i]->nr = ng[i];
+    ps[i]->map = IDENTITY_MAP;
+  }
+  if (M) {
+    sfdp_status s = multi_upload(*M);
+    if (s) return s;
+  }
+  HIPCHK(launch_kkt_metrics(t));
   HIPCHK(launch_gather(t, dg));
   HIPCHK(hipMemcpyAsync(hg, dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -913,6 +935,9 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
         o.krylov_its[k] = fl[FLAG_LOG + 16 * q + k];
         o.krylov_total += o.krylov_its[k];
       }
+      o.constr_viol = hg[i].red[MET_HEAD + 2 * q];
+      o.eta_blk = hg[i].red[MET_HEAD + 2 * q + 1];
+      o.t_setup_ms = ps[i]->t_setup_ms;
       if (bad[i][q] == 1) status = fail(SFDP_E_NOCONV, "non-finite residual");
       if (bad[i][q] == 2) status = fail(SFDP_E_NOCONV, "outer refinement limit reached");
       if (info[i]) info[i][q] = o;
@@ -941,6 +966,7 @@ sfdp_status create_problem3(Ctx* ctx, int n_elem, int sub_elem, sfdp_precision p
     return fail(SFDP_E_NOMEM, "host allocation");
   }
   p->ctx = ctx;
+  ctx->children++;
   p->dim = 3;
   p->N = n_elem;
   p->m = sub_elem;
@@ -979,6 +1005,7 @@ sfdp_status create_problem(Ctx* ctx, int dim, int n_elem, int sub_elem, sfdp_pre
   Problem* p = new (std::nothrow) Problem();
   if (!p) return fail(SFDP_E_NOMEM, "host allocation");
   p->ctx = ctx;
+  ctx->children++;
   p->dim = dim;
   p->N = n_elem;
   p->m = sub_elem;
@@ -1051,6 +1078,7 @@ void destroy_problem(Problem* p) {
   if (p->fsh) hipHostFree(p->fsh);
   for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
   p->ctx->used -= std::min(p->ctx->used, p->bytes);
+  p->ctx->children--;
   delete p;
 }
 
@@ -1279,14 +1307,18 @@ sfdp_status sfdp_ctx_create(int device, size_t mem_budget_bytes, void* stream, s
   return SFDP_OK;
 }
 
-void sfdp_ctx_destroy(sfdp_ctx* c) {
-  if (!c) return;
+sfdp_status sfdp_ctx_destroy(sfdp_ctx* c) {
+  if (!c) return SFDP_OK;
+  if (c->children.load() > 0)
+    return fail(SFDP_E_STATE, std::to_string(c->children.load()) +
+                                  " problems, batches or servers of this context are still alive");
   if (c->pool) {
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
     hipFree(c->pool);
   }
   delete c;
+  return SFDP_OK;
 }
 
 sfdp_status sfdp_problem_create(sfdp_ctx* ctx, int dim, int n_elem, int sub_elem, sfdp_precision prec,
@@ -1343,7 +1375,12 @@ sfdp_status sfdp_set_beta(sfdp_problem* p, double beta) {
   p->beta = beta;
   p->alpha = 1.0 / std::sqrt(beta);
   std::vector<Problem*> ps{p};
-  return setup_run(single_target(p), ps, nullptr);
+  const double t0 = wall_ms();
+  sfdp_status s = setup_run(single_target(p), ps, nullptr);
+  if (s) return s;
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  p->t_setup_ms = wall_ms() - t0;
+  return SFDP_OK;
 }
 
 sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double* f, double* x,
@@ -1440,6 +1477,7 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
   sfdp_status worst = SFDP_OK;
   const size_t n = p->n_free;
   std::vector<Problem*> ps{p};
+  const double t0 = wall_ms();
   for (int r0 = 0; r0 < nrhs; r0 += bsz) {
     const int ng = std::min(bsz, nrhs - r0);
     p->nr = ng;
@@ -1452,6 +1490,8 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
     if (s == SFDP_E_NOCONV) worst = s;
     else if (s) return s;
   }
+  if (info)
+    for (int r = 0; r < nrhs; ++r) info[r].t_solve_ms = wall_ms() - t0;
   return worst;
 }
 
@@ -1638,7 +1678,7 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
     if (info)
       for (int c = 0; c < nr; ++c) {
         sfdp_info& o = info[r0 + c];
-        memset(&o, 0, sizeof(o));
+        o = blank_info();
         o.n_feti = single_of(opts) ? 1 : 2;
         for (int k = 0; k < o.n_feti; ++k) {
           o.krylov_its[k] = p->gh->flags[FLAG_LOG + 16 * c + k];
@@ -1682,6 +1722,7 @@ sfdp_status sfdp_solve_full_space(sfdp_problem* p, int nrhs, const double* ybar,
   Target t = single_target(p);
   hipStream_t st = c.st;
   sfdp_status worst = SFDP_OK;
+  const double t_call = wall_ms();
   for (int q = 0; q < nrhs; ++q) {
     sfdp_info o{};
     c.log = &o;
@@ -1720,11 +1761,20 @@ sfdp_status sfdp_solve_full_space(sfdp_problem* p, int nrhs, const double* ybar,
       HIPCHK(launch_lin3(n, 1.0, lq, 1.0, dx + 2 * n, 0.0, nullptr, lq, st));
       o.outer_steps = step + 1;
     }
+    p->nr = 1;
+    p->map = IDENTITY_MAP;
+    HIPCHK(launch_kkt_metrics(t));
+    if ((s = gather_one(p))) return s;
+    o.constr_viol = p->gh->red[MET_HEAD];
+    o.eta_blk = p->gh->red[MET_HEAD + 1];
+    o.t_setup_ms = p->t_setup_ms;
     p->nr = 0;
     if (info) info[q] = o;
     if (bad) worst = fail(SFDP_E_NOCONV, "full-space refinement did not reach tol_kkt");
   }
   HIPCHK(hipStreamSynchronize(st));
+  if (info)
+    for (int q = 0; q < nrhs; ++q) info[q].t_solve_ms = wall_ms() - t_call;
   return worst;
 }
 
@@ -1789,7 +1839,13 @@ sfdp_status sfdp_batch_set_beta(sfdp_batch* b, const double* beta) {
     p->beta = beta[i];
     p->alpha = 1.0 / std::sqrt(beta[i]);
   }
-  return setup_run(b->M.t, b->probs, &b->M);
+  const double t0 = wall_ms();
+  sfdp_status s = setup_run(b->M.t, b->probs, &b->M);
+  if (s) return s;
+  HIPCHK(hipStreamSynchronize(b->ctx->stream));
+  const double ms = wall_ms() - t0;
+  for (Problem* p : b->probs) p->t_setup_ms = ms;
+  return SFDP_OK;
 }
 
 sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const double* const* ybar,
@@ -1815,6 +1871,7 @@ sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const d
     if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p))) return s;
   }
   HIPCHK(hipStreamSynchronize(b->ctx->stream));
+  const double t_call = wall_ms();
   std::vector<int64_t> ioff(n + 1, 0);
   for (int i = 0; i < n; ++i) ioff[i + 1] = ioff[i] + nrhs[i];
   sfdp_status worst = SFDP_OK;
@@ -1841,6 +1898,8 @@ sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const d
     if (s == SFDP_E_NOCONV) worst = s;
     else if (s) return s;
   }
+  if (info)
+    for (int64_t k = 0; k < ioff[n]; ++k) info[k].t_solve_ms = wall_ms() - t_call;
   return worst;
 }
 
@@ -2171,7 +2230,7 @@ sfdp_status server_tick(sfdp_server* S) {
       sl.req = r;
       sl.k = r->next++;
       sl.bad = 0;
-      sl.info = sfdp_info{};
+      sl.info = blank_info();
       const size_t nf = p->n_free;
       p->sl[s] = Slot{r->ybar + sl.k * nf, r->yc ? r->yc + sl.k * p->n_bdry : nullptr, r->y + sl.k * nf,
                       r->u + sl.k * nf, r->lam + sl.k * nf};
@@ -2468,6 +2527,7 @@ sfdp_status sfdp_server_create(sfdp_ctx* ctx, sfdp_precision prec, const sfdp_op
   sfdp_server* S = new (std::nothrow) sfdp_server();
   if (!S) return fail(SFDP_E_NOMEM, "host allocation");
   S->ctx = ctx;
+  ctx->children++;
   S->prec = prec;
   defaults(prec, opts, S->tol_kkt, S->tol_inner, S->max_outer, S->kmax);
   S->user_kmax = (opts && opts->max_krylov > 0) ? opts->max_krylov : 0;
@@ -2501,7 +2561,7 @@ sfdp_status sfdp_server_submit(sfdp_server* S, const sfdp_request* rq, uint64_t*
   r->y = rq->y;
   r->u = rq->u;
   r->lam = rq->lam;
-  r->info.assign(rq->nrhs, sfdp_info{});
+  r->info.assign(rq->nrhs, blank_info());
   r->t_submit = now_ms();
   {
     std::lock_guard<std::mutex> lk(S->mu);
@@ -2584,6 +2644,7 @@ void sfdp_server_destroy(sfdp_server* S) {
   if (S->gmap) hipFree(S->gmap);
   if (S->dg) hipFree(S->dg);
   if (S->hg) hipHostFree(S->hg);
+  S->ctx->children--;
   delete S;
 }
 

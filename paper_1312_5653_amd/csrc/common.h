@@ -27,6 +27,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 #include <functional>
 #include <string>
 #include <vector>
@@ -198,7 +199,7 @@ constexpr int FLAG_ITS = 8, FLAG_CNT = 16, FLAG_LOG = 64, FLAG_WORDS = FLAG_LOG 
 // (red[2 slot]: relative KKT residual, red[2 slot + 1]: imaginary ratio) and
 // the flag words.
 struct Gathered {
-  double red[2 * NRMAX];
+  double red[4 * NRMAX];  // [2 slot]: rho, [2 slot + 1]: imag ratio; from MET_HEAD the metrics
   int flags[FLAG_WORDS];
 };
 
@@ -297,6 +298,7 @@ struct Problem {
   int64_t n_free = 0, n_bdry = 0;
   sfdp_precision prec = SFDP_FP64;
   double beta = 0, alpha = 0;
+  double t_setup_ms = 0;  // host time of the last set-up (sfdp_set_beta or the batch's)
   bool factored = false;
   bool rshift = false;    // factors of K + alpha M instead of K + i alpha M
   Problem* pw = nullptr;  // twin with rshift, built on first use of S_p (Sec. 3.2)
@@ -418,6 +420,9 @@ struct Ctx {
   // demand, counted in `used`)
   void* pool = nullptr;
   size_t pool_bytes = 0;
+  // problems (batch members and twins included) and servers made from this
+  // context and not yet destroyed; sfdp_ctx_destroy refuses while it is > 0
+  std::atomic<int> children{0};
 };
 
 // The instances one launch covers: a single problem (its view passed by value)
@@ -500,8 +505,14 @@ hipError_t launch_apply_M(const Problem& p, int nrhs, const double* x, double* y
 // group slot of the c-th one in byte c.  red holds (rho, imag ratio) of slot s
 // at red[2 s], red[2 s + 1]; per-block partial sums follow from RED_HEAD.
 constexpr int RED_HEAD = 16;
+// Accuracy metrics of slot s at red[MET_HEAD + 2 s] (relative constraint
+// violation, Sec. 6.2) and red[MET_HEAD + 2 s + 1] (blockwise backward error);
+// their MET_N per-block partial sums per slot follow the residual partials.
+constexpr int MET_HEAD = 2 * NRMAX, MET_N = 11;
+static_assert(MET_HEAD + 2 * NRMAX <= RED_HEAD, "metric heads overlap the partial sums");
 int64_t red_pstride(const Problem& p);
 hipError_t launch_kkt_residual(const Target& t);
+hipError_t launch_kkt_metrics(const Target& t);
 hipError_t launch_make_rhs1(const Target& t);
 hipError_t launch_make_rhs2(const Target& t);
 hipError_t launch_update(const Target& t, int single);  // single: one complex solve per step

@@ -236,6 +236,146 @@ __global__ void __launch_bounds__(256) k_kkt_residual(Src src) {
   }
 }
 
+// Accuracy metrics of the KKT iterate (Sec. 2 KKT system; Sec. 6.2): the
+// relative constraint violation ||K y + Kc yc - M u|| / ||K y|| and the
+// blockwise backward error max_i ||r_i|| / (sum_j || |A_ij| |x_j| || + ||b_i||)
+// with |K|, |M|, |Kc| the entrywise absolute values of the assembled matrices.
+// Per node: Kx, Mx and the absolute-value products |K||x|, |M||x| from the same
+// stencils with absolute weights.
+__device__ inline void stencil_abs(const Sten& st, int N, int dim, int i, int j, int k, const double* x,
+                                   double& Kx, double& Mx, double& aKx, double& aMx) {
+  Kx = Mx = aKx = aMx = 0.0;
+  const int kr = dim == 3 ? 1 : 0;
+  for (int dk = -kr; dk <= kr; ++dk)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = i + di, jj = j + dj, kk = k + dk;
+        if (ii <= 0 || jj <= 0 || ii >= N || jj >= N) continue;
+        if (dim == 3 && (kk <= 0 || kk >= N)) continue;
+        const double v = dim == 3 ? x[fidx3(N, ii, jj, kk)] : x[(ii - 1) + (N - 1) * (jj - 1)];
+        const double mi = st.m[di + 1], mj = st.m[dj + 1];
+        double wk, wm;
+        if (dim == 3) {
+          const double mk = st.m[dk + 1];
+          wk = st.k[di + 1] * mj * mk + mi * st.k[dj + 1] * mk + mi * mj * st.k[dk + 1];
+          wm = mi * mj * mk;
+        } else {
+          wk = st.k[di + 1] * mj + mi * st.k[dj + 1];
+          wm = mi * mj;
+        }
+        Kx = fma(wk, v, Kx);
+        Mx = fma(wm, v, Mx);
+        aKx = fma(fabs(wk), fabs(v), aKx);
+        aMx = fma(fabs(wm), fabs(v), aMx);
+      }
+}
+// Kc yc and |Kc| |yc| at a free node (the stencil's boundary neighbours).
+__device__ inline void stencil_kc(const Sten& st, int N, int dim, int i, int j, int k, const int* f2b,
+                                  const double* yc, double& Kc, double& aKc) {
+  Kc = aKc = 0.0;
+  if (!yc) return;
+  const int kr = dim == 3 ? 1 : 0;
+  for (int dk = -kr; dk <= kr; ++dk)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = i + di, jj = j + dj, kk = k + dk;
+        const bool freen = dim == 3 ? free3(N, ii, jj, kk) : (ii > 0 && jj > 0 && ii < N && jj < N);
+        if (freen) continue;
+        const double mi = st.m[di + 1], mj = st.m[dj + 1];
+        double wk;
+        int64_t full;
+        if (dim == 3) {
+          const double mk = st.m[dk + 1];
+          wk = st.k[di + 1] * mj * mk + mi * st.k[dj + 1] * mk + mi * mj * st.k[dk + 1];
+          full = full3(N, ii, jj, kk);
+        } else {
+          wk = st.k[di + 1] * mj + mi * st.k[dj + 1];
+          full = ii + (int64_t)(N + 1) * jj;
+        }
+        const double v = yc[f2b[full]];
+        Kc = fma(wk, v, Kc);
+        aKc = fma(fabs(wk), fabs(v), aKc);
+      }
+}
+
+// Per-block partial sums of squares, MET_N per block in the order
+//   r1, r2, r3, K y, |M||y|, |K||lam|, M ybar, |M||u|, |M||lam|, |K||y|, |Kc||yc|.
+template <class Src>
+__global__ void __launch_bounds__(256) k_kkt_metrics(Src src) {
+  __shared__ double sh[MET_N][4];
+  const Dev& d = src.dev();
+  const int c = blockIdx.y;
+  if (c >= d.nr) return;
+  const int N = d.g.N, s = slot_of(d.map, c), bx = src.bx();
+  const int64_t nfree = d.n_free;
+  const int64_t nb = (nfree + 255) / 256;
+  const Slot& q = d.sl[s];
+  double* part = d.red + RED_HEAD + NRMAX * 2 * nb + (int64_t)s * MET_N * nb;
+  int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
+  double v[MET_N];
+  for (int e = 0; e < MET_N; ++e) v[e] = 0.0;
+  if (t < nfree) {
+    Sten st = make_sten(1.0 / N);
+    int i, j, k = 0;
+    if (d.g.dim == 3) ijk3(t, N, i, j, k);
+    else { i = (int)(t % (N - 1)) + 1; j = (int)(t / (N - 1)) + 1; }
+    double Ky, My, aKy, aMy, Kl, Ml, aKl, aMl, Ku, Mu, aKu, aMu, Kb, Mb, aKb, aMb, Kc, aKc;
+    stencil_abs(st, N, d.g.dim, i, j, k, q.y, Ky, My, aKy, aMy);
+    stencil_abs(st, N, d.g.dim, i, j, k, q.lam, Kl, Ml, aKl, aMl);
+    stencil_abs(st, N, d.g.dim, i, j, k, q.u, Ku, Mu, aKu, aMu);
+    stencil_abs(st, N, d.g.dim, i, j, k, q.ybar, Kb, Mb, aKb, aMb);
+    stencil_kc(st, N, d.g.dim, i, j, k, d.full2bdry, q.yc, Kc, aKc);
+    const double a1 = Mb - My - Kl;
+    const double a2 = -(d.beta * Mu - Ml);
+    const double a3 = -Kc - Ky + Mu;
+    const double w[MET_N] = {a1, a2, a3, Ky, aMy, aKl, Mb, aMu, aMl, aKy, aKc};
+    for (int e = 0; e < MET_N; ++e) v[e] = w[e] * w[e];
+  }
+  for (int e = 0; e < MET_N; ++e)
+    for (int off = 32; off > 0; off >>= 1) v[e] += __shfl_down(v[e], off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int e = 0; e < MET_N; ++e) sh[e][wv] = v[e];
+  __syncthreads();
+  if (threadIdx.x < MET_N) {
+    const int e = threadIdx.x;
+    part[(int64_t)e * nb + bx] = sh[e][0] + sh[e][1] + sh[e][2] + sh[e][3];
+  }
+}
+
+// Fixed-order sums of the metric partials; one block per right-hand side.
+template <class Src>
+__global__ void k_reduce_metrics(Src src) {
+  __shared__ double sh[MET_N][64];
+  const Dev& d = src.dev();
+  const int c = blockIdx.y;
+  if (c >= d.nr) return;
+  const int s = slot_of(d.map, c);
+  const int64_t nb = (d.n_free + 255) / 256;
+  const double* part = d.red + RED_HEAD + NRMAX * 2 * nb + (int64_t)s * MET_N * nb;
+  const int e = threadIdx.x / 64, l = threadIdx.x % 64;  // 11 x 64 threads
+  if (e < MET_N) {
+    double a = 0.0;
+    for (int64_t b = l; b < nb; b += 64) a += part[(int64_t)e * nb + b];
+    sh[e][l] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double n[MET_N];
+    for (int f = 0; f < MET_N; ++f) {
+      double a = 0.0;
+      for (int q = 0; q < 64; ++q) a += sh[f][q];
+      n[f] = sqrt(a);
+    }
+    const double den[3] = {n[4] + n[5] + n[6], d.beta * n[7] + n[8], n[9] + n[7] + n[10]};
+    double eta = 0.0;
+    for (int b = 0; b < 3; ++b)
+      if (n[b] > 0.0) eta = fmax(eta, n[b] / den[b]);
+    d.red[MET_HEAD + 2 * s] = n[3] > 0.0 ? n[2] / n[3] : n[2];
+    d.red[MET_HEAD + 2 * s + 1] = eta;
+  }
+}
+
 // red[2 slot + which] = sqrt(sum part[2b]) / sqrt(sum part[2b+1]) in a fixed
 // order; one block per (instance, right-hand side c = blockIdx.y)
 template <class Src>
@@ -347,7 +487,7 @@ template <class Src>
 __global__ void k_gather(Src src, Gathered* out) {
   const Dev& d = src.dev();
   Gathered& o = out[blockIdx.x];
-  if (threadIdx.x < 2 * NRMAX) o.red[threadIdx.x] = d.red ? d.red[threadIdx.x] : 0.0;
+  if (threadIdx.x < 4 * NRMAX) o.red[threadIdx.x] = d.red ? d.red[threadIdx.x] : 0.0;
   for (int i = threadIdx.x; i < FLAG_WORDS; i += blockDim.x) o.flags[i] = d.flags[i];
 }
 
@@ -500,6 +640,11 @@ int64_t red_pstride(const Problem& p) { return 2 * (int64_t)nblk(p.n_free); }
 hipError_t launch_kkt_residual(const Target& t) {
   launch2(t, K_NF256, k_kkt_residual<One>, k_kkt_residual<Many>, NRMAX, 256, 0);
   launch2(t, K_ONE, k_reduce_ratio<One>, k_reduce_ratio<Many>, NRMAX, 256, 0, 0);
+  return hipGetLastError();
+}
+hipError_t launch_kkt_metrics(const Target& t) {
+  launch2(t, K_NF256, k_kkt_metrics<One>, k_kkt_metrics<Many>, NRMAX, 256, 0);
+  launch2(t, K_ONE, k_reduce_metrics<One>, k_reduce_metrics<Many>, NRMAX, MET_N * 64, 0);
   return hipGetLastError();
 }
 hipError_t launch_make_rhs1(const Target& t) {

@@ -45,10 +45,14 @@ class Info(ctypes.Structure):
     _fields_ = [("rel_kkt", ctypes.c_double), ("rel_kkt_first", ctypes.c_double),
                 ("imag_ratio", ctypes.c_double), ("outer_steps", ctypes.c_int),
                 ("krylov_total", ctypes.c_int), ("krylov_its", ctypes.c_int * 16),
-                ("n_feti", ctypes.c_int), ("minres_its", ctypes.c_int)]
+                ("n_feti", ctypes.c_int), ("minres_its", ctypes.c_int),
+                ("constr_viol", ctypes.c_double), ("eta_blk", ctypes.c_double),
+                ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {"rel_kkt": self.rel_kkt, "rel_kkt_first": self.rel_kkt_first,
+                "constr_viol": self.constr_viol, "eta_blk": self.eta_blk,
+                "t_setup_ms": self.t_setup_ms, "t_solve_ms": self.t_solve_ms,
                 "imag_ratio": self.imag_ratio, "outer_steps": self.outer_steps,
                 "krylov_total": self.krylov_total, "n_feti": self.n_feti,
                 "krylov_its": list(self.krylov_its)[: min(self.n_feti, 16)],
@@ -97,7 +101,7 @@ def load_library(path: str = LIB_PATH):
     P, I, D, VP = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
     lib.sfdp_ctx_create.argtypes = [I, ctypes.c_size_t, VP, ctypes.POINTER(P)]
     lib.sfdp_ctx_destroy.argtypes = [P]
-    lib.sfdp_ctx_destroy.restype = None
+    lib.sfdp_ctx_destroy.restype = ctypes.c_int
     lib.sfdp_last_error.restype = ctypes.c_char_p
     lib.sfdp_problem_create.argtypes = [P, I, I, I, I, ctypes.POINTER(P)]
     lib.sfdp_problem_sizes.argtypes = [P, ctypes.POINTER(Sizes)]
@@ -175,8 +179,10 @@ class Context:
         self.device = device
 
     def close(self):
+        """Free the context; raises SfdpError (E_STATE) while problems, batches or
+        servers made from it are still open (close those first)."""
         if self._h:
-            _lib.sfdp_ctx_destroy(self._h)
+            _check(_lib.sfdp_ctx_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -51,3 +51,9 @@ def test_errors_without_gpu_are_reported_not_raised(lib):
     st = lib.sfdp_ctx_create(-1, 0, None, ctypes.byref(h))
     assert st != 0
     assert lib.sfdp_last_error()
+
+
+def test_destroying_a_null_context_is_a_no_op(lib):
+    lib.sfdp_ctx_destroy.argtypes = [ctypes.c_void_p]
+    lib.sfdp_ctx_destroy.restype = ctypes.c_int
+    assert lib.sfdp_ctx_destroy(None) == 0

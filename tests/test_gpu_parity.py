@@ -320,6 +320,61 @@ def test_error_codes(sf):
     prob.close()
 
 
+@pytest.mark.parametrize("dim,N,m,prec", [(2, 32, 8, 0), (2, 64, 16, 1), (3, 12, 4, 0)])
+def test_accuracy_metrics_match_oracle(sf, dim, N, m, prec):
+    """The relative constraint violation (Sec. 6.2) and the blockwise backward error that a
+    solve reports, computed on the GPU, against the oracle's on the returned iterate.  The
+    solve is cut short (one refinement step, three GMRES iterations) so that every residual
+    block is far above rounding and the two sides can be compared at 1e-10."""
+    sfdp, ctx = sf
+    mesh = fem.Mesh(dim, N)
+    A = fem.assemble(mesh)
+    beta = 1e-3
+    if dim == 2:
+        ybar, yc = W.thermal_target(N)
+    else:
+        ybar, yc = W.sine_target(3, N, *W.modes_for("eight3d", 1))
+        yc = W.random_vector(mesh.m, 3)
+    prob = sfdp.Problem(ctx, dim, N, m, prec)
+    prob.set_beta(beta)
+    y, u, lam, info, st = prob.solve_range_space(_t(ybar), _t(yc), max_outer=1, max_krylov=3, tol_kkt=1e-14)
+    assert st == -3
+    yh, uh, lh = y.cpu().numpy(), u.cpu().numpy(), lam.cpu().numpy()
+    cv = kkt.constraint_violation(A["K"], A["M"], A["Kc"], yc, yh, uh)
+    eta = kkt.eta_blk(A["K"], A["M"], A["Kc"], beta, ybar, yc, yh, uh, lh)
+    rho = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar, yc, yh, uh, lh)
+    assert cv > 1e-8 and eta > 1e-8
+    assert abs(info[0]["constr_viol"] - cv) <= 1e-10 * cv
+    assert abs(info[0]["eta_blk"] - eta) <= 1e-10 * eta
+    assert abs(info[0]["rel_kkt"] - rho) <= 1e-10 * rho
+    assert info[0]["t_setup_ms"] > 0 and info[0]["t_solve_ms"] > 0
+    # a converged solve reports metrics at rounding level
+    y, u, lam, info, st = prob.solve_range_space(_t(ybar), _t(yc), tol_kkt=1e-8)
+    assert st == 0 and 0 <= info[0]["constr_viol"] < 1e-6 and 0 <= info[0]["eta_blk"] < 1e-8
+    prob.close()
+
+
+def test_context_outlives_its_problems(sf):
+    """A context refuses to be destroyed (SFDP_E_STATE) while a problem, batch or
+    server made from it is alive, and is destroyed once they are closed."""
+    sfdp, _ = sf
+    ctx = sfdp.Context(0)
+    prob = sfdp.Problem(ctx, 2, 16, 8)
+    batch = sfdp.Batch(ctx, [16, 32], 8)
+    for live in (prob, batch):
+        with pytest.raises(sfdp.SfdpError) as e:
+            ctx.close()
+        assert e.value.status == -5
+        live.close()
+    srv = sfdp.Server(ctx)
+    with pytest.raises(sfdp.SfdpError) as e:
+        ctx.close()
+    assert e.value.status == -5
+    srv.close()
+    ctx.close()
+    assert ctx._h is None
+
+
 def test_argument_checks(sf):
     """Arguments the C ABI rejects with SFDP_E_INVALID before any launch: 3D
     subdomains of more than 9 cells a side, edge averages on a 3D problem, an
