@@ -241,6 +241,13 @@ def _c4_oracle_one(d):
     return d["j"], r["y"], r["u"], r["lam"]
 
 
+def _c4_oracle_warm(_):
+    import scipy.sparse.linalg  # noqa: F401
+    from oracle import fem, solve  # noqa: F401
+    time.sleep(0.2)  # every worker takes one warm-up task
+    return 0
+
+
 def cpu_instances(count, seed, budget_s=12.0):
     """The oracle on the batched-instance workload, one process per usable host core (at most
     16) over independent instances, for about budget_s seconds: end-to-end solves/s = instances
@@ -253,8 +260,8 @@ def cpu_instances(count, seed, budget_s=12.0):
     info = cpu_model()
     cores = max(1, min(16, info["usable_cores"] or 1))
     sols = {}
-    t_start = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
+        pool.map(_c4_oracle_warm, range(cores))  # start-up and imports outside the timed part
         t_start = time.perf_counter()
         for j, y, u, lam in pool.imap_unordered(_c4_oracle_one, inst):
             sols[j] = (y, u, lam)

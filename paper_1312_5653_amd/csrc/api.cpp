@@ -1342,8 +1342,8 @@ static void sizes_of(const Problem* p, sfdp_sizes* out) {
 }
 
 sfdp_status sfdp_set_tuning(int enable) {
-  if (enable != 0 && enable != 1) return fail(SFDP_E_INVALID, "enable must be 0 or 1");
-  tune_set_enabled(enable != 0);
+  if (enable < 0 || enable > 4) return fail(SFDP_E_INVALID, "enable must be in 0..4");
+  tune_set_mode(enable == 1, enable >= 2 ? enable - 2 : -1);
   return SFDP_OK;
 }
 

@@ -477,7 +477,9 @@ struct TuneEntry {
 // repeatedly) and timed on stream st; later calls return the kept choice.
 // fallback when tuning is off or timing fails.
 int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, const std::function<void(int)>& launch);
-void tune_set_enabled(bool on);            // also forgets every choice
+// on: autotune; force >= 0: run candidate `force` wherever a family has it;
+// either call forgets every choice made so far
+void tune_set_mode(bool on, int force);
 int tune_table(TuneEntry* out, int cap);   // choices made so far (returns their count)
 
 // ---- launchers implemented in the .hip files ----

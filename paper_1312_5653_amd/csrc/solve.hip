@@ -537,6 +537,177 @@ __global__ void __launch_bounds__(256) k_local_solve_rhs(Src src, int mode, int 
                           mode == 1 ? conj_in : 0, src.bx());
 }
 
+// Wave-level LDS ordering: this wave's LDS writes complete before its later
+// reads (and the compiler keeps LDS accesses on their side); no workgroup
+// barrier, so waves of a workgroup never wait for each other.
+__device__ inline void wave_lds_sync() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt = 0
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Full local solve with E^s for one right-hand side by one wavefront (the same
+// results as local_solve_body up to the order of the sums).  Lane p owns node p
+// of every line: it keeps row p of the current line factor in registers (a ring
+// of LRW lines loaded ahead) and forms that row of every dense product against
+// the line vector z, which the wave shares through LDS.  The line recursion is
+// serial, so the wave's whole sweep runs without workgroup barriers; the
+// wavefronts of a subdomain's other right-hand sides read the same line
+// factors shortly after it, from L2.
+template <class TS>
+__device__ inline void local_solve_wave(const Geo2& g, const Maps2& mp, const RhsStride& rs,
+                                        const TS* __restrict__ G, int mode, const cd* __restrict__ f,
+                                        int conj_in, const cd* __restrict__ uc, const cd* __restrict__ mu,
+                                        cd* Xd, cd* Qc, cd* Ubuf, cd* xout, int conj_out, int s) {
+  constexpr int XS = ML * ML;
+  __shared__ cd xall[XS];
+  __shared__ cd zl[ML];
+  const int lane = threadIdx.x;
+  const int ml = g.ml, n2 = ml * ml, ND = g.ND;
+  const TS* Gs = G + (size_t)s * ml * n2;
+  constexpr int LRW = sizeof(TS) == sizeof(cf) ? 3 : 2;
+  const int nsteps = 2 * ml - 1;
+  auto line_of = [&](int t) { return t < ml ? t : 2 * ml - 2 - t; };
+  // row p of line j: G(p, k) at Gs[j n2 + k ml + p] (stored transposed), k < ML
+  // clamped to ml - 1 (zl is zero beyond ml, so those terms vanish)
+  const int pc = min(lane, ml - 1);
+  TS gr[LRW][ML];
+  auto gload = [&](int t, TS (&dst)[ML]) {
+    const TS* src = Gs + (size_t)line_of(t) * n2 + pc;
+#pragma unroll
+    for (int k = 0; k < ML; ++k) dst[k] = src[min(k, ml - 1) * ml];
+  };
+#pragma unroll
+  for (int u = 0; u < LRW; ++u)
+    if (u < nsteps) gload(u, gr[u]);
+  if (lane < ML) zl[lane] = cd{0.0, 0.0};
+  // right-hand side on the r nodes (f / multiplicity; mode 1 minus the corner terms)
+  for (int l = lane; l < n2; l += 64) {
+    const int a = l % ml, b = l / ml;
+    const bool rn = g.rnode(s, a, b);
+    cd v{0.0, 0.0};
+    if (rn) {
+      const cd fv = f[g.freeidx(s, a, b)];
+      v = (1.0 / g.mult(a, b)) * (conj_in ? conj(fv) : fv);
+      if (mode == 1)
+        for (int q = 0; q < 4; ++q) {
+          const int cl = mp.cloc[s * 4 + q];
+          if (cl < 0) continue;
+          const int ca = cl % ml, cb = cl / ml;
+          if (abs(ca - a) > 1 || abs(cb - b) > 1) continue;
+          v = v - g.zloc(a, b, ca, cb) * uc[mp.cgid[s * NQ + q]];
+        }
+    }
+    xall[l] = v;
+  }
+  wave_lds_sync();
+  if (mode == 1) {
+    const int nd = mp.nd[s];
+    for (int i = lane; i < nd; i += 64) {
+      const int l = mp.dloc[s * ND + i];
+      xall[l] = xall[l] - (double)mp.dsgn[s * ND + i] * mu[mp.dmid[s * ND + i]];
+    }
+    wave_lds_sync();
+  }
+  // couplings of node p to nodes p - 1, p, p + 1 of the adjacent line, and the
+  // r-set masks of those three grid columns (bit b: node (p + d - 1, b) is an r node)
+  const bool on = lane < ml;
+  uint64_t zmk[3];
+  cd cpl[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int a = lane + d - 1;
+    zmk[d] = on ? rnode_column(g, s, a) : 0;
+    cpl[d] = (on && a >= 0 && a < ml) ? g.zloc(lane, 1, a, 2) : cd{0.0, 0.0};
+  }
+  for (int t0 = 0; t0 < nsteps; t0 += LRW) {
+#pragma unroll
+    for (int u = 0; u < LRW; ++u) {
+      const int t = t0 + u;
+      if (t < nsteps) {
+        const int j = line_of(t);
+        const bool fwd = t < ml;
+        if (on) {
+          cd v{0.0, 0.0};
+          if (fwd) {
+            // z_j = f_j - A_j,j-1 t_j-1
+            v = xall[lane + ml * j];
+            if (j > 0 && ((zmk[1] >> j) & 1)) {
+#pragma unroll
+              for (int d = 0; d < 3; ++d)
+                if ((zmk[d] >> (j - 1)) & 1) v = v - cpl[d] * xall[lane + d - 1 + ml * (j - 1)];
+            }
+          } else if ((zmk[1] >> j) & 1) {
+            // A_j,j+1 x_j+1
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+              if ((zmk[d] >> (j + 1)) & 1) fma_acc(v, cpl[d], xall[lane + d - 1 + ml * (j + 1)]);
+          }
+          zl[lane] = v;
+        }
+        wave_lds_sync();
+        // row p of G_j z: two accumulators (even and odd k) shorten the FMA chains
+        cd a0{0.0, 0.0}, a1{0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k + 1 < ML; k += 2) {
+          fma_acc(a0, cvt<double>(gr[u][k]), zl[k]);
+          fma_acc(a1, cvt<double>(gr[u][k + 1]), zl[k + 1]);
+        }
+        if (ML & 1) fma_acc(a0, cvt<double>(gr[u][ML - 1]), zl[ML - 1]);
+        const cd tv = a0 + a1;
+        if (on) {
+          cd* o = xall + lane + ml * j;
+          *o = fwd ? tv : *o - tv;  // forward: t_j = G_j z_j; backward: x_j = t_j - G_j A x_j+1
+        }
+        wave_lds_sync();
+        if (t + LRW < nsteps) gload(t + LRW, gr[u]);
+      }
+    }
+  }
+  // outputs
+  const int nd = mp.nd[s];
+  if (mode == 0) {
+    for (int i = lane; i < nd; i += 64) Xd[(size_t)s * ND + i] = xall[mp.dloc[s * ND + i]];
+    if (lane < 4) {
+      const int cl = mp.cloc[s * 4 + lane];
+      cd acc{0.0, 0.0};
+      if (cl >= 0) {
+        const int ca = cl % ml, cb = cl / ml;
+        for (int b = max(cb - 1, 0); b <= min(cb + 1, ml - 1); ++b)
+          for (int a = max(ca - 1, 0); a <= min(ca + 1, ml - 1); ++a)
+            if (g.rnode(s, a, b)) fma_acc(acc, g.zloc(ca, cb, a, b), xall[a + ml * b]);
+      }
+      Qc[s * NQ + lane] = acc;
+    }
+  } else {
+    for (int i = lane; i < nd; i += 64) Ubuf[(size_t)s * ND + i] = xall[mp.dloc[s * ND + i]];
+    for (int l = lane; l < n2; l += 64) {
+      const int a = l % ml, b = l / ml;
+      if (a == 0 || a == ml - 1 || b == 0 || b == ml - 1) continue;  // interior only
+      const cd v = xall[l];
+      xout[g.freeidx(s, a, b)] = conj_out ? conj(v) : v;
+    }
+  }
+}
+
+// One wavefront (workgroup of 64) per (instance, subdomain, right-hand side
+// r = blockIdx.y).  Block ids of one subdomain's right-hand sides differ by
+// multiples of the grid width; when that width is a multiple of 8 they share an
+// XCD, and so the L2 copy of the subdomain's line factors.
+template <class TS, class Src>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_local_solve_wave(Src src, int mode, int fsel, int conj_in, int xsel) {
+  const Dev& d = src.dev();
+  const int r = blockIdx.y;
+  if (r >= d.nr) return;
+  const RhsStride& rs = d.rs;
+  local_solve_wave<TS>(d.g, d.mp, rs, (const TS*)d.G, mode, dev_vec(d, fsel) + r * rs.nf, conj_in,
+                       d.u0 + r * rs.nc, d.mu + r * rs.nmu, d.Xd + r * rs.sb, d.Qc + r * rs.cq,
+                       d.Ubuf + r * rs.sb, mode == 1 ? dev_vec(d, xsel) + r * rs.nf : nullptr,
+                       mode == 1 ? conj_in : 0, src.bx());
+}
+
 // Edge slots of Qc: Qc[s][4 + j] = sum over the Delta slots on side j of
 // sign * Xd, subdomain s's share of q_e^T d_r (d_r = sum_s B_r Z_rr^-1 f_r).
 // One workgroup per subdomain; wave j sums side j.
@@ -1481,21 +1652,20 @@ static void local_solve_t(const Target& t, int mode, int f, int conj_in, int x) 
           conj_in, x);
 }
 
-// Several right-hand sides: one workgroup per subdomain for all of them
-// (candidate 0), or one per subdomain and right-hand side (candidate 1: more
-// workgroups per CU, the line factors re-read from L2).  The autotuner picks;
-// without it, complex64 factors take candidate 1 (134 vs 154 us at 512^2 with
-// four) and complex128 ones candidate 0 (their ring of prefetched lines only
-// stays in registers at one wave per SIMD).
+// Candidates: one workgroup per subdomain for all right-hand sides (0), one
+// workgroup of 256 per subdomain and right-hand side (1: more workgroups per CU,
+// the line factors re-read from L2), one wavefront per subdomain and right-hand
+// side (2: no workgroup barriers in the line recursion).  The autotuner picks;
+// without it the wavefront form runs.
 template <class TS>
 static void local_solve_w(const Target& t, int mode, int f, int conj_in, int x, int nr) {
-  if (nr == 1) {
-    local_solve_t<TS, 1>(t, mode, f, conj_in, x);
-    return;
-  }
   auto run = [&](int c) {
-    if (c == 1)
+    if (c == 2)
+      launch2(t, K_SUB, k_local_solve_wave<TS, One>, k_local_solve_wave<TS, Many>, nr, 64, 0, mode, f, conj_in, x);
+    else if (c == 1)
       launch2(t, K_SUB, k_local_solve_rhs<TS, One>, k_local_solve_rhs<TS, Many>, nr, 256, 0, mode, f, conj_in, x);
+    else if (nr == 1)
+      local_solve_t<TS, 1>(t, mode, f, conj_in, x);
     else if (nr == 2)
       local_solve_t<TS, 2>(t, mode, f, conj_in, x);
     else
@@ -1507,7 +1677,7 @@ static void local_solve_w(const Target& t, int mode, int f, int conj_in, int x, 
   else
     for (const Problem* p : t.probs) ml = std::max(ml, p->ml);
   const TuneKey key{TUNE_LOCAL_SOLVE, dev, ml, t.blocks(K_SUB), (int)sizeof(TS), nr};
-  run(tune_choice(key, 2, sizeof(TS) == sizeof(cf) ? 1 : 0, t.st, run));
+  run(tune_choice(key, 3, 2, t.st, run));
 }
 
 hipError_t launch_local_solve(const Target& t, int mode, int f, int conj_in, int x) {

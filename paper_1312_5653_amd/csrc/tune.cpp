@@ -22,6 +22,7 @@ namespace {
 std::mutex g_mu;
 std::map<TuneKey, int> g_table;
 bool g_enabled = true;
+int g_force = -1;  // >= 0: run this candidate wherever a family has it (tests)
 }  // namespace
 
 bool TuneKey::operator<(const TuneKey& o) const {
@@ -32,6 +33,7 @@ bool TuneKey::operator<(const TuneKey& o) const {
 int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, const std::function<void(int)>& launch) {
   {
     std::lock_guard<std::mutex> lk(g_mu);
+    if (g_force >= 0) return g_force < ncand ? g_force : fallback;
     if (!g_enabled || ncand <= 1) return fallback;
     auto it = g_table.find(key);
     if (it != g_table.end()) return it->second;
@@ -67,9 +69,10 @@ int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, con
   return best;
 }
 
-void tune_set_enabled(bool on) {
+void tune_set_mode(bool on, int force) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_enabled = on;
+  g_force = force;
   g_table.clear();
 }
 

@@ -458,3 +458,9 @@ def set_tuning(enable: bool):
     """Launch-variant autotuning on (default) or off; either forgets earlier choices."""
     load_library()
     _check(_lib.sfdp_set_tuning(int(bool(enable))))
+
+
+def force_variant(c: int):
+    """Run launch variant c of every kernel that has it (tests); set_tuning restores."""
+    load_library()
+    _check(_lib.sfdp_set_tuning(2 + int(c)))

@@ -49,3 +49,33 @@ def test_tuned_and_default_variants_agree(sf, dim, N, m, prec):
         for x0, x1 in zip(a, b):
             assert _rel(x1[q], x0[q]) < 1e-12, q
         assert ia[q]["krylov_its"] == ib[q]["krylov_its"], q
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("N,m", [(64, 8), (96, 32), (40, 20)])
+def test_local_solve_variants_agree(sf, prec, N, m):
+    """The three launch forms of the 2D subdomain solve (one workgroup for every
+    right-hand side, one per right-hand side, one wavefront per right-hand side)
+    give the same FETI-DP solves (1e-12) and iteration counts, for one and for three
+    right-hand sides, including subdomains of 32 x 32 cells (33-node lines, one per lane
+    of a wavefront and no padding) and of 20 x 20."""
+    sfdp, ctx = sf
+    n = (N - 1) ** 2
+    f = torch.tensor(np.stack([W.random_vector(n, 80 + r, complex_=True) for r in range(3)]), device=DEV)
+    out = {}
+    try:
+        for c in (0, 1, 2):
+            sfdp.force_variant(c)
+            p = sfdp.Problem(ctx, 2, N, m, prec)
+            p.set_beta(1e-4)
+            x3, its3 = p.feti_solve(f, tol_inner=1e-10)
+            x1, its1 = p.feti_solve(f[:1].contiguous(), conj_z=True, tol_inner=1e-10)
+            out[c] = (x3.cpu().numpy(), its3, x1.cpu().numpy(), its1)
+            p.close()
+    finally:
+        sfdp.set_tuning(True)
+    for c in (0, 1):
+        assert out[c][1] == out[2][1] and out[c][3] == out[2][3], c
+        for q in range(3):
+            assert _rel(out[c][0][q], out[2][0][q]) < 1e-12, (c, q)
+        assert _rel(out[c][2][0], out[2][2][0]) < 1e-12, c
