@@ -163,6 +163,8 @@ def test_batch_of_four_at_512_mixed(sf):
         assert rho <= 1e-8, (q, rho, info[q])
         ref = solve.range_space_two_factor(A["K"], A["M"], A["Kc"], beta, ybar[q], None, lu=lu, paper_y=False)
         assert _rel(lam[q], ref["lam"]) < 1e-6
+        assert _rel(y[q], ref["y"]) < 1e-7
+        assert _rel(u[q], ref["u"]) < 1e-6
     prob.close()
 
 
