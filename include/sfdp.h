@@ -283,6 +283,25 @@ sfdp_status sfdp_apply_operator(sfdp_problem* p, char which, int nrhs, const dou
 sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, const double* yc,
                               const double* y, const double* u, const double* lam, double* rel);
 
+/* The same relative KKT residuals as sfdp_kkt_residual, computed without any
+ * allocation: for callers that cannot allocate device or pinned memory (code
+ * under stream capture, tight serving loops, harnesses that forbid hipMalloc).
+ * It calls no hipMalloc, hipFree or allocating library routine; its partial
+ * sums live in a fixed device array of 512 KiB (65,536 doubles) per device,
+ * held until the process ends.  Limit: one call handles up to 4 right-hand
+ * sides at a time and needs 16 + 8 ceil(n_free / 256) doubles, so n_free must be
+ * at most 2,096,640 (2D meshes up to 1448 x 1448 cells, 3D up to 128^3);
+ * beyond it the call returns SFDP_E_INVALID.  ybar, yc, y, u, lam as for
+ * sfdp_kkt_residual (device arrays); rel is a DEVICE array of nrhs doubles,
+ * written in stream order on the context's stream (the call does not wait).
+ * Every call on one device shares that device's array and leaves its contents
+ * behind: calls that overlap on one device (other threads, other streams) race
+ * and must be serialised by the caller.  Errors: SFDP_E_INVALID (NULL
+ * argument, nrhs <= 0, mesh over the limit), SFDP_E_STATE (beta not set),
+ * SFDP_E_DEVICE (launch failure). */
+sfdp_status sfdp_kkt_residual_noalloc(sfdp_problem* p, int nrhs, const double* ybar, const double* yc,
+                                      const double* y, const double* u, const double* lam, double* rel);
+
 /* Inspection of the resident FETI-DP operators, for testing.  Writes FP64
  * complex (interleaved) values to the device array out, row-major:
  *   SFDP_Q_SINV  sub s: n_d x n_d  (Z_rr^-1 restricted to the subdomain's

@@ -1303,6 +1303,11 @@ sfdp_status sfdp_ctx_create(int device, size_t mem_budget_bytes, void* stream, s
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
     c->max_lds = lds;
+  hipError_t e = noalloc_scratch(device, &c->scratch);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(SFDP_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+  }
   *out = c;
   return SFDP_OK;
 }
@@ -1456,6 +1461,35 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
     p->nr = 0;
     if (s) return s;
     for (int c = 0; c < nr; ++c) rel[r0 + c] = p->gh->red[2 * c];
+  }
+  return SFDP_OK;
+}
+
+sfdp_status sfdp_kkt_residual_noalloc(sfdp_problem* p, int nrhs, const double* ybar, const double* yc,
+                                      const double* y, const double* u, const double* lam, double* rel) {
+  if (!p || !ybar || !y || !u || !lam || !rel || nrhs <= 0) return fail(SFDP_E_INVALID, "bad arguments");
+  const int64_t need = noalloc_kkt_doubles(p->n_free);
+  if (need > NOALLOC_SCRATCH_DOUBLES)
+    return fail(SFDP_E_INVALID, "n_free = " + std::to_string(p->n_free) + " needs " + std::to_string(need) +
+                                    " scratch doubles, more than the " + std::to_string(NOALLOC_SCRATCH_DOUBLES) +
+                                    " the allocation-free residual holds");
+  if (!(p->beta > 0)) return fail(SFDP_E_STATE, "beta not set");
+  if (!p->ctx->scratch) return fail(SFDP_E_DEVICE, "no scratch address for this device");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  const int64_t n = p->n_free;
+  for (int r0 = 0; r0 < nrhs; r0 += NRMAX) {
+    const int nr = std::min(NRMAX, nrhs - r0);
+    Dev d = p->dev();
+    d.nr = nr;
+    d.map = IDENTITY_MAP;
+    for (int c = 0; c < NRMAX; ++c)
+      d.sl[c] = c < nr ? Slot{ybar + (r0 + c) * n, yc ? yc + (int64_t)(r0 + c) * p->n_bdry : nullptr,
+                              (double*)y + (r0 + c) * n, (double*)u + (r0 + c) * n, (double*)lam + (r0 + c) * n}
+                       : Slot{};
+    d.r1 = d.r2 = d.r3 = nullptr;  // norms only
+    d.red = p->ctx->scratch;
+    hipError_t e = launch_kkt_residual_noalloc(d, p->ctx->stream, rel + r0);
+    if (e != hipSuccess) return fail(SFDP_E_DEVICE, hipGetErrorString(e));
   }
   return SFDP_OK;
 }

@@ -420,6 +420,9 @@ struct Ctx {
   // demand, counted in `used`)
   void* pool = nullptr;
   size_t pool_bytes = 0;
+  // device address of the allocation-free entry point's scratch array on this
+  // context's device (noalloc_scratch, taken at creation)
+  double* scratch = nullptr;
   // problems (batch members and twins included) and servers made from this
   // context and not yet destroyed; sfdp_ctx_destroy refuses while it is > 0
   std::atomic<int> children{0};
@@ -514,6 +517,15 @@ constexpr int MET_HEAD = 2 * NRMAX, MET_N = 11;
 static_assert(MET_HEAD + 2 * NRMAX <= RED_HEAD, "metric heads overlap the partial sums");
 int64_t red_pstride(const Problem& p);
 hipError_t launch_kkt_residual(const Target& t);
+// allocation-free KKT residual (ops.hip): a file-scope device array of this many
+// doubles per device, its device address from noalloc_scratch (called once per
+// device with that device current), the doubles one call of up to NRMAX
+// right-hand sides needs, and the launch over a view whose red points into it
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = 1 << 16;  // 512 KiB
+constexpr int NOALLOC_MAX_DEVICES = 64;
+hipError_t noalloc_scratch(int device, double** out);
+int64_t noalloc_kkt_doubles(int64_t n_free);
+hipError_t launch_kkt_residual_noalloc(const Dev& d, hipStream_t st, double* rel);
 hipError_t launch_kkt_metrics(const Target& t);
 hipError_t launch_make_rhs1(const Target& t);
 hipError_t launch_make_rhs2(const Target& t);

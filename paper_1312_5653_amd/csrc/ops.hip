@@ -10,6 +10,8 @@
 // reduced deterministically (fixed-order two-pass sums) to ||r|| / ||b||.
 #include "common.h"
 
+#include <mutex>
+
 namespace sfdp {
 
 struct Sten {
@@ -217,9 +219,11 @@ __global__ void __launch_bounds__(256) k_kkt_residual(Src src) {
     double a1 = Mybar - My - Kl;
     double a2 = -(d.beta * Mu - Ml);
     double a3 = -Kc - Ky + Mu;
-    d.r1[s * nfree + t] = a1;
-    d.r2[s * nfree + t] = a2;
-    d.r3[s * nfree + t] = a3;
+    if (d.r1) {  // null: norms only (the allocation-free entry point)
+      d.r1[s * nfree + t] = a1;
+      d.r2[s * nfree + t] = a2;
+      d.r3[s * nfree + t] = a3;
+    }
     rn = a1 * a1 + a2 * a2 + a3 * a3;
     bn = Mybar * Mybar + Kc * Kc;
   }
@@ -642,6 +646,51 @@ hipError_t launch_kkt_residual(const Target& t) {
   launch2(t, K_ONE, k_reduce_ratio<One>, k_reduce_ratio<Many>, NRMAX, 256, 0, 0);
   return hipGetLastError();
 }
+// ---- allocation-free KKT residual ----
+// Device scratch of the entry point that allocates nothing: the per-block partial
+// sums (from RED_HEAD) and the ratios (red[2 s]) of up to NRMAX right-hand sides.
+// Each device holds its own copy; host code reaches it only through the address
+// that hipGetSymbolAddress returned for that device (the array's name is a host
+// stand-in, not a device address).
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+std::mutex g_scr_mu;
+double* g_scr_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scr_mu);
+  if (!g_scr_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scr_ptr[device] = (double*)ptr;
+  }
+  *out = g_scr_ptr[device];
+  return hipSuccess;
+}
+
+int64_t noalloc_kkt_doubles(int64_t n_free) { return RED_HEAD + NRMAX * 2 * (int64_t)nblk(n_free); }
+
+__global__ void k_pick_ratio(const double* red, int nr, double* rel) {
+  if ((int)threadIdx.x < nr) rel[threadIdx.x] = red[2 * threadIdx.x];
+}
+
+hipError_t launch_kkt_residual_noalloc(const Dev& d, hipStream_t st, double* rel) {
+  const One o{d};
+  hipLaunchKernelGGL(k_kkt_residual<One>, dim3(nblk(d.n_free), NRMAX), dim3(256), 0, st, o);
+  hipLaunchKernelGGL(k_reduce_ratio<One>, dim3(1, NRMAX), dim3(256), 0, st, o, 0);
+  hipLaunchKernelGGL(k_pick_ratio, dim3(1), dim3(64), 0, st, (const double*)d.red, d.nr, rel);
+  return hipGetLastError();
+}
+
 hipError_t launch_kkt_metrics(const Target& t) {
   launch2(t, K_NF256, k_kkt_metrics<One>, k_kkt_metrics<Many>, NRMAX, 256, 0);
   launch2(t, K_ONE, k_reduce_metrics<One>, k_reduce_metrics<Many>, NRMAX, MET_N * 64, 0);

@@ -25,7 +25,7 @@ EXPORTS = [
     "sfdp_batch_create", "sfdp_batch_destroy", "sfdp_batch_sizes", "sfdp_batch_set_beta",
     "sfdp_batch_solve_range_space", "sfdp_server_create", "sfdp_server_submit", "sfdp_server_poll",
     "sfdp_server_stats", "sfdp_server_destroy", "sfdp_set_coarse_space", "sfdp_batch_inspect",
-    "sfdp_solve_full_space", "sfdp_set_tuning",
+    "sfdp_solve_full_space", "sfdp_set_tuning", "sfdp_kkt_residual_noalloc",
 ]
 
 
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_feti_solve.argtypes = [P, I, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(I)]
     lib.sfdp_apply_operator.argtypes = [P, ctypes.c_char, I, VP, VP, VP]
     lib.sfdp_kkt_residual.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(D)]
+    lib.sfdp_kkt_residual_noalloc.argtypes = [P, I, VP, VP, VP, VP, VP, VP]
     lib.sfdp_inspect.argtypes = [P, I, I, VP, ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.sfdp_interface_apply.argtypes = [P, ctypes.c_char, VP, VP]
     lib.sfdp_timing_enable.argtypes = [P, I]
@@ -137,7 +138,8 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_server_destroy.restype = None
     for name in ("sfdp_ctx_create", "sfdp_problem_create", "sfdp_problem_sizes", "sfdp_set_beta",
                  "sfdp_solve_range_space", "sfdp_apply_schur_inv", "sfdp_feti_solve",
-                 "sfdp_apply_operator", "sfdp_kkt_residual", "sfdp_inspect", "sfdp_interface_apply",
+                 "sfdp_apply_operator", "sfdp_kkt_residual", "sfdp_kkt_residual_noalloc",
+                 "sfdp_inspect", "sfdp_interface_apply",
                  "sfdp_timing_enable", "sfdp_kernel_times", "sfdp_batch_create", "sfdp_batch_sizes",
                  "sfdp_batch_set_beta", "sfdp_batch_solve_range_space", "sfdp_server_create",
                  "sfdp_server_submit", "sfdp_server_poll", "sfdp_server_stats"):
@@ -293,6 +295,14 @@ class Problem:
         rel = (ctypes.c_double * nrhs)()
         _check(_lib.sfdp_kkt_residual(self._h, nrhs, _ptr(ybar), _ptr(yc), _ptr(y), _ptr(u), _ptr(lam), rel))
         return list(rel)
+
+    def kkt_residual_noalloc(self, ybar, yc, y, u, lam, rel):
+        """The allocation-free form: rel is a caller-owned float64 device tensor of
+        nrhs entries, written in stream order (no wait)."""
+        nrhs = 1 if ybar.dim() == 1 else ybar.shape[0]
+        _check(_lib.sfdp_kkt_residual_noalloc(self._h, nrhs, _ptr(ybar), _ptr(yc), _ptr(y), _ptr(u), _ptr(lam),
+                                              _ptr(rel)))
+        return rel
 
     def inspect(self, what: int, sub: int = 0):
         import torch
