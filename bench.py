@@ -228,9 +228,11 @@ def cpu_baseline(N, m, beta, ybar, budget_s=15.0):
             "factor_s": t_factor, "solve_s": t_solve, "cpu": cpu_model()}
 
 
+_ONE_THREAD = {"OMP_NUM_THREADS": "1", "OPENBLAS_NUM_THREADS": "1", "MKL_NUM_THREADS": "1"}
+
+
 def _c4_oracle_one(d):
     """One batched instance on the oracle: assembly, SuperLU factor of Z, two-factor solve."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
     import scipy.sparse.linalg as spla
     from oracle import fem, solve
     from paper_1312_5653_amd import workloads
@@ -241,17 +243,20 @@ def _c4_oracle_one(d):
     return d["j"], r["y"], r["u"], r["lam"]
 
 
-def _c4_oracle_warm(_):
+def _c4_worker_init(barrier):
+    """Worker start-up outside the timed part: one BLAS thread, the oracle's imports, then
+    wait until every worker (and the parent) is ready."""
+    os.environ.update(_ONE_THREAD)
     import scipy.sparse.linalg  # noqa: F401
     from oracle import fem, solve  # noqa: F401
-    time.sleep(0.2)  # every worker takes one warm-up task
-    return 0
+    barrier.wait()
 
 
-def cpu_instances(count, seed, budget_s=12.0):
-    """The oracle on the batched-instance workload, one process per usable host core (at most
-    16) over independent instances, for about budget_s seconds: end-to-end solves/s = instances
-    finished / wall time.  Returns the figure and the oracle solutions it produced."""
+def cpu_instances(count, seed, budget_s=15.0):
+    """The oracle on the batched-instance workload, one single-threaded process per usable
+    host core (at most 16) over independent instances in order, for about budget_s seconds:
+    end-to-end solves/s = instances finished / wall time.  Returns the figure and the oracle
+    solutions it produced."""
     import multiprocessing as mp
     from paper_1312_5653_amd import workloads
     inst = workloads.c4_instances(count, seed)
@@ -260,19 +265,31 @@ def cpu_instances(count, seed, budget_s=12.0):
     info = cpu_model()
     cores = max(1, min(16, info["usable_cores"] or 1))
     sols = {}
-    with mp.get_context("spawn").Pool(cores) as pool:
-        pool.map(_c4_oracle_warm, range(cores))  # start-up and imports outside the timed part
-        t_start = time.perf_counter()
-        for j, y, u, lam in pool.imap_unordered(_c4_oracle_one, inst):
-            sols[j] = (y, u, lam)
-            if time.perf_counter() - t_start > budget_s:
-                break
-        el = time.perf_counter() - t_start
-        pool.terminate()
+    mctx = mp.get_context("spawn")
+    barrier = mctx.Barrier(cores + 1)
+    saved = {k: os.environ.get(k) for k in _ONE_THREAD}
+    os.environ.update(_ONE_THREAD)  # inherited by the spawned workers before numpy loads
+    try:
+        with mctx.Pool(cores, initializer=_c4_worker_init, initargs=(barrier,)) as pool:
+            barrier.wait(timeout=300)
+            t_start = time.perf_counter()
+            for j, y, u, lam in pool.imap_unordered(_c4_oracle_one, inst):
+                sols[j] = (y, u, lam)
+                if time.perf_counter() - t_start > budget_s:
+                    break
+            el = time.perf_counter() - t_start
+            pool.terminate()
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    Ns = sorted(inst[j]["N"] for j in sols)
     return {"value": len(sols) / el, "unit": "end-to-end solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sols)} of the {count} instances (assembly, SuperLU factor of Z and the "
-                      f"two-factor solve each) on {cores} processes, {el:.1f} s",
-            "cpu": info}, sols
+            "sample": f"{len(sols)} of the {count} instances (N {Ns[0]}..{Ns[-1]}; assembly, SuperLU "
+                      f"factor of Z and the two-factor solve each) on {cores} single-threaded processes, "
+                      f"{el:.1f} s", "cpu": info}, sols
 
 
 def run_instances(sfdp, torch, ctx, count, seed, tol_kkt):
@@ -532,6 +549,8 @@ def main():
     ap.add_argument("--c3", type=int, default=64, metavar="N",
                     help="3D configuration: N^3 cells in subdomains of 8^3 (0 skips it)")
     ap.add_argument("--c3-only", action="store_true", help="only the 3D configuration (for profiles)")
+    ap.add_argument("--instances-only", action="store_true",
+                    help="only the batched instances (set-up and solve; for profiles)")
     ap.add_argument("--c3-steps", type=int, default=5)
     ap.add_argument("--schur-betas", type=str, default="1e-2,1e-4,1e-6,1e-8,1e-10",
                     help="betas of the S versus S_p full-space comparison ('' to skip)")
@@ -568,6 +587,11 @@ def main():
     tol_kkt = 1e-8
     if args.c3_only:
         print(json.dumps({"c3_3d": run_c3(sfdp, torch, ctx, args.c3, beta, args.c3_steps, tol_kkt)}), flush=True)
+        ctx.close()
+        return
+    if args.instances_only:
+        r, _ = run_instances(sfdp, torch, ctx, args.instances, 0, tol_kkt)
+        print(json.dumps({"instances_batch": r}), flush=True)
         ctx.close()
         return
     res = {}
