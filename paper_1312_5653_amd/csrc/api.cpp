@@ -350,12 +350,17 @@ void setup_counts(size_t nsub, size_t ml, size_t ND, int nK, size_t c[8]) {
   c[2] = nsub * ND * ND;
   c[3] = nsub * ND * NQ;
   c[4] = nsub * ml * ml * 4;
-  c[5] = nsub * ml * ml * 32;
+  c[5] = 0;  // the line solves use the context's slots (ms_scr)
   c[6] = nsub * NQ * NQ;
   c[7] = (size_t)std::max(nK * nK, 1);
 }
 void setup_counts(const Problem& p, size_t c[8]) { setup_counts(p.nsub, p.ml, p.ND, p.nKmax(), c); }
 size_t pad256(size_t b) { return (b + 255) & ~(size_t)255; }
+// Bytes of the line-solve slots for a set-up of nsub subdomains in all, the
+// largest of m x m cells.
+size_t ms_bytes(size_t nsub, int m) {
+  return pad256(std::min(nsub, (size_t)MS_SLOTS_MAX) * ms_slot_cd(m) * sizeof(cd));
+}
 // Bytes of the pool share of one problem of this mesh.
 size_t setup_bytes(int n_elem, int sub_elem) {
   const size_t P = n_elem / sub_elem;
@@ -363,18 +368,25 @@ size_t setup_bytes(int n_elem, int sub_elem) {
   const int nK = (int)((P - 1) * (P - 1) + 2 * P * (P - 1));
   setup_counts(P * P, sub_elem + 1, ((4 * (sub_elem - 1) + 31) / 32) * 32, nK, c);
   for (int k = 0; k < 8; ++k) b += pad256(c[k] * sizeof(cd));
-  return b;
+  return b + ms_bytes(P * P, sub_elem);
 }
 
 // Carve every problem's set-up scratch out of the context's pool (grown when
 // too small; the stream must be idle).
 sfdp_status alloc_setup(Ctx* ctx, const std::vector<Problem*>& ps) {
-  size_t total = 0;
+  size_t total = 0, nsub = 0;
+  int mmax = 0;
   for (Problem* p : ps) {
     size_t c[8];
     setup_counts(*p, c);
     for (size_t k = 0; k < 8; ++k) total += pad256(c[k] * sizeof(cd));
+    if (p->dim == 2) {
+      nsub += p->nsub;
+      mmax = std::max(mmax, p->m);
+    }
   }
+  const size_t msb = nsub ? ms_bytes(nsub, mmax) : 0;
+  total += msb;
   if (total > ctx->pool_bytes) {
     if (ctx->pool) {
       hipFree(ctx->pool);
@@ -397,6 +409,7 @@ sfdp_status alloc_setup(Ctx* ctx, const std::vector<Problem*>& ps) {
       q += pad256(c[k] * sizeof(cd));
     }
   }
+  ctx->ms_scr = msb ? (cd*)q : nullptr;
   return SFDP_OK;
 }
 void free_setup(Problem& p) {

@@ -266,10 +266,14 @@ __host__ __device__ inline cd* dev_vec(const Dev& d, int sel) {
 // Block sources.  One: a single instance whose view is the kernel argument,
 // block index = blockIdx.x.  Many: instance = inst[blockIdx.x], block index
 // within it = blockIdx.x - first[instance].
+// dev_at(b) / bx_at(b): the same for block b of the map, for kernels whose
+// workgroups loop over the blocks of a launch kind.
 struct One {
   Dev d;
   __device__ inline const Dev& dev() const { return d; }
   __device__ inline int bx() const { return blockIdx.x; }
+  __device__ inline const Dev& dev_at(int) const { return d; }
+  __device__ inline int bx_at(int b) const { return b; }
 };
 struct Many {
   const Dev* devs;
@@ -277,6 +281,8 @@ struct Many {
   const int* first;
   __device__ inline const Dev& dev() const { return devs[inst[blockIdx.x]]; }
   __device__ inline int bx() const { return blockIdx.x - first[inst[blockIdx.x]]; }
+  __device__ inline const Dev& dev_at(int b) const { return devs[inst[b]]; }
+  __device__ inline int bx_at(int b) const { return b - first[inst[b]]; }
 };
 
 // Launch kinds: how many x-blocks an instance takes in a launch.
@@ -420,6 +426,9 @@ struct Ctx {
   // demand, counted in `used`)
   void* pool = nullptr;
   size_t pool_bytes = 0;
+  // line-solve slots of the set-up (MS_SLOTS_MAX at most, carved from the pool
+  // by alloc_setup; valid during a set-up)
+  cd* ms_scr = nullptr;
   // device address of the allocation-free entry point's scratch array on this
   // context's device (noalloc_scratch, taken at creation)
   double* scratch = nullptr;
@@ -487,6 +496,17 @@ int tune_table(TuneEntry* out, int cap);   // choices made so far (returns their
 
 // ---- launchers implemented in the .hip files ----
 // set-up (every instance of the target; FP64 scratch in the views)
+// Set-up line solves: workgroups loop over the subdomains, each with a slot of
+// global scratch for the forward results (per wavefront of 32 columns: ml lines
+// of ml x 32 complex); at most MS_SLOTS_MAX slots (workgroups) per launch.
+constexpr int MS_SLOTS_MAX = 512;
+constexpr int MS_WAVE_COLS = 32;
+// complex entries of a slot for subdomains of m x m cells (4m columns at most:
+// the Delta slots and the corners)
+inline size_t ms_slot_cd(int m) {
+  const size_t ml = m + 1, nw = (4 * (size_t)m + MS_WAVE_COLS - 1) / MS_WAVE_COLS;
+  return nw * ml * ml * MS_WAVE_COLS;
+}
 hipError_t launch_setup(const Target& t);
 // solve: nr <= NRMAX right-hand sides per instance (the views' nr), r-major
 // buffers with the strides of Problem::rs(); f and x name instance vectors

@@ -116,6 +116,140 @@ __global__ void __launch_bounds__(256) k_factor_lines(Src src) {
   }
 }
 
+// LDS visibility inside one wavefront: wait for this wave's LDS operations and
+// keep the compiler from moving memory accesses across (no workgroup barrier).
+__device__ inline void wave_sync_lds() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt = 0
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Gauss-Jordan inverse of the 33 x 33 block of k_factor_lines_wave in place, in
+// rotated coordinates: before pivot k lane p holds R[q] = T[p][(q + k0) % 33]
+// with k0 the first pivot of the current group of three, so pivot k sits at the
+// fixed register k - k0 and the pivot row passes through LDS in the same
+// rotation.  After each group the registers rotate by three; after all 33
+// pivots (the padding rows and columns beyond ml are identity and pivot
+// trivially) the rotation is whole again.  Every register index is static and
+// the loop body stays small (three pivots).
+__device__ __forceinline__ void gj_wave_invert(cd (&T)[MLMAX], cd (*rowk)[MLMAX], int p) {
+  static_assert(MLMAX % 3 == 0, "pivot groups of three");
+  for (int k0 = 0; k0 < MLMAX; k0 += 3) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int k = k0 + u;
+      cd* rk = rowk[k & 1];
+      if (p == k) {
+#pragma unroll
+        for (int q = 0; q < MLMAX; ++q) rk[q] = T[q];
+      }
+      wave_sync_lds();
+      const cd piv = cdiv(cd{1.0, 0.0}, rk[u]);
+      const bool me = p == k;
+      const cd f = me ? -piv : T[u] * piv;
+#pragma unroll
+      for (int q = 0; q < MLMAX; ++q) {
+        if (q == u) continue;
+        cd v = me ? cd{0.0, 0.0} : T[q];
+        fma_acc(v, -f, rk[q]);
+        T[q] = v;
+      }
+      T[u] = me ? piv : -f;
+    }
+    cd t0 = T[0], t1 = T[1], t2 = T[2];
+#pragma unroll
+    for (int q = 0; q < MLMAX - 3; ++q) T[q] = T[q + 3];
+    T[MLMAX - 3] = t0;
+    T[MLMAX - 2] = t1;
+    T[MLMAX - 1] = t2;
+  }
+}
+
+// The same line factorization with one wavefront per subdomain.  Lane p owns
+// row p of the current line block in registers (rows ml..63 are idle padding):
+// T_j is formed from the rows of G_j-1 (the neighbouring rows of
+// G_j-1 A_j-1,j by lane shuffles), then inverted in place by Gauss-Jordan
+// without pivoting, the pivot row passing through LDS.  The T_j and G_j are
+// complex symmetric, so lane p's row is also column p: the transposed store of
+// k_factor_lines becomes one coalesced store per column index.  One wavefront
+// needs no workgroup barrier; the per-step LDS traffic is the pivot row only.
+template <class Src>
+__global__ void __launch_bounds__(64) k_factor_lines_wave(Src src) {
+  __shared__ cd rowk[2][MLMAX];
+  __shared__ cd cpl[MLMAX][3];
+  const Dev& d = src.dev();
+  const Geo2& g = d.g;
+  const int s = src.bx(), ml = g.ml, n2 = ml * ml, p = threadIdx.x;
+  // coupling of node b of a line to node b + e - 1 of the neighbouring line
+  for (int t = p; t < ml * 3; t += 64) {
+    const int b = t / 3, e = t % 3, a = b + e - 1;
+    cpl[b][e] = (a >= 0 && a < ml) ? g.zloc(b, 1, a, 0) : cd{0.0, 0.0};
+  }
+  cd cplp[3], dgb[3], dgi[3];  // row p's couplings and its in-line band (boundary / interior lines)
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int a = p + e - 1;
+    const bool ok = p < ml && a >= 0 && a < ml;
+    cplp[e] = ok ? g.zloc(p, 1, a, 0) : cd{0.0, 0.0};
+    dgb[e] = ok ? g.zloc(p, 0, a, 0) : cd{0.0, 0.0};
+    dgi[e] = ok ? g.zloc(p, 1, a, 1) : cd{0.0, 0.0};
+  }
+  wave_sync_lds();
+  cd T[MLMAX];
+#pragma unroll
+  for (int q = 0; q < MLMAX; ++q) T[q] = cd{0.0, 0.0};
+  uint64_t mprev = 0;
+  for (int j = 0; j < ml; ++j) {
+    const bool bnd = j == 0 || j == ml - 1;
+    cd dg[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) dg[e] = bnd ? dgb[e] : dgi[e];
+    const uint64_t mj = __ballot(p < ml && g.rnode(s, p, j));  // r nodes of line j
+    const bool rp = (mj >> p) & 1;
+    const bool rpm = p >= 1 && ((mprev >> (p - 1)) & 1), rp0 = (mprev >> p) & 1,
+               rpp = p + 1 < ml && ((mprev >> (p + 1)) & 1);
+    // T_j row p = E_jj row p - sum_a A_j,j-1[p][a] U[a][:],  U = G_j-1 A_j-1,j;
+    // U row p from T (G_j-1 row p) in a sliding window, T overwritten behind it
+    cd prv{0.0, 0.0}, cur = T[0];
+#pragma unroll
+    for (int q = 0; q < MLMAX; ++q) {
+      const cd nxt = q + 1 < MLMAX ? T[q + 1] : cd{0.0, 0.0};
+      cd u{0.0, 0.0};
+      if (q >= 1 && ((mprev >> (q - 1)) & 1)) fma_acc(u, prv, cpl[q - 1][2]);
+      if ((mprev >> q) & 1) fma_acc(u, cur, cpl[q][1]);
+      if (q + 1 < ml && ((mprev >> (q + 1)) & 1)) fma_acc(u, nxt, cpl[q + 1][0]);
+      cd um, up;
+      um.x = __shfl(u.x, p - 1, 64);
+      um.y = __shfl(u.y, p - 1, 64);
+      up.x = __shfl(u.x, p + 1, 64);
+      up.y = __shfl(u.y, p + 1, 64);
+      const bool rq = (mj >> q) & 1;
+      cd v{0.0, 0.0};
+      if (rp && rq) {
+        v = q == p - 1 ? dg[0] : q == p ? dg[1] : q == p + 1 ? dg[2] : cd{0.0, 0.0};
+        if (rpm) v = v - cplp[0] * um;
+        if (rp0) v = v - cplp[1] * u;
+        if (rpp) v = v - cplp[2] * up;
+      } else if (p == q) {
+        v = cd{1.0, 0.0};
+      }
+      T[q] = v;
+      prv = cur;
+      cur = nxt;
+    }
+    // Gauss-Jordan: T <- T^-1 (rows and columns beyond ml are identity)
+    gj_wave_invert(T, rowk, p);
+    cd* out = d.G64 + ((size_t)s * ml + j) * n2;
+    if (p < ml) {
+#pragma unroll
+      for (int q = 0; q < MLMAX; ++q)
+        if (q < ml) out[q * ml + p] = T[q];
+    }
+    mprev = mj;
+  }
+}
+
 template <class Src>
 __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
   const Dev& d = src.dev();
@@ -292,6 +426,266 @@ __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
         }
       }
       __syncthreads();
+    }
+  }
+}
+
+// ---- multi_solve on the matrix cores ----
+// The same solves E^s X = [e_Delta, Z_rc] as k_multi_solve, with every line
+// product G_j Z (33 x 33 by 33 x 32, complex) on v_mfma_f64_16x16x4f64: rows and
+// contraction index 0..31 as 2 x 8 tiles of 16 x 4 (complex = four real
+// products), the 33rd row and column (ml = 33) on the vector units.  A
+// workgroup of four wavefronts takes one subdomain, wavefront w the columns
+// 32 w .. 32 w + 31; the wavefronts share nothing but the tables, so the line
+// recursion runs without workgroup barriers.  The forward results t_j wait for
+// the backward sweep in a per-workgroup slot of global scratch (ml x 32 complex
+// per wavefront and line); the workgroups loop over the subdomains, so the
+// scratch is at most MS_SLOTS_MAX slots whatever the batch size.
+//
+// Operand layouts of v_mfma_f64_16x16x4f64 (a wavefront of 64 lanes, l = lane):
+// A (16 x 4): lane l holds A[l % 16][l / 16]; B (4 x 16): lane l holds
+// B[l / 16][l % 16]; C/D (16 x 16): lane l, register r holds D[4 r + l / 16][l % 16],
+// so register r of a result tile is the B operand of contraction step r.
+typedef double d4v __attribute__((ext_vector_type(4)));
+constexpr int MS_COLS = 32;  // columns per wavefront
+static_assert(MS_COLS == MS_WAVE_COLS, "columns per wavefront");
+
+__device__ inline d4v mfma64(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <class Src>
+__global__ void __launch_bounds__(256) k_multi_solve_mfma(Src src, int total, cd* mscr, size_t slot_cd) {
+  __shared__ cd tb[4][MLMAX][MS_COLS];  // per wavefront: t_j (then x_j) of its columns
+  __shared__ int slotmap[MLMAX * MLMAX];
+  __shared__ int sdl[128];
+  __shared__ cd cpl[MLMAX][3];
+  __shared__ cd cst[4][9];
+  __shared__ int cab[4][2];
+  __shared__ int s_nc;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
+  cd* slot = mscr + (size_t)blockIdx.x * slot_cd;
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    const Dev& d = src.dev_at(b);
+    const Geo2& g = d.g;
+    const Maps2& mp = d.mp;
+    const int s = src.bx_at(b), ml = g.ml, n2 = ml * ml, ND = g.ND;
+    const int nd = mp.nd[s];
+    __syncthreads();  // the previous subdomain's tables are no longer read
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) slotmap[i] = -1;
+    if (threadIdx.x < ml * 3) {
+      const int p = threadIdx.x / 3, e = threadIdx.x % 3, a = p + e - 1;
+      cpl[p][e] = (a >= 0 && a < ml) ? g.zloc(p, 1, a, 0) : cd{0.0, 0.0};
+    }
+    if (threadIdx.x < 36) {
+      const int q = threadIdx.x / 9, e = threadIdx.x % 9;
+      const int cl = mp.cloc[s * 4 + q];  // corners are listed first (compact)
+      cd v{0.0, 0.0};
+      if (cl >= 0) {
+        const int ca = cl % ml, cb = cl / ml, a = ca + e % 3 - 1, bb = cb + e / 3 - 1;
+        if (a >= 0 && a < ml && bb >= 0 && bb < ml) v = g.zloc(a, bb, ca, cb);
+        if (e == 0) {
+          cab[q][0] = ca;
+          cab[q][1] = cb;
+        }
+      }
+      cst[q][e] = v;
+    }
+    if (threadIdx.x == 0) {
+      int nc = 0;
+      for (int q = 0; q < 4; ++q) nc += (mp.cloc[s * 4 + q] >= 0);
+      s_nc = nc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+      const int node = mp.dloc[s * ND + i];
+      sdl[i] = node;
+      slotmap[node] = i;
+    }
+    __syncthreads();
+    const int ncol = nd + s_nc, c0 = w * MS_COLS;
+    if (c0 >= ncol) continue;  // no columns for this wavefront (no barrier follows)
+    const bool big = ml == MLMAX;  // the 33rd row and column exist
+    const cd* G = d.G64 + (size_t)s * ml * n2;
+    cd (*T)[MS_COLS] = tb[w];
+    // Z[k][c] of line j: the right-hand side minus the coupling to line j - 1
+    // (forward) or the coupling to line j + 1 (backward), masked to r nodes
+    auto zval = [&](int k, int c, int j, bool fwd, uint64_t mj, uint64_t mo) -> cd {
+      const int col = c0 + c;
+      cd v{0.0, 0.0};
+      if (k >= ml || col >= ncol || !((mj >> k) & 1)) return v;
+      if (fwd) {
+        if (col < nd) {
+          if (sdl[col] == k + ml * j) v = cd{1.0, 0.0};
+        } else {
+          const int q = col - nd, da = k - cab[q][0] + 1, db = j - cab[q][1] + 1;
+          if (da >= 0 && da < 3 && db >= 0 && db < 3) v = cst[q][da + 3 * db];
+        }
+        if (j > 0)
+          for (int e = 0; e < 3; ++e) {
+            const int a = k + e - 1;
+            if (a >= 0 && a < ml && ((mo >> a) & 1)) v = v - cpl[k][e] * T[a][c];
+          }
+      } else {
+        for (int e = 0; e < 3; ++e) {
+          const int a = k + e - 1;
+          if (a >= 0 && a < ml && ((mo >> a) & 1)) fma_acc(v, cpl[k][e], T[a][c]);
+        }
+      }
+      return v;
+    };
+    // one line: X = C0 + sgn G_j Z with Z from zval; C0 = 0 (forward) or t_j (backward)
+    auto line = [&](int j, bool fwd, uint64_t mj, uint64_t mo, d4v (&Cr)[2][2], d4v (&Ci)[2][2],
+                    cd (&x32)[2]) {
+      const cd* Gj = G + (size_t)j * n2;  // element (p, q) at [q ml + p]
+      double br[8][2], bi[8][2];
+      cd z32[2];
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          const cd z = zval(4 * kk + lq, 16 * nt + lr, j, fwd, mj, mo);
+          br[kk][nt] = z.x;
+          bi[kk][nt] = z.y;
+        }
+        z32[nt] = big ? zval(32, 16 * nt + lr, j, fwd, mj, mo) : cd{0.0, 0.0};
+      }
+      wave_sync_lds();  // every read of T for Z is done before T is overwritten
+      const double sg = fwd ? 1.0 : -1.0;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        if (16 * mt >= ml) continue;
+        double ar[8], ai[8];
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          const int p = 16 * mt + lr, q = 4 * kk + lq;
+          const cd a = (p < ml && q < ml) ? Gj[(size_t)q * ml + p] : cd{0.0, 0.0};
+          ar[kk] = sg * a.x;
+          ai[kk] = sg * a.y;
+        }
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          d4v cr = Cr[mt][nt], ci = Ci[mt][nt];
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
+            if (4 * kk >= ml) break;
+            cr = mfma64(ar[kk], br[kk][nt], cr);
+            cr = mfma64(-ai[kk], bi[kk][nt], cr);
+            ci = mfma64(ar[kk], bi[kk][nt], ci);
+            ci = mfma64(ai[kk], br[kk][nt], ci);
+          }
+          if (big) {  // contraction index 32: rank-one term
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int p = 16 * mt + 4 * r + lq;
+              const cd gp = Gj[(size_t)32 * ml + p];
+              cd acc{cr[r], ci[r]};
+              fma_acc(acc, cd{sg * gp.x, sg * gp.y}, z32[nt]);
+              cr[r] = acc.x;
+              ci[r] = acc.y;
+            }
+          }
+          Cr[mt][nt] = cr;
+          Ci[mt][nt] = ci;
+        }
+      }
+      if (big) {  // row 32: sum over this lane's contraction indices, then over the lane groups
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          cd acc{0.0, 0.0};
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
+            const cd gq = Gj[(size_t)(4 * kk + lq) * ml + 32];
+            fma_acc(acc, gq, cd{br[kk][nt], bi[kk][nt]});
+          }
+          acc.x += __shfl_xor(acc.x, 16, 64);
+          acc.y += __shfl_xor(acc.y, 16, 64);
+          acc.x += __shfl_xor(acc.x, 32, 64);
+          acc.y += __shfl_xor(acc.y, 32, 64);
+          fma_acc(acc, Gj[(size_t)32 * ml + 32], z32[nt]);
+          x32[nt] = x32[nt] + cd{sg * acc.x, sg * acc.y};
+        }
+      }
+    };
+    // write x_j (registers) to T, and the outputs of line j if out
+    auto emit = [&](int j, const d4v (&Cr)[2][2], const d4v (&Ci)[2][2], const cd (&x32)[2], bool out) {
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int p = 16 * mt + 4 * r + lq, c = 16 * nt + lr;
+            if (p >= ml) continue;
+            const cd x{Cr[mt][nt][r], Ci[mt][nt][r]};
+            T[p][c] = x;
+            const int col = c0 + c;
+            if (!out || col >= ncol) continue;
+            const int node = p + ml * j, sl = slotmap[node];
+            if (col < nd) {
+              if (sl >= 0) d.Sinv64[((size_t)s * ND + sl) * ND + col] = x;
+            } else {
+              const int q = col - nd;
+              if (sl >= 0) d.Phi64[((size_t)s * ND + sl) * NQ + q] = x;
+              d.PhiFull[((size_t)s * n2 + node) * 4 + q] = x;
+            }
+          }
+      if (big && lq == 0) {
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          const int c = 16 * nt + lr, col = c0 + c, node = 32 + ml * j;
+          T[32][c] = x32[nt];
+          if (!out || col >= ncol) continue;
+          const int sl = slotmap[node];
+          if (col < nd) {
+            if (sl >= 0) d.Sinv64[((size_t)s * ND + sl) * ND + col] = x32[nt];
+          } else {
+            const int q = col - nd;
+            if (sl >= 0) d.Phi64[((size_t)s * ND + sl) * NQ + q] = x32[nt];
+            d.PhiFull[((size_t)s * n2 + node) * 4 + q] = x32[nt];
+          }
+        }
+      }
+      wave_sync_lds();
+    };
+    cd* wsl = slot + (size_t)w * ml * ml * MS_COLS;  // this wavefront's lines, ml x 32 each
+    d4v Cr[2][2], Ci[2][2];
+    cd x32[2];
+    // steps 0 .. ml-1: forward sweep t_j = G_j (rhs_j - A_j,j-1 t_j-1), kept in T
+    // and in the slot; steps ml .. 2 ml - 2: backward sweep x_j = t_j - G_j A_j,j+1 x_j+1
+    // (T holds x_j+1).  One loop, so the line body is generated once.
+    uint64_t mo = 0;  // r-node mask of the line the coupling reaches (j - 1 or j + 1)
+    for (int step = 0; step < 2 * ml - 1; ++step) {
+      const bool fwd = step < ml;
+      const int j = fwd ? step : 2 * ml - 2 - step;
+      const uint64_t mj = __ballot(l < ml && g.rnode(s, l, j));
+      cd* o = wsl + (size_t)j * ml * MS_COLS;
+      if (fwd) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt) Cr[mt][nt] = Ci[mt][nt] = d4v{0.0, 0.0, 0.0, 0.0};
+        x32[0] = x32[1] = cd{0.0, 0.0};
+      } else {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * mt + 4 * r + lq;
+              const cd t = row < ml ? o[row * MS_COLS + 16 * nt + lr] : cd{0.0, 0.0};
+              Cr[mt][nt][r] = t.x;
+              Ci[mt][nt][r] = t.y;
+            }
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) x32[nt] = big ? o[32 * MS_COLS + 16 * nt + lr] : cd{0.0, 0.0};
+      }
+      line(j, fwd, mj, mo, Cr, Ci, x32);
+      emit(j, Cr, Ci, x32, !fwd || j == ml - 1);
+      if (fwd && j < ml - 1)
+        for (int idx = l; idx < ml * MS_COLS; idx += 64) o[idx] = T[idx / MS_COLS][idx % MS_COLS];
+      mo = mj;  // the next line (j + 1 forward, j - 1 backward) couples to this one
     }
   }
 }
@@ -682,6 +1076,93 @@ __global__ void __launch_bounds__(256) k_gj_rows(int n, int k0, int b, cd* A, co
     if (r < nr && (i < k0 || i >= k0 + b)) A[(size_t)i * n + j] = v[rr];
   }
 }
+// The same update on the matrix cores (v_mfma_f64_16x16x4f64; operand layouts
+// as for k_multi_solve_mfma).  Workgroup (x, y, z) takes rows 32 y .. 32 y + 31
+// of matrix z and the columns [x jspan, (x + 1) jspan).  U = A_iK D (32 x b) is
+// formed once in LDS and held by every wavefront as negated A operands; the
+// wavefronts then sweep their columns in tiles of 16: C = A_ij (two 16 x 16
+// tiles), C += (-U) A_Kj over the b <= 32 pivots of the panel (8 contraction
+// steps of 4, four real products per complex one), stored back except in the
+// panel's rows and columns.
+constexpr int GJM_RT = 32;
+__global__ void __launch_bounds__(256) k_gj_rows_mfma(int n, int k0, int b, int jspan, cd* A, const cd* D,
+                                                      size_t sA, size_t sD) {
+  __shared__ cd Dl[GJ_PB * GJ_PB], Ak[GJM_RT * GJ_PB], Ul[GJM_RT * GJ_PB];
+  A += blockIdx.z * sA;
+  D += blockIdx.z * sD;
+  const int i0 = blockIdx.y * GJM_RT;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
+  gj_load_d(Dl, D, b);
+  for (int t = threadIdx.x; t < GJM_RT * GJ_PB; t += blockDim.x) {
+    const int r = t / GJ_PB, c = t % GJ_PB, i = i0 + r;
+    const bool in = i < n && c < b && (i < k0 || i >= k0 + b);
+    Ak[t] = in ? A[(size_t)i * n + k0 + c] : cd{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < GJM_RT * GJ_PB; t += blockDim.x) {
+    const int r = t / GJ_PB, c = t % GJ_PB;
+    cd u{0.0, 0.0};
+    for (int q = 0; q < b; ++q) fma_acc(u, Ak[r * GJ_PB + q], Dl[q * GJ_PB + c]);
+    Ul[t] = u;  // zero for rows of the panel, beyond n, and columns beyond b
+  }
+  __syncthreads();
+  double ar[2][8], ai[2][8];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const cd u = Ul[(16 * mt + lr) * GJ_PB + 4 * kk + lq];
+      ar[mt][kk] = -u.x;
+      ai[mt][kk] = -u.y;
+    }
+  bool rok[2][4];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 16 * mt + 4 * r + lq;
+      rok[mt][r] = i < n && (i < k0 || i >= k0 + b);
+    }
+  const int je = min(n, (int)(blockIdx.x + 1) * jspan);
+  for (int j0 = blockIdx.x * jspan + 16 * w; j0 < je; j0 += 64) {
+    const int j = j0 + lr;
+    const bool jin = j < je, jok = jin && (j < k0 || j >= k0 + b);
+    double br[8], bi[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 4 * kk + lq;
+      const cd v = (jin && k < b) ? A[(size_t)(k0 + k) * n + j] : cd{0.0, 0.0};
+      br[kk] = v.x;
+      bi[kk] = v.y;
+    }
+    d4v cr[2], ci[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 16 * mt + 4 * r + lq;
+        const cd v = (jok && rok[mt][r]) ? A[(size_t)i * n + j] : cd{0.0, 0.0};
+        cr[mt][r] = v.x;
+        ci[mt][r] = v.y;
+      }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        cr[mt] = mfma64(ar[mt][kk], br[kk], cr[mt]);
+        cr[mt] = mfma64(-ai[mt][kk], bi[kk], cr[mt]);
+        ci[mt] = mfma64(ar[mt][kk], bi[kk], ci[mt]);
+        ci[mt] = mfma64(ai[mt][kk], br[kk], ci[mt]);
+      }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 16 * mt + 4 * r + lq;
+        if (jok && rok[mt][r]) A[(size_t)i * n + j] = cd{cr[mt][r], ci[mt][r]};
+      }
+  }
+}
 // The panel itself, after k_gj_rows (old panel values staged in LDS before any
 // write): blocks [0, gx) take GJ_CT columns j each (the panel rows: A_Kj = D A_Kj,
 // A_KK = D), blocks [gx, 2 gx) take GJ_CT rows i each outside the panel
@@ -760,14 +1241,20 @@ __global__ void __launch_bounds__(256) k_gj_panel(int n, int k0, int b, int gx, 
 // entries).  Pivots [0, kb) must already have been taken.
 hipError_t gj_range(int n, int kb, int ke, cd* A, size_t sA, cd* work, size_t sW, int batch, hipStream_t st) {
   if (ke <= kb) return hipSuccess;
-  const int gx = (n + GJ_CT - 1) / GJ_CT, gy = (n + GJ_RT - 1) / GJ_RT;
+  const int gx = (n + GJ_CT - 1) / GJ_CT;
+  // outer update: rows by 32; columns split only when few matrices would leave
+  // the device idle (the panel's U is then formed again per column block)
+  const int gym = (n + GJM_RT - 1) / GJM_RT;
+  const int gxm = batch * gym >= 1024 ? 1 : std::max(1, std::min((n + 63) / 64, (1024 + batch * gym - 1) / (batch * gym)));
+  const int jspan = ((n + gxm - 1) / gxm + 63) / 64 * 64;
   hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, batch), dim3(256), 0, st, n, kb, std::min(GJ_PB, ke - kb),
                      (const cd*)A, work, sA, sW);
   for (int k0 = kb, p = 0; k0 < ke; k0 += GJ_PB, ++p) {
     const int b = std::min(GJ_PB, ke - k0);
     cd* D = work + (p & 1) * GJ_PB * GJ_PB;
     cd* Dn = work + ((p + 1) & 1) * GJ_PB * GJ_PB;
-    hipLaunchKernelGGL(k_gj_rows, dim3(gx, gy, batch), dim3(256), 0, st, n, k0, b, A, (const cd*)D, sA, sW);
+    hipLaunchKernelGGL(k_gj_rows_mfma, dim3(gxm, gym, batch), dim3(256), 0, st, n, k0, b, jspan, A,
+                       (const cd*)D, sA, sW);
     hipLaunchKernelGGL(k_gj_panel, dim3(2 * gx + 1, 1, batch), dim3(256), 0, st, n, k0, b, gx, ke, A,
                        (const cd*)D, Dn, sA, sW);
   }
@@ -798,8 +1285,18 @@ hipError_t launch_setup(const Target& t) {
   const int yK = (ND * (ND + 1) / 2 + 255) / 256;
   launch2(t, K_SUB, k_zero_sub<One>, k_zero_sub<Many>, yS, 256, 0, 0);
   launch2(t, K_SUB, k_zero_sub<One>, k_zero_sub<Many>, yP, 256, 0, 1);
-  launch2(t, K_SUB, k_factor_lines<One>, k_factor_lines<Many>, 1, 256, 0);
-  launch2(t, K_SUB, k_multi_solve<One>, k_multi_solve<Many>, 1, 256, 0);
+  launch2(t, K_SUB, k_factor_lines_wave<One>, k_factor_lines_wave<Many>, 1, 64, 0);
+  {
+    const int total = t.blocks(K_SUB), grid = std::min(total, MS_SLOTS_MAX);
+    cd* mscr = ps[0]->ctx->ms_scr;
+    size_t slot = 0;
+    for (Problem* p : ps) slot = std::max(slot, ms_slot_cd(p->m));
+    if (t.single())
+      hipLaunchKernelGGL(k_multi_solve_mfma<One>, dim3(grid), dim3(256), 0, t.st, t.src1(), total, mscr, slot);
+    else
+      hipLaunchKernelGGL(k_multi_solve_mfma<Many>, dim3(grid), dim3(256), 0, t.st, t.srcN(K_SUB), total, mscr,
+                         slot);
+  }
   launch2(t, K_SUB, k_edge_basis<One>, k_edge_basis<Many>, 1, 256, 0);
   launch2(t, K_SUB, k_copy_sub<One>, k_copy_sub<Many>, yS, 256, 0);
   launch2(t, K_SUB, k_invert_batched<One>, k_invert_batched<Many>, 1, 1024, 0);
