@@ -292,7 +292,7 @@ def cpu_instances(count, seed, budget_s=15.0):
                       f"{el:.1f} s", "cpu": info}, sols
 
 
-def run_instances(sfdp, torch, ctx, count, seed, tol_kkt):
+def run_instances(sfdp, torch, ctx, count, seed, tol_kkt, setup_bits=64):
     """Batched instances: `count` independent 2D instances, N_j in 64..256 (log-uniform,
     multiple of 32), subdomains of 32x32 cells, beta_j = 10^U[-6,-1], one 16-mode sine target
     each; every instance has a new beta, so a pass is set-up + solve (end to end)."""
@@ -303,6 +303,7 @@ def run_instances(sfdp, torch, ctx, count, seed, tol_kkt):
     ybars = [torch.tensor(workloads.sine_target(2, d["N"], *workloads.modes_for("sixteen2d", d["seed"]))[0],
                           device="cuda:0") for d in inst]
     b = sfdp.Batch(ctx, Ns, 32, sfdp.SFDP_MIXED)
+    sfdp.set_setup_arithmetic(setup_bits)
     try:
         b.set_beta(betas)
         b.solve_range_space(ybars, None, tol_kkt=tol_kkt)
@@ -314,6 +315,8 @@ def run_instances(sfdp, torch, ctx, count, seed, tol_kkt):
     except BaseException:
         b.close()
         raise
+    finally:
+        sfdp.set_setup_arithmetic(64)
     try:
         ys, us, ls, infos, st = b.solve_range_space(ybars, None, tol_kkt=tol_kkt)
         torch.cuda.synchronize()
@@ -330,22 +333,29 @@ def run_instances(sfdp, torch, ctx, count, seed, tol_kkt):
             "max_rel_kkt": rho, "max_constr_viol": max(i[0]["constr_viol"] for i in infos),
             "max_eta_blk": max(i[0]["eta_blk"] for i in infos),
             "krylov_its_per_solve": statistics.mean(i[0]["krylov_total"] for i in infos),
+            "refinement_steps": statistics.mean(i[0]["outer_steps"] for i in infos),
+            "setup_arithmetic": "complex64 (FP32 matrix cores)" if setup_bits == 32 else "FP64",
             "precision": "mixed"}, outs
 
 
-def run_serving(sfdp, torch, count, seed, tol_kkt, budget_gb):
+def run_serving(sfdp, torch, count, seed, tol_kkt, budget_gb, mean_gap_ms=5.0, warmup_s=0.0):
     """Served request stream (see workloads.c5_requests): requests are submitted at their
     arrival times to one server (mixed precision, memory budget budget_gb) and polled at the
-    end; latency is submit-to-result per request, throughput counts targets solved."""
+    end; latency is submit-to-result per request, throughput counts targets solved.  Requests
+    arriving in the first warmup_s seconds are served but left out of the latency figures."""
     import numpy as np
     from paper_1312_5653_amd import workloads
-    reqs = workloads.c5_requests(count, seed)
+    reqs = workloads.c5_requests(count, seed, mean_gap_ms)
+    cache = {}  # targets per (dim, N, nrhs, seed mod 8): long streams reuse them
     inputs = []
     for r in reqs:
         kind = "sixteen2d" if r["dim"] == 2 else "eight3d"
-        ys = [workloads.sine_target(r["dim"], r["N"], *workloads.modes_for(kind, r["seed"] * 8 + k))[0]
-              for k in range(r["nrhs"])]
-        inputs.append(torch.tensor(np.stack(ys), device="cuda:0"))
+        key = (r["dim"], r["N"], r["nrhs"], r["seed"] % 8)
+        if key not in cache:
+            ys = [workloads.sine_target(r["dim"], r["N"], *workloads.modes_for(kind, (r["seed"] % 8) * 8 + k))[0]
+                  for k in range(r["nrhs"])]
+            cache[key] = torch.tensor(np.stack(ys), device="cuda:0")
+        inputs.append(cache[key])
     torch.cuda.synchronize()
     ctx = sfdp.Context(0, mem_budget=int(budget_gb * (1 << 30)))
     srv = sfdp.Server(ctx, sfdp.SFDP_MIXED, tol_kkt=tol_kkt)
@@ -361,10 +371,11 @@ def run_serving(sfdp, torch, count, seed, tol_kkt, budget_gb):
     for r, tk in zip(reqs, tickets):
         try:
             _, _, _, info, l, st = srv.poll(tk)
-            lat.append(l)
             rho.extend(i["rel_kkt"] for i in info)
-            kind = f"{r['dim']}d_{'full' if r['full_space'] else 'range'}"
-            by_kind.setdefault(kind, []).append(l)
+            if r["arrival_ms"] >= warmup_s * 1e3:
+                lat.append(l)
+                kind = f"{r['dim']}d_{'full' if r['full_space'] else 'range'}"
+                by_kind.setdefault(kind, []).append(l)
         except sfdp.SfdpError as e:
             fails += 1
             errors[str(e)] = errors.get(str(e), 0) + 1
@@ -377,53 +388,79 @@ def run_serving(sfdp, torch, count, seed, tol_kkt, budget_gb):
     lat.sort()
     q = lambda f: lat[min(len(lat) - 1, int(round(f * (len(lat) - 1))))]
     solved = sum(r["nrhs"] for r in reqs)
-    kinds = {k: {"requests": len(v), "p50_ms": sorted(v)[len(v) // 2]} for k, v in sorted(by_kind.items())}
-    return {"requests": count, "seed": seed, "targets": solved, "mean_gap_ms": 5.0,
+    kinds = {k: {"requests": len(v), "p50_ms": sorted(v)[len(v) // 2],
+                 "p99_ms": sorted(v)[min(len(v) - 1, int(round(0.99 * (len(v) - 1))))]}
+             for k, v in sorted(by_kind.items())}
+    return {"requests": count, "seed": seed, "targets": solved, "mean_gap_ms": mean_gap_ms,
+            "offered_rps": 1e3 / mean_gap_ms, "warmup_s": warmup_s, "measured_requests": len(lat),
             "meshes": "2D N in 128..1024 (m = 32) with probability 0.75, else 3D N in 32..64 (m = 8); "
                       "a quarter of the requests use the full-space method",
             "kinds": kinds,
             "wall_s": wall, "solves_per_s": solved / wall, "requests_per_s": count / wall,
             "p50_ms": q(0.5), "p99_ms": q(0.99), "max_rel_kkt": max(rho), "failed": fails, "errors": errors,
             "setups": stats["setups"], "evictions": stats["evictions"], "ticks": stats["ticks"],
+            "solo_in_flight_max": stats["solo_in_flight_max"],
             "budget_gb": budget_gb, "precision": "mixed"}
 
 
+def run_serving_loads(sfdp, torch, capacity_rps, fractions, window_s, warmup_s, seed, tol_kkt, budget_gb):
+    """The served stream below saturation: for each fraction f of the measured capacity
+    (requests/s of the saturated stream), Poisson arrivals at f * capacity for
+    warmup_s + window_s seconds; latency over the requests after the warm-up."""
+    out = []
+    for f in fractions:
+        rate = f * capacity_rps
+        count = max(1, int(round(rate * (warmup_s + window_s))))
+        r = run_serving(sfdp, torch, count, seed + 1, tol_kkt, budget_gb, mean_gap_ms=1e3 / rate,
+                        warmup_s=warmup_s)
+        r["load_fraction"] = f
+        out.append(r)
+        print(f"serving load {f:.2f} of {capacity_rps:.2f} req/s: {count} requests, p50 {r['p50_ms']:.0f} ms, "
+              f"p99 {r['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def run_precision(sfdp, torch, ctx, precision, N, m, beta, ybar_t, steps, warmup, tol_kkt, tol_inner,
-                  batch, max_krylov=0, factors=0, edges=None, dim=2, full_space=False, schur_block=0):
+                  batch, max_krylov=0, factors=0, edges=None, dim=2, full_space=False, schur_block=0,
+                  setup_bits=64):
     p = sfdp.Problem(ctx, dim, N, m, precision)
     try:
         return _run_precision(sfdp, torch, p, beta, ybar_t, steps, warmup, tol_kkt, tol_inner, batch,
-                              max_krylov, factors, edges, full_space, schur_block)
+                              max_krylov, factors, edges, full_space, schur_block, setup_bits)
     finally:
         p.close()
 
 
 def _run_precision(sfdp, torch, p, beta, ybar_t, steps, warmup, tol_kkt, tol_inner, batch, max_krylov,
-                   factors, edges, full_space, schur_block):
+                   factors, edges, full_space, schur_block, setup_bits=64):
     if edges is not None:
         p.set_coarse_space(edges)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    p.set_beta(beta)
-    torch.cuda.synchronize()
-    setup_ms = (time.perf_counter() - t0) * 1e3
+    sfdp.set_setup_arithmetic(setup_bits)
+    try:
+        t0 = time.perf_counter()
+        p.set_beta(beta)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+    finally:
+        sfdp.set_setup_arithmetic(64)
     y = torch.empty_like(ybar_t)
     u = torch.empty_like(ybar_t)
     lam = torch.empty_like(ybar_t)
     nb = ybar_t.shape[0]
     solve = p.solve_full_space if full_space else p.solve_range_space
     sb = {"schur_block": schur_block} if schur_block else {}  # S_p factors: built in the first warmup call
+    kw = dict(tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch, max_krylov=max_krylov, factors=factors, **sb)
     for _ in range(warmup):
-        solve(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch,
-              max_krylov=max_krylov, factors=factors, **sb)
+        solve(ybar_t, None, y, u, lam, **kw)
+    # HIP events around the hot kernels during the timed calls
     p.timing_enable(True)
-    lat, rhos, its, feti, minres, cvs, etas = [], [], [], [], [], [], []
+    lat, rhos, its, feti, minres, cvs, etas, steps_seen = [], [], [], [], [], [], [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for _ in range(steps):
         t0 = time.perf_counter()
-        _, _, _, info, st = solve(ybar_t, None, y, u, lam, tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch,
-                                  max_krylov=max_krylov, factors=factors, **sb)
+        _, _, _, info, st = solve(ybar_t, None, y, u, lam, **kw)
         lat.append(time.perf_counter() - t0)
         rhos.extend(i["rel_kkt"] for i in info)
         its.extend(i["krylov_total"] for i in info)
@@ -431,19 +468,37 @@ def _run_precision(sfdp, torch, p, beta, ybar_t, steps, warmup, tol_kkt, tol_inn
         minres.extend(i["minres_its"] for i in info)
         cvs.extend(i["constr_viol"] for i in info)
         etas.extend(i["eta_blk"] for i in info)
+        steps_seen.extend(i["outer_steps"] for i in info)
         if st != 0:
             raise RuntimeError(f"solve did not converge: {info}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_all
     kt = p.kernel_times()
-    sizes = p.refresh_sizes()
     p.timing_enable(False)
+    # the same calls with their refinement steps replayed as captured HIP graphs
+    # (the first call runs eagerly, the second captures), for the comparison
+    ksteps = max(3, min(steps, 10))
+    sfdp.set_graphs(True)
+    try:
+        for _ in range(2):
+            solve(ybar_t, None, y, u, lam, **kw)
+        torch.cuda.synchronize()
+        t_e = time.perf_counter()
+        for _ in range(ksteps):
+            solve(ybar_t, None, y, u, lam, **kw)
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t_e) * 1e3 / ksteps
+    finally:
+        sfdp.set_graphs(False)
+    sizes = p.refresh_sizes()
     outs = [(y[r].cpu().numpy(), u[r].cpu().numpy(), lam[r].cpu().numpy()) for r in range(nb)]
     lat_ms = sorted(x * 1e3 for x in lat)
     q = lambda f: lat_ms[min(len(lat_ms) - 1, int(round(f * (len(lat_ms) - 1))))]
     return {"solves_per_s": nb * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps, "batch": nb,
+            "graph_ms_per_step": graph_ms,
             "p50_ms": q(0.5), "p99_ms": q(0.99), "setup_ms": setup_ms,
             "max_rel_kkt": max(rhos), "max_constr_viol": max(cvs), "max_eta_blk": max(etas),
+            "refinement_steps": statistics.mean(i for i in steps_seen) if steps_seen else None,
             "krylov_per_solve": statistics.mean(its),
             "feti_per_solve": statistics.mean(feti), "minres_per_solve": statistics.mean(minres),
             "kernel_times": kt, "sizes": sizes, "outs": outs, "beta": beta}
@@ -544,6 +599,10 @@ def main():
     ap.add_argument("--requests", type=int, default=100,
                     help="served request stream length (0 skips it)")
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
+    ap.add_argument("--serve-loads", type=str, default="0.5",
+                    help="fractions of the measured serving capacity offered as Poisson streams ('' for none)")
+    ap.add_argument("--serve-window", type=float, default=20.0,
+                    help="seconds of arrivals per load point after a 5 s warm-up")
     ap.add_argument("--max-krylov", type=int, default=0,
                     help="GMRES iteration cap per FETI-DP solve (0: library default)")
     ap.add_argument("--c3", type=int, default=64, metavar="N",
@@ -551,6 +610,10 @@ def main():
     ap.add_argument("--c3-only", action="store_true", help="only the 3D configuration (for profiles)")
     ap.add_argument("--instances-only", action="store_true",
                     help="only the batched instances (set-up and solve; for profiles)")
+    ap.add_argument("--side-stream", action="store_true",
+                    help="run the library on a torch stream of its own instead of the default stream")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the served stream and its load points")
     ap.add_argument("--c3-steps", type=int, default=5)
     ap.add_argument("--schur-betas", type=str, default="1e-2,1e-4,1e-6,1e-8,1e-10",
                     help="betas of the S versus S_p full-space comparison ('' to skip)")
@@ -583,11 +646,24 @@ def main():
         torch.mul(src_buf, 1.0, out=dst_buf)  # reads and writes MIB MiB once
         torch.cuda.synchronize()
         del src_buf, dst_buf
+    if args.side_stream:
+        side = torch.cuda.Stream()
+        torch.cuda.set_stream(side)
     ctx = sfdp.Context(0)
     tol_kkt = 1e-8
     if args.c3_only:
         print(json.dumps({"c3_3d": run_c3(sfdp, torch, ctx, args.c3, beta, args.c3_steps, tol_kkt)}), flush=True)
         ctx.close()
+        return
+    if args.serving_only:
+        ctx.close()
+        r = {"serving": run_serving(sfdp, torch, args.requests, 0, tol_kkt, args.serve_budget_gb)}
+        print(json.dumps(r), file=sys.stderr, flush=True)
+        if args.serve_loads:
+            fr = [float(x) for x in args.serve_loads.split(",")]
+            r["serving_loads"] = run_serving_loads(sfdp, torch, r["serving"]["requests_per_s"], fr,
+                                                   args.serve_window, 5.0, 0, tol_kkt, args.serve_budget_gb)
+        print(json.dumps(r), flush=True)
         return
     if args.instances_only:
         r, _ = run_instances(sfdp, torch, ctx, args.instances, 0, tol_kkt)
@@ -614,6 +690,11 @@ def main():
             if ob != beta:
                 res[f"{head}_beta{ob:g}"] = run_precision(sfdp, torch, ctx, hp, N, m, ob, ybar_t, args.steps,
                                                          args.warmup, tol_kkt, htin, B, args.max_krylov)
+        # the complex64 set-up (line factorization and line solves on the FP32
+        # matrix cores) against the FP64 one: refinement steps and solves/s
+        if hp == sfdp.SFDP_MIXED:
+            res[head + "_setup32"] = run_precision(sfdp, torch, ctx, hp, N, m, beta, ybar_t, args.steps,
+                                                   args.warmup, tol_kkt, htin, B, args.max_krylov, setup_bits=32)
         # the one-solve range-space form (same result, half the FETI-DP solves):
         # measured beside the two-factor form, never in its place
         res[head + "_single_solve"] = run_precision(sfdp, torch, ctx, hp, N, m, beta, ybar_t, args.steps,
@@ -671,8 +752,11 @@ def main():
         "p50_ms": res.get(head + "_b1", r)["p50_ms"],
         "p99_ms": res.get(head + "_b1", r)["p99_ms"],
         "step_p50_ms": r["p50_ms"],
+        # the same calls with their refinement steps replayed as captured HIP graphs
+        "graph_ms_per_step": r["graph_ms_per_step"],
         "step_p99_ms": r["p99_ms"],
         "setup_ms": r["setup_ms"],
+        "refinement_steps": r["refinement_steps"],
         "max_rel_kkt": r["max_rel_kkt"],
         "max_constr_viol": r["max_constr_viol"],
         "max_eta_blk": r["max_eta_blk"],
@@ -696,11 +780,12 @@ def main():
     for k in other:
         o = res[k]
         out[k] = {"batch": o["batch"], "beta": o["beta"], "solves_per_s": o["solves_per_s"],
-                  "ms_per_step": o["ms_per_step"], "factors": 1 if k.endswith("_single_solve") else 2,
+                  "ms_per_step": o["ms_per_step"], "graph_ms_per_step": o["graph_ms_per_step"], "factors": 1 if k.endswith("_single_solve") else 2,
                   "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"], "max_rel_kkt": o["max_rel_kkt"],
                   "max_constr_viol": o["max_constr_viol"], "max_eta_blk": o["max_eta_blk"],
                   "fwd_err_vs_oracle": None,
                   "krylov_its_per_solve": o["krylov_per_solve"], "feti_solves_per_solve": o["feti_per_solve"],
+                  "refinement_steps": o["refinement_steps"],
                   "setup_ms": o["setup_ms"]}
         if k.endswith("_full_space"):
             out[k]["method"] = "full-space MINRES, P_mgw with S^-1 by the complex factorization"
@@ -712,8 +797,14 @@ def main():
     inst_outs = None
     if args.instances > 0 and not args.headline_only:
         out["instances_batch"], inst_outs = run_instances(sfdp, torch, ctx, args.instances, 0, tol_kkt)
+        out["instances_batch_setup32"], _ = run_instances(sfdp, torch, ctx, args.instances, 0, tol_kkt,
+                                                          setup_bits=32)
     if args.requests > 0 and not args.headline_only:
         out["serving"] = run_serving(sfdp, torch, args.requests, 0, tol_kkt, args.serve_budget_gb)
+        if args.serve_loads:
+            fr = [float(x) for x in args.serve_loads.split(",")]
+            out["serving_loads"] = run_serving_loads(sfdp, torch, out["serving"]["requests_per_s"], fr,
+                                                     args.serve_window, 5.0, 0, tol_kkt, args.serve_budget_gb)
     if args.c3 > 0 and not args.headline_only:
         out["c3_3d"] = run_c3(sfdp, torch, ctx, args.c3, beta, args.c3_steps, tol_kkt, oracle)
     if args.schur_betas and not args.headline_only:

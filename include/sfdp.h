@@ -171,6 +171,34 @@ typedef struct {
  * relative).  SFDP_E_INVALID outside 0..4. */
 sfdp_status sfdp_set_tuning(int enable);
 
+/* Graph replay of refinement steps (enable = 1; default 0): a single 2D
+ * problem's range-space refinement step (right-hand sides of both factors,
+ * the FETI-DP solves with their persistent GMRES launches, the update and the
+ * next KKT residual) is captured into a HIP graph the second time the same
+ * step occurs (same active targets, caller arrays, inner tolerance and Krylov
+ * limit) and replayed from then on; the host keeps the convergence test
+ * between steps.  Captured steps are dropped when the problem's buffers, beta
+ * or coarse space change.  Steps with kernel timing enabled run eagerly.
+ * enable = 0 runs every step eagerly.  Results are bitwise the same either
+ * way.  Off by default: a step's launches are queued ahead of the GPU anyway,
+ * and the host's convergence test between steps stays, so replay does not
+ * shorten a solve (measured at 512^2 on MI355X: 3.47 ms per call replayed on a
+ * stream of the caller's, 3.57 ms on the null stream, which replays through a
+ * capture stream of its own, against 3.43-3.45 ms eagerly).
+ * SFDP_E_INVALID for other values. */
+sfdp_status sfdp_set_graphs(int enable);
+
+/* Arithmetic of the subdomain line factorization and line solves of the
+ * set-up (Sec. 4 factors, the local solves of Sec. 5) for problems with
+ * complex64 storage (SFDP_MIXED), from the next sfdp_set_beta (or batch
+ * set-up) on: bits = 64 (the default) computes them in FP64 on the FP64 matrix
+ * cores and rounds the stored factors to complex64 once; bits = 32 computes
+ * them in complex64 on the FP32 matrix cores (v_mfma_f32_16x16x4f32, FP32
+ * accumulation).  The interface Schur complements' inverses, the coarse
+ * problem and every solve stay FP64.  Other precisions always use 64.
+ * SFDP_E_INVALID for other values. */
+sfdp_status sfdp_set_setup_arithmetic(int bits);
+
 /* Sizes of a problem. */
 typedef struct {
   int64_t n_free;        /* unconstrained dofs (n_elem-1)^dim */
@@ -414,6 +442,7 @@ typedef struct {
   int64_t resident;    /* instances resident now */
   int64_t device_bytes;/* device memory held by the context */
   double mean_ms, p50_ms, p99_ms;  /* latency (submit to result) of completed requests */
+  int64_t solo_in_flight_max;  /* most 3D / full-space requests advancing together so far */
 } sfdp_server_info;
 /* opts as for sfdp_solve_range_space (batch is not used: slots hold up to 4). */
 sfdp_status sfdp_server_create(sfdp_ctx* ctx, sfdp_precision prec, const sfdp_opts* opts,

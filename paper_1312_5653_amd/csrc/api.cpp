@@ -54,7 +54,19 @@ namespace {
 
 constexpr int KMAX_LIMIT = 400;
 
+// Captured refinement steps of a problem refer to its buffers, beta and coarse
+// space by value: drop them whenever one of those changes.
+void graphs_clear(Problem& p) {
+  for (StepGraph& g : p.graphs)
+    if (g.exec) hipGraphExecDestroy(g.exec);
+  p.graphs.clear();
+  p.graph_seen.clear();
+}
+std::atomic<bool> g_graphs{false};  // sfdp_set_graphs
+std::atomic<int> g_setup_bits{64};  // sfdp_set_setup_arithmetic
+
 sfdp_status dalloc(Problem& p, void** ptr, size_t bytes) {
+  graphs_clear(p);
   Ctx* c = p.ctx;
   if (c->budget && c->used + bytes > c->budget)
     return fail(SFDP_E_NOMEM, "memory budget exceeded");
@@ -74,6 +86,7 @@ sfdp_status dupload(Problem& p, T** dst, const std::vector<T>& src) {
 }
 
 void dfree(Problem& p, void*& ptr, size_t bytes) {
+  graphs_clear(p);
   if (ptr) {
     hipFree(ptr);
     p.ctx->used -= std::min(p.ctx->used, bytes);
@@ -854,6 +867,82 @@ constexpr unsigned IDENTITY_MAP = 0x03020100u;
 // All unfinished targets take each two-factor step together; each stops on
 // its own test.  info[i] has ps[i]->nr entries.  M is the batch (null for a
 // single problem); dg / hg hold one Gathered record per problem.
+// The context's capture stream (non-blocking, default priority) and the two
+// events that order it after and before the library's stream: the library's
+// stream may be the null stream, which cannot be captured.
+sfdp_status capture_stream(Ctx* c) {
+  if (c->cap_stream) return SFDP_OK;
+  HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&c->cap_ev[0], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c->cap_ev[1], hipEventDisableTiming));
+  return SFDP_OK;
+}
+
+// Run one refinement step of a single problem through a captured graph: the
+// first occurrence of a step's key runs eagerly (and tunes its launches), the
+// second captures it on the capture stream and instantiates it, every later one
+// replays it.  A replay runs on the capture stream between two event waits, so
+// it stays in order with the library's stream.  A failed capture switches the
+// problem to eager steps.
+sfdp_status step_graph(Problem& p, const Target& t, double tin, int kmax, bool single,
+                       const std::function<sfdp_status(const Target&)>& body) {
+  StepKey key;
+  key.nr = p.nr;
+  key.map = p.map;
+  key.kmax = kmax;
+  key.single = single ? 1 : 0;
+  key.tin = tin;
+  key.tune_gen = tune_generation();
+  for (int c = 0; c < NRMAX; ++c) {
+    const Slot& q = p.sl[c];
+    const void* v[5] = {q.ybar, q.yc, q.y, q.u, q.lam};
+    for (int k = 0; k < 5; ++k) key.ptr[5 * c + k] = v[k];
+  }
+  Ctx* c = p.ctx;
+  // a library stream other than the null stream is captured and replayed on directly
+  const bool direct = t.st != nullptr;
+  auto replay = [&](hipGraphExec_t exec) -> sfdp_status {
+    if (direct) {
+      HIPCHK(hipGraphLaunch(exec, t.st));
+      return SFDP_OK;
+    }
+    HIPCHK(hipEventRecord(c->cap_ev[0], t.st));
+    HIPCHK(hipStreamWaitEvent(c->cap_stream, c->cap_ev[0], 0));
+    HIPCHK(hipGraphLaunch(exec, c->cap_stream));
+    HIPCHK(hipEventRecord(c->cap_ev[1], c->cap_stream));
+    HIPCHK(hipStreamWaitEvent(t.st, c->cap_ev[1], 0));
+    return SFDP_OK;
+  };
+  for (StepGraph& g : p.graphs)
+    if (g.key == key) return replay(g.exec);
+  bool seen = false;
+  for (const StepKey& k : p.graph_seen) seen = seen || k == key;
+  if (p.graph_off || !seen || p.graphs.size() >= 16) {
+    if (!seen && p.graph_seen.size() < 64) p.graph_seen.push_back(key);
+    return body(t);
+  }
+  sfdp_status s = direct ? SFDP_OK : capture_stream(c);
+  if (s) return s;
+  Target tc = t;
+  if (!direct) tc.st = c->cap_stream;
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(tc.st, hipStreamCaptureModeThreadLocal));
+  s = body(tc);
+  hipError_t e = hipStreamEndCapture(tc.st, &graph);
+  hipGraphExec_t exec = nullptr;
+  if (s == SFDP_OK && e == hipSuccess && graph) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) hipGraphDestroy(graph);
+  (void)hipGetLastError();
+  if (s != SFDP_OK || e != hipSuccess || !exec) {
+    // nothing of the capture ran: fall back to eager steps for this problem
+    if (exec) hipGraphExecDestroy(exec);
+    p.graph_off = true;
+    return body(t);
+  }
+  p.graphs.push_back(StepGraph{key, exec});
+  return replay(exec);
+}
+
 sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Multi* M, Gathered* dg,
                             Gathered* hg, double tol_kkt, double tol_first, double tol_inner, int max_outer,
                             int kmax, const std::vector<sfdp_info*>& info, bool single) {
@@ -877,10 +966,35 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
   HIPCHK(launch_group_init(t));
   HIPCHK(launch_fill_flags(t, 0, FLAG_WORDS));
   for (Problem* p : ps) p->init = 0;
+  // the KKT residual of the current iterate, gathered to the host (the end of
+  // every refinement step, and the start)
+  auto residual = [&](const Target& tt) -> hipError_t {
+    hipError_t e = launch_kkt_residual(tt);
+    if (e == hipSuccess) e = launch_gather(tt, dg);
+    if (e == hipSuccess) e = hipMemcpyAsync(hg, dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, tt.st);
+    return e;
+  };
+  // one refinement step of the group's active targets, then the new residual
+  // (on the stream of tt: the library's, or the capture stream)
+  auto step_body = [&](const Target& tt, double tin) -> sfdp_status {
+    HIPCHK(launch_make_rhs1(tt));
+    sfdp_status s = feti_run(tt, timed, V_CVEC, 0, V_CVEC2, tin, kmax);
+    if (s) return s;
+    if (!single) {
+      HIPCHK(launch_make_rhs2(tt));
+      s = feti_run(tt, timed, V_CVEC3, 0, V_CVEC, tin, kmax);
+      if (s) return s;
+    }
+    HIPCHK(launch_update(tt, single ? 1 : 0));
+    HIPCHK(residual(tt));
+    return SFDP_OK;
+  };
+  // a single 2D problem replays its steps as captured graphs (no timing events:
+  // event records are not captured)
+  const bool graphable = t.single() && t.one->dim == 2 && !M && !t.one->timing && g_graphs.load();
+  HIPCHK(residual(t));
   for (int step = 0;; ++step) {
-    HIPCHK(launch_kkt_residual(t));
-    HIPCHK(launch_gather(t, dg));
-    HIPCHK(hipMemcpyAsync(hg, dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, st));
+    if (t.single()) t.one->yield_point();
     HIPCHK(hipStreamSynchronize(st));
     bool any = false;
     for (size_t i = 0; i < n; ++i) {
@@ -910,15 +1024,10 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
       sfdp_status s = multi_upload(*M);
       if (s) return s;
     }
-    HIPCHK(launch_make_rhs1(t));
-    sfdp_status s = feti_run(t, timed, V_CVEC, 0, V_CVEC2, tin, kmax);
+    sfdp_status s = graphable ? step_graph(*t.one, t, tin, kmax, single,
+                                           [&](const Target& tt) { return step_body(tt, tin); })
+                              : step_body(t, tin);
     if (s) return s;
-    if (!single) {
-      HIPCHK(launch_make_rhs2(t));
-      s = feti_run(t, timed, V_CVEC3, 0, V_CVEC, tin, kmax);
-      if (s) return s;
-    }
-    HIPCHK(launch_update(t, single ? 1 : 0));
     for (size_t i = 0; i < n; ++i)
       for (int c = 0; c < ps[i]->nr; ++c) loc[i][(ps[i]->map >> (8 * c)) & 255].outer_steps = step + 1;
   }
@@ -1090,6 +1199,7 @@ void destroy_problem(Problem* p) {
   if (p->fsw) hipFree(p->fsw);
   if (p->fsh) hipHostFree(p->fsh);
   for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
+  graphs_clear(*p);
   p->ctx->used -= std::min(p->ctx->used, p->bytes);
   p->ctx->children--;
   delete p;
@@ -1098,6 +1208,7 @@ void destroy_problem(Problem* p) {
 // Factor one or several problems for their betas (one set-up sequence; the
 // stream must be idle).
 sfdp_status setup_run(const Target& t, const std::vector<Problem*>& ps, Multi* M) {
+  for (Problem* p : ps) graphs_clear(*p);
   if (ps.size() == 1 && ps[0]->dim == 3) return setup3(*ps[0]);
   for (Problem* p : ps) {
     sfdp_status s = alloc_factors(*p);
@@ -1110,7 +1221,9 @@ sfdp_status setup_run(const Target& t, const std::vector<Problem*>& ps, Multi* M
     sfdp_status s = multi_upload(*M);
     if (s) return s;
   }
-  hipError_t e = launch_setup(t);
+  Target ts = t;
+  ts.setup32 = g_setup_bits.load() == 32 && t.prec == SFDP_MIXED;
+  hipError_t e = launch_setup(ts);
   if (e == hipSuccess) e = hipStreamSynchronize(t.st);
   for (Problem* p : ps) free_setup(*p);
   if (e != hipSuccess) return fail(SFDP_E_DEVICE, std::string("setup: ") + hipGetErrorString(e));
@@ -1330,10 +1443,14 @@ sfdp_status sfdp_ctx_destroy(sfdp_ctx* c) {
   if (c->children.load() > 0)
     return fail(SFDP_E_STATE, std::to_string(c->children.load()) +
                                   " problems, batches or servers of this context are still alive");
-  if (c->pool) {
-    hipSetDevice(c->device);
-    hipStreamSynchronize(c->stream);
-    hipFree(c->pool);
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  if (c->pool) hipFree(c->pool);
+  if (c->cap_stream) {
+    hipStreamSynchronize(c->cap_stream);
+    hipStreamDestroy(c->cap_stream);
+    hipEventDestroy(c->cap_ev[0]);
+    hipEventDestroy(c->cap_ev[1]);
   }
   delete c;
   return SFDP_OK;
@@ -1359,6 +1476,18 @@ static void sizes_of(const Problem* p, sfdp_sizes* out) {
   out->resident_bytes = (int64_t)p->bytes;
 }
 
+sfdp_status sfdp_set_setup_arithmetic(int bits) {
+  if (bits != 32 && bits != 64) return fail(SFDP_E_INVALID, "bits must be 32 or 64");
+  g_setup_bits = bits;
+  return SFDP_OK;
+}
+
+sfdp_status sfdp_set_graphs(int enable) {
+  if (enable != 0 && enable != 1) return fail(SFDP_E_INVALID, "enable must be 0 or 1");
+  g_graphs = enable == 1;
+  return SFDP_OK;
+}
+
 sfdp_status sfdp_set_tuning(int enable) {
   if (enable < 0 || enable > 4) return fail(SFDP_E_INVALID, "enable must be in 0..4");
   tune_set_mode(enable == 1, enable >= 2 ? enable - 2 : -1);
@@ -1371,6 +1500,7 @@ sfdp_status sfdp_set_coarse_space(sfdp_problem* p, int edge_averages) {
   if (p->dim == 3 && edge_averages) return fail(SFDP_E_INVALID, "3D problems use the corner coarse space");
   const int nk = edge_averages ? p->nC + p->nE : p->nC;
   if (nk != p->nK) {
+    graphs_clear(*p);
     p->nK = nk;
     p->factored = false;  // the coarse matrix changes: sfdp_set_beta again
   }
@@ -1638,6 +1768,7 @@ sfdp_status fs_minres(FsCtx& c, double* V, const double* rr, double* dx, int& it
   double bet = beta1, oldb = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta1, cs = -1.0, sn = 0.0;
   for (int k = 1; k <= c.maxit; ++k) {
     its = k;
+    c.p->yield_point();
     HIPCHK(launch_lin3(n3, 1.0 / bet, y, 0.0, nullptr, 0.0, nullptr, v, st));
     HIPCHK(launch_kkt_apply(*c.p, v, y, st));
     if (k >= 2) HIPCHK(launch_lin3(n3, 1.0, y, -bet / oldb, r1, 0.0, nullptr, y, st));
@@ -1784,6 +1915,7 @@ sfdp_status sfdp_solve_full_space(sfdp_problem* p, int nrhs, const double* ybar,
     p->init = 0;
     bool bad = false;
     for (int step = 0;; ++step) {
+      p->yield_point();
       p->nr = 1;
       p->map = IDENTITY_MAP;
       HIPCHK(launch_kkt_residual(t));
@@ -2072,8 +2204,24 @@ struct SSolo {
   int dim = 2, n_elem = 0, sub_elem = 0;
   double beta = 0;
   double last_used = 0;
+  bool busy = false;  // a running job solves on it
 };
-constexpr size_t SOLO_KEEP = 2;  // solo problems kept resident at most
+constexpr size_t SOLO_KEEP = 4;  // idle solo problems kept resident at most
+constexpr size_t SOLO_JOBS = 4;  // solo requests in flight at once
+
+// A solo request in flight on a host thread of its own.  It runs only while it
+// holds the turn, which the worker hands to every job once per tick and takes
+// back at the job's next yield point (the start of a refinement step or of a
+// MINRES iteration), so the requests advance step by step, interleaved with the
+// batched ticks and with each other, on the server's stream.
+struct SJob {
+  sfdp_server* S = nullptr;
+  SReq* r = nullptr;
+  std::thread th;
+  bool turn = false;
+  bool done = false;
+  sfdp_status dev = SFDP_OK;  // a device error ends the service
+};
 
 }  // namespace
 
@@ -2104,8 +2252,12 @@ struct sfdp_server {
   std::vector<SReq*> finished;  // decided by the worker, published under the lock
   size_t pool_cap = 0;          // set-up scratch of one set-up pass (a larger instance passes alone)
   int user_kmax = 0;            // opts->max_krylov as given (0: each path's default)
-  std::deque<SReq*> solo;       // admitted 3D and full-space requests (worker only)
-  std::vector<SSolo> solos;     // their resident problems
+  std::deque<SReq*> solo;       // 3D and full-space requests waiting for a job (worker only)
+  std::vector<SSolo*> solos;    // their resident problems
+  std::vector<SJob*> jobs;      // solo requests in flight
+  int64_t n_jobs_max = 0;       // most jobs in flight at once
+  std::mutex tmu;               // turn hand-off between the worker and the jobs
+  std::condition_variable tcv;
 };
 
 namespace {
@@ -2373,27 +2525,43 @@ sfdp_status server_tick(sfdp_server* S) {
   return SFDP_OK;
 }
 
-// One request of the solo lane, solved whole on its (mesh, beta) problem: a 3D
-// instance cannot share the batched 2D launches, and a full-space request
-// runs MINRES with the factored Schur complement.  On a memory shortage the
-// idle batched instances and the other solo problems are dropped and the
-// set-up is tried once more.  Returns only device errors; everything else
-// finishes the request.
-sfdp_status server_solo(sfdp_server* S, SReq* r) {
+// Yield point of a job: hand the turn back to the worker and wait for the next.
+void job_yield(void* arg) {
+  SJob* j = (SJob*)arg;
+  sfdp_server* S = j->S;
+  std::unique_lock<std::mutex> lk(S->tmu);
+  j->turn = false;
+  S->tcv.notify_all();
+  S->tcv.wait(lk, [&] { return j->turn; });
+}
+
+// One request of the solo lane on its (mesh, beta) problem: a 3D instance
+// cannot share the batched 2D launches, and a full-space request runs MINRES
+// with the factored Schur complement.  Runs on the job's thread while it holds
+// the turn (the set-up in its first turn, then one refinement step or MINRES
+// iteration per turn).  On a memory shortage the idle batched instances and
+// the idle solo problems are dropped and the set-up is tried once more.
+// Returns only device errors; everything else finishes the request.
+sfdp_status server_solo(sfdp_server* S, SReq* r, SJob* job) {
   SSolo* home = nullptr;
-  for (SSolo& so : S->solos)
-    if (so.dim == r->dim && so.n_elem == r->n_elem && so.sub_elem == r->sub_elem && so.beta == r->beta) home = &so;
+  for (SSolo* so : S->solos)
+    if (!so->busy && so->dim == r->dim && so->n_elem == r->n_elem && so->sub_elem == r->sub_elem &&
+        so->beta == r->beta)
+      home = so;
+  auto drop_lru = [&]() {
+    int v = -1;
+    for (size_t i = 0; i < S->solos.size(); ++i)
+      if (!S->solos[i]->busy && (v < 0 || S->solos[i]->last_used < S->solos[v]->last_used)) v = (int)i;
+    if (v < 0) return false;
+    destroy_problem(S->solos[v]->p);
+    delete S->solos[v];
+    S->solos.erase(S->solos.begin() + v);
+    return true;
+  };
   if (!home) {
-    auto drop_lru = [&]() {
-      if (S->solos.empty()) return false;
-      size_t v = 0;
-      for (size_t i = 1; i < S->solos.size(); ++i)
-        if (S->solos[i].last_used < S->solos[v].last_used) v = i;
-      destroy_problem(S->solos[v].p);
-      S->solos.erase(S->solos.begin() + v);
-      return true;
-    };
-    while (S->solos.size() >= SOLO_KEEP) drop_lru();
+    size_t idle = 0;
+    for (SSolo* so : S->solos) idle += so->busy ? 0 : 1;
+    while (idle >= SOLO_KEEP && drop_lru()) --idle;
     Problem* p = nullptr;
     sfdp_status st = SFDP_OK;
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -2428,9 +2596,10 @@ sfdp_status server_solo(sfdp_server* S, SReq* r) {
       return SFDP_OK;
     }
     ++S->n_setups;
-    S->solos.push_back(SSolo{p, r->dim, r->n_elem, r->sub_elem, r->beta, 0.0});
-    home = &S->solos.back();
+    home = new SSolo{p, r->dim, r->n_elem, r->sub_elem, r->beta, 0.0, false};
+    S->solos.push_back(home);
   }
+  home->busy = true;
   home->last_used = now_ms();
   sfdp_opts o{};
   o.tol_kkt = S->tol_kkt;
@@ -2439,14 +2608,90 @@ sfdp_status server_solo(sfdp_server* S, SReq* r) {
   o.max_krylov = S->user_kmax;
   o.factors = S->single ? 1 : 2;
   sfdp_problem* sp = (sfdp_problem*)home->p;
+  sp->yield_fn = job_yield;
+  sp->yield_arg = job;
   sfdp_status st = r->mode == 1
                        ? sfdp_solve_full_space(sp, r->nrhs, r->ybar, r->yc, r->y, r->u, r->lam, &o, r->info.data())
                        : sfdp_solve_range_space(sp, r->nrhs, r->ybar, r->yc, r->y, r->u, r->lam, &o, r->info.data());
+  sp->yield_fn = nullptr;
+  sp->yield_arg = nullptr;
+  home->busy = false;
+  home->last_used = now_ms();
   if (st == SFDP_E_DEVICE) return st;
   r->done = r->nrhs;
   if (st) r->why = g_err;
   server_finish(S, r, st);
   return SFDP_OK;
+}
+
+void job_main(SJob* j) {
+  sfdp_server* S = j->S;
+  hipSetDevice(S->ctx->device);
+  {
+    std::unique_lock<std::mutex> lk(S->tmu);
+    S->tcv.wait(lk, [&] { return j->turn; });
+  }
+  const sfdp_status st = server_solo(S, j->r, j);
+  std::lock_guard<std::mutex> lk(S->tmu);
+  j->dev = st;
+  j->done = true;
+  j->turn = false;
+  S->tcv.notify_all();
+}
+
+// Give every job one turn (in start order) and wait for it to yield or end;
+// reap the jobs that ended.  Returns the first device error a job met.
+sfdp_status server_turns(sfdp_server* S) {
+  sfdp_status dev = SFDP_OK;
+  for (SJob* j : S->jobs) {
+    std::unique_lock<std::mutex> lk(S->tmu);
+    if (j->done) continue;
+    j->turn = true;
+    S->tcv.notify_all();
+    S->tcv.wait(lk, [&] { return !j->turn; });
+    if (j->dev && !dev) dev = j->dev;
+  }
+  for (size_t i = 0; i < S->jobs.size();) {
+    SJob* j = S->jobs[i];
+    bool done;
+    {
+      std::lock_guard<std::mutex> lk(S->tmu);
+      done = j->done;
+    }
+    if (!done) {
+      ++i;
+      continue;
+    }
+    j->th.join();
+    delete j;
+    S->jobs.erase(S->jobs.begin() + i);
+  }
+  return dev;
+}
+
+// Start jobs for waiting solo requests while fewer than SOLO_JOBS run, in
+// arrival order, one job per (dim, mesh, beta) at a time (a problem serves one
+// job at once).
+void server_start_jobs(sfdp_server* S) {
+  for (auto it = S->solo.begin(); it != S->solo.end() && S->jobs.size() < SOLO_JOBS;) {
+    SReq* r = *it;
+    bool clash = false;
+    for (SJob* j : S->jobs)
+      clash = clash || (j->r->dim == r->dim && j->r->n_elem == r->n_elem && j->r->sub_elem == r->sub_elem &&
+                        j->r->beta == r->beta);
+    if (clash) {
+      ++it;
+      continue;
+    }
+    SJob* j = new SJob();
+    j->S = S;
+    j->r = r;
+    j->th = std::thread(job_main, j);
+    S->jobs.push_back(j);
+    it = S->solo.erase(it);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->n_jobs_max = std::max(S->n_jobs_max, (int64_t)S->jobs.size());
+  }
 }
 
 void server_loop(sfdp_server* S) {
@@ -2457,7 +2702,7 @@ void server_loop(sfdp_server* S) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       for (;;) {
-        work = !S->solo.empty();
+        work = !S->solo.empty() || !S->jobs.empty();
         for (SInst* in : S->insts) work = work || in->busy();
         if (work || !S->pending.empty() || S->stop) break;
         S->cv_work.wait(lk);
@@ -2527,11 +2772,12 @@ void server_loop(sfdp_server* S) {
       }
     }
     if (!st) st = server_tick(S);
-    // then one request of the solo lane, so batched targets keep moving between them
-    if (!st && !S->solo.empty()) {
-      SReq* r = S->solo.front();
-      S->solo.pop_front();
-      st = server_solo(S, r);
+    // then one turn for every solo request in flight (a refinement step or a
+    // MINRES iteration each), so the batched targets and the solo requests
+    // advance together
+    if (!st) {
+      server_start_jobs(S);
+      st = server_turns(S);
     }
     std::lock_guard<std::mutex> lk(S->mu);
     // requests that could not be admitted yet go back to the front of the queue
@@ -2548,6 +2794,8 @@ void server_loop(sfdp_server* S) {
       }
       S->pending.clear();
       S->solo.clear();
+      // the jobs in flight end on the failing device: let them run out
+      while (!S->jobs.empty()) server_turns(S);
     }
     for (SReq* r : S->finished) {
       r->complete = true;
@@ -2659,6 +2907,7 @@ sfdp_status sfdp_server_stats(sfdp_server* S, sfdp_server_info* out) {
   out->ticks = S->n_ticks;
   out->resident = (int64_t)S->insts.size();
   out->device_bytes = (int64_t)S->ctx->used;
+  out->solo_in_flight_max = S->n_jobs_max;
   if (!S->lat.empty()) {
     std::vector<double> v = S->lat;
     std::sort(v.begin(), v.end());
@@ -2686,7 +2935,10 @@ void sfdp_server_destroy(sfdp_server* S) {
     destroy_problem(in->p);
     delete in;
   }
-  for (SSolo& so : S->solos) destroy_problem(so.p);
+  for (SSolo* so : S->solos) {
+    destroy_problem(so->p);
+    delete so;
+  }
   for (auto& kv : S->reqs) delete kv.second;
   if (S->gmap) hipFree(S->gmap);
   if (S->dg) hipFree(S->dg);

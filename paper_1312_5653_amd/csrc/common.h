@@ -290,6 +290,27 @@ struct Many {
 // NQ x NQ entries per subdomain in 256-entry blocks.
 enum Kind : int { K_SUB = 0, K_NC128, K_NC, K_NMU256, K_ASM256, K_NF256, K_SUB16, K_ONE, K_GMRES, K_NKIND };
 
+// Key of a captured refinement step (graph replay of a single 2D problem):
+// everything a step's launches take by value that can change between calls.
+struct StepKey {
+  int nr = 0, kmax = 0, single = 0;
+  unsigned map = 0, tune_gen = 0;
+  double tin = 0;
+  const void* ptr[5 * NRMAX] = {};  // the caller arrays of the group's slots
+  bool operator==(const StepKey& o) const {
+    if (nr != o.nr || kmax != o.kmax || single != o.single || map != o.map || tune_gen != o.tune_gen ||
+        tin != o.tin)
+      return false;
+    for (int i = 0; i < 5 * NRMAX; ++i)
+      if (ptr[i] != o.ptr[i]) return false;
+    return true;
+  }
+};
+struct StepGraph {
+  StepKey key;
+  hipGraphExec_t exec = nullptr;
+};
+
 // Host-side problem.
 struct Ctx;
 struct Three;  // state of a 3D instance (three.h)
@@ -353,6 +374,20 @@ struct Problem {
      *scr = nullptr, *Zs = nullptr;
   Gathered* gd = nullptr;  // gather record (device) and its pinned host copy
   Gathered* gh = nullptr;
+  // cooperative time-slicing: when set, the long solve loops call it at the
+  // start of every refinement step and MINRES iteration (the server's solo
+  // requests hand the device back to its worker there)
+  void (*yield_fn)(void*) = nullptr;
+  void* yield_arg = nullptr;
+  void yield_point() const {
+    if (yield_fn) yield_fn(yield_arg);
+  }
+  // captured refinement steps (graph replay) and the steps run once eagerly
+  // (a step is captured the second time its key occurs); cleared whenever a
+  // buffer, beta or the coarse space changes
+  std::vector<StepGraph> graphs;
+  std::vector<StepKey> graph_seen;
+  bool graph_off = false;  // a capture failed: this problem runs eagerly
   // kernel timing (events recorded around hot kernel launches)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -426,6 +461,10 @@ struct Ctx {
   // demand, counted in `used`)
   void* pool = nullptr;
   size_t pool_bytes = 0;
+  // capture stream of graph-replayed steps and its ordering events (created on
+  // first use; the library's stream may be the null stream, which cannot be captured)
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t cap_ev[2] = {nullptr, nullptr};
   // line-solve slots of the set-up (MS_SLOTS_MAX at most, carved from the pool
   // by alloc_setup; valid during a set-up)
   cd* ms_scr = nullptr;
@@ -456,6 +495,7 @@ struct Target {
   };
   std::vector<GGroup> ggroups;
   sfdp_precision prec = SFDP_FP64;
+  bool setup32 = false;  // set-up line factorization and line solves in complex64 arithmetic
   bool single() const { return one != nullptr; }
   int blocks(int kind) const { return one ? one->blocks(kind) : total[kind]; }
   One src1() const { return One{one->dev()}; }
@@ -489,6 +529,8 @@ struct TuneEntry {
 // repeatedly) and timed on stream st; later calls return the kept choice.
 // fallback when tuning is off or timing fails.
 int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, const std::function<void(int)>& launch);
+// changes whenever the tuning mode or the table is reset (part of StepKey)
+unsigned tune_generation();
 // on: autotune; force >= 0: run candidate `force` wherever a family has it;
 // either call forgets every choice made so far
 void tune_set_mode(bool on, int force);

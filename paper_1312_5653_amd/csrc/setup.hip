@@ -1,16 +1,17 @@
 // Setup of the FETI-DP operators of Z = K + i alpha M (Sec. 4 factor, Sec. 5 solver).
 //
-// Per subdomain (one workgroup each):
-//   1. factor_lines: block LDL^T of the extended local matrix E^s taken line by
-//      line (E^s is block tridiagonal with tridiagonal couplings between
-//      consecutive grid lines):  T_0 = A_00,  T_j = A_jj - A_j,j-1 T_j-1^-1 A_j-1,j,
-//      storing G_j = T_j^-1.  No pivoting: every T_j is a Schur complement of
-//      K + i alpha M restricted to remainder nodes, complex symmetric with
-//      positive definite real and imaginary parts on those nodes (plus decoupled
-//      identity rows), for which Gauss-Jordan without pivoting is stable.
-//   2. multi_solve: E^s X = [e_Delta, Z_rc] by the same recursion with panels of
-//      right-hand sides; the Delta rows give Z_rr^-1|Delta,Delta and
-//      Phi = Z_rr^-1 Z_rc.
+// Per subdomain:
+//   1. factor_lines (one wavefront): block LDL^T of the extended local matrix
+//      E^s taken line by line (E^s is block tridiagonal with tridiagonal
+//      couplings between consecutive grid lines):
+//      T_0 = A_00,  T_j = A_jj - A_j,j-1 T_j-1^-1 A_j-1,j,  storing G_j = T_j^-1.
+//      No pivoting: every T_j is a Schur complement of K + i alpha M restricted
+//      to remainder nodes, complex symmetric with positive definite real and
+//      imaginary parts on those nodes (plus decoupled identity rows), for which
+//      Gauss-Jordan without pivoting is stable.
+//   2. multi_solve (four wavefronts, the line products on the matrix cores):
+//      E^s X = [e_Delta, Z_rc] by the same recursion; the Delta rows give
+//      Z_rr^-1|Delta,Delta and Phi = Z_rr^-1 Z_rc.
 //   3. invert_batched: interface Schur complement S_bb = (Z_rr^-1|Delta,Delta)^-1,
 //      used by the Dirichlet preconditioner (Sec. 5).
 //   4. zcc_and_coarse: Z_cc* = Z_cc - Z_cr Phi per subdomain and the assembled
@@ -18,103 +19,12 @@
 //   5. the coarse inverse by Gauss-Jordan without pivoting (FP64): in LDS for
 //      small coarse matrices, one workgroup each for mid-size ones when several
 //      are set up together, and otherwise by panels of 32 pivots over the whole
-//      device.
+//      device (the trailing update on the matrix cores).
 #include "common.h"
 
 namespace sfdp {
 
 constexpr int MLMAX = 33;  // ml = m + 1 <= 33
-constexpr int CW = 32;     // right-hand-side panel width of multi_solve
-constexpr int RG = 256 / CW;            // row groups of a 256-thread workgroup
-constexpr int MT = (MLMAX + RG - 1) / RG;  // rows per thread in the panel products
-
-// In-place Gauss-Jordan inverse of an n x n complex matrix in LDS (row-major).
-__device__ void gj_invert_lds(cd* T, int n, cd* rowk, cd* colk) {
-  for (int k = 0; k < n; ++k) {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      rowk[t] = T[k * n + t];
-      colk[t] = T[t * n + k];
-    }
-    __syncthreads();
-    cd piv = cdiv(cd{1.0, 0.0}, rowk[k]);
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-      int i = idx / n, j = idx % n;
-      cd v;
-      if (i == k && j == k) v = piv;
-      else if (i == k) v = rowk[j] * piv;
-      else if (j == k) v = -(colk[i] * piv);
-      else v = T[idx] - colk[i] * (rowk[j] * piv);
-      T[idx] = v;
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-  }
-}
-
-template <class Src>
-__global__ void __launch_bounds__(256) k_factor_lines(Src src) {
-  __shared__ cd T[MLMAX * MLMAX];
-  __shared__ cd Gp[MLMAX * MLMAX];
-  __shared__ cd rowk[MLMAX], colk[MLMAX];
-  // per-subdomain tables: r-node mask; the coupling of node p of a line to
-  // node p + d - 1 of the neighbouring line (the same for every pair of lines
-  // and, the 1D matrices being symmetric, in both directions); Z between nodes
-  // p and p + d - 1 of one line, for the two boundary lines [0] and the
-  // interior lines [1] (E is Z on r x r and the identity elsewhere)
-  __shared__ unsigned char rmk[MLMAX * MLMAX];
-  __shared__ cd cpl[MLMAX][3];
-  __shared__ cd dgl[2][MLMAX][3];
-  const Dev& d = src.dev();
-  const Geo2& g = d.g;
-  cd* G64 = d.G64;
-  const int s = src.bx(), ml = g.ml, n2 = ml * ml;
-  for (int l = threadIdx.x; l < n2; l += blockDim.x) rmk[l] = g.rnode(s, l % ml, l / ml) ? 1 : 0;
-  if (threadIdx.x < ml * 3) {
-    const int p = threadIdx.x / 3, e = threadIdx.x % 3, a = p + e - 1;
-    const bool ok = a >= 0 && a < ml;
-    cpl[p][e] = ok ? g.zloc(p, 1, a, 0) : cd{0.0, 0.0};
-    dgl[0][p][e] = ok ? g.zloc(p, 0, a, 0) : cd{0.0, 0.0};
-    dgl[1][p][e] = ok ? g.zloc(p, 1, a, 1) : cd{0.0, 0.0};
-  }
-  __syncthreads();
-  for (int j = 0; j < ml; ++j) {
-    const int lt = (j == 0 || j == ml - 1) ? 0 : 1;
-    for (int idx = threadIdx.x; idx < n2; idx += blockDim.x) {
-      const int p = idx / ml, q = idx % ml;
-      // E_jj - E_j,j-1 G_j-1 E_j-1,j (masked couplings skipped, same order)
-      const bool rp = rmk[p + ml * j], rq = rmk[q + ml * j];
-      cd v{0.0, 0.0};
-      if (rp && rq) {
-        if (q >= p - 1 && q <= p + 1) v = dgl[lt][p][q - p + 1];
-      } else if (p == q) {
-        v = cd{1.0, 0.0};
-      }
-      if (j > 0 && rp && rq) {
-        for (int e = 0; e < 3; ++e) {
-          const int a = p + e - 1;
-          if (a < 0 || a >= ml || !rmk[a + ml * (j - 1)]) continue;
-          cd acc{0.0, 0.0};
-          for (int f = 0; f < 3; ++f) {
-            const int b = q + f - 1;
-            if (b < 0 || b >= ml || !rmk[b + ml * (j - 1)]) continue;
-            fma_acc(acc, Gp[a * ml + b], cpl[b][q - b + 1]);
-          }
-          v = v - cpl[p][e] * acc;
-        }
-      }
-      T[idx] = v;
-    }
-    __syncthreads();
-    gj_invert_lds(T, ml, rowk, colk);
-    cd* out = G64 + ((size_t)s * ml + j) * n2;
-    for (int idx = threadIdx.x; idx < n2; idx += blockDim.x) {
-      int p = idx / ml, q = idx % ml;
-      Gp[idx] = T[idx];
-      out[q * ml + p] = T[idx];  // transposed: element (p, q) at [q][p]
-    }
-    __syncthreads();
-  }
-}
 
 // LDS visibility inside one wavefront: wait for this wave's LDS operations and
 // keep the compiler from moving memory accesses across (no workgroup barrier).
@@ -133,31 +43,33 @@ __device__ inline void wave_sync_lds() {
 // pivots (the padding rows and columns beyond ml are identity and pivot
 // trivially) the rotation is whole again.  Every register index is static and
 // the loop body stays small (three pivots).
-__device__ __forceinline__ void gj_wave_invert(cd (&T)[MLMAX], cd (*rowk)[MLMAX], int p) {
+template <class R>
+__device__ __forceinline__ void gj_wave_invert(C<R> (&T)[MLMAX], C<R> (*rowk)[MLMAX], int p) {
+  using CR = C<R>;
   static_assert(MLMAX % 3 == 0, "pivot groups of three");
   for (int k0 = 0; k0 < MLMAX; k0 += 3) {
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
       const int k = k0 + u;
-      cd* rk = rowk[k & 1];
+      CR* rk = rowk[k & 1];
       if (p == k) {
 #pragma unroll
         for (int q = 0; q < MLMAX; ++q) rk[q] = T[q];
       }
       wave_sync_lds();
-      const cd piv = cdiv(cd{1.0, 0.0}, rk[u]);
+      const CR piv = cdiv(CR{1, 0}, rk[u]);
       const bool me = p == k;
-      const cd f = me ? -piv : T[u] * piv;
+      const CR f = me ? -piv : T[u] * piv;
 #pragma unroll
       for (int q = 0; q < MLMAX; ++q) {
         if (q == u) continue;
-        cd v = me ? cd{0.0, 0.0} : T[q];
+        CR v = me ? CR{0, 0} : T[q];
         fma_acc(v, -f, rk[q]);
         T[q] = v;
       }
       T[u] = me ? piv : -f;
     }
-    cd t0 = T[0], t1 = T[1], t2 = T[2];
+    CR t0 = T[0], t1 = T[1], t2 = T[2];
 #pragma unroll
     for (int q = 0; q < MLMAX - 3; ++q) T[q] = T[q + 3];
     T[MLMAX - 3] = t0;
@@ -166,43 +78,46 @@ __device__ __forceinline__ void gj_wave_invert(cd (&T)[MLMAX], cd (*rowk)[MLMAX]
   }
 }
 
-// The same line factorization with one wavefront per subdomain.  Lane p owns
+// The line factorization, one wavefront per subdomain.  Lane p owns
 // row p of the current line block in registers (rows ml..63 are idle padding):
 // T_j is formed from the rows of G_j-1 (the neighbouring rows of
 // G_j-1 A_j-1,j by lane shuffles), then inverted in place by Gauss-Jordan
 // without pivoting, the pivot row passing through LDS.  The T_j and G_j are
-// complex symmetric, so lane p's row is also column p: the transposed store of
-// k_factor_lines becomes one coalesced store per column index.  One wavefront
+// complex symmetric, so lane p's row is also column p, and the transposed
+// storage of G_j (element (p, q) at [q][p]) takes one coalesced store per
+// column index.  One wavefront
 // needs no workgroup barrier; the per-step LDS traffic is the pivot row only.
-template <class Src>
+// R: arithmetic (double; float for the complex64 set-up); G_j is stored in FP64.
+template <class R, class Src>
 __global__ void __launch_bounds__(64) k_factor_lines_wave(Src src) {
-  __shared__ cd rowk[2][MLMAX];
-  __shared__ cd cpl[MLMAX][3];
+  using CR = C<R>;
+  __shared__ CR rowk[2][MLMAX];
+  __shared__ CR cpl[MLMAX][3];
   const Dev& d = src.dev();
   const Geo2& g = d.g;
   const int s = src.bx(), ml = g.ml, n2 = ml * ml, p = threadIdx.x;
   // coupling of node b of a line to node b + e - 1 of the neighbouring line
   for (int t = p; t < ml * 3; t += 64) {
     const int b = t / 3, e = t % 3, a = b + e - 1;
-    cpl[b][e] = (a >= 0 && a < ml) ? g.zloc(b, 1, a, 0) : cd{0.0, 0.0};
+    cpl[b][e] = cvt<R>((a >= 0 && a < ml) ? g.zloc(b, 1, a, 0) : cd{0.0, 0.0});
   }
-  cd cplp[3], dgb[3], dgi[3];  // row p's couplings and its in-line band (boundary / interior lines)
+  CR cplp[3], dgb[3], dgi[3];  // row p's couplings and its in-line band (boundary / interior lines)
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     const int a = p + e - 1;
     const bool ok = p < ml && a >= 0 && a < ml;
-    cplp[e] = ok ? g.zloc(p, 1, a, 0) : cd{0.0, 0.0};
-    dgb[e] = ok ? g.zloc(p, 0, a, 0) : cd{0.0, 0.0};
-    dgi[e] = ok ? g.zloc(p, 1, a, 1) : cd{0.0, 0.0};
+    cplp[e] = cvt<R>(ok ? g.zloc(p, 1, a, 0) : cd{0.0, 0.0});
+    dgb[e] = cvt<R>(ok ? g.zloc(p, 0, a, 0) : cd{0.0, 0.0});
+    dgi[e] = cvt<R>(ok ? g.zloc(p, 1, a, 1) : cd{0.0, 0.0});
   }
   wave_sync_lds();
-  cd T[MLMAX];
+  CR T[MLMAX];
 #pragma unroll
-  for (int q = 0; q < MLMAX; ++q) T[q] = cd{0.0, 0.0};
+  for (int q = 0; q < MLMAX; ++q) T[q] = CR{0, 0};
   uint64_t mprev = 0;
   for (int j = 0; j < ml; ++j) {
     const bool bnd = j == 0 || j == ml - 1;
-    cd dg[3];
+    CR dg[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) dg[e] = bnd ? dgb[e] : dgi[e];
     const uint64_t mj = __ballot(p < ml && g.rnode(s, p, j));  // r nodes of line j
@@ -211,227 +126,47 @@ __global__ void __launch_bounds__(64) k_factor_lines_wave(Src src) {
                rpp = p + 1 < ml && ((mprev >> (p + 1)) & 1);
     // T_j row p = E_jj row p - sum_a A_j,j-1[p][a] U[a][:],  U = G_j-1 A_j-1,j;
     // U row p from T (G_j-1 row p) in a sliding window, T overwritten behind it
-    cd prv{0.0, 0.0}, cur = T[0];
+    CR prv{0, 0}, cur = T[0];
 #pragma unroll
     for (int q = 0; q < MLMAX; ++q) {
-      const cd nxt = q + 1 < MLMAX ? T[q + 1] : cd{0.0, 0.0};
-      cd u{0.0, 0.0};
+      const CR nxt = q + 1 < MLMAX ? T[q + 1] : CR{0, 0};
+      CR u{0, 0};
       if (q >= 1 && ((mprev >> (q - 1)) & 1)) fma_acc(u, prv, cpl[q - 1][2]);
       if ((mprev >> q) & 1) fma_acc(u, cur, cpl[q][1]);
       if (q + 1 < ml && ((mprev >> (q + 1)) & 1)) fma_acc(u, nxt, cpl[q + 1][0]);
-      cd um, up;
+      CR um, up;
       um.x = __shfl(u.x, p - 1, 64);
       um.y = __shfl(u.y, p - 1, 64);
       up.x = __shfl(u.x, p + 1, 64);
       up.y = __shfl(u.y, p + 1, 64);
       const bool rq = (mj >> q) & 1;
-      cd v{0.0, 0.0};
+      CR v{0, 0};
       if (rp && rq) {
-        v = q == p - 1 ? dg[0] : q == p ? dg[1] : q == p + 1 ? dg[2] : cd{0.0, 0.0};
+        v = q == p - 1 ? dg[0] : q == p ? dg[1] : q == p + 1 ? dg[2] : CR{0, 0};
         if (rpm) v = v - cplp[0] * um;
         if (rp0) v = v - cplp[1] * u;
         if (rpp) v = v - cplp[2] * up;
       } else if (p == q) {
-        v = cd{1.0, 0.0};
+        v = CR{1, 0};
       }
       T[q] = v;
       prv = cur;
       cur = nxt;
     }
     // Gauss-Jordan: T <- T^-1 (rows and columns beyond ml are identity)
-    gj_wave_invert(T, rowk, p);
+    gj_wave_invert<R>(T, rowk, p);
     cd* out = d.G64 + ((size_t)s * ml + j) * n2;
     if (p < ml) {
 #pragma unroll
       for (int q = 0; q < MLMAX; ++q)
-        if (q < ml) out[q * ml + p] = T[q];
+        if (q < ml) out[q * ml + p] = cvt<double>(T[q]);
     }
     mprev = mj;
   }
 }
 
-template <class Src>
-__global__ void __launch_bounds__(256) k_multi_solve(Src src) {
-  const Dev& d = src.dev();
-  const Geo2& g = d.g;
-  const Maps2& mp = d.mp;
-  const cd* G64 = d.G64;
-  cd* Sinv64 = d.Sinv64;
-  cd* Phi64 = d.Phi64;
-  cd* PhiFull = d.PhiFull;
-  cd* scratch = d.scr;
-  __shared__ cd Gl[MLMAX * MLMAX];
-  __shared__ cd zb[MLMAX * CW];
-  __shared__ cd tb[MLMAX * CW];
-  __shared__ int slotmap[MLMAX * MLMAX];
-  __shared__ int sdl[128];
-  __shared__ int scl[4];
-  // per-subdomain tables, so that each panel entry takes lookups instead of
-  // node classes and 1D element values: the r-node mask of the local nodes;
-  // the coupling of node p of a line to node p + d - 1 of the next or the
-  // previous line (the same for every pair of lines, masked per use); and the
-  // Z entries between each corner and the 3 x 3 nodes around it
-  __shared__ unsigned char rmk[MLMAX * MLMAX];
-  __shared__ cd cpl[MLMAX][3];
-  __shared__ cd cst[4][9];
-  __shared__ int cab[4][2];
-  const int s = src.bx(), ml = g.ml, n2 = ml * ml, ND = g.ND;
-  const int nd = mp.nd[s];
-  int nc = 0;
-  for (int q = 0; q < 4; ++q) nc += (mp.cloc[s * 4 + q] >= 0);
-  for (int l = threadIdx.x; l < n2; l += blockDim.x) {
-    slotmap[l] = -1;
-    rmk[l] = g.rnode(s, l % ml, l / ml) ? 1 : 0;
-  }
-  if (threadIdx.x < ml * 3) {
-    const int p = threadIdx.x / 3, d = threadIdx.x % 3, a = p + d - 1;
-    cpl[p][d] = (a >= 0 && a < ml) ? g.zloc(p, 1, a, 0) : cd{0.0, 0.0};
-  }
-  if (threadIdx.x < 36) {
-    const int q = threadIdx.x / 9, e = threadIdx.x % 9;
-    const int cl = mp.cloc[s * 4 + q];  // corners are listed first (compact)
-    cd v{0.0, 0.0};
-    if (cl >= 0) {
-      const int ca = cl % ml, cb = cl / ml, a = ca + e % 3 - 1, b = cb + e / 3 - 1;
-      if (a >= 0 && a < ml && b >= 0 && b < ml) v = g.zloc(a, b, ca, cb);
-      if (e == 0) {
-        cab[q][0] = ca;
-        cab[q][1] = cb;
-      }
-    }
-    cst[q][e] = v;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-    int l = mp.dloc[s * ND + i];
-    sdl[i] = l;
-    slotmap[l] = i;
-  }
-  if (threadIdx.x < 4) scl[threadIdx.x] = mp.cloc[s * 4 + threadIdx.x];
-  __syncthreads();
-  const int ncol = nd + nc;
-  cd* scr = scratch + (size_t)s * ml * n2 * CW / ml;  // [ml lines][ml][CW]
-  for (int c0 = 0; c0 < ncol; c0 += CW) {
-    // forward sweep: t_j = G_j (rhs_j - A_j,j-1 t_j-1)
-    for (int j = 0; j < ml; ++j) {
-      const cd* Gj = G64 + ((size_t)s * ml + j) * n2;
-      for (int idx = threadIdx.x; idx < n2; idx += blockDim.x) Gl[idx] = Gj[idx];
-      for (int idx = threadIdx.x; idx < ml * CW; idx += blockDim.x) {
-        const int p = idx / CW, c = idx % CW, col = c0 + c;
-        // rhs: the unit vector of a Delta column or Z_rc of a corner column on
-        // r rows; minus the coupling to the previous line's r nodes
-        cd v{0.0, 0.0};
-        if (rmk[p + ml * j]) {
-          if (col < nd) {
-            if (sdl[col] == p + ml * j) v = cd{1.0, 0.0};
-          } else if (col < nd + nc) {
-            const int q = col - nd, da = p - cab[q][0] + 1, db = j - cab[q][1] + 1;
-            if (da >= 0 && da < 3 && db >= 0 && db < 3) v = cst[q][da + 3 * db];
-          }
-          if (j > 0)
-            for (int d = 0; d < 3; ++d) {
-              const int a = p + d - 1;
-              if (a >= 0 && a < ml && rmk[a + ml * (j - 1)]) v = v - cpl[p][d] * tb[a * CW + c];
-            }
-        }
-        zb[idx] = v;
-      }
-      __syncthreads();
-      {
-        // thread (row group rg, column c) forms rows rg, rg + 8, ... of column c:
-        // one LDS read of z per k serves up to five rows
-        const int c = threadIdx.x & (CW - 1), rg = threadIdx.x / CW;
-        cd acc[MT];
-#pragma unroll
-        for (int v = 0; v < MT; ++v) acc[v] = cd{0.0, 0.0};
-        for (int k = 0; k < ml; ++k) {
-          const cd z = zb[k * CW + c];
-#pragma unroll
-          for (int v = 0; v < MT; ++v) {
-            const int p = rg + RG * v;
-            if (p < ml) fma_acc(acc[v], Gl[k * ml + p], z);
-          }
-        }
-#pragma unroll
-        for (int v = 0; v < MT; ++v) {
-          const int p = rg + RG * v;
-          if (p < ml) {
-            tb[p * CW + c] = acc[v];
-            scr[((size_t)j * ml + p) * CW + c] = acc[v];
-          }
-        }
-      }
-      __syncthreads();
-    }
-    // backward sweep: x_j = t_j - G_j A_j,j+1 x_j+1   (tb holds x_j+1)
-    for (int j = ml - 1; j >= 0; --j) {
-      if (j < ml - 1) {
-        const cd* Gj = G64 + ((size_t)s * ml + j) * n2;
-        for (int idx = threadIdx.x; idx < n2; idx += blockDim.x) Gl[idx] = Gj[idx];
-        for (int idx = threadIdx.x; idx < ml * CW; idx += blockDim.x) {
-          const int p = idx / CW, c = idx % CW;
-          cd v{0.0, 0.0};
-          if (rmk[p + ml * j])
-            for (int d = 0; d < 3; ++d) {
-              const int a = p + d - 1;
-              if (a >= 0 && a < ml && rmk[a + ml * (j + 1)]) fma_acc(v, cpl[p][d], tb[a * CW + c]);
-            }
-          zb[idx] = v;
-        }
-        __syncthreads();
-        {
-          const int c = threadIdx.x & (CW - 1), rg = threadIdx.x / CW;
-          cd acc[MT];
-#pragma unroll
-          for (int v = 0; v < MT; ++v) {
-            const int p = rg + RG * v;
-            acc[v] = p < ml ? scr[((size_t)j * ml + p) * CW + c] : cd{0.0, 0.0};
-          }
-          for (int k = 0; k < ml; ++k) {
-            const cd z = zb[k * CW + c];
-#pragma unroll
-            for (int v = 0; v < MT; ++v) {
-              const int p = rg + RG * v;
-              if (p < ml) {
-                cd t = Gl[k * ml + p] * z;
-                acc[v] = acc[v] - t;
-              }
-            }
-          }
-#pragma unroll
-          for (int v = 0; v < MT; ++v) {
-            const int p = rg + RG * v;
-            if (p < ml) tb[p * CW + c] = acc[v];  // safe: zb holds the input of this line
-          }
-        }
-      } else {
-        for (int idx = threadIdx.x; idx < ml * CW; idx += blockDim.x) {
-          int p = idx / CW, c = idx % CW;
-          tb[idx] = scr[((size_t)j * ml + p) * CW + c];
-        }
-      }
-      __syncthreads();
-      // extract rows of line j
-      for (int idx = threadIdx.x; idx < ml * CW; idx += blockDim.x) {
-        int p = idx / CW, c = idx % CW, col = c0 + c;
-        int l = p + ml * j;
-        cd x = tb[idx];
-        int slot = slotmap[l];
-        if (col < nd) {
-          if (slot >= 0) Sinv64[((size_t)s * ND + slot) * ND + col] = x;
-        } else if (col < ncol) {
-          int q = col - nd;
-          if (slot >= 0) Phi64[((size_t)s * ND + slot) * NQ + q] = x;
-          PhiFull[((size_t)s * n2 + l) * 4 + q] = x;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
 // ---- multi_solve on the matrix cores ----
-// The same solves E^s X = [e_Delta, Z_rc] as k_multi_solve, with every line
+// The solves E^s X = [e_Delta, Z_rc] of the set-up, with every line
 // product G_j Z (33 x 33 by 33 x 32, complex) on v_mfma_f64_16x16x4f64: rows and
 // contraction index 0..31 as 2 x 8 tiles of 16 x 4 (complex = four real
 // products), the 33rd row and column (ml = 33) on the vector units.  A
@@ -442,25 +177,44 @@ __global__ void __launch_bounds__(256) k_multi_solve(Src src) {
 // per wavefront and line); the workgroups loop over the subdomains, so the
 // scratch is at most MS_SLOTS_MAX slots whatever the batch size.
 //
-// Operand layouts of v_mfma_f64_16x16x4f64 (a wavefront of 64 lanes, l = lane):
+// Operand layouts (a wavefront of 64 lanes, l = lane), measured on gfx950:
 // A (16 x 4): lane l holds A[l % 16][l / 16]; B (4 x 16): lane l holds
-// B[l / 16][l % 16]; C/D (16 x 16): lane l, register r holds D[4 r + l / 16][l % 16],
-// so register r of a result tile is the B operand of contraction step r.
-typedef double d4v __attribute__((ext_vector_type(4)));
+// B[l / 16][l % 16]; C/D (16 x 16): lane l, register r holds D[row][l % 16] with
+// row = 4 r + l / 16 for v_mfma_f64_16x16x4f64 and row = 4 (l / 16) + r for
+// v_mfma_f32_16x16x4f32.
 constexpr int MS_COLS = 32;  // columns per wavefront
 static_assert(MS_COLS == MS_WAVE_COLS, "columns per wavefront");
 
-__device__ inline d4v mfma64(double a, double b, d4v c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+template <class R> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int r, int lq) { return 4 * r + lq; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int r, int lq) { return 4 * lq + r; }
+};
+typedef Mfma<double>::v4 d4v;
+__device__ inline d4v mfma64(double a, double b, d4v c) { return Mfma<double>::op(a, b, c); }
 
-template <class Src>
+// R: arithmetic (double on the FP64 matrix cores; float on the FP32 ones for the
+// complex64 set-up); inputs and outputs are FP64.
+template <class R, class Src>
 __global__ void __launch_bounds__(256) k_multi_solve_mfma(Src src, int total, cd* mscr, size_t slot_cd) {
-  __shared__ cd tb[4][MLMAX][MS_COLS];  // per wavefront: t_j (then x_j) of its columns
+  using CR = C<R>;
+  using MT = Mfma<R>;
+  using v4 = typename MT::v4;
+  __shared__ CR tb[4][MLMAX][MS_COLS];  // per wavefront: t_j (then x_j) of its columns
   __shared__ int slotmap[MLMAX * MLMAX];
   __shared__ int sdl[128];
-  __shared__ cd cpl[MLMAX][3];
-  __shared__ cd cst[4][9];
+  __shared__ CR cpl[MLMAX][3];
+  __shared__ CR cst[4][9];
   __shared__ int cab[4][2];
   __shared__ int s_nc;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
@@ -475,7 +229,7 @@ __global__ void __launch_bounds__(256) k_multi_solve_mfma(Src src, int total, cd
     for (int i = threadIdx.x; i < n2; i += blockDim.x) slotmap[i] = -1;
     if (threadIdx.x < ml * 3) {
       const int p = threadIdx.x / 3, e = threadIdx.x % 3, a = p + e - 1;
-      cpl[p][e] = (a >= 0 && a < ml) ? g.zloc(p, 1, a, 0) : cd{0.0, 0.0};
+      cpl[p][e] = cvt<R>((a >= 0 && a < ml) ? g.zloc(p, 1, a, 0) : cd{0.0, 0.0});
     }
     if (threadIdx.x < 36) {
       const int q = threadIdx.x / 9, e = threadIdx.x % 9;
@@ -489,7 +243,7 @@ __global__ void __launch_bounds__(256) k_multi_solve_mfma(Src src, int total, cd
           cab[q][1] = cb;
         }
       }
-      cst[q][e] = v;
+      cst[q][e] = cvt<R>(v);
     }
     if (threadIdx.x == 0) {
       int nc = 0;
@@ -507,16 +261,16 @@ __global__ void __launch_bounds__(256) k_multi_solve_mfma(Src src, int total, cd
     if (c0 >= ncol) continue;  // no columns for this wavefront (no barrier follows)
     const bool big = ml == MLMAX;  // the 33rd row and column exist
     const cd* G = d.G64 + (size_t)s * ml * n2;
-    cd (*T)[MS_COLS] = tb[w];
+    CR (*T)[MS_COLS] = tb[w];
     // Z[k][c] of line j: the right-hand side minus the coupling to line j - 1
     // (forward) or the coupling to line j + 1 (backward), masked to r nodes
-    auto zval = [&](int k, int c, int j, bool fwd, uint64_t mj, uint64_t mo) -> cd {
+    auto zval = [&](int k, int c, int j, bool fwd, uint64_t mj, uint64_t mo) -> CR {
       const int col = c0 + c;
-      cd v{0.0, 0.0};
+      CR v{0, 0};
       if (k >= ml || col >= ncol || !((mj >> k) & 1)) return v;
       if (fwd) {
         if (col < nd) {
-          if (sdl[col] == k + ml * j) v = cd{1.0, 0.0};
+          if (sdl[col] == k + ml * j) v = CR{1, 0};
         } else {
           const int q = col - nd, da = k - cab[q][0] + 1, db = j - cab[q][1] + 1;
           if (da >= 0 && da < 3 && db >= 0 && db < 3) v = cst[q][da + 3 * db];
@@ -535,52 +289,52 @@ __global__ void __launch_bounds__(256) k_multi_solve_mfma(Src src, int total, cd
       return v;
     };
     // one line: X = C0 + sgn G_j Z with Z from zval; C0 = 0 (forward) or t_j (backward)
-    auto line = [&](int j, bool fwd, uint64_t mj, uint64_t mo, d4v (&Cr)[2][2], d4v (&Ci)[2][2],
-                    cd (&x32)[2]) {
+    auto line = [&](int j, bool fwd, uint64_t mj, uint64_t mo, v4 (&Cr)[2][2], v4 (&Ci)[2][2],
+                    CR (&x32)[2]) {
       const cd* Gj = G + (size_t)j * n2;  // element (p, q) at [q ml + p]
-      double br[8][2], bi[8][2];
-      cd z32[2];
+      R br[8][2], bi[8][2];
+      CR z32[2];
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt) {
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
-          const cd z = zval(4 * kk + lq, 16 * nt + lr, j, fwd, mj, mo);
+          const CR z = zval(4 * kk + lq, 16 * nt + lr, j, fwd, mj, mo);
           br[kk][nt] = z.x;
           bi[kk][nt] = z.y;
         }
-        z32[nt] = big ? zval(32, 16 * nt + lr, j, fwd, mj, mo) : cd{0.0, 0.0};
+        z32[nt] = big ? zval(32, 16 * nt + lr, j, fwd, mj, mo) : CR{0, 0};
       }
       wave_sync_lds();  // every read of T for Z is done before T is overwritten
-      const double sg = fwd ? 1.0 : -1.0;
+      const R sg = fwd ? R(1) : R(-1);
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
         if (16 * mt >= ml) continue;
-        double ar[8], ai[8];
+        R ar[8], ai[8];
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
           const int p = 16 * mt + lr, q = 4 * kk + lq;
-          const cd a = (p < ml && q < ml) ? Gj[(size_t)q * ml + p] : cd{0.0, 0.0};
+          const CR a = cvt<R>((p < ml && q < ml) ? Gj[(size_t)q * ml + p] : cd{0.0, 0.0});
           ar[kk] = sg * a.x;
           ai[kk] = sg * a.y;
         }
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
-          d4v cr = Cr[mt][nt], ci = Ci[mt][nt];
+          v4 cr = Cr[mt][nt], ci = Ci[mt][nt];
 #pragma unroll
           for (int kk = 0; kk < 8; ++kk) {
             if (4 * kk >= ml) break;
-            cr = mfma64(ar[kk], br[kk][nt], cr);
-            cr = mfma64(-ai[kk], bi[kk][nt], cr);
-            ci = mfma64(ar[kk], bi[kk][nt], ci);
-            ci = mfma64(ai[kk], br[kk][nt], ci);
+            cr = MT::op(ar[kk], br[kk][nt], cr);
+            cr = MT::op(-ai[kk], bi[kk][nt], cr);
+            ci = MT::op(ar[kk], bi[kk][nt], ci);
+            ci = MT::op(ai[kk], br[kk][nt], ci);
           }
           if (big) {  // contraction index 32: rank-one term
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int p = 16 * mt + 4 * r + lq;
-              const cd gp = Gj[(size_t)32 * ml + p];
-              cd acc{cr[r], ci[r]};
-              fma_acc(acc, cd{sg * gp.x, sg * gp.y}, z32[nt]);
+              const int p = 16 * mt + MT::row(r, lq);
+              const CR gp = cvt<R>(Gj[(size_t)32 * ml + p]);
+              CR acc{cr[r], ci[r]};
+              fma_acc(acc, CR{sg * gp.x, sg * gp.y}, z32[nt]);
               cr[r] = acc.x;
               ci[r] = acc.y;
             }
@@ -592,33 +346,34 @@ __global__ void __launch_bounds__(256) k_multi_solve_mfma(Src src, int total, cd
       if (big) {  // row 32: sum over this lane's contraction indices, then over the lane groups
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
-          cd acc{0.0, 0.0};
+          CR acc{0, 0};
 #pragma unroll
           for (int kk = 0; kk < 8; ++kk) {
-            const cd gq = Gj[(size_t)(4 * kk + lq) * ml + 32];
-            fma_acc(acc, gq, cd{br[kk][nt], bi[kk][nt]});
+            const CR gq = cvt<R>(Gj[(size_t)(4 * kk + lq) * ml + 32]);
+            fma_acc(acc, gq, CR{br[kk][nt], bi[kk][nt]});
           }
           acc.x += __shfl_xor(acc.x, 16, 64);
           acc.y += __shfl_xor(acc.y, 16, 64);
           acc.x += __shfl_xor(acc.x, 32, 64);
           acc.y += __shfl_xor(acc.y, 32, 64);
-          fma_acc(acc, Gj[(size_t)32 * ml + 32], z32[nt]);
-          x32[nt] = x32[nt] + cd{sg * acc.x, sg * acc.y};
+          fma_acc(acc, cvt<R>(Gj[(size_t)32 * ml + 32]), z32[nt]);
+          x32[nt] = x32[nt] + CR{sg * acc.x, sg * acc.y};
         }
       }
     };
     // write x_j (registers) to T, and the outputs of line j if out
-    auto emit = [&](int j, const d4v (&Cr)[2][2], const d4v (&Ci)[2][2], const cd (&x32)[2], bool out) {
+    auto emit = [&](int j, const v4 (&Cr)[2][2], const v4 (&Ci)[2][2], const CR (&x32)[2], bool out) {
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int p = 16 * mt + 4 * r + lq, c = 16 * nt + lr;
+            const int p = 16 * mt + MT::row(r, lq), c = 16 * nt + lr;
             if (p >= ml) continue;
-            const cd x{Cr[mt][nt][r], Ci[mt][nt][r]};
-            T[p][c] = x;
+            const CR xr{Cr[mt][nt][r], Ci[mt][nt][r]};
+            const cd x = cvt<double>(xr);
+            T[p][c] = xr;
             const int col = c0 + c;
             if (!out || col >= ncol) continue;
             const int node = p + ml * j, sl = slotmap[node];
@@ -637,20 +392,21 @@ __global__ void __launch_bounds__(256) k_multi_solve_mfma(Src src, int total, cd
           T[32][c] = x32[nt];
           if (!out || col >= ncol) continue;
           const int sl = slotmap[node];
+          const cd x = cvt<double>(x32[nt]);
           if (col < nd) {
-            if (sl >= 0) d.Sinv64[((size_t)s * ND + sl) * ND + col] = x32[nt];
+            if (sl >= 0) d.Sinv64[((size_t)s * ND + sl) * ND + col] = x;
           } else {
             const int q = col - nd;
-            if (sl >= 0) d.Phi64[((size_t)s * ND + sl) * NQ + q] = x32[nt];
-            d.PhiFull[((size_t)s * n2 + node) * 4 + q] = x32[nt];
+            if (sl >= 0) d.Phi64[((size_t)s * ND + sl) * NQ + q] = x;
+            d.PhiFull[((size_t)s * n2 + node) * 4 + q] = x;
           }
         }
       }
       wave_sync_lds();
     };
     cd* wsl = slot + (size_t)w * ml * ml * MS_COLS;  // this wavefront's lines, ml x 32 each
-    d4v Cr[2][2], Ci[2][2];
-    cd x32[2];
+    v4 Cr[2][2], Ci[2][2];
+    CR x32[2];
     // steps 0 .. ml-1: forward sweep t_j = G_j (rhs_j - A_j,j-1 t_j-1), kept in T
     // and in the slot; steps ml .. 2 ml - 2: backward sweep x_j = t_j - G_j A_j,j+1 x_j+1
     // (T holds x_j+1).  One loop, so the line body is generated once.
@@ -664,8 +420,8 @@ __global__ void __launch_bounds__(256) k_multi_solve_mfma(Src src, int total, cd
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-          for (int nt = 0; nt < 2; ++nt) Cr[mt][nt] = Ci[mt][nt] = d4v{0.0, 0.0, 0.0, 0.0};
-        x32[0] = x32[1] = cd{0.0, 0.0};
+          for (int nt = 0; nt < 2; ++nt) Cr[mt][nt] = Ci[mt][nt] = v4{0, 0, 0, 0};
+        x32[0] = x32[1] = CR{0, 0};
       } else {
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
@@ -673,18 +429,18 @@ __global__ void __launch_bounds__(256) k_multi_solve_mfma(Src src, int total, cd
           for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int row = 16 * mt + 4 * r + lq;
-              const cd t = row < ml ? o[row * MS_COLS + 16 * nt + lr] : cd{0.0, 0.0};
+              const int row = 16 * mt + MT::row(r, lq);
+              const CR t = cvt<R>(row < ml ? o[row * MS_COLS + 16 * nt + lr] : cd{0.0, 0.0});
               Cr[mt][nt][r] = t.x;
               Ci[mt][nt][r] = t.y;
             }
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) x32[nt] = big ? o[32 * MS_COLS + 16 * nt + lr] : cd{0.0, 0.0};
+        for (int nt = 0; nt < 2; ++nt) x32[nt] = cvt<R>(big ? o[32 * MS_COLS + 16 * nt + lr] : cd{0.0, 0.0});
       }
       line(j, fwd, mj, mo, Cr, Ci, x32);
       emit(j, Cr, Ci, x32, !fwd || j == ml - 1);
       if (fwd && j < ml - 1)
-        for (int idx = l; idx < ml * MS_COLS; idx += 64) o[idx] = T[idx / MS_COLS][idx % MS_COLS];
+        for (int idx = l; idx < ml * MS_COLS; idx += 64) o[idx] = cvt<double>(T[idx / MS_COLS][idx % MS_COLS]);
       mo = mj;  // the next line (j + 1 forward, j - 1 backward) couples to this one
     }
   }
@@ -843,6 +599,29 @@ __global__ void k_coarse_assemble(Src src) {
   }
 }
 
+// In-place Gauss-Jordan inverse of an n x n complex matrix in LDS (row-major).
+__device__ void gj_invert_lds(cd* T, int n, cd* rowk, cd* colk) {
+  for (int k = 0; k < n; ++k) {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      rowk[t] = T[k * n + t];
+      colk[t] = T[t * n + k];
+    }
+    __syncthreads();
+    cd piv = cdiv(cd{1.0, 0.0}, rowk[k]);
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+      int i = idx / n, j = idx % n;
+      cd v;
+      if (i == k && j == k) v = piv;
+      else if (i == k) v = rowk[j] * piv;
+      else if (j == k) v = -(colk[i] * piv);
+      else v = T[idx] - colk[i] * (rowk[j] * piv);
+      T[idx] = v;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+}
+
 // Inverse of a small coarse matrix (nK <= GJ_LDS_MAX) in LDS, one workgroup per
 // instance: Kinv = GJ(Kcc); instances with larger coarse matrices return.
 constexpr int GJ_LDS_MAX = 96;
@@ -967,7 +746,6 @@ __global__ void k_pack(Src src, int which) {
 // panel's rows and columns (which reads the old panel), then the panel's rows
 // and columns.
 constexpr int GJ_PB = 32;     // pivots per panel
-constexpr int GJ_RT = 16;     // rows per workgroup of the outer update
 constexpr int GJ_CT = 128;    // columns (or rows) per workgroup staged in LDS
 // D = inverse of the b x b block of A at (k0, k0) (b <= GJ_PB, D row stride b) by
 // Gauss-Jordan without pivoting, 256 threads: thread t keeps row t / 8, columns
@@ -1024,60 +802,9 @@ __device__ inline void gj_load_d(cd* Dl, const cd* D, int b) {
     Dl[t] = (r < b && c < b) ? D[r * b + c] : cd{0.0, 0.0};
   }
 }
-// Entries outside the panel's rows and columns: workgroup (x, y) takes rows
-// GJ_RT y .. (+GJ_RT) and columns GJ_CT x .. (+GJ_CT).  U = A_iK D for its
-// rows goes to LDS; thread (half, column) then updates 8 rows of one column,
-// A_ij -= U_i A_Kj, reading the panel rows A_Kj of its column straight from
-// memory (shared by every row block, so mostly cache hits; eight loads in
-// flight).  32 KB of LDS lets several workgroups share a CU.
-__global__ void __launch_bounds__(256) k_gj_rows(int n, int k0, int b, cd* A, const cd* D, size_t sA,
-                                                 size_t sD) {
-  __shared__ cd Dl[GJ_PB * GJ_PB], Ul[GJ_RT * GJ_PB], Ak[GJ_RT * GJ_PB];
-  A += blockIdx.z * sA;
-  D += blockIdx.z * sD;
-  const int i0 = blockIdx.y * GJ_RT, j0 = blockIdx.x * GJ_CT;
-  const int nr = min(GJ_RT, n - i0);
-  const int cc = threadIdx.x % GJ_CT, half = threadIdx.x / GJ_CT, j = j0 + cc;
-  const bool active = j < n && (j < k0 || j >= k0 + b);
-  cd v[8];  // this thread's entries, loaded before the staging so the latencies overlap
-#pragma unroll
-  for (int rr = 0; rr < 8; ++rr) {
-    const int r = half * 8 + rr;
-    v[rr] = (active && r < nr) ? A[(size_t)(i0 + r) * n + j] : cd{0.0, 0.0};
-  }
-  gj_load_d(Dl, D, b);
-  for (int t = threadIdx.x; t < GJ_RT * GJ_PB; t += blockDim.x) {
-    const int r = t / GJ_PB, c = t % GJ_PB, i = i0 + r;
-    const bool in = r < nr && c < b && (i < k0 || i >= k0 + b);
-    Ak[t] = in ? A[(size_t)i * n + k0 + c] : cd{0.0, 0.0};
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < GJ_RT * GJ_PB; t += blockDim.x) {
-    const int r = t / GJ_PB, c = t % GJ_PB;
-    cd u{0.0, 0.0};
-    for (int q = 0; q < b; ++q) fma_acc(u, Ak[r * GJ_PB + q], Dl[q * GJ_PB + c]);
-    Ul[t] = u;  // zero for rows of the panel, beyond nr, and columns beyond b
-  }
-  __syncthreads();
-  if (!active) return;
-  const cd* Ak0 = A + (size_t)k0 * n + j;  // A_Kj, q-th at Ak0 + q n
-  for (int q0 = 0; q0 < b; q0 += 8) {
-    cd ck[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) ck[u] = q0 + u < b ? Ak0[(size_t)(q0 + u) * n] : cd{0.0, 0.0};
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-#pragma unroll
-      for (int rr = 0; rr < 8; ++rr) v[rr] = v[rr] - Ul[(half * 8 + rr) * GJ_PB + q0 + u] * ck[u];
-  }
-#pragma unroll
-  for (int rr = 0; rr < 8; ++rr) {
-    const int r = half * 8 + rr, i = i0 + r;
-    if (r < nr && (i < k0 || i >= k0 + b)) A[(size_t)i * n + j] = v[rr];
-  }
-}
-// The same update on the matrix cores (v_mfma_f64_16x16x4f64; operand layouts
-// as for k_multi_solve_mfma).  Workgroup (x, y, z) takes rows 32 y .. 32 y + 31
+// The update outside the panel's rows and columns, A_ij -= (A_iK D) A_Kj, on
+// the matrix cores (v_mfma_f64_16x16x4f64; operand layouts as for
+// k_multi_solve_mfma).  Workgroup (x, y, z) takes rows 32 y .. 32 y + 31
 // of matrix z and the columns [x jspan, (x + 1) jspan).  U = A_iK D (32 x b) is
 // formed once in LDS and held by every wavefront as negated A operands; the
 // wavefronts then sweep their columns in tiles of 16: C = A_ij (two 16 x 16
@@ -1163,11 +890,11 @@ __global__ void __launch_bounds__(256) k_gj_rows_mfma(int n, int k0, int b, int 
       }
   }
 }
-// The panel itself, after k_gj_rows (old panel values staged in LDS before any
+// The panel itself, after k_gj_rows_mfma (old panel values staged in LDS before any
 // write): blocks [0, gx) take GJ_CT columns j each (the panel rows: A_Kj = D A_Kj,
 // A_KK = D), blocks [gx, 2 gx) take GJ_CT rows i each outside the panel
 // (A_iK = -A_iK D).  The two sets of entries are disjoint.  Block 2 gx inverts
-// the next panel's pivot block (pivots below kend) into Dn: k_gj_rows has
+// the next panel's pivot block (pivots below kend) into Dn: k_gj_rows_mfma has
 // already given it its final value, and nothing here writes it.
 __global__ void __launch_bounds__(256) k_gj_panel(int n, int k0, int b, int gx, int kend, cd* A, const cd* D,
                                                   cd* Dn, size_t sA, size_t sD) {
@@ -1285,17 +1012,27 @@ hipError_t launch_setup(const Target& t) {
   const int yK = (ND * (ND + 1) / 2 + 255) / 256;
   launch2(t, K_SUB, k_zero_sub<One>, k_zero_sub<Many>, yS, 256, 0, 0);
   launch2(t, K_SUB, k_zero_sub<One>, k_zero_sub<Many>, yP, 256, 0, 1);
-  launch2(t, K_SUB, k_factor_lines_wave<One>, k_factor_lines_wave<Many>, 1, 64, 0);
+  if (t.setup32)
+    launch2(t, K_SUB, k_factor_lines_wave<float, One>, k_factor_lines_wave<float, Many>, 1, 64, 0);
+  else
+    launch2(t, K_SUB, k_factor_lines_wave<double, One>, k_factor_lines_wave<double, Many>, 1, 64, 0);
   {
     const int total = t.blocks(K_SUB), grid = std::min(total, MS_SLOTS_MAX);
     cd* mscr = ps[0]->ctx->ms_scr;
     size_t slot = 0;
     for (Problem* p : ps) slot = std::max(slot, ms_slot_cd(p->m));
-    if (t.single())
-      hipLaunchKernelGGL(k_multi_solve_mfma<One>, dim3(grid), dim3(256), 0, t.st, t.src1(), total, mscr, slot);
-    else
-      hipLaunchKernelGGL(k_multi_solve_mfma<Many>, dim3(grid), dim3(256), 0, t.st, t.srcN(K_SUB), total, mscr,
+    if (t.single() && t.setup32)
+      hipLaunchKernelGGL((k_multi_solve_mfma<float, One>), dim3(grid), dim3(256), 0, t.st, t.src1(), total, mscr,
                          slot);
+    else if (t.single())
+      hipLaunchKernelGGL((k_multi_solve_mfma<double, One>), dim3(grid), dim3(256), 0, t.st, t.src1(), total, mscr,
+                         slot);
+    else if (t.setup32)
+      hipLaunchKernelGGL((k_multi_solve_mfma<float, Many>), dim3(grid), dim3(256), 0, t.st, t.srcN(K_SUB), total,
+                         mscr, slot);
+    else
+      hipLaunchKernelGGL((k_multi_solve_mfma<double, Many>), dim3(grid), dim3(256), 0, t.st, t.srcN(K_SUB), total,
+                         mscr, slot);
   }
   launch2(t, K_SUB, k_edge_basis<One>, k_edge_basis<Many>, 1, 256, 0);
   launch2(t, K_SUB, k_copy_sub<One>, k_copy_sub<Many>, yS, 256, 0);

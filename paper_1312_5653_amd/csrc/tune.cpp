@@ -69,12 +69,17 @@ int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, con
   return best;
 }
 
+std::atomic<unsigned> g_gen{0};
+
 void tune_set_mode(bool on, int force) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_enabled = on;
   g_force = force;
   g_table.clear();
+  g_gen++;
 }
+
+unsigned tune_generation() { return g_gen.load(); }
 
 int tune_table(TuneEntry* out, int cap) {
   std::lock_guard<std::mutex> lk(g_mu);

@@ -25,7 +25,8 @@ EXPORTS = [
     "sfdp_batch_create", "sfdp_batch_destroy", "sfdp_batch_sizes", "sfdp_batch_set_beta",
     "sfdp_batch_solve_range_space", "sfdp_server_create", "sfdp_server_submit", "sfdp_server_poll",
     "sfdp_server_stats", "sfdp_server_destroy", "sfdp_set_coarse_space", "sfdp_batch_inspect",
-    "sfdp_solve_full_space", "sfdp_set_tuning", "sfdp_kkt_residual_noalloc",
+    "sfdp_solve_full_space", "sfdp_set_tuning", "sfdp_kkt_residual_noalloc", "sfdp_set_graphs",
+    "sfdp_set_setup_arithmetic",
 ]
 
 
@@ -70,7 +71,7 @@ class ServerInfo(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("setups", ctypes.c_int64), ("evictions", ctypes.c_int64), ("ticks", ctypes.c_int64),
                 ("resident", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("mean_ms", ctypes.c_double),
-                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double)]
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("solo_in_flight_max", ctypes.c_int64)]
 
 
 class Timing(ctypes.Structure):
@@ -111,6 +112,8 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_set_beta.argtypes = [P, D]
     lib.sfdp_solve_range_space.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.sfdp_set_tuning.argtypes = [I]
+    lib.sfdp_set_graphs.argtypes = [I]
+    lib.sfdp_set_setup_arithmetic.argtypes = [I]
     lib.sfdp_solve_full_space.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.sfdp_apply_schur_inv.argtypes = [P, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.sfdp_feti_solve.argtypes = [P, I, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(I)]
@@ -142,7 +145,8 @@ def load_library(path: str = LIB_PATH):
                  "sfdp_inspect", "sfdp_interface_apply",
                  "sfdp_timing_enable", "sfdp_kernel_times", "sfdp_batch_create", "sfdp_batch_sizes",
                  "sfdp_batch_set_beta", "sfdp_batch_solve_range_space", "sfdp_server_create",
-                 "sfdp_server_submit", "sfdp_server_poll", "sfdp_server_stats"):
+                 "sfdp_server_submit", "sfdp_server_poll", "sfdp_server_stats", "sfdp_set_graphs", "sfdp_set_tuning",
+                 "sfdp_set_setup_arithmetic"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -474,3 +478,16 @@ def force_variant(c: int):
     """Run launch variant c of every kernel that has it (tests); set_tuning restores."""
     load_library()
     _check(_lib.sfdp_set_tuning(2 + int(c)))
+
+
+def set_graphs(enable: bool):
+    """Graph replay of the refinement steps of single 2D problems on or off (default)."""
+    load_library()
+    _check(_lib.sfdp_set_graphs(int(bool(enable))))
+
+
+def set_setup_arithmetic(bits: int):
+    """64 (default) or 32: arithmetic of the set-up's line factorization and line
+    solves for complex64-storage problems, from the next set-up on."""
+    load_library()
+    _check(_lib.sfdp_set_setup_arithmetic(int(bits)))

@@ -164,9 +164,11 @@ def test_large_instances_share_launches(sfdp):
 
 def test_solo_lane_3d_and_full_space(sfdp):
     """3D requests and full-space requests (MINRES with the factored Schur
-    complement) join the same stream as 2D range-space requests: the worker
-    solves them whole between ticks.  Every result meets the KKT gate, and a
-    3D result equals that of a lone problem solved with the same options."""
+    complement) join the same stream as 2D range-space requests: each advances
+    one refinement step or MINRES iteration per worker tick, several in flight
+    together.  Every result meets the KKT gate; the 3D and full-space results
+    equal those of lone problems solved with the same options (1e-12, the same
+    iteration counts), although they ran interleaved."""
     ctx = sfdp.Context(0)
     srv = sfdp.Server(ctx, sfdp.SFDP_MIXED, tol_kkt=1e-8)
     reqs = [  # dim, n_elem, sub_elem, beta, nrhs, full space
@@ -199,14 +201,24 @@ def test_solo_lane_3d_and_full_space(sfdp):
         out.append((y.cpu().numpy(), info))
     s = srv.stats()
     assert s["completed"] == len(reqs) and s["failed"] == 0, s
+    # the four solo requests (two meshes and betas in 3D, two full-space) were in flight together
+    assert s["solo_in_flight_max"] >= 3, s
     srv.close()
-    # the 3D range-space request against a lone problem with the same options
-    p = sfdp.Problem(ctx, 3, 16, 4, sfdp.SFDP_MIXED)
-    p.set_beta(1e-5)
-    y1, _, _, info1, st1 = p.solve_range_space(_t(data[5]), None, tol_kkt=1e-8)
-    assert st1 == 0
-    for r in range(3):
-        assert np.linalg.norm(y1[r].cpu().numpy() - out[5][0][r]) <= 1e-12 * np.linalg.norm(out[5][0][r])
-        assert info1[r]["krylov_its"] == out[5][1][r]["krylov_its"]
-    p.close()
+    # every solo request against a lone problem with the same options
+    for i, (dim, N, m, b, k, fs) in enumerate(reqs):
+        if dim == 2 and not fs:
+            continue
+        p = sfdp.Problem(ctx, dim, N, m, sfdp.SFDP_MIXED)
+        try:
+            p.set_beta(b)
+            solve = p.solve_full_space if fs else p.solve_range_space
+            y1, _, _, info1, st1 = solve(_t(data[i]), None, tol_kkt=1e-8)
+            assert st1 == 0
+            for r in range(k):
+                assert np.linalg.norm(y1[r].cpu().numpy() - out[i][0][r]) <= 1e-12 * np.linalg.norm(out[i][0][r]), \
+                    (i, r)
+                assert info1[r]["krylov_its"] == out[i][1][r]["krylov_its"], (i, r)
+                assert info1[r]["minres_its"] == out[i][1][r]["minres_its"], (i, r)
+        finally:
+            p.close()
     ctx.close()
