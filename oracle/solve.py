@@ -197,7 +197,10 @@ def pearson_wathen_inverse(lu_p, M, r):
 
 
 def full_space_minres(K, M, Kc, beta, ybar, yc=None, tol=1e-12, maxit=50, lu=None, schur="exact"):
-    """O5: preconditioned MINRES (Paige and Saunders) on A x = b, the KKT system
+    """O5: preconditioned MINRES (C. C. Paige and M. A. Saunders, "Solution of sparse
+    indefinite systems of linear equations", SIAM J. Numer. Anal. 12 (1975) 617-629: the
+    Lanczos recurrence in the preconditioner's inner product with a Givens QR of the
+    tridiagonal matrix and the usual names of its scalars) on A x = b, the KKT system
     of Sec. 2, with P = blkdiag(M, beta M, S) (Sec. 3.2, the preconditioner of
     Murphy, Golub and Wathen, under which A has at most three distinct
     eigenvalues).  schur = "exact" applies S^-1 by the two complex factors;

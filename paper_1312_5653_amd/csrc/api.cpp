@@ -1746,7 +1746,8 @@ sfdp_status fs_pinv(FsCtx& c, const double* r, double* out) {
   return SFDP_OK;
 }
 
-// MINRES (Paige and Saunders) on A dx = rr with the preconditioner P_mgw, from
+// MINRES (C. C. Paige and M. A. Saunders, SIAM J. Numer. Anal. 12 (1975) 617-629;
+// the scalars carry that method's usual names) on A dx = rr with the preconditioner P_mgw, from
 // dx = 0: Lanczos in the P-inner product, Givens QR of its tridiagonal matrix,
 // search directions w.  V holds 8 device vectors of length 3n.
 sfdp_status fs_minres(FsCtx& c, double* V, const double* rr, double* dx, int& its) {
