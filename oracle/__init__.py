@@ -22,6 +22,10 @@ feti     FETI-DP written out from its definitions (Sec. 5: signed Boolean
          matrices, interface operator F and right-hand side d, corner coarse
          problem, Dirichlet preconditioner) with dense local inverses, for
          small meshes.  Used to pin the GPU path's intermediate quantities.
+elastic  Trilinear linear-elasticity elements on a box (Sec. 6.2 solid
+         cantilever control): stiffness, vector mass, pressure and body
+         loads, support reactions.  The KKT and range-space solvers above
+         take its K and V unchanged.
 
 Every function cites the passage of the paper it follows.  Where the paper is
 silent, the reading taken is stated in the docstring.
