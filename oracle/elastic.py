@@ -20,6 +20,10 @@ Numbering (a convention of this module and the library's documentation):
   c (0: x, 1: y, 2: z) of free node f;
 * "cantilever": clamped face i = 0; "cube": all six faces clamped (L = 1),
   for manufactured-solution tests.
+
+Decomposition cuts the cantilever into cubic subdomains for FETI-DP (Sec. 5)
+and exposes it on dofs to the dense routines of oracle.feti, so the same
+definitions of F_DP, d, K_cc*, S_bb and the recovery serve the elastic case.
 """
 from __future__ import annotations
 
@@ -193,3 +197,127 @@ def reactions(box: Box, u_free: np.ndarray, E: float = YOUNG, nu: float = POISSO
                     if box.fixed[nd]:
                         tot += fe[3 * l:3 * l + 3]
     return tot
+
+
+class _Dofs:
+    """Dof view of a Box for the generic FETI-DP routines of oracle.feti: full dof
+    3 node + c over all grid nodes, free dofs in the free numbering above."""
+
+    def __init__(self, box: Box):
+        node_of_free = np.nonzero(~box.fixed)[0]
+        self.n_full = 3 * box.ijk.shape[0]
+        self.free_full = (3 * node_of_free[:, None] + np.arange(3)[None, :]).ravel()
+        self.n = self.free_full.size
+
+
+class Decomposition:
+    """FETI-DP partition of a cantilever Box into Px x Py x Pz cubes of m^3 cells
+    (Sec. 5 applied to the Sec. 6.2 state equation), with the attributes the
+    dense routines of oracle.feti read (subs[s]: full, r, c, delta_loc, Br, Bc;
+    nmu, nC, mults, mult, corner_full, mesh; local_matrices, split_rhs), on dofs.
+
+    Readings (the paper names FETI-DPH without its primal set for this problem):
+    * corners: the three dofs of every subdomain vertex that is not clamped;
+    * Delta dofs: the other unclamped dofs of nodes shared by two or more
+      subdomains; fully redundant multipliers, one per pair (s_a < s_b) of the
+      subdomains sharing the node, per component, signed +1 on s_a, ordered by
+      the full dof (node, then component), then by pair;
+    * the remaining unclamped dofs (subdomain interior and free surface) are
+      local to their subdomain;
+    * local dof 3 l + c of local node l = a + (m+1) b + (m+1)^2 c (x fastest);
+      r and c sets in increasing local dof; subdomain s = sx + Px (sy + Py sz);
+      corners in increasing full dof.
+    """
+
+    def __init__(self, box: Box, m: int, E: float = YOUNG, nu: float = POISSON):
+        if box.clamp != "cantilever":
+            raise ValueError("the partition is written for the cantilever")
+        if box.n % m != 0 or m < 2:
+            raise ValueError("need n % m == 0 and m >= 2")
+        self.box, self.m, self.E, self.nu = box, m, E, nu
+        self.mesh = _Dofs(box)
+        self.Px, self.Py, self.Pz = box.nx // m, box.ny // m, box.nz // m
+        self.nsub = self.Px * self.Py * self.Pz
+        ml = m + 1
+        lc, lb, la = np.indices((ml, ml, ml)).reshape(3, -1)  # local node a + ml b + ml^2 c
+        vert = ((la == 0) | (la == m)) & ((lb == 0) | (lb == m)) & ((lc == 0) | (lc == m))
+        nodes = []
+        count = np.zeros(box.ijk.shape[0], dtype=np.int64)
+        for s in range(self.nsub):
+            sx, sy, sz = s % self.Px, (s // self.Px) % self.Py, s // (self.Px * self.Py)
+            nd = box.node(la + sx * m, lb + sy * m, lc + sz * m)
+            nodes.append(nd)
+            count[nd] += 1
+        self.mult = np.repeat(count, 3)  # per full dof
+        self.subs = []
+        for s in range(self.nsub):
+            nd = nodes[s]
+            clamped = box.fixed[nd]
+            corner_n = vert & ~clamped
+            delta_n = ~vert & ~clamped & (count[nd] >= 2)
+            local_n = ~vert & ~clamped & (count[nd] == 1)
+            rep = lambda mask: np.repeat(mask, 3)
+            full = (3 * nd[:, None] + np.arange(3)[None, :]).ravel()
+            self.subs.append({"nodes": nd, "full": full, "corner": rep(corner_n), "delta": rep(delta_n),
+                              "inter": rep(local_n)})
+        cset = np.unique(np.concatenate([sd["full"][sd["corner"]] for sd in self.subs]))
+        self.corner_full = cset
+        self.corner_id = {int(f): i for i, f in enumerate(cset)}
+        self.nC = cset.size
+        owners = {}
+        for s, sd in enumerate(self.subs):
+            for f in sd["full"][sd["delta"]]:
+                owners.setdefault(int(f), []).append(s)
+        self.mults = []
+        for f in sorted(owners):
+            ss = sorted(owners[f])
+            for a in range(len(ss)):
+                for b in range(a + 1, len(ss)):
+                    self.mults.append((f, ss[a], ss[b]))
+        self.nmu = len(self.mults)
+        for s, sd in enumerate(self.subs):
+            r = np.nonzero(sd["inter"] | sd["delta"])[0]
+            c = np.nonzero(sd["corner"])[0]
+            sd["r"], sd["c"], sd["delta_loc"] = r, c, np.nonzero(sd["delta"])[0]
+            pos = {int(l): i for i, l in enumerate(r)}
+            where = {int(f): i for i, f in enumerate(sd["full"])}
+            Br = np.zeros((self.nmu, r.size))
+            for k, (f, sa, sb) in enumerate(self.mults):
+                if s == sa or s == sb:
+                    Br[k, pos[where[f]]] = 1.0 if s == sa else -1.0
+            sd["Br"] = Br
+            Bc = np.zeros((c.size, self.nC))
+            for i, l in enumerate(c):
+                Bc[i, self.corner_id[int(sd["full"][l])]] = 1.0
+            sd["Bc"] = Bc
+
+    def local_matrices(self, alpha: float, shift: str = "imag"):
+        """Z^s = K^s + i alpha M^s (shift "imag") or K^s + alpha M^s ("real") of the
+        subdomain's elements over its local dofs, as dense rr, rc, cc blocks."""
+        m, ml = self.m, self.m + 1
+        Ke = elasticity_element(self.box.h, self.E, self.nu)
+        Me = mass_element(self.box.h)
+        Ze = Ke + (1j * alpha if shift == "imag" else alpha) * Me
+        Zloc = np.zeros((3 * ml ** 3, 3 * ml ** 3), dtype=np.complex128)
+        for ec in range(m):
+            for eb in range(m):
+                for ea in range(m):
+                    ln = [(ea + a) + ml * (eb + b) + ml * ml * (ec + c)
+                          for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+                    dofs = np.array([3 * l + k for l in ln for k in range(3)])
+                    Zloc[np.ix_(dofs, dofs)] += Ze
+        out = []
+        for sd in self.subs:
+            r, c = sd["r"], sd["c"]
+            out.append({"rr": Zloc[np.ix_(r, r)], "rc": Zloc[np.ix_(r, c)], "cc": Zloc[np.ix_(c, c)]})
+        return out
+
+    def split_rhs(self, f_free: np.ndarray):
+        """Per-subdomain remainder loads f_r^s = f / multiplicity, and global f_c."""
+        ffull = np.zeros(self.mesh.n_full, dtype=np.complex128)
+        ffull[self.mesh.free_full] = f_free
+        fr = []
+        for sd in self.subs:
+            fl = sd["full"][sd["r"]]
+            fr.append(ffull[fl] / self.mult[fl])
+        return fr, ffull[self.corner_full]

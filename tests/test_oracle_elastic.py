@@ -10,7 +10,7 @@ import pytest
 import scipy.sparse.linalg as spla
 
 from oracle import elastic as el
-from oracle import kkt, solve
+from oracle import feti, kkt, solve
 
 
 def _rigid_modes(h):
@@ -139,3 +139,54 @@ def test_range_space_equals_brute_force_kkt_on_the_cantilever():
         assert rel(o3["u"], o2["u"]) <= 1e-5, beta
         for o in (o1, o2, o3):
             assert kkt.rel_kkt(K, M, Kc, beta, ybar, None, o["y"], o["u"], o["lam"]) <= 1e-6
+
+
+def _interface_counts(box, m):
+    """Brute force over the grid nodes: corner dofs (unclamped subdomain vertices)
+    and fully redundant multipliers (C(k, 2) per component on every unclamped
+    non-vertex node shared by k >= 2 subdomains)."""
+    nC = nmu = 0
+    for k in range(box.nz + 1):
+        for j in range(box.ny + 1):
+            for i in range(1, box.nx + 1):
+                on = [i % m == 0, j % m == 0, k % m == 0]
+                share = [v % m == 0 and 0 < v < top for v, top in ((i, box.nx), (j, box.ny), (k, box.nz))]
+                mult = 2 ** sum(share)
+                if all(on):
+                    nC += 3
+                elif mult >= 2:
+                    nmu += 3 * mult * (mult - 1) // 2
+    return nC, nmu
+
+
+@pytest.mark.parametrize("n,m", [(2, 2), (4, 2), (4, 4)])
+def test_partition_counts_and_load_split(n, m):
+    box = el.Box(n)
+    dec = el.Decomposition(box, m)
+    assert (dec.nC, dec.nmu) == _interface_counts(box, m)
+    assert dec.nsub == (box.nx // m) * (box.ny // m) * (box.nz // m)
+    # the subdomain shares of a load add up to it (corners through f_c)
+    f = np.random.default_rng(3).standard_normal(box.n_dof)
+    fr, fc = dec.split_rhs(f)
+    back = np.zeros(dec.mesh.n_full)
+    for sd, x in zip(dec.subs, fr):
+        np.add.at(back, sd["full"][sd["r"]], x.real)
+    back[dec.corner_full] += fc.real
+    assert np.abs(back[dec.mesh.free_full] - f).max() <= 1e-14 * np.abs(f).max()
+
+
+@pytest.mark.parametrize("n,m", [(2, 2), (4, 2), (4, 4)])
+@pytest.mark.parametrize("beta", [1e-10, 1e-16])
+def test_elastic_fetidp_equals_direct_solve(n, m, beta):
+    """FETI-DP on the elasticity partition (dense interface solve) reproduces the
+    sparse direct solution of Z x = f (Sec. 5): a wrong sign, corner or
+    multiplier anywhere in the partition breaks it."""
+    box = el.Box(n)
+    dec = el.Decomposition(box, m)
+    A = el.assemble(box)
+    Z = solve.complex_factor(A["K"], A["M"], beta)
+    rng = np.random.default_rng(7)
+    f = rng.standard_normal(box.n_dof) + 1j * rng.standard_normal(box.n_dof)
+    x, _ = feti.fetidp_solve_dense(dec, beta ** -0.5, f)
+    ref = spla.spsolve(Z.tocsc(), f)
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
