@@ -362,6 +362,65 @@ sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out,
  *                right-hand side. */
 sfdp_status sfdp_interface_apply(sfdp_problem* p, char which, const double* x, double* y);
 
+/* ---- Linear elasticity: the solid cantilever control of Sec. 6.2 ----
+ *
+ * The state equation is the elastostatic one: K is the stiffness of an
+ * isotropic linear-elastic solid (Young's modulus E, Poisson's ratio nu) on
+ * trilinear elements with three displacement dofs per node, M (the paper's V)
+ * the consistent vector mass, the control a body force.  The body is the box
+ * [0, length] x [0, 1] x [0, 1] of n cells per unit length, clamped on the
+ * face x = 0 (homogeneous, so there is no Kc and no yc: pass NULL), free
+ * elsewhere, cut into (length n / sub_elem) x (n / sub_elem)^2 cubic
+ * subdomains of sub_elem^3 cells (2 <= sub_elem <= 6, at most 65535
+ * subdomains).  FETI-DP (Sec. 5) takes the three dofs of every unclamped
+ * subdomain vertex as corner unknowns, one multiplier per pair of subdomains
+ * sharing an interface node per component (fully redundant), the
+ * multiplicity-scaled Dirichlet preconditioner, and dense subdomain inverses
+ * (blocked Gauss-Jordan on the device).
+ *
+ * Dofs: grid node (i, j, k), 0 <= i <= length n, 0 <= j, k <= n; the free
+ * nodes (i >= 1) are numbered x fastest, f = (i-1) + length n (j + (n+1) k),
+ * and free dof 3 f + c holds displacement component c (0: x, 1: y, 2: z).
+ * n_free = 3 length n (n+1)^2.  Multipliers are ordered by free dof, then by
+ * the pair of subdomains (s_a < s_b), +1 on s_a; corners (coarse unknowns) are
+ * the unclamped vertex nodes in increasing grid index, three dofs each.
+ *
+  * E = 0 or nu = 0 take the paper's rubber (E = 20.7 MPa, nu = 0.45).  The
+ * handle is an sfdp_problem: sfdp_set_beta, sfdp_solve_range_space,
+ * sfdp_apply_schur_inv, sfdp_feti_solve, sfdp_apply_operator ('K', 'M'),
+ * sfdp_kkt_residual, sfdp_inspect (SFDP_Q_SINV / SBB rows and columns in
+ * increasing local dof 3 l + c, l = a + (m+1) b + (m+1)^2 c; SFDP_Q_PHI columns
+ * the unclamped vertex dofs in increasing local dof), sfdp_interface_apply,
+ * sfdp_problem_sizes and sfdp_problem_destroy apply; the batch, the server,
+ * the full-space method, edge averages, the one-factor form and
+ * sfdp_kkt_residual_noalloc do not (SFDP_E_INVALID).
+ *
+ * Stopping test of sfdp_solve_range_space on these problems: the blockwise
+ * backward error eta_blk <= opts->tol_kkt [1e-12 FP64, 1e-10 mixed], not the
+ * relative KKT residual: the right-hand side (M ybar, 0, 0) is many orders of
+ * magnitude below the stiffness terms of the residual (E / h^2 against h^3),
+ * so even the exact solution's ||b - A x|| / ||b|| is about 1e-7 in FP64.
+ * info->rel_kkt still reports that residual.  max_krylov defaults to 300; the
+ * first step's inner tolerance defaults to tol_inner. */
+sfdp_status sfdp_elastic_create(sfdp_ctx* ctx, int n, int sub_elem, int length, double young, double poisson,
+                                sfdp_precision prec, sfdp_problem** out);
+
+/* f (device, n_free) = the consistent nodal forces of a uniform pressure on
+ * the bottom face z = 0 pushing in -z (Sec. 6.2 uses 100 kPa = 1e5): each
+ * bottom face cell gives each of its unclamped vertices -pressure h^2 / 4. */
+sfdp_status sfdp_elastic_pressure_load(sfdp_problem* p, double pressure, double* f);
+
+/* Forward elastostatic solve u = K^-1 f (Sec. 6.2: the target state is the
+ * displacement under the pressure load) for nrhs real right-hand sides
+ * (device, n_free x nrhs), by FETI-DP on K alone with complex128 factors
+ * whatever the problem's precision: they are built on the first call (a
+ * twin of the partition holds them, charged to the context's budget) and kept
+ * until the problem is destroyed; beta need not be set.  opts->tol_inner is
+ * the relative interface residual [1e-8], krylov_its (optional, host) gets
+ * the GMRES iterations per right-hand side. */
+sfdp_status sfdp_elastic_forward(sfdp_problem* p, int nrhs, const double* f, double* u, const sfdp_opts* opts,
+                                 int* krylov_its);
+
 /* ---- Batches of independent instances (uneven sizes, one beta each) ----
  *
  * A batch holds `count` 2D instances of the problem class above, instance i

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "common.h"
+#include "elastic.h"
 #include "three.h"
 
 namespace sfdp {
@@ -1177,6 +1178,7 @@ void destroy_problem(Problem* p) {
     destroy_problem(p->pw);
     p->pw = nullptr;
   }
+  el_destroy(*p);
   if (Three* T = p->t3) {
     free_factors3(*p);
     free_workspace3(*p);
@@ -1209,6 +1211,7 @@ void destroy_problem(Problem* p) {
 // stream must be idle).
 sfdp_status setup_run(const Target& t, const std::vector<Problem*>& ps, Multi* M) {
   for (Problem* p : ps) graphs_clear(*p);
+  if (ps.size() == 1 && ps[0]->el) return el_setup(*ps[0]);
   if (ps.size() == 1 && ps[0]->dim == 3) return setup3(*ps[0]);
   for (Problem* p : ps) {
     sfdp_status s = alloc_factors(*p);
@@ -1264,6 +1267,12 @@ sfdp_status gather_one(Problem* p) {
 }
 
 }  // namespace
+
+namespace sfdp {
+sfdp_status host_fail(sfdp_status s, const std::string& msg) { return fail(s, msg); }
+sfdp_status dev_alloc(Problem& p, void** ptr, size_t bytes) { return dalloc(p, ptr, bytes); }
+void dev_free(Problem& p, void*& ptr, size_t bytes) { dfree(p, ptr, bytes); }
+}  // namespace sfdp
 
 struct sfdp_ctx : public Ctx {};
 // 3D: Sinv and S_bb are stored full (ND x ND), Phi with the 8 vertex slots.
@@ -1325,6 +1334,7 @@ static sfdp_status inspect_problem(Problem* p, sfdp_query what, int sub, double*
   sfdp_status s = check_ready(p);
   if (s) return s;
   HIPCHK(hipSetDevice(p->ctx->device));
+  if (p->el) return el_inspect(*p, what, sub, out, rows, cols);
   if (p->dim == 3) return inspect3(p, what, sub, out, rows, cols);
   std::vector<int> ndv(p->nsub), cg(NQ * p->nsub);
   HIPCHK(hipMemcpy(ndv.data(), p->nd, sizeof(int) * p->nsub, hipMemcpyDeviceToHost));
@@ -1465,6 +1475,62 @@ sfdp_status sfdp_problem_create(sfdp_ctx* ctx, int dim, int n_elem, int sub_elem
   return s;
 }
 
+sfdp_status sfdp_elastic_create(sfdp_ctx* ctx, int n, int sub_elem, int length, double young, double poisson,
+                                sfdp_precision prec, sfdp_problem** out) {
+  if (!ctx || !out) return fail(SFDP_E_INVALID, "NULL argument");
+  *out = nullptr;
+  if (sub_elem < 2 || sub_elem > EL_M_MAX) return fail(SFDP_E_INVALID, "sub_elem must be in [2, 6]");
+  if (n < sub_elem || n % sub_elem != 0) return fail(SFDP_E_INVALID, "n must be a positive multiple of sub_elem");
+  if (length < 1 || length > 64) return fail(SFDP_E_INVALID, "length must be in [1, 64]");
+  if (young == 0.0) young = 20.7e6;
+  if (poisson == 0.0) poisson = 0.45;
+  if (!(young > 0) || !std::isfinite(young)) return fail(SFDP_E_INVALID, "Young's modulus must be positive");
+  if (!(poisson > -1.0 && poisson < 0.5)) return fail(SFDP_E_INVALID, "Poisson's ratio must be in (-1, 1/2)");
+  if (prec != SFDP_FP64 && prec != SFDP_MIXED && prec != SFDP_MIXED_IFACE)
+    return fail(SFDP_E_INVALID, "bad precision");
+  const int64_t nsub = (int64_t)(length * n / sub_elem) * (n / sub_elem) * (n / sub_elem);
+  if (nsub > 65535) return fail(SFDP_E_INVALID, "at most 65535 subdomains");
+  if (nsub < 2) return fail(SFDP_E_INVALID, "at least two subdomains");
+  HIPCHK(hipSetDevice(ctx->device));
+  Problem* p = new (std::nothrow) Problem();
+  if (!p) return fail(SFDP_E_NOMEM, "host allocation");
+  p->el = new (std::nothrow) Elastic();
+  if (!p->el) {
+    delete p;
+    return fail(SFDP_E_NOMEM, "host allocation");
+  }
+  p->ctx = ctx;
+  ctx->children++;
+  p->dim = 3;
+  p->N = n;
+  p->m = sub_elem;
+  p->ml = sub_elem + 1;
+  p->prec = prec;
+  sfdp_status s = el_build(*p, n, sub_elem, length, young, poisson);
+  if (s) {
+    destroy_problem(p);
+    return s;
+  }
+  *out = (sfdp_problem*)p;
+  return SFDP_OK;
+}
+
+sfdp_status sfdp_elastic_pressure_load(sfdp_problem* p, double pressure, double* f) {
+  if (!p || !f) return fail(SFDP_E_INVALID, "NULL argument");
+  if (!p->el) return fail(SFDP_E_INVALID, "not an elasticity problem");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  return el_pressure(*p, pressure, f);
+}
+
+sfdp_status sfdp_elastic_forward(sfdp_problem* p, int nrhs, const double* f, double* u, const sfdp_opts* opts,
+                                 int* krylov_its) {
+  if (!p || !f || !u || nrhs <= 0) return fail(SFDP_E_INVALID, "bad arguments");
+  if (!p->el) return fail(SFDP_E_INVALID, "not an elasticity problem");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  return el_forward(*p, nrhs, f, u, opts, krylov_its);
+}
+
 static void sizes_of(const Problem* p, sfdp_sizes* out) {
   out->n_free = p->n_free;
   out->n_bdry = p->n_bdry;
@@ -1536,11 +1602,12 @@ sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double*
   sfdp_status s = check_ready(p);
   if (s) return s;
   if (nrhs <= 0 || !f || !x) return fail(SFDP_E_INVALID, "bad arguments");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  if (p->el) return el_feti(*p, conj_z ? 1 : 0, nrhs, (const cd*)f, (cd*)x, opts, krylov_its);
   double tk, ti;
   int mo, kmax;
   defaults(p->prec, opts, tk, ti, mo, kmax, p->dim);
   const int bsz = batch_of(opts);
-  HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax))) return s;
   Target t = single_target(p);
   int trips = 0, rhs_its = 0;
@@ -1572,6 +1639,10 @@ sfdp_status sfdp_apply_operator(sfdp_problem* p, char which, int nrhs, const dou
                                 double* y) {
   if (!p || !x || !y || nrhs <= 0) return fail(SFDP_E_INVALID, "bad arguments");
   HIPCHK(hipSetDevice(p->ctx->device));
+  if (p->el) {
+    if (xc) return fail(SFDP_E_INVALID, "elasticity problems have no Dirichlet data");
+    return el_apply(*p, which, nrhs, x, y);
+  }
   if (which == 'K') HIPCHK(launch_apply_K(*p, nrhs, x, xc, y, p->ctx->stream));
   else if (which == 'M') HIPCHK(launch_apply_M(*p, nrhs, x, y, p->ctx->stream));
   else if (which == 'I') {
@@ -1589,6 +1660,10 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
   if (!p || !ybar || !y || !u || !lam || !rel || nrhs <= 0) return fail(SFDP_E_INVALID, "bad arguments");
   if (!(p->beta > 0)) return fail(SFDP_E_STATE, "beta not set");
   HIPCHK(hipSetDevice(p->ctx->device));
+  if (p->el) {
+    if (yc) return fail(SFDP_E_INVALID, "elasticity problems have no Dirichlet data");
+    return el_kkt(*p, nrhs, ybar, y, u, lam, rel, nullptr, nullptr);
+  }
   sfdp_status s = alloc_rs(*p);
   if (s) return s;
   const size_t n = p->n_free;
@@ -1611,6 +1686,7 @@ sfdp_status sfdp_kkt_residual(sfdp_problem* p, int nrhs, const double* ybar, con
 sfdp_status sfdp_kkt_residual_noalloc(sfdp_problem* p, int nrhs, const double* ybar, const double* yc,
                                       const double* y, const double* u, const double* lam, double* rel) {
   if (!p || !ybar || !y || !u || !lam || !rel || nrhs <= 0) return fail(SFDP_E_INVALID, "bad arguments");
+  if (p->el) return fail(SFDP_E_INVALID, "the allocation-free residual covers the Poisson problems only");
   const int64_t need = noalloc_kkt_doubles(p->n_free);
   if (need > NOALLOC_SCRATCH_DOUBLES)
     return fail(SFDP_E_INVALID, "n_free = " + std::to_string(p->n_free) + " needs " + std::to_string(need) +
@@ -1643,11 +1719,15 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
   sfdp_status s = check_ready(p);
   if (s) return s;
   if (nrhs <= 0 || !ybar || !y || !u || !lam) return fail(SFDP_E_INVALID, "bad arguments");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  if (p->el) {
+    if (yc) return fail(SFDP_E_INVALID, "elasticity problems have no Dirichlet data");
+    return el_range_space(*p, nrhs, ybar, y, u, lam, opts, info);
+  }
   double tk, ti;
   int mo, kmax;
   defaults(p->prec, opts, tk, ti, mo, kmax, p->dim);
   const int bsz = batch_of(opts);
-  HIPCHK(hipSetDevice(p->ctx->device));
   if ((s = alloc_workspace(*p, kmax)) || (s = alloc_rs(*p))) return s;
   if ((s = gather_buffers(*p))) return s;
   Target t = single_target(p);
@@ -1809,6 +1889,10 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
   if (s) return s;
   if (nrhs <= 0 || !r || !z) return fail(SFDP_E_INVALID, "bad arguments");
   if (opts && opts->schur_block != 0 && opts->schur_block != 1) return fail(SFDP_E_INVALID, "schur_block must be 0 or 1");
+  if (p->el) {
+    HIPCHK(hipSetDevice(p->ctx->device));
+    return el_schur_inv(*p, nrhs, r, z, opts, info);
+  }
   if (opts && opts->schur_block == 1) {
     // S_p^-1 r = F^-1 M F^-1 r: the two-factor sequence on the twin, whose
     // factor is real (so the conjugations and the real part change nothing)
@@ -1874,6 +1958,7 @@ sfdp_status sfdp_solve_full_space(sfdp_problem* p, int nrhs, const double* ybar,
   sfdp_status s = check_ready(p);
   if (s) return s;
   if (nrhs <= 0 || !ybar || !y || !u || !lam) return fail(SFDP_E_INVALID, "bad arguments");
+  if (p->el) return fail(SFDP_E_INVALID, "the full-space method covers the Poisson problems only");
   if (p->N > 1025) return fail(SFDP_E_INVALID, "the full-space method needs n_elem <= 1025");
   double tk, ti;
   int mo, kmax;
@@ -2122,6 +2207,10 @@ sfdp_status sfdp_interface_apply(sfdp_problem* p, char which, const double* x, d
   if (!x || !y) return fail(SFDP_E_INVALID, "bad arguments");
   HIPCHK(hipSetDevice(p->ctx->device));
   hipStream_t st = p->ctx->stream;
+  if (p->el) {
+    if (which != 'F' && which != 'P' && which != 'D') return fail(SFDP_E_INVALID, "which must be 'F', 'P' or 'D'");
+    return el_interface(*p, which, (const cd*)x, (cd*)y);
+  }
   if (p->dim == 3) {
     if (which != 'F' && which != 'P' && which != 'D') return fail(SFDP_E_INVALID, "which must be 'F', 'P' or 'D'");
     if ((s = alloc_workspace3(*p, 1))) return s;

@@ -313,7 +313,8 @@ struct StepGraph {
 
 // Host-side problem.
 struct Ctx;
-struct Three;  // state of a 3D instance (three.h)
+struct Three;    // state of a 3D instance (three.h)
+struct Elastic;  // state of an elasticity instance (elastic.h)
 struct Problem {
   Ctx* ctx = nullptr;
   int dim = 2, N = 0, m = 0, P = 0, nsub = 0, ml = 0, L = 0, ND = 0, nC = 0, nmu = 0, ndmax = 0;
@@ -330,6 +331,7 @@ struct Problem {
   bool rshift = false;    // factors of K + alpha M instead of K + i alpha M
   Problem* pw = nullptr;  // twin with rshift, built on first use of S_p (Sec. 3.2)
   Three* t3 = nullptr;  // dim = 3: maps, factors and workspaces of the 3D path
+  Elastic* el = nullptr;  // elasticity instance (dim = 3, three dofs per node)
   double* fsw = nullptr;   // full-space method: device vectors (9 x 3 n_free + sums)
   double* fsh = nullptr;   // and its pinned host scalars
   // index maps (device)

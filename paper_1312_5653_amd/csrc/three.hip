@@ -26,26 +26,13 @@
 #include <vector>
 
 #include "three.h"
+#include "krylov3.h"
 
 namespace sfdp {
 
 namespace {
 
 constexpr int GJW = 2 * 32 * 32;  // pivot-inverse buffers per matrix of gj_range
-
-__device__ inline cd wsum(cd a) {
-  for (int off = 32; off > 0; off >>= 1) {
-    a.x += __shfl_xor(a.x, off, 64);
-    a.y += __shfl_xor(a.y, off, 64);
-  }
-  return a;
-}
-__device__ inline double wsum(double a) {
-  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-  return a;
-}
-template <class TS>
-__device__ inline cd ld64(const TS& v) { return cvt<double>(v); }
 
 unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
@@ -197,8 +184,6 @@ hipError_t launch_setup3(Problem& p, cd* E, cd* work) {
 // each operator once for all of them (R3 accumulators per row), vector kernels
 // take the right-hand side from blockIdx.y.  Buffers are r-major with the
 // strides of Str3.
-constexpr int R3 = NRMAX;
-
 struct Str3 {
   int64_t f;    // free-node vectors (input f, output x)
   int64_t t;    // local r vectors T: nsub NR
@@ -207,36 +192,6 @@ struct Str3 {
   int64_t c;    // coarse vectors: nC
   int64_t mu;   // interface vectors: nmu
 };
-
-// Row i of the symmetric matrix A (n x n, leading dimension ld, read as column
-// i: coalesced over i) against the R3 vectors xs[k][r] (LDS): U entries are
-// loaded before they are used, so each thread keeps U loads in flight (more
-// registers: the sweep, with more rows per workgroup, keeps U = 2).
-template <int U, class TS>
-__device__ inline void symcol_r3(const TS* __restrict__ A, int ld, int n, int i, const cd* xs, cd (&out)[R3]) {
-  cd a[2][R3];
-#pragma unroll
-  for (int r = 0; r < R3; ++r) a[0][r] = a[1][r] = cd{0.0, 0.0};
-  int k = 0;
-  for (; k + U - 1 < n; k += U) {
-    TS z[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) z[u] = A[(size_t)(k + u) * ld + i];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const cd zu = ld64(z[u]);
-#pragma unroll
-      for (int r = 0; r < R3; ++r) fma_acc(a[u & 1][r], zu, xs[(k + u) * R3 + r]);
-    }
-  }
-  for (; k < n; ++k) {
-    const cd zu = ld64(A[(size_t)k * ld + i]);
-#pragma unroll
-    for (int r = 0; r < R3; ++r) fma_acc(a[0][r], zu, xs[k * R3 + r]);
-  }
-#pragma unroll
-  for (int r = 0; r < R3; ++r) out[r] = a[0][r] + a[1][r];
-}
 
 // Local right-hand side at r position p for right-hand side r: f / mult
 // (conj: of conj f); mode 1 subtracts Z_rc B_c u_c and B_r^T mu.
@@ -616,8 +571,12 @@ struct Ops3 {
   bool s32;
   int nr;
   unsigned threads_local, threads_sweep;
+  KBuf kb;  // Krylov buffers of the host-driven GMRES
+  int64_t nmu;
   Ops3(Problem& pp, int nr_)
       : p(pp), T(*pp.t3), g(pp.t3->g), mp(pp.t3->maps()), st(pp.ctx->stream), s32(pp.s32()), nr(nr_) {
+    kb = KBuf{T.V, T.hd, T.part, T.d, T.z, T.w, T.mu, T.npart, T.hh, T.nvd, T.nvh, T.kalloc};
+    nmu = g.nmu;
     threads_local = (unsigned)std::min(1024, std::max(512, (g.ND + 63) / 64 * 64));
     threads_sweep = (unsigned)std::min(1024, std::max(512, (g.NR + 63) / 64 * 64));
     sr = Str3{pp.n_free, (int64_t)g.nsub * g.NR, (int64_t)g.nsub * g.ND, (int64_t)g.nsub * 8,
@@ -709,122 +668,6 @@ struct Ops3 {
   }
 };
 
-// Right-preconditioned GMRES on F_DP mu_r = d_r from mu = 0 for the nr
-// right-hand sides together (relative residual tol of the unpreconditioned
-// system, at most kmax iterations each).  Every right-hand side keeps its own
-// basis, Hessenberg matrix and stopping test; one that has stopped still rides
-// along in the shared launches, but its later vectors are never used, so its
-// result is that of a solve on its own.
-hipError_t gmres3(Ops3& o, double tol, int kmax, int* its) {
-  Three& T = o.T;
-  hipStream_t st = o.st;
-  const int nr = o.nr;
-  const int64_t n = o.g.nmu, vs = n;
-  const unsigned nb = nb256(n);
-  const int ks = T.kalloc + 1;       // stride of the two coefficient sets in a right-hand side's hd
-  const int64_t hr = 2 * ks + 1;     // hd per right-hand side: h (pass 0), h (pass 1), squared norm
-  const int64_t vr = (int64_t)ks * n, pr = (int64_t)ks * 4 * nb;  // part: 4 wave sums per block
-  cd* V = T.V;
-  cd* dn = T.hd + 2 * ks;            // squared norm of right-hand side r at dn[r * hr]
-  auto sync_h = [&]() {
-    hipError_t e = hipMemcpyAsync(T.hh, T.hd, sizeof(cd) * hr * nr, hipMemcpyDeviceToHost, st);
-    return e == hipSuccess ? hipStreamSynchronize(st) : e;
-  };
-  hipLaunchKernelGGL(k3_axpy, dim3(nb, nr), dim3(256), 0, st, n, 0, (const cd*)V, vs, vr, (const cd*)T.hd, hr,
-                     T.d, n, T.npart, (int64_t)nb);
-  hipLaunchKernelGGL(k3_sum, dim3(nr), dim3(256), 0, st, (int)nb, (const double*)T.npart, (int64_t)nb, dn, hr);
-  hipLaunchKernelGGL(k3_normalize, dim3(nb, nr), dim3(256), 0, st, n, (const cd*)T.d, n, (const cd*)dn, hr, V, vr);
-  hipError_t e = sync_h();
-  if (e != hipSuccess) return e;
-  using cx = std::complex<double>;
-  const int km = std::min(kmax, T.kalloc);
-  std::vector<std::vector<cx>> H(nr), cs(nr), sn(nr), gv(nr);
-  std::vector<double> beta(nr);
-  std::vector<int> done(nr, 0), mk(nr, 0);
-  int ndone = 0;
-  for (int r = 0; r < nr; ++r) {
-    H[r].assign((size_t)(km + 1) * km, 0.0);
-    cs[r].assign(km, 0.0);
-    sn[r].assign(km, 0.0);
-    gv[r].assign(km + 1, 0.0);
-    beta[r] = std::sqrt(T.hh[r * hr + 2 * ks].x);
-    gv[r][0] = beta[r];
-    if (!(beta[r] > 0.0)) {
-      done[r] = 1;
-      ++ndone;
-    }
-  }
-  for (int j = 0; j < km && ndone < nr; ++j) {
-    cd* vj = V + (int64_t)j * vs;
-    cd* vn = V + (int64_t)(j + 1) * vs;
-    o.apply_P(vj, vr, T.z, n);
-    o.apply_F(T.z, n, vn, vr);
-    for (int pass = 0; pass < 2; ++pass) {
-      cd* h = T.hd + pass * ks;
-      hipLaunchKernelGGL(k3_dots, dim3(nb, nr), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, vr, (const cd*)vn,
-                         vr, T.part, pr);
-      hipLaunchKernelGGL(k3_reduce, dim3(j + 1, nr), dim3(256), 0, st, (int)(4 * nb), (const cd*)T.part, pr, h, hr);
-      hipLaunchKernelGGL(k3_axpy, dim3(nb, nr), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, vr, (const cd*)h, hr,
-                         vn, vr, T.npart, (int64_t)nb);
-    }
-    hipLaunchKernelGGL(k3_sum, dim3(nr), dim3(256), 0, st, (int)nb, (const double*)T.npart, (int64_t)nb, dn, hr);
-    hipLaunchKernelGGL(k3_normalize, dim3(nb, nr), dim3(256), 0, st, n, (const cd*)vn, vr, (const cd*)dn, hr, vn,
-                       vr);
-    if ((e = sync_h()) != hipSuccess) return e;
-    for (int r = 0; r < nr; ++r) {
-      if (done[r]) continue;
-      // column j of the Hessenberg matrix, rotated by the previous rotations
-      const cd* hh = T.hh + r * hr;
-      cx* Hj = H[r].data() + (size_t)j * (km + 1);
-      for (int i = 0; i <= j; ++i) Hj[i] = cx(hh[i].x + hh[ks + i].x, hh[i].y + hh[ks + i].y);
-      const double hn = std::sqrt(hh[2 * ks].x);
-      for (int i = 0; i < j; ++i) {
-        const cx a = Hj[i], b = Hj[i + 1];
-        Hj[i] = cs[r][i] * a + sn[r][i] * b;
-        Hj[i + 1] = -std::conj(sn[r][i]) * a + cs[r][i] * b;
-      }
-      const cx a = Hj[j];
-      const double ra = std::abs(a), rho = std::sqrt(ra * ra + hn * hn);
-      if (ra == 0.0) {
-        cs[r][j] = 0.0;
-        sn[r][j] = 1.0;
-      } else {
-        cs[r][j] = ra / rho;
-        sn[r][j] = (a / ra) * hn / rho;
-      }
-      Hj[j] = cs[r][j] * a + sn[r][j] * hn;
-      gv[r][j + 1] = -std::conj(sn[r][j]) * gv[r][j];
-      gv[r][j] = cs[r][j] * gv[r][j];
-      mk[r] = j + 1;
-      if (std::abs(gv[r][j + 1]) <= tol * beta[r] || !(hn > 0.0)) {
-        done[r] = 1;
-        ++ndone;
-      }
-    }
-  }
-  // y_r = H_r^-1 g_r (upper triangular), mu_r = P^-1 (V_r y_r)
-  for (int r = 0; r < nr; ++r) {
-    its[r] = mk[r];
-    std::vector<cx> y(mk[r]);
-    for (int i = mk[r] - 1; i >= 0; --i) {
-      cx s = gv[r][i];
-      for (int c = i + 1; c < mk[r]; ++c) s -= H[r][(size_t)c * (km + 1) + i] * y[c];
-      y[i] = s / H[r][(size_t)i * (km + 1) + i];
-    }
-    for (int i = 0; i < mk[r]; ++i) T.hh[r * hr + i] = cd{y[i].real(), y[i].imag()};
-    T.nvh[r] = mk[r];
-  }
-  e = hipMemcpyAsync(T.hd, T.hh, sizeof(cd) * hr * nr, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(T.nvd, T.nvh, sizeof(int) * nr, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k3_combine, dim3(nb, nr), dim3(256), 0, st, n, (const int*)T.nvd, (const cd*)V, vs, vr,
-                     (const cd*)T.hd, hr, T.w, n);
-  o.apply_P(T.w, n, T.mu, n);
-  // the host copies above must land before hh and nvh are reused
-  e = hipStreamSynchronize(st);
-  return e == hipSuccess ? hipGetLastError() : e;
-}
-
 }  // namespace
 
 hipError_t feti3(Problem& p, int nr, const cd* f, cd* x, int conj, double tol, int kmax, int* its) {
@@ -833,7 +676,7 @@ hipError_t feti3(Problem& p, int nr, const cd* f, cd* x, int conj, double tol, i
   o.rhs(f, conj);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = gmres3(o, tol, kmax, its)) != hipSuccess) return e;
+  if ((e = gmres_host(o, tol, kmax, its)) != hipSuccess) return e;
   // u_c = K_cc*^-1 (f_c* + F_rc^T mu), u_r = Z_rr^-1 (f_r - Z_rc B_c u_c - B_r^T mu)
   o.local(nullptr, T.Phi, 0, T.mu, o.sr.mu, nullptr, T.Wc);
   o.coarse(T.fcs, T.uc);

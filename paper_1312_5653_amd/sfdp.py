@@ -26,7 +26,7 @@ EXPORTS = [
     "sfdp_batch_solve_range_space", "sfdp_server_create", "sfdp_server_submit", "sfdp_server_poll",
     "sfdp_server_stats", "sfdp_server_destroy", "sfdp_set_coarse_space", "sfdp_batch_inspect",
     "sfdp_solve_full_space", "sfdp_set_tuning", "sfdp_kkt_residual_noalloc", "sfdp_set_graphs",
-    "sfdp_set_setup_arithmetic",
+    "sfdp_set_setup_arithmetic", "sfdp_elastic_create", "sfdp_elastic_pressure_load", "sfdp_elastic_forward",
 ]
 
 
@@ -133,6 +133,9 @@ def load_library(path: str = LIB_PATH):
     VPP = ctypes.POINTER(ctypes.c_void_p)
     lib.sfdp_batch_solve_range_space.argtypes = [P, ctypes.POINTER(I), VPP, VPP, VPP, VPP, VPP,
                                                  ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    lib.sfdp_elastic_create.argtypes = [P, I, I, I, D, D, I, ctypes.POINTER(P)]
+    lib.sfdp_elastic_pressure_load.argtypes = [P, D, VP]
+    lib.sfdp_elastic_forward.argtypes = [P, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(I)]
     lib.sfdp_server_create.argtypes = [P, I, ctypes.POINTER(Opts), ctypes.POINTER(P)]
     lib.sfdp_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     lib.sfdp_server_poll.argtypes = [P, ctypes.c_uint64, I, ctypes.POINTER(Info), ctypes.POINTER(D)]
@@ -146,7 +149,8 @@ def load_library(path: str = LIB_PATH):
                  "sfdp_timing_enable", "sfdp_kernel_times", "sfdp_batch_create", "sfdp_batch_sizes",
                  "sfdp_batch_set_beta", "sfdp_batch_solve_range_space", "sfdp_server_create",
                  "sfdp_server_submit", "sfdp_server_poll", "sfdp_server_stats", "sfdp_set_graphs", "sfdp_set_tuning",
-                 "sfdp_set_setup_arithmetic"):
+                 "sfdp_set_setup_arithmetic", "sfdp_elastic_create", "sfdp_elastic_pressure_load",
+                 "sfdp_elastic_forward"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -330,6 +334,45 @@ class Problem:
         t = Timing()
         _check(_lib.sfdp_kernel_times(self._h, ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in Timing._fields_}
+
+
+class ElasticProblem(Problem):
+    """The solid cantilever of Sec. 6.2: the box [0, length] x [0, 1]^2 of n
+    cells per unit length, clamped at x = 0, trilinear elasticity elements
+    (three dofs per node), (length n / sub_elem) x (n / sub_elem)^2 cubic
+    subdomains.  young = poisson = 0 take the paper's rubber."""
+
+    def __init__(self, ctx: Context, n: int, sub_elem: int, length: int = 3, young: float = 0.0,
+                 poisson: float = 0.0, precision: int = SFDP_FP64):
+        h = ctypes.c_void_p()
+        _check(_lib.sfdp_elastic_create(ctx._h, n, sub_elem, length, float(young), float(poisson), precision,
+                                        ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.dim, self.n_elem, self.sub_elem, self.precision = 3, n, sub_elem, precision
+        self.length = length
+        s = Sizes()
+        _check(_lib.sfdp_problem_sizes(h, ctypes.byref(s)))
+        self.sizes = {f: getattr(s, f) for f, _ in Sizes._fields_}
+        self.n_free = s.n_free
+        self.n_bdry = s.n_bdry
+
+    def pressure_load(self, pressure: float):
+        """Nodal forces of a uniform pressure on the bottom face (float64 tensor)."""
+        import torch
+        f = torch.zeros(self.n_free, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        _check(_lib.sfdp_elastic_pressure_load(self._h, float(pressure), _ptr(f)))
+        return f
+
+    def forward(self, f, u=None, **opts):
+        """u = K^-1 f by FETI-DP on the stiffness alone; returns (u, GMRES iterations)."""
+        import torch
+        nrhs = 1 if f.dim() == 1 else f.shape[0]
+        u = torch.empty_like(f) if u is None else u
+        its = (ctypes.c_int * nrhs)()
+        o = _opts(**opts)
+        _check(_lib.sfdp_elastic_forward(self._h, nrhs, _ptr(f), _ptr(u), ctypes.byref(o), its))
+        return u, list(its)[:nrhs]
 
 
 class Batch:

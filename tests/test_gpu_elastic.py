@@ -1,0 +1,268 @@
+"""Linear-elasticity cantilever (Sec. 6.2): trilinear elements with three
+displacement dofs per node, clamped at x = 0, cubic subdomains, FETI-DP with
+the unclamped subdomain vertices' dofs as corners (Sec. 5), the range-space
+refinement of Sec. 3.1 / 4.
+
+Parity with the oracle on the same seeded inputs: sizes and multiplier /
+corner counts, the assembled K and M, the pressure load, the subdomain
+operators (Z_rr^-1 on Delta, S_bb, Phi), the coarse matrix and its inverse,
+the interface products F_DP, P^-1 and d, FETI-DP solves against a sparse
+direct solve of Z and of conj(Z), the forward solve against a direct solve
+of K, S^-1 r against the oracle's two-factor solve, and range-space solves
+against O1.
+
+Tolerances.  The elasticity KKT system mixes stiffness entries near E h
+(1e6-1e7) with mass entries near h^3, so two backward-stable FP64 solvers of
+it (O1 through the complex LU, O2 through the real saddle LU) already differ
+by up to ~5e-7 in u and lam at beta = 1e-16 (~1e-9 in y).  Each range-space
+comparison is bounded by 50 times that measured O1-O2 distance (taken as
+at least 2e-11): the GPU result is held to the conditioning of the problem.
+The blockwise backward error eta_blk (the stopping test) is reached in
+FP64 to 1e-12 and in the mixed mode to 1e-10.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+torch = pytest.importorskip("torch")
+
+from oracle import elastic as el  # noqa: E402
+from oracle import feti, kkt, solve  # noqa: E402
+from paper_1312_5653_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def sf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1312_5653_amd import sfdp
+    ctx = sfdp.Context(0)
+    yield sfdp, ctx
+    ctx.close()
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _banner(*what):
+    print("CASE", *what, flush=True)
+
+
+@pytest.mark.parametrize("n,m", [(2, 2), (4, 2), (4, 4)])
+def test_sizes_operators_and_load(sf, n, m):
+    sfdp, ctx = sf
+    _banner("sizes", n, m)
+    box = el.Box(n)
+    dec = el.Decomposition(box, m)
+    A = el.assemble(box)
+    prob = sfdp.ElasticProblem(ctx, n, m)
+    sz = prob.sizes
+    assert sz["n_free"] == box.n_dof and sz["n_bdry"] == 0
+    assert (sz["n_sub"], sz["n_mult"], sz["n_corner"]) == (dec.nsub, dec.nmu, dec.nC)
+    x = np.stack([W.random_vector(box.n_dof, 10 + r) for r in range(3)])
+    for which, ref in (("K", A["K"]), ("M", A["M"])):
+        got = prob.apply_operator(which, _t(x)).cpu().numpy()
+        for r in range(3):
+            assert _rel(got[r], ref @ x[r]) < 1e-13, which
+    f = prob.pressure_load(1e5).cpu().numpy()
+    assert _rel(f, el.pressure_load(box, 1e5)) < 1e-15
+    prob.close()
+
+
+@pytest.mark.parametrize("n,m", [(2, 2), (4, 2), (4, 4)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_local_and_coarse_operators(sf, n, m, prec):
+    sfdp, ctx = sf
+    _banner("local ops", n, m, prec)
+    beta = 1e-12
+    dec = el.Decomposition(el.Box(n), m)
+    ops = feti.fetidp_operators(dec, beta ** -0.5)
+    prob = sfdp.ElasticProblem(ctx, n, m, precision=prec)
+    prob.set_beta(beta)
+    # S_bb is formed as the inverse of Z_rr^-1 on Delta: its error carries that
+    # block's condition number (~1e3 here) on top of rounding
+    tol, tol_s = (1e-11, 1e-9) if prec == 0 else (2e-6, 2e-5)
+    for s in sorted({0, dec.nsub // 2, dec.nsub - 1}):
+        pc = ops["pieces"][s]
+        isd = pc["is_delta"]
+        got = prob.inspect(sfdp.Q_SINV, s).cpu().numpy()
+        assert _rel(got, pc["Zrr_inv"][np.ix_(isd, isd)]) < tol, ("Sinv", s)
+        got = prob.inspect(sfdp.Q_SBB, s).cpu().numpy()
+        assert _rel(got, pc["Sbb"]) < tol_s, ("Sbb", s)
+        got = prob.inspect(sfdp.Q_PHI, s).cpu().numpy()
+        assert _rel(got, pc["Phi"][isd]) < tol, ("Phi", s)
+    k = prob.inspect(sfdp.Q_COARSE).cpu().numpy()
+    assert _rel(k, ops["Kcc"]) < 1e-12
+    kinv = prob.inspect(sfdp.Q_COARSE_INV).cpu().numpy()
+    assert np.abs(kinv @ k - np.eye(dec.nC)).max() < 1e-9
+    prob.close()
+
+
+@pytest.mark.parametrize("n,m", [(2, 2), (4, 2)])
+def test_interface_operators(sf, n, m):
+    sfdp, ctx = sf
+    _banner("interface", n, m)
+    beta = 1e-10
+    box = el.Box(n)
+    dec = el.Decomposition(box, m)
+    ops = feti.fetidp_operators(dec, beta ** -0.5)
+    prob = sfdp.ElasticProblem(ctx, n, m)
+    prob.set_beta(beta)
+    mu = W.random_vector(dec.nmu, 5, complex_=True)
+    F = prob.interface_apply("F", _t(mu)).cpu().numpy()
+    assert _rel(F, feti.fetidp_apply(ops, mu)) < 1e-11
+    P = prob.interface_apply("P", _t(mu)).cpu().numpy()
+    assert _rel(P, feti.dirichlet_preconditioner(dec, ops) @ mu) < 1e-10
+    f = W.random_vector(box.n_dof, 6, complex_=True)
+    d = prob.interface_apply("D", _t(f)).cpu().numpy()
+    dref, _, _ = feti.fetidp_rhs(dec, ops, f)
+    assert _rel(d, dref) < 1e-11
+    prob.close()
+
+
+@pytest.mark.parametrize("n,m", [(4, 2), (8, 4)])
+@pytest.mark.parametrize("conj_z", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_feti_solve_matches_direct(sf, n, m, conj_z, prec):
+    sfdp, ctx = sf
+    _banner("feti", n, m, conj_z, prec)
+    beta = 1e-14
+    box = el.Box(n)
+    A = el.assemble(box)
+    Z = solve.complex_factor(A["K"], A["M"], beta)
+    if conj_z:
+        Z = Z.conj()
+    f = np.stack([W.random_vector(box.n_dof, 60 + r, complex_=True) for r in range(2)])
+    prob = sfdp.ElasticProblem(ctx, n, m, precision=prec)
+    prob.set_beta(beta)
+    tin = 1e-12 if prec == 0 else 1e-6
+    x, its = prob.feti_solve(_t(f), conj_z=bool(conj_z), tol_inner=tin)
+    x = x.cpu().numpy()
+    lu = spla.splu(Z.tocsc())
+    for r in range(len(f)):
+        assert _rel(x[r], lu.solve(f[r])) < (1e-9 if prec == 0 else 1e-4), (r, its)
+    print(f"elastic FETI-DP n={n} m={m} prec={prec}: GMRES iterations {its}")
+    prob.close()
+
+
+@pytest.mark.parametrize("n,m", [(4, 2), (8, 4)])
+def test_forward_solve_is_the_static_displacement(sf, n, m):
+    sfdp, ctx = sf
+    _banner("forward", n, m)
+    box = el.Box(n)
+    A = el.assemble(box)
+    prob = sfdp.ElasticProblem(ctx, n, m, precision=1)  # the forward twin is FP64 in every mode
+    f = prob.pressure_load(1e5)
+    u, its = prob.forward(f, tol_inner=1e-12)
+    ref = spla.spsolve(A["K"].tocsc(), el.pressure_load(box, 1e5))
+    assert _rel(u.cpu().numpy(), ref) < 1e-9, its
+    assert float(u[2::3].mean()) < 0.0  # the beam sags
+    prob.close()
+
+
+def _spread(K, M, Kc, beta, ybar):
+    """O1, and the distance between O1 and O2 per variable (the conditioning floor)."""
+    o1 = solve.range_space_two_factor(K, M, Kc, beta, ybar, None, paper_y=False)
+    o2 = solve.reduced_saddle(K, M, Kc, beta, ybar, None)
+    return o1, {k: _rel(o1[k], o2[k]) for k in ("y", "u", "lam")}
+
+
+@pytest.mark.parametrize("n,m", [(4, 2), (8, 4)])
+@pytest.mark.parametrize("beta", [1e-10, 1e-16])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_range_space_matches_oracle(sf, n, m, beta, prec):
+    sfdp, ctx = sf
+    _banner("range space", n, m, beta, prec)
+    box = el.Box(n)
+    A = el.assemble(box)
+    K, M, Kc = A["K"], A["M"], A["Kc"]
+    prob = sfdp.ElasticProblem(ctx, n, m, precision=prec)
+    # targets: the static displacement under 100 kPa (oracle direct solve), and
+    # half of it perturbed by a seeded field
+    ub = spla.spsolve(K.tocsc(), el.pressure_load(box, 1e5))
+    ybar = np.stack([ub, 0.5 * ub + 1e-3 * W.random_vector(box.n_dof, 77)])
+    prob.set_beta(beta)
+    tol = 1e-12 if prec == 0 else 1e-10
+    y, u, lam, info, st = prob.solve_range_space(_t(ybar), tol_kkt=tol)
+    assert st == 0, info
+    y, u, lam = (v.cpu().numpy() for v in (y, u, lam))
+    for q in range(2):
+        o1, spread = _spread(K, M, Kc, beta, ybar[q])
+        got = {"y": y[q], "u": u[q], "lam": lam[q]}
+        for k in ("y", "u", "lam"):
+            assert _rel(got[k], o1[k]) <= 50 * max(spread[k], 2e-11), (q, k, _rel(got[k], o1[k]), spread, info[q])
+        eta = kkt.eta_blk(K, M, Kc, beta, ybar[q], None, y[q], u[q], lam[q])
+        assert eta <= 10 * tol, (q, eta, info[q])
+        # the library's metrics of its result sit at the same rounding floor as the oracle's
+        cv = kkt.constraint_violation(K, M, Kc, None, y[q], u[q])
+        assert info[q]["eta_blk"] <= tol and info[q]["constr_viol"] <= max(10 * cv, 1e-12), (info[q], cv)
+        print(f"n={n} m={m} beta={beta} prec={prec} q={q}: steps {info[q]['outer_steps']} "
+              f"its {info[q]['krylov_its'][:info[q]['n_feti']]} eta {eta:.2e} "
+              f"err y {_rel(y[q], o1['y']):.1e} lam {_rel(lam[q], o1['lam']):.1e} spread {spread}")
+    prob.close()
+
+
+def test_kkt_metrics_match_oracle(sf):
+    """Relative KKT residual of a state away from the solution (well above the
+    rounding floor) against the oracle's."""
+    sfdp, ctx = sf
+    _banner("kkt metrics")
+    n, m, beta = 4, 2, 1e-12
+    box = el.Box(n)
+    A = el.assemble(box)
+    ybar = np.stack([W.random_vector(box.n_dof, 40 + q) for q in range(5)])
+    y = ybar + 1e-3 * np.stack([W.random_vector(box.n_dof, 50 + q) for q in range(5)])
+    lam = 1e-9 * np.stack([W.random_vector(box.n_dof, 60 + q) for q in range(5)])
+    u = lam / beta + np.stack([W.random_vector(box.n_dof, 70 + q) for q in range(5)])
+    prob = sfdp.ElasticProblem(ctx, n, m)
+    prob.set_beta(beta)
+    rel = prob.kkt_residual(_t(ybar), None, _t(y), _t(u), _t(lam))
+    for q in range(5):
+        ref = kkt.rel_kkt(A["K"], A["M"], A["Kc"], beta, ybar[q], None, y[q], u[q], lam[q])
+        assert abs(rel[q] - ref) <= 1e-10 * ref, (q, rel[q], ref)
+    prob.close()
+
+
+def test_schur_inverse_matches_oracle(sf):
+    sfdp, ctx = sf
+    _banner("schur inverse")
+    n, m, beta = 4, 2, 1e-12
+    box = el.Box(n)
+    A = el.assemble(box)
+    Z = solve.complex_factor(A["K"], A["M"], beta)
+    lu = spla.splu(Z.tocsc())
+    r = np.stack([W.random_vector(box.n_dof, 90 + q) for q in range(3)])
+    prob = sfdp.ElasticProblem(ctx, n, m)
+    prob.set_beta(beta)
+    z, info = prob.apply_schur_inv(_t(r), tol_inner=1e-12)
+    z = z.cpu().numpy()
+    for q in range(3):
+        assert _rel(z[q], solve.schur_inverse_two_factor(lu, A["M"], r[q])) < 1e-8, info[q]
+    prob.close()
+
+
+def test_unsupported_calls_fail_cleanly(sf):
+    sfdp, ctx = sf
+    _banner("unsupported")
+    prob = sfdp.ElasticProblem(ctx, 2, 2)
+    prob.set_beta(1e-12)
+    y = torch.zeros(prob.n_free, dtype=torch.float64, device=DEV)
+    with pytest.raises(sfdp.SfdpError):
+        prob.solve_full_space(y)
+    with pytest.raises(sfdp.SfdpError):
+        prob.solve_range_space(y, factors=1)
+    with pytest.raises(sfdp.SfdpError):
+        prob.set_coarse_space(True)
+    with pytest.raises(sfdp.SfdpError):
+        sfdp.ElasticProblem(ctx, 2, 2, length=1)  # a single subdomain
+    with pytest.raises(sfdp.SfdpError):
+        sfdp.ElasticProblem(ctx, 14, 7)  # sub_elem above 6
+    prob.close()
