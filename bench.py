@@ -578,6 +578,106 @@ def run_c3(sfdp, torch, ctx, N, beta, steps, tol_kkt, oracle=None, m=8, B=4):
             "resident_bytes": sz["resident_bytes"]}
 
 
+def run_elastic(sfdp, torch, ctx, n, m, beta, steps, precision, B=4, length=3):
+    """The Sec. 6.2 solid cantilever: rubber (E = 20.7 MPa, nu = 0.45) on [0, 3] x [0, 1]^2,
+    h = 1/n, (3n/m) x (n/m)^2 cubic subdomains of m^3 cells, beta = 1e-16 (Table 5's phi).
+    Targets: the beam-theory deflection under 100 kPa scaled by 1, 3/4, 1/2, 1/4 with seeded
+    1e-3 noise on all but the first.  Also timed: the GPU forward solve of the pressure load
+    (the paper's way of making its target) and the set-up."""
+    import numpy as np
+    from paper_1312_5653_amd import workloads
+    p = sfdp.ElasticProblem(ctx, n, m, length=length, precision=precision)
+    try:
+        nf = p.n_free
+        f = p.pressure_load(1e5)
+        p.forward(f)  # builds the forward factors
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ub, fwd_its = p.forward(f)
+        torch.cuda.synchronize()
+        fwd_ms = (time.perf_counter() - t0) * 1e3
+        ybar = np.stack([c * workloads.cantilever_target(n, length, seed=j, noise=1e-3 if j else 0.0)
+                         for j, c in enumerate((1.0, 0.75, 0.5, 0.25)[:B])])
+        ybar_t = torch.tensor(ybar, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.set_beta(beta)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        y, u, lam = (torch.empty_like(ybar_t) for _ in range(3))
+        p.solve_range_space(ybar_t, None, y, u, lam)
+        lat, infos = [], []
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            _, _, _, info, st = p.solve_range_space(ybar_t, None, y, u, lam)
+            lat.append((time.perf_counter() - t0) * 1e3)
+            infos.extend(info)
+            if st != 0:
+                raise RuntimeError(f"elastic solve did not converge: {info}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_all
+        sz = p.refresh_sizes()
+        outs = [(y[r].cpu().numpy(), u[r].cpu().numpy(), lam[r].cpu().numpy()) for r in range(B)]
+        its = [i["krylov_its"][k] for i in infos for k in range(min(i["n_feti"], 16))]
+        lat.sort()
+        return {"workload": f"Sec. 6.2 rubber cantilever [0,{length}]x[0,1]^2, h=1/{n}, "
+                            f"{sz['n_sub']} subdomains of {m}^3 cells, beta={beta:g}, {B} beam-deflection "
+                            f"targets per step",
+                "precision": "fp64" if precision == sfdp.SFDP_FP64 else "mixed",
+                "dofs": nf, "n_sub": sz["n_sub"], "n_mult": sz["n_mult"], "n_corner": sz["n_corner"],
+                "resident_bytes": sz["resident_bytes"],
+                "solves_per_s": B * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+                "p50_ms": lat[len(lat) // 2], "setup_ms": setup_ms,
+                "forward_ms": fwd_ms, "forward_krylov_its": fwd_its[0],
+                "refinement_steps": statistics.mean(i["outer_steps"] for i in infos),
+                "krylov_its_per_factor_solve": statistics.mean(its), "krylov_its_max": max(its),
+                "max_eta_blk": max(i["eta_blk"] for i in infos),
+                "max_constr_viol": max(i["constr_viol"] for i in infos),
+                "max_rel_kkt": max(i["rel_kkt"] for i in infos),
+                "outs": outs, "ybar": ybar, "n": n, "m": m, "beta": beta, "length": length}
+    finally:
+        p.close()
+
+
+def elastic_oracle(r, o1_max_dofs=6000, budget_s=10.0):
+    """Oracle leg of an elasticity line: the oracle's blockwise backward error of the GPU
+    results (its own K and M), the forward error against O1 where the oracle's sparse LU
+    is quick (h = 1/8), and the O1 timing there."""
+    import scipy.sparse.linalg as spla
+    from oracle import elastic as el
+    from oracle import kkt, solve
+    box = el.Box(r["n"], r["length"])
+    A = el.assemble(box)
+    K, M, Kc = A["K"], A["M"], A["Kc"]
+    etas = [kkt.eta_blk(K, M, Kc, r["beta"], yb, None, *o) for yb, o in zip(r["ybar"], r["outs"])]
+    res = {"oracle_eta_blk_max": max(etas)}
+    if box.n_dof <= o1_max_dofs:
+        t0 = time.perf_counter()
+        lu = spla.splu(solve.complex_factor(K, M, r["beta"]))
+        t_factor = time.perf_counter() - t0
+        refs, times = [], []
+        for yb in r["ybar"]:
+            t0 = time.perf_counter()
+            refs.append(solve.range_space_two_factor(K, M, Kc, r["beta"], yb, None, lu=lu, paper_y=False))
+            times.append(time.perf_counter() - t0)
+        res["fwd_err_vs_oracle"] = {"O1": fwd_err(r["outs"], refs)}
+        # the conditioning floor: O1 against the real saddle-point solve O2
+        o2 = solve.reduced_saddle(K, M, Kc, r["beta"], r["ybar"][0], None)
+        res["o1_vs_o2"] = fwd_err([(o2["y"], o2["u"], o2["lam"])], refs[:1])
+        t_solve = statistics.median(times)
+        res["cpu_baseline"] = {"value": 1.0 / t_solve, "unit": "Schur solves/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{len(times)} two-factor solves with one resident SuperLU factor of Z "
+                                         f"({box.n_dof} dofs); the factorization took {t_factor:.2f} s",
+                               "factor_s": t_factor, "solve_s": t_solve}
+    else:
+        res["fwd_err_vs_oracle"] = None
+        res["note"] = ("the oracle's SuperLU factor of Z takes about 2 minutes at 41,616 dofs: the result is "
+                       "checked by the oracle's backward error only")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -615,6 +715,9 @@ def main():
     ap.add_argument("--serving-only", action="store_true",
                     help="only the served stream and its load points")
     ap.add_argument("--c3-steps", type=int, default=5)
+    ap.add_argument("--elastic", type=str, default="8,16", metavar="N,...",
+                    help="cantilever meshes (cells per metre) of the Sec. 6.2 lines; empty to skip")
+    ap.add_argument("--elastic-only", action="store_true", help="only the elasticity lines")
     ap.add_argument("--schur-betas", type=str, default="1e-2,1e-4,1e-6,1e-8,1e-10",
                     help="betas of the S versus S_p full-space comparison ('' to skip)")
     ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB"),
@@ -653,6 +756,18 @@ def main():
     tol_kkt = 1e-8
     if args.c3_only:
         print(json.dumps({"c3_3d": run_c3(sfdp, torch, ctx, args.c3, beta, args.c3_steps, tol_kkt)}), flush=True)
+        ctx.close()
+        return
+    if args.elastic_only:
+        out = {}
+        for ne in [int(x) for x in args.elastic.split(",") if x]:
+            for pn, pv in (("mixed", sfdp.SFDP_MIXED), ("fp64", sfdp.SFDP_FP64)):
+                r = run_elastic(sfdp, torch, ctx, ne, 4, 1e-16, 5, pv)
+                if not args.no_cpu:
+                    r.update(elastic_oracle(r))
+                out[f"elastic_h{ne}_{pn}"] = {k: v for k, v in r.items() if k not in ("outs", "ybar")}
+                print(json.dumps(out[f"elastic_h{ne}_{pn}"]), file=sys.stderr, flush=True)
+        print(json.dumps(out), flush=True)
         ctx.close()
         return
     if args.serving_only:
@@ -807,6 +922,11 @@ def main():
                                                      args.serve_window, 5.0, 0, tol_kkt, args.serve_budget_gb)
     if args.c3 > 0 and not args.headline_only:
         out["c3_3d"] = run_c3(sfdp, torch, ctx, args.c3, beta, args.c3_steps, tol_kkt, oracle)
+    el_lines = {}
+    if args.elastic and not args.headline_only:
+        for ne in [int(x) for x in args.elastic.split(",") if x]:
+            for pn, pv in (("mixed", sfdp.SFDP_MIXED), ("fp64", sfdp.SFDP_FP64)):
+                el_lines[f"elastic_h{ne}_{pn}"] = run_elastic(sfdp, torch, ctx, ne, 4, 1e-16, 5, pv)
     if args.schur_betas and not args.headline_only:
         betas = [float(b) for b in args.schur_betas.split(",")]
         out["schur_block_comparison"] = run_schur_blocks(sfdp, torch, ctx, precs[0][1], N, m, betas, ybar_t,
@@ -830,6 +950,10 @@ def main():
                 "O1": fwd_err([inst_outs[j] for j in sorted(sols)], [dict(zip(("y", "u", "lam"), sols[j]))
                                                                     for j in sorted(sols)]),
                 "instances_compared": len(sols)}
+    for k, r in el_lines.items():
+        if oracle is not None:
+            r.update(elastic_oracle(r))
+        out[k] = {kk: v for kk, v in r.items() if kk not in ("outs", "ybar")}
     print(json.dumps(out), flush=True)
 
 

@@ -131,3 +131,27 @@ def c5_requests(count: int, seed: int, mean_gap_ms: float = 5.0, sub_elem: int =
         out.append({"arrival_ms": t, "dim": dim, "N": N, "m": m, "full_space": full_space, "beta": beta,
                     "nrhs": nrhs, "seed": seed * 100003 + j})
     return out
+
+
+def cantilever_target(n: int, length: int = 3, seed: int = 0, young: float = 20.7e6, pressure: float = 1e5,
+                      noise: float = 0.0):
+    """Target displacement of the Sec. 6.2 cantilever shape, without any solve:
+    at every free node (dof 3 f + c, free nodes x fastest over i = 1..length n,
+    j, k = 0..n, h = 1 / n) the z component is the Euler-Bernoulli deflection of a
+    clamped beam of length L, unit square section (I = 1/12) under the line load
+    q = pressure x 1 m,
+        w(x) = -q x^2 (6 L^2 - 4 L x + x^2) / (24 E I),
+    (0.59 m at the tip for the paper's rubber and 100 kPa), x and y components
+    zero, plus `noise` times max |w| times seeded N(0, 1) values on every dof."""
+    L = float(length)
+    nx = length * n
+    i = np.arange(1, nx + 1)
+    x = i / n
+    w = -pressure * x ** 2 * (6 * L * L - 4 * L * x + x * x) / (24.0 * young / 12.0)
+    nodes = (n + 1) * (n + 1) * nx
+    y = np.zeros((nodes, 3))
+    y[:, 2] = np.tile(w, (n + 1) * (n + 1))  # x fastest: i varies first
+    y = y.ravel()
+    if noise:
+        y = y + noise * np.abs(w).max() * np.random.default_rng(seed).standard_normal(y.size)
+    return y
