@@ -445,7 +445,7 @@ sfdp_status ensure_ws(Problem& p, Elastic& el, int kmax) {
 // range-space vectors (NRMAX copies) and the partial-sum buffers
 sfdp_status ensure_rs(Problem& p, Elastic& el) {
   if (el.r1) return SFDP_OK;
-  const size_t R = NRMAX, n = el.g.n_free, nb = (n + 255) / 256;
+  const size_t R = NRMAX, n = el.g.n_free, nb = (n + 15) / 16;  // workgroups of the KKT kernel (16 rows each)
   List& o = el.owned;
   sfdp_status s;
   if ((s = take(p, o, &el.r1, R * n)) || (s = take(p, o, &el.r3, R * n)) || (s = take(p, o, &el.c1, R * n)) ||

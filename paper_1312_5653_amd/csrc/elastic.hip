@@ -307,69 +307,109 @@ __global__ void __launch_bounds__(1024) kel_sweep(GeoE g, MapsE mp, StrE st, int
   }
 }
 
-// Interface product on one subdomain for nr right-hand sides: xs = B_r^T x on
+// Interface product of one subdomain for nr right-hand sides: xs = B_r^T x on
 // its Delta dofs (scaled by 1 / multiplicity when `scale`), Y_s = Mat xs,
-// Wc_s = Phi^T xs; Mat is read once for all of them.
+// Wc_s = Phi^T xs.  Workgroup (s, y): for y < nsl, rows [64 y, 64 y + 64) of
+// Y_s, each row split over the four waves by column (k = wave mod 4) and the
+// partial sums added through LDS, so a subdomain's block streams through
+// several workgroups at once; y = nsl computes Wc_s.  Every workgroup gathers
+// xs for the whole subdomain (a few KB from L2).
 template <class TS, int U>
-__global__ void __launch_bounds__(1024) kel_local(GeoE g, MapsE mp, StrE st, int nr, const TS* __restrict__ Mat,
-                                                  const TS* __restrict__ Phi, int scale, const cd* x, int64_t xr,
-                                                  cd* Y, cd* Wc) {
+__global__ void __launch_bounds__(256) kel_local(GeoE g, MapsE mp, StrE st, int nr, int nsl,
+                                                 const TS* __restrict__ Mat, const TS* __restrict__ Phi, int scale,
+                                                 const cd* x, int64_t xr, cd* Y, cd* Wc) {
   extern __shared__ cd xs[];  // [ND][R3]
-  const int s = blockIdx.x, ND = g.ND, nd = mp.nds[s];
-  for (int i = threadIdx.x; i < ND; i += blockDim.x) {
+  __shared__ cd red[3][64][R3];
+  const int s = blockIdx.x, sl = blockIdx.y, ND = g.ND, nd = mp.nds[s];
+  const int i0 = sl * 64;
+  if (sl < nsl && i0 >= nd) return;  // rows beyond this subdomain's Delta count
+  for (int i = threadIdx.x; i < nd; i += blockDim.x) {
     cd v[R3];
 #pragma unroll
     for (int r = 0; r < R3; ++r) v[r] = cd{0.0, 0.0};
-    if (i < nd) {
-      const size_t base = ((size_t)s * ND + i) * 3;
-      for (int j = 0; j < 3; ++j) {
-        const int k = mp.dmu[base + j];
-        if (k < 0) continue;
-        const double sg = mp.dsg[base + j];
+    const size_t base = ((size_t)s * ND + i) * 3;
+    for (int j = 0; j < 3; ++j) {
+      const int k = mp.dmu[base + j];
+      if (k < 0) continue;
+      const double sg = mp.dsg[base + j];
 #pragma unroll
-        for (int r = 0; r < R3; ++r)
-          if (r < nr) v[r] = v[r] + sg * x[r * xr + k];
-      }
-      if (scale) {
-        const double w = mp.dw[(size_t)s * ND + i];
+      for (int r = 0; r < R3; ++r)
+        if (r < nr) v[r] = v[r] + sg * x[r * xr + k];
+    }
+    if (scale) {
+      const double w = mp.dw[(size_t)s * ND + i];
 #pragma unroll
-        for (int r = 0; r < R3; ++r) v[r] = w * v[r];
-      }
+      for (int r = 0; r < R3; ++r) v[r] = w * v[r];
     }
 #pragma unroll
     for (int r = 0; r < R3; ++r) xs[i * R3 + r] = v[r];
   }
   __syncthreads();
-  if (Mat) {
-    const TS* A = Mat + (size_t)s * ND * ND;
-    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-      cd y[R3];
-      symcol_r3<U>(A, ND, nd, i, xs, y);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (sl < nsl) {
+    const int i = i0 + lane;
+    const bool row = i < nd;
+    const TS* A = Mat + (size_t)s * ND * ND + (row ? i : 0);
+    cd acc[R3];
 #pragma unroll
-      for (int r = 0; r < R3; ++r)
-        if (r < nr) Y[r * st.y + (size_t)s * ND + i] = y[r];
-    }
-  }
-  if (Phi) {
-    const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int q = wv; q < EQ; q += nw) {
-      cd acc[R3];
+    for (int r = 0; r < R3; ++r) acc[r] = cd{0.0, 0.0};
+    int k = wv;
+    for (; k + 4 * (U - 1) < nd; k += 4 * U) {
+      TS z[U];
 #pragma unroll
-      for (int r = 0; r < R3; ++r) acc[r] = cd{0.0, 0.0};
-      for (int i = lane; i < nd; i += 64) {
-        const cd ph = ld64(Phi[((size_t)s * ND + i) * EQ + q]);
+      for (int u = 0; u < U; ++u) z[u] = A[(size_t)(k + 4 * u) * ND];
 #pragma unroll
-        for (int r = 0; r < R3; ++r) fma_acc(acc[r], ph, xs[i * R3 + r]);
-      }
+      for (int u = 0; u < U; ++u) {
+        const cd zu = ld64(z[u]);
 #pragma unroll
-      for (int r = 0; r < R3; ++r) acc[r] = wsum(acc[r]);
-      if (lane == 0) {
-#pragma unroll
-        for (int r = 0; r < R3; ++r)
-          if (r < nr) Wc[r * st.w + (size_t)s * EQ + q] = acc[r];
+        for (int r = 0; r < R3; ++r) fma_acc(acc[r], zu, xs[(k + 4 * u) * R3 + r]);
       }
     }
+    for (; k < nd; k += 4) {
+      const cd zu = ld64(A[(size_t)k * ND]);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) fma_acc(acc[r], zu, xs[k * R3 + r]);
+    }
+    if (wv > 0) {
+#pragma unroll
+      for (int r = 0; r < R3; ++r) red[wv - 1][lane][r] = acc[r];
+    }
+    __syncthreads();
+    if (wv == 0 && row) {
+#pragma unroll
+      for (int r = 0; r < R3; ++r) {
+        const cd a = (acc[r] + red[0][lane][r]) + (red[1][lane][r] + red[2][lane][r]);
+        if (r < nr) Y[r * st.y + (size_t)s * ND + i] = a;
+      }
+    }
+    return;
   }
+  // corner terms: wave wv takes the six slots 6 wv .. 6 wv + 5, each lane a row
+  constexpr int QW = EQ / 4;
+  cd acc[QW][R3];
+#pragma unroll
+  for (int a = 0; a < QW; ++a)
+#pragma unroll
+    for (int r = 0; r < R3; ++r) acc[a][r] = cd{0.0, 0.0};
+  for (int i = lane; i < nd; i += 64) {
+    const TS* ph = Phi + ((size_t)s * ND + i) * EQ + QW * wv;
+    TS z[QW];
+#pragma unroll
+    for (int a = 0; a < QW; ++a) z[a] = ph[a];
+#pragma unroll
+    for (int a = 0; a < QW; ++a) {
+      const cd za = ld64(z[a]);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) fma_acc(acc[a][r], za, xs[i * R3 + r]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < QW; ++a)
+#pragma unroll
+    for (int r = 0; r < R3; ++r) {
+      const cd v = wsum(acc[a][r]);
+      if (lane == 0 && r < nr) Wc[r * st.w + (size_t)s * EQ + QW * wv + a] = v;
+    }
 }
 
 // out[c] = add[c] + sum of Wc over the corner's owners (fixed order); r = blockIdx.y
@@ -384,34 +424,49 @@ __global__ void kel_corner_sum(int nC, StrE st, const int* cown, const cd* Wc, c
   out[r * st.c + c] = acc;
 }
 
-// Per multiplier k with copies (s+, d+) and (s-, d-), right-hand side r = blockIdx.y:
+// Per multiplier k with copies (s+, d+) and (s-, d-), for every right-hand side r:
 //   out_k = sc_k (v+ - v-),  v = Y[s ystride + o_s + d] + phis (Phi_s[d] . u_c(B_c s))
 // with o_s = ni[s] when `at_ni` (Y holds whole r vectors), else 0, and
-// sc_k = 1 / multiplicity when `scale`, else 1.
+// sc_k = 1 / multiplicity when `scale`, else 1.  One thread per multiplier, so
+// the Phi rows are read once for all right-hand sides.
 template <class TS>
-__global__ void kel_scatter(GeoE g, MapsE mp, StrE st, const cd* Y, int64_t yr, int ystride, int at_ni,
+__global__ void kel_scatter(GeoE g, MapsE mp, StrE st, int nr, const cd* Y, int64_t yr, int ystride, int at_ni,
                             const TS* Phi, const cd* uc, double phis, int scale, cd* out, int64_t orr) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= g.nmu) return;
-  Y += r * yr;
-  uc += r * st.c;
-  cd acc{0.0, 0.0};
+  cd acc[R3];
+#pragma unroll
+  for (int r = 0; r < R3; ++r) acc[r] = cd{0.0, 0.0};
   for (int side = 0; side < 2; ++side) {
     const int own = mp.muown[2 * k + side];
     const int s = own / g.ND, d = own % g.ND;
-    cd v = Y[(size_t)s * ystride + (at_ni ? mp.ni[s] : 0) + d];
+    const size_t at = (size_t)s * ystride + (at_ni ? mp.ni[s] : 0) + d;
+    cd v[R3];
+#pragma unroll
+    for (int r = 0; r < R3; ++r) v[r] = r < nr ? Y[r * yr + at] : cd{0.0, 0.0};
     if (Phi) {
-      cd pc{0.0, 0.0};
+      cd pc[R3];
+#pragma unroll
+      for (int r = 0; r < R3; ++r) pc[r] = cd{0.0, 0.0};
+#pragma unroll 6
       for (int q = 0; q < EQ; ++q) {
         const int c = mp.cg[s * EQ + q];
-        if (c >= 0) fma_acc(pc, ld64(Phi[((size_t)s * g.ND + d) * EQ + q]), uc[c]);
+        if (c < 0) continue;
+        const cd ph = ld64(Phi[((size_t)s * g.ND + d) * EQ + q]);
+#pragma unroll
+        for (int r = 0; r < R3; ++r)
+          if (r < nr) fma_acc(pc[r], ph, uc[r * st.c + c]);
       }
-      v = v + phis * pc;
+#pragma unroll
+      for (int r = 0; r < R3; ++r) v[r] = v[r] + phis * pc[r];
     }
-    acc = side == 0 ? acc + v : acc - v;
+#pragma unroll
+    for (int r = 0; r < R3; ++r) acc[r] = side == 0 ? acc[r] + v[r] : acc[r] - v[r];
   }
-  if (scale) acc = (double)mp.muw[k] * acc;
-  out[r * orr + k] = acc;
+  const double sc = scale ? (double)mp.muw[k] : 1.0;
+#pragma unroll
+  for (int r = 0; r < R3; ++r)
+    if (r < nr) out[r * orr + k] = sc * acc[r];
 }
 
 // Displacements on the free dofs: corner dofs from u_c, every other dof the
@@ -449,20 +504,21 @@ struct OpsE {
   hipStream_t st;
   bool s32;
   int nr;
-  unsigned threads_local, threads_sweep;
+  unsigned threads_sweep;
   KBuf kb;
   int64_t nmu;
   OpsE(Elastic& e, bool s32_, const cd* Kinv_, int nr_, hipStream_t st_)
       : el(e), g(e.g), mp(e.maps()), sr(e.str()), Kinv(Kinv_), st(st_), s32(s32_), nr(nr_) {
     kb = e.kb;
     nmu = g.nmu;
-    threads_local = (unsigned)std::min(1024, std::max(256, (g.ND + 63) / 64 * 64));
     threads_sweep = (unsigned)std::min(1024, std::max(256, (g.NR + 63) / 64 * 64));
   }
+  // row slices of 64 for Mat (when given), and one more workgroup per subdomain for Phi
   template <class TS>
   void local_t(const void* Mat, const void* Phi, int scale, const cd* x, int64_t xr, cd* Y, cd* Wc) {
-    hipLaunchKernelGGL((kel_local<TS, 8>), dim3(g.nsub), dim3(threads_local), sizeof(cd) * g.ND * R3, st, g, mp, sr,
-                       nr, (const TS*)Mat, (const TS*)Phi, scale, x, xr, Y, Wc);
+    const int nsl = Mat ? (g.ND + 63) / 64 : 0;
+    hipLaunchKernelGGL((kel_local<TS, 4>), dim3(g.nsub, nsl + (Phi ? 1 : 0)), dim3(256), sizeof(cd) * g.ND * R3, st,
+                       g, mp, sr, nr, nsl, (const TS*)Mat, (const TS*)Phi, scale, x, xr, Y, Wc);
   }
   void local(const void* Mat, const void* Phi, int scale, const cd* x, int64_t xr, cd* Y, cd* Wc) {
     if (s32) local_t<cf>(Mat, Phi, scale, x, xr, Y, Wc);
@@ -470,12 +526,12 @@ struct OpsE {
   }
   void scatter(const cd* Y, int64_t yr, int ystride, int at_ni, bool phi, double phis, int scale, cd* out,
                int64_t orr) {
-    const dim3 grid(nbe(g.nmu), nr);
+    const dim3 grid(nbe(g.nmu));
     if (s32)
-      hipLaunchKernelGGL(kel_scatter<cf>, grid, dim3(256), 0, st, g, mp, sr, Y, yr, ystride, at_ni,
+      hipLaunchKernelGGL(kel_scatter<cf>, grid, dim3(256), 0, st, g, mp, sr, nr, Y, yr, ystride, at_ni,
                          phi ? (const cf*)el.Phi : (const cf*)nullptr, (const cd*)el.uc, phis, scale, out, orr);
     else
-      hipLaunchKernelGGL(kel_scatter<cd>, grid, dim3(256), 0, st, g, mp, sr, Y, yr, ystride, at_ni,
+      hipLaunchKernelGGL(kel_scatter<cd>, grid, dim3(256), 0, st, g, mp, sr, nr, Y, yr, ystride, at_ni,
                          phi ? (const cd*)el.Phi : (const cd*)nullptr, (const cd*)el.uc, phis, scale, out, orr);
   }
   template <class TS>
@@ -493,7 +549,7 @@ struct OpsE {
   void coarse(const cd* add, cd* out) {
     hipLaunchKernelGGL(kel_corner_sum, dim3(nbe(g.nC), nr), dim3(256), 0, st, g.nC, sr, mp.cown, (const cd*)el.Wc,
                        add, el.gc);
-    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4, nr), dim3(256), 0, st, g.nC, sr.c, Kinv, (const cd*)el.gc,
+    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4), dim3(256), 0, st, g.nC, sr.c, nr, Kinv, (const cd*)el.gc,
                        out);
   }
   // out = F_DP x
@@ -512,7 +568,7 @@ struct OpsE {
     sweep(f, conj, 0);
     hipLaunchKernelGGL(kel_corner_sum, dim3(nbe(g.nC), nr), dim3(256), 0, st, g.nC, sr, mp.cown, (const cd*)el.Wc,
                        (const cd*)nullptr, el.fcs);
-    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4, nr), dim3(256), 0, st, g.nC, sr.c, Kinv, (const cd*)el.fcs,
+    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4), dim3(256), 0, st, g.nC, sr.c, nr, Kinv, (const cd*)el.fcs,
                        el.uc);
     scatter(el.T, sr.t, g.NR, 1, true, -1.0, 0, el.kb.d, sr.mu);
   }
@@ -552,20 +608,31 @@ hipError_t el_launch_interface(Elastic& el, bool s32, const cd* Kinv, char which
 
 // ------------------------------------------------- KKT products (CSR, FP64) --
 
+// CSR rows are taken by 16 lanes each (16 rows per workgroup of 256), the
+// lanes striding over the row's entries so that neighbouring lanes read
+// neighbouring entries; the row's sums are folded over the 16 lanes.
+constexpr int EL_RL = 16;
+__device__ inline double fold16(double v) {
+  for (int off = EL_RL / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // y_r = A x_r for the rows of the CSR matrix (values a); r = blockIdx.y
-__global__ void kel_spmv(int64_t n, const int* rp, const int* ci, const double* a, const double* x, double* y) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int r = blockIdx.y;
+__global__ void __launch_bounds__(256) kel_spmv(int64_t n, const int* rp, const int* ci, const double* a,
+                                                const double* x, double* y) {
+  const int64_t t = (int64_t)blockIdx.x * (256 / EL_RL) + threadIdx.x / EL_RL;
+  const int sub = threadIdx.x % EL_RL, r = blockIdx.y;
   x += r * n;
   double acc = 0.0;
-  for (int j = rp[t]; j < rp[t + 1]; ++j) acc = fma(a[j], x[ci[j]], acc);
-  y[r * n + t] = acc;
+  if (t < n)
+    for (int j = rp[t] + sub; j < rp[t + 1]; j += EL_RL) acc = fma(a[j], x[ci[j]], acc);
+  acc = fold16(acc);
+  if (t < n && sub == 0) y[r * n + t] = acc;
 }
 
 hipError_t el_launch_spmv(const Elastic& el, char which, int nr, const double* x, double* y, hipStream_t st) {
   const int64_t n = el.g.n_free;
-  hipLaunchKernelGGL(kel_spmv, dim3(nbe(n), nr), dim3(256), 0, st, n, (const int*)el.rp, (const int*)el.ci,
+  hipLaunchKernelGGL(kel_spmv, dim3((unsigned)((n + 15) / 16), nr), dim3(256), 0, st, n, (const int*)el.rp, (const int*)el.ci,
                      (const double*)(which == 'K' ? el.Kv : el.Mv), x, y);
   return hipGetLastError();
 }
@@ -574,19 +641,19 @@ hipError_t el_launch_spmv(const Elastic& el, char which, int nr, const double* x
 // (y, u, lam) with right-hand side (M ybar, 0, 0),
 //   r1 = M ybar - M y - K lam,  r2 = -(beta M u - M lam),  r3 = -K y + M u,
 // and the squares of the EL_SUMS quantities summed over the workgroup into
-// part[(i nb + block) EL_SUMS + e].
+// part[(i nb + block) EL_SUMS + e].  16 lanes per row.
 __global__ void __launch_bounds__(256) kel_kkt(int64_t n, const int* rp, const int* ci, const double* Kv,
                                                const double* Mv, SlotE sl, double beta, int keep, double* r1,
                                                double* r3, double* part) {
   __shared__ double sh[EL_SUMS][4];
-  const int i = blockIdx.y;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, sub = threadIdx.x % EL_RL;
+  const int64_t t = (int64_t)blockIdx.x * (256 / EL_RL) + threadIdx.x / EL_RL;
   double w[EL_SUMS];
   for (int e = 0; e < EL_SUMS; ++e) w[e] = 0.0;
+  double Mb = 0, My = 0, aMy = 0, Kl = 0, aKl = 0, Mu = 0, aMu = 0, Ml = 0, aMl = 0, Ky = 0, aKy = 0;
   if (t < n) {
     const double *yb = sl.ybar[i], *y = sl.y[i], *u = sl.u[i], *lam = sl.lam[i];
-    double Mb = 0, My = 0, aMy = 0, Kl = 0, aKl = 0, Mu = 0, aMu = 0, Ml = 0, aMl = 0, Ky = 0, aKy = 0;
-    for (int j = rp[t]; j < rp[t + 1]; ++j) {
+    for (int j = rp[t] + sub; j < rp[t + 1]; j += EL_RL) {
       const int c = ci[j];
       const double k = Kv[j], m = Mv[j], ak = fabs(k), am = fabs(m);
       const double vb = yb[c], vy = y[c], vl = lam[c], vu = u[c];
@@ -602,6 +669,10 @@ __global__ void __launch_bounds__(256) kel_kkt(int64_t n, const int* rp, const i
       Ky = fma(k, vy, Ky);
       aKy = fma(ak, fabs(vy), aKy);
     }
+  }
+  Mb = fold16(Mb); My = fold16(My); aMy = fold16(aMy); Kl = fold16(Kl); aKl = fold16(aKl); Mu = fold16(Mu);
+  aMu = fold16(aMu); Ml = fold16(Ml); aMl = fold16(aMl); Ky = fold16(Ky); aKy = fold16(aKy);
+  if (t < n && sub == 0) {
     const double a1 = Mb - My - Kl, a2 = -(beta * Mu - Ml), a3 = -Ky + Mu;
     if (keep) {
       r1[i * n + t] = a1;
@@ -644,7 +715,7 @@ __global__ void __launch_bounds__(256) kel_sum(int nb, int ne, const double* par
 
 hipError_t el_launch_kkt(Elastic& el, int nr, const SlotE& sl, double beta, bool keep, hipStream_t st) {
   const int64_t n = el.g.n_free;
-  const unsigned nb = nbe(n);
+  const unsigned nb = (unsigned)((n + 15) / 16);
   hipLaunchKernelGGL(kel_kkt, dim3(nb, nr), dim3(256), 0, st, n, (const int*)el.rp, (const int*)el.ci,
                      (const double*)el.Kv, (const double*)el.Mv, sl, beta, keep ? 1 : 0, el.r1, el.r3, el.part);
   hipLaunchKernelGGL(kel_sum, dim3(nr), dim3(256), 0, st, (int)nb, EL_SUMS, (const double*)el.part, el.sums);
@@ -665,25 +736,27 @@ hipError_t el_launch_rhs1(Elastic& el, const ActE& a, double alpha, hipStream_t 
   return hipGetLastError();
 }
 
-// c3_c = conj(r1_i + M c2_c)
-__global__ void kel_rhs2(int64_t n, const int* rp, const int* ci, const double* Mv, ActE a, const double* r1,
-                         const cd* c2, cd* c3) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int c = blockIdx.y, i = a.idx[c];
+// c3_c = conj(r1_i + M c2_c); 16 lanes per row
+__global__ void __launch_bounds__(256) kel_rhs2(int64_t n, const int* rp, const int* ci, const double* Mv, ActE a,
+                                                const double* r1, const cd* c2, cd* c3) {
+  const int64_t t = (int64_t)blockIdx.x * (256 / EL_RL) + threadIdx.x / EL_RL;
+  const int sub = threadIdx.x % EL_RL, c = blockIdx.y, i = a.idx[c];
   const cd* w = c2 + c * n;
-  double re = r1[i * n + t], im = 0.0;
-  for (int j = rp[t]; j < rp[t + 1]; ++j) {
-    const cd v = w[ci[j]];
-    re = fma(Mv[j], v.x, re);
-    im = fma(Mv[j], v.y, im);
-  }
-  c3[c * n + t] = cd{re, -im};
+  double re = 0.0, im = 0.0;
+  if (t < n)
+    for (int j = rp[t] + sub; j < rp[t + 1]; j += EL_RL) {
+      const cd v = w[ci[j]];
+      re = fma(Mv[j], v.x, re);
+      im = fma(Mv[j], v.y, im);
+    }
+  re = fold16(re);
+  im = fold16(im);
+  if (t < n && sub == 0) c3[c * n + t] = cd{r1[i * n + t] + re, -im};
 }
 
 hipError_t el_launch_rhs2(Elastic& el, const ActE& a, hipStream_t st) {
   const int64_t n = el.g.n_free;
-  hipLaunchKernelGGL(kel_rhs2, dim3(nbe(n), a.n), dim3(256), 0, st, n, (const int*)el.rp, (const int*)el.ci,
+  hipLaunchKernelGGL(kel_rhs2, dim3((unsigned)((n + 15) / 16), a.n), dim3(256), 0, st, n, (const int*)el.rp, (const int*)el.ci,
                      (const double*)el.Mv, a, (const double*)el.r1, (const cd*)el.c2, el.c3);
   return hipGetLastError();
 }

@@ -82,8 +82,8 @@ __global__ void k3_sum(int nb, const double* npart, int64_t pr, cd* out, int64_t
 __global__ void k3_normalize(int64_t n, const cd* w, int64_t wr, const cd* nrm, int64_t hr, cd* v, int64_t vr);
 __global__ void k3_combine(int64_t n, const int* nv, const cd* V, int64_t vs, int64_t vr, const cd* y,
                            int64_t hr, cd* out, int64_t orr);
-// y_r = A x_r (n x n, FP64), one wave per row; r = blockIdx.y, vectors at + r * stride
-__global__ void k3_dense_mv(int n, int64_t stride, const cd* A, const cd* x, cd* y);
+// y_r = A x_r (n x n, FP64) for r < nr (vectors at + r * stride), A read once
+__global__ void k3_dense_mv(int n, int64_t stride, int nr, const cd* A, const cd* x, cd* y);
 
 // Ops: stream st, right-hand sides nr, interface length nmu, buffers kb, and
 // apply_P(x, xr, out, orr) / apply_F(x, xr, out, orr) (preconditioner and

@@ -359,15 +359,26 @@ __global__ void k3_corner_sum(int nC, Str3 st, const int* cown, const cd* Wc, co
   out[r * st.c + c] = acc;
 }
 
-// y_r = A x_r (n x n, FP64), one wave per row; r = blockIdx.y
-__global__ void k3_dense_mv(int n, int64_t stride, const cd* A, const cd* x, cd* y) {
+// y_r = A x_r (n x n, FP64) for the nr right-hand sides together (A read
+// once), one wave per row
+__global__ void k3_dense_mv(int n, int64_t stride, int nr, const cd* A, const cd* x, cd* y) {
   const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (row >= n) return;
-  x += blockIdx.y * stride;
-  cd acc{0.0, 0.0};
-  for (int j = lane; j < n; j += 64) fma_acc(acc, A[(size_t)row * n + j], x[j]);
-  acc = wsum(acc);
-  if (lane == 0) y[blockIdx.y * stride + row] = acc;
+  cd acc[R3];
+#pragma unroll
+  for (int r = 0; r < R3; ++r) acc[r] = cd{0.0, 0.0};
+  for (int j = lane; j < n; j += 64) {
+    const cd a = A[(size_t)row * n + j];
+#pragma unroll
+    for (int r = 0; r < R3; ++r)
+      if (r < nr) fma_acc(acc[r], a, x[r * stride + j]);
+  }
+#pragma unroll
+  for (int r = 0; r < R3; ++r) {
+    if (r >= nr) continue;
+    const cd v = wsum(acc[r]);
+    if (lane == 0) y[r * stride + row] = v;
+  }
 }
 
 // Per multiplier k with owners (s+, d+) and (s-, d-), right-hand side r = blockIdx.y:
@@ -643,7 +654,7 @@ struct Ops3 {
   void coarse(const cd* add, cd* out) {
     hipLaunchKernelGGL(k3_corner_sum, dim3(nb256(g.nC), nr), dim3(256), 0, st, g.nC, sr, (const int*)T.cown,
                        (const cd*)T.Wc, add, T.gc);
-    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4, nr), dim3(256), 0, st, g.nC, sr.c, (const cd*)p.Kinv,
+    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4), dim3(256), 0, st, g.nC, sr.c, nr, (const cd*)p.Kinv,
                        (const cd*)T.gc, out);
   }
   // out = F_DP x (x and out with right-hand-side strides xr, orr)
@@ -662,7 +673,7 @@ struct Ops3 {
     sweep(f, conj, 0);
     hipLaunchKernelGGL(k3_corner_sum, dim3(nb256(g.nC), nr), dim3(256), 0, st, g.nC, sr, (const int*)T.cown,
                        (const cd*)T.Wc, (const cd*)nullptr, T.fcs);
-    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4, nr), dim3(256), 0, st, g.nC, sr.c, (const cd*)p.Kinv,
+    hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4), dim3(256), 0, st, g.nC, sr.c, nr, (const cd*)p.Kinv,
                        (const cd*)T.fcs, T.uc);
     scatter(T.T, sr.t, g.NR, g.nI, true, -1.0, 0, T.d, sr.mu);
   }
