@@ -641,6 +641,38 @@ def run_elastic(sfdp, torch, ctx, n, m, beta, steps, precision, B=4, length=3):
         p.close()
 
 
+def run_elastic_betas(sfdp, torch, ctx, n, m, betas, tol_inner=1e-9, length=3):
+    """Table 4's experiment on this path: the FETI-DP iterations of the two factors
+    K - V/(i sqrt(phi)) = K + i alpha V (the paper's "-", the first solve of a step) and
+    K + V/(i sqrt(phi)) (its "+", the second, by conjugation) over phi = beta, for the
+    first refinement step of one range-space solve of the beam-deflection target,
+    FP64, inner tolerance 1e-9 (the paper's threshold); corners only (no RAUG)."""
+    import numpy as np
+    from paper_1312_5653_amd import workloads
+    p = sfdp.ElasticProblem(ctx, n, m, length=length, precision=sfdp.SFDP_FP64)
+    rows = []
+    try:
+        yb = torch.tensor(workloads.cantilever_target(n, length)[None, :], device="cuda:0")
+        for beta in betas:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.set_beta(beta)
+            torch.cuda.synchronize()
+            setup_ms = (time.perf_counter() - t0) * 1e3
+            t0 = time.perf_counter()
+            _, _, _, info, st = p.solve_range_space(yb, tol_inner=tol_inner)
+            torch.cuda.synchronize()
+            i = info[0]
+            rows.append({"phi": beta, "minus_its": i["krylov_its"][0], "plus_its": i["krylov_its"][1],
+                         "refinement_steps": i["outer_steps"], "solve_ms": (time.perf_counter() - t0) * 1e3,
+                         "setup_ms": setup_ms, "eta_blk": i["eta_blk"], "status": st})
+    finally:
+        p.close()
+    return {"workload": f"Sec. 6.2 rubber cantilever h=1/{n}, {(3 * n // m) * (n // m) ** 2} subdomains of {m}^3 "
+                        f"cells, FP64, inner tolerance {tol_inner:g}, first refinement step's two solves",
+            "rows": rows}
+
+
 def elastic_oracle(r, o1_max_dofs=6000, budget_s=10.0):
     """Oracle leg of an elasticity line: the oracle's blockwise backward error of the GPU
     results (its own K and M), the forward error against O1 where the oracle's sparse LU
@@ -673,8 +705,8 @@ def elastic_oracle(r, o1_max_dofs=6000, budget_s=10.0):
                                "factor_s": t_factor, "solve_s": t_solve}
     else:
         res["fwd_err_vs_oracle"] = None
-        res["note"] = ("the oracle's SuperLU factor of Z takes about 2 minutes at 41,616 dofs: the result is "
-                       "checked by the oracle's backward error only")
+        res["note"] = ("the oracle's SuperLU factor of Z takes about 2 minutes at 41,616 dofs and grows "
+                       "quickly beyond: the result is checked by the oracle's backward error only")
     return res
 
 
@@ -717,7 +749,11 @@ def main():
     ap.add_argument("--c3-steps", type=int, default=5)
     ap.add_argument("--elastic", type=str, default="8,16", metavar="N,...",
                     help="cantilever meshes (cells per metre) of the Sec. 6.2 lines; empty to skip")
+    ap.add_argument("--elastic-m6", type=int, default=24, metavar="N",
+                    help="cantilever mesh of the line with 6^3-cell subdomains (0 to skip)")
     ap.add_argument("--elastic-only", action="store_true", help="only the elasticity lines")
+    ap.add_argument("--elastic-betas", type=str, default="1e-7,1e-8,1e-9,1e-10,1e-11,1e-12,1e-13,1e-14,1e-15,1e-16,1e-17,1e-18",
+                    help="phi values of the Table 4 analogue (cantilever at h = 1/16); empty to skip")
     ap.add_argument("--schur-betas", type=str, default="1e-2,1e-4,1e-6,1e-8,1e-10",
                     help="betas of the S versus S_p full-space comparison ('' to skip)")
     ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB"),
@@ -767,6 +803,14 @@ def main():
                     r.update(elastic_oracle(r))
                 out[f"elastic_h{ne}_{pn}"] = {k: v for k, v in r.items() if k not in ("outs", "ybar")}
                 print(json.dumps(out[f"elastic_h{ne}_{pn}"]), file=sys.stderr, flush=True)
+        if args.elastic_m6:
+            r = run_elastic(sfdp, torch, ctx, args.elastic_m6, 6, 1e-16, 5, sfdp.SFDP_MIXED)
+            if not args.no_cpu:
+                r.update(elastic_oracle(r))
+            out[f"elastic_h{args.elastic_m6}_m6_mixed"] = {k: v for k, v in r.items() if k not in ("outs", "ybar")}
+        if args.elastic_betas:
+            out["elastic_phi_dependence"] = run_elastic_betas(sfdp, torch, ctx, 16, 4,
+                                                              [float(b) for b in args.elastic_betas.split(",")])
         print(json.dumps(out), flush=True)
         ctx.close()
         return
@@ -927,6 +971,12 @@ def main():
         for ne in [int(x) for x in args.elastic.split(",") if x]:
             for pn, pv in (("mixed", sfdp.SFDP_MIXED), ("fp64", sfdp.SFDP_FP64)):
                 el_lines[f"elastic_h{ne}_{pn}"] = run_elastic(sfdp, torch, ctx, ne, 4, 1e-16, 5, pv)
+        if args.elastic_m6:
+            el_lines[f"elastic_h{args.elastic_m6}_m6_mixed"] = run_elastic(sfdp, torch, ctx, args.elastic_m6, 6,
+                                                                          1e-16, 5, sfdp.SFDP_MIXED)
+        if args.elastic_betas:
+            out["elastic_phi_dependence"] = run_elastic_betas(sfdp, torch, ctx, 16, 4,
+                                                              [float(b) for b in args.elastic_betas.split(",")])
     if args.schur_betas and not args.headline_only:
         betas = [float(b) for b in args.schur_betas.split(",")]
         out["schur_block_comparison"] = run_schur_blocks(sfdp, torch, ctx, precs[0][1], N, m, betas, ybar_t,

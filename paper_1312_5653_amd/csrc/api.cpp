@@ -18,6 +18,7 @@
 
 #include "common.h"
 #include "elastic.h"
+#include "krylov3.h"
 #include "three.h"
 
 namespace sfdp {
@@ -614,10 +615,10 @@ void free_workspace3(Problem& p) {
   dfree(p, (void*&)T.hd, sizeof(cd) * R * (2 * kk + 1));
   dfree(p, (void*&)T.npart, sizeof(double) * R * nb);
   dfree(p, (void*&)T.nvd, sizeof(int) * R);
-  if (T.hh) hipHostFree(T.hh);
-  if (T.nvh) hipHostFree(T.nvh);
-  T.hh = nullptr;
-  T.nvh = nullptr;
+  dfree(p, (void*&)T.gs, sizeof(cd) * R * gs_len(T.kalloc));
+  dfree(p, (void*&)T.gi, sizeof(int) * GI_WORDS);
+  if (T.gih) hipHostFree(T.gih);
+  T.gih = nullptr;
   T.kalloc = 0;
 }
 sfdp_status alloc_workspace3(Problem& p, int kmax) {
@@ -638,10 +639,12 @@ sfdp_status alloc_workspace3(Problem& p, int kmax) {
   if ((s = dalloc(p, (void**)&T.V, sizeof(cd) * R * kk * nm)) ||
       (s = dalloc(p, (void**)&T.part, sizeof(cd) * R * kk * 4 * nb)) ||
       (s = dalloc(p, (void**)&T.hd, sizeof(cd) * R * (2 * kk + 1))) ||
-      (s = dalloc(p, (void**)&T.npart, sizeof(double) * R * nb)) || (s = dalloc(p, (void**)&T.nvd, sizeof(int) * R)))
+      (s = dalloc(p, (void**)&T.npart, sizeof(double) * R * nb)) || (s = dalloc(p, (void**)&T.nvd, sizeof(int) * R)) ||
+      (s = dalloc(p, (void**)&T.gs, sizeof(cd) * R * gs_len(kmax))) ||
+      (s = dalloc(p, (void**)&T.gi, sizeof(int) * GI_WORDS)))
     return s;
-  if (hipHostMalloc((void**)&T.hh, sizeof(cd) * R * (2 * kk + 1)) != hipSuccess ||
-      hipHostMalloc((void**)&T.nvh, sizeof(int) * R) != hipSuccess) {
+  if (hipHostMalloc((void**)&T.gih, sizeof(int) * GI_WORDS) != hipSuccess) {
+    T.gih = nullptr;
     return fail(SFDP_E_NOMEM, "pinned host allocation");
   }
   T.kalloc = kmax;

@@ -323,8 +323,7 @@ void free_twin(Problem& p, Elastic& el) {
 
 void free_krylov(Problem& p, Elastic& el) {
   release(p, el.kowned);
-  if (el.kb.hh) hipHostFree(el.kb.hh);
-  if (el.kb.nvh) hipHostFree(el.kb.nvh);
+  if (el.kb.gih) hipHostFree(el.kb.gih);
   el.kb = KBuf{};
 }
 
@@ -433,11 +432,13 @@ sfdp_status ensure_ws(Problem& p, Elastic& el, int kmax) {
   if ((s = take(p, o, &kb.V, R * kk * nm)) || (s = take(p, o, &kb.part, R * kk * 4 * nb)) ||
       (s = take(p, o, &kb.hd, R * (2 * kk + 1))) || (s = take(p, o, &kb.d, R * nm)) ||
       (s = take(p, o, &kb.z, R * nm)) || (s = take(p, o, &kb.w, R * nm)) || (s = take(p, o, &kb.mu, R * nm)) ||
-      (s = take(p, o, &kb.npart, R * nb)) || (s = take(p, o, &kb.nvd, R)))
+      (s = take(p, o, &kb.npart, R * nb)) || (s = take(p, o, &kb.nvd, R)) ||
+      (s = take(p, o, &kb.gs, R * gs_len(kmax))) || (s = take(p, o, &kb.gi, (size_t)GI_WORDS)))
     return s;
-  if (hipHostMalloc((void**)&kb.hh, sizeof(cd) * R * (2 * kk + 1)) != hipSuccess ||
-      hipHostMalloc((void**)&kb.nvh, sizeof(int) * R) != hipSuccess)
+  if (hipHostMalloc((void**)&kb.gih, sizeof(int) * GI_WORDS) != hipSuccess) {
+    kb.gih = nullptr;
     return host_fail(SFDP_E_NOMEM, "pinned host allocation");
+  }
   kb.kalloc = kmax;
   return SFDP_OK;
 }

@@ -6,8 +6,7 @@
 // synchronisation per iteration) for up to NRMAX right-hand sides in lockstep.
 // The Krylov vector kernels are defined in three.hip.
 #pragma once
-#include <complex>
-#include <vector>
+#include <algorithm>
 
 #include "common.h"
 
@@ -63,15 +62,24 @@ __device__ inline void symcol_r3(const TS* __restrict__ A, int ld, int n, int i,
 
 // Device buffers of one GMRES (NRMAX right-hand sides, kalloc + 1 basis vectors
 // each; hd per right-hand side: two coefficient sets and the squared norm,
-// 2 (kalloc + 1) + 1 entries; hh its pinned host copy; nvd / nvh the basis
-// lengths of the final combination).
+// 2 (kalloc + 1) + 1 entries; nvd the basis lengths of the final combination;
+// gs per right-hand side the Givens state (gs_len entries: Hessenberg columns,
+// rotations, rotated right-hand side, ||d||); gi per right-hand side its
+// activity and iteration count, then one word "any active"; gih a pinned copy
+// of gi).
 struct KBuf {
   cd *V, *hd, *part, *d, *z, *w, *mu;
   double* npart;
-  cd* hh;
-  int *nvd, *nvh;
+  int* nvd;
   int kalloc;
+  cd* gs;
+  int *gi, *gih;
 };
+
+// Givens state per right-hand side for kalloc K: H columns (K x (K + 1)), c
+// (K), s (K), g (K + 1), beta (1)
+__host__ __device__ inline int64_t gs_len(int K) { return (int64_t)(K + 1) * K + 3 * (int64_t)K + 2; }
+constexpr int GI_WORDS = 2 * NRMAX + 1;
 
 __global__ void k3_dots(int64_t n, int nv, const cd* V, int64_t vs, int64_t vr, const cd* w, int64_t wr, cd* part,
                         int64_t pr);
@@ -85,15 +93,33 @@ __global__ void k3_combine(int64_t n, const int* nv, const cd* V, int64_t vs, in
 // y_r = A x_r (n x n, FP64) for r < nr (vectors at + r * stride), A read once
 __global__ void k3_dense_mv(int n, int64_t stride, int nr, const cd* A, const cd* x, cd* y);
 
+// Givens steps on the device (three.hip).  init: beta_r = sqrt of the squared
+// norm in hd, g_r = (beta_r, 0, ...), active_r = beta_r > 0.  step j: column j of
+// H_r from the two Gram-Schmidt coefficient sets and the new vector's norm,
+// rotated by the previous rotations, a new rotation, g_r updated, and the
+// stopping test; gi[2 NRMAX] = any right-hand side still active.  solve: y_r =
+// H_r^-1 g_r over its_r columns into hd (the combination coefficients) and
+// nvd_r = its_r.  One thread per right-hand side.
+__global__ void k3_gm_init(int nr, int K, const cd* hd, int64_t hr, int ks, cd* gs, int* gi);
+__global__ void k3_gm_step(int nr, int K, int j, int kmax, double tol, const cd* hd, int64_t hr, int ks, cd* gs,
+                           int* gi);
+__global__ void k3_gm_solve(int nr, int K, const cd* gs, const int* gi, cd* hd, int64_t hr, int* nvd);
+
 // Ops: stream st, right-hand sides nr, interface length nmu, buffers kb, and
 // apply_P(x, xr, out, orr) / apply_F(x, xr, out, orr) (preconditioner and
 // interface operator on right-hand-side-strided vectors).
 // Right-preconditioned GMRES on F_DP mu_r = d_r from mu = 0 for the nr
 // right-hand sides together (relative residual tol of the unpreconditioned
 // system, at most kmax iterations each).  Every right-hand side keeps its own
-// basis, Hessenberg matrix and stopping test; one that has stopped still rides
-// along in the shared launches, but its later vectors are never used, so its
-// result is that of a solve on its own.
+// basis, Hessenberg matrix and stopping test, all on the device: the host
+// enqueues GM_BATCH iterations at a time and reads back only the activity
+// words between batches, so it does not wait for the GPU in every iteration.
+// A right-hand side that has stopped rides along in the shared launches, but
+// its later vectors are never used, so its result is that of a solve on its
+// own; iterations enqueued after every right-hand side has stopped (at most
+// GM_BATCH - 1) change nothing.
+constexpr int GM_BATCH = 4;
+
 template <class Ops>
 hipError_t gmres_host(Ops& o, double tol, int kmax, int* its) {
   KBuf& T = o.kb;
@@ -106,104 +132,53 @@ hipError_t gmres_host(Ops& o, double tol, int kmax, int* its) {
   const int64_t vr = (int64_t)ks * n, pr = (int64_t)ks * 4 * nb;  // part: 4 wave sums per block
   cd* V = T.V;
   cd* dn = T.hd + 2 * ks;            // squared norm of right-hand side r at dn[r * hr]
-  auto sync_h = [&]() {
-    hipError_t e = hipMemcpyAsync(T.hh, T.hd, sizeof(cd) * hr * nr, hipMemcpyDeviceToHost, st);
-    return e == hipSuccess ? hipStreamSynchronize(st) : e;
-  };
+  const int K = T.kalloc;
   hipLaunchKernelGGL(k3_axpy, dim3(nb, nr), dim3(256), 0, st, n, 0, (const cd*)V, vs, vr, (const cd*)T.hd, hr,
                      T.d, n, T.npart, (int64_t)nb);
   hipLaunchKernelGGL(k3_sum, dim3(nr), dim3(256), 0, st, (int)nb, (const double*)T.npart, (int64_t)nb, dn, hr);
   hipLaunchKernelGGL(k3_normalize, dim3(nb, nr), dim3(256), 0, st, n, (const cd*)T.d, n, (const cd*)dn, hr, V, vr);
-  hipError_t e = sync_h();
+  hipLaunchKernelGGL(k3_gm_init, dim3(1), dim3(64), 0, st, nr, K, (const cd*)T.hd, hr, ks, T.gs, T.gi);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  using cx = std::complex<double>;
-  const int km = std::min(kmax, T.kalloc);
-  std::vector<std::vector<cx>> H(nr), cs(nr), sn(nr), gv(nr);
-  std::vector<double> beta(nr);
-  std::vector<int> done(nr, 0), mk(nr, 0);
-  int ndone = 0;
-  for (int r = 0; r < nr; ++r) {
-    H[r].assign((size_t)(km + 1) * km, 0.0);
-    cs[r].assign(km, 0.0);
-    sn[r].assign(km, 0.0);
-    gv[r].assign(km + 1, 0.0);
-    beta[r] = std::sqrt(T.hh[r * hr + 2 * ks].x);
-    gv[r][0] = beta[r];
-    if (!(beta[r] > 0.0)) {
-      done[r] = 1;
-      ++ndone;
-    }
-  }
-  for (int j = 0; j < km && ndone < nr; ++j) {
-    cd* vj = V + (int64_t)j * vs;
-    cd* vn = V + (int64_t)(j + 1) * vs;
-    o.apply_P(vj, vr, T.z, n);
-    o.apply_F(T.z, n, vn, vr);
-    for (int pass = 0; pass < 2; ++pass) {
-      cd* h = T.hd + pass * ks;
-      hipLaunchKernelGGL(k3_dots, dim3(nb, nr), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, vr, (const cd*)vn,
-                         vr, T.part, pr);
-      hipLaunchKernelGGL(k3_reduce, dim3(j + 1, nr), dim3(256), 0, st, (int)(4 * nb), (const cd*)T.part, pr, h, hr);
-      hipLaunchKernelGGL(k3_axpy, dim3(nb, nr), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, vr, (const cd*)h, hr,
-                         vn, vr, T.npart, (int64_t)nb);
-    }
-    hipLaunchKernelGGL(k3_sum, dim3(nr), dim3(256), 0, st, (int)nb, (const double*)T.npart, (int64_t)nb, dn, hr);
-    hipLaunchKernelGGL(k3_normalize, dim3(nb, nr), dim3(256), 0, st, n, (const cd*)vn, vr, (const cd*)dn, hr, vn,
-                       vr);
-    if ((e = sync_h()) != hipSuccess) return e;
-    for (int r = 0; r < nr; ++r) {
-      if (done[r]) continue;
-      // column j of the Hessenberg matrix, rotated by the previous rotations
-      const cd* hh = T.hh + r * hr;
-      cx* Hj = H[r].data() + (size_t)j * (km + 1);
-      for (int i = 0; i <= j; ++i) Hj[i] = cx(hh[i].x + hh[ks + i].x, hh[i].y + hh[ks + i].y);
-      const double hn = std::sqrt(hh[2 * ks].x);
-      for (int i = 0; i < j; ++i) {
-        const cx a = Hj[i], b = Hj[i + 1];
-        Hj[i] = cs[r][i] * a + sn[r][i] * b;
-        Hj[i + 1] = -std::conj(sn[r][i]) * a + cs[r][i] * b;
+  const int km = std::min(kmax, K);
+  for (int j = 0; j < km;) {
+    const int jb = std::min(km, j + GM_BATCH);
+    for (; j < jb; ++j) {
+      cd* vj = V + (int64_t)j * vs;
+      cd* vn = V + (int64_t)(j + 1) * vs;
+      o.apply_P(vj, vr, T.z, n);
+      o.apply_F(T.z, n, vn, vr);
+      for (int pass = 0; pass < 2; ++pass) {
+        cd* h = T.hd + pass * ks;
+        hipLaunchKernelGGL(k3_dots, dim3(nb, nr), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, vr, (const cd*)vn,
+                           vr, T.part, pr);
+        hipLaunchKernelGGL(k3_reduce, dim3(j + 1, nr), dim3(256), 0, st, (int)(4 * nb), (const cd*)T.part, pr, h,
+                           hr);
+        hipLaunchKernelGGL(k3_axpy, dim3(nb, nr), dim3(256), 0, st, n, j + 1, (const cd*)V, vs, vr, (const cd*)h,
+                           hr, vn, vr, T.npart, (int64_t)nb);
       }
-      const cx a = Hj[j];
-      const double ra = std::abs(a), rho = std::sqrt(ra * ra + hn * hn);
-      if (ra == 0.0) {
-        cs[r][j] = 0.0;
-        sn[r][j] = 1.0;
-      } else {
-        cs[r][j] = ra / rho;
-        sn[r][j] = (a / ra) * hn / rho;
-      }
-      Hj[j] = cs[r][j] * a + sn[r][j] * hn;
-      gv[r][j + 1] = -std::conj(sn[r][j]) * gv[r][j];
-      gv[r][j] = cs[r][j] * gv[r][j];
-      mk[r] = j + 1;
-      if (std::abs(gv[r][j + 1]) <= tol * beta[r] || !(hn > 0.0)) {
-        done[r] = 1;
-        ++ndone;
-      }
+      hipLaunchKernelGGL(k3_sum, dim3(nr), dim3(256), 0, st, (int)nb, (const double*)T.npart, (int64_t)nb, dn, hr);
+      hipLaunchKernelGGL(k3_normalize, dim3(nb, nr), dim3(256), 0, st, n, (const cd*)vn, vr, (const cd*)dn, hr, vn,
+                         vr);
+      hipLaunchKernelGGL(k3_gm_step, dim3(1), dim3(64), 0, st, nr, K, j, kmax, tol, (const cd*)T.hd, hr, ks, T.gs,
+                         T.gi);
     }
+    if ((e = hipMemcpyAsync(T.gih, T.gi, sizeof(int) * GI_WORDS, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return e;
+    if (!T.gih[2 * NRMAX]) break;
   }
-  // y_r = H_r^-1 g_r (upper triangular), mu_r = P^-1 (V_r y_r)
-  for (int r = 0; r < nr; ++r) {
-    its[r] = mk[r];
-    std::vector<cx> y(mk[r]);
-    for (int i = mk[r] - 1; i >= 0; --i) {
-      cx s = gv[r][i];
-      for (int c = i + 1; c < mk[r]; ++c) s -= H[r][(size_t)c * (km + 1) + i] * y[c];
-      y[i] = s / H[r][(size_t)i * (km + 1) + i];
-    }
-    for (int i = 0; i < mk[r]; ++i) T.hh[r * hr + i] = cd{y[i].real(), y[i].imag()};
-    T.nvh[r] = mk[r];
-  }
-  e = hipMemcpyAsync(T.hd, T.hh, sizeof(cd) * hr * nr, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(T.nvd, T.nvh, sizeof(int) * nr, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return e;
+  // y_r = H_r^-1 g_r, mu_r = P^-1 (V_r y_r)
+  hipLaunchKernelGGL(k3_gm_solve, dim3(1), dim3(64), 0, st, nr, K, (const cd*)T.gs, (const int*)T.gi, T.hd, hr,
+                     T.nvd);
   hipLaunchKernelGGL(k3_combine, dim3(nb, nr), dim3(256), 0, st, n, (const int*)T.nvd, (const cd*)V, vs, vr,
                      (const cd*)T.hd, hr, T.w, n);
   o.apply_P(T.w, n, T.mu, n);
-  // the host copies above must land before hh and nvh are reused
-  e = hipStreamSynchronize(st);
-  return e == hipSuccess ? hipGetLastError() : e;
+  if ((e = hipMemcpyAsync(T.gih, T.gi, sizeof(int) * GI_WORDS, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return e;
+  for (int r = 0; r < nr; ++r) its[r] = T.gih[2 * r + 1];
+  return hipGetLastError();
 }
-
 
 }  // namespace sfdp

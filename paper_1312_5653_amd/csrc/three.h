@@ -100,10 +100,10 @@ struct Three {
   cd *T = nullptr, *Y = nullptr, *Wc = nullptr, *fcs = nullptr, *uc = nullptr, *gc = nullptr, *d = nullptr,
      *mu = nullptr, *z = nullptr, *w = nullptr, *V = nullptr, *part = nullptr, *hd = nullptr;
   double* npart = nullptr;
-  cd* hh = nullptr;    // pinned host copy of hd
-  int* nvd = nullptr;  // basis lengths of the final combination (device, pinned host)
-  int* nvh = nullptr;
+  int* nvd = nullptr;  // basis lengths of the final combination
   int kalloc = 0;
+  cd* gs = nullptr;    // Givens state of the GMRES (device)
+  int *gi = nullptr, *gih = nullptr;  // activity words (device, pinned host)
   Maps3 maps() const { return Maps3{rl, rpos, nds, dmu, dsg, muown, cg, cown}; }
 };
 

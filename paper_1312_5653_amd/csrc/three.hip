@@ -561,6 +561,90 @@ __global__ void k3_combine(int64_t n, const int* nv, const cd* V, int64_t vs, in
   out[r * orr + t] = a;
 }
 
+// ---- Givens state of the host-loop GMRES on the device (krylov3.h) ----
+namespace {
+struct GmView {
+  cd *H, *c, *s, *g, *beta;  // H column j at H + j (K + 1)
+  __device__ GmView(cd* gs, int K, int r) {
+    H = gs + r * gs_len(K);
+    c = H + (int64_t)(K + 1) * K;
+    s = c + K;
+    g = s + K;
+    beta = g + K + 1;
+  }
+};
+__device__ inline void gm_live(int nr, int* gi) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int any = 0;
+    for (int r = 0; r < nr; ++r) any |= gi[2 * r];
+    gi[2 * NRMAX] = any;
+  }
+}
+}  // namespace
+
+__global__ void k3_gm_init(int nr, int K, const cd* hd, int64_t hr, int ks, cd* gs, int* gi) {
+  const int r = threadIdx.x;
+  if (r < nr) {
+    GmView v(gs, K, r);
+    const double b = sqrt(hd[r * hr + 2 * ks].x);
+    v.beta[0] = cd{b, 0.0};
+    for (int i = 0; i <= K; ++i) v.g[i] = cd{i == 0 ? b : 0.0, 0.0};
+    gi[2 * r] = b > 0.0 ? 1 : 0;
+    gi[2 * r + 1] = 0;
+  }
+  gm_live(nr, gi);
+}
+
+// column j: h = (pass-0 + pass-1 coefficients, ||w||); previous rotations
+// [c_i s_i; -conj(s_i) c_i] (c_i real), then the rotation that zeroes ||w||
+__global__ void k3_gm_step(int nr, int K, int j, int kmax, double tol, const cd* hd, int64_t hr, int ks, cd* gs,
+                           int* gi) {
+  const int r = threadIdx.x;
+  if (r < nr && gi[2 * r]) {
+    GmView v(gs, K, r);
+    cd* Hj = v.H + (int64_t)j * (K + 1);
+    const cd* h = hd + r * hr;
+    for (int i = 0; i <= j; ++i) Hj[i] = h[i] + h[ks + i];
+    const double hn = sqrt(h[2 * ks].x);
+    for (int i = 0; i < j; ++i) {
+      const cd a = Hj[i], b = Hj[i + 1];
+      Hj[i] = v.c[i] * a + v.s[i] * b;
+      Hj[i + 1] = v.c[i] * b - conj(v.s[i]) * a;
+    }
+    const cd a = Hj[j];
+    const double ra = sqrt(abs2(a)), rho = sqrt(ra * ra + hn * hn);
+    if (ra == 0.0) {
+      v.c[j] = cd{0.0, 0.0};
+      v.s[j] = cd{1.0, 0.0};
+    } else {
+      v.c[j] = cd{ra / rho, 0.0};
+      v.s[j] = (hn / (ra * rho)) * a;
+    }
+    Hj[j] = v.c[j] * a + hn * v.s[j];
+    const cd gj = v.g[j];
+    v.g[j + 1] = -1.0 * (conj(v.s[j]) * gj);
+    v.g[j] = v.c[j] * gj;
+    gi[2 * r + 1] = j + 1;
+    if (sqrt(abs2(v.g[j + 1])) <= tol * v.beta[0].x || !(hn > 0.0) || j + 1 >= kmax) gi[2 * r] = 0;
+  }
+  gm_live(nr, gi);
+}
+
+__global__ void k3_gm_solve(int nr, int K, const cd* gs, const int* gi, cd* hd, int64_t hr, int* nvd) {
+  const int r = threadIdx.x;
+  if (r >= nr) return;
+  GmView v(const_cast<cd*>(gs), K, r);
+  const int m = gi[2 * r + 1];
+  cd* y = hd + r * hr;
+  for (int i = m - 1; i >= 0; --i) {
+    cd t = v.g[i];
+    for (int c = i + 1; c < m; ++c) t = t - v.H[(int64_t)c * (K + 1) + i] * y[c];
+    y[i] = cdiv(t, v.H[(int64_t)i * (K + 1) + i]);
+  }
+  nvd[r] = m;
+}
+
 __global__ void k3_log(int* flags, int c, int q, int its) {
   flags[FLAG_ITS + c] = its;
   const int k = flags[FLAG_CNT + q];
@@ -586,7 +670,7 @@ struct Ops3 {
   int64_t nmu;
   Ops3(Problem& pp, int nr_)
       : p(pp), T(*pp.t3), g(pp.t3->g), mp(pp.t3->maps()), st(pp.ctx->stream), s32(pp.s32()), nr(nr_) {
-    kb = KBuf{T.V, T.hd, T.part, T.d, T.z, T.w, T.mu, T.npart, T.hh, T.nvd, T.nvh, T.kalloc};
+    kb = KBuf{T.V, T.hd, T.part, T.d, T.z, T.w, T.mu, T.npart, T.nvd, T.kalloc, T.gs, T.gi, T.gih};
     nmu = g.nmu;
     threads_local = (unsigned)std::min(1024, std::max(512, (g.ND + 63) / 64 * 64));
     threads_sweep = (unsigned)std::min(1024, std::max(512, (g.NR + 63) / 64 * 64));

@@ -77,7 +77,7 @@ def test_sizes_operators_and_load(sf, n, m):
     prob.close()
 
 
-@pytest.mark.parametrize("n,m", [(2, 2), (4, 2), (4, 4)])
+@pytest.mark.parametrize("n,m", [(2, 2), (4, 2), (4, 4), (6, 6)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_local_and_coarse_operators(sf, n, m, prec):
     sfdp, ctx = sf
@@ -128,7 +128,7 @@ def test_interface_operators(sf, n, m):
     prob.close()
 
 
-@pytest.mark.parametrize("n,m", [(4, 2), (8, 4)])
+@pytest.mark.parametrize("n,m", [(4, 2), (8, 4), (12, 6)])
 @pytest.mark.parametrize("conj_z", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_feti_solve_matches_direct(sf, n, m, conj_z, prec):
