@@ -65,8 +65,8 @@ __device__ inline void symcol_r3(const TS* __restrict__ A, int ld, int n, int i,
 // 2 (kalloc + 1) + 1 entries; nvd the basis lengths of the final combination;
 // gs per right-hand side the Givens state (gs_len entries: Hessenberg columns,
 // rotations, rotated right-hand side, ||d||); gi per right-hand side its
-// activity and iteration count, then one word "any active"; gih a pinned copy
-// of gi).
+// activity and iteration count, then the word "any active" and a counter used
+// by the step kernel; gih a pinned copy of gi).
 struct KBuf {
   cd *V, *hd, *part, *d, *z, *w, *mu;
   double* npart;
@@ -79,7 +79,7 @@ struct KBuf {
 // Givens state per right-hand side for kalloc K: H columns (K x (K + 1)), c
 // (K), s (K), g (K + 1), beta (1)
 __host__ __device__ inline int64_t gs_len(int K) { return (int64_t)(K + 1) * K + 3 * (int64_t)K + 2; }
-constexpr int GI_WORDS = 2 * NRMAX + 1;
+constexpr int GI_WORDS = 2 * NRMAX + 2;
 
 __global__ void k3_dots(int64_t n, int nv, const cd* V, int64_t vs, int64_t vr, const cd* w, int64_t wr, cd* part,
                         int64_t pr);
@@ -94,16 +94,18 @@ __global__ void k3_combine(int64_t n, const int* nv, const cd* V, int64_t vs, in
 __global__ void k3_dense_mv(int n, int64_t stride, int nr, const cd* A, const cd* x, cd* y);
 
 // Givens steps on the device (three.hip).  init: beta_r = sqrt of the squared
-// norm in hd, g_r = (beta_r, 0, ...), active_r = beta_r > 0.  step j: column j of
-// H_r from the two Gram-Schmidt coefficient sets and the new vector's norm,
-// rotated by the previous rotations, a new rotation, g_r updated, and the
-// stopping test; gi[2 NRMAX] = any right-hand side still active.  solve: y_r =
-// H_r^-1 g_r over its_r columns into hd (the combination coefficients) and
-// nvd_r = its_r.  One thread per right-hand side.
+// norm in hd, g_r = (beta_r, 0, ...), active_r = beta_r > 0.  step j (one wave per
+// right-hand side, the column and the rotations staged in LDS): column j of H_r
+// from the two Gram-Schmidt coefficient sets and the new vector's norm, rotated
+// by the previous rotations, a new rotation, g_r updated, and the stopping test;
+// the last workgroup publishes gi[2 NRMAX] = any right-hand side still active.
+// solve (one wave per right-hand side, the triangle in LDS when it has at most
+// mlds columns): y_r = H_r^-1 g_r over its_r columns into hd (the combination
+// coefficients) and nvd_r = its_r.
 __global__ void k3_gm_init(int nr, int K, const cd* hd, int64_t hr, int ks, cd* gs, int* gi);
 __global__ void k3_gm_step(int nr, int K, int j, int kmax, double tol, const cd* hd, int64_t hr, int ks, cd* gs,
                            int* gi);
-__global__ void k3_gm_solve(int nr, int K, const cd* gs, const int* gi, cd* hd, int64_t hr, int* nvd);
+__global__ void k3_gm_solve(int K, const cd* gs, const int* gi, cd* hd, int64_t hr, int* nvd, int mlds);
 
 // Ops: stream st, right-hand sides nr, interface length nmu, buffers kb, and
 // apply_P(x, xr, out, orr) / apply_F(x, xr, out, orr) (preconditioner and
@@ -119,6 +121,7 @@ __global__ void k3_gm_solve(int nr, int K, const cd* gs, const int* gi, cd* hd, 
 // own; iterations enqueued after every right-hand side has stopped (at most
 // GM_BATCH - 1) change nothing.
 constexpr int GM_BATCH = 4;
+constexpr int GM_LDS_COLS = 112;  // back substitution with the triangle in LDS up to this many columns
 
 template <class Ops>
 hipError_t gmres_host(Ops& o, double tol, int kmax, int* its) {
@@ -160,17 +163,23 @@ hipError_t gmres_host(Ops& o, double tol, int kmax, int* its) {
       hipLaunchKernelGGL(k3_sum, dim3(nr), dim3(256), 0, st, (int)nb, (const double*)T.npart, (int64_t)nb, dn, hr);
       hipLaunchKernelGGL(k3_normalize, dim3(nb, nr), dim3(256), 0, st, n, (const cd*)vn, vr, (const cd*)dn, hr, vn,
                          vr);
-      hipLaunchKernelGGL(k3_gm_step, dim3(1), dim3(64), 0, st, nr, K, j, kmax, tol, (const cd*)T.hd, hr, ks, T.gs,
-                         T.gi);
+      hipLaunchKernelGGL(k3_gm_step, dim3(nr), dim3(64), sizeof(cd) * (3 * (size_t)K + 1), st, nr, K, j, kmax, tol,
+                         (const cd*)T.hd, hr, ks, T.gs, T.gi);
     }
     if ((e = hipMemcpyAsync(T.gih, T.gi, sizeof(int) * GI_WORDS, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return e;
     if (!T.gih[2 * NRMAX]) break;
   }
-  // y_r = H_r^-1 g_r, mu_r = P^-1 (V_r y_r)
-  hipLaunchKernelGGL(k3_gm_solve, dim3(1), dim3(64), 0, st, nr, K, (const cd*)T.gs, (const int*)T.gi, T.hd, hr,
-                     T.nvd);
+  // y_r = H_r^-1 g_r (the triangle in LDS up to GM_LDS_COLS columns), mu_r = P^-1 (V_r y_r)
+  if ((e = hipMemcpyAsync(T.gih, T.gi, sizeof(int) * GI_WORDS, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return e;
+  int mmax = 0;
+  for (int r = 0; r < nr; ++r) mmax = std::max(mmax, T.gih[2 * r + 1]);
+  const int mlds = mmax <= GM_LDS_COLS ? mmax : 0;
+  hipLaunchKernelGGL(k3_gm_solve, dim3(nr), dim3(64), sizeof(cd) * ((size_t)mlds * (mlds + 1) / 2 + K + 1), st, K,
+                     (const cd*)T.gs, (const int*)T.gi, T.hd, hr, T.nvd, mlds);
   hipLaunchKernelGGL(k3_combine, dim3(nb, nr), dim3(256), 0, st, n, (const int*)T.nvd, (const cd*)V, vs, vr,
                      (const cd*)T.hd, hr, T.w, n);
   o.apply_P(T.w, n, T.mu, n);

@@ -593,56 +593,108 @@ __global__ void k3_gm_init(int nr, int K, const cd* hd, int64_t hr, int ks, cd* 
     gi[2 * r] = b > 0.0 ? 1 : 0;
     gi[2 * r + 1] = 0;
   }
+  if (threadIdx.x == 0) gi[2 * NRMAX + 1] = 0;
   gm_live(nr, gi);
 }
 
-// column j: h = (pass-0 + pass-1 coefficients, ||w||); previous rotations
-// [c_i s_i; -conj(s_i) c_i] (c_i real), then the rotation that zeroes ||w||
+// Column j of right-hand side r = blockIdx.x (one wave): h = pass-0 + pass-1
+// coefficients and ||w||, staged with the previous rotations in LDS by the
+// wave; lane 0 applies the rotations [c_i s_i; -conj(s_i) c_i] (c_i real) and
+// forms the one that zeroes ||w||; the wave writes the column back.  The last
+// workgroup to finish publishes "any active" (a counter of finished workgroups
+// in gi[2 NRMAX + 1], reset by that workgroup).
 __global__ void k3_gm_step(int nr, int K, int j, int kmax, double tol, const cd* hd, int64_t hr, int ks, cd* gs,
                            int* gi) {
-  const int r = threadIdx.x;
-  if (r < nr && gi[2 * r]) {
+  extern __shared__ cd lm[];  // Hj (K + 1), c (K), s (K)
+  const int r = blockIdx.x, lane = threadIdx.x;
+  const bool act = gi[2 * r] != 0;
+  if (act) {
     GmView v(gs, K, r);
-    cd* Hj = v.H + (int64_t)j * (K + 1);
+    cd* Hj = lm;
+    cd* c = lm + (K + 1);
+    cd* sn = c + K;
     const cd* h = hd + r * hr;
-    for (int i = 0; i <= j; ++i) Hj[i] = h[i] + h[ks + i];
-    const double hn = sqrt(h[2 * ks].x);
-    for (int i = 0; i < j; ++i) {
-      const cd a = Hj[i], b = Hj[i + 1];
-      Hj[i] = v.c[i] * a + v.s[i] * b;
-      Hj[i + 1] = v.c[i] * b - conj(v.s[i]) * a;
+    for (int i = lane; i <= j; i += 64) Hj[i] = h[i] + h[ks + i];
+    for (int i = lane; i < j; i += 64) {
+      c[i] = v.c[i];
+      sn[i] = v.s[i];
     }
-    const cd a = Hj[j];
-    const double ra = sqrt(abs2(a)), rho = sqrt(ra * ra + hn * hn);
-    if (ra == 0.0) {
-      v.c[j] = cd{0.0, 0.0};
-      v.s[j] = cd{1.0, 0.0};
-    } else {
-      v.c[j] = cd{ra / rho, 0.0};
-      v.s[j] = (hn / (ra * rho)) * a;
+    __syncthreads();
+    if (lane == 0) {
+      const double hn = sqrt(h[2 * ks].x);
+      for (int i = 0; i < j; ++i) {
+        const cd a = Hj[i], b = Hj[i + 1];
+        Hj[i] = c[i] * a + sn[i] * b;
+        Hj[i + 1] = c[i] * b - conj(sn[i]) * a;
+      }
+      const cd a = Hj[j];
+      const double ra = sqrt(abs2(a)), rho = sqrt(ra * ra + hn * hn);
+      cd cj, sj;
+      if (ra == 0.0) {
+        cj = cd{0.0, 0.0};
+        sj = cd{1.0, 0.0};
+      } else {
+        cj = cd{ra / rho, 0.0};
+        sj = (hn / (ra * rho)) * a;
+      }
+      v.c[j] = cj;
+      v.s[j] = sj;
+      Hj[j] = cj * a + hn * sj;
+      const cd gj = v.g[j];
+      v.g[j + 1] = -1.0 * (conj(sj) * gj);
+      v.g[j] = cj * gj;
+      gi[2 * r + 1] = j + 1;
+      if (sqrt(abs2(v.g[j + 1])) <= tol * v.beta[0].x || !(hn > 0.0) || j + 1 >= kmax) gi[2 * r] = 0;
     }
-    Hj[j] = v.c[j] * a + hn * v.s[j];
-    const cd gj = v.g[j];
-    v.g[j + 1] = -1.0 * (conj(v.s[j]) * gj);
-    v.g[j] = v.c[j] * gj;
-    gi[2 * r + 1] = j + 1;
-    if (sqrt(abs2(v.g[j + 1])) <= tol * v.beta[0].x || !(hn > 0.0) || j + 1 >= kmax) gi[2 * r] = 0;
+    __syncthreads();
+    cd* Hc = v.H + (int64_t)j * (K + 1);
+    for (int i = lane; i <= j; i += 64) Hc[i] = Hj[i];
   }
-  gm_live(nr, gi);
+  // the last workgroup to finish publishes whether any right-hand side is active
+  __syncthreads();
+  if (lane == 0) {
+    __threadfence();
+    const int done = atomicAdd(gi + 2 * NRMAX + 1, 1);
+    if (done == nr - 1) {
+      __threadfence();
+      int any = 0;
+      for (int q = 0; q < nr; ++q) any |= __hip_atomic_load(gi + 2 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      gi[2 * NRMAX] = any;
+      gi[2 * NRMAX + 1] = 0;
+    }
+  }
 }
 
-__global__ void k3_gm_solve(int nr, int K, const cd* gs, const int* gi, cd* hd, int64_t hr, int* nvd) {
-  const int r = threadIdx.x;
-  if (r >= nr) return;
+// y_r = H_r^-1 g_r over its_r columns (right-hand side r = blockIdx.x, one wave):
+// t = g in LDS; for i = m - 1 .. 0, lane 0 forms y_i = t_i / H_ii, then every
+// t_c, c < i, takes -H_ic y_i.  The triangle is staged in LDS when it has at
+// most mlds columns (packed by columns), else read from global memory.  Writes y
+// to hd (the combination coefficients) and nvd_r = its_r.
+__global__ void k3_gm_solve(int K, const cd* gs, const int* gi, cd* hd, int64_t hr, int* nvd, int mlds) {
+  extern __shared__ cd lm[];  // triangle (mlds (mlds + 1) / 2), then t (K + 1)
+  const int r = blockIdx.x, lane = threadIdx.x;
   GmView v(const_cast<cd*>(gs), K, r);
   const int m = gi[2 * r + 1];
+  const bool inlds = m <= mlds;
+  cd* tri = lm;
+  cd* tv = lm + (size_t)mlds * (mlds + 1) / 2;
+  if (inlds)
+    for (int i = 0; i < m; ++i)
+      for (int c = lane; c <= i; c += 64) tri[i * (i + 1) / 2 + c] = v.H[(int64_t)i * (K + 1) + c];
+  for (int c = lane; c < m; c += 64) tv[c] = v.g[c];
   cd* y = hd + r * hr;
+  __syncthreads();
   for (int i = m - 1; i >= 0; --i) {
-    cd t = v.g[i];
-    for (int c = i + 1; c < m; ++c) t = t - v.H[(int64_t)c * (K + 1) + i] * y[c];
-    y[i] = cdiv(t, v.H[(int64_t)i * (K + 1) + i]);
+    const cd hii = inlds ? tri[i * (i + 1) / 2 + i] : v.H[(int64_t)i * (K + 1) + i];
+    const cd yi = cdiv(tv[i], hii);
+    for (int c = lane; c < i; c += 64) {
+      const cd hic = inlds ? tri[i * (i + 1) / 2 + c] : v.H[(int64_t)i * (K + 1) + c];
+      tv[c] = tv[c] - hic * yi;
+    }
+    if (lane == 0) y[i] = yi;
+    __syncthreads();
   }
-  nvd[r] = m;
+  if (lane == 0) nvd[r] = m;
 }
 
 __global__ void k3_log(int* flags, int c, int q, int its) {
