@@ -160,15 +160,16 @@ typedef struct {
 /* Launch-variant autotuning (enable = 1, the default): kernels with variants
  * that compute the same results in different launch shapes (the 2D subdomain
  * solve: one workgroup for all right-hand sides, one workgroup per right-hand
- * side, or one wavefront per right-hand side; the 3D sweeps and interface
- * products: the depth of their load pipeline) time every variant on the real
- * operands the first time they run for a (kernel, shape, precision,
+ * side, one wavefront per right-hand side, or one workgroup with a wavefront
+ * per right-hand side and the line factors staged once; the 3D sweeps and
+ * interface products: the depth of their load pipeline) time every variant on
+ * the real operands the first time they run for a (kernel, shape, precision,
  * right-hand sides) key on a device, and keep the fastest for the process.
- * enable = 0 runs fixed defaults; enable = 2 + c (c = 0, 1, 2) runs variant c
+ * enable = 0 runs fixed defaults; enable = 2 + c (c = 0 .. 3) runs variant c
  * of every kernel that has it (the defaults elsewhere), for tests that compare
  * the variants.  Any call forgets the choices made so far.  Results do not
  * depend on the variant beyond the order of the floating-point sums (1e-12
- * relative).  SFDP_E_INVALID outside 0..4. */
+ * relative).  SFDP_E_INVALID outside 0..5. */
 sfdp_status sfdp_set_tuning(int enable);
 
 /* Graph replay of refinement steps (enable = 1; default 0): a single 2D

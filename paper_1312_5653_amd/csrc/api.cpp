@@ -1558,7 +1558,7 @@ sfdp_status sfdp_set_graphs(int enable) {
 }
 
 sfdp_status sfdp_set_tuning(int enable) {
-  if (enable < 0 || enable > 4) return fail(SFDP_E_INVALID, "enable must be in 0..4");
+  if (enable < 0 || enable > 5) return fail(SFDP_E_INVALID, "enable must be in 0..5");
   tune_set_mode(enable == 1, enable >= 2 ? enable - 2 : -1);
   return SFDP_OK;
 }

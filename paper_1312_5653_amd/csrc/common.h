@@ -529,8 +529,12 @@ struct TuneEntry {
 // The variant to run for key: on the first call every candidate 0..ncand-1 is
 // launched (launch(c); candidates must compute the same results and may run
 // repeatedly) and timed on stream st; later calls return the kept choice.
-// fallback when tuning is off or timing fails.
-int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, const std::function<void(int)>& launch);
+// fallback when tuning is off or timing fails.  weight (optional, ncand
+// entries) scales each candidate's measured time before the comparison: a
+// weight above 1 makes a candidate that moves more bytes win only by that
+// margin, since its traffic competes with work running beside it.
+int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, const std::function<void(int)>& launch,
+                const float* weight = nullptr);
 // changes whenever the tuning mode or the table is reset (part of StepKey)
 unsigned tune_generation();
 // on: autotune; force >= 0: run candidate `force` wherever a family has it;

@@ -28,6 +28,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 namespace sfdp {
 
@@ -291,17 +292,51 @@ __device__ inline void line_mv(const TS* Gl, int ml, const T* z, T* red, T* out,
   for (int r = 0; r < NRT; ++r) acc[r] = T{0, 0};
   if (lane < ml) {
     // fixed trip count (kq <= KQ), clamped indices and out-of-range terms
-    // selected to zero: the wave issues its LDS reads back to back instead of
-    // waiting for each k's operands before the next (k0, k1 are wave-uniform)
+    // selected to zero (k0, k1 are wave-uniform)
     constexpr int KQ = (ML + 3) / 4;
     const int k0 = wv * kq, k1 = min(ml, k0 + kq);
+    if constexpr (NRT == 1) {
+      // one right-hand side: the compiler's own order, which keeps the register
+      // count low enough for four workgroups per CU
 #pragma unroll
-    for (int u = 0; u < KQ; ++u) {
-      const int k = min(k0 + u, ml - 1);
-      auto gk = cvt<typename real_of<T>::type>(Gl[k * ml + lane]);
-      if (k0 + u >= k1) gk = decltype(gk){0, 0};
+      for (int u = 0; u < KQ; ++u) {
+        const int k = min(k0 + u, ml - 1);
+        auto gk = cvt<typename real_of<T>::type>(Gl[k * ml + lane]);
+        if (k0 + u >= k1) gk = decltype(gk){0, 0};
+        fma_acc(acc[0], gk, z[k]);
+      }
+    } else {
+      // several right-hand sides: the operands go to registers in chunks of CH
+      // terms, the next chunk's LDS reads issued before the current chunk's
+      // multiply-adds; the scheduling barriers keep the compiler from sinking
+      // each read to its use, which costs one LDS round trip per term
+      constexpr int CH = 3;
+      static_assert(KQ % CH == 0, "whole chunks");
+      TS gv[2][CH];
+      T zv[2][CH][NRT];
+      auto fetch = [&](int c, int b) {
 #pragma unroll
-      for (int r = 0; r < NRT; ++r) fma_acc(acc[r], gk, z[r * ML + k]);
+        for (int i = 0; i < CH; ++i) {
+          const int k = min(k0 + c * CH + i, ml - 1);
+          gv[b][i] = Gl[k * ml + lane];
+#pragma unroll
+          for (int r = 0; r < NRT; ++r) zv[b][i][r] = z[r * ML + k];
+        }
+      };
+      fetch(0, 0);
+#pragma unroll
+      for (int c = 0; c < KQ / CH; ++c) {
+        if (c + 1 < KQ / CH) fetch(c + 1, (c + 1) & 1);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          auto gk = cvt<typename real_of<T>::type>(gv[c & 1][i]);
+          if (k0 + c * CH + i >= k1) gk = decltype(gk){0, 0};
+#pragma unroll
+          for (int r = 0; r < NRT; ++r) fma_acc(acc[r], gk, zv[c & 1][i][r]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
 #pragma unroll
     for (int r = 0; r < NRT; ++r) red[(r * 4 + wv) * ML + lane] = acc[r];
@@ -706,6 +741,269 @@ k_local_solve_wave(Src src, int mode, int fsel, int conj_in, int xsel) {
                        d.u0 + r * rs.nc, d.mu + r * rs.nmu, d.Xd + r * rs.sb, d.Qc + r * rs.cq,
                        d.Ubuf + r * rs.sb, mode == 1 ? dev_vec(d, xsel) + r * rs.nf : nullptr,
                        mode == 1 ? conj_in : 0, src.bx());
+}
+
+// Values of the adjacent lanes (DPP wavefront shifts; lane 0, resp. 63, gets
+// zero).  Every lane of the wave must be active.
+__device__ inline double dpp_shr1(double v) {  // lane p <- lane p - 1
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x138, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double dpp_shl1(double v) {  // lane p <- lane p + 1
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x130, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline cd lane_from_below(cd v) { return cd{dpp_shr1(v.x), dpp_shr1(v.y)}; }
+__device__ inline cd lane_from_above(cd v) { return cd{dpp_shl1(v.x), dpp_shl1(v.y)}; }
+
+// Full local solve with E^s for nr <= 4 right-hand sides by one workgroup of
+// four wavefronts (the same results as local_solve_body up to the order of the
+// sums).  Wave w runs the line recursion of right-hand side w: lane p owns node
+// p of every line, keeps the previous step's result at its node in a register
+// (the neighbours' values come from the adjacent lanes by DPP shifts) and reads
+// its node's value of the current line from LDS one step ahead, so the only LDS
+// round trip inside a step is the line product.  The workgroup stages every
+// line factor into LDS once for all right-hand sides: the factor of step t + 1
+// is copied from a ring of GRD register copies (each loaded GRD - 1 steps
+// before it is stored), widened to FP64, into one of two LDS slots while step t
+// reads the other, and one workgroup barrier per step separates the two.  The
+// factors leave HBM once per subdomain, where one workgroup or one wavefront
+// per right-hand side reads them once per right-hand side (from L2 when their
+// sweeps stay close).  lds: ls_group_bytes() bytes.
+constexpr int LSG_GE = (ML * ML + 255) / 256;  // line-factor entries staged per thread
+constexpr int LSG_KC = 11;                     // product terms per register chunk
+static_assert(ML % LSG_KC == 0, "the line length is a whole number of product chunks");
+__host__ __device__ constexpr size_t ls_group_bytes() {
+  return 4 * ML * ML * sizeof(cd) + 4 * 64 * sizeof(cd) + 2 * ML * ML * sizeof(cd);
+}
+template <class TS>
+__device__ inline void local_solve_group(const Geo2& g, const Maps2& mp, const RhsStride& rs, int nr,
+                                         const TS* __restrict__ G, int mode, const cd* __restrict__ f0,
+                                         int conj_in, const cd* __restrict__ uc0, const cd* __restrict__ mu0,
+                                         cd* Xd0, cd* Qc0, cd* Ubuf0, cd* xout0, int conj_out, int s,
+                                         char* lds) {
+  constexpr int XS = ML * ML;
+  constexpr int GRD = 3;  // line factors in flight per thread
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cd* xall = (cd*)lds + (size_t)w * XS;
+  cd* zl = (cd*)lds + 4 * XS + w * 64;
+  cd* gbuf = (cd*)(lds + 4 * XS * sizeof(cd) + 4 * 64 * sizeof(cd));  // factors staged in FP64
+  const int ml = g.ml, n2 = ml * ml, ND = g.ND;
+  const TS* Gs = G + (size_t)s * ml * n2;
+  const int nsteps = 2 * ml - 1;
+  auto line_of = [&](int t) { return t < ml ? t : 2 * ml - 2 - t; };
+  // staging: thread e takes entries e, e + 256, ... of a line (clamped loads)
+  // the ring holds the entries as two-lane vectors of their real type, which
+  // the compiler keeps in registers (an array of the struct type it did not)
+  using RV = decltype(TS{}.x);
+  typedef RV GV __attribute__((ext_vector_type(2)));
+  GV greg[GRD * LSG_GE];
+#define LSG_LOAD(t, slot)                                                                        \
+  {                                                                                              \
+    const GV* src_ = (const GV*)(Gs + (size_t)line_of(t) * n2);                                  \
+    _Pragma("unroll") for (int i = 0; i < LSG_GE; ++i)                                           \
+      greg[(slot) * LSG_GE + i] = src_[min((int)threadIdx.x + 256 * i, n2 - 1)];                 \
+  }
+#define LSG_STORE(t, slot)                                                                       \
+  {                                                                                              \
+    cd* dst_ = gbuf + ((t) & 1) * XS;                                                            \
+    _Pragma("unroll") for (int i = 0; i < LSG_GE; ++i) {                                         \
+      const int e_ = threadIdx.x + 256 * i;                                                      \
+      const GV v_ = greg[(slot) * LSG_GE + i];                                                   \
+      if (e_ < n2) dst_[e_] = cd{(double)v_.x, (double)v_.y};                                    \
+    }                                                                                            \
+  }
+#pragma unroll
+  for (int u = 0; u < GRD; ++u)
+    if (u < nsteps) LSG_LOAD(u, u);
+  const bool act = w < nr;  // uniform over the wave
+  const cd* f = f0 + w * rs.nf;
+  const cd* uc = uc0 + w * rs.nc;
+  const cd* mu = mu0 + w * rs.nmu;
+  if (lane < ML) zl[lane] = cd{0.0, 0.0};
+  if (act) {
+    // right-hand side on the r nodes (f / multiplicity; mode 1 minus the corner terms)
+    for (int l = lane; l < n2; l += 64) {
+      const int a = l % ml, b = l / ml;
+      const bool rn = g.rnode(s, a, b);
+      cd v{0.0, 0.0};
+      if (rn) {
+        const cd fv = f[g.freeidx(s, a, b)];
+        v = (1.0 / g.mult(a, b)) * (conj_in ? conj(fv) : fv);
+        if (mode == 1)
+          for (int q = 0; q < 4; ++q) {
+            const int cl = mp.cloc[s * 4 + q];
+            if (cl < 0) continue;
+            const int ca = cl % ml, cb = cl / ml;
+            if (abs(ca - a) > 1 || abs(cb - b) > 1) continue;
+            v = v - g.zloc(a, b, ca, cb) * uc[mp.cgid[s * NQ + q]];
+          }
+      }
+      xall[l] = v;
+    }
+    wave_lds_sync();
+    if (mode == 1) {
+      const int nd = mp.nd[s];
+      for (int i = lane; i < nd; i += 64) {
+        const int l = mp.dloc[s * ND + i];
+        xall[l] = xall[l] - (double)mp.dsgn[s * ND + i] * mu[mp.dmid[s * ND + i]];
+      }
+      wave_lds_sync();
+    }
+  }
+  LSG_STORE(0, 0);
+  __syncthreads();
+  // couplings of node p to nodes p - 1, p, p + 1 of the adjacent line, and the
+  // r-set masks of those three grid columns (bit b: node (p + d - 1, b) is an r node)
+  const bool on = act && lane < ml;
+  const int pc = min(lane, ml - 1);
+  uint64_t zmk[3];
+  cd cpl[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int a = lane + d - 1;
+    zmk[d] = on ? rnode_column(g, s, a) : 0;
+    cpl[d] = (on && a >= 0 && a < ml) ? g.zloc(lane, 1, a, 2) : cd{0.0, 0.0};
+  }
+  // per-lane state of the recursion: the previous step's result at node p
+  // (forward: t_(j-1); backward: x_(j+1)), whose neighbours p - 1 and p + 1 come
+  // from the adjacent lanes by DPP shifts, and the current line's own value
+  // (forward: f_j; backward: t_j), read from LDS one step ahead
+  cd tprev{0.0, 0.0};
+  cd fcur = on ? xall[lane] : cd{0.0, 0.0};
+  // one step; U = t mod GRD is a compile-time constant, so the register ring
+  // is indexed statically
+  auto step = [&](int t, auto uconst) {
+    constexpr int u = decltype(uconst)::value;
+    {
+      {
+        // greg[u] (the factor of step t) is in LDS: reuse it for step t + GRD
+        if (t + GRD < nsteps) LSG_LOAD(t + GRD, u);
+        if (act) {
+          const int j = line_of(t);
+          const bool fwd = t < ml;
+          const cd fnext = (on && t + 1 < nsteps) ? xall[lane + ml * line_of(t + 1)] : cd{0.0, 0.0};
+          const cd nb[3] = {lane_from_below(tprev), tprev, lane_from_above(tprev)};
+          if (on) {
+            cd v{0.0, 0.0};
+            if (fwd) {
+              // z_j = f_j - A_j,j-1 t_j-1
+              v = fcur;
+              if (j > 0 && ((zmk[1] >> j) & 1)) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                  if ((zmk[d] >> (j - 1)) & 1) v = v - cpl[d] * nb[d];
+              }
+            } else if ((zmk[1] >> j) & 1) {
+              // A_j,j+1 x_j+1
+#pragma unroll
+              for (int d = 0; d < 3; ++d)
+                if ((zmk[d] >> (j + 1)) & 1) fma_acc(v, cpl[d], nb[d]);
+            }
+            zl[lane] = v;
+          }
+          wave_lds_sync();
+          // row p of G_j z (G stored transposed: G(p, k) at k ml + p; k clamped to
+          // ml - 1, where zl is zero), four accumulators (k mod 4).  The LDS
+          // operands go to registers in chunks of LSG_KC terms, the next chunk's
+          // reads issued before the current chunk's multiply-adds; the scheduling
+          // barriers keep the compiler from sinking each read to its use (which
+          // costs one LDS round trip per term)
+          const cd* gl = gbuf + (t & 1) * XS + pc;
+          cd acc[4] = {cd{0.0, 0.0}, cd{0.0, 0.0}, cd{0.0, 0.0}, cd{0.0, 0.0}};
+          cd gk[2][LSG_KC];
+          cd zk[2][LSG_KC];
+#pragma unroll
+          for (int i = 0; i < LSG_KC; ++i) {
+            gk[0][i] = gl[min(i, ml - 1) * ml];
+            zk[0][i] = zl[i];
+          }
+#pragma unroll
+          for (int c = 0; c < ML / LSG_KC; ++c) {
+            if (c + 1 < ML / LSG_KC) {
+#pragma unroll
+              for (int i = 0; i < LSG_KC; ++i) {
+                const int k = (c + 1) * LSG_KC + i;
+                gk[(c + 1) & 1][i] = gl[min(k, ml - 1) * ml];
+                zk[(c + 1) & 1][i] = zl[k];
+              }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < LSG_KC; ++i) {
+              const int k = c * LSG_KC + i;
+              fma_acc(acc[k & 3], gk[c & 1][i], zk[c & 1][i]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          const cd tv = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+          // forward: t_j = G_j z_j; backward: x_j = t_j - G_j A x_j+1
+          const cd res = fwd ? tv : fcur - tv;
+          if (on) xall[lane + ml * j] = res;
+          tprev = res;
+          fcur = fnext;
+        }
+        // the factor of step t + 1 into the other slot (its last reader, step
+        // t - 1, finished before the previous barrier)
+        if (t + 1 < nsteps) LSG_STORE(t + 1, (u + 1) % GRD);
+        __syncthreads();
+      }
+    }
+  };
+  static_assert(GRD == 3, "the step calls below cover GRD ring slots");
+  for (int t0 = 0; t0 < nsteps; t0 += GRD) {
+    step(t0, std::integral_constant<int, 0>{});
+    if (t0 + 1 < nsteps) step(t0 + 1, std::integral_constant<int, 1>{});
+    if (t0 + 2 < nsteps) step(t0 + 2, std::integral_constant<int, 2>{});
+  }
+#undef LSG_LOAD
+#undef LSG_STORE
+  if (!act) return;
+  wave_lds_sync();
+  // outputs
+  const int nd = mp.nd[s];
+  if (mode == 0) {
+    cd* Xd = Xd0 + w * rs.sb;
+    cd* Qc = Qc0 + w * rs.cq;
+    for (int i = lane; i < nd; i += 64) Xd[(size_t)s * ND + i] = xall[mp.dloc[s * ND + i]];
+    if (lane < 4) {
+      const int cl = mp.cloc[s * 4 + lane];
+      cd acc{0.0, 0.0};
+      if (cl >= 0) {
+        const int ca = cl % ml, cb = cl / ml;
+        for (int b = max(cb - 1, 0); b <= min(cb + 1, ml - 1); ++b)
+          for (int a = max(ca - 1, 0); a <= min(ca + 1, ml - 1); ++a)
+            if (g.rnode(s, a, b)) fma_acc(acc, g.zloc(ca, cb, a, b), xall[a + ml * b]);
+      }
+      Qc[s * NQ + lane] = acc;
+    }
+  } else {
+    cd* Ubuf = Ubuf0 + w * rs.sb;
+    cd* xout = xout0 + w * rs.nf;
+    for (int i = lane; i < nd; i += 64) Ubuf[(size_t)s * ND + i] = xall[mp.dloc[s * ND + i]];
+    for (int l = lane; l < n2; l += 64) {
+      const int a = l % ml, b = l / ml;
+      if (a == 0 || a == ml - 1 || b == 0 || b == ml - 1) continue;  // interior only
+      const cd v = xall[l];
+      xout[g.freeidx(s, a, b)] = conj_out ? conj(v) : v;
+    }
+  }
+}
+
+// One workgroup of four wavefronts per (instance, subdomain), wave w serving
+// right-hand side w; dynamic LDS ls_group_bytes().
+template <class TS, class Src>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_local_solve_group(Src src, int mode, int fsel, int conj_in, int xsel) {
+  const Dev& d = src.dev();
+  if (d.nr <= 0) return;
+  extern __shared__ __align__(16) char smem[];
+  const RhsStride& rs = d.rs;
+  local_solve_group<TS>(d.g, d.mp, rs, d.nr, (const TS*)d.G, mode, dev_vec(d, fsel), conj_in, d.u0, d.mu,
+                        d.Xd, d.Qc, d.Ubuf, mode == 1 ? dev_vec(d, xsel) : nullptr, mode == 1 ? conj_in : 0,
+                        src.bx(), smem);
 }
 
 // Edge slots of Qc: Qc[s][4 + j] = sum over the Delta slots on side j of
@@ -1655,12 +1953,20 @@ static void local_solve_t(const Target& t, int mode, int f, int conj_in, int x) 
 // Candidates: one workgroup per subdomain for all right-hand sides (0), one
 // workgroup of 256 per subdomain and right-hand side (1: more workgroups per CU,
 // the line factors re-read from L2), one wavefront per subdomain and right-hand
-// side (2: no workgroup barriers in the line recursion).  The autotuner picks;
-// without it the wavefront form runs.
+// side (2: no workgroup barriers in the line recursion), one workgroup of four
+// wavefronts per subdomain, a wavefront per right-hand side, the line factors
+// staged once into LDS for all of them (3).  The autotuner picks; without it
+// the wavefront form runs.
 template <class TS>
 static void local_solve_w(const Target& t, int mode, int f, int conj_in, int x, int nr) {
   auto run = [&](int c) {
-    if (c == 2)
+    if (c == 3) {
+      const size_t lds = ls_group_bytes();
+      (void)ensure_lds((const void*)k_local_solve_group<TS, One>, lds);
+      (void)ensure_lds((const void*)k_local_solve_group<TS, Many>, lds);
+      launch2(t, K_SUB, k_local_solve_group<TS, One>, k_local_solve_group<TS, Many>, 1, 256, lds, mode, f,
+              conj_in, x);
+    } else if (c == 2)
       launch2(t, K_SUB, k_local_solve_wave<TS, One>, k_local_solve_wave<TS, Many>, nr, 64, 0, mode, f, conj_in, x);
     else if (c == 1)
       launch2(t, K_SUB, k_local_solve_rhs<TS, One>, k_local_solve_rhs<TS, Many>, nr, 256, 0, mode, f, conj_in, x);
@@ -1677,7 +1983,11 @@ static void local_solve_w(const Target& t, int mode, int f, int conj_in, int x, 
   else
     for (const Problem* p : t.probs) ml = std::max(ml, p->ml);
   const TuneKey key{TUNE_LOCAL_SOLVE, dev, ml, t.blocks(K_SUB), (int)sizeof(TS), nr};
-  run(tune_choice(key, 3, 2, t.st, run));
+  // the workgroup per right-hand side reads the line factors once per
+  // right-hand side (2.3 x the bytes of the other forms at 512^2, measured):
+  // it has to be 3% faster to be chosen
+  static const float weight[4] = {1.f, 1.03f, 1.f, 1.f};
+  run(tune_choice(key, 4, 2, t.st, run, weight));
 }
 
 hipError_t launch_local_solve(const Target& t, int mode, int f, int conj_in, int x) {

@@ -30,7 +30,8 @@ bool TuneKey::operator<(const TuneKey& o) const {
   return std::lexicographical_compare(a, a + 6, b, b + 6);
 }
 
-int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, const std::function<void(int)>& launch) {
+int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, const std::function<void(int)>& launch,
+                const float* weight) {
   {
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_force >= 0) return g_force < ncand ? g_force : fallback;
@@ -57,9 +58,10 @@ int tune_choice(const TuneKey& key, int ncand, int fallback, hipStream_t st, con
     }
     if (!ok) break;
     std::sort(t.begin(), t.end());
-    if (c == 0 || t[1] < best_ms) {
+    const float ms = t[1] * (weight ? weight[c] : 1.f);
+    if (c == 0 || ms < best_ms) {
       best = c;
-      best_ms = t[1];
+      best_ms = ms;
     }
   }
   for (hipEvent_t& e : ev) hipEventDestroy(e);

@@ -54,9 +54,10 @@ def test_tuned_and_default_variants_agree(sf, dim, N, m, prec):
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("N,m", [(64, 8), (96, 32), (40, 20)])
 def test_local_solve_variants_agree(sf, prec, N, m):
-    """The three launch forms of the 2D subdomain solve (one workgroup for every
-    right-hand side, one per right-hand side, one wavefront per right-hand side)
-    give the same FETI-DP solves (1e-11) and iteration counts, for one and for three
+    """The four launch forms of the 2D subdomain solve (one workgroup for every
+    right-hand side, one per right-hand side, one wavefront per right-hand side, one
+    workgroup with a wavefront per right-hand side and the line factors staged once)
+    give the same FETI-DP solves and iteration counts, for one and for three
     right-hand sides, including subdomains of 32 x 32 cells (33-node lines, one per lane
     of a wavefront and no padding) and of 20 x 20.  The forms sum the line products in
     different orders; that rounding, carried through a GMRES solve to a relative
@@ -69,7 +70,7 @@ def test_local_solve_variants_agree(sf, prec, N, m):
     f = torch.tensor(np.stack([W.random_vector(n, 80 + r, complex_=True) for r in range(3)]), device=DEV)
     out = {}
     try:
-        for c in (0, 1, 2):
+        for c in (0, 1, 2, 3):
             sfdp.force_variant(c)
             p = sfdp.Problem(ctx, 2, N, m, prec)
             p.set_beta(1e-4)
@@ -79,7 +80,7 @@ def test_local_solve_variants_agree(sf, prec, N, m):
             p.close()
     finally:
         sfdp.set_tuning(True)
-    for c in (0, 1):
+    for c in (0, 1, 3):
         assert out[c][1] == out[2][1] and out[c][3] == out[2][3], c
         for q in range(3):
             assert _rel(out[c][0][q], out[2][0][q]) < 1e-10, (c, q)
