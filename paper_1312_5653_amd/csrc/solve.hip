@@ -758,6 +758,40 @@ __device__ inline double dpp_shl1(double v) {  // lane p <- lane p + 1
 __device__ inline cd lane_from_below(cd v) { return cd{dpp_shr1(v.x), dpp_shr1(v.y)}; }
 __device__ inline cd lane_from_above(cd v) { return cd{dpp_shl1(v.x), dpp_shl1(v.y)}; }
 
+// Sum of a lane's value and its partner's 32 lanes away, the lower half's
+// value first (v_permlane32_swap: each lane sees lane (l mod 32) and lane
+// 32 + (l mod 32)); .x holds the sum, in every lane of the pair the same bits.
+__device__ inline cd halves_sum(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto sl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto sh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double a = __hiloint2double(sh[0], sl[0]), b = __hiloint2double(sh[1], sl[1]);
+  return cd{a + b, 0.0};
+}
+// Sum over lanes 0 .. 47 (the caller's values are zero from lane 33 on):
+// inclusive scans within each row of 16 lanes (DPP row shifts by 1, 2, 4, 8),
+// then the three row totals read from lanes 15, 31, 47.  Every lane gets it.
+__device__ inline double row_scan16(double v) {
+#define SFDP_ROW_SHR(v, n)                                                                              \
+  __hiloint2double(__builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x110 + (n), 0xf, 0xf, true),      \
+                   __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x110 + (n), 0xf, 0xf, true))
+  v = v + SFDP_ROW_SHR(v, 1);
+  v = v + SFDP_ROW_SHR(v, 2);
+  v = v + SFDP_ROW_SHR(v, 4);
+  v = v + SFDP_ROW_SHR(v, 8);
+#undef SFDP_ROW_SHR
+  return v;
+}
+__device__ inline double lane_value(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ inline cd row32_sum(cd c) {
+  const double x = row_scan16(c.x), y = row_scan16(c.y);
+  return cd{(lane_value(x, 15) + lane_value(x, 31)) + lane_value(x, 47),
+            (lane_value(y, 15) + lane_value(y, 31)) + lane_value(y, 47)};
+}
+
 // Full local solve with E^s for nr <= 4 right-hand sides by one workgroup of
 // four wavefronts (the same results as local_solve_body up to the order of the
 // sums).  Wave w runs the line recursion of right-hand side w: lane p owns node
@@ -773,8 +807,9 @@ __device__ inline cd lane_from_above(cd v) { return cd{dpp_shl1(v.x), dpp_shl1(v
 // per right-hand side reads them once per right-hand side (from L2 when their
 // sweeps stay close).  lds: ls_group_bytes() bytes.
 constexpr int LSG_GE = (ML * ML + 255) / 256;  // line-factor entries staged per thread
-constexpr int LSG_KC = 11;                     // product terms per register chunk
-static_assert(ML % LSG_KC == 0, "the line length is a whole number of product chunks");
+constexpr int LSG_KH = (ML + 1) / 2;           // product terms per wavefront half (17)
+constexpr int LSG_KC0 = 9, LSG_KC1 = LSG_KH - LSG_KC0;  // the two register chunks of a half
+static_assert(ML == 33, "rows 0 .. 31 by lane pairs plus row 32");
 __host__ __device__ constexpr size_t ls_group_bytes() {
   return 4 * ML * ML * sizeof(cd) + 4 * 64 * sizeof(cd) + 2 * ML * ML * sizeof(cd);
 }
@@ -822,7 +857,7 @@ __device__ inline void local_solve_group(const Geo2& g, const Maps2& mp, const R
   const cd* f = f0 + w * rs.nf;
   const cd* uc = uc0 + w * rs.nc;
   const cd* mu = mu0 + w * rs.nmu;
-  if (lane < ML) zl[lane] = cd{0.0, 0.0};
+  zl[lane] = cd{0.0, 0.0};  // entries ml .. 63 stay zero
   if (act) {
     // right-hand side on the r nodes (f / multiplicity; mode 1 minus the corner terms)
     for (int l = lane; l < n2; l += 64) {
@@ -886,6 +921,7 @@ __device__ inline void local_solve_group(const Geo2& g, const Maps2& mp, const R
           const bool fwd = t < ml;
           const cd fnext = (on && t + 1 < nsteps) ? xall[lane + ml * line_of(t + 1)] : cd{0.0, 0.0};
           const cd nb[3] = {lane_from_below(tprev), tprev, lane_from_above(tprev)};
+          cd vz{0.0, 0.0};  // z at this lane's node (zero off the line)
           if (on) {
             cd v{0.0, 0.0};
             if (fwd) {
@@ -903,43 +939,53 @@ __device__ inline void local_solve_group(const Geo2& g, const Maps2& mp, const R
                 if ((zmk[d] >> (j + 1)) & 1) fma_acc(v, cpl[d], nb[d]);
             }
             zl[lane] = v;
+            vz = v;
           }
           wave_lds_sync();
-          // row p of G_j z (G stored transposed: G(p, k) at k ml + p; k clamped to
-          // ml - 1, where zl is zero), four accumulators (k mod 4).  The LDS
-          // operands go to registers in chunks of LSG_KC terms, the next chunk's
-          // reads issued before the current chunk's multiply-adds; the scheduling
-          // barriers keep the compiler from sinking each read to its use (which
-          // costs one LDS round trip per term)
-          const cd* gl = gbuf + (t & 1) * XS + pc;
+          // G_j z (G stored transposed: G(p, k) at k ml + p; k clamped to ml - 1,
+          // where z is zero).  Rows q = 0 .. 31: the half h = lane / 32 of the
+          // wavefront sums the terms k = 17 h .. 17 h + 16 (z is zero from ml on),
+          // lane q + 32 h taking row q, four accumulators (i mod 4); the operands
+          // go to registers a chunk at a time, the next chunk's LDS reads issued
+          // before the current chunk's multiply-adds (the scheduling barriers keep
+          // the compiler from sinking each read to its use).  The two halves' sums
+          // meet by a 32-lane swap.  Row 32 (ml = 33): one term per lane, summed
+          // by row scans and three lane reads.
+          const int q = lane & 31, kb = (lane >> 5) * LSG_KH;
+          const cd* gl = gbuf + (t & 1) * XS + min(q, ml - 1);
           cd acc[4] = {cd{0.0, 0.0}, cd{0.0, 0.0}, cd{0.0, 0.0}, cd{0.0, 0.0}};
-          cd gk[2][LSG_KC];
-          cd zk[2][LSG_KC];
+          cd gk[2][LSG_KC0];
+          cd zk[2][LSG_KC0];
+          auto fetch = [&](int i0, int n, int b) {
 #pragma unroll
-          for (int i = 0; i < LSG_KC; ++i) {
-            gk[0][i] = gl[min(i, ml - 1) * ml];
-            zk[0][i] = zl[i];
-          }
-#pragma unroll
-          for (int c = 0; c < ML / LSG_KC; ++c) {
-            if (c + 1 < ML / LSG_KC) {
-#pragma unroll
-              for (int i = 0; i < LSG_KC; ++i) {
-                const int k = (c + 1) * LSG_KC + i;
-                gk[(c + 1) & 1][i] = gl[min(k, ml - 1) * ml];
-                zk[(c + 1) & 1][i] = zl[k];
+            for (int i = 0; i < LSG_KC0; ++i) {
+              if (i < n) {
+                const int k = kb + i0 + i;
+                gk[b][i] = gl[min(k, ml - 1) * ml];
+                zk[b][i] = zl[k];
               }
             }
-            __builtin_amdgcn_sched_barrier(0);
+          };
+          fetch(0, LSG_KC0, 0);
+          fetch(LSG_KC0, LSG_KC1, 1);
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int i = 0; i < LSG_KC; ++i) {
-              const int k = c * LSG_KC + i;
-              fma_acc(acc[k & 3], gk[c & 1][i], zk[c & 1][i]);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-          }
-          const cd tv = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-          // forward: t_j = G_j z_j; backward: x_j = t_j - G_j A x_j+1
+          for (int i = 0; i < LSG_KC0; ++i) fma_acc(acc[i & 3], gk[0][i], zk[0][i]);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int i = 0; i < LSG_KC1; ++i) fma_acc(acc[(LSG_KC0 + i) & 3], gk[1][i], zk[1][i]);
+          const cd part = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+          // lanes q and q + 32 both get half 0's and half 1's sums of row q
+          const cd lo_hi_x = halves_sum(part.x), lo_hi_y = halves_sum(part.y);
+          cd tv{lo_hi_x.x, lo_hi_y.x};
+          if (ml == ML) {
+            // row 32: term G(32, l) z_l in lane l < 33
+            cd c32{0.0, 0.0};
+            const cd g32 = gbuf[(t & 1) * XS + min(lane, ml - 1) * ml + (ML - 1)];
+            fma_acc(c32, g32, vz);
+            const cd r32 = row32_sum(c32);
+            if (lane == ML - 1) tv = r32;
+          }          // forward: t_j = G_j z_j; backward: x_j = t_j - G_j A x_j+1
           const cd res = fwd ? tv : fcur - tv;
           if (on) xall[lane + ml * j] = res;
           tprev = res;
