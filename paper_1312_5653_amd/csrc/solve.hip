@@ -813,7 +813,7 @@ static_assert(ML == 33, "rows 0 .. 31 by lane pairs plus row 32");
 __host__ __device__ constexpr size_t ls_group_bytes() {
   return 4 * ML * ML * sizeof(cd) + 4 * 64 * sizeof(cd) + 2 * ML * ML * sizeof(cd);
 }
-template <class TS>
+template <class TS, int MLC>
 __device__ inline void local_solve_group(const Geo2& g, const Maps2& mp, const RhsStride& rs, int nr,
                                          const TS* __restrict__ G, int mode, const cd* __restrict__ f0,
                                          int conj_in, const cd* __restrict__ uc0, const cd* __restrict__ mu0,
@@ -825,7 +825,9 @@ __device__ inline void local_solve_group(const Geo2& g, const Maps2& mp, const R
   cd* xall = (cd*)lds + (size_t)w * XS;
   cd* zl = (cd*)lds + 4 * XS + w * 64;
   cd* gbuf = (cd*)(lds + 4 * XS * sizeof(cd) + 4 * 64 * sizeof(cd));  // factors staged in FP64
-  const int ml = g.ml, n2 = ml * ml, ND = g.ND;
+  // MLC = ML: lines of 33 nodes known at compile time (offsets fold into the
+  // LDS and global addressing); MLC = 0: any line length up to ML
+  const int ml = MLC ? MLC : g.ml, n2 = ml * ml, ND = g.ND;
   const TS* Gs = G + (size_t)s * ml * n2;
   const int nsteps = 2 * ml - 1;
   auto line_of = [&](int t) { return t < ml ? t : 2 * ml - 2 - t; };
@@ -956,12 +958,19 @@ __device__ inline void local_solve_group(const Geo2& g, const Maps2& mp, const R
           cd acc[4] = {cd{0.0, 0.0}, cd{0.0, 0.0}, cd{0.0, 0.0}, cd{0.0, 0.0}};
           cd gk[2][LSG_KC0];
           cd zk[2][LSG_KC0];
+          // 33-node lines: terms i < 16 at constant offsets from the half's first
+          // row; the 17th (k = 33 in the upper half, where z is zero) reads row 32
+          const cd* glb = gl + kb * ml;
+          const cd* gl16 = gl + min(kb + LSG_KH - 1, ml - 1) * ml;
           auto fetch = [&](int i0, int n, int b) {
 #pragma unroll
             for (int i = 0; i < LSG_KC0; ++i) {
               if (i < n) {
                 const int k = kb + i0 + i;
-                gk[b][i] = gl[min(k, ml - 1) * ml];
+                if constexpr (MLC == ML)
+                  gk[b][i] = i0 + i < LSG_KH - 1 ? glb[(i0 + i) * ML] : *gl16;
+                else
+                  gk[b][i] = gl[min(k, ml - 1) * ml];
                 zk[b][i] = zl[k];
               }
             }
@@ -1039,15 +1048,16 @@ __device__ inline void local_solve_group(const Geo2& g, const Maps2& mp, const R
 }
 
 // One workgroup of four wavefronts per (instance, subdomain), wave w serving
-// right-hand side w; dynamic LDS ls_group_bytes().
-template <class TS, class Src>
+// right-hand side w; dynamic LDS ls_group_bytes().  MLC = ML when every
+// instance of the launch has 33-node lines, else 0.
+template <class TS, int MLC, class Src>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_local_solve_group(Src src, int mode, int fsel, int conj_in, int xsel) {
   const Dev& d = src.dev();
   if (d.nr <= 0) return;
   extern __shared__ __align__(16) char smem[];
   const RhsStride& rs = d.rs;
-  local_solve_group<TS>(d.g, d.mp, rs, d.nr, (const TS*)d.G, mode, dev_vec(d, fsel), conj_in, d.u0, d.mu,
+  local_solve_group<TS, MLC>(d.g, d.mp, rs, d.nr, (const TS*)d.G, mode, dev_vec(d, fsel), conj_in, d.u0, d.mu,
                         d.Xd, d.Qc, d.Ubuf, mode == 1 ? dev_vec(d, xsel) : nullptr, mode == 1 ? conj_in : 0,
                         src.bx(), smem);
 }
@@ -2008,10 +2018,20 @@ static void local_solve_w(const Target& t, int mode, int f, int conj_in, int x, 
   auto run = [&](int c) {
     if (c == 3) {
       const size_t lds = ls_group_bytes();
-      (void)ensure_lds((const void*)k_local_solve_group<TS, One>, lds);
-      (void)ensure_lds((const void*)k_local_solve_group<TS, Many>, lds);
-      launch2(t, K_SUB, k_local_solve_group<TS, One>, k_local_solve_group<TS, Many>, 1, 256, lds, mode, f,
-              conj_in, x);
+      bool all33 = t.single() ? t.one->ml == ML : true;
+      if (!t.single())
+        for (const Problem* p : t.probs) all33 = all33 && p->ml == ML;
+      if (all33) {
+        (void)ensure_lds((const void*)k_local_solve_group<TS, ML, One>, lds);
+        (void)ensure_lds((const void*)k_local_solve_group<TS, ML, Many>, lds);
+        launch2(t, K_SUB, k_local_solve_group<TS, ML, One>, k_local_solve_group<TS, ML, Many>, 1, 256, lds, mode,
+                f, conj_in, x);
+      } else {
+        (void)ensure_lds((const void*)k_local_solve_group<TS, 0, One>, lds);
+        (void)ensure_lds((const void*)k_local_solve_group<TS, 0, Many>, lds);
+        launch2(t, K_SUB, k_local_solve_group<TS, 0, One>, k_local_solve_group<TS, 0, Many>, 1, 256, lds, mode, f,
+                conj_in, x);
+      }
     } else if (c == 2)
       launch2(t, K_SUB, k_local_solve_wave<TS, One>, k_local_solve_wave<TS, Many>, nr, 64, 0, mode, f, conj_in, x);
     else if (c == 1)
