@@ -39,7 +39,9 @@
  * Memory: every array argument is a DEVICE pointer on the context's GPU
  * (e.g. torch.Tensor.data_ptr() of a CUDA tensor), FP64, contiguous, owned by
  * the caller and accessed in stream order on the stream given at context
- * creation.  Complex vectors are interleaved (re, im) pairs.  Multiple
+ * creation; the calls that take sfdp_opts accept host pointers instead when
+ * opts->host_ptrs = 1 (staged by the library, the call then returns with the
+ * outputs in host memory).  Complex vectors are interleaved (re, im) pairs.  Multiple
  * right-hand sides are stored one after another (column-major n x nrhs).
  * The library owns factors and workspaces; their device memory is charged
  * against the context's memory budget.
@@ -132,6 +134,14 @@ typedef struct {
                        at 3e-7 or 1e-5, and the second step corrects it, so a
                        looser first solve saves GMRES iterations; set it to
                        tol_inner for the same tolerance in every step */
+  int host_ptrs;    /* 1: the array arguments of the call are host pointers
+                       (sfdp_solve_range_space, sfdp_solve_full_space,
+                       sfdp_apply_schur_inv, sfdp_feti_solve,
+                       sfdp_elastic_forward): the library copies the inputs
+                       into a device buffer the problem keeps (grown on
+                       demand, charged to the memory budget), runs the call
+                       and copies the outputs back before returning [0:
+                       device pointers].  SFDP_E_INVALID for other values */
 } sfdp_opts;
 
 /* Per-solve report. */
@@ -222,6 +232,11 @@ sfdp_status sfdp_ctx_create(int device, size_t mem_budget_bytes, void* stream, s
  * them is alive: destroy those first.  NULL is a no-op (SFDP_OK). */
 sfdp_status sfdp_ctx_destroy(sfdp_ctx* ctx);
 const char* sfdp_last_error(void);
+/* Revision of the structures and calls declared here: 2 since
+ * sfdp_opts.host_ptrs (host arrays staged by the library).  A binding reads it
+ * before relying on something a library built from older sources lacks (an
+ * older library would take host addresses for device ones). */
+int sfdp_abi_version(void);
 
 /* Set up the mesh, the subdomain partition and the interface maps (Sec. 5:
  * signed Boolean matrices, corners) for the problem class described above. */

@@ -97,6 +97,42 @@ void dfree(Problem& p, void*& ptr, size_t bytes) {
   ptr = nullptr;
 }
 
+// ---- host-array staging (sfdp_opts.host_ptrs) ----
+// The calls that take sfdp_opts accept host arrays: inputs go into a device
+// buffer the problem keeps (grown on demand, charged to the memory budget),
+// the call runs on device pointers with host_ptrs cleared, and the outputs
+// are copied back on the context's stream before the call returns.
+namespace {
+bool host_ptrs(const sfdp_opts* o) { return o && o->host_ptrs == 1; }
+sfdp_status check_host_ptrs(const sfdp_opts* o) {
+  if (o && o->host_ptrs != 0 && o->host_ptrs != 1) return fail(SFDP_E_INVALID, "host_ptrs must be 0 or 1");
+  return SFDP_OK;
+}
+sfdp_status stage_area(Problem& p, size_t doubles, double** d) {
+  if (doubles > p.stage_n) {
+    dfree(p, (void*&)p.stage, sizeof(double) * p.stage_n);
+    p.stage_n = 0;
+    sfdp_status s = dalloc(p, (void**)&p.stage, sizeof(double) * doubles);
+    if (s) return s;
+    p.stage_n = doubles;
+  }
+  *d = p.stage;
+  return SFDP_OK;
+}
+sfdp_status stage_in(Problem& p, double* d, const double* h, size_t n) {
+  HIPCHK(hipMemcpyAsync(d, h, sizeof(double) * n, hipMemcpyHostToDevice, p.ctx->stream));
+  return SFDP_OK;
+}
+sfdp_status stage_out(Problem& p, double* h, const double* d, size_t n) {
+  HIPCHK(hipMemcpyAsync(h, d, sizeof(double) * n, hipMemcpyDeviceToHost, p.ctx->stream));
+  return SFDP_OK;
+}
+sfdp_status stage_done(Problem& p) {
+  HIPCHK(hipStreamSynchronize(p.ctx->stream));
+  return SFDP_OK;
+}
+}  // namespace
+
 // Build the 2D partition and interface maps on the host.
 // Largest coarse problem for which the edge-augmented space is the default.
 constexpr int KAUG_DEFAULT_MAX = 1024;
@@ -1203,6 +1239,7 @@ void destroy_problem(Problem* p) {
   if (p->gh) hipHostFree(p->gh);
   if (p->fsw) hipFree(p->fsw);
   if (p->fsh) hipHostFree(p->fsh);
+  if (p->stage) hipFree(p->stage);
   for (hipEvent_t e : p->ev_pool) hipEventDestroy(e);
   graphs_clear(*p);
   p->ctx->used -= std::min(p->ctx->used, p->bytes);
@@ -1422,6 +1459,7 @@ struct sfdp_batch {
 extern "C" {
 
 const char* sfdp_last_error(void) { return g_err.c_str(); }
+int sfdp_abi_version(void) { return 2; }
 
 sfdp_status sfdp_ctx_create(int device, size_t mem_budget_bytes, void* stream, sfdp_ctx** out) {
   if (!out) return fail(SFDP_E_INVALID, "out is NULL");
@@ -1530,7 +1568,20 @@ sfdp_status sfdp_elastic_forward(sfdp_problem* p, int nrhs, const double* f, dou
                                  int* krylov_its) {
   if (!p || !f || !u || nrhs <= 0) return fail(SFDP_E_INVALID, "bad arguments");
   if (!p->el) return fail(SFDP_E_INVALID, "not an elasticity problem");
+  sfdp_status s = check_host_ptrs(opts);
+  if (s) return s;
   HIPCHK(hipSetDevice(p->ctx->device));
+  if (host_ptrs(opts)) {
+    const size_t n = (size_t)p->n_free * nrhs;
+    double* d = nullptr;
+    if ((s = stage_area(*p, 2 * n, &d)) || (s = stage_in(*p, d, f, n))) return s;
+    sfdp_opts o = *opts;
+    o.host_ptrs = 0;
+    s = el_forward(*p, nrhs, d, d + n, &o, krylov_its);
+    if (s) return s;
+    if ((s = stage_out(*p, u, d + n, n))) return s;
+    return stage_done(*p);
+  }
   return el_forward(*p, nrhs, f, u, opts, krylov_its);
 }
 
@@ -1600,12 +1651,25 @@ sfdp_status sfdp_set_beta(sfdp_problem* p, double beta) {
   return SFDP_OK;
 }
 
+
 sfdp_status sfdp_feti_solve(sfdp_problem* p, int conj_z, int nrhs, const double* f, double* x,
                             const sfdp_opts* opts, int* krylov_its) {
   sfdp_status s = check_ready(p);
   if (s) return s;
   if (nrhs <= 0 || !f || !x) return fail(SFDP_E_INVALID, "bad arguments");
+  if ((s = check_host_ptrs(opts))) return s;
   HIPCHK(hipSetDevice(p->ctx->device));
+  if (host_ptrs(opts)) {
+    const size_t n = 2 * (size_t)p->n_free * nrhs;  // complex, interleaved
+    double* d = nullptr;
+    if ((s = stage_area(*p, 2 * n, &d)) || (s = stage_in(*p, d, f, n))) return s;
+    sfdp_opts o = *opts;
+    o.host_ptrs = 0;
+    s = sfdp_feti_solve(p, conj_z, nrhs, d, d + n, &o, krylov_its);
+    if (s) return s;
+    if ((s = stage_out(*p, x, d + n, n))) return s;
+    return stage_done(*p);
+  }
   if (p->el) return el_feti(*p, conj_z ? 1 : 0, nrhs, (const cd*)f, (cd*)x, opts, krylov_its);
   double tk, ti;
   int mo, kmax;
@@ -1722,7 +1786,23 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
   sfdp_status s = check_ready(p);
   if (s) return s;
   if (nrhs <= 0 || !ybar || !y || !u || !lam) return fail(SFDP_E_INVALID, "bad arguments");
+  if ((s = check_host_ptrs(opts))) return s;
   HIPCHK(hipSetDevice(p->ctx->device));
+  if (host_ptrs(opts)) {
+    const size_t n = (size_t)p->n_free * nrhs, nb = yc ? (size_t)p->n_bdry * nrhs : 0;
+    double* d = nullptr;
+    if ((s = stage_area(*p, 4 * n + nb, &d)) || (s = stage_in(*p, d, ybar, n))) return s;
+    if (yc && (s = stage_in(*p, d + 4 * n, yc, nb))) return s;
+    sfdp_opts o = *opts;
+    o.host_ptrs = 0;
+    s = sfdp_solve_range_space(p, nrhs, d, yc ? d + 4 * n : nullptr, d + n, d + 2 * n, d + 3 * n, &o, info);
+    if (s != SFDP_OK && s != SFDP_E_NOCONV) return s;
+    sfdp_status c;
+    if ((c = stage_out(*p, y, d + n, n)) || (c = stage_out(*p, u, d + 2 * n, n)) ||
+        (c = stage_out(*p, lam, d + 3 * n, n)) || (c = stage_done(*p)))
+      return c;
+    return s;
+  }
   if (p->el) {
     if (yc) return fail(SFDP_E_INVALID, "elasticity problems have no Dirichlet data");
     return el_range_space(*p, nrhs, ybar, y, u, lam, opts, info);
@@ -1892,6 +1972,19 @@ sfdp_status sfdp_apply_schur_inv(sfdp_problem* p, int nrhs, const double* r, dou
   if (s) return s;
   if (nrhs <= 0 || !r || !z) return fail(SFDP_E_INVALID, "bad arguments");
   if (opts && opts->schur_block != 0 && opts->schur_block != 1) return fail(SFDP_E_INVALID, "schur_block must be 0 or 1");
+  if ((s = check_host_ptrs(opts))) return s;
+  if (host_ptrs(opts)) {
+    HIPCHK(hipSetDevice(p->ctx->device));
+    const size_t n = (size_t)p->n_free * nrhs;
+    double* d = nullptr;
+    if ((s = stage_area(*p, 2 * n, &d)) || (s = stage_in(*p, d, r, n))) return s;
+    sfdp_opts o = *opts;
+    o.host_ptrs = 0;
+    s = sfdp_apply_schur_inv(p, nrhs, d, d + n, &o, info);
+    if (s) return s;
+    if ((s = stage_out(*p, z, d + n, n))) return s;
+    return stage_done(*p);
+  }
   if (p->el) {
     HIPCHK(hipSetDevice(p->ctx->device));
     return el_schur_inv(*p, nrhs, r, z, opts, info);
@@ -1963,6 +2056,23 @@ sfdp_status sfdp_solve_full_space(sfdp_problem* p, int nrhs, const double* ybar,
   if (nrhs <= 0 || !ybar || !y || !u || !lam) return fail(SFDP_E_INVALID, "bad arguments");
   if (p->el) return fail(SFDP_E_INVALID, "the full-space method covers the Poisson problems only");
   if (p->N > 1025) return fail(SFDP_E_INVALID, "the full-space method needs n_elem <= 1025");
+  if ((s = check_host_ptrs(opts))) return s;
+  if (host_ptrs(opts)) {
+    HIPCHK(hipSetDevice(p->ctx->device));
+    const size_t n = (size_t)p->n_free * nrhs, nb = yc ? (size_t)p->n_bdry * nrhs : 0;
+    double* d = nullptr;
+    if ((s = stage_area(*p, 4 * n + nb, &d)) || (s = stage_in(*p, d, ybar, n))) return s;
+    if (yc && (s = stage_in(*p, d + 4 * n, yc, nb))) return s;
+    sfdp_opts o = *opts;
+    o.host_ptrs = 0;
+    s = sfdp_solve_full_space(p, nrhs, d, yc ? d + 4 * n : nullptr, d + n, d + 2 * n, d + 3 * n, &o, info);
+    if (s != SFDP_OK && s != SFDP_E_NOCONV) return s;
+    sfdp_status c;
+    if ((c = stage_out(*p, y, d + n, n)) || (c = stage_out(*p, u, d + 2 * n, n)) ||
+        (c = stage_out(*p, lam, d + 3 * n, n)) || (c = stage_done(*p)))
+      return c;
+    return s;
+  }
   double tk, ti;
   int mo, kmax;
   defaults(p->prec, opts, tk, ti, mo, kmax, p->dim);

@@ -334,6 +334,8 @@ struct Problem {
   Elastic* el = nullptr;  // elasticity instance (dim = 3, three dofs per node)
   double* fsw = nullptr;   // full-space method: device vectors (9 x 3 n_free + sums)
   double* fsh = nullptr;   // and its pinned host scalars
+  double* stage = nullptr; // device copies of host arrays (sfdp_opts.host_ptrs), stage_n doubles
+  size_t stage_n = 0;
   // index maps (device)
   int *dloc = nullptr, *dmid = nullptr, *dpart = nullptr, *nd = nullptr, *cloc = nullptr,
       *cgid = nullptr, *muown = nullptr, *mufree = nullptr, *cown = nullptr, *cfree = nullptr,

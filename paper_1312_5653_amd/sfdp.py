@@ -18,7 +18,7 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_NOCONV", -4: "E_DEVICE
 Q_SINV, Q_SBB, Q_PHI, Q_COARSE, Q_COARSE_INV = 0, 1, 2, 3, 4
 
 EXPORTS = [
-    "sfdp_ctx_create", "sfdp_ctx_destroy", "sfdp_last_error", "sfdp_problem_create",
+    "sfdp_ctx_create", "sfdp_ctx_destroy", "sfdp_last_error", "sfdp_abi_version", "sfdp_problem_create",
     "sfdp_problem_sizes", "sfdp_problem_destroy", "sfdp_set_beta", "sfdp_solve_range_space",
     "sfdp_apply_schur_inv", "sfdp_feti_solve", "sfdp_apply_operator", "sfdp_kkt_residual",
     "sfdp_inspect", "sfdp_interface_apply", "sfdp_timing_enable", "sfdp_kernel_times",
@@ -39,7 +39,8 @@ class SfdpError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("tol_kkt", ctypes.c_double), ("tol_inner", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("max_krylov", ctypes.c_int), ("factors", ctypes.c_int),
-                ("batch", ctypes.c_int), ("schur_block", ctypes.c_int), ("tol_inner_first", ctypes.c_double)]
+                ("batch", ctypes.c_int), ("schur_block", ctypes.c_int), ("tol_inner_first", ctypes.c_double),
+                ("host_ptrs", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -104,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_ctx_destroy.argtypes = [P]
     lib.sfdp_ctx_destroy.restype = ctypes.c_int
     lib.sfdp_last_error.restype = ctypes.c_char_p
+    lib.sfdp_abi_version.restype = ctypes.c_int
+    lib.sfdp_abi_version.argtypes = []
     lib.sfdp_problem_create.argtypes = [P, I, I, I, I, ctypes.POINTER(P)]
     lib.sfdp_problem_sizes.argtypes = [P, ctypes.POINTER(Sizes)]
     lib.sfdp_set_coarse_space.argtypes = [P, I]
@@ -162,17 +165,27 @@ def _check(st: int, allow_noconv: bool = False):
     raise SfdpError(st, _lib.sfdp_last_error().decode())
 
 
-def _ptr(t):
+def _ptr(t, host=False):
+    """Address of a contiguous CUDA tensor (host=True: of a CPU tensor, for the
+    calls that stage host arrays)."""
     if t is None:
         return None
-    if not t.is_cuda or not t.is_contiguous():
-        raise ValueError("arrays must be contiguous CUDA tensors")
+    if not t.is_contiguous() or t.is_cuda == host:
+        raise ValueError("arrays must be contiguous " + ("CPU" if host else "CUDA") + " tensors")
+    if host and _lib.sfdp_abi_version() < 2:
+        raise RuntimeError("this libsfdp.so predates host-array staging; rebuild it")
     return ctypes.c_void_p(t.data_ptr())
 
 
 def _opts(tol_kkt=0.0, tol_inner=0.0, max_outer=0, max_krylov=0, batch=0, factors=0, schur_block=0,
-          tol_inner_first=0.0):
-    return Opts(tol_kkt, tol_inner, max_outer, max_krylov, factors, batch, schur_block, tol_inner_first)
+          tol_inner_first=0.0, host_ptrs=0):
+    return Opts(tol_kkt, tol_inner, max_outer, max_krylov, factors, batch, schur_block, tol_inner_first,
+                host_ptrs)
+
+
+def _host(t):
+    """1 when t is a host (CPU) tensor: the library stages it (sfdp_opts.host_ptrs)."""
+    return 1 if t.device.type == "cpu" else 0
 
 
 class Context:
@@ -250,8 +263,10 @@ class Problem:
         u = torch.empty_like(ybar) if u is None else u
         lam = torch.empty_like(ybar) if lam is None else lam
         infos = (Info * nrhs)()
-        o = _opts(**opts)
-        st = _lib.sfdp_solve_range_space(self._h, nrhs, _ptr(ybar), _ptr(yc), _ptr(y), _ptr(u), _ptr(lam),
+        o = _opts(**{"host_ptrs": _host(ybar), **opts})
+        h = bool(o.host_ptrs)
+        st = _lib.sfdp_solve_range_space(self._h, nrhs, _ptr(ybar, h), _ptr(yc, h), _ptr(y, h), _ptr(u, h),
+                                         _ptr(lam, h),
                                          ctypes.byref(o), infos)
         _check(st, allow_noconv=True)
         return y, u, lam, [i.as_dict() for i in infos], st
@@ -266,8 +281,10 @@ class Problem:
         u = torch.empty_like(ybar) if u is None else u
         lam = torch.empty_like(ybar) if lam is None else lam
         infos = (Info * nrhs)()
-        o = _opts(**opts)
-        st = _lib.sfdp_solve_full_space(self._h, nrhs, _ptr(ybar), _ptr(yc), _ptr(y), _ptr(u), _ptr(lam),
+        o = _opts(**{"host_ptrs": _host(ybar), **opts})
+        h = bool(o.host_ptrs)
+        st = _lib.sfdp_solve_full_space(self._h, nrhs, _ptr(ybar, h), _ptr(yc, h), _ptr(y, h), _ptr(u, h),
+                                        _ptr(lam, h),
                                         ctypes.byref(o), infos)
         _check(st, allow_noconv=True)
         return y, u, lam, [i.as_dict() for i in infos], st
@@ -278,8 +295,9 @@ class Problem:
         nrhs = 1 if r.dim() == 1 else r.shape[0]
         z = torch.empty_like(r) if z is None else z
         infos = (Info * nrhs)()
-        o = _opts(**opts)
-        _check(_lib.sfdp_apply_schur_inv(self._h, nrhs, _ptr(r), _ptr(z), ctypes.byref(o), infos))
+        o = _opts(**{"host_ptrs": _host(r), **opts})
+        h = bool(o.host_ptrs)
+        _check(_lib.sfdp_apply_schur_inv(self._h, nrhs, _ptr(r, h), _ptr(z, h), ctypes.byref(o), infos))
         return z, [i.as_dict() for i in infos]
 
     def feti_solve(self, f, conj_z: bool = False, x=None, **opts):
@@ -287,8 +305,9 @@ class Problem:
         nrhs = 1 if f.dim() == 1 else f.shape[0]
         x = torch.empty_like(f) if x is None else x
         its = (ctypes.c_int * nrhs)()
-        o = _opts(**opts)
-        _check(_lib.sfdp_feti_solve(self._h, int(conj_z), nrhs, _ptr(f), _ptr(x), ctypes.byref(o), its))
+        o = _opts(**{"host_ptrs": _host(f), **opts})
+        h = bool(o.host_ptrs)
+        _check(_lib.sfdp_feti_solve(self._h, int(conj_z), nrhs, _ptr(f, h), _ptr(x, h), ctypes.byref(o), its))
         return x, list(its)[:nrhs]
 
     def apply_operator(self, which: str, x, xc=None, y=None):
@@ -370,8 +389,9 @@ class ElasticProblem(Problem):
         nrhs = 1 if f.dim() == 1 else f.shape[0]
         u = torch.empty_like(f) if u is None else u
         its = (ctypes.c_int * nrhs)()
-        o = _opts(**opts)
-        _check(_lib.sfdp_elastic_forward(self._h, nrhs, _ptr(f), _ptr(u), ctypes.byref(o), its))
+        o = _opts(**{"host_ptrs": _host(f), **opts})
+        h = bool(o.host_ptrs)
+        _check(_lib.sfdp_elastic_forward(self._h, nrhs, _ptr(f, h), _ptr(u, h), ctypes.byref(o), its))
         return u, list(its)[:nrhs]
 
 

@@ -57,3 +57,38 @@ def test_destroying_a_null_context_is_a_no_op(lib):
     lib.sfdp_ctx_destroy.argtypes = [ctypes.c_void_p]
     lib.sfdp_ctx_destroy.restype = ctypes.c_int
     assert lib.sfdp_ctx_destroy(None) == 0
+
+
+def test_binding_structures_match_the_header(tmp_path):
+    """Size and field offsets of every structure of include/sfdp.h, as the C
+    compiler lays it out, equal those of the binding's ctypes structures (a field
+    added on one side only would shift everything after it)."""
+    import shutil
+    import subprocess
+
+    from paper_1312_5653_amd import sfdp
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = {"sfdp_opts": sfdp.Opts, "sfdp_info": sfdp.Info, "sfdp_request": sfdp.Request,
+             "sfdp_server_info": sfdp.ServerInfo, "sfdp_timing": sfdp.Timing, "sfdp_sizes": sfdp.Sizes}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sfdp.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            name, field, val = line.split()
+            got[(name, field)] = int(val)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
