@@ -798,14 +798,18 @@ __device__ inline cd row32_sum(cd c) {
 // p of every line, keeps the previous step's result at its node in a register
 // (the neighbours' values come from the adjacent lanes by DPP shifts) and reads
 // its node's value of the current line from LDS one step ahead, so the only LDS
-// round trip inside a step is the line product.  The workgroup stages every
-// line factor into LDS once for all right-hand sides: the factor of step t + 1
-// is copied from a ring of GRD register copies (each loaded GRD - 1 steps
-// before it is stored), widened to FP64, into one of two LDS slots while step t
-// reads the other, and one workgroup barrier per step separates the two.  The
-// factors leave HBM once per subdomain, where one workgroup or one wavefront
-// per right-hand side reads them once per right-hand side (from L2 when their
-// sweeps stay close).  lds: ls_group_bytes() bytes.
+// round trip inside a step is the line product.  That product runs by lane
+// pairs: the two halves of the wavefront each sum 17 of the 33 terms of rows
+// 0 .. 31 and a 32-lane swap joins them; row 32 is one term per lane summed by
+// row scans.  The workgroup stages every line factor into LDS once for all
+// right-hand sides: the factor of step t + 1 is copied from a ring of GRD
+// register copies (each loaded GRD - 1 steps before it is stored), widened to
+// FP64, into one of two LDS slots while step t reads the other, and one
+// workgroup barrier per step separates the two.  The factors leave HBM once per
+// subdomain, where one workgroup or one wavefront per right-hand side reads
+// them once per right-hand side (from L2 when their sweeps stay close).
+// MLC = ML compiles the form for 33-node lines (constant offsets), MLC = 0 any
+// line length up to ML.  lds: ls_group_bytes() bytes.
 constexpr int LSG_GE = (ML * ML + 255) / 256;  // line-factor entries staged per thread
 constexpr int LSG_KH = (ML + 1) / 2;           // product terms per wavefront half (17)
 constexpr int LSG_KC0 = 9, LSG_KC1 = LSG_KH - LSG_KC0;  // the two register chunks of a half
@@ -825,8 +829,6 @@ __device__ inline void local_solve_group(const Geo2& g, const Maps2& mp, const R
   cd* xall = (cd*)lds + (size_t)w * XS;
   cd* zl = (cd*)lds + 4 * XS + w * 64;
   cd* gbuf = (cd*)(lds + 4 * XS * sizeof(cd) + 4 * 64 * sizeof(cd));  // factors staged in FP64
-  // MLC = ML: lines of 33 nodes known at compile time (offsets fold into the
-  // LDS and global addressing); MLC = 0: any line length up to ML
   const int ml = MLC ? MLC : g.ml, n2 = ml * ml, ND = g.ND;
   const TS* Gs = G + (size_t)s * ml * n2;
   const int nsteps = 2 * ml - 1;
