@@ -424,6 +424,45 @@ __global__ void kel_corner_sum(int nC, StrE st, const int* cown, const cd* Wc, c
   out[r * st.c + c] = acc;
 }
 
+// Y[r][s ystride + d] += phis (Phi_s[d] . u_c(B_c s)) for the Delta dofs d < nds[s]
+// of subdomain s = blockIdx.x and every right-hand side r < nr: the subdomain's
+// EQ corner values of u_c are staged in LDS once (zero for a clamped slot, which
+// adds nothing), then every thread forms its rows' sums with all its Phi loads
+// independent of each other.  The same sums, in the same order, as the corner
+// term of kel_scatter, added once per Delta dof instead of once per multiplier
+// side.
+template <class TS>
+__global__ void __launch_bounds__(256) kel_phi_add(GeoE g, MapsE mp, StrE st, int nr, const TS* Phi,
+                                                   const cd* uc, double phis, cd* Y, int64_t yr, int ystride) {
+  __shared__ cd ucs[EQ][R3];
+  const int s = blockIdx.x;
+  if (threadIdx.x < EQ * R3) {
+    const int q = threadIdx.x / R3, r = threadIdx.x % R3;
+    const int c = mp.cg[s * EQ + q];
+    ucs[q][r] = (c >= 0 && r < nr) ? uc[r * st.c + c] : cd{0.0, 0.0};
+  }
+  __syncthreads();
+  const int nd = mp.nds[s];
+  for (int d = threadIdx.x; d < nd; d += blockDim.x) {
+    const TS* ph = Phi + ((size_t)s * g.ND + d) * EQ;
+    cd acc[R3];
+#pragma unroll
+    for (int r = 0; r < R3; ++r) acc[r] = cd{0.0, 0.0};
+#pragma unroll 6
+    for (int q = 0; q < EQ; ++q) {
+      const cd p = ld64(ph[q]);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) fma_acc(acc[r], p, ucs[q][r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R3; ++r) {
+      if (r >= nr) break;
+      cd* y = Y + r * yr + (size_t)s * ystride + d;
+      *y = *y + phis * acc[r];
+    }
+  }
+}
+
 // Per multiplier k with copies (s+, d+) and (s-, d-), for every right-hand side r:
 //   out_k = sc_k (v+ - v-),  v = Y[s ystride + o_s + d] + phis (Phi_s[d] . u_c(B_c s))
 // with o_s = ni[s] when `at_ni` (Y holds whole r vectors), else 0, and
@@ -552,11 +591,18 @@ struct OpsE {
     hipLaunchKernelGGL(k3_dense_mv, dim3((g.nC + 3) / 4), dim3(256), 0, st, g.nC, sr.c, nr, Kinv, (const cd*)el.gc,
                        out);
   }
-  // out = F_DP x
+  // out = F_DP x: the corner term goes into the local products (el.Y, scratch
+  // until the next local product) once per Delta dof, then a plain scatter
   void apply_F(const cd* x, int64_t xr, cd* out, int64_t orr) {
     local(el.Sinv, el.Phi, 0, x, xr, el.Y, el.Wc);
     coarse(nullptr, el.uc);
-    scatter(el.Y, sr.y, g.ND, 0, true, 1.0, 0, out, orr);
+    if (s32)
+      hipLaunchKernelGGL(kel_phi_add<cf>, dim3(g.nsub), dim3(256), 0, st, g, mp, sr, nr, (const cf*)el.Phi,
+                         (const cd*)el.uc, 1.0, el.Y, sr.y, g.ND);
+    else
+      hipLaunchKernelGGL(kel_phi_add<cd>, dim3(g.nsub), dim3(256), 0, st, g, mp, sr, nr, (const cd*)el.Phi,
+                         (const cd*)el.uc, 1.0, el.Y, sr.y, g.ND);
+    scatter(el.Y, sr.y, g.ND, 0, false, 0.0, 0, out, orr);
   }
   // out = W B_r S_bb B_r^T W x
   void apply_P(const cd* x, int64_t xr, cd* out, int64_t orr) {

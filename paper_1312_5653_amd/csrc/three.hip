@@ -381,6 +381,43 @@ __global__ void k3_dense_mv(int n, int64_t stride, int nr, const cd* A, const cd
   }
 }
 
+// Y[r][s ystride + d] += phis (Phi_s[d] . u_c(B_c s)) for the Delta nodes d < nds[s]
+// of subdomain s = blockIdx.x and every right-hand side r < nr: the subdomain's
+// eight corner values of u_c staged in LDS once (zero for a Dirichlet slot,
+// which adds nothing), the same sums in the same order as the corner term of
+// k3_scatter, added once per Delta node instead of once per multiplier side.
+template <class TS>
+__global__ void __launch_bounds__(256) k3_phi_add(Geo3 g, Maps3 mp, Str3 st, int nr, const TS* Phi, const cd* uc,
+                                                  double phis, cd* Y, int64_t yr, int ystride) {
+  __shared__ cd ucs[8][R3];
+  const int s = blockIdx.x;
+  if (threadIdx.x < 8 * R3) {
+    const int q = threadIdx.x / R3, r = threadIdx.x % R3;
+    const int c = mp.cg[s * 8 + q];
+    ucs[q][r] = (c >= 0 && r < nr) ? uc[r * st.c + c] : cd{0.0, 0.0};
+  }
+  __syncthreads();
+  const int nd = mp.nds[s];
+  for (int d = threadIdx.x; d < nd; d += blockDim.x) {
+    const TS* ph = Phi + ((size_t)s * g.ND + d) * 8;
+    cd acc[R3];
+#pragma unroll
+    for (int r = 0; r < R3; ++r) acc[r] = cd{0.0, 0.0};
+#pragma unroll 4
+    for (int q = 0; q < 8; ++q) {
+      const cd pq = ld64(ph[q]);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) fma_acc(acc[r], pq, ucs[q][r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R3; ++r) {
+      if (r >= nr) break;
+      cd* y = Y + r * yr + (size_t)s * ystride + d;
+      *y = *y + phis * acc[r];
+    }
+  }
+}
+
 // Per multiplier k with owners (s+, d+) and (s-, d-), right-hand side r = blockIdx.y:
 //   out_k = sc_k (v+ - v-),  v = Y[s ystride + yoff + d] + phis (Phi_s[d] . u_c(B_c s))
 // with sc_k = 1 / multiplicity when `scale`, else 1.  Y has right-hand-side
@@ -794,10 +831,18 @@ struct Ops3 {
                        (const cd*)T.gc, out);
   }
   // out = F_DP x (x and out with right-hand-side strides xr, orr)
+  // (the corner term goes into the local products T.Y, scratch until the next
+  // local product, once per Delta node; then a plain scatter)
   void apply_F(const cd* x, int64_t xr, cd* out, int64_t orr) {
     local(T.Sinv, T.Phi, 0, x, xr, T.Y, T.Wc);
     coarse(nullptr, T.uc);
-    scatter(T.Y, sr.y, g.ND, 0, true, 1.0, 0, out, orr);
+    if (s32)
+      hipLaunchKernelGGL(k3_phi_add<cf>, dim3(g.nsub), dim3(256), 0, st, g, mp, sr, nr, (const cf*)T.Phi,
+                         (const cd*)T.uc, 1.0, T.Y, sr.y, g.ND);
+    else
+      hipLaunchKernelGGL(k3_phi_add<cd>, dim3(g.nsub), dim3(256), 0, st, g, mp, sr, nr, (const cd*)T.Phi,
+                         (const cd*)T.uc, 1.0, T.Y, sr.y, g.ND);
+    scatter(T.Y, sr.y, g.ND, 0, false, 0.0, 0, out, orr);
   }
   // out = W B_r S_bb B_r^T W x
   void apply_P(const cd* x, int64_t xr, cd* out, int64_t orr) {
