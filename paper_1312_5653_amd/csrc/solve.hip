@@ -1116,23 +1116,53 @@ __global__ void k_coarse_rhs(Src src, int fsel, int conj_in) {
   fcs[c] = v;
 }
 
-// u0 = Kinv x (x = fcs or ymin; coarse inverse over nK unknowns), one wavefront per row.
+// u0_r = Kinv x_r (x from dev_vec(xsel)) for every right-hand side r < nr: one
+// wavefront per coarse row reads that row of the coarse inverse once for all
+// right-hand sides, four of its strides' loads issued before their
+// multiply-adds; each right-hand side's terms in the order k = lane, lane + 64,
+// ..., then the wavefront sum.
 template <class Src>
 __global__ void k_dense_mv(Src src, int xsel) {
   const Dev& d = src.dev();
-  if ((int)blockIdx.y >= d.nr) return;
+  const int nr = d.nr;
+  if (nr <= 0) return;
   const int n = d.g.nK, row = src.bx();
   const int64_t stride = d.rs.nc;
-  const cd* __restrict__ A = d.Kinv;
-  const cd* x = dev_vec(d, xsel) + blockIdx.y * stride;
-  cd* y = d.u0 + blockIdx.y * stride;
-  cd acc{0.0, 0.0};
-  for (int k = threadIdx.x; k < n; k += 64) fma_acc(acc, A[(size_t)row * n + k], x[k]);
-  for (int off = 32; off > 0; off >>= 1) {
-    acc.x += __shfl_down(acc.x, off, 64);
-    acc.y += __shfl_down(acc.y, off, 64);
+  const cd* __restrict__ A = d.Kinv + (size_t)row * n;
+  const cd* x = dev_vec(d, xsel);
+  cd acc[NRMAX];
+#pragma unroll
+  for (int r = 0; r < NRMAX; ++r) acc[r] = cd{0.0, 0.0};
+  int k = threadIdx.x;
+  for (; k + 192 < n; k += 256) {
+    cd a[4], xv[4][NRMAX];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = A[k + 64 * u];
+#pragma unroll
+      for (int r = 0; r < NRMAX; ++r) xv[u][r] = r < nr ? x[r * stride + k + 64 * u] : cd{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < NRMAX; ++r) fma_acc(acc[r], a[u], xv[u][r]);
   }
-  if (threadIdx.x == 0) y[row] = acc;
+  for (; k < n; k += 64) {
+    const cd a = A[k];
+#pragma unroll
+    for (int r = 0; r < NRMAX; ++r)
+      if (r < nr) fma_acc(acc[r], a, x[r * stride + k]);
+  }
+#pragma unroll
+  for (int r = 0; r < NRMAX; ++r) {
+    if (r >= nr) break;
+    cd v = acc[r];
+    for (int off = 32; off > 0; off >>= 1) {
+      v.x += __shfl_down(v.x, off, 64);
+      v.y += __shfl_down(v.y, off, 64);
+    }
+    if (threadIdx.x == 0) d.u0[r * stride + row] = v;
+  }
 }
 
 // d_k = sum over the two subdomains of sign * (Xd - sum over coarse slots Phi u0)
@@ -2069,7 +2099,7 @@ hipError_t launch_local_solve(const Target& t, int mode, int f, int conj_in, int
 hipError_t launch_coarse_rhs(const Target& t, int f, int conj_in) {
   launch2(t, K_SUB, k_edge_rhs<One>, k_edge_rhs<Many>, NRMAX, 256, 0);
   launch2(t, K_NC128, k_coarse_rhs<One>, k_coarse_rhs<Many>, NRMAX, 128, 0, f, conj_in);
-  launch2(t, K_NC, k_dense_mv<One>, k_dense_mv<Many>, NRMAX, 64, 0, (int)V_FCS);
+  launch2(t, K_NC, k_dense_mv<One>, k_dense_mv<Many>, 1, 64, 0, (int)V_FCS);
   return hipGetLastError();
 }
 
@@ -2278,7 +2308,7 @@ hipError_t launch_recover_coarse(const Target& t) {
   if (t.s32()) launch2(t, K_SUB, k_frct<cf, One>, k_frct<cf, Many>, NRMAX, 64 * NQ, 0);
   else launch2(t, K_SUB, k_frct<cd, One>, k_frct<cd, Many>, NRMAX, 64 * NQ, 0);
   launch2(t, K_NC128, k_corner_sum<One>, k_corner_sum<Many>, NRMAX, 128, 0);
-  launch2(t, K_NC, k_dense_mv<One>, k_dense_mv<Many>, NRMAX, 64, 0, (int)V_YMIN);
+  launch2(t, K_NC, k_dense_mv<One>, k_dense_mv<Many>, 1, 64, 0, (int)V_YMIN);
   launch2(t, K_NMU256, k_add_edge_mult<One>, k_add_edge_mult<Many>, NRMAX, 256, 0);
   return hipGetLastError();
 }

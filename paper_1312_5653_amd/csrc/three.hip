@@ -367,7 +367,23 @@ __global__ void k3_dense_mv(int n, int64_t stride, int nr, const cd* A, const cd
   cd acc[R3];
 #pragma unroll
   for (int r = 0; r < R3; ++r) acc[r] = cd{0.0, 0.0};
-  for (int j = lane; j < n; j += 64) {
+  // four strides' loads issued before their multiply-adds; each right-hand
+  // side's terms in the order j = lane, lane + 64, ...
+  int j = lane;
+  for (; j + 192 < n; j += 256) {
+    cd a[4], xv[4][R3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = A[(size_t)row * n + j + 64 * u];
+#pragma unroll
+      for (int r = 0; r < R3; ++r) xv[u][r] = r < nr ? x[r * stride + j + 64 * u] : cd{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < R3; ++r) fma_acc(acc[r], a[u], xv[u][r]);
+  }
+  for (; j < n; j += 64) {
     const cd a = A[(size_t)row * n + j];
 #pragma unroll
     for (int r = 0; r < R3; ++r)
