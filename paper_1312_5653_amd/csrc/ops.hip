@@ -24,71 +24,194 @@ __host__ __device__ inline Sten make_sten(double h) {
   return s;
 }
 
-// K x + Kc xc (xc may be null) and M x at free node (i, j), 1-based grid coords.
+// Stencil neighbourhoods.  The Q = 9 (2D) or 27 (3D) neighbours of a free node at
+// 1-based grid coordinates (i, j, k) (k = 0 in 2D) are numbered
+// q = (di + 1) + 3 (dj + 1) + 9 (dk + 1), the order every stencil sum below runs in.
+// The gathers issue all of a node's loads unconditionally -- a neighbour outside
+// the free set reads the node itself and is then replaced by zero -- so the loads
+// of a stencil are in flight together instead of one round trip after another;
+// a zero in place of a skipped neighbour leaves every sum unchanged.
 struct Field {
   const double* x;   // free values, stride n_free
   const double* xc;  // boundary values or null
 };
-__device__ inline double val(const Field& f, int N, const int* full2bdry, int i, int j) {
-  if (i <= 0 || j <= 0 || i >= N || j >= N) {
-    if (!f.xc) return 0.0;
-    return f.xc[full2bdry[i + (N + 1) * j]];
+template <int D>
+struct Nb {
+  static constexpr int Q = D == 3 ? 27 : 9;
+};
+template <int D>
+__device__ inline void nb_off(int q, int& di, int& dj, int& dk) {
+  di = q % 3 - 1;
+  dj = (q / 3) % 3 - 1;
+  dk = D == 3 ? q / 9 - 1 : 0;
+}
+template <int D>
+__device__ inline bool nb_free(int N, int i, int j, int k, int q) {
+  int di, dj, dk;
+  nb_off<D>(q, di, dj, dk);
+  const unsigned n1 = (unsigned)(N - 1);
+  bool f = (unsigned)(i + di - 1) < n1 && (unsigned)(j + dj - 1) < n1;
+  if (D == 3) f = f && (unsigned)(k + dk - 1) < n1;
+  return f;
+}
+// free index t -> grid coordinates; 32-bit divisions while the index fits
+__device__ inline void ij2(int64_t t, int N, int& i, int& j) {
+  const int n1 = N - 1;
+  if (t <= 0x7fffffff) {
+    const unsigned u = (unsigned)t;
+    i = (int)(u % (unsigned)n1) + 1;
+    j = (int)(u / (unsigned)n1) + 1;
+  } else {
+    i = (int)(t % n1) + 1;
+    j = (int)(t / n1) + 1;
   }
-  return f.x[(i - 1) + (N - 1) * (j - 1)];
 }
-__device__ inline void stencil_KM(const Sten& st, int N, const int* f2b, const Field& f, int i,
-                                  int j, double& Kx, double& Mx) {
-  Kx = 0.0;
-  Mx = 0.0;
-  for (int dj = -1; dj <= 1; ++dj)
-    for (int di = -1; di <= 1; ++di) {
-      double v = val(f, N, f2b, i + di, j + dj);
-      double wk = st.k[di + 1] * st.m[dj + 1] + st.m[di + 1] * st.k[dj + 1];
-      double wm = st.m[di + 1] * st.m[dj + 1];
-      Kx = fma(wk, v, Kx);
-      Mx = fma(wm, v, Mx);
-    }
-}
-
-// 3D: free index t -> grid coordinates (1-based), values and the 27-point
-// stencils K = k1 (x) m1 (x) m1 + m1 (x) k1 (x) m1 + m1 (x) m1 (x) k1, M = m1 (x) m1 (x) m1.
 __device__ inline void ijk3(int64_t t, int N, int& i, int& j, int& k) {
   const int64_t n1 = N - 1;
-  i = (int)(t % n1) + 1;
-  j = (int)((t / n1) % n1) + 1;
-  k = (int)(t / (n1 * n1)) + 1;
+  if (t <= 0x7fffffff) {
+    const unsigned u = (unsigned)t, m = (unsigned)n1, w = u / m;
+    i = (int)(u - w * m) + 1;
+    j = (int)(w % m) + 1;
+    k = (int)(w / m) + 1;
+  } else {
+    i = (int)(t % n1) + 1;
+    j = (int)((t / n1) % n1) + 1;
+    k = (int)(t / (n1 * n1)) + 1;
+  }
 }
-__device__ inline bool free3(int N, int i, int j, int k) {
-  return i > 0 && j > 0 && k > 0 && i < N && j < N && k < N;
+template <int D>
+__device__ inline void node_ijk(int64_t t, int N, int& i, int& j, int& k) {
+  if (D == 3) ijk3(t, N, i, j, k);
+  else { ij2(t, N, i, j); k = 0; }
 }
-__device__ inline int64_t fidx3(int N, int i, int j, int k) {
+// v[q] = x at free neighbour q, zero at boundary neighbours (t: the node's free index)
+template <int D, class T>
+__device__ inline void gather_free(const T* x, int N, int i, int j, int k, int64_t t, T (&v)[Nb<D>::Q]) {
   const int64_t n1 = N - 1;
-  return (i - 1) + n1 * ((j - 1) + n1 * (int64_t)(k - 1));
+#pragma unroll
+  for (int q = 0; q < Nb<D>::Q; ++q) {
+    int di, dj, dk;
+    nb_off<D>(q, di, dj, dk);
+    const bool f = nb_free<D>(N, i, j, k, q);
+    const T a = x[f ? t + di + n1 * (dj + n1 * dk) : t];
+    v[q] = f ? a : T{};
+  }
 }
-__device__ inline int64_t full3(int N, int i, int j, int k) {
+// a node with at least one boundary neighbour
+template <int D>
+__device__ inline bool near_bdry(int N, int i, int j, int k) {
+  bool e = i == 1 || j == 1 || i == N - 1 || j == N - 1;
+  if (D == 3) e = e || k == 1 || k == N - 1;
+  return e;
+}
+// v[q] = xc[full2bdry[neighbour q]] at the boundary neighbours (free entries kept);
+// full2bdry covers the full grid, (N+1)^D nodes, so its loads are in range for every q
+template <int D>
+__device__ inline void gather_bdry(const double* xc, const int* f2b, int N, int i, int j, int k,
+                                   double (&v)[Nb<D>::Q]) {
   const int64_t n1 = N + 1;
-  return i + n1 * (j + n1 * (int64_t)k);
+  int b[Nb<D>::Q];
+#pragma unroll
+  for (int q = 0; q < Nb<D>::Q; ++q) {
+    int di, dj, dk;
+    nb_off<D>(q, di, dj, dk);
+    b[q] = f2b[(i + di) + n1 * ((j + dj) + n1 * (int64_t)(k + dk))];
+  }
+#pragma unroll
+  for (int q = 0; q < Nb<D>::Q; ++q) {
+    const bool f = nb_free<D>(N, i, j, k, q);
+    const double a = xc[f ? 0 : b[q]];
+    if (!f) v[q] = a;
+  }
 }
-__device__ inline void stencil_KM3(const Sten& st, int N, const int* f2b, const Field& f, int i, int j, int k,
-                                   double& Kx, double& Mx) {
+// stencil weights of neighbour q: K = k1 (x) m1 [(x) m1] + ..., M = m1 (x) m1 [(x) m1]
+template <int D>
+__device__ inline void nb_weights(const Sten& st, int q, double& wk, double& wm) {
+  int di, dj, dk;
+  nb_off<D>(q, di, dj, dk);
+  const double mi = st.m[di + 1], mj = st.m[dj + 1];
+  if (D == 3) {
+    const double mk = st.m[dk + 1];
+    wk = st.k[di + 1] * mj * mk + mi * st.k[dj + 1] * mk + mi * mj * st.k[dk + 1];
+    wm = mi * mj * mk;
+  } else {
+    wk = st.k[di + 1] * mj + mi * st.k[dj + 1];
+    wm = mi * mj;
+  }
+}
+// Stencil kernels: 256-thread blocks, one instantiation per dimension (the 2D
+// and 3D gathers need very different register budgets).
+#define STENCIL_BOUNDS __launch_bounds__(256)
+
+// K x + Kc xc (xc may be null) and M x at free node t = (i, j, k)
+template <int D>
+__device__ inline void stencil_KM(const Sten& st, int N, const int* f2b, const Field& f, int i, int j, int k,
+                                  int64_t t, double& Kx, double& Mx) {
+  double v[Nb<D>::Q];
+  gather_free<D>(f.x, N, i, j, k, t, v);
+  if (f.xc && near_bdry<D>(N, i, j, k)) gather_bdry<D>(f.xc, f2b, N, i, j, k, v);
   Kx = 0.0;
   Mx = 0.0;
-  for (int dk = -1; dk <= 1; ++dk)
-    for (int dj = -1; dj <= 1; ++dj)
-      for (int di = -1; di <= 1; ++di) {
-        const int ii = i + di, jj = j + dj, kk = k + dk;
-        double v;
-        if (free3(N, ii, jj, kk)) v = f.x[fidx3(N, ii, jj, kk)];
-        else if (f.xc) v = f.xc[f2b[full3(N, ii, jj, kk)]];
-        else continue;
-        const double mi = st.m[di + 1], mj = st.m[dj + 1], mk = st.m[dk + 1];
-        const double wk = st.k[di + 1] * mj * mk + mi * st.k[dj + 1] * mk + mi * mj * st.k[dk + 1];
-        Kx = fma(wk, v, Kx);
-        Mx = fma(mi * mj * mk, v, Mx);
+#pragma unroll
+  for (int q = 0; q < Nb<D>::Q; ++q) {
+    double wk, wm;
+    nb_weights<D>(st, q, wk, wm);
+    Kx = fma(wk, v[q], Kx);
+    Mx = fma(wm, v[q], Mx);
+  }}
+// K x_f, M x_f and, with ABS, |K| |x_f| and |M| |x_f| for F free-node fields
+// (zero at boundary neighbours), neighbour by neighbour: one neighbour's address
+// serves the F loads, so no per-neighbour offsets stay live between fields.
+template <int D, int F, bool ABS>
+__device__ inline void stencil_fields(const Sten& st, int N, int i, int j, int k, int64_t t,
+                                      const double* const (&x)[F], double (&Kx)[F], double (&Mx)[F],
+                                      double (&aKx)[F], double (&aMx)[F]) {
+  const int64_t n1 = N - 1;
+#pragma unroll
+  for (int f = 0; f < F; ++f) Kx[f] = Mx[f] = aKx[f] = aMx[f] = 0.0;
+#pragma unroll
+  for (int q = 0; q < Nb<D>::Q; ++q) {
+    int di, dj, dk;
+    nb_off<D>(q, di, dj, dk);
+    const bool fr = nb_free<D>(N, i, j, k, q);
+    const int64_t idx = fr ? t + di + n1 * (dj + n1 * dk) : t;
+    double wk, wm;
+    nb_weights<D>(st, q, wk, wm);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const double a = x[f][idx];
+      const double v = fr ? a : 0.0;
+      Kx[f] = fma(wk, v, Kx[f]);
+      Mx[f] = fma(wm, v, Mx[f]);
+      if (ABS) {
+        aKx[f] = fma(fabs(wk), fabs(v), aKx[f]);
+        aMx[f] = fma(fabs(wm), fabs(v), aMx[f]);
       }
+    }
+  }
+}
+// Kc yc and |Kc| |yc| at a free node (the stencil's boundary neighbours; zero
+// when yc is null or the node has none)
+template <int D>
+__device__ inline void stencil_kc(const Sten& st, int N, int i, int j, int k, const int* f2b, const double* yc,
+                                  double& Kc, double& aKc) {
+  Kc = aKc = 0.0;
+  if (!yc || !near_bdry<D>(N, i, j, k)) return;
+  double v[Nb<D>::Q];
+#pragma unroll
+  for (int q = 0; q < Nb<D>::Q; ++q) v[q] = 0.0;
+  gather_bdry<D>(yc, f2b, N, i, j, k, v);
+#pragma unroll
+  for (int q = 0; q < Nb<D>::Q; ++q) {
+    double wk, wm;
+    nb_weights<D>(st, q, wk, wm);
+    Kc = fma(wk, v[q], Kc);
+    aKc = fma(fabs(wk), fabs(v[q]), aKc);
+  }
 }
 
-__global__ void k_apply_KM(int N, int dim, const int* f2b, const double* x, const double* xc, double* yK,
+template <int D>
+__global__ void STENCIL_BOUNDS k_apply_KM(int N, const int* f2b, const double* x, const double* xc, double* yK,
                            double* yM, int64_t nfree, int64_t nbdry) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int r = blockIdx.y;
@@ -96,14 +219,9 @@ __global__ void k_apply_KM(int N, int dim, const int* f2b, const double* x, cons
   Sten st = make_sten(1.0 / N);
   Field f{x + r * nfree, xc ? xc + r * nbdry : nullptr};
   double Kx, Mx;
-  if (dim == 3) {
-    int i, j, k;
-    ijk3(t, N, i, j, k);
-    stencil_KM3(st, N, f2b, f, i, j, k, Kx, Mx);
-  } else {
-    int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
-    stencil_KM(st, N, f2b, f, i, j, Kx, Mx);
-  }
+  int i, j, k;
+  node_ijk<D>(t, N, i, j, k);
+  stencil_KM<D>(st, N, f2b, f, i, j, k, t, Kx, Mx);
   if (yK) yK[r * nfree + t] = Kx;
   if (yM) yM[r * nfree + t] = Mx;
 }
@@ -116,55 +234,45 @@ __global__ void k_apply_KM(int N, int dim, const int* f2b, const double* x, cons
 __device__ inline int slot_of(unsigned map, int c) { return (int)((map >> (8 * c)) & 255u); }
 
 // v = conj(r1 + M dw) = r1 + M conj(dw)   (dw = cvec2, v = cvec3)
-template <class Src>
-__global__ void k_make_rhs2(Src src) {
+template <int D>
+__device__ inline cd mrhs2_node(const Sten& st, int N, int i, int j, int k, int64_t t, double r1t, const cd* dw) {
+  cd v[Nb<D>::Q];
+  gather_free<D>(dw, N, i, j, k, t, v);
+  cd acc{r1t, 0.0};
+#pragma unroll
+  for (int q = 0; q < Nb<D>::Q; ++q) {
+    double wk, wm;
+    nb_weights<D>(st, q, wk, wm);
+    acc.x = fma(wm, v[q].x, acc.x);
+    acc.y = fma(-wm, v[q].y, acc.y);
+  }
+  return acc;
+}
+template <int D, class Src>
+__global__ void STENCIL_BOUNDS k_make_rhs2(Src src) {
   const Dev& d = src.dev();
   const int c = blockIdx.y;
-  if (c >= d.nr) return;
+  if (c >= d.nr || d.g.dim != D) return;
   const int64_t nfree = d.n_free;
   int64_t t = (int64_t)src.bx() * blockDim.x + threadIdx.x;
   if (t >= nfree) return;
   const int N = d.g.N, s = slot_of(d.map, c);
   const double* r1 = d.r1 + s * nfree;
   const cd* dw = d.cvec2 + c * nfree;
-  Sten st = make_sten(1.0 / N);
-  cd acc{r1[t], 0.0};
-  if (d.g.dim == 3) {
-    int i, j, k;
-    ijk3(t, N, i, j, k);
-    for (int dk = -1; dk <= 1; ++dk)
-      for (int dj = -1; dj <= 1; ++dj)
-        for (int di = -1; di <= 1; ++di) {
-          if (!free3(N, i + di, j + dj, k + dk)) continue;
-          const cd w = dw[fidx3(N, i + di, j + dj, k + dk)];
-          const double wm = st.m[di + 1] * st.m[dj + 1] * st.m[dk + 1];
-          acc.x = fma(wm, w.x, acc.x);
-          acc.y = fma(-wm, w.y, acc.y);
-        }
-    d.cvec3[c * nfree + t] = acc;
-    return;
-  }
-  int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
-  for (int dj = -1; dj <= 1; ++dj)
-    for (int di = -1; di <= 1; ++di) {
-      int ii = i + di, jj = j + dj;
-      if (ii <= 0 || jj <= 0 || ii >= N || jj >= N) continue;
-      cd w = dw[(ii - 1) + (N - 1) * (jj - 1)];
-      double wm = st.m[di + 1] * st.m[dj + 1];
-      acc.x = fma(wm, w.x, acc.x);
-      acc.y = fma(-wm, w.y, acc.y);
-    }
-  d.cvec3[c * nfree + t] = acc;
+  const Sten st = make_sten(1.0 / N);
+  int i, j, k;
+  node_ijk<D>(t, N, i, j, k);
+  d.cvec3[c * nfree + t] = mrhs2_node<D>(st, N, i, j, k, t, r1[t], dw);
 }
 
 // per-node KKT residual and its squared norms, block partial sums
 // (red + RED_HEAD + slot * pstride, pairs (||r||^2, ||b||^2) per block)
-template <class Src>
-__global__ void __launch_bounds__(256) k_kkt_residual(Src src) {
+template <int D, class Src>
+__global__ void STENCIL_BOUNDS k_kkt_residual(Src src) {
   __shared__ double sh[2][4];
   const Dev& d = src.dev();
   const int c = blockIdx.y;
-  if (c >= d.nr) return;
+  if (c >= d.nr || d.g.dim != D) return;
   const int N = d.g.N, s = slot_of(d.map, c), bx = src.bx();
   const int64_t nfree = d.n_free, nbdry = d.n_bdry;
   const int64_t pstride = 2 * ((nfree + 255) / 256);
@@ -178,44 +286,15 @@ __global__ void __launch_bounds__(256) k_kkt_residual(Src src) {
   int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   double rn = 0.0, bn = 0.0;
   if (t < nfree) {
-    Sten st = make_sten(1.0 / N);
-    double Kyb_unused, Mybar, Ky, My, Kl, Ml, Ku_unused, Mu, Kc;
-    if (d.g.dim == 3) {
-      int i, j, k;
-      ijk3(t, N, i, j, k);
-      stencil_KM3(st, N, f2b, Field{ybar, nullptr}, i, j, k, Kyb_unused, Mybar);
-      stencil_KM3(st, N, f2b, Field{y, nullptr}, i, j, k, Ky, My);
-      stencil_KM3(st, N, f2b, Field{lam, nullptr}, i, j, k, Kl, Ml);
-      stencil_KM3(st, N, f2b, Field{u, nullptr}, i, j, k, Ku_unused, Mu);
-      Kc = 0.0;
-      if (yc)
-        for (int dk = -1; dk <= 1; ++dk)
-          for (int dj = -1; dj <= 1; ++dj)
-            for (int di = -1; di <= 1; ++di) {
-              const int ii = i + di, jj = j + dj, kk = k + dk;
-              if (free3(N, ii, jj, kk)) continue;
-              const double mi = st.m[di + 1], mj = st.m[dj + 1], mk = st.m[dk + 1];
-              const double wk = st.k[di + 1] * mj * mk + mi * st.k[dj + 1] * mk + mi * mj * st.k[dk + 1];
-              Kc = fma(wk, yc[f2b[full3(N, ii, jj, kk)]], Kc);
-            }
-    } else {
-    int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
-    stencil_KM(st, N, f2b, Field{ybar, nullptr}, i, j, Kyb_unused, Mybar);
-    stencil_KM(st, N, f2b, Field{y, nullptr}, i, j, Ky, My);
-    stencil_KM(st, N, f2b, Field{lam, nullptr}, i, j, Kl, Ml);
-    stencil_KM(st, N, f2b, Field{u, nullptr}, i, j, Ku_unused, Mu);
-    // Kc yc: stencil on a field that is zero at free nodes and yc on the boundary
-    Kc = 0.0;
-    if (yc) {
-      for (int dj = -1; dj <= 1; ++dj)
-        for (int di = -1; di <= 1; ++di) {
-          int ii = i + di, jj = j + dj;
-          if (ii > 0 && jj > 0 && ii < N && jj < N) continue;
-          double wk = st.k[di + 1] * st.m[dj + 1] + st.m[di + 1] * st.k[dj + 1];
-          Kc = fma(wk, yc[f2b[ii + (N + 1) * jj]], Kc);
-        }
-    }
-    }
+    const Sten st = make_sten(1.0 / N);
+    int i, j, k;
+    node_ijk<D>(t, N, i, j, k);
+    // fields ybar, y, lam, u
+    const double* const xs[4] = {ybar, y, lam, u};
+    double K[4], M[4], aK_unused[4], aM_unused[4], Kc, aKc_unused;
+    stencil_fields<D, 4, false>(st, N, i, j, k, t, xs, K, M, aK_unused, aM_unused);
+    stencil_kc<D>(st, N, i, j, k, f2b, yc, Kc, aKc_unused);
+    const double Mybar = M[0], Ky = K[1], My = M[1], Kl = K[2], Ml = M[2], Mu = M[3];
     double a1 = Mybar - My - Kl;
     double a2 = -(d.beta * Mu - Ml);
     double a3 = -Kc - Ky + Mu;
@@ -246,70 +325,35 @@ __global__ void __launch_bounds__(256) k_kkt_residual(Src src) {
 // with |K|, |M|, |Kc| the entrywise absolute values of the assembled matrices.
 // Per node: Kx, Mx and the absolute-value products |K||x|, |M||x| from the same
 // stencils with absolute weights.
-__device__ inline void stencil_abs(const Sten& st, int N, int dim, int i, int j, int k, const double* x,
-                                   double& Kx, double& Mx, double& aKx, double& aMx) {
-  Kx = Mx = aKx = aMx = 0.0;
-  const int kr = dim == 3 ? 1 : 0;
-  for (int dk = -kr; dk <= kr; ++dk)
-    for (int dj = -1; dj <= 1; ++dj)
-      for (int di = -1; di <= 1; ++di) {
-        const int ii = i + di, jj = j + dj, kk = k + dk;
-        if (ii <= 0 || jj <= 0 || ii >= N || jj >= N) continue;
-        if (dim == 3 && (kk <= 0 || kk >= N)) continue;
-        const double v = dim == 3 ? x[fidx3(N, ii, jj, kk)] : x[(ii - 1) + (N - 1) * (jj - 1)];
-        const double mi = st.m[di + 1], mj = st.m[dj + 1];
-        double wk, wm;
-        if (dim == 3) {
-          const double mk = st.m[dk + 1];
-          wk = st.k[di + 1] * mj * mk + mi * st.k[dj + 1] * mk + mi * mj * st.k[dk + 1];
-          wm = mi * mj * mk;
-        } else {
-          wk = st.k[di + 1] * mj + mi * st.k[dj + 1];
-          wm = mi * mj;
-        }
-        Kx = fma(wk, v, Kx);
-        Mx = fma(wm, v, Mx);
-        aKx = fma(fabs(wk), fabs(v), aKx);
-        aMx = fma(fabs(wm), fabs(v), aMx);
-      }
-}
-// Kc yc and |Kc| |yc| at a free node (the stencil's boundary neighbours).
-__device__ inline void stencil_kc(const Sten& st, int N, int dim, int i, int j, int k, const int* f2b,
-                                  const double* yc, double& Kc, double& aKc) {
-  Kc = aKc = 0.0;
-  if (!yc) return;
-  const int kr = dim == 3 ? 1 : 0;
-  for (int dk = -kr; dk <= kr; ++dk)
-    for (int dj = -1; dj <= 1; ++dj)
-      for (int di = -1; di <= 1; ++di) {
-        const int ii = i + di, jj = j + dj, kk = k + dk;
-        const bool freen = dim == 3 ? free3(N, ii, jj, kk) : (ii > 0 && jj > 0 && ii < N && jj < N);
-        if (freen) continue;
-        const double mi = st.m[di + 1], mj = st.m[dj + 1];
-        double wk;
-        int64_t full;
-        if (dim == 3) {
-          const double mk = st.m[dk + 1];
-          wk = st.k[di + 1] * mj * mk + mi * st.k[dj + 1] * mk + mi * mj * st.k[dk + 1];
-          full = full3(N, ii, jj, kk);
-        } else {
-          wk = st.k[di + 1] * mj + mi * st.k[dj + 1];
-          full = ii + (int64_t)(N + 1) * jj;
-        }
-        const double v = yc[f2b[full]];
-        Kc = fma(wk, v, Kc);
-        aKc = fma(fabs(wk), fabs(v), aKc);
-      }
+// The eleven per-node values whose squares the metrics sum, at free node t.
+template <int D>
+__device__ inline void metrics_node(const Dev& d, const Slot& q, int N, int64_t t, double (&w)[MET_N]) {
+  const Sten st = make_sten(1.0 / N);
+  int i, j, k;
+  node_ijk<D>(t, N, i, j, k);
+  // fields y, lam, u, ybar
+  const double* const xs[4] = {q.y, q.lam, q.u, q.ybar};
+  double K[4], M[4], aK[4], aM[4], Kc, aKc;
+  stencil_fields<D, 4, true>(st, N, i, j, k, t, xs, K, M, aK, aM);
+  stencil_kc<D>(st, N, i, j, k, d.full2bdry, q.yc, Kc, aKc);
+  const double Ky = K[0], My = M[0], aKy = aK[0], aMy = aM[0], Kl = K[1], Ml = M[1], aKl = aK[1], aMl = aM[1];
+  const double Mu = M[2], aMu = aM[2], Mb = M[3];
+  const double a1 = Mb - My - Kl;
+  const double a2 = -(d.beta * Mu - Ml);
+  const double a3 = -Kc - Ky + Mu;
+  const double x[MET_N] = {a1, a2, a3, Ky, aMy, aKl, Mb, aMu, aMl, aKy, aKc};
+#pragma unroll
+  for (int e = 0; e < MET_N; ++e) w[e] = x[e];
 }
 
 // Per-block partial sums of squares, MET_N per block in the order
 //   r1, r2, r3, K y, |M||y|, |K||lam|, M ybar, |M||u|, |M||lam|, |K||y|, |Kc||yc|.
-template <class Src>
-__global__ void __launch_bounds__(256) k_kkt_metrics(Src src) {
+template <int D, class Src>
+__global__ void STENCIL_BOUNDS k_kkt_metrics(Src src) {
   __shared__ double sh[MET_N][4];
   const Dev& d = src.dev();
   const int c = blockIdx.y;
-  if (c >= d.nr) return;
+  if (c >= d.nr || d.g.dim != D) return;
   const int N = d.g.N, s = slot_of(d.map, c), bx = src.bx();
   const int64_t nfree = d.n_free;
   const int64_t nb = (nfree + 255) / 256;
@@ -319,20 +363,8 @@ __global__ void __launch_bounds__(256) k_kkt_metrics(Src src) {
   double v[MET_N];
   for (int e = 0; e < MET_N; ++e) v[e] = 0.0;
   if (t < nfree) {
-    Sten st = make_sten(1.0 / N);
-    int i, j, k = 0;
-    if (d.g.dim == 3) ijk3(t, N, i, j, k);
-    else { i = (int)(t % (N - 1)) + 1; j = (int)(t / (N - 1)) + 1; }
-    double Ky, My, aKy, aMy, Kl, Ml, aKl, aMl, Ku, Mu, aKu, aMu, Kb, Mb, aKb, aMb, Kc, aKc;
-    stencil_abs(st, N, d.g.dim, i, j, k, q.y, Ky, My, aKy, aMy);
-    stencil_abs(st, N, d.g.dim, i, j, k, q.lam, Kl, Ml, aKl, aMl);
-    stencil_abs(st, N, d.g.dim, i, j, k, q.u, Ku, Mu, aKu, aMu);
-    stencil_abs(st, N, d.g.dim, i, j, k, q.ybar, Kb, Mb, aKb, aMb);
-    stencil_kc(st, N, d.g.dim, i, j, k, d.full2bdry, q.yc, Kc, aKc);
-    const double a1 = Mb - My - Kl;
-    const double a2 = -(d.beta * Mu - Ml);
-    const double a3 = -Kc - Ky + Mu;
-    const double w[MET_N] = {a1, a2, a3, Ky, aMy, aKl, Mb, aMu, aMl, aKy, aKc};
+    double w[MET_N];
+    metrics_node<D>(d, q, N, t, w);
     for (int e = 0; e < MET_N; ++e) v[e] = w[e] * w[e];
   }
   for (int e = 0; e < MET_N; ++e)
@@ -522,23 +554,18 @@ __global__ void k_copy(int64_t n, const double* x, double* y) {
 
 // out = A x for x = (y, u, lam), three free-node blocks of length n (Sec. 2 KKT
 // matrix): out1 = M y + K lam, out2 = beta M u - M lam, out3 = K y - M u.
-__global__ void k_kkt_apply(int N, int dim, double beta, const double* x, double* out, int64_t n) {
+template <int D>
+__global__ void STENCIL_BOUNDS k_kkt_apply(int N, double beta, const double* x, double* out, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const Sten st = make_sten(1.0 / N);
-  double Ky, My, Ku, Mu, Kl, Ml;
-  if (dim == 3) {
-    int i, j, k;
-    ijk3(t, N, i, j, k);
-    stencil_KM3(st, N, nullptr, Field{x, nullptr}, i, j, k, Ky, My);
-    stencil_KM3(st, N, nullptr, Field{x + n, nullptr}, i, j, k, Ku, Mu);
-    stencil_KM3(st, N, nullptr, Field{x + 2 * n, nullptr}, i, j, k, Kl, Ml);
-  } else {
-    const int i = (int)(t % (N - 1)) + 1, j = (int)(t / (N - 1)) + 1;
-    stencil_KM(st, N, nullptr, Field{x, nullptr}, i, j, Ky, My);
-    stencil_KM(st, N, nullptr, Field{x + n, nullptr}, i, j, Ku, Mu);
-    stencil_KM(st, N, nullptr, Field{x + 2 * n, nullptr}, i, j, Kl, Ml);
-  }
+  int i, j, k;
+  node_ijk<D>(t, N, i, j, k);
+  // fields y, u, lam
+  const double* const xs[3] = {x, x + n, x + 2 * n};
+  double K[3], M[3], aK_unused[3], aM_unused[3];
+  stencil_fields<D, 3, false>(st, N, i, j, k, t, xs, K, M, aK_unused, aM_unused);
+  const double Ky = K[0], My = M[0], Mu = M[1], Kl = K[2], Ml = M[2];
   out[t] = My + Kl;
   out[n + t] = beta * Mu - Ml;
   out[2 * n + t] = Ky - Mu;
@@ -627,14 +654,26 @@ __global__ void __launch_bounds__(256) k_sum_parts(int nb, const double* part, d
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// The dimensions among a target's instances (bit D set for D = 2, 3).  A stencil
+// kernel is launched once per dimension present; each instantiation's blocks
+// return on the instances of the other one.
+static inline unsigned target_dims(const Target& t) {
+  if (t.single()) return 1u << t.one->dim;
+  unsigned m = 0;
+  for (const Problem* p : t.probs) m |= 1u << p->dim;
+  return m;
+}
+
 hipError_t launch_apply_K(const Problem& p, int nrhs, const double* x, const double* xc, double* y,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_apply_KM, dim3(nblk(p.n_free), nrhs), dim3(256), 0, st, p.N, p.dim, p.full2bdry, x,
-                     xc, y, (double*)nullptr, p.n_free, p.n_bdry);
+  auto* kern = p.dim == 3 ? k_apply_KM<3> : k_apply_KM<2>;
+  hipLaunchKernelGGL(kern, dim3(nblk(p.n_free), nrhs), dim3(256), 0, st, p.N, p.full2bdry, x, xc, y,
+                     (double*)nullptr, p.n_free, p.n_bdry);
   return hipGetLastError();
 }
 hipError_t launch_apply_M(const Problem& p, int nrhs, const double* x, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_apply_KM, dim3(nblk(p.n_free), nrhs), dim3(256), 0, st, p.N, p.dim, p.full2bdry, x,
+  auto* kern = p.dim == 3 ? k_apply_KM<3> : k_apply_KM<2>;
+  hipLaunchKernelGGL(kern, dim3(nblk(p.n_free), nrhs), dim3(256), 0, st, p.N, p.full2bdry, x,
                      (const double*)nullptr, (double*)nullptr, y, p.n_free, p.n_bdry);
   return hipGetLastError();
 }
@@ -642,7 +681,9 @@ hipError_t launch_apply_M(const Problem& p, int nrhs, const double* x, double* y
 int64_t red_pstride(const Problem& p) { return 2 * (int64_t)nblk(p.n_free); }
 
 hipError_t launch_kkt_residual(const Target& t) {
-  launch2(t, K_NF256, k_kkt_residual<One>, k_kkt_residual<Many>, NRMAX, 256, 0);
+  const unsigned dims = target_dims(t);
+  if (dims & 4u) launch2(t, K_NF256, k_kkt_residual<2, One>, k_kkt_residual<2, Many>, NRMAX, 256, 0);
+  if (dims & 8u) launch2(t, K_NF256, k_kkt_residual<3, One>, k_kkt_residual<3, Many>, NRMAX, 256, 0);
   launch2(t, K_ONE, k_reduce_ratio<One>, k_reduce_ratio<Many>, NRMAX, 256, 0, 0);
   return hipGetLastError();
 }
@@ -685,14 +726,17 @@ __global__ void k_pick_ratio(const double* red, int nr, double* rel) {
 
 hipError_t launch_kkt_residual_noalloc(const Dev& d, hipStream_t st, double* rel) {
   const One o{d};
-  hipLaunchKernelGGL(k_kkt_residual<One>, dim3(nblk(d.n_free), NRMAX), dim3(256), 0, st, o);
+  auto* kern = d.g.dim == 3 ? k_kkt_residual<3, One> : k_kkt_residual<2, One>;
+  hipLaunchKernelGGL(kern, dim3(nblk(d.n_free), NRMAX), dim3(256), 0, st, o);
   hipLaunchKernelGGL(k_reduce_ratio<One>, dim3(1, NRMAX), dim3(256), 0, st, o, 0);
   hipLaunchKernelGGL(k_pick_ratio, dim3(1), dim3(64), 0, st, (const double*)d.red, d.nr, rel);
   return hipGetLastError();
 }
 
 hipError_t launch_kkt_metrics(const Target& t) {
-  launch2(t, K_NF256, k_kkt_metrics<One>, k_kkt_metrics<Many>, NRMAX, 256, 0);
+  const unsigned dims = target_dims(t);
+  if (dims & 4u) launch2(t, K_NF256, k_kkt_metrics<2, One>, k_kkt_metrics<2, Many>, NRMAX, 256, 0);
+  if (dims & 8u) launch2(t, K_NF256, k_kkt_metrics<3, One>, k_kkt_metrics<3, Many>, NRMAX, 256, 0);
   launch2(t, K_ONE, k_reduce_metrics<One>, k_reduce_metrics<Many>, NRMAX, MET_N * 64, 0);
   return hipGetLastError();
 }
@@ -701,7 +745,9 @@ hipError_t launch_make_rhs1(const Target& t) {
   return hipGetLastError();
 }
 hipError_t launch_make_rhs2(const Target& t) {
-  launch2(t, K_NF256, k_make_rhs2<One>, k_make_rhs2<Many>, NRMAX, 256, 0);
+  const unsigned dims = target_dims(t);
+  if (dims & 4u) launch2(t, K_NF256, k_make_rhs2<2, One>, k_make_rhs2<2, Many>, NRMAX, 256, 0);
+  if (dims & 8u) launch2(t, K_NF256, k_make_rhs2<3, One>, k_make_rhs2<3, Many>, NRMAX, 256, 0);
   return hipGetLastError();
 }
 hipError_t launch_update(const Target& t, int single) {
@@ -744,7 +790,8 @@ hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t st) {
 }
 
 hipError_t launch_kkt_apply(const Problem& p, const double* x, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_kkt_apply, dim3(nblk(p.n_free)), dim3(256), 0, st, p.N, p.dim, p.beta, x, out, p.n_free);
+  auto* kern = p.dim == 3 ? k_kkt_apply<3> : k_kkt_apply<2>;
+  hipLaunchKernelGGL(kern, dim3(nblk(p.n_free)), dim3(256), 0, st, p.N, p.beta, x, out, p.n_free);
   return hipGetLastError();
 }
 hipError_t launch_mass_inverse(const Problem& p, const double* x, double scale, double* out, hipStream_t st) {
