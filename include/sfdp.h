@@ -199,6 +199,22 @@ sfdp_status sfdp_set_tuning(int enable);
  * SFDP_E_INVALID for other values. */
 sfdp_status sfdp_set_graphs(int enable);
 
+/* Launch form of the persistent GMRES kernel in the range-space solves of a
+ * single problem (sfdp_solve_range_space and its host-array form).  Its grid
+ * barrier needs every workgroup resident at once.  mode = 1 (the default):
+ * a plain launch whose workgroups first count themselves on a device word and
+ * wait, bounded, until all have arrived; if they do not (other work holds the
+ * compute units), every workgroup returns without work, the refinement step
+ * leaves the iterate unchanged (the update kernel sees the flag) and runs
+ * again with cooperative launches, which that problem then keeps.  mode = 0:
+ * cooperative launches always (hipLaunchCooperativeKernel guarantees
+ * co-residency, at ~11 us of idle device before and after each launch on
+ * MI355X).  mode = 2: as 1 with no wait in the check, so that the fallback
+ * runs (for tests).  Results are the same in every mode.  Batches and the
+ * other entry points always launch cooperatively.  SFDP_E_INVALID for other
+ * values. */
+sfdp_status sfdp_set_gmres_launch(int mode);
+
 /* Arithmetic of the subdomain line factorization and line solves of the
  * set-up (Sec. 4 factors, the local solves of Sec. 5) for problems with
  * complex64 storage (SFDP_MIXED), from the next sfdp_set_beta (or batch

@@ -65,6 +65,7 @@ void graphs_clear(Problem& p) {
   p.graph_seen.clear();
 }
 std::atomic<bool> g_graphs{false};  // sfdp_set_graphs
+std::atomic<int> g_gmres_launch{1};  // sfdp_set_gmres_launch
 std::atomic<int> g_setup_bits{64};  // sfdp_set_setup_arithmetic
 
 sfdp_status dalloc(Problem& p, void** ptr, size_t bytes) {
@@ -933,6 +934,7 @@ sfdp_status step_graph(Problem& p, const Target& t, double tin, int kmax, bool s
   key.single = single ? 1 : 0;
   key.tin = tin;
   key.tune_gen = tune_generation();
+  key.plain = p.gmres_coop ? 0 : p.gmres_plain;
   for (int c = 0; c < NRMAX; ++c) {
     const Slot& q = p.sl[c];
     const void* v[5] = {q.ybar, q.yc, q.y, q.u, q.lam};
@@ -1032,10 +1034,34 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
   // a single 2D problem replays its steps as captured graphs (no timing events:
   // event records are not captured)
   const bool graphable = t.single() && t.one->dim == 2 && !M && !t.one->timing && g_graphs.load();
+  // a single problem's GMRES solves use plain launches that check their grid's
+  // co-residency; a step whose check failed changed nothing and runs again with
+  // cooperative launches
+  struct PlainScope {
+    Problem* p;
+    ~PlainScope() {
+      if (p) p->gmres_plain = 0;
+    }
+  } plain_scope{t.single() ? t.one : nullptr};
+  if (t.single()) t.one->gmres_plain = g_gmres_launch.load();
+  int pre_flags[FLAG_WORDS];  // a single problem's device flags before the current step
   HIPCHK(residual(t));
   for (int step = 0;; ++step) {
     if (t.single()) t.one->yield_point();
     HIPCHK(hipStreamSynchronize(st));
+    if (step > 0 && t.single() && hg[0].flags[FLAG_NOTRES]) {
+      // the flags as they were before the step (iteration logs of any GMRES
+      // launch of it that did finish are dropped), then the same step again
+      t.one->gmres_coop = true;
+      HIPCHK(hipMemcpy(t.one->flags, pre_flags, sizeof(pre_flags), hipMemcpyHostToDevice));
+      --step;
+      const double tin = step == 0 ? tol_first : tol_inner;
+      sfdp_status s = graphable ? step_graph(*t.one, t, tin, kmax, single,
+                                             [&](const Target& tt) { return step_body(tt, tin); })
+                                : step_body(t, tin);
+      if (s) return s;
+      continue;
+    }
     bool any = false;
     for (size_t i = 0; i < n; ++i) {
       Problem* p = ps[i];
@@ -1064,6 +1090,7 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
       sfdp_status s = multi_upload(*M);
       if (s) return s;
     }
+    if (t.single()) std::memcpy(pre_flags, hg[0].flags, sizeof(pre_flags));
     sfdp_status s = graphable ? step_graph(*t.one, t, tin, kmax, single,
                                            [&](const Target& tt) { return step_body(tt, tin); })
                               : step_body(t, tin);
@@ -1599,6 +1626,12 @@ static void sizes_of(const Problem* p, sfdp_sizes* out) {
 sfdp_status sfdp_set_setup_arithmetic(int bits) {
   if (bits != 32 && bits != 64) return fail(SFDP_E_INVALID, "bits must be 32 or 64");
   g_setup_bits = bits;
+  return SFDP_OK;
+}
+
+sfdp_status sfdp_set_gmres_launch(int mode) {
+  if (mode < 0 || mode > 2) return fail(SFDP_E_INVALID, "mode must be 0, 1 or 2");
+  g_gmres_launch = mode;
   return SFDP_OK;
 }
 

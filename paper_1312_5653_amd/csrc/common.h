@@ -189,11 +189,12 @@ struct RhsStride {
   int64_t cq;   // per-subdomain coarse-slot buffers (nsub * NQ)
 };
 
-// Device flag words of an instance: [1] grid-barrier error, [3] GMRES loop
+// Device flag words of an instance: [1] grid-barrier error, [FLAG_NOTRES] a
+// plain GMRES launch whose grid was not co-resident (it did no work), [3] GMRES loop
 // trips, [4] GMRES iterations summed over right-hand sides, [FLAG_ITS + r]
 // iterations of right-hand side r in the last GMRES launch, [FLAG_CNT + slot]
 // FETI-DP solves logged for a group slot, [FLAG_LOG + 16 slot + k] their counts.
-constexpr int FLAG_ITS = 8, FLAG_CNT = 16, FLAG_LOG = 64, FLAG_WORDS = FLAG_LOG + NRMAX * 16;
+constexpr int FLAG_NOTRES = 2, FLAG_ITS = 8, FLAG_CNT = 16, FLAG_LOG = 64, FLAG_WORDS = FLAG_LOG + NRMAX * 16;
 
 // Per-instance record gathered to the host after a step: residual heads
 // (red[2 slot]: relative KKT residual, red[2 slot + 1]: imaginary ratio) and
@@ -295,11 +296,12 @@ enum Kind : int { K_SUB = 0, K_NC128, K_NC, K_NMU256, K_ASM256, K_NF256, K_SUB16
 struct StepKey {
   int nr = 0, kmax = 0, single = 0;
   unsigned map = 0, tune_gen = 0;
+  int plain = 0;  // GMRES launch form captured (Problem::gmres_plain unless gmres_coop)
   double tin = 0;
   const void* ptr[5 * NRMAX] = {};  // the caller arrays of the group's slots
   bool operator==(const StepKey& o) const {
     if (nr != o.nr || kmax != o.kmax || single != o.single || map != o.map || tune_gen != o.tune_gen ||
-        tin != o.tin)
+        plain != o.plain || tin != o.tin)
       return false;
     for (int i = 0; i < 5 * NRMAX; ++i)
       if (ptr[i] != o.ptr[i]) return false;
@@ -392,6 +394,12 @@ struct Problem {
   std::vector<StepGraph> graphs;
   std::vector<StepKey> graph_seen;
   bool graph_off = false;  // a capture failed: this problem runs eagerly
+  // GMRES launch form of the current range-space call: 0 cooperative, 1 plain
+  // launch that first checks that its grid is co-resident, 2 the same with no
+  // wait in the check (tests of the fallback); gmres_coop: a plain launch found
+  // its grid not co-resident once, so this problem launches cooperatively from then on
+  int gmres_plain = 0;
+  bool gmres_coop = false;
   // kernel timing (events recorded around hot kernel launches)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;

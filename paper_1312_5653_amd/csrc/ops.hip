@@ -459,6 +459,7 @@ __global__ void __launch_bounds__(256) k_update(Src src, int single) {
   const Dev& d = src.dev();
   const int c = blockIdx.y;
   if (c >= d.nr) return;
+  if (d.flags[FLAG_NOTRES]) return;  // a GMRES grid of this step did no work: keep the iterate
   const int s = slot_of(d.map, c), bx = src.bx();
   const int64_t n = d.n_free, pstride = 2 * ((n + 255) / 256);
   const cd* dw = d.cvec2 + c * n;

@@ -55,7 +55,8 @@ __device__ inline void lds_sync() {
 // block count and block index of the group that synchronises (one instance's
 // share of the grid).
 constexpr int BAR_GROUPS = 16, BAR_STRIDE = 32, BAR_TOP = BAR_GROUPS * BAR_STRIDE,
-              BAR_GEN = BAR_TOP + BAR_STRIDE, BAR_WORDS = BAR_GEN + BAR_STRIDE;
+              BAR_GEN = BAR_TOP + BAR_STRIDE, BAR_ARRIVE = BAR_GEN + BAR_STRIDE,
+              BAR_WORDS = BAR_ARRIVE + BAR_STRIDE;
 __device__ inline void grid_barrier(unsigned* bar, unsigned nblocks, unsigned blk, unsigned& epoch,
                                     int* err) {
   // Data exchanged between blocks uses agent-scope atomic loads and stores
@@ -87,6 +88,46 @@ __device__ inline void grid_barrier(unsigned* bar, unsigned nblocks, unsigned bl
     }
   }
   __syncthreads();
+}
+
+// Start of a plain (not cooperative) launch of a kernel that uses grid_barrier:
+// whether the grid is co-resident.  Every block arrives on one counter and
+// waits, for at most `spins` polls, until all `total` have.  The count and an
+// abort bit share the word, so the blocks agree: a block whose wait ran out sets
+// the bit only by a compare-and-swap from a short count, and once the count is
+// complete it can no longer be set.  On abort every block must return before any
+// work (a late block sees the bit in its own arrival), and *notres is set.  A
+// cooperative launch saves this check but costs ~11 us of idle device on each
+// side of the kernel (measured on MI355X), a plain one does not.
+constexpr unsigned ARRIVE_ABORT = 1u << 31;
+constexpr int CORESIDENT_SPINS = 1 << 12;
+__device__ inline bool grid_coresident(unsigned* word, unsigned total, int spins, int* notres) {
+  __shared__ int go;
+  if (threadIdx.x == 0) {
+    unsigned v = __hip_atomic_fetch_add(word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    int n = 0, r = 1;
+    for (;;) {
+      if (v & ARRIVE_ABORT) { r = 0; break; }
+      if (v >= total) break;
+      if (n >= spins) {
+        unsigned expect = v;
+        if (__hip_atomic_compare_exchange_strong(word, &expect, v | ARRIVE_ABORT, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          __hip_atomic_store(notres, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          r = 0;
+          break;
+        }
+        v = expect;  // the word moved on: test the new value
+        continue;
+      }
+      ++n;
+      __builtin_amdgcn_s_sleep(1);
+      v = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    go = r;
+  }
+  __syncthreads();
+  return go != 0;
 }
 
 // Coherent (agent-scope) access to data written by one block and read by
@@ -1654,6 +1695,7 @@ struct GmresArgs {
 struct GmresLaunch {
   double tol;
   int kmax, r0, resident;
+  int check_spins;  // plain launch: the co-residency check's wait (grid_coresident); -1 cooperative
   int o_red, o_xs, o_wch, o_hv, o_h2, o_cs, o_sn, o_g, o_ucs, o_S, o_I;
 };
 
@@ -1939,15 +1981,22 @@ __device__ inline void gmres_body(const Geo2& g, const Maps2& mp, const cf* __re
   }
 }
 
-// One cooperative launch; every instance's blocks (its share gb0 .. gb0+gnb-1
-// of the grid) run the Krylov solve of its group's right-hand sides r0 ..
-// r0 + NRT - 1 with their own grid barrier.  Instances with no such
-// right-hand side return at once.
+// One cooperative launch, or for a single instance a plain launch that first
+// checks that its grid is co-resident (and returns at once if not); every
+// instance's blocks (its share gb0 .. gb0+gnb-1 of the grid) run the Krylov
+// solve of its group's right-hand sides r0 .. r0 + NRT - 1 with their own grid
+// barrier.  Instances with no such right-hand side return at once.
 template <class TS, int NRT, class Src>
 __global__ void __launch_bounds__(256) k_gmres(Src src, GmresLaunch L) {
   const Dev& d = src.dev();
   const int nr = min(NRT, d.nr - L.r0);
   if (nr <= 0) return;
+  // plain launch: nothing to do once a grid of this step was found not co-resident
+  // (the step runs again), else the check
+  if (L.check_spins >= 0 &&
+      (d.flags[FLAG_NOTRES] ||
+       !grid_coresident(d.bar + BAR_ARRIVE, (unsigned)d.gnb, L.check_spins, d.flags + FLAG_NOTRES)))
+    return;
   const RhsStride rs = d.rs;
   GmresArgs a;
   a.rs = rs;
@@ -2217,6 +2266,7 @@ static hipError_t gmres_t(const Target& t, int gi, double tol, int kmax, int r0)
   L.kmax = kmax;
   L.r0 = r0;
   L.resident = resident ? 1 : 0;
+  L.check_spins = -1;
   launch2(t, K_ONE, k_bar_reset<One>, k_bar_reset<Many>, 1, 256, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -2231,6 +2281,10 @@ static hipError_t gmres_t(const Target& t, int gi, double tol, int kmax, int r0)
     const void* fn = (const void*)k_gmres<TS, NRT, One>;
     e = ensure_lds(fn, lds);
     if (e != hipSuccess) return e;
+    if (t.one->gmres_plain && !t.one->gmres_coop) {
+      L.check_spins = t.one->gmres_plain == 2 ? 0 : CORESIDENT_SPINS;
+      return hipLaunchKernel(fn, dim3(t.one->gmres_blocks), dim3(256), args, lds, t.st);
+    }
     return hipLaunchCooperativeKernel(fn, dim3(t.one->gmres_blocks), dim3(256), args, lds, t.st);
   }
   Many src{t.devs, t.ggroups[gi].inst, t.first[K_GMRES]};

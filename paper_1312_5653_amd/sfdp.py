@@ -27,6 +27,7 @@ EXPORTS = [
     "sfdp_server_stats", "sfdp_server_destroy", "sfdp_set_coarse_space", "sfdp_batch_inspect",
     "sfdp_solve_full_space", "sfdp_set_tuning", "sfdp_kkt_residual_noalloc", "sfdp_set_graphs",
     "sfdp_set_setup_arithmetic", "sfdp_elastic_create", "sfdp_elastic_pressure_load", "sfdp_elastic_forward",
+    "sfdp_set_gmres_launch",
 ]
 
 
@@ -116,6 +117,7 @@ def load_library(path: str = LIB_PATH):
     lib.sfdp_solve_range_space.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.sfdp_set_tuning.argtypes = [I]
     lib.sfdp_set_graphs.argtypes = [I]
+    lib.sfdp_set_gmres_launch.argtypes = [I]
     lib.sfdp_set_setup_arithmetic.argtypes = [I]
     lib.sfdp_solve_full_space.argtypes = [P, I, VP, VP, VP, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.sfdp_apply_schur_inv.argtypes = [P, I, VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Info)]
@@ -153,7 +155,7 @@ def load_library(path: str = LIB_PATH):
                  "sfdp_batch_set_beta", "sfdp_batch_solve_range_space", "sfdp_server_create",
                  "sfdp_server_submit", "sfdp_server_poll", "sfdp_server_stats", "sfdp_set_graphs", "sfdp_set_tuning",
                  "sfdp_set_setup_arithmetic", "sfdp_elastic_create", "sfdp_elastic_pressure_load",
-                 "sfdp_elastic_forward"):
+                 "sfdp_elastic_forward", "sfdp_set_gmres_launch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -547,6 +549,14 @@ def set_graphs(enable: bool):
     """Graph replay of the refinement steps of single 2D problems on or off (default)."""
     load_library()
     _check(_lib.sfdp_set_graphs(int(bool(enable))))
+
+
+def set_gmres_launch(mode: int):
+    """GMRES launch form of single-problem range-space solves: 1 (default) plain
+    launch with a co-residency check and cooperative fallback, 0 cooperative
+    always, 2 the plain launch with no wait in its check (forces the fallback)."""
+    load_library()
+    _check(_lib.sfdp_set_gmres_launch(int(mode)))
 
 
 def set_setup_arithmetic(bits: int):

@@ -53,6 +53,20 @@ def test_errors_without_gpu_are_reported_not_raised(lib):
     assert lib.sfdp_last_error()
 
 
+def test_process_settings_reject_values_outside_their_range(lib):
+    """The process-wide switches take their documented values only (host code, no GPU)."""
+    for name, good, bad in (("sfdp_set_gmres_launch", (0, 1, 2), (-1, 3)), ("sfdp_set_graphs", (0, 1), (2,)),
+                            ("sfdp_set_tuning", (1,), (-1, 6))):
+        fn = getattr(lib, name)
+        fn.argtypes = [ctypes.c_int]
+        fn.restype = ctypes.c_int
+        for v in bad:
+            assert fn(v) != 0, (name, v)
+        for v in good:
+            assert fn(v) == 0, (name, v)
+    assert lib.sfdp_set_gmres_launch(1) == 0 and lib.sfdp_set_graphs(0) == 0
+
+
 def test_destroying_a_null_context_is_a_no_op(lib):
     lib.sfdp_ctx_destroy.argtypes = [ctypes.c_void_p]
     lib.sfdp_ctx_destroy.restype = ctypes.c_int
