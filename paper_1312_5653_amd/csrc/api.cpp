@@ -715,13 +715,11 @@ struct Multi {
   int* dmap = nullptr;
   size_t map_cap = 0;
   int g_kmax = -1, g_width = -1;
-  Gathered* dgather = nullptr;  // per-instance residual heads and flag words
-  Gathered* hgather = nullptr;
+  Gathered* hgather = nullptr;  // per-instance residual heads and flag words (pinned host)
   ~Multi() {
     if (ddev) hipFree(ddev);
     if (hdev) hipHostFree(hdev);
     if (dmap) hipFree(dmap);
-    if (dgather) hipFree(dgather);
     if (hgather) hipHostFree(hgather);
   }
 };
@@ -730,15 +728,13 @@ sfdp_status multi_grow(Multi& M, size_t n_inst, size_t n_map) {
   if (n_inst > M.dev_cap) {
     if (M.ddev) hipFree(M.ddev);
     if (M.hdev) hipHostFree(M.hdev);
-    if (M.dgather) hipFree(M.dgather);
     if (M.hgather) hipHostFree(M.hgather);
     M.ddev = nullptr;
     M.hdev = nullptr;
-    M.dgather = nullptr;
     M.hgather = nullptr;
     size_t cap = std::max<size_t>(n_inst, 2 * M.dev_cap);
     if (hipMalloc(&M.ddev, sizeof(Dev) * cap) || hipHostMalloc(&M.hdev, sizeof(Dev) * cap) ||
-        hipMalloc(&M.dgather, sizeof(Gathered) * cap) || hipHostMalloc(&M.hgather, sizeof(Gathered) * cap))
+        hipHostMalloc(&M.hgather, sizeof(Gathered) * cap))
       return fail(SFDP_E_NOMEM, "batch descriptor allocation failed");
     M.dev_cap = cap;
   }
@@ -903,11 +899,6 @@ sfdp_status feti_run(const Target& t, Problem* timed, int fsel, int conj, int xs
 
 constexpr unsigned IDENTITY_MAP = 0x03020100u;
 
-// Range-space solves of every problem's group: nr targets in slots 0..nr-1,
-// caller arrays in the problem's slots.
-// All unfinished targets take each two-factor step together; each stops on
-// its own test.  info[i] has ps[i]->nr entries.  M is the batch (null for a
-// single problem); dg / hg hold one Gathered record per problem.
 // The context's capture stream (non-blocking, default priority) and the two
 // events that order it after and before the library's stream: the library's
 // stream may be the null stream, which cannot be captured.
@@ -985,8 +976,13 @@ sfdp_status step_graph(Problem& p, const Target& t, double tin, int kmax, bool s
   return replay(exec);
 }
 
-sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Multi* M, Gathered* dg,
-                            Gathered* hg, double tol_kkt, double tol_first, double tol_inner, int max_outer,
+// Range-space solves of every problem's group: nr targets in slots 0..nr-1,
+// caller arrays in the problem's slots.
+// All unfinished targets take each two-factor step together; each stops on
+// its own test.  info[i] has ps[i]->nr entries.  M is the batch (null for a
+// single problem); hg holds one Gathered record per problem (pinned host memory).
+sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Multi* M, Gathered* hg,
+                            double tol_kkt, double tol_first, double tol_inner, int max_outer,
                             int kmax, const std::vector<sfdp_info*>& info, bool single) {
   const size_t n = ps.size();
   hipStream_t st = t.st;
@@ -1012,8 +1008,7 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
   // every refinement step, and the start)
   auto residual = [&](const Target& tt) -> hipError_t {
     hipError_t e = launch_kkt_residual(tt);
-    if (e == hipSuccess) e = launch_gather(tt, dg);
-    if (e == hipSuccess) e = hipMemcpyAsync(hg, dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, tt.st);
+    if (e == hipSuccess) e = launch_gather(tt, hg);
     return e;
   };
   // one refinement step of the group's active targets, then the new residual
@@ -1108,8 +1103,7 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
     if (s) return s;
   }
   HIPCHK(launch_kkt_metrics(t));
-  HIPCHK(launch_gather(t, dg));
-  HIPCHK(hipMemcpyAsync(hg, dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(launch_gather(t, hg));
   HIPCHK(hipStreamSynchronize(st));
   if (timed) HIPCHK(ev_harvest(*timed));
   sfdp_status status = SFDP_OK;
@@ -1262,7 +1256,6 @@ void destroy_problem(Problem* p) {
                  p->bar, p->flags, p->r1, p->r2, p->r3, p->red, p->cvec, p->cvec2, p->cvec3};
   for (void* a : arr)
     if (a) hipFree(a);
-  if (p->gd) hipFree(p->gd);
   if (p->gh) hipHostFree(p->gh);
   if (p->fsw) hipFree(p->fsw);
   if (p->fsh) hipHostFree(p->fsh);
@@ -1312,9 +1305,7 @@ Target single_target(Problem* p) {
 // The problem's gather buffers (device record and its pinned host copy),
 // allocated on first use and kept until the problem is destroyed.
 sfdp_status gather_buffers(Problem& p) {
-  if (p.gd) return SFDP_OK;
-  sfdp_status s = dalloc(p, (void**)&p.gd, sizeof(Gathered));
-  if (s) return s;
+  if (p.gh) return SFDP_OK;
   if (hipHostMalloc((void**)&p.gh, sizeof(Gathered)) != hipSuccess) {
     p.gh = nullptr;
     return fail(SFDP_E_NOMEM, "pinned gather buffer");
@@ -1327,8 +1318,7 @@ sfdp_status gather_one(Problem* p) {
   sfdp_status s = gather_buffers(*p);
   if (s) return s;
   Target t = single_target(p);
-  HIPCHK(launch_gather(t, p->gd));
-  HIPCHK(hipMemcpyAsync(p->gh, p->gd, sizeof(Gathered), hipMemcpyDeviceToHost, t.st));
+  HIPCHK(launch_gather(t, p->gh));
   HIPCHK(hipStreamSynchronize(t.st));
   return SFDP_OK;
 }
@@ -1857,7 +1847,7 @@ sfdp_status sfdp_solve_range_space(sfdp_problem* p, int nrhs, const double* ybar
     p->set_slots(ng, ybar + r0 * n, yc ? yc + r0 * p->n_bdry : nullptr, y + r0 * n, u + r0 * n,
                  lam + r0 * n);
     std::vector<sfdp_info*> inf{info ? info + r0 : nullptr};
-    s = range_space_run(t, ps, nullptr, p->gd, p->gh, tk, first_tol(p->prec, opts, ti), ti, mo, kmax, inf,
+    s = range_space_run(t, ps, nullptr, p->gh, tk, first_tol(p->prec, opts, ti), ti, mo, kmax, inf,
                         single_of(opts));
     p->nr = 0;
     if (s == SFDP_E_NOCONV) worst = s;
@@ -2302,7 +2292,7 @@ sfdp_status sfdp_batch_solve_range_space(sfdp_batch* b, const int* nrhs, const d
     }
     sfdp_status s = multi_groups(b->M, kmax, w == 1 ? 1 : w == 2 ? 2 : 4, b->gmap, b->gcap);
     if (!s)
-      s = range_space_run(b->M.t, b->probs, &b->M, b->M.dgather, b->M.hgather, tk,
+      s = range_space_run(b->M.t, b->probs, &b->M, b->M.hgather, tk,
                           first_tol(b->probs[0]->prec, opts, ti), ti, mo, kmax, inf,
                           single_of(opts));
     for (Problem* p : b->probs) p->nr = 0;
@@ -2480,8 +2470,7 @@ struct sfdp_server {
   int* gmap = nullptr;
   size_t gcap = 0;
   std::vector<Problem*> active_set;       // instances of the current target
-  Gathered* dg = nullptr;
-  Gathered* hg = nullptr;
+  Gathered* hg = nullptr;  // pinned host, written by the gather kernel
   size_t gath_cap = 0;
   int64_t n_submit = 0, n_complete = 0, n_failed = 0, n_setups = 0, n_evict = 0, n_ticks = 0;
   std::string worker_error;
@@ -2637,10 +2626,9 @@ sfdp_status server_target(sfdp_server* S, const std::vector<Problem*>& act) {
   sfdp_status s = multi_groups(S->M, S->kmax, w, S->gmap, S->gcap);
   if (s) return s;
   if (act.size() > S->gath_cap) {
-    if (S->dg) hipFree(S->dg);
     if (S->hg) hipHostFree(S->hg);
     S->gath_cap = std::max(act.size(), 2 * S->gath_cap);
-    if (hipMalloc(&S->dg, sizeof(Gathered) * S->gath_cap) || hipHostMalloc(&S->hg, sizeof(Gathered) * S->gath_cap))
+    if (hipHostMalloc(&S->hg, sizeof(Gathered) * S->gath_cap))
       return fail(SFDP_E_NOMEM, "server gather buffers");
   }
   return SFDP_OK;
@@ -2693,8 +2681,7 @@ sfdp_status server_tick(sfdp_server* S) {
   const size_t n = act.size();
   HIPCHK(launch_group_init(t));  // also clears the new slots' iteration logs
   HIPCHK(launch_kkt_residual(t));
-  HIPCHK(launch_gather(t, S->dg));
-  HIPCHK(hipMemcpyAsync(S->hg, S->dg, sizeof(Gathered) * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(launch_gather(t, S->hg));
   HIPCHK(hipStreamSynchronize(st));
   bool any = false;
   for (size_t i = 0; i < n; ++i) {
@@ -3177,7 +3164,6 @@ void sfdp_server_destroy(sfdp_server* S) {
   }
   for (auto& kv : S->reqs) delete kv.second;
   if (S->gmap) hipFree(S->gmap);
-  if (S->dg) hipFree(S->dg);
   if (S->hg) hipHostFree(S->hg);
   S->ctx->children--;
   delete S;

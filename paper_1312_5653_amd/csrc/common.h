@@ -378,8 +378,7 @@ struct Problem {
   // set-up scratch (valid during sfdp_set_beta only)
   cd *G64 = nullptr, *Sinv64 = nullptr, *S64 = nullptr, *Phi64 = nullptr, *PhiFull = nullptr,
      *scr = nullptr, *Zs = nullptr;
-  Gathered* gd = nullptr;  // gather record (device) and its pinned host copy
-  Gathered* gh = nullptr;
+  Gathered* gh = nullptr;  // gather record (pinned host, written by the gather kernel)
   // cooperative time-slicing: when set, the long solve loops call it at the
   // start of every refinement step and MINRES iteration (the server's solo
   // requests hand the device back to its worker there)
@@ -622,6 +621,8 @@ hipError_t launch_mass_inverse(const Problem& p, const double* x, double scale, 
 hipError_t launch_lin3(int64_t n, double a, const double* x, double b, const double* y, double c, const double* z,
                        double* out, hipStream_t st);
 hipError_t launch_dot(int64_t n, const double* x, const double* y, double* part, double* out, hipStream_t st);
-hipError_t launch_gather(const Target& t, Gathered* out);  // out[i]: instance i of the target
+// out[i]: instance i of the target; out is pinned host memory (hipHostMalloc),
+// written by the kernel with system-scope stores, read after the stream is synchronized
+hipError_t launch_gather(const Target& t, Gathered* out);
 
 }  // namespace sfdp
