@@ -453,8 +453,10 @@ def _run_precision(sfdp, torch, p, beta, ybar_t, steps, warmup, tol_kkt, tol_inn
     kw = dict(tol_kkt=tol_kkt, tol_inner=tol_inner, batch=batch, max_krylov=max_krylov, factors=factors, **sb)
     for _ in range(warmup):
         solve(ybar_t, None, y, u, lam, **kw)
-    # HIP events around the hot kernels during the timed calls
-    p.timing_enable(True)
+    # HIP events around the GMRES launches (the roofline's kernel) during the timed
+    # calls; the subdomain solve's events (each record idles the device ~6 us) are
+    # taken in a short pass of their own after the timed region
+    p.timing_enable(2)
     lat, rhos, its, feti, minres, cvs, etas, steps_seen = [], [], [], [], [], [], [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -474,7 +476,15 @@ def _run_precision(sfdp, torch, p, beta, ybar_t, steps, warmup, tol_kkt, tol_inn
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_all
     kt = p.kernel_times()
+    lsteps = max(2, min(steps, 5))
+    p.timing_enable(1)
+    for _ in range(lsteps):
+        solve(ybar_t, None, y, u, lam, **kw)
+    kt_local = p.kernel_times()
     p.timing_enable(False)
+    kt["local_ms"], kt["local_launches"] = kt_local["local_ms"], kt_local["local_launches"]
+    # the subdomain solve's share of a timed step: its time per call over the step time
+    kt["local_share"] = kt_local["local_ms"] / lsteps / (elapsed * 1e3 / steps)
     # the same calls with their refinement steps replayed as captured HIP graphs
     # (the first call runs eagerly, the second captures), for the comparison
     ksteps = max(3, min(steps, 10))
@@ -938,7 +948,8 @@ def main():
         "subdomain_solve_kernel": {"kernel": "k_local_solve", "launch_ms": local_ms,
                                    "launches": kt["local_launches"], "rhs_per_launch": B,
                                    "achieved_gbs": local_gbs, "frac": local_gbs / HBM_PEAK_GBS,
-                                   "time_share": kt["local_ms"] / (r["ms_per_step"] * args.steps)},
+                                   "time_share": kt["local_share"],
+                                   "timed": "HIP events in a pass of their own after the timed region"},
     }
     other = [k for k in res if k != head]
     for k in other:

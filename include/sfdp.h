@@ -553,10 +553,12 @@ void sfdp_server_destroy(sfdp_server* s);
 /* Kernel timing with HIP events recorded on the context's stream around the
  * launches of the two hot kernels of every FETI-DP solve: the persistent
  * interface GMRES kernel and the batched subdomain solve kernel (two launches
- * per FETI-DP solve).  enable != 0 starts recording (and clears the totals);
- * sfdp_kernel_times reports totals in milliseconds, launch counts and the
- * GMRES iterations done by the timed launches.  Timing adds one event pair per
- * launch and is meant for measurement runs. */
+ * per FETI-DP solve).  enable = 1 records both, enable = 2 the GMRES launches
+ * only, enable = 0 stops; 1 and 2 clear the totals.  sfdp_kernel_times reports
+ * totals in milliseconds, launch counts and the GMRES iterations done by the
+ * timed launches.  Timing adds one event pair per timed launch (on MI355X each
+ * event record leaves the device idle ~6 us) and is meant for measurement
+ * runs.  SFDP_E_INVALID outside 0..2. */
 typedef struct {
   double gmres_ms;        /* summed duration of the GMRES kernel launches */
   double local_ms;        /* summed duration of the subdomain solve launches */

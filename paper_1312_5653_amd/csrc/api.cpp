@@ -299,7 +299,7 @@ sfdp_status check_launch(Problem& p, int kmax) {
 // Event pairs around hot launches (kind 0: GMRES, 1: subdomain solve).
 hipError_t ev_begin(Problem* p, int kind, int* slot) {
   *slot = -1;
-  if (!p || !p->timing) return hipSuccess;
+  if (!p || !p->timing || (p->timing == 2 && kind != 0)) return hipSuccess;
   if (p->ev_used + 2 > (int)p->ev_pool.size()) {
     for (int i = 0; i < 64; ++i) {
       hipEvent_t e;
@@ -2311,11 +2311,12 @@ sfdp_status sfdp_inspect(sfdp_problem* p, sfdp_query what, int sub, double* out,
 
 sfdp_status sfdp_timing_enable(sfdp_problem* p, int enable) {
   if (!p) return fail(SFDP_E_INVALID, "null problem");
+  if (enable < 0 || enable > 2) return fail(SFDP_E_INVALID, "enable must be 0, 1 or 2");
   HIPCHK(hipSetDevice(p->ctx->device));
   HIPCHK(hipStreamSynchronize(p->ctx->stream));
   p->ev_pending.clear();
   p->ev_used = 0;
-  p->timing = enable != 0;
+  p->timing = enable;
   p->t_gmres_ms = p->t_local_ms = 0;
   p->n_gmres = p->n_local = p->it_gmres = p->it_rhs = 0;
   return SFDP_OK;

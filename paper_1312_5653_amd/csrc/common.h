@@ -400,7 +400,7 @@ struct Problem {
   int gmres_plain = 0;
   bool gmres_coop = false;
   // kernel timing (events recorded around hot kernel launches)
-  bool timing = false;
+  int timing = 0;  // event timing: 0 off, 1 GMRES and subdomain-solve launches, 2 GMRES only
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, int>> ev_pending;  // (event index, kind: 0 gmres, 1 local)
   int ev_used = 0;

@@ -348,7 +348,8 @@ class Problem:
         _check(_lib.sfdp_interface_apply(self._h, which.encode(), _ptr(x), _ptr(y)))
         return y
 
-    def timing_enable(self, enable: bool = True):
+    def timing_enable(self, enable=True):
+        """True / 1: time the GMRES and subdomain-solve launches; 2: the GMRES launches only; 0 off."""
         _check(_lib.sfdp_timing_enable(self._h, int(enable)))
 
     def kernel_times(self):

@@ -59,3 +59,27 @@ def test_launch_forms_give_the_same_solves(sf, prec, N, m, graphs):
             assert ia == ib, (mode, ia, ib)
             for a, b in zip(xa, xb):
                 assert np.array_equal(a, b), mode
+
+
+def test_timing_modes_record_the_kernels_they_name(sf):
+    """sfdp_timing_enable: 1 times the GMRES and subdomain-solve launches, 2 the
+    GMRES launches only; the solves are the same either way."""
+    sfdp, ctx = sf
+    p = sfdp.Problem(ctx, 2, 64, 8, 1)
+    p.set_beta(1e-4)
+    yb = torch.tensor(np.stack([W.sine_target(2, 64, *W.modes_for("sixteen2d", 50 + s))[0] for s in range(2)]),
+                      device=DEV)
+    res = {}
+    for mode in (1, 2):
+        p.timing_enable(mode)
+        y, u, lam = (torch.empty_like(yb) for _ in range(3))
+        _, _, _, info, st = p.solve_range_space(yb, None, y, u, lam)
+        assert st == 0, info
+        res[mode] = (p.kernel_times(), y.cpu().numpy())
+        p.timing_enable(0)
+    (k1, y1), (k2, y2) = res[1], res[2]
+    assert k1["gmres_launches"] > 0 and k1["local_launches"] > 0 and k1["local_ms"] > 0
+    assert k2["gmres_launches"] == k1["gmres_launches"] and k2["gmres_ms"] > 0
+    assert k2["local_launches"] == 0 and k2["local_ms"] == 0
+    assert np.array_equal(y1, y2)
+    p.close()
