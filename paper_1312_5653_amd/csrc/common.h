@@ -622,7 +622,7 @@ hipError_t launch_lin3(int64_t n, double a, const double* x, double b, const dou
                        double* out, hipStream_t st);
 hipError_t launch_dot(int64_t n, const double* x, const double* y, double* part, double* out, hipStream_t st);
 // out[i]: instance i of the target; out is pinned host memory (hipHostMalloc),
-// written by the kernel with system-scope stores, read after the stream is synchronized
+// written by the kernel (then a system-scope fence), read after the stream is synchronized
 hipError_t launch_gather(const Target& t, Gathered* out);
 
 }  // namespace sfdp

@@ -520,17 +520,14 @@ __global__ void k_fill_flags(Src src, int first, int count) {
 }
 
 // out[instance] = residual heads and flag words (one block per instance), written
-// straight into pinned host memory with system-scope stores: the host reads them
-// once the stream is synchronized, with no copy in between
+// straight into pinned host memory (plain stores, coalesced, then a system-scope
+// fence): the host reads them once the stream is synchronized, with no copy in between
 template <class Src>
 __global__ void k_gather(Src src, Gathered* out) {
   const Dev& d = src.dev();
   Gathered& o = out[blockIdx.x];
-  if (threadIdx.x < 4 * NRMAX)
-    __hip_atomic_store(&o.red[threadIdx.x], d.red ? d.red[threadIdx.x] : 0.0, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
-  for (int i = threadIdx.x; i < FLAG_WORDS; i += blockDim.x)
-    __hip_atomic_store(&o.flags[i], d.flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (threadIdx.x < 4 * NRMAX) o.red[threadIdx.x] = d.red ? d.red[threadIdx.x] : 0.0;
+  for (int i = threadIdx.x; i < FLAG_WORDS; i += blockDim.x) o.flags[i] = d.flags[i];
   __threadfence_system();
 }
 

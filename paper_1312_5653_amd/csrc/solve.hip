@@ -98,11 +98,13 @@ __device__ inline void grid_barrier(unsigned* bar, unsigned nblocks, unsigned bl
 // complete it can no longer be set.  On abort every block must return before any
 // work (a late block sees the bit in its own arrival), and *notres is set.  A
 // cooperative launch saves this check but costs ~11 us of idle device on each
-// side of the kernel (measured on MI355X), a plain one does not.
+// side of the kernel (measured on MI355X), a plain one does not.  `go` is an LDS
+// word that carries thread 0's answer to the block (the caller's dynamic LDS, free
+// at that point: a static LDS word would grow the kernel's LDS allocation by one
+// granule and cost co-resident blocks where the dynamic layout fills the CU).
 constexpr unsigned ARRIVE_ABORT = 1u << 31;
 constexpr int CORESIDENT_SPINS = 1 << 12;
-__device__ inline bool grid_coresident(unsigned* word, unsigned total, int spins, int* notres) {
-  __shared__ int go;
+__device__ inline bool grid_coresident(unsigned* word, unsigned total, int spins, int* notres, int& go) {
   if (threadIdx.x == 0) {
     unsigned v = __hip_atomic_fetch_add(word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     int n = 0, r = 1;
@@ -127,7 +129,9 @@ __device__ inline bool grid_coresident(unsigned* word, unsigned total, int spins
     go = r;
   }
   __syncthreads();
-  return go != 0;
+  const bool ok = go != 0;
+  __syncthreads();  // every thread has read go before the caller reuses the word
+  return ok;
 }
 
 // Coherent (agent-scope) access to data written by one block and read by
@@ -1991,12 +1995,16 @@ __global__ void __launch_bounds__(256) k_gmres(Src src, GmresLaunch L) {
   const Dev& d = src.dev();
   const int nr = min(NRT, d.nr - L.r0);
   if (nr <= 0) return;
-  // plain launch: nothing to do once a grid of this step was found not co-resident
-  // (the step runs again), else the check
-  if (L.check_spins >= 0 &&
-      (d.flags[FLAG_NOTRES] ||
-       !grid_coresident(d.bar + BAR_ARRIVE, (unsigned)d.gnb, L.check_spins, d.flags + FLAG_NOTRES)))
-    return;
+  // plain launch (single problems only, so the batch form carries none of this code
+  // and keeps its register count): nothing to do once a grid of this step was found
+  // not co-resident (the step runs again), else the check
+  if constexpr (std::is_same<Src, One>::value) {
+    extern __shared__ __align__(16) char smem[];
+    if (L.check_spins >= 0 &&
+        (d.flags[FLAG_NOTRES] || !grid_coresident(d.bar + BAR_ARRIVE, (unsigned)d.gnb, L.check_spins,
+                                                  d.flags + FLAG_NOTRES, *(int*)smem)))
+      return;
+  }
   const RhsStride rs = d.rs;
   GmresArgs a;
   a.rs = rs;
