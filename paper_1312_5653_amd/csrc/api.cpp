@@ -978,6 +978,26 @@ sfdp_status step_graph(Problem& p, const Target& t, double tin, int kmax, bool s
   return replay(exec);
 }
 
+// Waits for the n records of a gather launched last on st: spins on their ready
+// words in pinned host memory (no wake-up latency of a blocking synchronization),
+// asking the stream every few hundred polls so that a failed or finished stream
+// ends the wait.
+static hipError_t wait_gathered(Gathered* hg, size_t n, hipStream_t st) {
+  for (unsigned it = 1;; ++it) {
+    bool all = true;
+    for (size_t i = 0; i < n && all; ++i) all = __atomic_load_n(&hg[i].ready, __ATOMIC_ACQUIRE) != 0;
+    if (all) return hipSuccess;
+    if (it % 256 == 0) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) return hipStreamSynchronize(st);  // finished: the records are complete
+      if (e != hipErrorNotReady) return e;
+    }
+  }
+}
+static void clear_gathered(Gathered* hg, size_t n) {
+  for (size_t i = 0; i < n; ++i) __atomic_store_n(&hg[i].ready, 0, __ATOMIC_RELEASE);
+}
+
 // Range-space solves of every problem's group: nr targets in slots 0..nr-1,
 // caller arrays in the problem's slots.
 // All unfinished targets take each two-factor step together; each stops on
@@ -1042,10 +1062,11 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
   } plain_scope{t.single() ? t.one : nullptr};
   if (t.single()) t.one->gmres_plain = g_gmres_launch.load();
   int pre_flags[FLAG_WORDS];  // a single problem's device flags before the current step
+  clear_gathered(hg, n);
   HIPCHK(residual(t));
   for (int step = 0;; ++step) {
     if (t.single()) t.one->yield_point();
-    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(wait_gathered(hg, n, st));
     if (step > 0 && t.single() && hg[0].flags[FLAG_NOTRES]) {
       // the flags as they were before the step (iteration logs of any GMRES
       // launch of it that did finish are dropped), then the same step again
@@ -1053,6 +1074,7 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
       HIPCHK(hipMemcpy(t.one->flags, pre_flags, sizeof(pre_flags), hipMemcpyHostToDevice));
       --step;
       const double tin = step == 0 ? tol_first : tol_inner;
+      clear_gathered(hg, n);
       sfdp_status s = graphable ? step_graph(*t.one, t, tin, kmax, single,
                                              [&](const Target& tt) { return step_body(tt, tin); })
                                 : step_body(t, tin);
@@ -1088,6 +1110,7 @@ sfdp_status range_space_run(const Target& t, const std::vector<Problem*>& ps, Mu
       if (s) return s;
     }
     if (t.single()) std::memcpy(pre_flags, hg[0].flags, sizeof(pre_flags));
+    clear_gathered(hg, n);
     sfdp_status s = graphable ? step_graph(*t.one, t, tin, kmax, single,
                                            [&](const Target& tt) { return step_body(tt, tin); })
                               : step_body(t, tin);

@@ -202,6 +202,7 @@ constexpr int FLAG_NOTRES = 2, FLAG_ITS = 8, FLAG_CNT = 16, FLAG_LOG = 64, FLAG_
 struct Gathered {
   double red[4 * NRMAX];  // [2 slot]: rho, [2 slot + 1]: imag ratio; from MET_HEAD the metrics
   int flags[FLAG_WORDS];
+  int ready;              // set to 1 by the gather kernel after the rest (the host clears it)
 };
 
 // Selectors of an instance's complex vectors, passed to kernels so that one

@@ -529,6 +529,11 @@ __global__ void k_gather(Src src, Gathered* out) {
   if (threadIdx.x < 4 * NRMAX) o.red[threadIdx.x] = d.red ? d.red[threadIdx.x] : 0.0;
   for (int i = threadIdx.x; i < FLAG_WORDS; i += blockDim.x) o.flags[i] = d.flags[i];
   __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&o.ready, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+  }
 }
 
 __global__ void k_imag_scaled(int64_t n, const cd* x, double s, double* y) {
