@@ -193,9 +193,9 @@ sfdp_status sfdp_set_tuning(int enable);
  * enable = 0 runs every step eagerly.  Results are bitwise the same either
  * way.  Off by default: a step's launches are queued ahead of the GPU anyway,
  * and the host's convergence test between steps stays, so replay does not
- * shorten a solve (measured at 512^2 on MI355X: 3.41 ms per call replayed from
+ * shorten a solve (measured at 512^2 on MI355X: 3.32 ms per call replayed from
  * the null stream, which replays through a capture stream of its own, against
- * 3.27 ms eagerly).
+ * 3.22 ms eagerly).
  * SFDP_E_INVALID for other values. */
 sfdp_status sfdp_set_graphs(int enable);
 
